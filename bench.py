@@ -1,0 +1,192 @@
+#!/usr/bin/env python3
+"""Benchmark of the k-means hot path on one MI355X.
+
+One step = one complete fit (Lloyd's with MTI pruning, every iteration until
+no label changes or max_iters) of the workload below, inputs resident in HBM.
+value = Lloyd iterations per second over the timed steps.
+
+Workload (default): n = 1,000,000 points, d = 32, k = 100, FP32 points from a
+100-component Gaussian mixture (means U[-20,20]^d, sigma U[0.5,2], Dirichlet
+weights), k-means++ seeding, max_iters = 100, tol = 0.
+
+Also reported, measured in the same run:
+  roofline      for the kernel group with the largest GPU time, from HIP
+                events on the launch stream over the timed steps
+  cpu_baseline  the FP64 oracle (MTI variant, OpenMP) timed on the host on
+                the same workload and C0; its labels are compared with the
+                GPU's at every iteration ("exact" in the output)
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP32_MFMA = 157.3e12      # MI355X dense FP32 matrix, FLOP/s
+PEAK_BF16_MFMA = 2516.6e12
+PEAK_HBM = 8.0e12              # bytes/s
+PEAK_FP64_VALU = 78.6e12
+
+METRIC = ("Lloyd iters/s and point·centroid dists/s (% MFMA peak) "
+          "at exact assignments")
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-iters", type=int, default=0,
+                    help="oracle iterations for the CPU baseline (0 = whole fit)")
+    return ap.parse_args()
+
+
+def group_work(g, n, d, k, sx, ctr, iters):
+    """Algorithmic work of kernel group g summed over one fit:
+    (amount, unit, bound, peak).  ctr: per-iteration counters (iters x 8)."""
+    scanned_dense = int(ctr[0, 1]) if iters else 0
+    scanned_list = int(ctr[1:iters, 1].sum()) if iters > 1 else 0
+    if g == 0:     # dense tile: 2 d flops per point-centroid pair
+        return 2.0 * d * k * scanned_dense, "TFLOP/s", "mfma", PEAK_FP32_MFMA
+    if g == 1:
+        return 2.0 * d * k * scanned_list, "TFLOP/s", "mfma", PEAK_FP32_MFMA
+    if g == 5:     # leaf sums: every row gathered once + perm + leaf sums out
+        per_iter = n * d * sx + 4.0 * n + (n / 64.0 + k) * d * 8.0
+        return per_iter * iters, "GB/s", "hbm", PEAK_HBM
+    if g == 3:     # filter: label, bound in/out, survivor index; rows tightened
+        tot = 0.0
+        for t in range(1, iters):
+            pa = int(ctr[t, 2])
+            tot += 12.0 * n + (n - pa) * (d * sx) + 4.0 * int(ctr[t, 1])
+        return tot, "GB/s", "hbm", PEAK_HBM
+    if g == 4:     # sort: labels read twice, perm written, block counts
+        return (12.0 * n) * iters, "GB/s", "hbm", PEAK_HBM
+    return None
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; "
+                          "multi-GPU sharding is described in DESIGN.md",
+                          "n_gpus": a.gpus}), flush=True)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import paper_1606_08905_amd as knor
+    import workloads
+
+    knor.load()
+    t_gen = time.perf_counter()
+    w = workloads.config(2)
+    n, d, k = w.n, w.d, w.k
+    print(f"# data n={n} d={d} k={k} generated in {time.perf_counter() - t_gen:.1f}s",
+          file=sys.stderr, flush=True)
+    X = torch.from_numpy(w.X).cuda()
+    C0 = torch.from_numpy(w.C0).cuda()
+    torch.cuda.synchronize()
+
+    def step(profile=None, history=False):
+        return knor.fit(X, k, C0=C0, max_iters=w.max_iters, tol=w.tol,
+                        prune=True, counters=True, profile=profile,
+                        history=history)
+
+    for _ in range(a.warmup):
+        step()
+    torch.cuda.synchronize()
+
+    prof_ms = np.zeros(knor.NPROF)
+    prof_n = np.zeros(knor.NPROF, np.int64)
+    iters_total = 0
+    stats = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(a.steps):
+        C, lab, st = step(profile=(prof_ms, prof_n))
+        iters_total += st["iters"]
+        stats.append(st)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    print(f"# timed {a.steps} fits in {dt:.3f}s", file=sys.stderr, flush=True)
+
+    value = iters_total / dt
+    iters = stats[-1]["iters"]
+    ctr = stats[-1]["counters"]
+    dists_eff = iters_total * n * k / dt
+    dists_done = sum(s["dists_computed"] for s in stats) / dt
+
+    # roofline of the dominant kernel group
+    kernels = {}
+    for g, name in enumerate(knor.PROF_GROUPS):
+        if prof_n[g]:
+            kernels[name] = {"ms_total": round(float(prof_ms[g]), 4),
+                             "launches": int(prof_n[g]),
+                             "us_per_launch": round(1e3 * prof_ms[g] / prof_n[g], 3)}
+    g_dom = int(np.argmax(prof_ms))
+    roof = None
+    wk = group_work(g_dom, n, d, k, 4, ctr, iters)
+    if wk is not None:
+        amount, unit, bound, peak = wk
+        per_launch = amount / max(1, prof_n[g_dom] / a.steps)
+        sec_per_launch = prof_ms[g_dom] / prof_n[g_dom] / 1e3
+        achieved = per_launch / sec_per_launch
+        scale = 1e12 if unit == "TFLOP/s" else 1e9
+        roof = {"kernel": knor.PROF_GROUPS[g_dom], "bound": bound,
+                "achieved": round(achieved / scale, 3),
+                "peak": round(peak / scale, 1), "unit": unit,
+                "frac": round(achieved / peak, 4), "traffic": None}
+    # the dense distance tile, whatever dominates
+    tile = None
+    if prof_n[0]:
+        fl = group_work(0, n, d, k, 4, ctr, iters)[0]
+        sec = prof_ms[0] / prof_n[0] / 1e3
+        tile = {"tflops": round(fl / sec / 1e12, 2),
+                "frac_fp32_mfma_peak": round(fl / sec / PEAK_FP32_MFMA, 4),
+                "us": round(sec * 1e6, 2)}
+
+    out = {
+        "metric": METRIC, "value": round(value, 3), "unit": "iters/s",
+        "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
+        "ms_per_step": round(1e3 * dt / a.steps, 3),
+        "higher_is_better": True, "scaling": "strong", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "gaussian-mixture n=1e6 d=32 k=100 f32 MTI "
+                               "k-means++ max_iters=100 tol=0",
+                   "n": n, "d": d, "k": k, "iters_per_fit": iters,
+                   "prune": "MTI"},
+        "eff_dists_per_s": dists_eff, "computed_dists_per_s": dists_done,
+        "dense_tile": tile, "roofline": roof, "kernels": kernels,
+        "rechecked_per_fit": stats[-1]["rechecked"],
+    }
+
+    # CPU baseline: the FP64 oracle on the same inputs, plus exactness check
+    if not a.no_cpu_baseline:
+        import oracle
+        _, _, sth = step(history=True)
+        hist = sth["label_history"].cpu().numpy()
+        X64 = w.x64()
+        its = a.cpu_iters if a.cpu_iters > 0 else w.max_iters
+        tc = time.perf_counter()
+        ref = oracle.mti_fit(X64, w.C0, its, tol=w.tol, history=True,
+                             objective=False)
+        tcpu = time.perf_counter() - tc
+        m = min(ref.iters, hist.shape[0])
+        exact = bool((hist[:m] == ref.label_hist[:m]).all()) and (
+            ref.iters == sth["iters"] or its < w.max_iters)
+        out["cpu_baseline"] = {
+            "value": round(ref.iters / tcpu, 4), "unit": "iters/s",
+            "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": f"FP64 MTI oracle, same workload and C0, {ref.iters} "
+                      f"iterations ({'whole fit' if its >= w.max_iters else 'first iterations'})"}
+        out["exact"] = exact
+        out["exact_iters_compared"] = int(m)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

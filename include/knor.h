@@ -1,0 +1,183 @@
+/*
+ * knor.h -- C ABI of the MI355X (gfx950) k-means library.
+ *
+ * The library implements the Lloyd iteration of Mhembere et al., "knor: A
+ * NUMA-Optimized In-Memory, Distributed and Semi-External-Memory k-means
+ * Library" (HPDC'17, arXiv 1606.08905): the nearest-centroid assignment
+ * (Algorithm 1), optionally pruned by the minimal triangle inequality (MTI,
+ * Section "Minimal Triangle Inequality (MTI) Pruning"), followed by the
+ * centroid update (Phase II / the merge of per-thread partial centroids of
+ * Algorithm 1).  All compute runs in HIP kernels on one GPU.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Points X are n x d, row-major, contiguous, in DEVICE memory, of the
+ *    element type given by knor_dtype (BF16 as raw 16-bit patterns).
+ *  - Centroids are k x d row-major FP64 in DEVICE memory.  Labels are int32
+ *    in DEVICE memory.  The caller owns every array passed in.
+ *  - Distances are squared Euclidean, D(x, c) = sum_i (x_i - c_i)^2 (Section
+ *    "Nomenclature"); the assigned centroid is the lowest index among those
+ *    whose D, evaluated in FP64 in index order without fused multiply-add,
+ *    is smallest (Algorithm 1's strict "<" scan).  Lower-precision arithmetic
+ *    is used only where a rounding-error bound proves it picks that same
+ *    centroid; every other point is recomputed in that FP64 form.
+ *  - A centroid is the mean of its members (Phase II), summed in FP64 in a
+ *    fixed order: members by increasing point index, leaves of 64
+ *    consecutive members summed left to right starting from the first
+ *    member, leaf sums combined pairwise with the split at the largest power
+ *    of two below the leaf count, then one correctly rounded division by the
+ *    member count.  A cluster without members keeps its previous centroid.
+ *  - Work is stream-ordered on opts->stream (a hipStream_t; NULL = the null
+ *    stream).  knor_assign and knor_update return before the work finishes;
+ *    knor_fit returns after it finishes, because it observes convergence.
+ *  - Argument errors are detected before any device work is enqueued; on
+ *    every error return, the output arrays are left untouched.
+ *  - Limits: 1 <= d <= 256, 1 <= k <= 16384, 1 <= n < 2^31, k <= n (fit).
+ *  - The library keeps no global mutable state; concurrent calls on
+ *    different streams are independent.
+ */
+#ifndef KNOR_H
+#define KNOR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  KNOR_OK = 0,
+  KNOR_ERR_INVALID_ARG = 1,   /* a size, pointer or option is out of range  */
+  KNOR_ERR_OUT_OF_MEMORY = 2, /* device workspace could not be allocated, or
+                                 exceeds opts->workspace_cap               */
+  KNOR_ERR_HIP = 3,           /* a HIP runtime call failed                  */
+  KNOR_ERR_NUMERIC = 4,       /* NaN or Inf in X or in the centroids        */
+  KNOR_ERR_UNSUPPORTED = 5    /* valid request this build does not handle   */
+} knor_status;
+
+typedef enum { KNOR_F64 = 0, KNOR_F32 = 1, KNOR_BF16 = 2 } knor_dtype;
+
+/* Initial centroids.  The paper does not specify initialisation. */
+typedef enum {
+  KNOR_INIT_GIVEN = 0, /* C_init holds the k x d FP64 initial centroids      */
+  KNOR_INIT_FORGY = 1  /* k distinct rows of X chosen from opts->seed: the
+                          first k entries of a Fisher-Yates shuffle of 0..n-1
+                          driven by SplitMix64(seed), j = next() % (i + 1)
+                          for i = n-1 down to 1                              */
+} knor_init;
+
+typedef struct {
+  uint32_t struct_size; /* sizeof(knor_opts); 0 selects all defaults        */
+  int32_t prune;        /* 0: every point scans every centroid;
+                           1: MTI pruning (default)                          */
+  int32_t recheck;      /* 1: FP64 recheck of near-tie points only (default);
+                           2: FP64 recheck of every point (validation mode)  */
+  int32_t check_numeric;/* 1: reject NaN/Inf in X and C (default 1)         */
+  uint64_t seed;        /* KNOR_INIT_FORGY seed                              */
+  void* stream;         /* hipStream_t; NULL = null stream                   */
+  size_t workspace_cap; /* bytes of device workspace allowed; 0 = unlimited  */
+  int32_t* label_history; /* DEVICE, optional: max_iters x n; row t receives
+                             the labels produced by iteration t's assignment */
+  int64_t* iter_counters; /* HOST, optional: max_iters x KNOR_NCOUNTERS; row
+                             t receives that iteration's counters (below)    */
+  int32_t poll_every;   /* knor_fit checks convergence on the host every this
+                           many iterations (default 4); iterations enqueued
+                           after convergence do no work                       */
+  double* profile_ms;   /* HOST, optional: KNOR_NPROF entries.  knor_fit adds
+                           the GPU time (HIP events on opts->stream) of every
+                           launch of each kernel group (below)               */
+  int64_t* profile_launches; /* HOST, optional: KNOR_NPROF launch counts     */
+} knor_opts;
+
+/* Kernel groups timed by opts->profile_ms. */
+enum {
+  KNOR_PROF_ASSIGN_DENSE = 0, /* distance tile + argmin over all points      */
+  KNOR_PROF_ASSIGN_LIST = 1,  /* distance tile + argmin over MTI survivors   */
+  KNOR_PROF_RECHECK = 2,      /* FP64 recheck of near-tie points             */
+  KNOR_PROF_FILTER = 3,       /* MTI bound update, Clause 1 and tightening   */
+  KNOR_PROF_SORT = 4,         /* update pass 1: stable counting sort          */
+  KNOR_PROF_LEAF = 5,         /* update pass 2: leaf sums (gathers X)         */
+  KNOR_PROF_TREE = 6,         /* update pass 2: tree, division, operands      */
+  KNOR_PROF_CC = 7,           /* MTI centroid-pair bounds s(c)                */
+  KNOR_NPROF = 8
+};
+
+/* Per-iteration counters (columns of opts->iter_counters). */
+enum {
+  KNOR_CNT_CHANGED = 0,   /* labels that differ from the previous iteration  */
+  KNOR_CNT_SCANNED = 1,   /* points whose distances to all k were evaluated  */
+  KNOR_CNT_PRUNED_A = 2,  /* MTI: decided by the drift-updated bound          */
+  KNOR_CNT_PRUNED_B = 3,  /* MTI: decided after tightening the bound          */
+  KNOR_CNT_RECHECKED = 4, /* points recomputed in FP64                        */
+  KNOR_NCOUNTERS = 8
+};
+
+typedef struct {
+  int32_t iters;          /* iterations performed                            */
+  int32_t converged;      /* 1 if #changed <= tol * n was reached            */
+  int64_t changed_last;   /* #changed in the last iteration                  */
+  int64_t dists_computed; /* point-centroid distances evaluated (all iters)  */
+  int64_t scanned;        /* sum of KNOR_CNT_SCANNED                         */
+  int64_t pruned_a;       /* sum of KNOR_CNT_PRUNED_A                        */
+  int64_t pruned_b;       /* sum of KNOR_CNT_PRUNED_B                        */
+  int64_t rechecked;      /* sum of KNOR_CNT_RECHECKED                       */
+  double objective;       /* sum over points of D(x, c_label) for the final
+                             labels and the centroids they were assigned to  */
+  double seconds;         /* wall time of the call                           */
+} knor_stats;
+
+/* knor_fit: Lloyd's algorithm (Sections "Introduction", "Parallel Lloyd's
+ * Algorithm"; MTI per Section "Minimal Triangle Inequality (MTI) Pruning"
+ * when opts->prune = 1).  Iteration t assigns every point to its nearest
+ * centroid, counts changed labels (all n at t = 0), replaces each centroid
+ * by the mean of its members, and stops once #changed <= tol * n or after
+ * max_iters iterations.  The returned centroids are the means of the
+ * returned labels.
+ *   X          DEVICE n x d, dtype dt.
+ *   C_init     DEVICE k x d FP64 when init == KNOR_INIT_GIVEN, else NULL.
+ *   max_iters  >= 1.       tol  in [0, 1).
+ *   opts       may be NULL (defaults).
+ *   C_out      DEVICE k x d FP64, written on success.
+ *   labels_out DEVICE n int32, written on success.
+ *   st         HOST, may be NULL.
+ * Blocks until the fit is complete.  Labels do not depend on prune or on
+ * the storage dtype beyond the values X holds. */
+knor_status knor_fit(const void* X, knor_dtype dt, int64_t n, int32_t d,
+                     int32_t k, knor_init init, const double* C_init,
+                     int32_t max_iters, double tol, const knor_opts* opts,
+                     double* C_out, int32_t* labels_out, knor_stats* st);
+
+/* knor_assign: one assignment step (Algorithm 1, nearest-centroid loop).
+ *   C          DEVICE k x d FP64.
+ *   labels_out DEVICE n int32: the nearest centroid of every point.
+ *   dist2_out  DEVICE n FP64 or NULL: D(x, c_label) evaluated in FP64 in
+ *              index order (the same value the definition above compares).
+ * Asynchronous on opts->stream. */
+knor_status knor_assign(const void* X, knor_dtype dt, int64_t n, int32_t d,
+                        const double* C, int32_t k, const knor_opts* opts,
+                        int32_t* labels_out, double* dist2_out);
+
+/* knor_update: one centroid update (Phase II; the merge of Algorithm 1).
+ *   labels     DEVICE n int32, each in [0, k).  A label outside that range
+ *              is not detected on the device; the caller guarantees range.
+ *   C_prev     DEVICE k x d FP64: kept for clusters without members.
+ *   C_out      DEVICE k x d FP64 (may equal C_prev).
+ *   counts_out DEVICE k int64 or NULL: members per cluster.
+ * Asynchronous on opts->stream. */
+knor_status knor_update(const void* X, knor_dtype dt, int64_t n, int32_t d,
+                        const int32_t* labels, int32_t k,
+                        const double* C_prev, const knor_opts* opts,
+                        double* C_out, int64_t* counts_out);
+
+/* Human-readable name of a status code (static storage). */
+const char* knor_status_string(knor_status s);
+
+/* Library version as major*10000 + minor*100 + patch. */
+int32_t knor_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* KNOR_H */

@@ -100,6 +100,8 @@ class Oracle:
         L.oracle_canonical_sum.argtypes = [P, i64]
         L.oracle_canonical_sum.restype = f64
         L.oracle_num_threads.restype = ctypes.c_int
+        L.oracle_objective.argtypes = [P, i64, ctypes.c_int, P, P]
+        L.oracle_objective.restype = f64
         self.L = L
 
     def num_threads(self) -> int:
@@ -135,6 +137,14 @@ class Oracle:
     def canonical_sum(self, v) -> float:
         v = _f64(v)
         return float(self.L.oracle_canonical_sum(_ptr(v), v.size))
+
+    def objective(self, X, C, labels) -> float:
+        """Canonical sum over points of D(x_p, c_{labels[p]})."""
+        X, C = _f64(X), _f64(C)
+        labels = np.ascontiguousarray(labels, dtype=np.int32)
+        n, d = X.shape
+        return float(self.L.oracle_objective(_ptr(X), n, d, _ptr(C),
+                                             _ptr(labels)))
 
     def cc_bounds(self, C):
         C = _f64(C)
@@ -215,6 +225,10 @@ def canonical_sum(v):
 
 def cc_bounds(C):
     return default().cc_bounds(C)
+
+
+def objective(X, C, labels):
+    return default().objective(X, C, labels)
 
 
 def fit(X, C0, max_iters, tol=0.0, history=False, objective=True):

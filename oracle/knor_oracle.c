@@ -398,6 +398,18 @@ int oracle_cc_bounds(const double* C, int k, int d, double* s) {
   return OR_OK;
 }
 
+/* Objective for given labels: canonical sum over points of D(x_p, c_{l_p}). */
+double oracle_objective(const double* X, int64_t n, int d, const double* C,
+                        const int32_t* labels) {
+  double* D = (double*)malloc(sizeof(double) * (size_t)(n ? n : 1));
+#pragma omp parallel for schedule(static)
+  for (int64_t p = 0; p < n; ++p)
+    D[p] = oracle_dist2(X + (size_t)p * d, C + (size_t)labels[p] * d, d);
+  double s = oracle_canonical_sum(D, n);
+  free(D);
+  return s;
+}
+
 int oracle_num_threads(void) {
 #ifdef _OPENMP
   return omp_get_max_threads();

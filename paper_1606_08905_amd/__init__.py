@@ -1,0 +1,238 @@
+"""Python binding of the MI355X k-means library (libknor.so, C ABI in
+include/knor.h).
+
+Argument marshalling only: tensors must already live on the GPU; every step
+of the Lloyd iteration runs in the library's HIP kernels.  There is no CPU
+fallback -- importing works without a GPU, but every call needs the built
+library and a visible GPU, and fails loudly otherwise.
+
+    C, labels, stats = fit(X, k, C0=C0, max_iters=100, tol=0.0, prune=True)
+    labels = assign(X, C)
+    C_new, counts = update(X, labels, C_prev)
+
+X: (n, d) CUDA tensor of float64, float32 or bfloat16, row-major contiguous.
+C, C0, C_prev: (k, d) CUDA float64.  labels: (n,) CUDA int32.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+__all__ = ["fit", "assign", "update", "load", "KnorError", "COUNTERS",
+           "library_path"]
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+_LIB = os.path.join(_PKG, "libknor.so")
+
+KNOR_OK, KNOR_ERR_INVALID_ARG, KNOR_ERR_OUT_OF_MEMORY, KNOR_ERR_HIP, \
+    KNOR_ERR_NUMERIC, KNOR_ERR_UNSUPPORTED = range(6)
+INIT_GIVEN, INIT_FORGY = 0, 1
+NCOUNTERS = 8
+COUNTERS = ("changed", "scanned", "pruned_a", "pruned_b", "rechecked")
+
+
+class KnorError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"knor error {code}: {msg}")
+        self.code = code
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_uint32), ("prune", ctypes.c_int32),
+                ("recheck", ctypes.c_int32), ("check_numeric", ctypes.c_int32),
+                ("seed", ctypes.c_uint64), ("stream", ctypes.c_void_p),
+                ("workspace_cap", ctypes.c_size_t),
+                ("label_history", ctypes.c_void_p),
+                ("iter_counters", ctypes.c_void_p),
+                ("poll_every", ctypes.c_int32),
+                ("profile_ms", ctypes.c_void_p),
+                ("profile_launches", ctypes.c_void_p)]
+
+
+NPROF = 8
+PROF_GROUPS = ("assign_dense", "assign_list", "recheck", "filter", "sort",
+               "leaf", "tree", "cc")
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int32), ("converged", ctypes.c_int32),
+                ("changed_last", ctypes.c_int64),
+                ("dists_computed", ctypes.c_int64),
+                ("scanned", ctypes.c_int64), ("pruned_a", ctypes.c_int64),
+                ("pruned_b", ctypes.c_int64), ("rechecked", ctypes.c_int64),
+                ("objective", ctypes.c_double), ("seconds", ctypes.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+_lib = None
+
+
+def library_path() -> str:
+    return _LIB
+
+
+def load():
+    """Load libknor.so (raises if it was not built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB):
+        raise RuntimeError(
+            f"{_LIB} is missing: build it first (python -m "
+            "paper_1606_08905_amd._build); there is no CPU fallback")
+    L = ctypes.CDLL(_LIB)
+    P, i32, i64, f64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    L.knor_fit.argtypes = [P, ctypes.c_int, i64, i32, i32, ctypes.c_int, P, i32,
+                           f64, ctypes.POINTER(Opts), P, P, ctypes.POINTER(Stats)]
+    L.knor_fit.restype = ctypes.c_int
+    L.knor_assign.argtypes = [P, ctypes.c_int, i64, i32, P, i32,
+                              ctypes.POINTER(Opts), P, P]
+    L.knor_assign.restype = ctypes.c_int
+    L.knor_update.argtypes = [P, ctypes.c_int, i64, i32, P, i32, P,
+                              ctypes.POINTER(Opts), P, P]
+    L.knor_update.restype = ctypes.c_int
+    L.knor_status_string.argtypes = [ctypes.c_int]
+    L.knor_status_string.restype = ctypes.c_char_p
+    L.knor_version.restype = ctypes.c_int32
+    _lib = L
+    return L
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _dtype_code(t):
+    torch = _torch()
+    m = {torch.float64: 0, torch.float32: 1, torch.bfloat16: 2}
+    if t.dtype not in m:
+        raise TypeError(f"unsupported point dtype {t.dtype}")
+    return m[t.dtype]
+
+
+def _check_dev(t, name):
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a GPU tensor (no CPU path exists)")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+
+
+def _raise(rc):
+    if rc != KNOR_OK:
+        raise KnorError(rc, load().knor_status_string(rc).decode())
+
+
+def _opts(prune=True, recheck=1, check_numeric=True, seed=0, stream=None,
+          workspace_cap=0, label_history=None, iter_counters=None,
+          poll_every=4, profile=None):
+    torch = _torch()
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    o = Opts()
+    o.struct_size = ctypes.sizeof(Opts)
+    o.prune = 1 if prune else 0
+    o.recheck = int(recheck)
+    o.check_numeric = 1 if check_numeric else 0
+    o.seed = int(seed)
+    o.stream = ctypes.c_void_p(stream.cuda_stream)
+    o.workspace_cap = int(workspace_cap)
+    o.label_history = label_history.data_ptr() if label_history is not None else None
+    o.iter_counters = iter_counters.ctypes.data if iter_counters is not None else None
+    o.poll_every = int(poll_every)
+    if profile is not None:
+        ms, launches = profile
+        o.profile_ms = ms.ctypes.data
+        o.profile_launches = launches.ctypes.data
+    return o
+
+
+def fit(X, k, C0=None, init="given", max_iters=100, tol=0.0, prune=True,
+        recheck=1, seed=0, history=False, counters=False, out=None,
+        check_numeric=True, workspace_cap=0, poll_every=4, profile=None):
+    """Lloyd's k-means on the GPU.  Returns (C, labels, stats dict).
+
+    history=True adds stats["label_history"]: (iters, n) int32 CUDA tensor of
+    the labels each iteration's assignment produced.  counters=True adds
+    stats["counters"]: (iters, 8) int64 numpy array (KNOR_CNT_* columns).
+    out=(C, labels) reuses preallocated output tensors.  profile=(ms, launches)
+    (float64 and int64 numpy arrays of NPROF entries) accumulates per-group
+    GPU time measured with HIP events on the launch stream."""
+    torch = _torch()
+    import numpy as np
+    L = load()
+    _check_dev(X, "X")
+    n, d = X.shape
+    dev = X.device
+    if out is None:
+        C = torch.empty((k, d), dtype=torch.float64, device=dev)
+        lab = torch.empty((n,), dtype=torch.int32, device=dev)
+    else:
+        C, lab = out
+    init_code = INIT_GIVEN if init == "given" else INIT_FORGY
+    if init_code == INIT_GIVEN:
+        if C0 is None:
+            raise ValueError("init='given' needs C0")
+        C0 = torch.as_tensor(C0, dtype=torch.float64, device=dev).contiguous()
+        c0p = C0.data_ptr()
+    else:
+        c0p = None
+    hist = torch.empty((max_iters, n), dtype=torch.int32, device=dev) if history else None
+    cnt = np.zeros((max_iters, NCOUNTERS), np.int64) if counters else None
+    o = _opts(prune, recheck, check_numeric, seed, None, workspace_cap, hist,
+              cnt, poll_every, profile)
+    st = Stats()
+    rc = L.knor_fit(X.data_ptr(), _dtype_code(X), n, d, k, init_code, c0p,
+                    max_iters, float(tol), ctypes.byref(o), C.data_ptr(),
+                    lab.data_ptr(), ctypes.byref(st))
+    _raise(rc)
+    s = st.as_dict()
+    if history:
+        s["label_history"] = hist[: st.iters]
+    if counters:
+        s["counters"] = cnt[: st.iters]
+    return C, lab, s
+
+
+def assign(X, C, recheck=1, dist2=False):
+    """Nearest centroid of every row of X (and, with dist2=True, the FP64
+    squared distance to it).  Asynchronous on the current stream."""
+    torch = _torch()
+    L = load()
+    _check_dev(X, "X")
+    _check_dev(C, "C")
+    if C.dtype != torch.float64:
+        raise TypeError("C must be float64")
+    n, d = X.shape
+    k = C.shape[0]
+    lab = torch.empty((n,), dtype=torch.int32, device=X.device)
+    dd = torch.empty((n,), dtype=torch.float64, device=X.device) if dist2 else None
+    o = _opts(recheck=recheck)
+    rc = L.knor_assign(X.data_ptr(), _dtype_code(X), n, d, C.data_ptr(), k,
+                       ctypes.byref(o), lab.data_ptr(),
+                       dd.data_ptr() if dd is not None else None)
+    _raise(rc)
+    return (lab, dd) if dist2 else lab
+
+
+def update(X, labels, C_prev):
+    """Centroids as member means (empty clusters keep C_prev) and counts."""
+    torch = _torch()
+    L = load()
+    _check_dev(X, "X")
+    _check_dev(labels, "labels")
+    _check_dev(C_prev, "C_prev")
+    if labels.dtype != torch.int32 or C_prev.dtype != torch.float64:
+        raise TypeError("labels must be int32 and C_prev float64")
+    n, d = X.shape
+    k = C_prev.shape[0]
+    C = torch.empty_like(C_prev)
+    cnt = torch.empty((k,), dtype=torch.int64, device=X.device)
+    o = _opts()
+    rc = L.knor_update(X.data_ptr(), _dtype_code(X), n, d, labels.data_ptr(), k,
+                       C_prev.data_ptr(), ctypes.byref(o), C.data_ptr(),
+                       cnt.data_ptr())
+    _raise(rc)
+    return C, cnt

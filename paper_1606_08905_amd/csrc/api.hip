@@ -1,0 +1,555 @@
+// C ABI of the k-means library: argument validation, stream-ordered device
+// workspace, and the Lloyd iteration driver (Mhembere et al., HPDC'17,
+// Sections "Parallel Lloyd's Algorithm" and "Minimal Triangle Inequality
+// (MTI) Pruning").  Every arithmetic step runs in the kernels of this
+// library; the host only validates, allocates, enqueues and polls.
+#include <chrono>
+#include <math.h>
+#include <string.h>
+#include <unordered_map>
+#include <vector>
+
+#include "common.h"
+
+namespace knor {
+
+// ---------------------------------------------------------------------------
+// small kernels
+// ---------------------------------------------------------------------------
+
+template <typename T>
+__global__ __launch_bounds__(256) void check_finite_kernel(const T* __restrict__ p,
+                                                           int64_t count,
+                                                           int* __restrict__ bad) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  bool b = false;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride)
+    b |= !isfinite(to_f64<T>(p[i]));
+  if (__ballot(b) && lane_id() == 0) atomicOr(bad, 1);
+}
+
+hipError_t launch_check_finite(const void* p, knor_dtype dt, int64_t count,
+                               int* bad, hipStream_t s) {
+  int64_t blocks = (count + 255) / 256;
+  int grid = (int)(blocks < 4096 ? (blocks < 1 ? 1 : blocks) : 4096);
+  switch (dt) {
+    case KNOR_F64:
+      hipLaunchKernelGGL(check_finite_kernel<double>, dim3(grid), dim3(256), 0,
+                         s, (const double*)p, count, bad);
+      break;
+    case KNOR_F32:
+      hipLaunchKernelGGL(check_finite_kernel<float>, dim3(grid), dim3(256), 0,
+                         s, (const float*)p, count, bad);
+      break;
+    case KNOR_BF16:
+      hipLaunchKernelGGL(check_finite_kernel<uint16_t>, dim3(grid), dim3(256), 0,
+                         s, (const uint16_t*)p, count, bad);
+      break;
+  }
+  return hipGetLastError();
+}
+
+__global__ void fill_i32_kernel(int32_t* p, int64_t count, int32_t v,
+                                const int* done) {
+  if (done && *done) return;
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) p[i] = v;
+}
+
+hipError_t launch_fill_i32(int32_t* p, int64_t count, int32_t v,
+                           const int* done, hipStream_t s) {
+  if (count == 0) return hipSuccess;
+  hipLaunchKernelGGL(fill_i32_kernel, dim3((count + 255) / 256), dim3(256), 0,
+                     s, p, count, v, done);
+  return hipGetLastError();
+}
+
+__global__ void copy_i32_kernel(const int32_t* __restrict__ a,
+                                int32_t* __restrict__ b, int64_t count,
+                                const int* done) {
+  if (done && *done) return;
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) b[i] = a[i];
+}
+
+hipError_t launch_copy_i32(const int32_t* a, int32_t* b, int64_t count,
+                           const int* done, hipStream_t s) {
+  if (count == 0) return hipSuccess;
+  hipLaunchKernelGGL(copy_i32_kernel, dim3((count + 255) / 256), dim3(256), 0,
+                     s, a, b, count, done);
+  return hipGetLastError();
+}
+
+// Iteration t's stopping rule: #changed <= tol * n.
+__global__ void converge_kernel(const unsigned long long* ctr, double tol_n,
+                                int t, int* done, int* iters) {
+  if (*done) return;
+  *iters = t + 1;
+  if ((double)ctr[CNT_CHANGED] <= tol_n) *done = 1;
+}
+
+hipError_t launch_converge(const unsigned long long* ctr, double tol_n, int t,
+                           int* done, int* iters, hipStream_t s) {
+  hipLaunchKernelGGL(converge_kernel, dim3(1), dim3(1), 0, s, ctr, tol_n, t,
+                     done, iters);
+  return hipGetLastError();
+}
+
+template <typename T>
+__global__ void gather_rows_kernel(const T* __restrict__ X, int d,
+                                   const int64_t* __restrict__ rows, int k,
+                                   double* __restrict__ C) {
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (int64_t)k * d) return;
+  int j = (int)(e / d), i = (int)(e - (int64_t)j * d);
+  C[e] = to_f64<T>(X[(size_t)rows[j] * d + i]);
+}
+
+hipError_t launch_gather_rows(const void* X, knor_dtype dt, int d,
+                              const int64_t* rows, int k, double* C,
+                              hipStream_t s) {
+  int64_t tot = (int64_t)k * d;
+  dim3 g((tot + 255) / 256);
+  switch (dt) {
+    case KNOR_F64:
+      hipLaunchKernelGGL(gather_rows_kernel<double>, g, dim3(256), 0, s,
+                         (const double*)X, d, rows, k, C);
+      break;
+    case KNOR_F32:
+      hipLaunchKernelGGL(gather_rows_kernel<float>, g, dim3(256), 0, s,
+                         (const float*)X, d, rows, k, C);
+      break;
+    case KNOR_BF16:
+      hipLaunchKernelGGL(gather_rows_kernel<uint16_t>, g, dim3(256), 0, s,
+                         (const uint16_t*)X, d, rows, k, C);
+      break;
+  }
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// kernel-group timing
+// ---------------------------------------------------------------------------
+
+void Prof::begin(int g) {
+  if (!on) return;
+  hipEvent_t a = nullptr, b = nullptr;
+  if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) {
+    (void)hipGetLastError();
+    on = false;
+    return;
+  }
+  (void)hipEventRecord(a, stream);
+  groups.push_back(g);
+  starts.push_back(a);
+  ends.push_back(b);
+}
+
+void Prof::end() {
+  if (!on || ends.empty()) return;
+  (void)hipEventRecord(ends.back(), stream);
+}
+
+void Prof::collect(double* ms, int64_t* launches) {
+  if (groups.empty()) return;
+  (void)hipEventSynchronize(ends.back());
+  for (size_t i = 0; i < groups.size(); ++i) {
+    float t = 0.0f;
+    if (hipEventElapsedTime(&t, starts[i], ends[i]) != hipSuccess) {
+      (void)hipGetLastError();
+      continue;
+    }
+    if (ms) ms[groups[i]] += t;
+    if (launches) launches[groups[i]] += 1;
+  }
+}
+
+Prof::~Prof() {
+  for (auto e : starts) (void)hipEventDestroy(e);
+  for (auto e : ends) (void)hipEventDestroy(e);
+}
+
+// ---------------------------------------------------------------------------
+// workspace: one stream-ordered allocation carved into aligned pieces
+// ---------------------------------------------------------------------------
+
+struct Arena {
+  size_t bytes = 0;
+  std::vector<std::pair<void**, size_t>> want;
+  void add(void** slot, size_t b) {
+    want.push_back({slot, b});
+    bytes += (b + 255) & ~(size_t)255;
+  }
+  char* base = nullptr;
+  hipStream_t stream = nullptr;
+  knor_status alloc(hipStream_t s, size_t cap) {
+    stream = s;
+    if (cap && bytes > cap) return KNOR_ERR_OUT_OF_MEMORY;
+    if (bytes == 0) return KNOR_OK;
+    if (hipMallocAsync((void**)&base, bytes, s) != hipSuccess) {
+      (void)hipGetLastError();
+      base = nullptr;
+      return KNOR_ERR_OUT_OF_MEMORY;
+    }
+    char* c = base;
+    for (auto& w : want) {
+      *w.first = c;
+      c += (w.second + 255) & ~(size_t)255;
+    }
+    return KNOR_OK;
+  }
+  ~Arena() {
+    if (base) (void)hipFreeAsync(base, stream);
+  }
+};
+
+struct Opts {
+  int prune = 1, recheck = 1, check_numeric = 1, poll_every = 4;
+  uint64_t seed = 0;
+  hipStream_t stream = nullptr;
+  size_t cap = 0;
+  int32_t* label_history = nullptr;
+  int64_t* iter_counters = nullptr;
+  double* profile_ms = nullptr;
+  int64_t* profile_launches = nullptr;
+};
+
+static knor_status read_opts(const knor_opts* o, Opts* out) {
+  if (!o || o->struct_size == 0) return KNOR_OK;
+  if (o->struct_size != sizeof(knor_opts)) return KNOR_ERR_INVALID_ARG;
+  if (o->prune < 0 || o->prune > 1) return KNOR_ERR_INVALID_ARG;
+  if (o->recheck < 1 || o->recheck > 2) return KNOR_ERR_INVALID_ARG;
+  if (o->check_numeric < 0 || o->check_numeric > 1) return KNOR_ERR_INVALID_ARG;
+  if (o->poll_every < 0) return KNOR_ERR_INVALID_ARG;
+  out->prune = o->prune;
+  out->recheck = o->recheck;
+  out->check_numeric = o->check_numeric;
+  out->seed = o->seed;
+  out->stream = (hipStream_t)o->stream;
+  out->cap = o->workspace_cap;
+  out->label_history = o->label_history;
+  out->iter_counters = o->iter_counters;
+  out->profile_ms = o->profile_ms;
+  out->profile_launches = o->profile_launches;
+  if (o->poll_every > 0) out->poll_every = o->poll_every;
+  return KNOR_OK;
+}
+
+static bool dtype_ok(knor_dtype dt) {
+  return dt == KNOR_F64 || dt == KNOR_F32 || dt == KNOR_BF16;
+}
+
+#define HIPCHK(x)                                   \
+  do {                                              \
+    if ((x) != hipSuccess) {                        \
+      (void)hipGetLastError();                      \
+      return KNOR_ERR_HIP;                          \
+    }                                               \
+  } while (0)
+
+// SplitMix64 (Steele, Lea, Flood 2014).
+static uint64_t splitmix64(uint64_t* state) {
+  uint64_t z = (*state += 0x9e3779b97f4a7c15ull);
+  z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+  z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+  return z ^ (z >> 31);
+}
+
+// The last k slots of a Fisher-Yates pass over 0..n-1 (i = n-1 down to n-k).
+static std::vector<int64_t> forgy_rows(int64_t n, int k, uint64_t seed) {
+  std::unordered_map<int64_t, int64_t> swapped;
+  auto at = [&](int64_t i) {
+    auto it = swapped.find(i);
+    return it == swapped.end() ? i : it->second;
+  };
+  uint64_t st = seed;
+  std::vector<int64_t> rows(k);
+  for (int r = 0; r < k; ++r) {
+    int64_t i = n - 1 - r;
+    int64_t j = (int64_t)(splitmix64(&st) % (uint64_t)(i + 1));
+    int64_t vi = at(i), vj = at(j);
+    swapped[i] = vj;
+    swapped[j] = vi;
+    rows[r] = vj;
+  }
+  return rows;
+}
+
+// ---------------------------------------------------------------------------
+// fit
+// ---------------------------------------------------------------------------
+
+static knor_status fit_impl(const void* X, knor_dtype dt, int64_t n, int d,
+                            int k, knor_init init, const double* C_init,
+                            int max_iters, double tol, const Opts& o,
+                            double* C_out, int32_t* labels_out,
+                            knor_stats* st) {
+  auto t0 = std::chrono::steady_clock::now();
+  hipStream_t s = o.stream;
+  const int kpad = (k + 15) / 16 * 16;
+  const int dp = pad_dim(d);
+  const bool mti = o.prune == 1;
+
+  CentroidOps ops{};
+  ops.k = k; ops.kpad = kpad; ops.d = d; ops.dp = dp;
+  ops.C64 = C_out;
+  UpdatePlan plan{};
+  void* upd_ws = nullptr;
+  float *u = nullptr, *drift = nullptr, *s_half = nullptr;
+  int *surv = nullptr, *flags = nullptr, *flagbuf = nullptr;
+  unsigned long long* ctr = nullptr;
+  int64_t* rows_dev = nullptr;
+  double *dist2 = nullptr, *sumtmp = nullptr, *objective = nullptr;
+  int32_t* prev_labels = nullptr;
+  (void)prev_labels;
+
+  Arena ar;
+  ar.add((void**)&ops.Cm2, sizeof(float) * (size_t)kpad * dp);
+  ar.add((void**)&ops.cn, sizeof(float) * (size_t)kpad);
+  ar.add((void**)&drift, sizeof(float) * (size_t)k);
+  ar.add((void**)&s_half, sizeof(float) * (size_t)k);
+  ar.add((void**)&flags, sizeof(int) * (size_t)n);
+  if (mti) {
+    ar.add((void**)&u, sizeof(float) * (size_t)n);
+    ar.add((void**)&surv, sizeof(int) * (size_t)n);
+  }
+  ar.add((void**)&ctr, sizeof(unsigned long long) * CNT_ROWS * (size_t)(max_iters + 1));
+  ar.add((void**)&flagbuf, sizeof(int) * 8);   // done, iters, bad
+  ar.add((void**)&rows_dev, sizeof(int64_t) * (size_t)k);
+  ar.add(&upd_ws, update_workspace_bytes(n, k, d));
+  ar.add((void**)&dist2, sizeof(double) * (size_t)n);
+  ar.add((void**)&sumtmp, sizeof(double) * (size_t)(n / kLeaf + 2));
+  ar.add((void**)&objective, sizeof(double));
+  knor_status rs = ar.alloc(s, o.cap);
+  if (rs != KNOR_OK) return rs;
+  update_plan_init(&plan, n, k, d, upd_ws);
+  int* done = flagbuf;
+  int* iters_dev = flagbuf + 1;
+  int* bad = flagbuf + 2;
+
+  HIPCHK(hipMemsetAsync(flagbuf, 0, sizeof(int) * 8, s));
+  HIPCHK(hipMemsetAsync(ctr, 0, sizeof(unsigned long long) * CNT_ROWS * (size_t)(max_iters + 1), s));
+
+  // numeric check of the inputs before anything is written to the outputs
+  if (o.check_numeric) {
+    HIPCHK(launch_check_finite(X, dt, n * (int64_t)d, bad, s));
+    if (init == KNOR_INIT_GIVEN)
+      HIPCHK(launch_check_finite(C_init, KNOR_F64, (int64_t)k * d, bad, s));
+    int hbad = 0;
+    HIPCHK(hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (hbad) return KNOR_ERR_NUMERIC;
+  }
+
+  // initial centroids into the working buffer C_out
+  if (init == KNOR_INIT_GIVEN) {
+    if (C_init != C_out)
+      HIPCHK(hipMemcpyAsync(C_out, C_init, sizeof(double) * (size_t)k * d,
+                            hipMemcpyDeviceToDevice, s));
+  } else {
+    std::vector<int64_t> rows = forgy_rows(n, k, o.seed);
+    HIPCHK(hipMemcpyAsync(rows_dev, rows.data(), sizeof(int64_t) * k,
+                          hipMemcpyHostToDevice, s));
+    HIPCHK(launch_gather_rows(X, dt, d, rows_dev, k, C_out, s));
+    HIPCHK(hipStreamSynchronize(s));   // `rows` leaves scope
+  }
+  HIPCHK(launch_prep_centroids(ops, s));
+  HIPCHK(launch_fill_i32(labels_out, n, -1, nullptr, s));   // every label changes at t = 0
+
+  Prof prof;
+  prof.stream = s;
+  prof.on = o.profile_ms != nullptr || o.profile_launches != nullptr;
+  Prof* pp = prof.on ? &prof : nullptr;
+  const double tol_n = tol * (double)n;
+  int hdone = 0;
+  int t = 0;
+  for (t = 0; t < max_iters; ++t) {
+    unsigned long long* row = ctr + (size_t)t * CNT_ROWS;
+    AssignJob job{};
+    job.X = X; job.dt = dt; job.n = n; job.d = d;
+    job.labels = labels_out; job.u = mti ? u : nullptr;
+    job.flags = flags; job.ctr = row; job.done = done;
+    job.recheck_all = o.recheck == 2;
+    if (mti && t > 0) {
+      prof.begin(KNOR_PROF_FILTER);
+      HIPCHK(launch_mti_filter(X, dt, n, d, C_out, labels_out, u, drift, s_half,
+                               surv, row, done, s));
+      prof.end();
+      job.list = surv;
+      job.list_len = &row[CNT_SURVIVORS];
+    }
+    prof.begin(job.list ? KNOR_PROF_ASSIGN_LIST : KNOR_PROF_ASSIGN_DENSE);
+    HIPCHK(launch_assign(ops, job, s));
+    prof.end();
+    if (dt != KNOR_F64) {
+      prof.begin(KNOR_PROF_RECHECK);
+      HIPCHK(launch_recheck(ops, job, s));
+      prof.end();
+    }
+    if (o.label_history)
+      HIPCHK(launch_copy_i32(labels_out, o.label_history + (size_t)t * n, n, done, s));
+    HIPCHK(launch_update(plan, X, dt, labels_out, C_out, C_out, nullptr, &ops,
+                         mti ? drift : nullptr, done, s, pp));
+    if (mti) {
+      prof.begin(KNOR_PROF_CC);
+      HIPCHK(launch_cc_bounds(C_out, k, d, s_half, s));
+      prof.end();
+    }
+    HIPCHK(launch_converge(row, tol_n, t, done, iters_dev, s));
+    if ((t + 1) % o.poll_every == 0 || t + 1 == max_iters) {
+      HIPCHK(hipMemcpyAsync(&hdone, done, sizeof(int), hipMemcpyDeviceToHost, s));
+      HIPCHK(hipStreamSynchronize(s));
+      if (hdone) break;
+    }
+  }
+
+  // final objective: sum over points of D(x, C_out[label]) in the canonical order
+  HIPCHK(launch_exact_dist2(X, dt, n, d, C_out, labels_out, dist2, s));
+  HIPCHK(launch_canonical_sum(dist2, n, sumtmp, objective, s));
+
+  int hiters = 0;
+  std::vector<unsigned long long> hc((size_t)CNT_ROWS * (max_iters + 1));
+  double hobj = 0.0;
+  HIPCHK(hipMemcpyAsync(&hiters, iters_dev, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(&hdone, done, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(hc.data(), ctr, sizeof(unsigned long long) * hc.size(),
+                        hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(&hobj, objective, sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  prof.collect(o.profile_ms, o.profile_launches);
+
+  if (o.iter_counters)
+    for (int i = 0; i < hiters; ++i)
+      for (int c = 0; c < KNOR_NCOUNTERS; ++c)
+        o.iter_counters[(size_t)i * KNOR_NCOUNTERS + c] =
+            (int64_t)hc[(size_t)i * CNT_ROWS + c];
+  if (st) {
+    memset(st, 0, sizeof(*st));
+    st->iters = hiters;
+    st->converged = hdone;
+    st->changed_last = hiters > 0 ? (int64_t)hc[(size_t)(hiters - 1) * CNT_ROWS + CNT_CHANGED] : 0;
+    for (int i = 0; i < hiters; ++i) {
+      const unsigned long long* r = &hc[(size_t)i * CNT_ROWS];
+      st->scanned += (int64_t)r[CNT_SCANNED];
+      st->pruned_a += (int64_t)r[CNT_PRUNED_A];
+      st->pruned_b += (int64_t)r[CNT_PRUNED_B];
+      st->rechecked += (int64_t)r[CNT_RECHECKED];
+      int64_t tighten = (mti && i > 0) ? (n - (int64_t)r[CNT_PRUNED_A]) : 0;
+      st->dists_computed += ((int64_t)r[CNT_SCANNED] + (int64_t)r[CNT_RECHECKED]) * k + tighten;
+    }
+    st->objective = hobj;
+    st->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  }
+  return KNOR_OK;
+}
+
+}  // namespace knor
+
+using namespace knor;
+
+extern "C" {
+
+const char* knor_status_string(knor_status s) {
+  switch (s) {
+    case KNOR_OK: return "ok";
+    case KNOR_ERR_INVALID_ARG: return "invalid argument";
+    case KNOR_ERR_OUT_OF_MEMORY: return "out of device memory or over workspace cap";
+    case KNOR_ERR_HIP: return "HIP runtime error";
+    case KNOR_ERR_NUMERIC: return "NaN or Inf in the input";
+    case KNOR_ERR_UNSUPPORTED: return "unsupported by this build";
+  }
+  return "unknown status";
+}
+
+int32_t knor_version(void) { return 100; }
+
+knor_status knor_fit(const void* X, knor_dtype dt, int64_t n, int32_t d,
+                     int32_t k, knor_init init, const double* C_init,
+                     int32_t max_iters, double tol, const knor_opts* opts,
+                     double* C_out, int32_t* labels_out, knor_stats* st) {
+  Opts o;
+  if (knor_status r = read_opts(opts, &o)) return r;
+  if (!X || !C_out || !labels_out || !dtype_ok(dt)) return KNOR_ERR_INVALID_ARG;
+  if (n < 1 || n >= (int64_t)1 << 31 || d < 1 || d > kMaxD || k < 1 ||
+      k > kMaxK || (int64_t)k > n || max_iters < 1 || !(tol >= 0.0 && tol < 1.0))
+    return KNOR_ERR_INVALID_ARG;
+  if (init == KNOR_INIT_GIVEN) {
+    if (!C_init) return KNOR_ERR_INVALID_ARG;
+  } else if (init != KNOR_INIT_FORGY) {
+    return KNOR_ERR_INVALID_ARG;
+  }
+  if (dt == KNOR_BF16) return KNOR_ERR_UNSUPPORTED;
+  return fit_impl(X, dt, n, d, k, init, C_init, max_iters, tol, o, C_out,
+                  labels_out, st);
+}
+
+knor_status knor_assign(const void* X, knor_dtype dt, int64_t n, int32_t d,
+                        const double* C, int32_t k, const knor_opts* opts,
+                        int32_t* labels_out, double* dist2_out) {
+  Opts o;
+  if (knor_status r = read_opts(opts, &o)) return r;
+  if (!X || !C || !labels_out || !dtype_ok(dt)) return KNOR_ERR_INVALID_ARG;
+  if (n < 0 || n >= (int64_t)1 << 31 || d < 1 || d > kMaxD || k < 1 || k > kMaxK)
+    return KNOR_ERR_INVALID_ARG;
+  if (dt == KNOR_BF16) return KNOR_ERR_UNSUPPORTED;
+  if (n == 0) return KNOR_OK;
+  hipStream_t s = o.stream;
+  CentroidOps ops{};
+  ops.k = k; ops.kpad = (k + 15) / 16 * 16; ops.d = d; ops.dp = pad_dim(d);
+  ops.C64 = const_cast<double*>(C);
+  int* flags = nullptr;
+  unsigned long long* ctr = nullptr;
+  Arena ar;
+  ar.add((void**)&ops.Cm2, sizeof(float) * (size_t)ops.kpad * ops.dp);
+  ar.add((void**)&ops.cn, sizeof(float) * (size_t)ops.kpad);
+  ar.add((void**)&flags, sizeof(int) * (size_t)n);
+  ar.add((void**)&ctr, sizeof(unsigned long long) * (CNT_ROWS + 8));
+  if (knor_status r = ar.alloc(s, o.cap)) return r;
+  int* done = (int*)(ctr + CNT_ROWS);
+  HIPCHK(hipMemsetAsync(ctr, 0, sizeof(unsigned long long) * (CNT_ROWS + 8), s));
+  HIPCHK(launch_prep_centroids(ops, s));
+  AssignJob job{};
+  job.X = X; job.dt = dt; job.n = n; job.d = d;
+  job.labels = labels_out; job.flags = flags; job.ctr = ctr; job.done = done;
+  job.recheck_all = o.recheck == 2;
+  job.dist2 = nullptr;
+  HIPCHK(launch_assign(ops, job, s));
+  HIPCHK(launch_recheck(ops, job, s));
+  if (dist2_out)
+    HIPCHK(launch_exact_dist2(X, dt, n, d, C, labels_out, dist2_out, s));
+  return KNOR_OK;
+}
+
+knor_status knor_update(const void* X, knor_dtype dt, int64_t n, int32_t d,
+                        const int32_t* labels, int32_t k, const double* C_prev,
+                        const knor_opts* opts, double* C_out,
+                        int64_t* counts_out) {
+  Opts o;
+  if (knor_status r = read_opts(opts, &o)) return r;
+  if (!X || !labels || !C_prev || !C_out || !dtype_ok(dt))
+    return KNOR_ERR_INVALID_ARG;
+  if (n < 0 || n >= (int64_t)1 << 31 || d < 1 || d > kMaxD || k < 1 || k > kMaxK)
+    return KNOR_ERR_INVALID_ARG;
+  hipStream_t s = o.stream;
+  if (n == 0) {
+    if (C_out != C_prev)
+      HIPCHK(hipMemcpyAsync(C_out, C_prev, sizeof(double) * (size_t)k * d,
+                            hipMemcpyDeviceToDevice, s));
+    if (counts_out) HIPCHK(hipMemsetAsync(counts_out, 0, sizeof(int64_t) * k, s));
+    return KNOR_OK;
+  }
+  void* ws = nullptr;
+  int* done = nullptr;
+  Arena ar;
+  ar.add(&ws, update_workspace_bytes(n, k, d));
+  ar.add((void**)&done, sizeof(int) * 4);
+  if (knor_status r = ar.alloc(s, o.cap)) return r;
+  UpdatePlan plan{};
+  update_plan_init(&plan, n, k, d, ws);
+  HIPCHK(hipMemsetAsync(done, 0, sizeof(int) * 4, s));
+  HIPCHK(launch_update(plan, X, dt, labels, C_prev, C_out, counts_out, nullptr,
+                       nullptr, done, s));
+  return KNOR_OK;
+}
+
+}  // extern "C"

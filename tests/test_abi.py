@@ -1,0 +1,88 @@
+"""Host-only checks of the C ABI: the library loads, exports every function
+that include/knor.h declares, and rejects invalid arguments before touching
+any device memory (so these run without a GPU)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_1606_08905_amd as knor
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "knor.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(knor_[a-z_]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    if not os.path.exists(knor.library_path()):
+        pytest.skip("libknor.so not built")
+    return knor.load()
+
+
+def test_exports_every_declared_symbol(L):
+    names = _declared()
+    assert {"knor_fit", "knor_assign", "knor_update", "knor_status_string",
+            "knor_version"} <= set(names)
+    for nm in names:
+        assert hasattr(L, nm), nm
+
+
+def test_status_strings(L):
+    for code in range(6):
+        assert L.knor_status_string(code)
+    assert L.knor_version() >= 100
+
+
+FAKE = ctypes.c_void_p(0x1000)   # never dereferenced: validation fails first
+
+
+def _fit(L, **kw):
+    a = dict(X=FAKE, dt=1, n=100, d=8, k=4, init=0, C=FAKE, it=10, tol=0.0,
+             opts=None, Cout=FAKE, lab=FAKE, st=None)
+    a.update(kw)
+    return L.knor_fit(a["X"], a["dt"], a["n"], a["d"], a["k"], a["init"], a["C"],
+                      a["it"], a["tol"], a["opts"], a["Cout"], a["lab"], a["st"])
+
+
+@pytest.mark.parametrize("kw", [
+    dict(X=None), dict(dt=9), dict(n=0), dict(d=0), dict(d=257), dict(k=0),
+    dict(k=101), dict(k=20000, n=30000), dict(it=0), dict(tol=1.0),
+    dict(tol=-0.1), dict(tol=float("nan")), dict(init=0, C=None), dict(init=5),
+    dict(Cout=None), dict(lab=None), dict(n=1 << 31),
+])
+def test_fit_rejects_invalid(L, kw):
+    assert _fit(L, **kw) == knor.KNOR_ERR_INVALID_ARG
+
+
+def test_fit_rejects_bad_opts(L):
+    o = knor.Opts()
+    o.struct_size = 3
+    assert _fit(L, opts=ctypes.byref(o)) == knor.KNOR_ERR_INVALID_ARG
+    o = knor.Opts()
+    o.struct_size = ctypes.sizeof(knor.Opts)
+    o.prune = 1
+    o.recheck = 7
+    assert _fit(L, opts=ctypes.byref(o)) == knor.KNOR_ERR_INVALID_ARG
+
+
+def test_assign_update_reject_invalid(L):
+    P = FAKE
+    assert L.knor_assign(None, 1, 10, 4, P, 2, None, P, None) == knor.KNOR_ERR_INVALID_ARG
+    assert L.knor_assign(P, 1, 10, 0, P, 2, None, P, None) == knor.KNOR_ERR_INVALID_ARG
+    assert L.knor_assign(P, 1, 10, 4, P, 0, None, P, None) == knor.KNOR_ERR_INVALID_ARG
+    assert L.knor_update(P, 1, 10, 4, None, 2, P, None, P, None) == knor.KNOR_ERR_INVALID_ARG
+    assert L.knor_update(P, 1, -1, 4, P, 2, P, None, P, None) == knor.KNOR_ERR_INVALID_ARG
+    assert L.knor_update(P, 3, 10, 4, P, 2, P, None, P, None) == knor.KNOR_ERR_INVALID_ARG
+
+
+def test_binding_refuses_cpu_tensors():
+    import torch
+    X = torch.zeros((10, 4))
+    with pytest.raises((ValueError, RuntimeError)):
+        knor.fit(X, 2, C0=torch.zeros((2, 4), dtype=torch.float64))

@@ -1,0 +1,276 @@
+"""GPU parity: the HIP path against the FP64 oracle on the same seeded inputs.
+
+Bars: labels bit-exact (integer results); FP64 centroids bit-exact (both
+sides use the same canonical summation order and correctly rounded FP64
+division); the FP64 objective bit-exact (same canonical order).  Every call
+goes through the C ABI via the thin binding.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+
+def _knor():
+    import paper_1606_08905_amd as knor
+    knor.load()
+    return knor
+
+
+def _dev(a, dtype):
+    import torch
+    if dtype == "bf16":
+        return torch.from_numpy(a.view(np.int16)).cuda().view(torch.bfloat16)
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def _data(n, d, k, dtype="f32", seed=0, scale=1.0, shift=0.0):
+    rng = np.random.default_rng(seed)
+    kc = max(2, min(k, 64))
+    mu = rng.uniform(-10, 10, size=(kc, d)) * scale + shift
+    X = workloads.gaussian_mixture(rng, n, mu, np.full(kc, scale), np.ones(kc), dtype)
+    rows = workloads.distinct_rows(rng, n, k)
+    C = workloads.to_f64(X[rows], dtype).copy()
+    return X, C
+
+
+def _print_case(**kw):
+    print("CASE", kw, flush=True)
+
+
+# ---------------------------------------------------------------------------
+# assignment
+# ---------------------------------------------------------------------------
+
+ASSIGN_CASES = [
+    # n, d, k   (ragged n, d not a power of two, k not a multiple of 16)
+    (1, 3, 1), (100, 3, 2), (1000, 8, 7), (4097, 16, 16), (5000, 32, 100),
+    (3001, 33, 17), (2500, 64, 257), (2000, 100, 50), (1500, 128, 33),
+    (1000, 256, 20), (20000, 32, 1000), (777, 5, 300),
+]
+
+
+@pytest.mark.parametrize("n,d,k", ASSIGN_CASES)
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_assign_parity(n, d, k, dtype):
+    knor = _knor()
+    _print_case(test="assign", n=n, d=d, k=k, dtype=dtype)
+    X, C = _data(n, d, k, dtype, seed=n + d + k)
+    lab_o, D_o = oracle.assign(workloads.to_f64(X, dtype), C)
+    lab, dd = knor.assign(_dev(X, dtype), _dev(C, "f64"), dist2=True)
+    assert (lab.cpu().numpy() == lab_o).all()
+    assert (dd.cpu().numpy() == D_o).all()
+
+
+@pytest.mark.parametrize("recheck", [1, 2])
+def test_assign_ties_and_duplicates(recheck):
+    """Integer data: many exact ties; the lowest index must win."""
+    knor = _knor()
+    rng = np.random.default_rng(5)
+    X = rng.integers(-3, 4, size=(5000, 8)).astype(np.float32)
+    C = rng.integers(-3, 4, size=(40, 8)).astype(np.float64)
+    C[20:] = C[:20]                       # duplicated centroids: exact ties
+    lab_o, _ = oracle.assign(X.astype(np.float64), C)
+    lab = knor.assign(_dev(X, "f32"), _dev(C, "f64"), recheck=recheck)
+    assert (lab.cpu().numpy() == lab_o).all()
+
+
+@pytest.mark.parametrize("scale,shift", [(1e-3, 0.0), (1.0, 1e4), (1e3, 0.0), (1.0, -3e5)])
+def test_assign_far_from_origin(scale, shift):
+    """Large |x| relative to the cluster spread stresses the error bound."""
+    knor = _knor()
+    X, C = _data(6000, 32, 50, "f32", seed=3, scale=scale, shift=shift)
+    lab_o, _ = oracle.assign(X.astype(np.float64), C)
+    lab = knor.assign(_dev(X, "f32"), _dev(C, "f64"))
+    assert (lab.cpu().numpy() == lab_o).all()
+
+
+# ---------------------------------------------------------------------------
+# update
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("n,d,k", [(1, 4, 1), (100, 3, 5), (5000, 16, 10),
+                                   (70000, 32, 100), (20000, 64, 1000),
+                                   (9000, 33, 4096), (3000, 256, 7)])
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_update_parity(n, d, k, dtype):
+    knor = _knor()
+    _print_case(test="update", n=n, d=d, k=k, dtype=dtype)
+    rng = np.random.default_rng(n * 7 + k)
+    X = workloads.cast(rng.normal(size=(n, d)) * 5, dtype)
+    # skewed labels with empty clusters
+    lab = (rng.zipf(1.5, size=n) % k).astype(np.int32)
+    Cp = rng.normal(size=(k, d))
+    C_o, cnt_o = oracle.update(workloads.to_f64(X, dtype), lab, Cp)
+    C, cnt = knor.update(_dev(X, dtype), _dev(lab, None), _dev(Cp, "f64"))
+    assert (cnt.cpu().numpy() == cnt_o).all()
+    assert (C.cpu().numpy() == C_o).all()
+
+
+# ---------------------------------------------------------------------------
+# fit: identical labels at every iteration, bit-exact centroids
+# ---------------------------------------------------------------------------
+
+def _fit_compare(w_X, dtype, C0, k, iters, prune, recheck=1, tol=0.0,
+                 oracle_fit=None):
+    knor = _knor()
+    X64 = workloads.to_f64(w_X, dtype)
+    # the MTI oracle's labels equal plain Lloyd's at every iteration (pinned
+    # in test_oracle_pins); it is used where the plain oracle is too slow
+    ref = (oracle_fit or oracle.fit)(X64, C0, iters, tol=tol, history=True)
+    C, lab, st = knor.fit(_dev(w_X, dtype), k, C0=_dev(C0, "f64"),
+                          max_iters=iters, tol=tol, prune=prune,
+                          recheck=recheck, history=True, counters=True)
+    assert st["iters"] == ref.iters
+    assert bool(st["converged"]) == ref.converged
+    hist = st["label_history"].cpu().numpy()
+    for t in range(ref.iters):
+        assert (hist[t] == ref.label_hist[t]).all(), f"iteration {t}"
+    assert (lab.cpu().numpy() == ref.labels).all()
+    assert (C.cpu().numpy() == ref.C).all()
+    assert st["counters"][:, 0].tolist() == ref.changed.tolist()
+    obj = oracle.objective(X64, ref.C, ref.labels)
+    assert st["objective"] == obj
+    return st, ref
+
+
+@pytest.mark.parametrize("prune", [False, True])
+def test_fit_config1_full(prune):
+    w = workloads.config(1)
+    _print_case(test="fit-config1", prune=prune)
+    _fit_compare(w.X, w.dtype, w.C0, w.k, w.max_iters, prune)
+
+
+@pytest.mark.parametrize("prune", [False, True])
+@pytest.mark.parametrize("seed", [0, 2])
+def test_fit_config2_small(prune, seed):
+    w = workloads.config(2, n=40000, seed=seed)
+    _print_case(test="fit-config2-small", prune=prune, seed=seed)
+    st, ref = _fit_compare(w.X, w.dtype, w.C0, w.k, 60, prune)
+    if prune:
+        # most points are decided by the bounds after the first iterations
+        assert st["pruned_a"] + st["pruned_b"] > 0.3 * 40000 * (st["iters"] - 1)
+
+
+def test_fit_recheck_all_equals_oracle():
+    w = workloads.config(2, n=8000, k=30, seed=4)
+    _fit_compare(w.X, w.dtype, w.C0, w.k, 30, True, recheck=2)
+
+
+def test_fit_tol_early_stop():
+    w = workloads.config(2, n=20000, k=40, seed=5)
+    _fit_compare(w.X, w.dtype, w.C0, w.k, 50, True, tol=0.01)
+
+
+def test_fit_uniform_and_duplicates():
+    X = workloads.uniform_cube(30000, 8, "f32", seed=3)
+    _fit_compare(X, "f32", X[:64].astype(np.float64), 64, 25, True)
+    rng = np.random.default_rng(2)
+    base = rng.integers(-4, 5, size=(300, 4)).astype(np.float32)
+    Xd = base[rng.integers(0, 300, size=20000)]
+    _fit_compare(Xd, "f32", Xd[:12].astype(np.float64), 12, 30, True)
+
+
+def test_fit_k_edge_cases():
+    rng = np.random.default_rng(8)
+    X = rng.normal(size=(300, 5)).astype(np.float32)
+    _fit_compare(X, "f32", X[:1].astype(np.float64), 1, 5, True)
+    _fit_compare(X, "f32", X.astype(np.float64), 300, 5, True)   # k = n
+
+
+def _splitmix64(state):
+    M = (1 << 64) - 1
+    state = (state + 0x9E3779B97F4A7C15) & M
+    z = state
+    z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & M
+    z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & M
+    return state, z ^ (z >> 31)
+
+
+def _forgy_rows(n, k, seed):
+    # the last k slots of a Fisher-Yates pass, i = n-1 down to n-k
+    a = {}
+    st = seed
+    rows = []
+    for r in range(k):
+        i = n - 1 - r
+        st, z = _splitmix64(st)
+        j = z % (i + 1)
+        vi, vj = a.get(i, i), a.get(j, j)
+        a[i], a[j] = vj, vi
+        rows.append(vj)
+    return rows
+
+
+def test_fit_forgy_init_matches_given():
+    knor = _knor()
+    w = workloads.config(1, n=5000)
+    rows = _forgy_rows(5000, 10, 1234)
+    C0 = w.x64()[rows]
+    C1, l1, s1 = knor.fit(_dev(w.X, "f64"), 10, init="forgy", seed=1234, max_iters=20)
+    C2, l2, s2 = knor.fit(_dev(w.X, "f64"), 10, C0=_dev(C0, "f64"), max_iters=20)
+    assert (C1.cpu().numpy() == C2.cpu().numpy()).all()
+    assert (l1.cpu().numpy() == l2.cpu().numpy()).all()
+
+
+def test_fit_numeric_error_leaves_outputs():
+    import torch
+    knor = _knor()
+    X = torch.randn(1000, 8, device="cuda")
+    X[17, 3] = float("nan")
+    C0 = X[:4].double().clone()
+    C0[0] = 0
+    C = torch.full((4, 8), 7.0, dtype=torch.float64, device="cuda")
+    lab = torch.full((1000,), 3, dtype=torch.int32, device="cuda")
+    with pytest.raises(knor.KnorError) as e:
+        knor.fit(X, 4, C0=C0, out=(C, lab))
+    assert e.value.code == knor.KNOR_ERR_NUMERIC
+    assert (C == 7.0).all() and (lab == 3).all()
+
+
+def test_fit_workspace_cap():
+    import torch
+    knor = _knor()
+    X = torch.randn(1000, 8, device="cuda")
+    with pytest.raises(knor.KnorError) as e:
+        knor.fit(X, 4, C0=X[:4].double(), workspace_cap=1024)
+    assert e.value.code == knor.KNOR_ERR_OUT_OF_MEMORY
+
+
+def test_fit_deterministic_repeat():
+    knor = _knor()
+    w = workloads.config(2, n=30000, k=50, seed=1)
+    Xd = _dev(w.X, "f32")
+    a = knor.fit(Xd, 50, C0=_dev(w.C0, "f64"), max_iters=30)
+    b = knor.fit(Xd, 50, C0=_dev(w.C0, "f64"), max_iters=30)
+    assert (a[0] == b[0]).all() and (a[1] == b[1]).all()
+    assert a[2]["rechecked"] == b[2]["rechecked"]
+
+
+def test_resume_equals_uninterrupted():
+    """State (C, labels, t) resumes exactly: MTI is exact, so restarting from
+    the centroids of iteration t reproduces the remaining iterations."""
+    knor = _knor()
+    w = workloads.config(2, n=20000, k=40, seed=6)
+    Xd = _dev(w.X, "f32")
+    Cfull, lfull, sfull = knor.fit(Xd, 40, C0=_dev(w.C0, "f64"), max_iters=25)
+    Ca, la, sa = knor.fit(Xd, 40, C0=_dev(w.C0, "f64"), max_iters=10)
+    Cb, lb, sb = knor.fit(Xd, 40, C0=Ca, max_iters=15)
+    assert (Cb == Cfull).all() and (lb == lfull).all()
+
+
+# ---------------------------------------------------------------------------
+# full-size configuration 2 (the benchmark workload)
+# ---------------------------------------------------------------------------
+
+def test_fit_config2_full_size():
+    w = workloads.config(2)
+    _print_case(test="fit-config2-full")
+    st, ref = _fit_compare(w.X, w.dtype, w.C0, w.k, w.max_iters, True,
+                           oracle_fit=oracle.mti_fit)
+    print("config2 iters", st["iters"], "rechecked", st["rechecked"], flush=True)
