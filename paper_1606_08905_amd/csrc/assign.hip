@@ -97,6 +97,25 @@ hipError_t launch_prep_centroids(const CentroidOps& o, hipStream_t s) {
 
 constexpr int kTileThreads = 256;
 
+// Load KS consecutive floats (16-byte aligned when KS >= 4, 8-byte when 2).
+template <int KS>
+__device__ __forceinline__ void load_slice(float (&dst)[KS], const float* src) {
+  if constexpr (KS % 4 == 0) {
+#pragma unroll
+    for (int s = 0; s < KS; s += 4) {
+      float4 v = *reinterpret_cast<const float4*>(src + s);
+      dst[s] = v.x; dst[s + 1] = v.y; dst[s + 2] = v.z; dst[s + 3] = v.w;
+    }
+  } else {
+    static_assert(KS % 2 == 0, "slice width");
+#pragma unroll
+    for (int s = 0; s < KS; s += 2) {
+      float2 v = *reinterpret_cast<const float2*>(src + s);
+      dst[s] = v.x; dst[s + 1] = v.y;
+    }
+  }
+}
+
 template <int DP>
 struct TileCfg {
   static constexpr int KS = DP / 4;                      // k-steps per MFMA
@@ -141,12 +160,7 @@ __global__ __launch_bounds__(kTileThreads) void assign_mfma_f32(
       pid[pb] = p;
       const float* row = X + (size_t)p * d + grp * KS;
       if (valid[pb] && vec) {
-#pragma unroll
-        for (int s = 0; s < KS; s += 4) {
-          float4 v = *reinterpret_cast<const float4*>(row + s);
-          bx[pb][s] = v.x; bx[pb][s + 1] = v.y;
-          bx[pb][s + 2] = v.z; bx[pb][s + 3] = v.w;
-        }
+        load_slice<KS>(bx[pb], row);
       } else {
 #pragma unroll
         for (int s = 0; s < KS; ++s) {
@@ -186,12 +200,7 @@ __global__ __launch_bounds__(kTileThreads) void assign_mfma_f32(
 
       for (int cb = 0; cb < cc; cb += 16) {
         float a[KS];
-        const float* arow = &sC[(cb + col) * LDA + grp * KS];
-#pragma unroll
-        for (int s = 0; s < KS; s += 4) {
-          float4 v = *reinterpret_cast<const float4*>(arow + s);
-          a[s] = v.x; a[s + 1] = v.y; a[s + 2] = v.z; a[s + 3] = v.w;
-        }
+        load_slice<KS>(a, &sC[(cb + col) * LDA + grp * KS]);
         f4 init;
         init[0] = sN[cb + 4 * grp + 0];
         init[1] = sN[cb + 4 * grp + 1];
