@@ -127,7 +127,7 @@ def _raise(rc):
 
 def _opts(prune=True, recheck=1, check_numeric=True, seed=0, stream=None,
           workspace_cap=0, label_history=None, iter_counters=None,
-          poll_every=4, profile=None):
+          poll_every=0, profile=None):
     torch = _torch()
     if stream is None:
         stream = torch.cuda.current_stream()
@@ -151,7 +151,7 @@ def _opts(prune=True, recheck=1, check_numeric=True, seed=0, stream=None,
 
 def fit(X, k, C0=None, init="given", max_iters=100, tol=0.0, prune=True,
         recheck=1, seed=0, history=False, counters=False, out=None,
-        check_numeric=True, workspace_cap=0, poll_every=4, profile=None):
+        check_numeric=True, workspace_cap=0, poll_every=0, profile=None):
     """Lloyd's k-means on the GPU.  Returns (C, labels, stats dict).
 
     history=True adds stats["label_history"]: (iters, n) int32 CUDA tensor of

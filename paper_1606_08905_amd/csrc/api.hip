@@ -31,7 +31,7 @@ __global__ __launch_bounds__(256) void check_finite_kernel(const T* __restrict__
 hipError_t launch_check_finite(const void* p, knor_dtype dt, int64_t count,
                                int* bad, hipStream_t s) {
   int64_t blocks = (count + 255) / 256;
-  int grid = (int)(blocks < 4096 ? (blocks < 1 ? 1 : blocks) : 4096);
+  int grid = (int)(blocks < 1024 ? (blocks < 1 ? 1 : blocks) : 1024);
   switch (dt) {
     case KNOR_F64:
       hipLaunchKernelGGL(check_finite_kernel<double>, dim3(grid), dim3(256), 0,
@@ -49,49 +49,31 @@ hipError_t launch_check_finite(const void* p, knor_dtype dt, int64_t count,
   return hipGetLastError();
 }
 
-__global__ void fill_i32_kernel(int32_t* p, int64_t count, int32_t v,
-                                const int* done) {
-  if (done && *done) return;
+__global__ void fill_i32_kernel(int32_t* p, int64_t count, int32_t v) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < count) p[i] = v;
 }
 
-hipError_t launch_fill_i32(int32_t* p, int64_t count, int32_t v,
-                           const int* done, hipStream_t s) {
+hipError_t launch_fill_i32(int32_t* p, int64_t count, int32_t v, hipStream_t s) {
   if (count == 0) return hipSuccess;
   hipLaunchKernelGGL(fill_i32_kernel, dim3((count + 255) / 256), dim3(256), 0,
-                     s, p, count, v, done);
+                     s, p, count, v);
   return hipGetLastError();
 }
 
 __global__ void copy_i32_kernel(const int32_t* __restrict__ a,
                                 int32_t* __restrict__ b, int64_t count,
-                                const int* done) {
-  if (done && *done) return;
+                                const int* conv, int iter) {
+  if (*conv < iter) return;
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < count) b[i] = a[i];
 }
 
 hipError_t launch_copy_i32(const int32_t* a, int32_t* b, int64_t count,
-                           const int* done, hipStream_t s) {
+                           const int* conv, int iter, hipStream_t s) {
   if (count == 0) return hipSuccess;
   hipLaunchKernelGGL(copy_i32_kernel, dim3((count + 255) / 256), dim3(256), 0,
-                     s, a, b, count, done);
-  return hipGetLastError();
-}
-
-// Iteration t's stopping rule: #changed <= tol * n.
-__global__ void converge_kernel(const unsigned long long* ctr, double tol_n,
-                                int t, int* done, int* iters) {
-  if (*done) return;
-  *iters = t + 1;
-  if ((double)ctr[CNT_CHANGED] <= tol_n) *done = 1;
-}
-
-hipError_t launch_converge(const unsigned long long* ctr, double tol_n, int t,
-                           int* done, int* iters, hipStream_t s) {
-  hipLaunchKernelGGL(converge_kernel, dim3(1), dim3(1), 0, s, ctr, tol_n, t,
-                     done, iters);
+                     s, a, b, count, conv, iter);
   return hipGetLastError();
 }
 
@@ -204,7 +186,7 @@ struct Arena {
 };
 
 struct Opts {
-  int prune = 1, recheck = 1, check_numeric = 1, poll_every = 4;
+  int prune = 1, recheck = 1, check_numeric = 1, poll_every = 8;
   uint64_t seed = 0;
   hipStream_t stream = nullptr;
   size_t cap = 0;
@@ -289,32 +271,38 @@ static knor_status fit_impl(const void* X, knor_dtype dt, int64_t n, int d,
   const int kpad = (k + 15) / 16 * 16;
   const int dp = pad_dim(d);
   const bool mti = o.prune == 1;
+  const int nseg = nseg_of_n(n);
 
   CentroidOps ops{};
   ops.k = k; ops.kpad = kpad; ops.d = d; ops.dp = dp;
-  ops.C64 = C_out;
+  ops.C64 = C_out;                 // the output buffer is the working copy
   UpdatePlan plan{};
   void* upd_ws = nullptr;
   float *u = nullptr, *drift = nullptr, *s_half = nullptr;
-  int *surv = nullptr, *flags = nullptr, *flagbuf = nullptr;
+  int *list = nullptr, *seg_cnt = nullptr, *flags = nullptr, *ucnt = nullptr;
+  const int64_t units_cap = max_units(n);
+  int *flagbuf = nullptr, *dirty = nullptr;
   unsigned long long* ctr = nullptr;
   int64_t* rows_dev = nullptr;
   double *dist2 = nullptr, *sumtmp = nullptr, *objective = nullptr;
-  int32_t* prev_labels = nullptr;
-  (void)prev_labels;
 
   Arena ar;
   ar.add((void**)&ops.Cm2, sizeof(float) * (size_t)kpad * dp);
   ar.add((void**)&ops.cn, sizeof(float) * (size_t)kpad);
+  ar.add((void**)&ops.CT, sizeof(double) * (size_t)k * d);
   ar.add((void**)&drift, sizeof(float) * (size_t)k);
   ar.add((void**)&s_half, sizeof(float) * (size_t)k);
-  ar.add((void**)&flags, sizeof(int) * (size_t)n);
+  ar.add((void**)&dirty, sizeof(int) * (size_t)k);
+  ar.add((void**)&flags, sizeof(int) * (size_t)nseg * kSeg);
+  ar.add((void**)&ucnt, sizeof(int) * (size_t)units_cap);
   if (mti) {
     ar.add((void**)&u, sizeof(float) * (size_t)n);
-    ar.add((void**)&surv, sizeof(int) * (size_t)n);
+    ar.add((void**)&list, sizeof(int) * (size_t)nseg * kSeg);
+    ar.add((void**)&seg_cnt, sizeof(int) * (size_t)nseg);
   }
-  ar.add((void**)&ctr, sizeof(unsigned long long) * CNT_ROWS * (size_t)(max_iters + 1));
-  ar.add((void**)&flagbuf, sizeof(int) * 8);   // done, iters, bad
+  const size_t ctr_bytes = sizeof(unsigned long long) * ROW_STRIDE * (size_t)max_iters;
+  ar.add((void**)&ctr, ctr_bytes);
+  ar.add((void**)&flagbuf, sizeof(int) * 8);   // conv, bad
   ar.add((void**)&rows_dev, sizeof(int64_t) * (size_t)k);
   ar.add(&upd_ws, update_workspace_bytes(n, k, d));
   ar.add((void**)&dist2, sizeof(double) * (size_t)n);
@@ -323,12 +311,13 @@ static knor_status fit_impl(const void* X, knor_dtype dt, int64_t n, int d,
   knor_status rs = ar.alloc(s, o.cap);
   if (rs != KNOR_OK) return rs;
   update_plan_init(&plan, n, k, d, upd_ws);
-  int* done = flagbuf;
-  int* iters_dev = flagbuf + 1;
-  int* bad = flagbuf + 2;
+  int* conv = flagbuf;
+  int* bad = flagbuf + 1;
+  HIPCHK(update_plan_reset(plan, s));
 
   HIPCHK(hipMemsetAsync(flagbuf, 0, sizeof(int) * 8, s));
-  HIPCHK(hipMemsetAsync(ctr, 0, sizeof(unsigned long long) * CNT_ROWS * (size_t)(max_iters + 1), s));
+  HIPCHK(launch_fill_i32(conv, 1, kNotConverged, s));
+  HIPCHK(hipMemsetAsync(ctr, 0, ctr_bytes, s));
 
   // numeric check of the inputs before anything is written to the outputs
   if (o.check_numeric) {
@@ -354,31 +343,34 @@ static knor_status fit_impl(const void* X, knor_dtype dt, int64_t n, int d,
     HIPCHK(hipStreamSynchronize(s));   // `rows` leaves scope
   }
   HIPCHK(launch_prep_centroids(ops, s));
-  HIPCHK(launch_fill_i32(labels_out, n, -1, nullptr, s));   // every label changes at t = 0
+  HIPCHK(launch_fill_i32(labels_out, n, -1, s));   // every label changes at t = 0
+  HIPCHK(launch_fill_i32(dirty, k, 1, s));         // every cluster is summed at t = 0
 
   Prof prof;
   prof.stream = s;
   prof.on = o.profile_ms != nullptr || o.profile_launches != nullptr;
   Prof* pp = prof.on ? &prof : nullptr;
   const double tol_n = tol * (double)n;
-  int hdone = 0;
-  int t = 0;
-  for (t = 0; t < max_iters; ++t) {
-    unsigned long long* row = ctr + (size_t)t * CNT_ROWS;
+  int hconv = kNotConverged;
+  for (int t = 0; t < max_iters; ++t) {
+    unsigned long long* row = ctr + (size_t)t * ROW_STRIDE;
     AssignJob job{};
     job.X = X; job.dt = dt; job.n = n; job.d = d;
     job.labels = labels_out; job.u = mti ? u : nullptr;
-    job.flags = flags; job.ctr = row; job.done = done;
-    job.recheck_all = o.recheck == 2;
-    if (mti && t > 0) {
+    job.flags = flags; job.row = row; job.conv = conv; job.iter = t;
+    job.ucnt = ucnt;
+    job.dirty = dirty; job.recheck_all = o.recheck == 2;
+    const bool seg = mti && t > 0;
+    if (seg) {
       prof.begin(KNOR_PROF_FILTER);
       HIPCHK(launch_mti_filter(X, dt, n, d, C_out, labels_out, u, drift, s_half,
-                               surv, row, done, s));
+                               list, seg_cnt, row - ROW_STRIDE, row, conv, t, s));
       prof.end();
-      job.list = surv;
-      job.list_len = &row[CNT_SURVIVORS];
+      job.list = list;
+      job.seg_cnt = seg_cnt;
+      job.nseg = nseg;
     }
-    prof.begin(job.list ? KNOR_PROF_ASSIGN_LIST : KNOR_PROF_ASSIGN_DENSE);
+    prof.begin(seg ? KNOR_PROF_ASSIGN_LIST : KNOR_PROF_ASSIGN_DENSE);
     HIPCHK(launch_assign(ops, job, s));
     prof.end();
     if (dt != KNOR_F64) {
@@ -387,19 +379,22 @@ static knor_status fit_impl(const void* X, knor_dtype dt, int64_t n, int d,
       prof.end();
     }
     if (o.label_history)
-      HIPCHK(launch_copy_i32(labels_out, o.label_history + (size_t)t * n, n, done, s));
+      HIPCHK(launch_copy_i32(labels_out, o.label_history + (size_t)t * n, n,
+                             conv, t, s));
+    IterCtl ctl;
+    ctl.row = row; ctl.conv = conv; ctl.iter = t; ctl.tol_n = tol_n;
+    ctl.segmented = seg; ctl.n = n;
     HIPCHK(launch_update(plan, X, dt, labels_out, C_out, C_out, nullptr, &ops,
-                         mti ? drift : nullptr, done, s, pp));
+                         mti ? drift : nullptr, dirty, &ctl, s, pp));
     if (mti) {
       prof.begin(KNOR_PROF_CC);
-      HIPCHK(launch_cc_bounds(C_out, k, d, s_half, s));
+      HIPCHK(launch_cc_bounds(ops, s_half, conv, t, s));
       prof.end();
     }
-    HIPCHK(launch_converge(row, tol_n, t, done, iters_dev, s));
     if ((t + 1) % o.poll_every == 0 || t + 1 == max_iters) {
-      HIPCHK(hipMemcpyAsync(&hdone, done, sizeof(int), hipMemcpyDeviceToHost, s));
+      HIPCHK(hipMemcpyAsync(&hconv, conv, sizeof(int), hipMemcpyDeviceToHost, s));
       HIPCHK(hipStreamSynchronize(s));
-      if (hdone) break;
+      if (hconv != kNotConverged) break;
     }
   }
 
@@ -407,35 +402,39 @@ static knor_status fit_impl(const void* X, knor_dtype dt, int64_t n, int d,
   HIPCHK(launch_exact_dist2(X, dt, n, d, C_out, labels_out, dist2, s));
   HIPCHK(launch_canonical_sum(dist2, n, sumtmp, objective, s));
 
-  int hiters = 0;
-  std::vector<unsigned long long> hc((size_t)CNT_ROWS * (max_iters + 1));
+  std::vector<unsigned long long> hc((size_t)ROW_STRIDE * max_iters);
   double hobj = 0.0;
-  HIPCHK(hipMemcpyAsync(&hiters, iters_dev, sizeof(int), hipMemcpyDeviceToHost, s));
-  HIPCHK(hipMemcpyAsync(&hdone, done, sizeof(int), hipMemcpyDeviceToHost, s));
-  HIPCHK(hipMemcpyAsync(hc.data(), ctr, sizeof(unsigned long long) * hc.size(),
-                        hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(&hconv, conv, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(hc.data(), ctr, ctr_bytes, hipMemcpyDeviceToHost, s));
   HIPCHK(hipMemcpyAsync(&hobj, objective, sizeof(double), hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
   prof.collect(o.profile_ms, o.profile_launches);
+  const int converged = hconv != kNotConverged;
+  const int hiters = converged ? hconv + 1 : max_iters;
 
   if (o.iter_counters)
-    for (int i = 0; i < hiters; ++i)
-      for (int c = 0; c < KNOR_NCOUNTERS; ++c)
-        o.iter_counters[(size_t)i * KNOR_NCOUNTERS + c] =
-            (int64_t)hc[(size_t)i * CNT_ROWS + c];
+    for (int i = 0; i < hiters; ++i) {
+      const unsigned long long* r = &hc[(size_t)i * ROW_STRIDE];
+      int64_t* dst = o.iter_counters + (size_t)i * KNOR_NCOUNTERS;
+      dst[KNOR_CNT_CHANGED] = (int64_t)r[ROW_CHANGED];
+      dst[KNOR_CNT_SCANNED] = (int64_t)r[ROW_SCANNED];
+      dst[KNOR_CNT_PRUNED_A] = (int64_t)r[ROW_PRUNED_A];
+      dst[KNOR_CNT_PRUNED_B] = (int64_t)r[ROW_PRUNED_B];
+      dst[KNOR_CNT_RECHECKED] = (int64_t)r[ROW_FLAG_HEAD];
+    }
   if (st) {
     memset(st, 0, sizeof(*st));
     st->iters = hiters;
-    st->converged = hdone;
-    st->changed_last = hiters > 0 ? (int64_t)hc[(size_t)(hiters - 1) * CNT_ROWS + CNT_CHANGED] : 0;
+    st->converged = converged;
+    st->changed_last = (int64_t)hc[(size_t)(hiters - 1) * ROW_STRIDE + ROW_CHANGED];
     for (int i = 0; i < hiters; ++i) {
-      const unsigned long long* r = &hc[(size_t)i * CNT_ROWS];
-      st->scanned += (int64_t)r[CNT_SCANNED];
-      st->pruned_a += (int64_t)r[CNT_PRUNED_A];
-      st->pruned_b += (int64_t)r[CNT_PRUNED_B];
-      st->rechecked += (int64_t)r[CNT_RECHECKED];
-      int64_t tighten = (mti && i > 0) ? (n - (int64_t)r[CNT_PRUNED_A]) : 0;
-      st->dists_computed += ((int64_t)r[CNT_SCANNED] + (int64_t)r[CNT_RECHECKED]) * k + tighten;
+      const unsigned long long* r = &hc[(size_t)i * ROW_STRIDE];
+      st->scanned += (int64_t)r[ROW_SCANNED];
+      st->pruned_a += (int64_t)r[ROW_PRUNED_A];
+      st->pruned_b += (int64_t)r[ROW_PRUNED_B];
+      st->rechecked += (int64_t)r[ROW_FLAG_HEAD];
+      const int64_t tighten = (mti && i > 0) ? (n - (int64_t)r[ROW_PRUNED_A]) : 0;
+      st->dists_computed += ((int64_t)r[ROW_SCANNED] + (int64_t)r[ROW_FLAG_HEAD]) * k + tighten;
     }
     st->objective = hobj;
     st->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
@@ -498,21 +497,28 @@ knor_status knor_assign(const void* X, knor_dtype dt, int64_t n, int32_t d,
   ops.k = k; ops.kpad = (k + 15) / 16 * 16; ops.d = d; ops.dp = pad_dim(d);
   ops.C64 = const_cast<double*>(C);
   int* flags = nullptr;
+  int* conv = nullptr;
+  int* ucnt = nullptr;
   unsigned long long* ctr = nullptr;
+  const int64_t units_cap = max_units(n);
   Arena ar;
   ar.add((void**)&ops.Cm2, sizeof(float) * (size_t)ops.kpad * ops.dp);
   ar.add((void**)&ops.cn, sizeof(float) * (size_t)ops.kpad);
-  ar.add((void**)&flags, sizeof(int) * (size_t)n);
-  ar.add((void**)&ctr, sizeof(unsigned long long) * (CNT_ROWS + 8));
+  ar.add((void**)&ops.CT, sizeof(double) * (size_t)k * d);
+  ar.add((void**)&flags, sizeof(int) * (size_t)nseg_of_n(n) * kSeg);
+  ar.add((void**)&ucnt, sizeof(int) * (size_t)units_cap);
+  ar.add((void**)&ctr, sizeof(unsigned long long) * ROW_STRIDE);
+  ar.add((void**)&conv, sizeof(int) * 4);
   if (knor_status r = ar.alloc(s, o.cap)) return r;
-  int* done = (int*)(ctr + CNT_ROWS);
-  HIPCHK(hipMemsetAsync(ctr, 0, sizeof(unsigned long long) * (CNT_ROWS + 8), s));
+  HIPCHK(hipMemsetAsync(ctr, 0, sizeof(unsigned long long) * ROW_STRIDE, s));
+  HIPCHK(launch_fill_i32(conv, 1, kNotConverged, s));
+  HIPCHK(launch_fill_i32(labels_out, n, -1, s));
   HIPCHK(launch_prep_centroids(ops, s));
   AssignJob job{};
   job.X = X; job.dt = dt; job.n = n; job.d = d;
-  job.labels = labels_out; job.flags = flags; job.ctr = ctr; job.done = done;
-  job.recheck_all = o.recheck == 2;
-  job.dist2 = nullptr;
+  job.labels = labels_out; job.flags = flags; job.row = ctr; job.conv = conv;
+  job.ucnt = ucnt;
+  job.iter = 0; job.recheck_all = o.recheck == 2;
   HIPCHK(launch_assign(ops, job, s));
   HIPCHK(launch_recheck(ops, job, s));
   if (dist2_out)
@@ -539,16 +545,19 @@ knor_status knor_update(const void* X, knor_dtype dt, int64_t n, int32_t d,
     return KNOR_OK;
   }
   void* ws = nullptr;
-  int* done = nullptr;
+  int* conv = nullptr;
   Arena ar;
   ar.add(&ws, update_workspace_bytes(n, k, d));
-  ar.add((void**)&done, sizeof(int) * 4);
+  ar.add((void**)&conv, sizeof(int) * 4);
   if (knor_status r = ar.alloc(s, o.cap)) return r;
   UpdatePlan plan{};
   update_plan_init(&plan, n, k, d, ws);
-  HIPCHK(hipMemsetAsync(done, 0, sizeof(int) * 4, s));
+  HIPCHK(update_plan_reset(plan, s));
+  HIPCHK(launch_fill_i32(conv, 1, kNotConverged, s));
+  IterCtl ctl;
+  ctl.conv = conv;
   HIPCHK(launch_update(plan, X, dt, labels, C_prev, C_out, counts_out, nullptr,
-                       nullptr, done, s));
+                       nullptr, nullptr, &ctl, s));
   return KNOR_OK;
 }
 

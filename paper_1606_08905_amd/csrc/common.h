@@ -24,18 +24,36 @@ constexpr int kLeaf = 64;          // members per leaf of the canonical sum
 constexpr double kEta = 9.5367431640625e-07;   // 2^-20: relative pruning margin
 constexpr int kMaxD = 256;
 constexpr int kMaxK = 16384;
+constexpr int kSeg = 4096;         // points per MTI filter block / list segment
 
-// per-iteration device counters (unsigned long long each), one row per
-// iteration; columns 0..4 mirror KNOR_CNT_*; the rest are list heads.
+// Per-iteration device counter row (unsigned long long entries).  Partial
+// counts are added by workgroups into kChgSlots slots per quantity, one slot
+// per 128-byte line, so that concurrent atomic adds do not serialise on one
+// address; the iteration's last kernel folds them into the totals.
+constexpr int kChgSlots = 32;
+constexpr int kSlotStride = 16;
 enum {
-  CNT_CHANGED = KNOR_CNT_CHANGED,
-  CNT_SCANNED = KNOR_CNT_SCANNED,
-  CNT_PRUNED_A = KNOR_CNT_PRUNED_A,
-  CNT_PRUNED_B = KNOR_CNT_PRUNED_B,
-  CNT_RECHECKED = KNOR_CNT_RECHECKED,  // = length of the FP64 recheck list
-  CNT_SURVIVORS = 5,                   // = length of the survivor list
-  CNT_ROWS = 8
+  SLOT_CHANGED = 0,                          // labels changed
+  SLOT_FLAGGED = 1,                          // points sent to the FP64 recheck
+  SLOT_CAND = 2,                             // MTI stage-A candidates
+  SLOT_SURV = 3,                             // MTI survivors (tile scans)
+  NSLOTQ = 4,
+  ROW_CHANGED = NSLOTQ * kChgSlots * kSlotStride,   // totals
+  ROW_SCANNED = ROW_CHANGED + 1,
+  ROW_PRUNED_A = ROW_CHANGED + 2,
+  ROW_PRUNED_B = ROW_CHANGED + 3,
+  ROW_FLAG_HEAD = ROW_CHANGED + 4,           // FP64 rechecked points
+  ROW_TIGHTEN = ROW_CHANGED + 5,             // 1 if stage B ran
+  ROW_TIGHTEN_NEXT = ROW_CHANGED + 6,        // 1: run stage B next iteration
+  ROW_STRIDE = ROW_CHANGED + 16
 };
+
+__device__ __forceinline__ unsigned long long* row_slot(unsigned long long* row,
+                                                        int q, int salt) {
+  return &row[(q * kChgSlots + (salt & (kChgSlots - 1))) * kSlotStride];
+}
+
+constexpr int kNotConverged = 0x7fffffff;
 
 // ---------------------------------------------------------------------------
 // device helpers
@@ -93,8 +111,8 @@ __device__ __forceinline__ uint64_t lanemask_lt() {
   return l == 0 ? 0ull : (~0ull >> (64 - l));
 }
 
-// Append the calling lanes whose `want` is true to list[], in an order that
-// does not matter to any result; head is the list length counter.
+// Append the calling lanes whose `want` is true to list[] (used only for the
+// rare near-tie points); head is the list length counter.
 __device__ __forceinline__ void wave_append(bool want, int value,
                                             unsigned long long* head,
                                             int* list) {
@@ -108,11 +126,48 @@ __device__ __forceinline__ void wave_append(bool want, int value,
   if (want) list[base + __popcll(m & lanemask_lt())] = value;
 }
 
-// Add a per-lane 0/1 predicate count of the whole wave to *ctr.
-__device__ __forceinline__ void wave_count(bool pred, unsigned long long* ctr) {
+// Add the wave's count of `pred` to one of the spread changed-label slots.
+__device__ __forceinline__ void wave_count_changed(bool pred,
+                                                   unsigned long long* row,
+                                                   int salt) {
   uint64_t m = __ballot(pred);
   if (m && lane_id() == __ffsll((unsigned long long)m) - 1)
-    atomicAdd(ctr, (unsigned long long)__popcll(m));
+    atomicAdd(row_slot(row, SLOT_CHANGED, salt), (unsigned long long)__popcll(m));
+}
+
+// Workgroup-wide sums of up to four per-thread counters, added once per
+// workgroup into the spread slots q0..q0+nq-1 of `row` (all threads call).
+template <int NQ>
+__device__ __forceinline__ void block_add_slots(unsigned long long* row,
+                                                const int (&q)[NQ],
+                                                const unsigned long long (&v)[NQ]) {
+  __shared__ unsigned long long part[NQ][16];
+  const int wave = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+  unsigned long long s[NQ];
+#pragma unroll
+  for (int i = 0; i < NQ; ++i) {
+    s[i] = v[i];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) s[i] += __shfl_xor(s[i], off);
+  }
+  if ((threadIdx.x & 63) == 0)
+#pragma unroll
+    for (int i = 0; i < NQ; ++i) part[i][wave] = s[i];
+  __syncthreads();
+  if (threadIdx.x == 0)
+#pragma unroll
+    for (int i = 0; i < NQ; ++i) {
+      unsigned long long t = 0;
+      for (int w = 0; w < nw; ++w) t += part[i][w];
+      if (t) atomicAdd(row_slot(row, q[i], blockIdx.x), t);
+    }
+}
+
+// Record a label change: both clusters lose/gain a member.
+__device__ __forceinline__ void mark_dirty(int* dirty, int old_lab, int new_lab) {
+  if (!dirty) return;
+  dirty[new_lab] = 1;
+  if (old_lab >= 0) dirty[old_lab] = 1;
 }
 
 }  // namespace knor
@@ -125,28 +180,53 @@ namespace knor {
 // Centroid operands derived from the FP64 centroids.
 struct CentroidOps {
   double* C64;     // k x d canonical centroids
+  double* CT;      // d x k transposed copy (coalesced per-centroid lanes)
   float* Cm2;      // kpad x dp: -2 * fp32(c), zero-padded; pad rows zero
   float* cn;       // kpad: fp32(|c|^2) (pad rows +inf)
   uint16_t* Cbf;   // kpad x dp BF16 rounding of c (BF16 path only) or null
   int k, kpad, d, dp;
 };
 
-// Arguments of one assignment pass over a point set.
+// The point set one assignment pass covers.
+//  dense:      all n points (seg_cnt == null)
+//  segmented:  segment b holds seg_cnt[b] point indices at list[b*kSeg ...]
+// The tile kernel works in units of up points (see tile_f32_unit_points);
+// unit u writes its near-tie points to flags[u*up ...] and their number to
+// ucnt[u].  Counts of changed labels go to the spread slots of `row`.
 struct AssignJob {
   const void* X;
   knor_dtype dt;
   int64_t n;
   int d;
-  const int* list;                   // survivor indices, or null = all points
-  const unsigned long long* list_len;// device length of `list` (if list)
+  const int* list;
+  const int* seg_cnt;
+  int nseg;
   int32_t* labels;                   // in: previous labels; out: new labels
   float* u;                          // MTI upper bounds (or null)
-  int* flags;                        // FP64 recheck list (n entries)
-  unsigned long long* ctr;           // this iteration's counter row
-  const int* done;                   // skip all work when *done != 0
-  int recheck_all;                   // 2 = send every point to the recheck
-  double* dist2;                     // optional per-point exact D (or null)
+  int* flags;                        // per-unit recheck slices
+  int* ucnt;                         // per unit: recheck slice length
+  unsigned long long* row;           // this iteration's counter row
+  const int* conv;                   // skip when *conv < iter
+  int iter;
+  int* dirty;                        // clusters whose membership changed
+  int recheck_all;                   // 1 = send every point to the recheck
 };
+
+// Unit geometry of the FP32 tile (padded dimension dp, padded centroid
+// count kpad): points per unit, and the number of units of a pass.
+bool tile_f32_resident(int dp, int kpad);
+int tile_f32_unit_points(int dp, int kpad);
+inline int64_t assign_units(int dp, int kpad, int64_t n, bool segmented,
+                            int nseg) {
+  const int up = tile_f32_unit_points(dp, kpad);
+  return segmented ? (int64_t)nseg * (kSeg / up) : (n + up - 1) / up;
+}
+// capacity (in units) every per-unit array needs for n points
+inline int64_t max_units(int64_t n) {
+  return (int64_t)((n + kSeg - 1) / kSeg) * (kSeg / 16);
+}
+hipError_t launch_tile_f32(const CentroidOps& o, const AssignJob& j,
+                           hipStream_t s);
 
 hipError_t launch_prep_centroids(const CentroidOps& ops, hipStream_t s);
 hipError_t launch_assign(const CentroidOps& ops, const AssignJob& job,
@@ -178,8 +258,11 @@ struct UpdatePlan {
   int k, d;
   int B;              // points per histogram block
   int nb;             // number of blocks
-  // device workspace
-  int* blockcnt;      // nb x k (block-major)
+  int seglen;         // blocks per column-scan segment
+  int nsegc;          // column-scan segments
+  int* blockcnt;      // nb x k (block-major) label counts
+  int* segsum;        // nsegc x k: exclusive prefix over segments
+  int* ticket;        // last-block-done counter of the segment scan
   int* nj;            // k: members per cluster
   int* off;           // k+1: first member slot of each cluster
   int* leaf_off;      // k+1: first leaf of each cluster
@@ -189,31 +272,45 @@ struct UpdatePlan {
 };
 size_t update_workspace_bytes(int64_t n, int k, int d);
 void update_plan_init(UpdatePlan* p, int64_t n, int k, int d, void* ws);
+hipError_t update_plan_reset(const UpdatePlan& p, hipStream_t s);
+
+// Iteration bookkeeping that rides on the update's last kernel.
+struct IterCtl {
+  unsigned long long* row = nullptr;  // counter row of this iteration
+  int* conv = nullptr;                // iteration that converged (or max int)
+  int iter = 0;
+  double tol_n = 0.0;
+  int segmented = 0;                  // MTI survivors were scanned
+  int64_t n = 0;
+};
+
 hipError_t launch_update(const UpdatePlan& p, const void* X, knor_dtype dt,
                          const int32_t* labels, const double* C_prev,
                          double* C_out, int64_t* counts_out,
                          CentroidOps* ops /* may be null */,
-                         float* drift /* may be null */, const int* done,
-                         hipStream_t s, Prof* prof = nullptr);
+                         float* drift /* may be null */,
+                         int* dirty /* may be null: all clusters */,
+                         const IterCtl* ctl /* may be null */, hipStream_t s,
+                         Prof* prof = nullptr);
 
 // MTI.
-hipError_t launch_cc_bounds(const double* C64, int k, int d, float* s_half,
-                            hipStream_t s);
+hipError_t launch_cc_bounds(const CentroidOps& ops, float* s_half,
+                            const int* conv, int iter, hipStream_t s);
 hipError_t launch_mti_filter(const void* X, knor_dtype dt, int64_t n, int d,
                              const double* C64, const int32_t* labels,
                              float* u, const float* drift, const float* s_half,
-                             int* survivors, unsigned long long* ctr,
-                             const int* done, hipStream_t s);
+                             int* list, int* seg_cnt,
+                             const unsigned long long* prev_row,
+                             unsigned long long* row, const int* conv,
+                             int iter, hipStream_t s);
 
 // Misc.
 hipError_t launch_check_finite(const void* p, knor_dtype dt, int64_t count,
                                int* bad, hipStream_t s);
 hipError_t launch_fill_i32(int32_t* p, int64_t count, int32_t v,
-                           const int* done, hipStream_t s);
+                           hipStream_t s);
 hipError_t launch_copy_i32(const int32_t* src, int32_t* dst, int64_t count,
-                           const int* done, hipStream_t s);
-hipError_t launch_converge(const unsigned long long* ctr, double tol_n,
-                           int t, int* done, int* iters, hipStream_t s);
+                           const int* conv, int iter, hipStream_t s);
 hipError_t launch_gather_rows(const void* X, knor_dtype dt, int d,
                               const int64_t* rows, int k, double* C64,
                               hipStream_t s);
@@ -223,5 +320,7 @@ inline int pad_dim(int d) {
   while (p < d) p *= 2;
   return p;
 }
+
+inline int nseg_of_n(int64_t n) { return (int)((n + kSeg - 1) / kSeg); }
 
 }  // namespace knor

@@ -11,8 +11,9 @@
 //              centroid and no distance is evaluated.
 //   Clause 3:  otherwise tighten u to d(x, c_a) (FP64, rounded up) and test
 //              Clause 1 again with the tight bound.
-//   Survivors are appended (wave ballot + one atomic per wave) to a list that
-//   the assignment tile scans against every centroid.
+// Each filter block owns one segment of kSeg consecutive points and writes
+// its survivors to its own slice of the list (no global atomics); the
+// assignment tile then scans the survivors against every centroid.
 // The strict test with margin eta keeps every pruned centroid farther than
 // the kept one by a relative gap of about 4 eta, far above FP64 rounding, so
 // the labels equal the unpruned FP64 argmin.
@@ -22,102 +23,189 @@
 
 namespace knor {
 
-// s_bits[i] <- min over j != i of the rounded-down 1/2 d(c_i, c_j), as the
-// bit pattern of a non-negative float (so integer atomicMin orders them).
-// Block = one wave of 64 centroids i; blockIdx.y selects a segment of j.
-__global__ __launch_bounds__(64) void cc_bounds_kernel(
-    const double* __restrict__ C64, int k, int d, int jseg,
-    unsigned int* __restrict__ s_bits) {
-  const int i = blockIdx.x * 64 + threadIdx.x;
-  const int j0 = blockIdx.y * jseg;
-  const int j1 = j0 + jseg < k ? j0 + jseg : k;
-  if (i >= k) return;
+// s_half[i] = rounded-down 1/2 min_{j != i} d(c_i, c_j).  One block per i;
+// threads over j read the transposed copy CT (contiguous across lanes).
+__global__ __launch_bounds__(256) void cc_bounds_kernel(
+    const double* __restrict__ C64, const double* __restrict__ CT, int k,
+    int d, float* __restrict__ s_half, const int* __restrict__ conv,
+    int iter) {
+  __shared__ double red[256];
+  if (*conv < iter) return;
+  const int i = blockIdx.x;
   const double* ci = C64 + (size_t)i * d;
   double best = INFINITY;
-  for (int j = j0; j < j1; ++j) {
+  for (int j = threadIdx.x; j < k; j += blockDim.x) {
     if (j == i) continue;
-    double D = dist2_canon<double>(ci, C64 + (size_t)j * d, d);
-    best = D < best ? D : best;
+    double acc = 0.0;
+    for (int dim = 0; dim < d; ++dim) {
+      double t = __dsub_rn(ci[dim], CT[(size_t)dim * k + j]);
+      acc = __dadd_rn(acc, __dmul_rn(t, t));
+    }
+    best = acc < best ? acc : best;
   }
-  if (best < INFINITY) {
-    float v = f32_down(0.5 * sqrt(best) * (1.0 - (double)(d + 8) * 2.220446049250313e-16));
-    atomicMin(&s_bits[i], __float_as_uint(v));
+  red[threadIdx.x] = best;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s && red[threadIdx.x + s] < red[threadIdx.x])
+      red[threadIdx.x] = red[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    double m = red[0];
+    s_half[i] = m < INFINITY
+                    ? f32_down(0.5 * sqrt(m) * (1.0 - (double)(d + 8) * 2.220446049250313e-16))
+                    : INFINITY;
   }
 }
 
-__global__ void fill_u32(unsigned int* p, int n, unsigned int v) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) p[i] = v;
-}
-
-hipError_t launch_cc_bounds(const double* C64, int k, int d, float* s_half,
-                            hipStream_t s) {
-  unsigned int* bits = reinterpret_cast<unsigned int*>(s_half);
-  hipLaunchKernelGGL(fill_u32, dim3((k + 255) / 256), dim3(256), 0, s, bits, k,
-                     0x7f800000u /* +inf */);
-  const int jseg = 128;
-  dim3 grid((k + 63) / 64, (k + jseg - 1) / jseg);
-  hipLaunchKernelGGL(cc_bounds_kernel, grid, dim3(64), 0, s, C64, k, d, jseg,
-                     bits);
+hipError_t launch_cc_bounds(const CentroidOps& o, float* s_half,
+                            const int* conv, int iter, hipStream_t s) {
+  hipLaunchKernelGGL(cc_bounds_kernel, dim3(o.k), dim3(256), 0, s, o.C64, o.CT,
+                     o.k, o.d, s_half, conv, iter);
   return hipGetLastError();
 }
 
+constexpr int kFilterThreads = 1024;
+constexpr int kTightenLanes = 8;     // lanes cooperating on one point's distance
+
+// Clause 3 (tightening) pays off only while it still prunes: it runs in the
+// first iterations, every 8th iteration, and whenever the previous run
+// pruned at least 1/16 of its candidates (decided on the device).  Skipping
+// it is always exact: the candidates are then scanned in full.
+__device__ __forceinline__ bool tighten_now(const unsigned long long* prev_row,
+                                            int iter) {
+  return iter <= 2 || (iter & 7) == 0 ||
+         (prev_row && prev_row[ROW_TIGHTEN_NEXT] != 0);
+}
+
 template <typename T>
-__global__ __launch_bounds__(256) void mti_filter_kernel(
+__global__ __launch_bounds__(kFilterThreads) void mti_filter_kernel(
     const T* __restrict__ X, int64_t n, int d, const double* __restrict__ C64,
     const int32_t* __restrict__ labels, float* __restrict__ u,
     const float* __restrict__ drift, const float* __restrict__ s_half,
-    int* __restrict__ survivors, unsigned long long* __restrict__ ctr,
-    const int* __restrict__ done) {
-  if (*done) return;
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t p0 = (int64_t)blockIdx.x * blockDim.x; p0 < n; p0 += stride) {
-    const int64_t p = p0 + threadIdx.x;
-    const bool valid = p < n;
-    bool pa = false, pb = false, surv = false;
-    if (valid) {
+    int* __restrict__ list, int* __restrict__ seg_cnt,
+    const unsigned long long* __restrict__ prev_row,
+    unsigned long long* __restrict__ row, const int* __restrict__ conv,
+    int iter) {
+  __shared__ int candA[kSeg];
+  __shared__ int nA, nB;
+  if (*conv < iter) return;
+  const int seg = blockIdx.x;
+  const int64_t p0 = (int64_t)seg * kSeg;
+  const bool tighten = tighten_now(prev_row, iter);
+  if (threadIdx.x == 0) { nA = 0; nB = 0; }
+  if (tighten && seg == 0 && threadIdx.x == 0) row[ROW_TIGHTEN] = 1;
+  __syncthreads();
+
+  // Clause 1 with the drift-updated bound, for every point of the segment
+  for (int i = 0; i < kSeg / kFilterThreads; ++i) {
+    const int64_t p = p0 + i * kFilterThreads + threadIdx.x;
+    bool cand = false;
+    if (p < n) {
       const int a = labels[p];
-      const double s = (double)s_half[a];
-      // Clause 1 with the drift-updated bound
-      double ub = f32_up(((double)u[p] + (double)drift[a]) * (1.0 + 8.881784197001252e-16));
-      if (ub * (1.0 + kEta) < s) {
-        pa = true;
+      const double ub = f32_up(((double)u[p] + (double)drift[a]) * (1.0 + 8.881784197001252e-16));
+      if (ub * (1.0 + kEta) < (double)s_half[a]) {
+        u[p] = (float)ub;
       } else {
-        // Clause 3: tighten to the exact distance, then Clause 1 again
-        double D = dist2_canon<T>(X + (size_t)p * d, C64 + (size_t)a * d, d);
-        ub = f32_up(sqrt(D) * (1.0 + (double)(d + 8) * 2.220446049250313e-16));
-        if (ub * (1.0 + kEta) < s) pb = true; else surv = true;
+        cand = true;
       }
-      u[p] = (float)ub;
     }
-    wave_count(pa, &ctr[CNT_PRUNED_A]);
-    wave_count(pb, &ctr[CNT_PRUNED_B]);
-    wave_append(surv, (int)p, &ctr[CNT_SURVIVORS], survivors);
+    uint64_t m = __ballot(cand);
+    if (m) {
+      int base = 0;
+      if (lane_id() == __ffsll((unsigned long long)m) - 1)
+        base = atomicAdd(&nA, __popcll(m));            // LDS atomic
+      base = __shfl(base, __ffsll((unsigned long long)m) - 1);
+      if (cand) candA[base + __popcll(m & lanemask_lt())] = (int)p;
+    }
   }
+  __syncthreads();
+  const int na = nA;
+  if (!tighten) {
+    // every candidate survives to the full scan (in index order of candA's
+    // slots; the order does not affect any result)
+    for (int c = threadIdx.x; c < na; c += kFilterThreads) list[p0 + c] = candA[c];
+    if (threadIdx.x == 0) seg_cnt[seg] = na;
+    const int q[2] = {SLOT_CAND, SLOT_SURV};
+    const unsigned long long v[2] = {threadIdx.x == 0 ? (unsigned long long)na : 0ull,
+                                     threadIdx.x == 0 ? (unsigned long long)na : 0ull};
+    block_add_slots<2>(row, q, v);
+    return;
+  }
+
+  // Clause 3: tighten to d(x, c_a) for the candidates, kTightenLanes lanes
+  // per point, then Clause 1 again with the tight bound
+  const int r = threadIdx.x % kTightenLanes;
+  const int slot = threadIdx.x / kTightenLanes;
+  constexpr int per_pass = kFilterThreads / kTightenLanes;
+  for (int c0 = 0; c0 < na; c0 += per_pass) {
+    const int c = c0 + slot;
+    const bool live = c < na;
+    const int p = live ? candA[c] : 0;
+    const int a = live ? labels[p] : 0;
+    double part = 0.0;
+    if (live) {
+      const T* x = X + (size_t)p * d;
+      const double* ca = C64 + (size_t)a * d;
+      for (int dim = r; dim < d; dim += kTightenLanes) {
+        double t = to_f64<T>(x[dim]) - ca[dim];
+        part = part + t * t;
+      }
+    }
+#pragma unroll
+    for (int off = 1; off < kTightenLanes; off <<= 1) part += __shfl_xor(part, off);
+    bool surv = false;
+    if (live && r == 0) {
+      // any summation order of d non-negative terms: relative error below
+      // (d + 2) 2^-53; inflate to an upper bound of the exact distance
+      const double ub = f32_up(sqrt(part * (1.0 + (double)(d + 8) * 2.220446049250313e-16)) *
+                               (1.0 + 8.881784197001252e-16));
+      u[p] = (float)ub;
+      surv = !(ub * (1.0 + kEta) < (double)s_half[a]);
+    }
+    uint64_t m = __ballot(surv);
+    if (m) {
+      int base = 0;
+      if (lane_id() == __ffsll((unsigned long long)m) - 1)
+        base = atomicAdd(&nB, __popcll(m));
+      base = __shfl(base, __ffsll((unsigned long long)m) - 1);
+      if (surv) list[p0 + base + __popcll(m & lanemask_lt())] = p;
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) seg_cnt[seg] = nB;
+  const int q[2] = {SLOT_CAND, SLOT_SURV};
+  const unsigned long long v[2] = {threadIdx.x == 0 ? (unsigned long long)na : 0ull,
+                                   threadIdx.x == 0 ? (unsigned long long)nB : 0ull};
+  block_add_slots<2>(row, q, v);
 }
 
 hipError_t launch_mti_filter(const void* X, knor_dtype dt, int64_t n, int d,
                              const double* C64, const int32_t* labels,
                              float* u, const float* drift, const float* s_half,
-                             int* survivors, unsigned long long* ctr,
-                             const int* done, hipStream_t s) {
-  int64_t blocks = (n + 255) / 256;
-  int grid = (int)(blocks < 8192 ? (blocks < 1 ? 1 : blocks) : 8192);
+                             int* list, int* seg_cnt,
+                             const unsigned long long* prev_row,
+                             unsigned long long* row, const int* conv,
+                             int iter, hipStream_t s) {
+  const int nseg = nseg_of_n(n);
   switch (dt) {
     case KNOR_F64:
-      hipLaunchKernelGGL(mti_filter_kernel<double>, dim3(grid), dim3(256), 0, s,
-                         (const double*)X, n, d, C64, labels, u, drift, s_half,
-                         survivors, ctr, done);
+      hipLaunchKernelGGL(mti_filter_kernel<double>, dim3(nseg),
+                         dim3(kFilterThreads), 0, s, (const double*)X, n, d,
+                         C64, labels, u, drift, s_half, list, seg_cnt,
+                         prev_row, row, conv, iter);
       break;
     case KNOR_F32:
-      hipLaunchKernelGGL(mti_filter_kernel<float>, dim3(grid), dim3(256), 0, s,
-                         (const float*)X, n, d, C64, labels, u, drift, s_half,
-                         survivors, ctr, done);
+      hipLaunchKernelGGL(mti_filter_kernel<float>, dim3(nseg),
+                         dim3(kFilterThreads), 0, s, (const float*)X, n, d, C64,
+                         labels, u, drift, s_half, list, seg_cnt, prev_row, row,
+                         conv, iter);
       break;
     case KNOR_BF16:
-      hipLaunchKernelGGL(mti_filter_kernel<uint16_t>, dim3(grid), dim3(256), 0,
-                         s, (const uint16_t*)X, n, d, C64, labels, u, drift,
-                         s_half, survivors, ctr, done);
+      hipLaunchKernelGGL(mti_filter_kernel<uint16_t>, dim3(nseg),
+                         dim3(kFilterThreads), 0, s, (const uint16_t*)X, n, d,
+                         C64, labels, u, drift, s_half, list, seg_cnt,
+                         prev_row, row, conv, iter);
       break;
   }
   return hipGetLastError();

@@ -4,49 +4,95 @@
 //
 // Here the merge is an atomic-free, two-pass segmented reduction whose FP64
 // summation order is fixed and independent of the launch configuration:
-//   pass 1  stable counting sort of point indices by label (perm), with
-//           per-block histograms, column scans and an in-order scatter that
-//           ranks equal labels inside a wave with per-bit ballots;
+//   pass 1  stable counting sort of point indices by label (perm): per-range
+//           label histograms, prefix sums over ranges and clusters, and an
+//           in-order scatter that ranks equal labels inside a wave with
+//           per-bit ballots;
 //   pass 2  leaf sums: each leaf = 64 consecutive members of one cluster in
 //           increasing point index, summed left to right from the first;
 //           then per cluster a pairwise tree over its leaves (bottom-up,
 //           node a absorbs node a+s at stride s), one correctly rounded
 //           division by the member count, and the derived operands.
-// A cluster without members keeps its previous centroid.
+// A cluster without members keeps its previous centroid.  Inside a fit, a
+// cluster whose member set did not change since the last update ("clean")
+// has the same canonical sum, so pass 2 skips it and keeps its centroid.
+//
+// Pass 1 has two schedules.  For k <= kFusedMaxK, one workgroup of 16 waves
+// owns a range of points; each wave owns a sub-range and a private running
+// table in LDS, and every workgroup derives its own offsets from the range
+// totals (two kernels).  For larger k, per-block counts go through a
+// segmented column scan (four kernels).
 #include <math.h>
 
 #include "common.h"
 
 namespace knor {
 
+constexpr int kFusedMaxK = 768;            // 16 x k running tables within 48 KB
+constexpr int kFusedWaves = 16;
+
 // ---------------------------------------------------------------------------
 // plan / workspace
 // ---------------------------------------------------------------------------
 
+static bool fused_sort(int k) { return k <= kFusedMaxK; }
+
 static int choose_block(int64_t n, int k) {
-  int64_t B = 4096;
+  if (fused_sort(k)) {
+    // sub-range per wave; a workgroup covers kFusedWaves sub-ranges and the
+    // range-total matrix stays below 2^16 entries
+    const int64_t unit = (int64_t)kFusedWaves * 1024;
+    int64_t r = (n * (int64_t)k + unit * 65536 - 1) / (unit * 65536);
+    if (r < 1) r = 1;
+    return (int)(1024 * r);
+  }
+  // one wave per block: enough blocks to occupy the GPU, while the nb x k
+  // count matrix stays within max(n, 2^24) entries
+  int64_t B = 1024;
+  while (n / B > 4096 && B < 4096) B *= 2;
   int64_t cap = n > (1 << 24) ? n : (1 << 24);
   while (((n + B - 1) / B) * (int64_t)k > cap && B < (1 << 22)) B *= 2;
   return (int)B;
 }
 
-static int nseg_of(int nb) { return (nb + 31) / 32; }
+// blocks per column-scan segment: the scatter re-adds at most seglen-1 rows
+static int choose_seglen(int k) {
+  int s = 16384 / k;
+  return s < 1 ? 1 : (s > 32 ? 32 : s);
+}
 
 static size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
+static void plan_dims(int64_t n, int k, int* B, int* nb, int* seglen,
+                      int* nsegc) {
+  *B = choose_block(n, k);
+  if (fused_sort(k)) {
+    const int64_t range = (int64_t)*B * kFusedWaves;
+    *nb = (int)((n + range - 1) / range);    // workgroup ranges
+    *seglen = 1;
+    *nsegc = 0;
+  } else {
+    *nb = (int)((n + *B - 1) / *B);
+    *seglen = choose_seglen(k);
+    *nsegc = (*nb + *seglen - 1) / *seglen;
+  }
+}
+
 size_t update_workspace_bytes(int64_t n, int k, int d) {
-  int B = choose_block(n, k);
-  int64_t nb = (n + B - 1) / B;
-  int64_t maxleaves = n / kLeaf + k + 1;
-  int nseg = nseg_of((int)nb);
+  int B, nb, seglen, nsegc;
+  plan_dims(n, k, &B, &nb, &seglen, &nsegc);
+  const int64_t maxleaves = n / kLeaf + k + 1;
+  const size_t cnt_entries = fused_sort(k) ? (size_t)nb * (kFusedWaves + 1) * k
+                                           : (size_t)nb * k;
   size_t b = 0;
-  b += align256(sizeof(int) * (size_t)nb * k);          // blockcnt
-  b += align256(sizeof(int) * (size_t)nseg * k);        // segment sums
-  b += align256(sizeof(int) * (size_t)k);               // nj
-  b += align256(sizeof(int) * (size_t)(k + 1));         // off
-  b += align256(sizeof(int) * (size_t)(k + 1));         // leaf_off
-  b += align256(sizeof(int) * (size_t)n);               // perm
-  b += align256(sizeof(double) * (size_t)maxleaves * d);// leafsum
+  b += align256(sizeof(int) * cnt_entries);                  // blockcnt
+  b += align256(sizeof(int) * (size_t)(nsegc > 0 ? nsegc : 1) * k);  // segsum
+  b += align256(sizeof(int) * 64);                           // ticket
+  b += align256(sizeof(int) * (size_t)k);                    // nj
+  b += align256(sizeof(int) * (size_t)(k + 1));              // off
+  b += align256(sizeof(int) * (size_t)(k + 1));              // leaf_off
+  b += align256(sizeof(int) * (size_t)n);                    // perm
+  b += align256(sizeof(double) * (size_t)maxleaves * d);     // leafsum
   return b;
 }
 
@@ -54,13 +100,14 @@ void update_plan_init(UpdatePlan* p, int64_t n, int k, int d, void* ws) {
   p->n = n;
   p->k = k;
   p->d = d;
-  p->B = choose_block(n, k);
-  p->nb = (int)((n + p->B - 1) / p->B);
+  plan_dims(n, k, &p->B, &p->nb, &p->seglen, &p->nsegc);
   p->max_leaves = n / kLeaf + k + 1;
+  const size_t cnt_entries = fused_sort(k) ? (size_t)p->nb * (kFusedWaves + 1) * k
+                                           : (size_t)p->nb * k;
   char* c = (char*)ws;
-  p->blockcnt = (int*)c; c += align256(sizeof(int) * (size_t)p->nb * k);
-  // segment sums follow blockcnt; addressed through blockcnt + nb*k rounded
-  c += align256(sizeof(int) * (size_t)nseg_of(p->nb) * k);
+  p->blockcnt = (int*)c; c += align256(sizeof(int) * cnt_entries);
+  p->segsum = (int*)c; c += align256(sizeof(int) * (size_t)(p->nsegc > 0 ? p->nsegc : 1) * k);
+  p->ticket = (int*)c; c += align256(sizeof(int) * 64);
   p->nj = (int*)c; c += align256(sizeof(int) * (size_t)k);
   p->off = (int*)c; c += align256(sizeof(int) * (size_t)(k + 1));
   p->leaf_off = (int*)c; c += align256(sizeof(int) * (size_t)(k + 1));
@@ -68,91 +115,32 @@ void update_plan_init(UpdatePlan* p, int64_t n, int k, int d, void* ws) {
   p->leafsum = (double*)c;
 }
 
-static int* segsum_ptr(const UpdatePlan& p) {
-  return (int*)((char*)p.blockcnt + align256(sizeof(int) * (size_t)p.nb * p.k));
+hipError_t update_plan_reset(const UpdatePlan& p, hipStream_t s) {
+  return hipMemsetAsync(p.ticket, 0, sizeof(int) * 64, s);
 }
 
-// ---------------------------------------------------------------------------
-// pass 1: stable counting sort by label
-// ---------------------------------------------------------------------------
+#define SKIP_IF_CONVERGED \
+  if (*conv < iter) return;
 
-// Per-block label histogram; blockcnt is block-major [b][j].
-__global__ __launch_bounds__(256) void hist_kernel(const int32_t* __restrict__ labels,
-                                                   int64_t n, int k, int B,
-                                                   int* __restrict__ blockcnt,
-                                                   const int* __restrict__ done) {
-  extern __shared__ int sh[];
-  if (*done) return;
-  const int b = blockIdx.x;
-  for (int j = threadIdx.x; j < k; j += blockDim.x) sh[j] = 0;
-  __syncthreads();
-  int64_t p0 = (int64_t)b * B, p1 = p0 + B < n ? p0 + B : n;
-  for (int64_t p = p0 + threadIdx.x; p < p1; p += blockDim.x) {
-    unsigned lab = (unsigned)labels[p];
-    if (lab < (unsigned)k) atomicAdd(&sh[lab], 1);   // out-of-range: ignored
+// Rank of each lane among the lanes holding the same label (one ballot per
+// label bit); returns the mask of those lanes.
+__device__ __forceinline__ uint64_t same_label_mask(bool valid, int lab,
+                                                    int bits) {
+  uint64_t mask = __ballot(valid);
+  for (int bit = 0; bit < bits; ++bit) {
+    const bool on = (lab >> bit) & 1;
+    const uint64_t bb = __ballot(on);
+    mask &= on ? bb : ~bb;
   }
-  __syncthreads();
-  int* row = blockcnt + (size_t)b * k;
-  for (int j = threadIdx.x; j < k; j += blockDim.x) row[j] = sh[j];
+  return mask;
 }
 
-// Column scan, phase A: per (segment of 32 blocks, cluster) sum.
-__global__ __launch_bounds__(256) void colscan_a(const int* __restrict__ blockcnt,
-                                                 int nb, int k,
-                                                 int* __restrict__ segsum,
-                                                 const int* __restrict__ done) {
-  if (*done) return;
-  int j = blockIdx.x * blockDim.x + threadIdx.x;
-  int seg = blockIdx.y;
-  if (j >= k) return;
-  int b0 = seg * 32, b1 = b0 + 32 < nb ? b0 + 32 : nb;
-  int s = 0;
-  for (int b = b0; b < b1; ++b) s += blockcnt[(size_t)b * k + j];
-  segsum[(size_t)seg * k + j] = s;
-}
-
-// Phase B: per cluster, exclusive scan over segments; nj = total.
-__global__ __launch_bounds__(256) void colscan_b(int* __restrict__ segsum,
-                                                 int nseg, int k,
-                                                 int* __restrict__ nj,
-                                                 const int* __restrict__ done) {
-  if (*done) return;
-  int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= k) return;
-  int run = 0;
-  for (int s = 0; s < nseg; ++s) {
-    int v = segsum[(size_t)s * k + j];
-    segsum[(size_t)s * k + j] = run;
-    run += v;
-  }
-  nj[j] = run;
-}
-
-// Phase C: per (segment, cluster), exclusive prefix of blockcnt in place.
-__global__ __launch_bounds__(256) void colscan_c(int* __restrict__ blockcnt,
-                                                 int nb, int k,
-                                                 const int* __restrict__ segsum,
-                                                 const int* __restrict__ done) {
-  if (*done) return;
-  int j = blockIdx.x * blockDim.x + threadIdx.x;
-  int seg = blockIdx.y;
-  if (j >= k) return;
-  int b0 = seg * 32, b1 = b0 + 32 < nb ? b0 + 32 : nb;
-  int run = segsum[(size_t)seg * k + j];
-  for (int b = b0; b < b1; ++b) {
-    int v = blockcnt[(size_t)b * k + j];
-    blockcnt[(size_t)b * k + j] = run;
-    run += v;
-  }
-}
-
-// Exclusive scans over clusters: off (members) and leaf_off (leaves of 64).
-__global__ __launch_bounds__(1024) void cluster_scan(const int* __restrict__ nj,
-                                                     int k, int* __restrict__ off,
-                                                     int* __restrict__ leaf_off,
-                                                     const int* __restrict__ done) {
-  __shared__ int sa[1024], sb[1024];
-  if (*done) return;
+// Exclusive scans over clusters of per-cluster totals: off (members) and
+// leaf_off (leaves of 64).  Run by one block of 1024 threads.
+__device__ void cluster_scan_block(const int* __restrict__ nj, int k,
+                                   int* __restrict__ off,
+                                   int* __restrict__ leaf_off, int* sa,
+                                   int* sb) {
   const int per = (k + 1023) / 1024;
   const int j0 = threadIdx.x * per;
   int a = 0, l = 0;
@@ -184,19 +172,215 @@ __global__ __launch_bounds__(1024) void cluster_scan(const int* __restrict__ nj,
   }
 }
 
-// In-order scatter: one wave per block walks its points in chunks of 64.
-// Lanes holding the same label find each other with one ballot per label
-// bit; a lane's rank among them is the count of such lanes below it.
+// ---------------------------------------------------------------------------
+// pass 1, fused schedule (k <= kFusedMaxK): two kernels
+// ---------------------------------------------------------------------------
+//
+// cnt layout per range r: kFusedWaves rows of per-wave counts, then one row
+// of range totals: cnt[(r * (W + 1) + w) * k + j].
+
+__global__ __launch_bounds__(1024) void hist_fused(const int32_t* __restrict__ labels,
+                                                   int64_t n, int k, int SB,
+                                                   int* __restrict__ cnt,
+                                                   const int* __restrict__ conv,
+                                                   int iter) {
+  extern __shared__ int tab[];               // kFusedWaves x k
+  SKIP_IF_CONVERGED
+  const int r = blockIdx.x, wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  for (int e = threadIdx.x; e < kFusedWaves * k; e += blockDim.x) tab[e] = 0;
+  __syncthreads();
+  const int64_t p0 = ((int64_t)r * kFusedWaves + wave) * SB;
+  const int64_t p1 = p0 + SB < n ? p0 + SB : n;
+  int* t = tab + wave * k;
+  for (int64_t p = p0 + lane; p < p1; p += 64) {
+    const unsigned lab = (unsigned)labels[p];
+    if (lab < (unsigned)k) atomicAdd(&t[lab], 1);   // LDS; order-free count
+  }
+  __syncthreads();
+  int* out = cnt + (size_t)r * (kFusedWaves + 1) * k;
+  for (int j = threadIdx.x; j < k; j += blockDim.x) {
+    int s = 0;
+    for (int w = 0; w < kFusedWaves; ++w) {
+      const int v = tab[w * k + j];
+      out[(size_t)w * k + j] = v;
+      s += v;
+    }
+    out[(size_t)kFusedWaves * k + j] = s;
+  }
+}
+
+__global__ __launch_bounds__(1024) void scatter_fused(
+    const int32_t* __restrict__ labels, int64_t n, int k, int SB, int nr,
+    int bits, const int* __restrict__ cnt, const int* __restrict__ dirty,
+    int* __restrict__ perm, int* __restrict__ nj_out, int* __restrict__ off_out,
+    int* __restrict__ leaf_off_out, const int* __restrict__ conv, int iter) {
+  extern __shared__ int run[];               // kFusedWaves x k
+  __shared__ int sa[1024], sb[1024];
+  SKIP_IF_CONVERGED
+  const int r = blockIdx.x, wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int j = threadIdx.x;                 // k <= 1024: one cluster per thread
+  int tot = 0, pre = 0;
+  if (j < k)
+    for (int rr = 0; rr < nr; ++rr) {
+      const int v = cnt[((size_t)rr * (kFusedWaves + 1) + kFusedWaves) * k + j];
+      tot += v;
+      if (rr < r) pre += v;
+    }
+  // exclusive prefix over clusters of the totals (members and leaves)
+  const int lv = (tot + kLeaf - 1) / kLeaf;
+  sa[threadIdx.x] = tot;
+  sb[threadIdx.x] = lv;
+  __syncthreads();
+  for (int s = 1; s < 1024; s <<= 1) {
+    const int va = threadIdx.x >= s ? sa[threadIdx.x - s] : 0;
+    const int vb = threadIdx.x >= s ? sb[threadIdx.x - s] : 0;
+    __syncthreads();
+    sa[threadIdx.x] += va;
+    sb[threadIdx.x] += vb;
+    __syncthreads();
+  }
+  const int off = sa[threadIdx.x] - tot;
+  if (r == 0) {
+    if (j < k) {
+      nj_out[j] = tot;
+      off_out[j] = off;
+      leaf_off_out[j] = sb[threadIdx.x] - lv;
+    }
+    if (threadIdx.x == 1023) {
+      off_out[k] = sa[1023];
+      leaf_off_out[k] = sb[1023];
+    }
+  }
+  if (j < k) {
+    int base = off + pre;
+    const int* mine = cnt + (size_t)r * (kFusedWaves + 1) * k;
+    for (int w = 0; w < kFusedWaves; ++w) {
+      run[w * k + j] = base;
+      base += mine[(size_t)w * k + j];
+    }
+  }
+  __syncthreads();
+  // each wave walks its sub-range in chunks of 64 with its own table
+  int* t = run + wave * k;
+  const uint64_t lt = lanemask_lt();
+  const int64_t p0 = ((int64_t)r * kFusedWaves + wave) * SB;
+  const int64_t p1 = p0 + SB < n ? p0 + SB : n;
+  for (int64_t c = p0; c < p1; c += 64) {
+    const int64_t p = c + lane;
+    int lab = p < p1 ? labels[p] : 0;
+    const bool valid = p < p1 && (unsigned)lab < (unsigned)k;
+    if (!valid) lab = 0;
+    const uint64_t mask = same_label_mask(valid, lab, bits);
+    const int rank = __popcll(mask & lt);
+    const int cntl = __popcll(mask);
+    int pos = 0;
+    if (valid) pos = t[lab] + rank;
+    __builtin_amdgcn_wave_barrier();
+    if (valid) {
+      if (!dirty || dirty[lab]) perm[pos] = (int)p;
+      if (rank == cntl - 1) t[lab] = pos + 1;
+    }
+    __builtin_amdgcn_wave_barrier();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// pass 1, large-k schedule: four kernels
+// ---------------------------------------------------------------------------
+
+// Per-block label histogram; blockcnt is block-major [b][j].  Labels outside
+// [0, k) are ignored by every pass.
+__global__ __launch_bounds__(256) void hist_kernel(const int32_t* __restrict__ labels,
+                                                   int64_t n, int k, int B,
+                                                   int* __restrict__ blockcnt,
+                                                   const int* __restrict__ conv,
+                                                   int iter) {
+  extern __shared__ int sh[];
+  SKIP_IF_CONVERGED
+  const int b = blockIdx.x;
+  for (int j = threadIdx.x; j < k; j += blockDim.x) sh[j] = 0;
+  __syncthreads();
+  int64_t p0 = (int64_t)b * B, p1 = p0 + B < n ? p0 + B : n;
+  for (int64_t p = p0 + threadIdx.x; p < p1; p += blockDim.x) {
+    unsigned lab = (unsigned)labels[p];
+    if (lab < (unsigned)k) atomicAdd(&sh[lab], 1);   // LDS; order-free count
+  }
+  __syncthreads();
+  int* row = blockcnt + (size_t)b * k;
+  for (int j = threadIdx.x; j < k; j += blockDim.x) row[j] = sh[j];
+}
+
+// Column scan, phase A: per (segment of seglen blocks, cluster) sum.
+__global__ __launch_bounds__(256) void colscan_a(const int* __restrict__ blockcnt,
+                                                 int nb, int k, int seglen,
+                                                 int* __restrict__ segsum,
+                                                 const int* __restrict__ conv,
+                                                 int iter) {
+  SKIP_IF_CONVERGED
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  const int seg = blockIdx.y;
+  if (j >= k) return;
+  const int b0 = seg * seglen, b1 = b0 + seglen < nb ? b0 + seglen : nb;
+  int s = 0;
+  for (int b = b0; b < b1; ++b) s += blockcnt[(size_t)b * k + j];
+  segsum[(size_t)seg * k + j] = s;
+}
+
+// Phase B: per cluster, exclusive scan over segments (in place) and the
+// cluster total nj.  The last block to finish (a ticket taken after a device
+// fence; nobody waits on it) runs the scans over clusters.
+__global__ __launch_bounds__(1024) void colscan_b(int* __restrict__ segsum,
+                                                  int nsegc, int k,
+                                                  int* __restrict__ nj,
+                                                  int* __restrict__ off,
+                                                  int* __restrict__ leaf_off,
+                                                  int* __restrict__ ticket,
+                                                  const int* __restrict__ conv,
+                                                  int iter) {
+  __shared__ int sa[1024], sb[1024];
+  __shared__ int last;
+  SKIP_IF_CONVERGED
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j < k) {
+    int run = 0;
+    for (int s = 0; s < nsegc; ++s) {
+      int v = segsum[(size_t)s * k + j];
+      segsum[(size_t)s * k + j] = run;
+      run += v;
+    }
+    nj[j] = run;
+  }
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) last = atomicAdd(ticket, 1) == (int)gridDim.x - 1;
+  __syncthreads();
+  if (!last) return;
+  __threadfence();
+  cluster_scan_block(nj, k, off, leaf_off, sa, sb);
+  if (threadIdx.x == 0) *ticket = 0;     // ready for the next iteration
+}
+
+// In-order scatter: one wave per block walks its points in chunks of 64,
+// starting from off[j] + the segment prefix + the counts of the earlier
+// blocks of its segment.  Members of clean clusters are ranked but not
+// written (pass 2 skips them).
 __global__ __launch_bounds__(64) void scatter_kernel(
     const int32_t* __restrict__ labels, int64_t n, int k, int B, int bits,
-    const int* __restrict__ blockcnt, const int* __restrict__ off,
-    int* __restrict__ perm, const int* __restrict__ done) {
+    int seglen, const int* __restrict__ blockcnt,
+    const int* __restrict__ segsum, const int* __restrict__ off,
+    const int* __restrict__ dirty, int* __restrict__ perm,
+    const int* __restrict__ conv, int iter) {
   extern __shared__ int run[];
-  if (*done) return;
+  SKIP_IF_CONVERGED
   const int b = blockIdx.x;
   const int lane = threadIdx.x;
-  const int* row = blockcnt + (size_t)b * k;
-  for (int j = lane; j < k; j += 64) run[j] = off[j] + row[j];
+  const int seg = b / seglen;
+  const int* sp = segsum + (size_t)seg * k;
+  for (int j = lane; j < k; j += 64) {
+    int r = off[j] + sp[j];
+    for (int bb = seg * seglen; bb < b; ++bb) r += blockcnt[(size_t)bb * k + j];
+    run[j] = r;
+  }
   __syncthreads();
   const uint64_t lt = lanemask_lt();
   int64_t p0 = (int64_t)b * B, p1 = p0 + B < n ? p0 + B : n;
@@ -205,19 +389,14 @@ __global__ __launch_bounds__(64) void scatter_kernel(
     int lab = p < p1 ? labels[p] : 0;
     bool valid = p < p1 && (unsigned)lab < (unsigned)k;
     if (!valid) lab = 0;
-    uint64_t mask = __ballot(valid);
-    for (int bit = 0; bit < bits; ++bit) {
-      bool on = (lab >> bit) & 1;
-      uint64_t bb = __ballot(on);
-      mask &= on ? bb : ~bb;
-    }
+    const uint64_t mask = same_label_mask(valid, lab, bits);
     int rank = __popcll(mask & lt);
     int cnt = __popcll(mask);
     int pos = 0;
     if (valid) pos = run[lab] + rank;
     __builtin_amdgcn_wave_barrier();
     if (valid) {
-      perm[pos] = (int)p;
+      if (!dirty || dirty[lab]) perm[pos] = (int)p;
       if (rank == cnt - 1) run[lab] = pos + 1;
     }
     __builtin_amdgcn_wave_barrier();
@@ -238,62 +417,129 @@ __device__ __forceinline__ int cluster_of_leaf(const int* __restrict__ leaf_off,
   return lo;
 }
 
-// G lanes per leaf (G = power of two >= d, at most 64); lane t of a group
-// owns dimensions t, t+G, ...  Each leaf is summed left to right.
+// One wave per leaf.  Lane m loads member m's row (a chunk of DC dimensions
+// at a time) into the wave's LDS tile, then lane i sums dimension i over the
+// members in order (left to right, starting from the first member).
+constexpr int kLeafWaves = 4;
+
 template <typename T>
-__global__ __launch_bounds__(256) void leaf_kernel(
-    const T* __restrict__ X, int d, int G, const int* __restrict__ perm,
+struct LeafCfg {
+  static constexpr int DC = 128 / (int)sizeof(T);      // dims per chunk
+  static constexpr int LD = DC + 1;                    // odd row stride
+};
+
+template <typename T>
+__global__ __launch_bounds__(64 * kLeafWaves) void leaf_kernel(
+    const T* __restrict__ X, int d, const int* __restrict__ perm,
     const int* __restrict__ nj, const int* __restrict__ off,
-    const int* __restrict__ leaf_off, int k, double* __restrict__ leafsum,
-    const int* __restrict__ done) {
-  if (*done) return;
+    const int* __restrict__ leaf_off, int k, const int* __restrict__ dirty,
+    double* __restrict__ leafsum, const int* __restrict__ conv, int iter) {
+  constexpr int DC = LeafCfg<T>::DC, LD = LeafCfg<T>::LD;
+  __shared__ T tile[kLeafWaves][kLeaf * LD];
+  SKIP_IF_CONVERGED
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int total = leaf_off[k];
-  const int per_block = blockDim.x / G;
-  const int g = blockIdx.x * per_block + threadIdx.x / G;
-  const int t = threadIdx.x % G;
-  if (g >= total) return;
+  const int g = blockIdx.x * kLeafWaves + wave;
+  if (g >= total) return;                    // per wave; no block barrier used
   const int j = cluster_of_leaf(leaf_off, k, g);
+  if (dirty && !dirty[j]) return;
   const int L = g - leaf_off[j];
   const int m0 = off[j] + L * kLeaf;
   int cnt = nj[j] - L * kLeaf;
   if (cnt > kLeaf) cnt = kLeaf;
-  for (int i = t; i < d; i += G) {
-    double s = to_f64<T>(X[(size_t)perm[m0] * d + i]);
-    for (int m = 1; m < cnt; ++m)
-      s = __dadd_rn(s, to_f64<T>(X[(size_t)perm[m0 + m] * d + i]));
-    leafsum[(size_t)g * d + i] = s;
+  const int p = lane < cnt ? perm[m0 + lane] : 0;
+  T* tl = tile[wave];
+  for (int c0 = 0; c0 < d; c0 += DC) {
+    const int dc = d - c0 < DC ? d - c0 : DC;
+    if (lane < cnt) {
+      const T* xr = X + (size_t)p * d + c0;
+      for (int i = 0; i < dc; ++i) tl[lane * LD + i] = xr[i];
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    if (lane < dc) {
+      double s = to_f64<T>(tl[lane]);
+      for (int m = 1; m < cnt; ++m) s = __dadd_rn(s, to_f64<T>(tl[m * LD + lane]));
+      leafsum[(size_t)g * d + c0 + lane] = s;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   }
 }
 
+constexpr int kTreeLdsDoubles = 6144;   // 48 KB: trees that fit run in LDS
+
 // One workgroup per cluster: tree over its leaves, mean, operands, drift.
+// Block 0 also closes the iteration: totals of the counters and the
+// stopping rule (#changed <= tol * n).
 __global__ __launch_bounds__(256) void tree_finalize(
     double* __restrict__ leafsum, const int* __restrict__ nj,
-    const int* __restrict__ leaf_off, int k, int d,
-    const double* C_prev, double* C_out, int64_t* __restrict__ counts_out,
-    float* __restrict__ Cm2, float* __restrict__ cn, int dp,
-    float* __restrict__ drift, const int* __restrict__ done) {
+    const int* __restrict__ leaf_off, int k, int d, const double* C_prev,
+    double* C_out, int64_t* __restrict__ counts_out, float* __restrict__ Cm2,
+    float* __restrict__ cn, double* __restrict__ CT, int dp,
+    float* __restrict__ drift, int* __restrict__ dirty, IterCtl ctl,
+    const int* __restrict__ conv, int iter) {
   __shared__ double red[256];
   __shared__ double cval[kMaxD];
-  if (*done) return;
+  __shared__ double tree[kTreeLdsDoubles];
+  SKIP_IF_CONVERGED
   const int j = blockIdx.x;
+
+  if (j == 0 && ctl.row && threadIdx.x == 0) {
+    unsigned long long* row = ctl.row;
+    unsigned long long tot[NSLOTQ];
+    for (int q = 0; q < NSLOTQ; ++q) {
+      unsigned long long s = 0;
+      for (int i = 0; i < kChgSlots; ++i) s += row[(q * kChgSlots + i) * kSlotStride];
+      tot[q] = s;
+    }
+    row[ROW_CHANGED] = tot[SLOT_CHANGED];
+    row[ROW_FLAG_HEAD] = tot[SLOT_FLAGGED];
+    if (ctl.segmented) {
+      row[ROW_SCANNED] = tot[SLOT_SURV];
+      row[ROW_PRUNED_A] = (unsigned long long)ctl.n - tot[SLOT_CAND];
+      row[ROW_PRUNED_B] = tot[SLOT_CAND] - tot[SLOT_SURV];
+      // keep tightening while it prunes at least 1/16 of its candidates
+      row[ROW_TIGHTEN_NEXT] =
+          row[ROW_TIGHTEN] && 16 * (tot[SLOT_CAND] - tot[SLOT_SURV]) >= tot[SLOT_CAND];
+    } else {
+      row[ROW_SCANNED] = (unsigned long long)ctl.n;
+    }
+    if ((double)tot[SLOT_CHANGED] <= ctl.tol_n) *ctl.conv = iter;
+  }
+
   const int cntj = nj[j];
+  if (counts_out && threadIdx.x == 0) counts_out[j] = cntj;
+  if (dirty && !dirty[j]) {
+    if (drift && threadIdx.x == 0) drift[j] = 0.0f;     // centroid unchanged
+    return;
+  }
   const int m = leaf_off[j + 1] - leaf_off[j];
   double* base = leafsum + (size_t)leaf_off[j] * d;
+  const bool in_lds = (size_t)m * d <= (size_t)kTreeLdsDoubles;
+  double* node = in_lds ? tree : base;
+  if (in_lds) {
+    for (int e = threadIdx.x; e < m * d; e += blockDim.x) tree[e] = base[e];
+    __syncthreads();
+  }
   for (int s = 1; s < m; s <<= 1) {
     const int pairs = (m - s - 1) / (2 * s) + 1;
     for (int e = threadIdx.x; e < pairs * d; e += blockDim.x) {
       int i = e / d, dim = e - i * d;
       int a = i * 2 * s;
-      base[(size_t)a * d + dim] =
-          __dadd_rn(base[(size_t)a * d + dim], base[(size_t)(a + s) * d + dim]);
+      node[(size_t)a * d + dim] =
+          __dadd_rn(node[(size_t)a * d + dim], node[(size_t)(a + s) * d + dim]);
     }
     __syncthreads();
   }
   double diff2 = 0.0;
   for (int dim = threadIdx.x; dim < d; dim += blockDim.x) {
     double old = C_prev[(size_t)j * d + dim];
-    double c = cntj > 0 ? __ddiv_rn(base[dim], (double)cntj) : old;
+    double c = cntj > 0 ? __ddiv_rn(node[dim], (double)cntj) : old;
     C_out[(size_t)j * d + dim] = c;
+    if (CT) CT[(size_t)dim * k + j] = c;
     cval[dim] = c;
     double t = __dsub_rn(c, old);
     diff2 = __dadd_rn(diff2, __dmul_rn(t, t));
@@ -305,7 +551,6 @@ __global__ __launch_bounds__(256) void tree_finalize(
     __syncthreads();
   }
   if (threadIdx.x == 0) {
-    if (counts_out) counts_out[j] = cntj;
     if (drift)
       drift[j] = f32_up(sqrt(red[0]) * (1.0 + (double)(d + 8) * 2.220446049250313e-16));
     if (cn) {
@@ -313,6 +558,7 @@ __global__ __launch_bounds__(256) void tree_finalize(
       for (int dim = 0; dim < d; ++dim) ss = __dadd_rn(ss, __dmul_rn(cval[dim], cval[dim]));
       cn[j] = (float)ss;
     }
+    if (dirty) dirty[j] = 0;
   }
   if (Cm2)
     for (int dim = threadIdx.x; dim < dp; dim += blockDim.x)
@@ -322,55 +568,60 @@ __global__ __launch_bounds__(256) void tree_finalize(
 hipError_t launch_update(const UpdatePlan& p, const void* X, knor_dtype dt,
                          const int32_t* labels, const double* C_prev,
                          double* C_out, int64_t* counts_out, CentroidOps* ops,
-                         float* drift, const int* done, hipStream_t s,
-                         Prof* prof) {
+                         float* drift, int* dirty, const IterCtl* ctl,
+                         hipStream_t s, Prof* prof) {
+  // ctl->conv must point at device memory (max int when no fit is running)
   const int k = p.k, d = p.d;
-  const size_t lds_k = sizeof(int) * (size_t)k;
-  if (prof) prof->begin(KNOR_PROF_SORT);
-  hipLaunchKernelGGL(hist_kernel, dim3(p.nb), dim3(256), lds_k, s, labels, p.n,
-                     k, p.B, p.blockcnt, done);
-  int* seg = segsum_ptr(p);
-  int nseg = nseg_of(p.nb);
-  dim3 g2((k + 255) / 256, nseg);
-  hipLaunchKernelGGL(colscan_a, g2, dim3(256), 0, s, p.blockcnt, p.nb, k, seg,
-                     done);
-  hipLaunchKernelGGL(colscan_b, dim3((k + 255) / 256), dim3(256), 0, s, seg,
-                     nseg, k, p.nj, done);
-  hipLaunchKernelGGL(colscan_c, g2, dim3(256), 0, s, p.blockcnt, p.nb, k, seg,
-                     done);
-  hipLaunchKernelGGL(cluster_scan, dim3(1), dim3(1024), 0, s, p.nj, k, p.off,
-                     p.leaf_off, done);
+  const int* conv = ctl->conv;
+  const int iter = ctl->iter;
   int bits = 0;
   while ((1 << bits) < k) ++bits;
-  hipLaunchKernelGGL(scatter_kernel, dim3(p.nb), dim3(64), lds_k, s, labels,
-                     p.n, k, p.B, bits, p.blockcnt, p.off, p.perm, done);
+  if (prof) prof->begin(KNOR_PROF_SORT);
+  if (fused_sort(k)) {
+    const size_t lds = sizeof(int) * (size_t)kFusedWaves * k;
+    hipLaunchKernelGGL(hist_fused, dim3(p.nb), dim3(1024), lds, s, labels, p.n,
+                       k, p.B, p.blockcnt, conv, iter);
+    hipLaunchKernelGGL(scatter_fused, dim3(p.nb), dim3(1024), lds, s, labels,
+                       p.n, k, p.B, p.nb, bits, p.blockcnt, dirty, p.perm, p.nj,
+                       p.off, p.leaf_off, conv, iter);
+  } else {
+    const size_t lds_k = sizeof(int) * (size_t)k;
+    hipLaunchKernelGGL(hist_kernel, dim3(p.nb), dim3(256), lds_k, s, labels,
+                       p.n, k, p.B, p.blockcnt, conv, iter);
+    hipLaunchKernelGGL(colscan_a, dim3((k + 255) / 256, p.nsegc), dim3(256), 0,
+                       s, p.blockcnt, p.nb, k, p.seglen, p.segsum, conv, iter);
+    hipLaunchKernelGGL(colscan_b, dim3((k + 1023) / 1024), dim3(1024), 0, s,
+                       p.segsum, p.nsegc, k, p.nj, p.off, p.leaf_off, p.ticket,
+                       conv, iter);
+    hipLaunchKernelGGL(scatter_kernel, dim3(p.nb), dim3(64), lds_k, s, labels,
+                       p.n, k, p.B, bits, p.seglen, p.blockcnt, p.segsum, p.off,
+                       dirty, p.perm, conv, iter);
+  }
   if (prof) { prof->end(); prof->begin(KNOR_PROF_LEAF); }
-  int G = 1;
-  while (G < d && G < 64) G *= 2;
-  const int per_block = 256 / G;
-  const int64_t lblocks = (p.max_leaves + per_block - 1) / per_block;
+  const int64_t lblocks = (p.max_leaves + kLeafWaves - 1) / kLeafWaves;
   switch (dt) {
     case KNOR_F64:
-      hipLaunchKernelGGL(leaf_kernel<double>, dim3(lblocks), dim3(256), 0, s,
-                         (const double*)X, d, G, p.perm, p.nj, p.off,
-                         p.leaf_off, k, p.leafsum, done);
+      hipLaunchKernelGGL(leaf_kernel<double>, dim3(lblocks), dim3(64 * kLeafWaves),
+                         0, s, (const double*)X, d, p.perm, p.nj, p.off,
+                         p.leaf_off, k, dirty, p.leafsum, conv, iter);
       break;
     case KNOR_F32:
-      hipLaunchKernelGGL(leaf_kernel<float>, dim3(lblocks), dim3(256), 0, s,
-                         (const float*)X, d, G, p.perm, p.nj, p.off,
-                         p.leaf_off, k, p.leafsum, done);
+      hipLaunchKernelGGL(leaf_kernel<float>, dim3(lblocks), dim3(64 * kLeafWaves),
+                         0, s, (const float*)X, d, p.perm, p.nj, p.off,
+                         p.leaf_off, k, dirty, p.leafsum, conv, iter);
       break;
     case KNOR_BF16:
-      hipLaunchKernelGGL(leaf_kernel<uint16_t>, dim3(lblocks), dim3(256), 0, s,
-                         (const uint16_t*)X, d, G, p.perm, p.nj, p.off,
-                         p.leaf_off, k, p.leafsum, done);
+      hipLaunchKernelGGL(leaf_kernel<uint16_t>, dim3(lblocks), dim3(64 * kLeafWaves),
+                         0, s, (const uint16_t*)X, d, p.perm, p.nj, p.off,
+                         p.leaf_off, k, dirty, p.leafsum, conv, iter);
       break;
   }
   if (prof) { prof->end(); prof->begin(KNOR_PROF_TREE); }
   hipLaunchKernelGGL(tree_finalize, dim3(k), dim3(256), 0, s, p.leafsum, p.nj,
                      p.leaf_off, k, d, C_prev, C_out, counts_out,
                      ops ? ops->Cm2 : nullptr, ops ? ops->cn : nullptr,
-                     ops ? ops->dp : 0, drift, done);
+                     ops ? ops->CT : nullptr, ops ? ops->dp : 0, drift, dirty,
+                     *ctl, conv, iter);
   if (prof) prof->end();
   return hipGetLastError();
 }
