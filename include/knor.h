@@ -88,6 +88,8 @@ typedef struct {
                            the GPU time (HIP events on opts->stream) of every
                            launch of each kernel group (below)               */
   int64_t* profile_launches; /* HOST, optional: KNOR_NPROF launch counts     */
+  int32_t profile_mask; /* bit g set: time kernel group g; 0 = every group.
+                           Each timed launch adds two event records          */
 } knor_opts;
 
 /* Kernel groups timed by opts->profile_ms. */

@@ -46,7 +46,8 @@ class Opts(ctypes.Structure):
                 ("iter_counters", ctypes.c_void_p),
                 ("poll_every", ctypes.c_int32),
                 ("profile_ms", ctypes.c_void_p),
-                ("profile_launches", ctypes.c_void_p)]
+                ("profile_launches", ctypes.c_void_p),
+                ("profile_mask", ctypes.c_int32)]
 
 
 NPROF = 8
@@ -143,9 +144,10 @@ def _opts(prune=True, recheck=1, check_numeric=True, seed=0, stream=None,
     o.iter_counters = iter_counters.ctypes.data if iter_counters is not None else None
     o.poll_every = int(poll_every)
     if profile is not None:
-        ms, launches = profile
+        ms, launches = profile[0], profile[1]
         o.profile_ms = ms.ctypes.data
         o.profile_launches = launches.ctypes.data
+        o.profile_mask = int(profile[2]) if len(profile) > 2 else 0
     return o
 
 
@@ -157,9 +159,10 @@ def fit(X, k, C0=None, init="given", max_iters=100, tol=0.0, prune=True,
     history=True adds stats["label_history"]: (iters, n) int32 CUDA tensor of
     the labels each iteration's assignment produced.  counters=True adds
     stats["counters"]: (iters, 8) int64 numpy array (KNOR_CNT_* columns).
-    out=(C, labels) reuses preallocated output tensors.  profile=(ms, launches)
-    (float64 and int64 numpy arrays of NPROF entries) accumulates per-group
-    GPU time measured with HIP events on the launch stream."""
+    out=(C, labels) reuses preallocated output tensors.  profile=(ms, launches
+    [, mask]) (float64 and int64 numpy arrays of NPROF entries, optional bit
+    mask of groups) accumulates per-group GPU time measured with HIP events
+    on the launch stream."""
     torch = _torch()
     import numpy as np
     L = load()

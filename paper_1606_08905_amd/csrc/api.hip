@@ -114,7 +114,8 @@ hipError_t launch_gather_rows(const void* X, knor_dtype dt, int d,
 // ---------------------------------------------------------------------------
 
 void Prof::begin(int g) {
-  if (!on) return;
+  open = false;
+  if (!on || !((mask >> g) & 1)) return;
   hipEvent_t a = nullptr, b = nullptr;
   if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) {
     (void)hipGetLastError();
@@ -125,11 +126,13 @@ void Prof::begin(int g) {
   groups.push_back(g);
   starts.push_back(a);
   ends.push_back(b);
+  open = true;
 }
 
 void Prof::end() {
-  if (!on || ends.empty()) return;
+  if (!on || !open) return;
   (void)hipEventRecord(ends.back(), stream);
+  open = false;
 }
 
 void Prof::collect(double* ms, int64_t* launches) {
@@ -194,6 +197,7 @@ struct Opts {
   int64_t* iter_counters = nullptr;
   double* profile_ms = nullptr;
   int64_t* profile_launches = nullptr;
+  int profile_mask = 0;
 };
 
 static knor_status read_opts(const knor_opts* o, Opts* out) {
@@ -213,6 +217,7 @@ static knor_status read_opts(const knor_opts* o, Opts* out) {
   out->iter_counters = o->iter_counters;
   out->profile_ms = o->profile_ms;
   out->profile_launches = o->profile_launches;
+  out->profile_mask = o->profile_mask;
   if (o->poll_every > 0) out->poll_every = o->poll_every;
   return KNOR_OK;
 }
@@ -280,7 +285,6 @@ static knor_status fit_impl(const void* X, knor_dtype dt, int64_t n, int d,
   void* upd_ws = nullptr;
   float *u = nullptr, *drift = nullptr, *s_half = nullptr;
   int *list = nullptr, *seg_cnt = nullptr, *flags = nullptr, *ucnt = nullptr;
-  const int64_t units_cap = max_units(n);
   int *flagbuf = nullptr, *dirty = nullptr;
   unsigned long long* ctr = nullptr;
   int64_t* rows_dev = nullptr;
@@ -293,8 +297,8 @@ static knor_status fit_impl(const void* X, knor_dtype dt, int64_t n, int d,
   ar.add((void**)&drift, sizeof(float) * (size_t)k);
   ar.add((void**)&s_half, sizeof(float) * (size_t)k);
   ar.add((void**)&dirty, sizeof(int) * (size_t)k);
-  ar.add((void**)&flags, sizeof(int) * (size_t)nseg * kSeg);
-  ar.add((void**)&ucnt, sizeof(int) * (size_t)units_cap);
+  ar.add((void**)&flags, sizeof(int) * (size_t)tile_f32_flag_capacity(dp, kpad, n, nseg));
+  ar.add((void**)&ucnt, sizeof(int) * (size_t)kTileMaxGrid);
   if (mti) {
     ar.add((void**)&u, sizeof(float) * (size_t)n);
     ar.add((void**)&list, sizeof(int) * (size_t)nseg * kSeg);
@@ -349,6 +353,7 @@ static knor_status fit_impl(const void* X, knor_dtype dt, int64_t n, int d,
   Prof prof;
   prof.stream = s;
   prof.on = o.profile_ms != nullptr || o.profile_launches != nullptr;
+  prof.mask = o.profile_mask ? o.profile_mask : ~0;
   Prof* pp = prof.on ? &prof : nullptr;
   const double tol_n = tol * (double)n;
   int hconv = kNotConverged;
@@ -500,13 +505,13 @@ knor_status knor_assign(const void* X, knor_dtype dt, int64_t n, int32_t d,
   int* conv = nullptr;
   int* ucnt = nullptr;
   unsigned long long* ctr = nullptr;
-  const int64_t units_cap = max_units(n);
   Arena ar;
   ar.add((void**)&ops.Cm2, sizeof(float) * (size_t)ops.kpad * ops.dp);
   ar.add((void**)&ops.cn, sizeof(float) * (size_t)ops.kpad);
   ar.add((void**)&ops.CT, sizeof(double) * (size_t)k * d);
-  ar.add((void**)&flags, sizeof(int) * (size_t)nseg_of_n(n) * kSeg);
-  ar.add((void**)&ucnt, sizeof(int) * (size_t)units_cap);
+  ar.add((void**)&flags, sizeof(int) * (size_t)tile_f32_flag_capacity(
+                              ops.dp, ops.kpad, n, nseg_of_n(n)));
+  ar.add((void**)&ucnt, sizeof(int) * (size_t)kTileMaxGrid);
   ar.add((void**)&ctr, sizeof(unsigned long long) * ROW_STRIDE);
   ar.add((void**)&conv, sizeof(int) * 4);
   if (knor_status r = ar.alloc(s, o.cap)) return r;

@@ -112,46 +112,80 @@ __global__ __launch_bounds__(256) void exact_assign_lane(
   }
 }
 
-// The FP64 recheck.  One wave per tile unit walks the unit's near-tie points;
-// for each point the lanes split the centroids, the point's coordinates are
-// wave-uniform and the transposed centroid copy makes the lanes' reads
-// contiguous.  The lexicographic (D, j) minimum over lanes is the
-// lowest-index argmin.  rchg[unit] receives the number of labels changed.
+// The FP64 recheck.  One workgroup per recheck slice (one slice per tile
+// workgroup); its 256 threads are split into groups of tpf threads
+// (tpf = min(256, pow2 >= k)), each group takes one of the slice's near-tie
+// points and its threads split the centroids, so all (point, centroid)
+// distances of a slice are in flight at once.  Each distance is the
+// canonical FP64 form; the transposed centroid copy makes the threads' reads
+// contiguous.  The lexicographic (D, j) minimum is the lowest-index argmin.
 template <typename T>
-__global__ __launch_bounds__(256) void exact_recheck_wave(
+__global__ __launch_bounds__(256) void exact_recheck_unit(
     const T* __restrict__ X, int d, const double* __restrict__ CT, int k,
-    const int* __restrict__ flags, const int* __restrict__ ucnt, int up,
-    int64_t nunits, int32_t* __restrict__ labels, float* __restrict__ ub,
-    unsigned long long* __restrict__ row, const int* __restrict__ conv,
-    int iter, int* __restrict__ dirty) {
+    int tpf, const int* __restrict__ flags, const int* __restrict__ ucnt,
+    int64_t cap, int32_t* __restrict__ labels,
+    float* __restrict__ ub, unsigned long long* __restrict__ row,
+    const int* __restrict__ conv, int iter, int* __restrict__ dirty) {
+  __shared__ double red_d[4];
+  __shared__ int red_j[4];
   if (*conv < iter) return;
-  const int lane = threadIdx.x & 63;
-  const int64_t wstride = (int64_t)gridDim.x * (blockDim.x >> 6);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int G = 256 / tpf;                   // points per pass
+  const int gsel = threadIdx.x / tpf, t = threadIdx.x % tpf;
   unsigned long long changes = 0;
-  for (int64_t unit = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-       unit < nunits; unit += wstride) {
-    const int nf = ucnt[unit];
-    for (int f = 0; f < nf; ++f) {
-      const int p = __builtin_amdgcn_readfirstlane(flags[unit * up + f]);
+  {
+    const int64_t unit = blockIdx.x;
+    const int nf = ucnt[unit];               // uniform over the workgroup
+    for (int f0 = 0; f0 < nf; f0 += G) {
+      const int f = f0 + gsel;
+      const bool live_f = f < nf;
+      const int p = live_f ? flags[unit * cap + f] : 0;
       const T* x = X + (size_t)p * d;
       double best = INFINITY;
       int a = 0x7fffffff;
-      for (int j = lane; j < k; j += 64) {
+      constexpr int kC = 16;                 // dimensions loaded together
+      for (int j = t; live_f && j < k; j += tpf) {
         double acc = 0.0;
-#pragma unroll 8
-        for (int i = 0; i < d; ++i) {
-          double t = __dsub_rn(to_f64<T>(x[i]), CT[(size_t)i * k + j]);
-          acc = __dadd_rn(acc, __dmul_rn(t, t));
+        for (int i0 = 0; i0 < d; i0 += kC) {
+          double cv[kC], xv[kC];
+#pragma unroll
+          for (int q = 0; q < kC; ++q) {
+            const bool in = i0 + q < d;
+            cv[q] = in ? CT[(size_t)(i0 + q) * k + j] : 0.0;
+            xv[q] = in ? to_f64<T>(x[i0 + q]) : 0.0;
+          }
+#pragma unroll
+          for (int q = 0; q < kC; ++q)
+            if (i0 + q < d) {
+              const double dd = __dsub_rn(xv[q], cv[q]);
+              acc = __dadd_rn(acc, __dmul_rn(dd, dd));
+            }
         }
         if (acc < best) { best = acc; a = j; }
       }
-      for (int off = 32; off > 0; off >>= 1) {
-        double ob = __shfl_xor(best, off);
-        int oa = __shfl_xor(a, off);
+      // minimum within the wave part of the group
+      const int span = tpf < 64 ? tpf : 64;
+      for (int off = span >> 1; off > 0; off >>= 1) {
+        const double ob = __shfl_xor(best, off);
+        const int oa = __shfl_xor(a, off);
         if (ob < best || (ob == best && oa < a)) { best = ob; a = oa; }
       }
-      if (lane == 0) {
-        int32_t old = labels[p];
+      // groups wider than a wave combine their waves through LDS
+      if (tpf > 64) {
+        __syncthreads();
+        if (lane == 0) { red_d[wave] = best; red_j[wave] = a; }
+        __syncthreads();
+        const int w0 = (gsel * tpf) >> 6, nw = tpf >> 6;
+        best = red_d[w0];
+        a = red_j[w0];
+        for (int w = 1; w < nw; ++w) {
+          const double ob = red_d[w0 + w];
+          const int oa = red_j[w0 + w];
+          if (ob < best || (ob == best && oa < a)) { best = ob; a = oa; }
+        }
+      }
+      if (live_f && t == 0) {
+        const int32_t old = labels[p];
         labels[p] = a;
         if (old != a) {
           ++changes;
@@ -184,21 +218,21 @@ hipError_t launch_assign(const CentroidOps& o, const AssignJob& j,
 
 hipError_t launch_recheck(const CentroidOps& o, const AssignJob& j,
                           hipStream_t s) {
-  const bool seg = j.seg_cnt != nullptr;
-  const int64_t nunits = assign_units(o.dp, o.kpad, j.n, seg, j.nseg);
-  const int up = tile_f32_unit_points(o.dp, o.kpad);
-  int64_t blocks = (nunits + 3) / 4;
-  int grid = (int)(blocks < 2048 ? (blocks < 1 ? 1 : blocks) : 2048);
+  const TileGeom g = tile_f32_geometry(o.dp, o.kpad, j.n, j.seg_cnt != nullptr,
+                                       j.nseg);
+  int tpf = 1;
+  while (tpf < o.k && tpf < 256) tpf *= 2;
   switch (j.dt) {
     case KNOR_F32:
-      hipLaunchKernelGGL(exact_recheck_wave<float>, dim3(grid), dim3(256), 0, s,
-                         (const float*)j.X, j.d, o.CT, o.k, j.flags, j.ucnt, up,
-                         nunits, j.labels, j.u, j.row, j.conv, j.iter, j.dirty);
+      hipLaunchKernelGGL(exact_recheck_unit<float>, dim3(g.grid), dim3(256), 0, s,
+                         (const float*)j.X, j.d, o.CT, o.k, tpf, j.flags, j.ucnt,
+                         g.cap, j.labels, j.u, j.row, j.conv, j.iter,
+                         j.dirty);
       break;
     case KNOR_BF16:
-      hipLaunchKernelGGL(exact_recheck_wave<uint16_t>, dim3(grid), dim3(256), 0,
-                         s, (const uint16_t*)j.X, j.d, o.CT, o.k, j.flags,
-                         j.ucnt, up, nunits, j.labels, j.u, j.row, j.conv,
+      hipLaunchKernelGGL(exact_recheck_unit<uint16_t>, dim3(g.grid), dim3(256), 0,
+                         s, (const uint16_t*)j.X, j.d, o.CT, o.k, tpf, j.flags,
+                         j.ucnt, g.cap, j.labels, j.u, j.row, j.conv,
                          j.iter, j.dirty);
       break;
     default:

@@ -190,9 +190,10 @@ struct CentroidOps {
 // The point set one assignment pass covers.
 //  dense:      all n points (seg_cnt == null)
 //  segmented:  segment b holds seg_cnt[b] point indices at list[b*kSeg ...]
-// The tile kernel works in units of up points (see tile_f32_unit_points);
-// unit u writes its near-tie points to flags[u*up ...] and their number to
-// ucnt[u].  Counts of changed labels go to the spread slots of `row`.
+// The FP32 tile runs a grid of TileGeom::grid workgroups; workgroup b writes
+// its near-tie points to flags[b*cap ...] and their number to ucnt[b], and
+// the FP64 recheck reads the same slices.  Counts of changed labels go to
+// the spread slots of `row`.
 struct AssignJob {
   const void* X;
   knor_dtype dt;
@@ -203,8 +204,8 @@ struct AssignJob {
   int nseg;
   int32_t* labels;                   // in: previous labels; out: new labels
   float* u;                          // MTI upper bounds (or null)
-  int* flags;                        // per-unit recheck slices
-  int* ucnt;                         // per unit: recheck slice length
+  int* flags;                        // per-workgroup recheck slices
+  int* ucnt;                         // per workgroup: recheck slice length
   unsigned long long* row;           // this iteration's counter row
   const int* conv;                   // skip when *conv < iter
   int iter;
@@ -212,19 +213,19 @@ struct AssignJob {
   int recheck_all;                   // 1 = send every point to the recheck
 };
 
-// Unit geometry of the FP32 tile (padded dimension dp, padded centroid
-// count kpad): points per unit, and the number of units of a pass.
+// Launch geometry of the FP32 tile (padded dimension dp, padded centroid
+// count kpad) for a dense pass over n points or a segmented pass over nseg
+// segments: grid size and per-workgroup recheck slice capacity.
+constexpr int kTileMaxGrid = 2048;
+struct TileGeom {
+  int grid;
+  int64_t cap;
+  bool resident;
+};
 bool tile_f32_resident(int dp, int kpad);
-int tile_f32_unit_points(int dp, int kpad);
-inline int64_t assign_units(int dp, int kpad, int64_t n, bool segmented,
-                            int nseg) {
-  const int up = tile_f32_unit_points(dp, kpad);
-  return segmented ? (int64_t)nseg * (kSeg / up) : (n + up - 1) / up;
-}
-// capacity (in units) every per-unit array needs for n points
-inline int64_t max_units(int64_t n) {
-  return (int64_t)((n + kSeg - 1) / kSeg) * (kSeg / 16);
-}
+TileGeom tile_f32_geometry(int dp, int kpad, int64_t n, bool segmented, int nseg);
+// entries the flags array needs for either kind of pass
+int64_t tile_f32_flag_capacity(int dp, int kpad, int64_t n, int nseg);
 hipError_t launch_tile_f32(const CentroidOps& o, const AssignJob& j,
                            hipStream_t s);
 
@@ -243,6 +244,8 @@ hipError_t launch_canonical_sum(const double* v, int64_t n, double* tmp,
 struct Prof {
   hipStream_t stream = nullptr;
   bool on = false;
+  int mask = ~0;
+  bool open = false;
   std::vector<int> groups;
   std::vector<hipEvent_t> starts, ends;
   void begin(int g);

@@ -37,6 +37,7 @@ __global__ __launch_bounds__(256) void cc_bounds_kernel(
   for (int j = threadIdx.x; j < k; j += blockDim.x) {
     if (j == i) continue;
     double acc = 0.0;
+#pragma unroll 8
     for (int dim = 0; dim < d; ++dim) {
       double t = __dsub_rn(ci[dim], CT[(size_t)dim * k + j]);
       acc = __dadd_rn(acc, __dmul_rn(t, t));

@@ -23,7 +23,7 @@
 // then every other centroid's exact squared distance exceeds the best one's
 // by more than the FP64 evaluation error of the definition, so the FP64
 // argmin (and its lowest-index rule) must select the same centroid.  Every
-// other point goes to its unit's slice of the FP64 recheck list.
+// other point goes to its workgroup's slice of the FP64 recheck list.
 //
 // Two schedules:
 //  resident  all centroids fit in LDS: staged once per workgroup, then each
@@ -40,31 +40,55 @@ typedef float f4 __attribute__((ext_vector_type(4)));
 
 constexpr int kTileThreads = 256;
 constexpr size_t kResidentLds = 65536;
+constexpr int kResidentGrid = 1024;
+constexpr int kChunkedGrid = kTileMaxGrid;
+static_assert(kResidentGrid <= kTileMaxGrid, "grid bound");
 
-template <int DP>
+// Point blocks of 16 per wave: fewer for wide rows (register budget).
+constexpr int res_pb(int dp) { return dp >= 128 ? 1 : 2; }
+constexpr int chk_pb(int dp) { return dp >= 256 ? 1 : (dp >= 128 ? 2 : 4); }
+
+template <int DP, int PB_>
 struct F32Tile {
   static constexpr int KS = DP / 4;                    // dims per lane group
-  static constexpr int PB = DP >= 256 ? 1 : (DP >= 128 ? 2 : 4);
+  static constexpr int PB = PB_;
   static constexpr int LDA = DP + 4;                   // LDS row stride
   static constexpr int CK = (4096 / DP) < 16 ? 16 : (4096 / DP);
   static constexpr int WUP = 16 * PB;                  // points per wave unit
   static constexpr int BUP = 4 * WUP;                  // points per block unit
 };
 
-static int pb_of(int dp) { return dp >= 256 ? 1 : (dp >= 128 ? 2 : 4); }
-
 bool tile_f32_resident(int dp, int kpad) {
   return (size_t)kpad * (dp + 4) * 4 + (size_t)kpad * 4 <= kResidentLds;
 }
 
-int tile_f32_unit_points(int dp, int kpad) {
-  return (tile_f32_resident(dp, kpad) ? 16 : 64) * pb_of(dp);
+TileGeom tile_f32_geometry(int dp, int kpad, int64_t n, bool seg, int nseg) {
+  TileGeom g{};
+  g.resident = tile_f32_resident(dp, kpad);
+  if (g.resident) {
+    const int wup = 16 * res_pb(dp);
+    const int64_t nwu = seg ? (int64_t)nseg * (kSeg / wup) : (n + wup - 1) / wup;
+    int64_t blocks = (nwu + 3) / 4;
+    g.grid = (int)(blocks < kResidentGrid ? (blocks < 1 ? 1 : blocks) : kResidentGrid);
+    const int64_t per_wave = (nwu + 4LL * g.grid - 1) / (4LL * g.grid);
+    g.cap = per_wave * 4 * wup;
+  } else {
+    const int bup = 64 * chk_pb(dp);
+    const int64_t units = seg ? (int64_t)nseg * (kSeg / bup) : (n + bup - 1) / bup;
+    g.grid = (int)(units < kChunkedGrid ? (units < 1 ? 1 : units) : kChunkedGrid);
+    g.cap = (units + g.grid - 1) / g.grid * bup;
+  }
+  return g;
+}
+
+int64_t tile_f32_flag_capacity(int dp, int kpad, int64_t n, int nseg) {
+  const TileGeom a = tile_f32_geometry(dp, kpad, n, false, nseg);
+  const TileGeom b = tile_f32_geometry(dp, kpad, n, true, nseg);
+  const int64_t ca = (int64_t)a.grid * a.cap, cb = (int64_t)b.grid * b.cap;
+  return ca > cb ? ca : cb;
 }
 
 // min / max without NaN canonicalisation (inputs are finite or +inf)
-__device__ __forceinline__ float fmin_nc(float a, float b) {
-  return __builtin_amdgcn_fmed3f(a, b, -INFINITY);
-}
 __device__ __forceinline__ float fmax_nc(float a, float b) {
   return __builtin_amdgcn_fmed3f(a, b, INFINITY);
 }
@@ -88,26 +112,25 @@ __device__ __forceinline__ void load_slice(float (&dst)[KS], const float* src) {
 }
 
 // Per-wave state for PB blocks of 16 points.
-template <int DP>
+template <class T>
 struct WaveState {
-  static constexpr int KS = F32Tile<DP>::KS, PB = F32Tile<DP>::PB;
-  float bx[PB][KS];
-  int64_t pid[PB];
-  bool valid[PB];
-  double xs[PB];
-  float b1[PB], b2[PB];
-  int i1[PB];
+  float bx[T::PB][T::KS];
+  int64_t pid[T::PB];
+  bool valid[T::PB];
+  double xs[T::PB];
+  float b1[T::PB], b2[T::PB];
+  int i1[T::PB];
 };
 
 // Load the wave's points q0 + pb*16 + col (pb < PB) of a range of length m;
 // with a list, point = list[base + q].
-template <int DP>
-__device__ __forceinline__ void load_points(WaveState<DP>& w,
+template <class T>
+__device__ __forceinline__ void load_points(WaveState<T>& w,
                                             const float* __restrict__ X, int d,
                                             int vec, const int* __restrict__ list,
                                             int64_t base, int64_t q0, int64_t m,
                                             int col, int grp) {
-  constexpr int KS = F32Tile<DP>::KS, PB = F32Tile<DP>::PB;
+  constexpr int KS = T::KS, PB = T::PB;
 #pragma unroll
   for (int pb = 0; pb < PB; ++pb) {
     const int64_t q = q0 + pb * 16 + col;
@@ -137,25 +160,37 @@ __device__ __forceinline__ void load_points(WaveState<DP>& w,
   }
 }
 
-// One block of 16 centroids (rows of A from LDS, norms as the accumulator
-// seed) against the wave's PB point blocks.  The PB accumulation chains are
-// interleaved so consecutive matrix instructions are independent.
-template <int DP>
-__device__ __forceinline__ void tile_block(WaveState<DP>& w, const float* arow,
-                                           const float* nrow, int jb) {
-  constexpr int KS = F32Tile<DP>::KS, PB = F32Tile<DP>::PB;
-  float a[KS];
-  load_slice<KS>(a, arow);
+// Operands of one block of 16 centroids: A slice (rows from LDS) and the
+// accumulator seed (their norms).
+template <class T>
+struct ABlock {
+  float a[T::KS];
   f4 init;
-  init[0] = nrow[0]; init[1] = nrow[1]; init[2] = nrow[2]; init[3] = nrow[3];
+};
+
+template <class T>
+__device__ __forceinline__ void load_ablock(ABlock<T>& o, const float* arow,
+                                            const float* nrow) {
+  load_slice<T::KS>(o.a, arow);
+  o.init = *reinterpret_cast<const f4*>(nrow);
+}
+
+// One block of 16 centroids against the wave's PB point blocks.  The PB
+// accumulation chains are interleaved so consecutive matrix instructions are
+// independent.  Epilogue per value: second-best = med3(best, second, y),
+// then best and its index by one compare and two selects.
+template <class T>
+__device__ __forceinline__ void tile_block(WaveState<T>& w, const ABlock<T>& o,
+                                           int jb) {
+  constexpr int KS = T::KS, PB = T::PB;
   f4 acc[PB];
 #pragma unroll
-  for (int pb = 0; pb < PB; ++pb) acc[pb] = init;
+  for (int pb = 0; pb < PB; ++pb) acc[pb] = o.init;
 #pragma unroll
   for (int s = 0; s < KS; ++s)
 #pragma unroll
     for (int pb = 0; pb < PB; ++pb)
-      acc[pb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[s], w.bx[pb][s], acc[pb], 0, 0, 0);
+      acc[pb] = __builtin_amdgcn_mfma_f32_16x16x4f32(o.a[s], w.bx[pb][s], acc[pb], 0, 0, 0);
 #pragma unroll
   for (int pb = 0; pb < PB; ++pb)
 #pragma unroll
@@ -164,8 +199,25 @@ __device__ __forceinline__ void tile_block(WaveState<DP>& w, const float* arow,
       w.b2[pb] = __builtin_amdgcn_fmed3f(w.b1[pb], w.b2[pb], y);
       const bool lt = y < w.b1[pb];
       w.i1[pb] = lt ? (jb + r) : w.i1[pb];
-      w.b1[pb] = fmin_nc(w.b1[pb], y);
+      w.b1[pb] = lt ? y : w.b1[pb];
     }
+}
+
+// All centroid blocks [c0, c0 + cc) staged at sC/sN, with the next block's
+// operands loaded from LDS before the current block's matrix work.
+template <class T>
+__device__ __forceinline__ void tile_sweep(WaveState<T>& w, const float* sC,
+                                           const float* sN, int cc, int c0,
+                                           int col, int grp) {
+  constexpr int LDA = T::LDA, KS = T::KS;
+  ABlock<T> cur, nxt;
+  load_ablock<T>(cur, &sC[col * LDA + grp * KS], &sN[4 * grp]);
+  for (int cb = 0; cb < cc; cb += 16) {
+    if (cb + 16 < cc)
+      load_ablock<T>(nxt, &sC[(cb + 16 + col) * LDA + grp * KS], &sN[cb + 16 + 4 * grp]);
+    tile_block<T>(w, cur, c0 + cb + 4 * grp);
+    cur = nxt;
+  }
 }
 
 // Largest fp32(|c|^2) over the real centroids of a staged chunk.
@@ -180,9 +232,9 @@ __device__ __forceinline__ float chunk_cmax(const float* sN, int cc, int c0,
 }
 
 // Combine the four lane groups (each saw a different quarter of centroids).
-template <int DP>
-__device__ __forceinline__ void merge_groups(WaveState<DP>& w) {
-  constexpr int PB = F32Tile<DP>::PB;
+template <class T>
+__device__ __forceinline__ void merge_groups(WaveState<T>& w) {
+  constexpr int PB = T::PB;
 #pragma unroll
   for (int off = 16; off <= 32; off <<= 1) {
 #pragma unroll
@@ -191,10 +243,13 @@ __device__ __forceinline__ void merge_groups(WaveState<DP>& w) {
       const float ob2 = __shfl_xor(w.b2[pb], off);
       const int oi1 = __shfl_xor(w.i1[pb], off);
       w.xs[pb] += __shfl_xor(w.xs[pb], off);
-      const float nb2 = fmin_nc(fmax_nc(w.b1[pb], ob1), fmin_nc(w.b2[pb], ob2));
+      // second best of the union: min(max(b1, ob1), min(b2, ob2))
+      const float hi = w.b1[pb] < ob1 ? ob1 : w.b1[pb];
+      const float lo2 = w.b2[pb] < ob2 ? w.b2[pb] : ob2;
+      const float nb2 = hi < lo2 ? hi : lo2;
       const bool take = ob1 < w.b1[pb] || (ob1 == w.b1[pb] && oi1 < w.i1[pb]);
       w.i1[pb] = take ? oi1 : w.i1[pb];
-      w.b1[pb] = fmin_nc(w.b1[pb], ob1);
+      w.b1[pb] = take ? ob1 : w.b1[pb];
       w.b2[pb] = nb2;
     }
   }
@@ -202,12 +257,12 @@ __device__ __forceinline__ void merge_groups(WaveState<DP>& w) {
 
 // Decide each point (lane group g finalises point block pb with pb % 4 == g).
 // Writes labels / bounds of decided points; returns per-block flags.
-template <int DP>
+template <class T>
 __device__ __forceinline__ void finalize_points(
-    WaveState<DP>& w, float cmax, int d, int grp, int recheck_all,
+    WaveState<T>& w, float cmax, int d, int grp, int recheck_all,
     int32_t* __restrict__ labels, float* __restrict__ ub, int* __restrict__ dirty,
-    bool (&flag)[F32Tile<DP>::PB], bool& changed) {
-  constexpr int PB = F32Tile<DP>::PB;
+    bool (&flag)[T::PB], bool& changed) {
+  constexpr int PB = T::PB;
   static_assert(PB <= 4, "one finalised point per lane");
   const double R2 = (double)cmax * (1.0 + 2.384185791015625e-07);  // 1+2^-22
   const double u24 = 5.9604644775390625e-08;                        // 2^-24
@@ -260,24 +315,48 @@ __device__ __forceinline__ bool unit_range(int64_t unit, int up, int64_t n,
   return true;
 }
 
+// Append this wave's flagged points to the workgroup's slice.
+template <class T>
+__device__ __forceinline__ int append_flags(const WaveState<T>& w,
+                                            const bool (&flag)[T::PB],
+                                            int* sFlag, int* __restrict__ slice,
+                                            int lane) {
+  int total = 0;
+#pragma unroll
+  for (int pb = 0; pb < T::PB; ++pb) total += __popcll(__ballot(flag[pb]));
+  if (total == 0) return 0;
+  int base = 0;
+  if (lane == 0) base = atomicAdd(sFlag, total);           // LDS
+  base = __shfl(base, 0);
+#pragma unroll
+  for (int pb = 0; pb < T::PB; ++pb) {
+    const uint64_t fm = __ballot(flag[pb]);
+    if (flag[pb]) slice[base + __popcll(fm & lanemask_lt())] = (int)w.pid[pb];
+    base += __popcll(fm);
+  }
+  return total;
+}
+
 template <int DP>
 __global__ __launch_bounds__(kTileThreads) void tile_f32_resident_kernel(
     const float* __restrict__ X, int64_t n, int d,
     const float* __restrict__ Cm2, const float* __restrict__ cn, int k,
     int kpad, const int* __restrict__ list, const int* __restrict__ seg_cnt,
     int nseg, int32_t* __restrict__ labels, float* __restrict__ ub,
-    int* __restrict__ flags, int* __restrict__ ucnt,
+    int* __restrict__ flags, int64_t cap, int* __restrict__ ucnt,
     unsigned long long* __restrict__ row, const int* __restrict__ conv,
     int iter, int* __restrict__ dirty, int recheck_all, int vec) {
-  using T = F32Tile<DP>;
+  using T = F32Tile<DP, res_pb(DP)>;
   constexpr int LDA = T::LDA, PB = T::PB, WUP = T::WUP;
   extern __shared__ __attribute__((aligned(16))) float smem[];
+  __shared__ int sFlag;
   float* sC = smem;
   float* sN = smem + (size_t)kpad * LDA;
   if (*conv < iter) return;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int col = lane & 15, grp = lane >> 4;
 
+  if (threadIdx.x == 0) sFlag = 0;
   for (int e = threadIdx.x; e < kpad * (DP / 4); e += kTileThreads) {
     const int r = e / (DP / 4), q4 = e - r * (DP / 4);
     *reinterpret_cast<float4*>(&sC[r * LDA + q4 * 4]) =
@@ -287,41 +366,31 @@ __global__ __launch_bounds__(kTileThreads) void tile_f32_resident_kernel(
   __syncthreads();
   const float cmax = chunk_cmax(sN, kpad, 0, k, lane);
 
+  int* slice = flags + (int64_t)blockIdx.x * cap;
   const int64_t nwu = seg_cnt ? (int64_t)nseg * (kSeg / WUP) : (n + WUP - 1) / WUP;
-  WaveState<DP> w;
+  WaveState<T> w;
   unsigned long long tot_flag = 0, tot_chg = 0;
   for (int64_t wu = (int64_t)blockIdx.x * 4 + wave; wu < nwu;
        wu += (int64_t)gridDim.x * 4) {
     int64_t q0, m, base;
-    if (!unit_range(wu, WUP, n, seg_cnt, nseg, q0, m, base)) {
-      if (lane == 0) ucnt[wu] = 0;
-      continue;
-    }
-    load_points<DP>(w, X, d, vec, list, base, q0, m, col, grp);
-    for (int cb = 0; cb < kpad; cb += 16)
-      tile_block<DP>(w, &sC[(cb + col) * LDA + grp * T::KS], &sN[cb + 4 * grp],
-                     cb + 4 * grp);
-    merge_groups<DP>(w);
+    if (!unit_range(wu, WUP, n, seg_cnt, nseg, q0, m, base)) continue;
+    load_points<T>(w, X, d, vec, list, base, q0, m, col, grp);
+    tile_sweep<T>(w, sC, sN, kpad, 0, col, grp);
+    merge_groups<T>(w);
     bool flag[PB], changed;
-    finalize_points<DP>(w, cmax, d, grp, recheck_all, labels, ub, dirty, flag,
-                        changed);
-    int nf = 0;
-#pragma unroll
-    for (int pb = 0; pb < PB; ++pb) {
-      const uint64_t fm = __ballot(flag[pb]);
-      if (flag[pb]) flags[wu * WUP + nf + __popcll(fm & lanemask_lt())] = (int)w.pid[pb];
-      nf += __popcll(fm);
-    }
+    finalize_points<T>(w, cmax, d, grp, recheck_all, labels, ub, dirty, flag,
+                       changed);
+    const int nf = append_flags<T>(w, flag, &sFlag, slice, lane);
     const int nc = __popcll(__ballot(changed));
     if (lane == 0) {
-      ucnt[wu] = nf;
       tot_flag += nf;
       tot_chg += nc;
     }
   }
   const int q[2] = {SLOT_FLAGGED, SLOT_CHANGED};
   const unsigned long long v[2] = {tot_flag, tot_chg};
-  block_add_slots<2>(row, q, v);
+  block_add_slots<2>(row, q, v);               // includes a barrier
+  if (threadIdx.x == 0) ucnt[blockIdx.x] = sFlag;
 }
 
 template <int DP>
@@ -330,33 +399,31 @@ __global__ __launch_bounds__(kTileThreads) void tile_f32_chunked_kernel(
     const float* __restrict__ Cm2, const float* __restrict__ cn, int k,
     int kpad, const int* __restrict__ list, const int* __restrict__ seg_cnt,
     int nseg, int32_t* __restrict__ labels, float* __restrict__ ub,
-    int* __restrict__ flags, int* __restrict__ ucnt,
+    int* __restrict__ flags, int64_t cap, int* __restrict__ ucnt,
     unsigned long long* __restrict__ row, const int* __restrict__ conv,
     int iter, int* __restrict__ dirty, int recheck_all, int vec) {
-  using T = F32Tile<DP>;
+  using T = F32Tile<DP, chk_pb(DP)>;
   constexpr int LDA = T::LDA, PB = T::PB, CK = T::CK, WUP = T::WUP, BUP = T::BUP;
   __shared__ __attribute__((aligned(16))) float sC[CK * LDA];
-  __shared__ float sN[CK];
+  __shared__ __attribute__((aligned(16))) float sN[CK];
   __shared__ int sFlag, sChg;
   if (*conv < iter) return;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int col = lane & 15, grp = lane >> 4;
   const int64_t units = seg_cnt ? (int64_t)nseg * (kSeg / BUP) : (n + BUP - 1) / BUP;
+  if (threadIdx.x == 0) { sFlag = 0; sChg = 0; }
 
-  WaveState<DP> w;
-  unsigned long long tot_flag = 0, tot_chg = 0;
+  int* slice = flags + (int64_t)blockIdx.x * cap;
+  WaveState<T> w;
   for (int64_t unit = blockIdx.x; unit < units; unit += gridDim.x) {
     int64_t q0, m, base;
-    if (!unit_range(unit, BUP, n, seg_cnt, nseg, q0, m, base)) {
-      if (threadIdx.x == 0) ucnt[unit] = 0;
+    if (!unit_range(unit, BUP, n, seg_cnt, nseg, q0, m, base))
       continue;                                // uniform over the workgroup
-    }
-    load_points<DP>(w, X, d, vec, list, base, q0 + wave * WUP, m, col, grp);
+    load_points<T>(w, X, d, vec, list, base, q0 + wave * WUP, m, col, grp);
     float cmax = 0.0f;
     for (int c0 = 0; c0 < kpad; c0 += CK) {
       const int cc = (kpad - c0) < CK ? (kpad - c0) : CK;
       __syncthreads();
-      if (c0 == 0 && threadIdx.x == 0) { sFlag = 0; sChg = 0; }
       for (int e = threadIdx.x; e < cc * (DP / 4); e += kTileThreads) {
         const int r = e / (DP / 4), q4 = e - r * (DP / 4);
         *reinterpret_cast<float4*>(&sC[r * LDA + q4 * 4]) =
@@ -365,60 +432,44 @@ __global__ __launch_bounds__(kTileThreads) void tile_f32_chunked_kernel(
       for (int e = threadIdx.x; e < cc; e += kTileThreads) sN[e] = cn[c0 + e];
       __syncthreads();
       cmax = fmax_nc(cmax, chunk_cmax(sN, cc, c0, k, lane));
-      for (int cb = 0; cb < cc; cb += 16)
-        tile_block<DP>(w, &sC[(cb + col) * LDA + grp * T::KS], &sN[cb + 4 * grp],
-                       c0 + cb + 4 * grp);
+      tile_sweep<T>(w, sC, sN, cc, c0, col, grp);
     }
-    merge_groups<DP>(w);
+    merge_groups<T>(w);
     bool flag[PB], changed;
-    finalize_points<DP>(w, cmax, d, grp, recheck_all, labels, ub, dirty, flag,
-                        changed);
-#pragma unroll
-    for (int pb = 0; pb < PB; ++pb) {
-      const uint64_t fm = __ballot(flag[pb]);
-      if (fm) {
-        int fb = 0;
-        if (lane == __ffsll((unsigned long long)fm) - 1) fb = atomicAdd(&sFlag, __popcll(fm));
-        fb = __shfl(fb, __ffsll((unsigned long long)fm) - 1);
-        if (flag[pb]) flags[unit * BUP + fb + __popcll(fm & lanemask_lt())] = (int)w.pid[pb];
-      }
-    }
+    finalize_points<T>(w, cmax, d, grp, recheck_all, labels, ub, dirty, flag,
+                       changed);
+    append_flags<T>(w, flag, &sFlag, slice, lane);
     const uint64_t cm = __ballot(changed);
-    if (cm && lane == __ffsll((unsigned long long)cm) - 1) atomicAdd(&sChg, __popcll(cm));
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      ucnt[unit] = sFlag;
-      tot_flag += sFlag;
-      tot_chg += sChg;
-    }
+    if (cm && lane == 0) atomicAdd(&sChg, __popcll(cm));
   }
+  __syncthreads();
   const int q[2] = {SLOT_FLAGGED, SLOT_CHANGED};
-  const unsigned long long v[2] = {tot_flag, tot_chg};
+  const unsigned long long v[2] = {threadIdx.x == 0 ? (unsigned long long)sFlag : 0ull,
+                                   threadIdx.x == 0 ? (unsigned long long)sChg : 0ull};
   block_add_slots<2>(row, q, v);
+  if (threadIdx.x == 0) ucnt[blockIdx.x] = sFlag;
 }
 
 template <int DP>
 static hipError_t launch_dp(const CentroidOps& o, const AssignJob& j,
                             hipStream_t s) {
-  using T = F32Tile<DP>;
   const int vec = (int)(j.d == DP && ((uintptr_t)j.X & 15) == 0);
   const bool seg = j.seg_cnt != nullptr;
-  if (tile_f32_resident(DP, o.kpad)) {
-    const int64_t nwu = seg ? (int64_t)j.nseg * (kSeg / T::WUP) : (j.n + T::WUP - 1) / T::WUP;
-    int64_t blocks = (nwu + 3) / 4;
-    const int grid = (int)(blocks < 1024 ? (blocks < 1 ? 1 : blocks) : 1024);
+  const TileGeom g = tile_f32_geometry(DP, o.kpad, j.n, seg, j.nseg);
+  if (g.resident) {
+    using T = F32Tile<DP, res_pb(DP)>;
     const size_t lds = (size_t)o.kpad * T::LDA * 4 + (size_t)o.kpad * 4;
-    hipLaunchKernelGGL(tile_f32_resident_kernel<DP>, dim3(grid), dim3(kTileThreads),
+    hipLaunchKernelGGL(tile_f32_resident_kernel<DP>, dim3(g.grid), dim3(kTileThreads),
                        lds, s, (const float*)j.X, j.n, j.d, o.Cm2, o.cn, o.k,
                        o.kpad, j.list, j.seg_cnt, j.nseg, j.labels, j.u, j.flags,
-                       j.ucnt, j.row, j.conv, j.iter, j.dirty, j.recheck_all, vec);
+                       g.cap, j.ucnt, j.row, j.conv, j.iter, j.dirty,
+                       j.recheck_all, vec);
   } else {
-    const int64_t units = seg ? (int64_t)j.nseg * (kSeg / T::BUP) : (j.n + T::BUP - 1) / T::BUP;
-    const int grid = (int)(units < 2048 ? (units < 1 ? 1 : units) : 2048);
-    hipLaunchKernelGGL(tile_f32_chunked_kernel<DP>, dim3(grid), dim3(kTileThreads),
+    hipLaunchKernelGGL(tile_f32_chunked_kernel<DP>, dim3(g.grid), dim3(kTileThreads),
                        0, s, (const float*)j.X, j.n, j.d, o.Cm2, o.cn, o.k,
                        o.kpad, j.list, j.seg_cnt, j.nseg, j.labels, j.u, j.flags,
-                       j.ucnt, j.row, j.conv, j.iter, j.dirty, j.recheck_all, vec);
+                       g.cap, j.ucnt, j.row, j.conv, j.iter, j.dirty,
+                       j.recheck_all, vec);
   }
   return hipGetLastError();
 }

@@ -39,12 +39,15 @@ static bool fused_sort(int k) { return k <= kFusedMaxK; }
 
 static int choose_block(int64_t n, int k) {
   if (fused_sort(k)) {
-    // sub-range per wave; a workgroup covers kFusedWaves sub-ranges and the
-    // range-total matrix stays below 2^16 entries
-    const int64_t unit = (int64_t)kFusedWaves * 1024;
-    int64_t r = (n * (int64_t)k + unit * 65536 - 1) / (unit * 65536);
-    if (r < 1) r = 1;
-    return (int)(1024 * r);
+    // sub-range per wave (a multiple of 64 points); a workgroup covers
+    // kFusedWaves sub-ranges; at most 64 workgroups, so that each one's
+    // prefix over the earlier ranges stays short
+    int64_t ranges = 65536 / k;
+    if (ranges > 64) ranges = 64;
+    int64_t sb = (n + kFusedWaves * ranges - 1) / (kFusedWaves * ranges);
+    sb = (sb + 63) / 64 * 64;
+    if (sb < 64) sb = 64;
+    return (int)sb;
   }
   // one wave per block: enough blocks to occupy the GPU, while the nb x k
   // count matrix stays within max(n, 2^24) entries
@@ -220,12 +223,14 @@ __global__ __launch_bounds__(1024) void scatter_fused(
   const int r = blockIdx.x, wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int j = threadIdx.x;                 // k <= 1024: one cluster per thread
   int tot = 0, pre = 0;
-  if (j < k)
+  if (j < k) {
+#pragma unroll 16
     for (int rr = 0; rr < nr; ++rr) {
       const int v = cnt[((size_t)rr * (kFusedWaves + 1) + kFusedWaves) * k + j];
       tot += v;
-      if (rr < r) pre += v;
+      pre += rr < r ? v : 0;
     }
+  }
   // exclusive prefix over clusters of the totals (members and leaves)
   const int lv = (tot + kLeaf - 1) / kLeaf;
   sa[threadIdx.x] = tot;
@@ -260,27 +265,38 @@ __global__ __launch_bounds__(1024) void scatter_fused(
     }
   }
   __syncthreads();
-  // each wave walks its sub-range in chunks of 64 with its own table
+  // each wave walks its sub-range in chunks of 64 with its own table; the
+  // labels of 16 chunks are loaded ahead so the walk only waits on LDS
   int* t = run + wave * k;
   const uint64_t lt = lanemask_lt();
   const int64_t p0 = ((int64_t)r * kFusedWaves + wave) * SB;
   const int64_t p1 = p0 + SB < n ? p0 + SB : n;
-  for (int64_t c = p0; c < p1; c += 64) {
-    const int64_t p = c + lane;
-    int lab = p < p1 ? labels[p] : 0;
-    const bool valid = p < p1 && (unsigned)lab < (unsigned)k;
-    if (!valid) lab = 0;
-    const uint64_t mask = same_label_mask(valid, lab, bits);
-    const int rank = __popcll(mask & lt);
-    const int cntl = __popcll(mask);
-    int pos = 0;
-    if (valid) pos = t[lab] + rank;
-    __builtin_amdgcn_wave_barrier();
-    if (valid) {
-      if (!dirty || dirty[lab]) perm[pos] = (int)p;
-      if (rank == cntl - 1) t[lab] = pos + 1;
+  constexpr int kAhead = 16;
+  for (int64_t c0 = p0; c0 < p1; c0 += 64 * kAhead) {
+    int labs[kAhead];
+#pragma unroll
+    for (int q = 0; q < kAhead; ++q) {
+      const int64_t p = c0 + q * 64 + lane;
+      labs[q] = p < p1 ? labels[p] : -1;
     }
-    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (int q = 0; q < kAhead; ++q) {
+      const int64_t p = c0 + q * 64 + lane;
+      int lab = labs[q];
+      const bool valid = p < p1 && (unsigned)lab < (unsigned)k;
+      if (!valid) lab = 0;
+      const uint64_t mask = same_label_mask(valid, lab, bits);
+      const int rank = __popcll(mask & lt);
+      const int cntl = __popcll(mask);
+      int pos = 0;
+      if (valid) pos = t[lab] + rank;
+      __builtin_amdgcn_wave_barrier();
+      if (valid) {
+        if (!dirty || dirty[lab]) perm[pos] = (int)p;
+        if (rank == cntl - 1) t[lab] = pos + 1;
+      }
+      __builtin_amdgcn_wave_barrier();
+    }
   }
 }
 
@@ -487,12 +503,17 @@ __global__ __launch_bounds__(256) void tree_finalize(
   SKIP_IF_CONVERGED
   const int j = blockIdx.x;
 
-  if (j == 0 && ctl.row && threadIdx.x == 0) {
+  if (j == 0 && ctl.row) {
+    // fold the spread slots: thread (q, i) loads slot i of quantity q
+    __shared__ unsigned long long slot[NSLOTQ * kChgSlots];
     unsigned long long* row = ctl.row;
+    if (threadIdx.x < NSLOTQ * kChgSlots) slot[threadIdx.x] = row[threadIdx.x * kSlotStride];
+    __syncthreads();
+    if (threadIdx.x == 0) {
     unsigned long long tot[NSLOTQ];
     for (int q = 0; q < NSLOTQ; ++q) {
       unsigned long long s = 0;
-      for (int i = 0; i < kChgSlots; ++i) s += row[(q * kChgSlots + i) * kSlotStride];
+      for (int i = 0; i < kChgSlots; ++i) s += slot[q * kChgSlots + i];
       tot[q] = s;
     }
     row[ROW_CHANGED] = tot[SLOT_CHANGED];
@@ -508,6 +529,7 @@ __global__ __launch_bounds__(256) void tree_finalize(
       row[ROW_SCANNED] = (unsigned long long)ctl.n;
     }
     if ((double)tot[SLOT_CHANGED] <= ctl.tol_n) *ctl.conv = iter;
+    }
   }
 
   const int cntj = nj[j];
