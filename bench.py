@@ -30,6 +30,34 @@ PEAK_BF16_MFMA = 2516.6e12
 PEAK_HBM = 8.0e12              # bytes/s
 PEAK_FP64_VALU = 78.6e12
 
+# HBM bytes per launch of a kernel group, from rocprofv3 FETCH_SIZE and
+# WRITE_SIZE runs on this workload (medians over launches), each scaled by what
+# the counter reads for a 2 GiB device copy (fetch x2.0, write x1.0).  A figure
+# is reported only while the kernel sources it was measured on are unchanged.
+MEASURED_TRAFFIC = {
+    "assign_list": {
+        "bytes": (39695.8 + 7542.2) * 1024,
+        "sources": {
+            "tile_f32.hip": "16b5beb74478542c900fca0683866aa6a62bfe82e17c62eed060fba303f92508",
+            "common.h": "e319868d6f43accd7e8752a544a1ee98906d8454174194c561409a60b3a85dc9",
+        },
+    },
+}
+
+
+def measured_traffic(group):
+    import hashlib
+    m = MEASURED_TRAFFIC.get(group)
+    if m is None:
+        return None
+    csrc = os.path.join(ROOT, "paper_1606_08905_amd", "csrc")
+    for fname, digest in m["sources"].items():
+        with open(os.path.join(csrc, fname), "rb") as f:
+            if hashlib.sha256(f.read()).hexdigest() != digest:
+                return None
+    return m["bytes"]
+
+
 METRIC = ("Lloyd iters/s and point·centroid dists/s (% MFMA peak) "
           "at exact assignments")
 
@@ -42,6 +70,10 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=0,
                     help="oracle iterations for the CPU baseline (0 = whole fit)")
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="also run one device-to-device copy of this many MiB "
+                         "before the timed region (a known-size kernel for "
+                         "scaling HBM byte counters)")
     return ap.parse_args()
 
 
@@ -99,6 +131,14 @@ def main():
     for _ in range(a.warmup):
         step()
     torch.cuda.synchronize()
+    if a.copy_calibration_mib > 0:
+        nel = a.copy_calibration_mib << 18            # float32 elements
+        src = torch.ones(nel, dtype=torch.float32, device=X.device)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     # untimed calibration fit with every kernel group under HIP events: the
     # per-group breakdown, and which group dominates
@@ -146,7 +186,8 @@ def main():
         roof = {"kernel": knor.PROF_GROUPS[g_dom], "bound": bound,
                 "achieved": round(achieved / scale, 3),
                 "peak": round(peak / scale, 1), "unit": unit,
-                "frac": round(achieved / peak, 4), "traffic": None,
+                "frac": round(achieved / peak, 4),
+                "traffic": measured_traffic(knor.PROF_GROUPS[g_dom]),
                 "us_per_launch": round(sec_per_launch * 1e6, 3)}
     # the dense distance tile (iteration 0), whatever dominates
     tile = None

@@ -82,7 +82,7 @@ typedef struct {
   int64_t* iter_counters; /* HOST, optional: max_iters x KNOR_NCOUNTERS; row
                              t receives that iteration's counters (below)    */
   int32_t poll_every;   /* knor_fit checks convergence on the host every this
-                           many iterations (default 4); iterations enqueued
+                           many iterations (default 8); iterations enqueued
                            after convergence do no work                       */
   double* profile_ms;   /* HOST, optional: KNOR_NPROF entries.  knor_fit adds
                            the GPU time (HIP events on opts->stream) of every

@@ -112,56 +112,146 @@ __global__ __launch_bounds__(256) void exact_assign_lane(
   }
 }
 
-// The FP64 recheck.  One workgroup per recheck slice (one slice per tile
-// workgroup); its 256 threads are split into groups of tpf threads
-// (tpf = min(256, pow2 >= k)), each group takes one of the slice's near-tie
-// points and its threads split the centroids, so all (point, centroid)
-// distances of a slice are in flight at once.  Each distance is the
-// canonical FP64 form; the transposed centroid copy makes the threads' reads
-// contiguous.  The lexicographic (D, j) minimum is the lowest-index argmin.
+// Sixteen dimensions [i0, i0 + 16) of a point row, as FP64.  `full` means
+// the chunk lies inside the row and the row start is 16-byte aligned, so the
+// chunk is read with 16-byte loads; otherwise dimensions past the end are
+// clamped to the last one (valid addresses; the caller drops them).
 template <typename T>
+__device__ __forceinline__ void load_x_chunk(const T* __restrict__ x, int i0,
+                                             int d, bool full, double (&xv)[16]) {
+  if (full) {
+    if constexpr (sizeof(T) == 4) {
+#pragma unroll
+      for (int q4 = 0; q4 < 4; ++q4) {
+        const float4 v = reinterpret_cast<const float4*>(x + i0)[q4];
+        xv[4 * q4] = v.x; xv[4 * q4 + 1] = v.y;
+        xv[4 * q4 + 2] = v.z; xv[4 * q4 + 3] = v.w;
+      }
+      return;
+    } else if constexpr (sizeof(T) == 2) {
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const uint4 v = reinterpret_cast<const uint4*>(x + i0)[h];
+        const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          xv[8 * h + 2 * e] = (double)__uint_as_float(w[e] << 16);
+          xv[8 * h + 2 * e + 1] = (double)__uint_as_float(w[e] & 0xffff0000u);
+        }
+      }
+      return;
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int dim = (i0 + q < d) ? (i0 + q) : (d - 1);
+    xv[q] = to_f64<T>(x[dim]);
+  }
+}
+
+// The FP64 recheck.  Workgroup b takes the recheck slices [b*S, b*S + S)
+// (one slice per tile workgroup) as one list of nf near-tie points, so that
+// the grid is small enough to be resident at once.  Its 256 threads are
+// split into groups of tpf threads, each group takes one point and its
+// threads split the centroids.  tpf starts at min(256, pow2 >= k) and is
+// halved until all nf points fit in one pass, so that a workgroup costs a
+// fixed number of dependent memory round trips.  Each distance is the
+// canonical FP64 form.  With LDSC the FP64 centroids are staged in LDS once
+// per workgroup (row stride d + 1 doubles); otherwise they are read from the
+// transposed global copy, which makes the threads' reads contiguous.  The
+// lexicographic (D, j) minimum is the lowest-index argmin.
+constexpr int kRecheckSlices = 4;
+
+template <typename T, bool LDSC>
 __global__ __launch_bounds__(256) void exact_recheck_unit(
-    const T* __restrict__ X, int d, const double* __restrict__ CT, int k,
-    int tpf, const int* __restrict__ flags, const int* __restrict__ ucnt,
-    int64_t cap, int32_t* __restrict__ labels,
+    const T* __restrict__ X, int d, int vec, const double* __restrict__ C64,
+    const double* __restrict__ CT, int k,
+    int tpf_max, const int* __restrict__ flags, const int* __restrict__ ucnt,
+    int nslices, int64_t cap, int32_t* __restrict__ labels,
     float* __restrict__ ub, unsigned long long* __restrict__ row,
     const int* __restrict__ conv, int iter, int* __restrict__ dirty) {
+  extern __shared__ __attribute__((aligned(16))) double sC[];
   __shared__ double red_d[4];
   __shared__ int red_j[4];
+  // this workgroup's slices and the start of each within its list (read
+  // together with the convergence flag: one round trip)
+  const int s0 = blockIdx.x * kRecheckSlices;
+  int cnt[kRecheckSlices];
+#pragma unroll
+  for (int i = 0; i < kRecheckSlices; ++i)
+    cnt[i] = s0 + i < nslices ? ucnt[s0 + i] : 0;
   if (*conv < iter) return;
+  int sstart[kRecheckSlices + 1];
+  sstart[0] = 0;
+#pragma unroll
+  for (int i = 0; i < kRecheckSlices; ++i) sstart[i + 1] = sstart[i] + cnt[i];
+  const int nf = sstart[kRecheckSlices];     // uniform over the workgroup
+  if (nf == 0) return;
+  int tpf = tpf_max;
+  while (tpf > 1 && (256 / tpf) < nf) tpf >>= 1;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int G = 256 / tpf;                   // points per pass
   const int gsel = threadIdx.x / tpf, t = threadIdx.x % tpf;
+  auto point_of = [&](int f) {
+    int si = 0;
+#pragma unroll
+    for (int i = 1; i < kRecheckSlices; ++i) si += (f >= sstart[i]) ? 1 : 0;
+    return flags[(int64_t)(s0 + si) * cap + (f - sstart[si])];
+  };
+  // the first pass's point index is fetched before the centroid staging
+  int p_next = gsel < nf ? point_of(gsel) : 0;
+  const int ldc = d + 1;
+  if constexpr (LDSC) {
+    for (int e = threadIdx.x; e < k * d; e += 256) {
+      const int jj = e / d, ii = e - jj * d;
+      sC[jj * ldc + ii] = C64[e];
+    }
+    __syncthreads();
+  }
   unsigned long long changes = 0;
   {
-    const int64_t unit = blockIdx.x;
-    const int nf = ucnt[unit];               // uniform over the workgroup
     for (int f0 = 0; f0 < nf; f0 += G) {
       const int f = f0 + gsel;
       const bool live_f = f < nf;
-      const int p = live_f ? flags[unit * cap + f] : 0;
+      const int p = p_next;
+      if (f0 + G < nf) p_next = f + G < nf ? point_of(f + G) : 0;
       const T* x = X + (size_t)p * d;
+      const int32_t old = (live_f && t == 0) ? labels[p] : 0;
       double best = INFINITY;
       int a = 0x7fffffff;
       constexpr int kC = 16;                 // dimensions loaded together
-      for (int j = t; live_f && j < k; j += tpf) {
-        double acc = 0.0;
+      // two centroids per step (j and j + tpf), so that both rows' loads
+      // are in flight together; a thread visits its centroids in
+      // increasing index, so a strict "<" keeps the lowest index
+      for (int j = t; live_f && j < k; j += 2 * tpf) {
+        const bool has2 = j + tpf < k;
+        const int j2 = has2 ? j + tpf : j;
+        double acc = 0.0, acc2 = 0.0;
         for (int i0 = 0; i0 < d; i0 += kC) {
-          double cv[kC], xv[kC];
+          double cv[kC], cv2[kC], xv[kC];
+          load_x_chunk<T>(x, i0, d, vec && i0 + kC <= d, xv);
 #pragma unroll
           for (int q = 0; q < kC; ++q) {
-            const bool in = i0 + q < d;
-            cv[q] = in ? CT[(size_t)(i0 + q) * k + j] : 0.0;
-            xv[q] = in ? to_f64<T>(x[i0 + q]) : 0.0;
+            const int dim = (i0 + q < d) ? (i0 + q) : (d - 1);
+            if constexpr (LDSC) {
+              cv[q] = sC[j * ldc + dim];
+              cv2[q] = sC[j2 * ldc + dim];
+            } else {
+              cv[q] = CT[(size_t)dim * k + j];
+              cv2[q] = CT[(size_t)dim * k + j2];
+            }
           }
 #pragma unroll
           for (int q = 0; q < kC; ++q)
             if (i0 + q < d) {
               const double dd = __dsub_rn(xv[q], cv[q]);
               acc = __dadd_rn(acc, __dmul_rn(dd, dd));
+              const double dd2 = __dsub_rn(xv[q], cv2[q]);
+              acc2 = __dadd_rn(acc2, __dmul_rn(dd2, dd2));
             }
         }
         if (acc < best) { best = acc; a = j; }
+        if (has2 && acc2 < best) { best = acc2; a = j2; }
       }
       // minimum within the wave part of the group
       const int span = tpf < 64 ? tpf : 64;
@@ -185,7 +275,6 @@ __global__ __launch_bounds__(256) void exact_recheck_unit(
         }
       }
       if (live_f && t == 0) {
-        const int32_t old = labels[p];
         labels[p] = a;
         if (old != a) {
           ++changes;
@@ -216,6 +305,27 @@ hipError_t launch_assign(const CentroidOps& o, const AssignJob& j,
   return hipErrorNotSupported;
 }
 
+constexpr size_t kRecheckLds = 65536;
+
+template <typename T>
+static void launch_recheck_t(const CentroidOps& o, const AssignJob& j,
+                             const TileGeom& g, int tpf, hipStream_t s) {
+  const int vec = (int)(((uintptr_t)j.X & 15) == 0 &&
+                        ((size_t)j.d * sizeof(T)) % 16 == 0);
+  const size_t lds = (size_t)o.k * (j.d + 1) * sizeof(double);
+  const int grid = (g.grid + kRecheckSlices - 1) / kRecheckSlices;
+  if (lds <= kRecheckLds)
+    hipLaunchKernelGGL((exact_recheck_unit<T, true>), dim3(grid), dim3(256),
+                       lds, s, (const T*)j.X, j.d, vec, o.C64, o.CT, o.k, tpf,
+                       j.flags, j.ucnt, g.grid, g.cap, j.labels, j.u, j.row, j.conv,
+                       j.iter, j.dirty);
+  else
+    hipLaunchKernelGGL((exact_recheck_unit<T, false>), dim3(grid), dim3(256),
+                       0, s, (const T*)j.X, j.d, vec, o.C64, o.CT, o.k, tpf,
+                       j.flags, j.ucnt, g.grid, g.cap, j.labels, j.u, j.row, j.conv,
+                       j.iter, j.dirty);
+}
+
 hipError_t launch_recheck(const CentroidOps& o, const AssignJob& j,
                           hipStream_t s) {
   const TileGeom g = tile_f32_geometry(o.dp, o.kpad, j.n, j.seg_cnt != nullptr,
@@ -223,18 +333,8 @@ hipError_t launch_recheck(const CentroidOps& o, const AssignJob& j,
   int tpf = 1;
   while (tpf < o.k && tpf < 256) tpf *= 2;
   switch (j.dt) {
-    case KNOR_F32:
-      hipLaunchKernelGGL(exact_recheck_unit<float>, dim3(g.grid), dim3(256), 0, s,
-                         (const float*)j.X, j.d, o.CT, o.k, tpf, j.flags, j.ucnt,
-                         g.cap, j.labels, j.u, j.row, j.conv, j.iter,
-                         j.dirty);
-      break;
-    case KNOR_BF16:
-      hipLaunchKernelGGL(exact_recheck_unit<uint16_t>, dim3(g.grid), dim3(256), 0,
-                         s, (const uint16_t*)j.X, j.d, o.CT, o.k, tpf, j.flags,
-                         j.ucnt, g.cap, j.labels, j.u, j.row, j.conv,
-                         j.iter, j.dirty);
-      break;
+    case KNOR_F32: launch_recheck_t<float>(o, j, g, tpf, s); break;
+    case KNOR_BF16: launch_recheck_t<uint16_t>(o, j, g, tpf, s); break;
     default:
       return hipSuccess;   // FP64 data never uses the recheck list
   }

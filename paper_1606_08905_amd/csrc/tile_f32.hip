@@ -40,7 +40,10 @@ typedef float f4 __attribute__((ext_vector_type(4)));
 
 constexpr int kTileThreads = 256;
 constexpr size_t kResidentLds = 65536;
-constexpr int kResidentGrid = 1024;
+#ifndef KNOR_RESIDENT_GRID
+#define KNOR_RESIDENT_GRID 1024
+#endif
+constexpr int kResidentGrid = KNOR_RESIDENT_GRID;
 constexpr int kChunkedGrid = kTileMaxGrid;
 static_assert(kResidentGrid <= kTileMaxGrid, "grid bound");
 
@@ -120,14 +123,18 @@ struct WaveState {
   double xs[T::PB];
   float b1[T::PB], b2[T::PB];
   int i1[T::PB];
+  int32_t old[T::PB];     // previous label (loaded with the point)
 };
 
 // Load the wave's points q0 + pb*16 + col (pb < PB) of a range of length m;
-// with a list, point = list[base + q].
+// with a list, point = list[base + q].  The lane group that will finalise a
+// point block also fetches the points' previous labels here, so that the
+// read overlaps the matrix work.
 template <class T>
 __device__ __forceinline__ void load_points(WaveState<T>& w,
                                             const float* __restrict__ X, int d,
                                             int vec, const int* __restrict__ list,
+                                            const int32_t* __restrict__ labels,
                                             int64_t base, int64_t q0, int64_t m,
                                             int col, int grp) {
   constexpr int KS = T::KS, PB = T::PB;
@@ -137,6 +144,7 @@ __device__ __forceinline__ void load_points(WaveState<T>& w,
     w.valid[pb] = q < m;
     const int64_t p = w.valid[pb] ? (list ? (int64_t)list[base + q] : q) : 0;
     w.pid[pb] = p;
+    w.old[pb] = (w.valid[pb] && (pb & 3) == grp) ? labels[p] : 0;
     const float* xr = X + (size_t)p * d + grp * KS;
     if (w.valid[pb] && vec) {
       load_slice<KS>(w.bx[pb], xr);
@@ -283,7 +291,7 @@ __device__ __forceinline__ void finalize_points(
     flag[pb] = recheck_all || !(gap > thr);
     if (!flag[pb]) {
       const int64_t p = w.pid[pb];
-      const int32_t old = labels[p];
+      const int32_t old = w.old[pb];
       labels[p] = w.i1[pb];
       if (old != w.i1[pb]) {
         changed = true;
@@ -374,7 +382,7 @@ __global__ __launch_bounds__(kTileThreads) void tile_f32_resident_kernel(
        wu += (int64_t)gridDim.x * 4) {
     int64_t q0, m, base;
     if (!unit_range(wu, WUP, n, seg_cnt, nseg, q0, m, base)) continue;
-    load_points<T>(w, X, d, vec, list, base, q0, m, col, grp);
+    load_points<T>(w, X, d, vec, list, labels, base, q0, m, col, grp);
     tile_sweep<T>(w, sC, sN, kpad, 0, col, grp);
     merge_groups<T>(w);
     bool flag[PB], changed;
@@ -419,7 +427,7 @@ __global__ __launch_bounds__(kTileThreads) void tile_f32_chunked_kernel(
     int64_t q0, m, base;
     if (!unit_range(unit, BUP, n, seg_cnt, nseg, q0, m, base))
       continue;                                // uniform over the workgroup
-    load_points<T>(w, X, d, vec, list, base, q0 + wave * WUP, m, col, grp);
+    load_points<T>(w, X, d, vec, list, labels, base, q0 + wave * WUP, m, col, grp);
     float cmax = 0.0f;
     for (int c0 = 0; c0 < kpad; c0 += CK) {
       const int cc = (kpad - c0) < CK ? (kpad - c0) : CK;
