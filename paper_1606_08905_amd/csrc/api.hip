@@ -262,6 +262,24 @@ static std::vector<int64_t> forgy_rows(int64_t n, int k, uint64_t seed) {
   return rows;
 }
 
+// Centroid operands of the tile that serves points of type dt: FP32 -2c for
+// FP32 points, the BF16 hi/lo terms of -2c for BF16 points (FP64 points use
+// the canonical centroids directly); FP32 norms for both.
+static void add_operands(Arena& ar, CentroidOps& ops, knor_dtype dt) {
+  if (dt == KNOR_F32)
+    ar.add((void**)&ops.Cm2, sizeof(float) * (size_t)ops.kpad * ops.dp);
+  if (dt == KNOR_BF16) {
+    ar.add((void**)&ops.Chi, sizeof(uint16_t) * (size_t)ops.kpad * ops.dpb);
+    ar.add((void**)&ops.Clo, sizeof(uint16_t) * (size_t)ops.kpad * ops.dpb);
+  }
+  ar.add((void**)&ops.cn, sizeof(float) * (size_t)ops.kpad);
+}
+
+static int64_t flag_capacity(const CentroidOps& ops, knor_dtype dt, int64_t n,
+                             int nseg) {
+  return dt == KNOR_F64 ? 1 : tile_flag_capacity(ops, dt, n, nseg);
+}
+
 // ---------------------------------------------------------------------------
 // fit
 // ---------------------------------------------------------------------------
@@ -279,7 +297,7 @@ static knor_status fit_impl(const void* X, knor_dtype dt, int64_t n, int d,
   const int nseg = nseg_of_n(n);
 
   CentroidOps ops{};
-  ops.k = k; ops.kpad = kpad; ops.d = d; ops.dp = dp;
+  ops.k = k; ops.kpad = kpad; ops.d = d; ops.dp = dp; ops.dpb = pad_dim_bf16(d);
   ops.C64 = C_out;                 // the output buffer is the working copy
   UpdatePlan plan{};
   void* upd_ws = nullptr;
@@ -291,13 +309,12 @@ static knor_status fit_impl(const void* X, knor_dtype dt, int64_t n, int d,
   double *dist2 = nullptr, *sumtmp = nullptr, *objective = nullptr;
 
   Arena ar;
-  ar.add((void**)&ops.Cm2, sizeof(float) * (size_t)kpad * dp);
-  ar.add((void**)&ops.cn, sizeof(float) * (size_t)kpad);
+  add_operands(ar, ops, dt);
   ar.add((void**)&ops.CT, sizeof(double) * (size_t)k * d);
   ar.add((void**)&drift, sizeof(float) * (size_t)k);
   ar.add((void**)&s_half, sizeof(float) * (size_t)k);
   ar.add((void**)&dirty, sizeof(int) * (size_t)k);
-  ar.add((void**)&flags, sizeof(int) * (size_t)tile_f32_flag_capacity(dp, kpad, n, nseg));
+  ar.add((void**)&flags, sizeof(int) * (size_t)flag_capacity(ops, dt, n, nseg));
   ar.add((void**)&ucnt, sizeof(int) * (size_t)kTileMaxGrid);
   if (mti) {
     ar.add((void**)&u, sizeof(float) * (size_t)n);
@@ -482,7 +499,6 @@ knor_status knor_fit(const void* X, knor_dtype dt, int64_t n, int32_t d,
   } else if (init != KNOR_INIT_FORGY) {
     return KNOR_ERR_INVALID_ARG;
   }
-  if (dt == KNOR_BF16) return KNOR_ERR_UNSUPPORTED;
   return fit_impl(X, dt, n, d, k, init, C_init, max_iters, tol, o, C_out,
                   labels_out, st);
 }
@@ -495,22 +511,20 @@ knor_status knor_assign(const void* X, knor_dtype dt, int64_t n, int32_t d,
   if (!X || !C || !labels_out || !dtype_ok(dt)) return KNOR_ERR_INVALID_ARG;
   if (n < 0 || n >= (int64_t)1 << 31 || d < 1 || d > kMaxD || k < 1 || k > kMaxK)
     return KNOR_ERR_INVALID_ARG;
-  if (dt == KNOR_BF16) return KNOR_ERR_UNSUPPORTED;
   if (n == 0) return KNOR_OK;
   hipStream_t s = o.stream;
   CentroidOps ops{};
   ops.k = k; ops.kpad = (k + 15) / 16 * 16; ops.d = d; ops.dp = pad_dim(d);
+  ops.dpb = pad_dim_bf16(d);
   ops.C64 = const_cast<double*>(C);
   int* flags = nullptr;
   int* conv = nullptr;
   int* ucnt = nullptr;
   unsigned long long* ctr = nullptr;
   Arena ar;
-  ar.add((void**)&ops.Cm2, sizeof(float) * (size_t)ops.kpad * ops.dp);
-  ar.add((void**)&ops.cn, sizeof(float) * (size_t)ops.kpad);
+  add_operands(ar, ops, dt);
   ar.add((void**)&ops.CT, sizeof(double) * (size_t)k * d);
-  ar.add((void**)&flags, sizeof(int) * (size_t)tile_f32_flag_capacity(
-                              ops.dp, ops.kpad, n, nseg_of_n(n)));
+  ar.add((void**)&flags, sizeof(int) * (size_t)flag_capacity(ops, dt, n, nseg_of_n(n)));
   ar.add((void**)&ucnt, sizeof(int) * (size_t)kTileMaxGrid);
   ar.add((void**)&ctr, sizeof(unsigned long long) * ROW_STRIDE);
   ar.add((void**)&conv, sizeof(int) * 4);

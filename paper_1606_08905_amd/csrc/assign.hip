@@ -15,35 +15,29 @@ namespace knor {
 // centroid operands
 // ---------------------------------------------------------------------------
 
-__device__ __forceinline__ uint16_t bf16_rne(double c) {
-  uint64_t b = (uint64_t)__double_as_longlong(c);
-  double a = fabs(c);
-  uint16_t out = 0;
-  if (a != 0.0) {
-    int e = ilogb(a);
-    if (e < -126) e = -126;
-    double r = rint(ldexp(a, 7 - e));
-    float y = (float)ldexp(r, e - 7);
-    out = (uint16_t)(__float_as_uint(y) >> 16);
-  }
-  return out | (uint16_t)((b >> 48) & 0x8000u);
-}
-
-// One wave per centroid row: Cm2 = -2 * RNE_fp32(c) (exact scaling), zero
-// padded to dp columns; cn = RNE_fp32(|c|^2) with the sum in FP64 index
-// order; CT = transposed FP64 copy.  Rows k..kpad-1 are padding: Cm2 = 0,
+// One wave per centroid row.  Cm2 = -2 * RNE_fp32(c) (exact scaling), zero
+// padded to dp columns; for the BF16 tile Chi = RNE_bf16(-2c) and
+// Clo = RNE_bf16(-2c - Chi) (the difference is exact in FP64), zero padded
+// to dpb columns; cn = RNE_fp32(|c|^2) with the sum in FP64 index order;
+// CT = transposed FP64 copy.  Rows k..kpad-1 are padding: operands 0,
 // cn = +inf (they can never be chosen).
 __global__ __launch_bounds__(256) void prep_centroids_kernel(
-    const double* __restrict__ C64, int k, int kpad, int d, int dp,
+    const double* __restrict__ C64, int k, int kpad, int d, int dp, int dpb,
     float* __restrict__ Cm2, float* __restrict__ cn, double* __restrict__ CT,
-    uint16_t* __restrict__ Cbf) {
+    uint16_t* __restrict__ Chi, uint16_t* __restrict__ Clo) {
   int j = blockIdx.x * 4 + (threadIdx.x >> 6);
   int lane = threadIdx.x & 63;
   if (j >= kpad) return;
-  for (int i = lane; i < dp; i += 64) {
+  const int wmax = dp > dpb ? dp : dpb;
+  for (int i = lane; i < wmax; i += 64) {
     double c = (j < k && i < d) ? C64[(size_t)j * d + i] : 0.0;
-    Cm2[(size_t)j * dp + i] = -2.0f * (float)c;
-    if (Cbf) Cbf[(size_t)j * dp + i] = bf16_rne(c);
+    if (Cm2 && i < dp) Cm2[(size_t)j * dp + i] = -2.0f * (float)c;
+    if (Chi && i < dpb) {
+      uint16_t h, l;
+      bf16_split_m2(c, h, l);
+      Chi[(size_t)j * dpb + i] = h;
+      Clo[(size_t)j * dpb + i] = l;
+    }
     if (j < k && i < d && CT) CT[(size_t)i * k + j] = c;
   }
   if (lane == 0) {
@@ -60,7 +54,8 @@ __global__ __launch_bounds__(256) void prep_centroids_kernel(
 hipError_t launch_prep_centroids(const CentroidOps& o, hipStream_t s) {
   int blocks = (o.kpad + 3) / 4;
   hipLaunchKernelGGL(prep_centroids_kernel, dim3(blocks), dim3(256), 0, s,
-                     o.C64, o.k, o.kpad, o.d, o.dp, o.Cm2, o.cn, o.CT, o.Cbf);
+                     o.C64, o.k, o.kpad, o.d, o.dp, o.dpb, o.Cm2, o.cn, o.CT,
+                     o.Chi, o.Clo);
   return hipGetLastError();
 }
 
@@ -302,6 +297,7 @@ hipError_t launch_assign(const CentroidOps& o, const AssignJob& j,
     return hipGetLastError();
   }
   if (j.dt == KNOR_F32) return launch_tile_f32(o, j, s);
+  if (j.dt == KNOR_BF16) return launch_tile_bf16(o, j, s);
   return hipErrorNotSupported;
 }
 
@@ -328,8 +324,7 @@ static void launch_recheck_t(const CentroidOps& o, const AssignJob& j,
 
 hipError_t launch_recheck(const CentroidOps& o, const AssignJob& j,
                           hipStream_t s) {
-  const TileGeom g = tile_f32_geometry(o.dp, o.kpad, j.n, j.seg_cnt != nullptr,
-                                       j.nseg);
+  const TileGeom g = tile_geometry(o, j.dt, j.n, j.seg_cnt != nullptr, j.nseg);
   int tpf = 1;
   while (tpf < o.k && tpf < 256) tpf *= 2;
   switch (j.dt) {

@@ -163,6 +163,34 @@ __device__ __forceinline__ void block_add_slots(unsigned long long* row,
     }
 }
 
+// BF16 round-to-nearest-even of an FP64 value in one rounding (no detour
+// through FP32): scale to an 8-bit integer significand at the value's binade
+// (binade -126 below the normal range), rint, scale back; the result has at
+// most 8 significant bits, so its FP32 image is exact and its upper half is
+// the BF16 pattern.
+__device__ __forceinline__ uint16_t bf16_rne(double c) {
+  const uint64_t b = (uint64_t)__double_as_longlong(c);
+  const double a = fabs(c);
+  uint16_t out = 0;
+  if (a != 0.0) {
+    int e = ilogb(a);
+    if (e < -126) e = -126;
+    const double r = rint(ldexp(a, 7 - e));
+    const float y = (float)ldexp(r, e - 7);
+    out = (uint16_t)(__float_as_uint(y) >> 16);
+  }
+  return out | (uint16_t)((b >> 48) & 0x8000u);
+}
+
+// The two BF16 terms of -2c used by the BF16 tile: hi = bf16(-2c),
+// lo = bf16(-2c - hi) (the difference is exact in FP64).
+__device__ __forceinline__ void bf16_split_m2(double c, uint16_t& hi, uint16_t& lo) {
+  const double m2 = -2.0 * c;
+  hi = bf16_rne(m2);
+  const double hv = (double)__uint_as_float(((uint32_t)hi) << 16);
+  lo = bf16_rne(m2 - hv);
+}
+
 // Record a label change: both clusters lose/gain a member.
 __device__ __forceinline__ void mark_dirty(int* dirty, int old_lab, int new_lab) {
   if (!dirty) return;
@@ -183,8 +211,9 @@ struct CentroidOps {
   double* CT;      // d x k transposed copy (coalesced per-centroid lanes)
   float* Cm2;      // kpad x dp: -2 * fp32(c), zero-padded; pad rows zero
   float* cn;       // kpad: fp32(|c|^2) (pad rows +inf)
-  uint16_t* Cbf;   // kpad x dp BF16 rounding of c (BF16 path only) or null
-  int k, kpad, d, dp;
+  uint16_t* Chi;   // kpad x dpb BF16 bf16(-2c), zero-padded (BF16 path) or null
+  uint16_t* Clo;   // kpad x dpb BF16 bf16(-2c - Chi) (BF16 path) or null
+  int k, kpad, d, dp, dpb;
 };
 
 // The point set one assignment pass covers.
@@ -224,10 +253,18 @@ struct TileGeom {
 };
 bool tile_f32_resident(int dp, int kpad);
 TileGeom tile_f32_geometry(int dp, int kpad, int64_t n, bool segmented, int nseg);
+bool tile_bf16_resident(int dpb, int kpad);
+TileGeom tile_bf16_geometry(int dpb, int kpad, int64_t n, bool segmented, int nseg);
+// the geometry of the tile that serves points of type dt
+TileGeom tile_geometry(const CentroidOps& o, knor_dtype dt, int64_t n,
+                       bool segmented, int nseg);
 // entries the flags array needs for either kind of pass
-int64_t tile_f32_flag_capacity(int dp, int kpad, int64_t n, int nseg);
+int64_t tile_flag_capacity(const CentroidOps& o, knor_dtype dt, int64_t n,
+                           int nseg);
 hipError_t launch_tile_f32(const CentroidOps& o, const AssignJob& j,
                            hipStream_t s);
+hipError_t launch_tile_bf16(const CentroidOps& o, const AssignJob& j,
+                            hipStream_t s);
 
 hipError_t launch_prep_centroids(const CentroidOps& ops, hipStream_t s);
 hipError_t launch_assign(const CentroidOps& ops, const AssignJob& job,
@@ -318,6 +355,12 @@ hipError_t launch_gather_rows(const void* X, knor_dtype dt, int d,
                               const int64_t* rows, int k, double* C64,
                               hipStream_t s);
 
+// padded row length of the BF16 tile: a power of two, at least one K-step
+inline int pad_dim_bf16(int d) {
+  int p = 32;
+  while (p < d) p *= 2;
+  return p;
+}
 inline int pad_dim(int d) {
   int p = 8;
   while (p < d) p *= 2;

@@ -32,13 +32,10 @@
 //            waves of a workgroup, which finalise 64*PB-point units.
 #include <math.h>
 
-#include "common.h"
+#include "tile_common.h"
 
 namespace knor {
 
-typedef float f4 __attribute__((ext_vector_type(4)));
-
-constexpr int kTileThreads = 256;
 constexpr size_t kResidentLds = 65536;
 #ifndef KNOR_RESIDENT_GRID
 #define KNOR_RESIDENT_GRID 1024
@@ -53,12 +50,23 @@ constexpr int chk_pb(int dp) { return dp >= 256 ? 1 : (dp >= 128 ? 2 : 4); }
 
 template <int DP, int PB_>
 struct F32Tile {
+  using Frag = float;
   static constexpr int KS = DP / 4;                    // dims per lane group
   static constexpr int PB = PB_;
   static constexpr int LDA = DP + 4;                   // LDS row stride
   static constexpr int CK = (4096 / DP) < 16 ? 16 : (4096 / DP);
   static constexpr int WUP = 16 * PB;                  // points per wave unit
   static constexpr int BUP = 4 * WUP;                  // points per block unit
+  // u = 2^-24.  Rounding c to FP32 (2u|x||c| after the -2 scaling), |c|^2
+  // to FP32 (u R^2), each of the d products and d+1 accumulation steps at
+  // 2u of the running magnitude; plus 2^-100 (1 + R) for subnormals flushed
+  // by the matrix core.
+  __device__ static double bound(double xn2, double R2, int d) {
+    const double u24 = 5.9604644775390625e-08;
+    const double xr = sqrt(xn2 * R2);
+    return (u24 * ((2.0 * d + 5.0) * R2 + (4.0 * d + 10.0) * xr) +
+            7.888609052210118e-31 * (1.0 + sqrt(R2))) * (1.0 + 9.765625e-04);
+  }
 };
 
 bool tile_f32_resident(int dp, int kpad) {
@@ -84,16 +92,18 @@ TileGeom tile_f32_geometry(int dp, int kpad, int64_t n, bool seg, int nseg) {
   return g;
 }
 
-int64_t tile_f32_flag_capacity(int dp, int kpad, int64_t n, int nseg) {
-  const TileGeom a = tile_f32_geometry(dp, kpad, n, false, nseg);
-  const TileGeom b = tile_f32_geometry(dp, kpad, n, true, nseg);
-  const int64_t ca = (int64_t)a.grid * a.cap, cb = (int64_t)b.grid * b.cap;
-  return ca > cb ? ca : cb;
+TileGeom tile_geometry(const CentroidOps& o, knor_dtype dt, int64_t n,
+                       bool seg, int nseg) {
+  if (dt == KNOR_BF16) return tile_bf16_geometry(o.dpb, o.kpad, n, seg, nseg);
+  return tile_f32_geometry(o.dp, o.kpad, n, seg, nseg);
 }
 
-// min / max without NaN canonicalisation (inputs are finite or +inf)
-__device__ __forceinline__ float fmax_nc(float a, float b) {
-  return __builtin_amdgcn_fmed3f(a, b, INFINITY);
+int64_t tile_flag_capacity(const CentroidOps& o, knor_dtype dt, int64_t n,
+                           int nseg) {
+  const TileGeom a = tile_geometry(o, dt, n, false, nseg);
+  const TileGeom b = tile_geometry(o, dt, n, true, nseg);
+  const int64_t ca = (int64_t)a.grid * a.cap, cb = (int64_t)b.grid * b.cap;
+  return ca > cb ? ca : cb;
 }
 
 template <int KS>
@@ -113,18 +123,6 @@ __device__ __forceinline__ void load_slice(float (&dst)[KS], const float* src) {
     }
   }
 }
-
-// Per-wave state for PB blocks of 16 points.
-template <class T>
-struct WaveState {
-  float bx[T::PB][T::KS];
-  int64_t pid[T::PB];
-  bool valid[T::PB];
-  double xs[T::PB];
-  float b1[T::PB], b2[T::PB];
-  int i1[T::PB];
-  int32_t old[T::PB];     // previous label (loaded with the point)
-};
 
 // Load the wave's points q0 + pb*16 + col (pb < PB) of a range of length m;
 // with a list, point = list[base + q].  The lane group that will finalise a
@@ -226,123 +224,6 @@ __device__ __forceinline__ void tile_sweep(WaveState<T>& w, const float* sC,
     tile_block<T>(w, cur, c0 + cb + 4 * grp);
     cur = nxt;
   }
-}
-
-// Largest fp32(|c|^2) over the real centroids of a staged chunk.
-__device__ __forceinline__ float chunk_cmax(const float* sN, int cc, int c0,
-                                            int k, int lane) {
-  float mx = 0.0f;
-  for (int e = lane; e < cc; e += 64)
-    if (c0 + e < k) mx = fmax_nc(mx, sN[e]);
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) mx = fmax_nc(mx, __shfl_xor(mx, off));
-  return mx;
-}
-
-// Combine the four lane groups (each saw a different quarter of centroids).
-template <class T>
-__device__ __forceinline__ void merge_groups(WaveState<T>& w) {
-  constexpr int PB = T::PB;
-#pragma unroll
-  for (int off = 16; off <= 32; off <<= 1) {
-#pragma unroll
-    for (int pb = 0; pb < PB; ++pb) {
-      const float ob1 = __shfl_xor(w.b1[pb], off);
-      const float ob2 = __shfl_xor(w.b2[pb], off);
-      const int oi1 = __shfl_xor(w.i1[pb], off);
-      w.xs[pb] += __shfl_xor(w.xs[pb], off);
-      // second best of the union: min(max(b1, ob1), min(b2, ob2))
-      const float hi = w.b1[pb] < ob1 ? ob1 : w.b1[pb];
-      const float lo2 = w.b2[pb] < ob2 ? w.b2[pb] : ob2;
-      const float nb2 = hi < lo2 ? hi : lo2;
-      const bool take = ob1 < w.b1[pb] || (ob1 == w.b1[pb] && oi1 < w.i1[pb]);
-      w.i1[pb] = take ? oi1 : w.i1[pb];
-      w.b1[pb] = take ? ob1 : w.b1[pb];
-      w.b2[pb] = nb2;
-    }
-  }
-}
-
-// Decide each point (lane group g finalises point block pb with pb % 4 == g).
-// Writes labels / bounds of decided points; returns per-block flags.
-template <class T>
-__device__ __forceinline__ void finalize_points(
-    WaveState<T>& w, float cmax, int d, int grp, int recheck_all,
-    int32_t* __restrict__ labels, float* __restrict__ ub, int* __restrict__ dirty,
-    bool (&flag)[T::PB], bool& changed) {
-  constexpr int PB = T::PB;
-  static_assert(PB <= 4, "one finalised point per lane");
-  const double R2 = (double)cmax * (1.0 + 2.384185791015625e-07);  // 1+2^-22
-  const double u24 = 5.9604644775390625e-08;                        // 2^-24
-  const double e64 = (double)(d + 2) * 1.1102230246251565e-16;     // (d+2)2^-53
-  changed = false;
-#pragma unroll
-  for (int pb = 0; pb < PB; ++pb) {
-    flag[pb] = false;
-    if (!(w.valid[pb] && (pb & 3) == grp)) continue;
-    const double xn2 = w.xs[pb] * (1.0 + (double)(d + 4) * 2.220446049250313e-16);
-    const double E = u24 * ((2.0 * d + 5.0) * R2 + (4.0 * d + 10.0) * sqrt(xn2 * R2)) *
-                     (1.0 + 9.765625e-04);
-    const double y1 = (double)w.b1[pb], y2 = (double)w.b2[pb];
-    double dbest = xn2 + y1 + E;
-    if (!(dbest > 0.0)) dbest = 0.0;
-    const double thr = 2.0 * E + 2.01 * e64 * dbest;
-    const double gap = y2 - y1;
-    flag[pb] = recheck_all || !(gap > thr);
-    if (!flag[pb]) {
-      const int64_t p = w.pid[pb];
-      const int32_t old = w.old[pb];
-      labels[p] = w.i1[pb];
-      if (old != w.i1[pb]) {
-        changed = true;
-        mark_dirty(dirty, old, w.i1[pb]);
-      }
-      if (ub) ub[p] = f32_up(sqrt(dbest) * (1.0 + 8.881784197001252e-16));
-    }
-  }
-}
-
-// Unit -> (range of points) of a dense or segmented pass.  Segmented units
-// are ordered tile-major (all segments' first tiles, then second tiles, ...)
-// so that occupied units spread over the grid.
-__device__ __forceinline__ bool unit_range(int64_t unit, int up, int64_t n,
-                                           const int* __restrict__ seg_cnt,
-                                           int nseg, int64_t& q0, int64_t& m,
-                                           int64_t& base) {
-  if (seg_cnt) {
-    const int64_t t = unit / nseg;
-    const int s = (int)(unit - t * nseg);
-    m = seg_cnt[s];
-    q0 = t * up;
-    base = (int64_t)s * kSeg;
-    return q0 < m;
-  }
-  m = n;
-  q0 = unit * up;
-  base = 0;
-  return true;
-}
-
-// Append this wave's flagged points to the workgroup's slice.
-template <class T>
-__device__ __forceinline__ int append_flags(const WaveState<T>& w,
-                                            const bool (&flag)[T::PB],
-                                            int* sFlag, int* __restrict__ slice,
-                                            int lane) {
-  int total = 0;
-#pragma unroll
-  for (int pb = 0; pb < T::PB; ++pb) total += __popcll(__ballot(flag[pb]));
-  if (total == 0) return 0;
-  int base = 0;
-  if (lane == 0) base = atomicAdd(sFlag, total);           // LDS
-  base = __shfl(base, 0);
-#pragma unroll
-  for (int pb = 0; pb < T::PB; ++pb) {
-    const uint64_t fm = __ballot(flag[pb]);
-    if (flag[pb]) slice[base + __popcll(fm & lanemask_lt())] = (int)w.pid[pb];
-    base += __popcll(fm);
-  }
-  return total;
 }
 
 template <int DP>

@@ -495,6 +495,7 @@ __global__ __launch_bounds__(256) void tree_finalize(
     const int* __restrict__ leaf_off, int k, int d, const double* C_prev,
     double* C_out, int64_t* __restrict__ counts_out, float* __restrict__ Cm2,
     float* __restrict__ cn, double* __restrict__ CT, int dp,
+    uint16_t* __restrict__ Chi, uint16_t* __restrict__ Clo, int dpb,
     float* __restrict__ drift, int* __restrict__ dirty, IterCtl ctl,
     const int* __restrict__ conv, int iter) {
   __shared__ double red[256];
@@ -585,6 +586,13 @@ __global__ __launch_bounds__(256) void tree_finalize(
   if (Cm2)
     for (int dim = threadIdx.x; dim < dp; dim += blockDim.x)
       Cm2[(size_t)j * dp + dim] = dim < d ? -2.0f * (float)cval[dim] : 0.0f;
+  if (Chi)
+    for (int dim = threadIdx.x; dim < dpb; dim += blockDim.x) {
+      uint16_t h, l;
+      bf16_split_m2(dim < d ? cval[dim] : 0.0, h, l);
+      Chi[(size_t)j * dpb + dim] = h;
+      Clo[(size_t)j * dpb + dim] = l;
+    }
 }
 
 hipError_t launch_update(const UpdatePlan& p, const void* X, knor_dtype dt,
@@ -642,7 +650,9 @@ hipError_t launch_update(const UpdatePlan& p, const void* X, knor_dtype dt,
   hipLaunchKernelGGL(tree_finalize, dim3(k), dim3(256), 0, s, p.leafsum, p.nj,
                      p.leaf_off, k, d, C_prev, C_out, counts_out,
                      ops ? ops->Cm2 : nullptr, ops ? ops->cn : nullptr,
-                     ops ? ops->CT : nullptr, ops ? ops->dp : 0, drift, dirty,
+                     ops ? ops->CT : nullptr, ops ? ops->dp : 0,
+                     ops ? ops->Chi : nullptr, ops ? ops->Clo : nullptr,
+                     ops ? ops->dpb : 0, drift, dirty,
                      *ctl, conv, iter);
   if (prof) prof->end();
   return hipGetLastError();

@@ -56,7 +56,7 @@ ASSIGN_CASES = [
 
 
 @pytest.mark.parametrize("n,d,k", ASSIGN_CASES)
-@pytest.mark.parametrize("dtype", ["f32", "f64"])
+@pytest.mark.parametrize("dtype", ["f32", "f64", "bf16"])
 def test_assign_parity(n, d, k, dtype):
     knor = _knor()
     _print_case(test="assign", n=n, d=d, k=k, dtype=dtype)
@@ -68,25 +68,48 @@ def test_assign_parity(n, d, k, dtype):
 
 
 @pytest.mark.parametrize("recheck", [1, 2])
-def test_assign_ties_and_duplicates(recheck):
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+def test_assign_ties_and_duplicates(recheck, dtype):
     """Integer data: many exact ties; the lowest index must win."""
     knor = _knor()
     rng = np.random.default_rng(5)
-    X = rng.integers(-3, 4, size=(5000, 8)).astype(np.float32)
+    X = workloads.cast(rng.integers(-3, 4, size=(5000, 8)).astype(np.float64), dtype)
     C = rng.integers(-3, 4, size=(40, 8)).astype(np.float64)
     C[20:] = C[:20]                       # duplicated centroids: exact ties
-    lab_o, _ = oracle.assign(X.astype(np.float64), C)
-    lab = knor.assign(_dev(X, "f32"), _dev(C, "f64"), recheck=recheck)
+    lab_o, _ = oracle.assign(workloads.to_f64(X, dtype), C)
+    lab = knor.assign(_dev(X, dtype), _dev(C, "f64"), recheck=recheck)
     assert (lab.cpu().numpy() == lab_o).all()
 
 
 @pytest.mark.parametrize("scale,shift", [(1e-3, 0.0), (1.0, 1e4), (1e3, 0.0), (1.0, -3e5)])
-def test_assign_far_from_origin(scale, shift):
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+def test_assign_far_from_origin(scale, shift, dtype):
     """Large |x| relative to the cluster spread stresses the error bound."""
     knor = _knor()
-    X, C = _data(6000, 32, 50, "f32", seed=3, scale=scale, shift=shift)
-    lab_o, _ = oracle.assign(X.astype(np.float64), C)
-    lab = knor.assign(_dev(X, "f32"), _dev(C, "f64"))
+    X, C = _data(6000, 32, 50, dtype, seed=3, scale=scale, shift=shift)
+    lab_o, _ = oracle.assign(workloads.to_f64(X, dtype), C)
+    lab = knor.assign(_dev(X, dtype), _dev(C, "f64"))
+    assert (lab.cpu().numpy() == lab_o).all()
+
+
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+@pytest.mark.parametrize("d", [16, 64])
+def test_assign_near_bisectors(dtype, d):
+    """Points placed on and near the bisecting hyperplanes of centroid pairs
+    (then rounded to the storage type): the squared-distance gaps fall
+    around the tile's decision threshold, so a bound that is too small shows
+    up as a label that differs from the oracle."""
+    knor = _knor()
+    rng = np.random.default_rng(40 + d)
+    k = 48
+    C = rng.normal(size=(k, d)) * 4.0
+    a = rng.integers(0, k, size=20000)
+    b = (a + 1 + rng.integers(0, k - 1, size=20000)) % k
+    mid = 0.5 * (C[a] + C[b])
+    step = (C[b] - C[a]) * rng.uniform(-1e-3, 1e-3, size=(20000, 1))
+    X = workloads.cast(mid + step, dtype)
+    lab_o, _ = oracle.assign(workloads.to_f64(X, dtype), C)
+    lab = knor.assign(_dev(X, dtype), _dev(C, "f64"))
     assert (lab.cpu().numpy() == lab_o).all()
 
 
@@ -97,7 +120,7 @@ def test_assign_far_from_origin(scale, shift):
 @pytest.mark.parametrize("n,d,k", [(1, 4, 1), (100, 3, 5), (5000, 16, 10),
                                    (70000, 32, 100), (20000, 64, 1000),
                                    (9000, 33, 4096), (3000, 256, 7)])
-@pytest.mark.parametrize("dtype", ["f32", "f64"])
+@pytest.mark.parametrize("dtype", ["f32", "f64", "bf16"])
 def test_update_parity(n, d, k, dtype):
     knor = _knor()
     _print_case(test="update", n=n, d=d, k=k, dtype=dtype)
@@ -155,6 +178,26 @@ def test_fit_config2_small(prune, seed):
     if prune:
         # most points are decided by the bounds after the first iterations
         assert st["pruned_a"] + st["pruned_b"] > 0.3 * 40000 * (st["iters"] - 1)
+
+
+@pytest.mark.parametrize("prune", [False, True])
+def test_fit_config3_small(prune):
+    """The mixed-precision workload (BF16 points, d=64, k=256, 5% uniform
+    outliers) at a reduced n."""
+    w = workloads.config(3, n=30000)
+    _print_case(test="fit-config3-small", prune=prune)
+    st, ref = _fit_compare(w.X, w.dtype, w.C0, w.k, w.max_iters, prune,
+                           oracle_fit=oracle.mti_fit)
+    print("config3-small rechecked", st["rechecked"], "of", 30000 * st["iters"],
+          flush=True)
+
+
+def test_fit_bf16_shapes():
+    for (n, d, k, seed) in [(5000, 3, 7, 1), (8000, 33, 40, 2), (3000, 128, 20, 3),
+                            (2000, 256, 9, 4), (6000, 16, 600, 5)]:
+        X, C0 = _data(n, d, k, "bf16", seed=seed)
+        _print_case(test="fit-bf16", n=n, d=d, k=k)
+        _fit_compare(X, "bf16", C0, k, 12, True, oracle_fit=oracle.mti_fit)
 
 
 def test_fit_recheck_all_equals_oracle():
