@@ -293,6 +293,15 @@ struct Prof {
 };
 
 // Two-pass segmented update.
+// first tree stage: blocks of TB leaves (a power of two), TB x d doubles
+// within kTreeBlockDoubles of LDS
+constexpr int kTreeBlockDoubles = 4096;
+inline int tree_block_leaves(int d) {
+  int tb = 64;
+  while (tb > 1 && tb * d > kTreeBlockDoubles) tb >>= 1;
+  return tb;
+}
+
 struct UpdatePlan {
   int64_t n;
   int k, d;
@@ -306,9 +315,11 @@ struct UpdatePlan {
   int* nj;            // k: members per cluster
   int* off;           // k+1: first member slot of each cluster
   int* leaf_off;      // k+1: first leaf of each cluster
+  int* rpre;          // nb x k: exclusive prefix over ranges (fused sort)
   int* perm;          // n: point indices sorted by (label, index)
   double* leafsum;    // (n/64 + k) x d
   int64_t max_leaves;
+  int tb;             // leaves per block of the first tree stage
 };
 size_t update_workspace_bytes(int64_t n, int k, int d);
 void update_plan_init(UpdatePlan* p, int64_t n, int k, int d, void* ws);

@@ -30,6 +30,7 @@ namespace knor {
 
 constexpr int kFusedMaxK = 768;            // 16 x k running tables within 48 KB
 constexpr int kFusedWaves = 16;
+constexpr int kFusedMaxRanges = 1024;
 
 // ---------------------------------------------------------------------------
 // plan / workspace
@@ -39,11 +40,12 @@ static bool fused_sort(int k) { return k <= kFusedMaxK; }
 
 static int choose_block(int64_t n, int k) {
   if (fused_sort(k)) {
-    // sub-range per wave (a multiple of 64 points); a workgroup covers
-    // kFusedWaves sub-ranges; at most 64 workgroups, so that each one's
-    // prefix over the earlier ranges stays short
-    int64_t ranges = 65536 / k;
-    if (ranges > 64) ranges = 64;
+    // sub-range per wave (a multiple of 64 points, about 512); a workgroup
+    // covers kFusedWaves sub-ranges; up to kFusedMaxRanges workgroups, whose
+    // prefixes over earlier ranges come from a separate column scan
+    int64_t ranges = (n + kFusedWaves * 512 - 1) / (kFusedWaves * 512);
+    if (ranges > kFusedMaxRanges) ranges = kFusedMaxRanges;
+    if (ranges < 1) ranges = 1;
     int64_t sb = (n + kFusedWaves * ranges - 1) / (kFusedWaves * ranges);
     sb = (sb + 63) / 64 * 64;
     if (sb < 64) sb = 64;
@@ -94,6 +96,7 @@ size_t update_workspace_bytes(int64_t n, int k, int d) {
   b += align256(sizeof(int) * (size_t)k);                    // nj
   b += align256(sizeof(int) * (size_t)(k + 1));              // off
   b += align256(sizeof(int) * (size_t)(k + 1));              // leaf_off
+  b += align256(sizeof(int) * (size_t)(fused_sort(k) ? nb : 1) * k);  // rpre
   b += align256(sizeof(int) * (size_t)n);                    // perm
   b += align256(sizeof(double) * (size_t)maxleaves * d);     // leafsum
   return b;
@@ -105,6 +108,7 @@ void update_plan_init(UpdatePlan* p, int64_t n, int k, int d, void* ws) {
   p->d = d;
   plan_dims(n, k, &p->B, &p->nb, &p->seglen, &p->nsegc);
   p->max_leaves = n / kLeaf + k + 1;
+  p->tb = tree_block_leaves(d);
   const size_t cnt_entries = fused_sort(k) ? (size_t)p->nb * (kFusedWaves + 1) * k
                                            : (size_t)p->nb * k;
   char* c = (char*)ws;
@@ -114,6 +118,7 @@ void update_plan_init(UpdatePlan* p, int64_t n, int k, int d, void* ws) {
   p->nj = (int*)c; c += align256(sizeof(int) * (size_t)k);
   p->off = (int*)c; c += align256(sizeof(int) * (size_t)(k + 1));
   p->leaf_off = (int*)c; c += align256(sizeof(int) * (size_t)(k + 1));
+  p->rpre = (int*)c; c += align256(sizeof(int) * (size_t)(fused_sort(k) ? p->nb : 1) * k);
   p->perm = (int*)c; c += align256(sizeof(int) * (size_t)n);
   p->leafsum = (double*)c;
 }
@@ -212,25 +217,62 @@ __global__ __launch_bounds__(1024) void hist_fused(const int32_t* __restrict__ l
   }
 }
 
+// Per cluster j (one workgroup each): exclusive prefix over the ranges of
+// the range totals, rpre[r * k + j], and the cluster total nj[j].
+__global__ __launch_bounds__(256) void range_scan(const int* __restrict__ cnt,
+                                                  int nr, int k,
+                                                  int* __restrict__ rpre,
+                                                  int* __restrict__ nj,
+                                                  const int* __restrict__ conv,
+                                                  int iter) {
+  __shared__ int part[256];
+  SKIP_IF_CONVERGED
+  const int j = blockIdx.x;
+  const int per = (nr + 255) / 256;
+  const int r0 = threadIdx.x * per;
+  int v[4];
+  int local = 0;
+  for (int q = 0; q < per; q += 4) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int r = r0 + q + u;
+      v[u] = (q + u < per && r < nr)
+                 ? cnt[((size_t)r * (kFusedWaves + 1) + kFusedWaves) * k + j] : 0;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) local += v[u];
+  }
+  part[threadIdx.x] = local;
+  __syncthreads();
+  for (int s = 1; s < 256; s <<= 1) {
+    const int t = threadIdx.x >= s ? part[threadIdx.x - s] : 0;
+    __syncthreads();
+    part[threadIdx.x] += t;
+    __syncthreads();
+  }
+  int run = part[threadIdx.x] - local;
+  for (int q = 0; q < per; ++q) {
+    const int r = r0 + q;
+    if (r >= nr) break;
+    rpre[(size_t)r * k + j] = run;
+    run += cnt[((size_t)r * (kFusedWaves + 1) + kFusedWaves) * k + j];
+  }
+  if (threadIdx.x == 255) nj[j] = part[255];
+}
+
 __global__ __launch_bounds__(1024) void scatter_fused(
-    const int32_t* __restrict__ labels, int64_t n, int k, int SB, int nr,
-    int bits, const int* __restrict__ cnt, const int* __restrict__ dirty,
-    int* __restrict__ perm, int* __restrict__ nj_out, int* __restrict__ off_out,
+    const int32_t* __restrict__ labels, int64_t n, int k, int SB,
+    int bits, const int* __restrict__ cnt, const int* __restrict__ rpre,
+    const int* __restrict__ nj_in, const int* __restrict__ dirty,
+    int* __restrict__ perm, int* __restrict__ off_out,
     int* __restrict__ leaf_off_out, const int* __restrict__ conv, int iter) {
   extern __shared__ int run[];               // kFusedWaves x k
   __shared__ int sa[1024], sb[1024];
   SKIP_IF_CONVERGED
   const int r = blockIdx.x, wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int j = threadIdx.x;                 // k <= 1024: one cluster per thread
-  int tot = 0, pre = 0;
-  if (j < k) {
-#pragma unroll 16
-    for (int rr = 0; rr < nr; ++rr) {
-      const int v = cnt[((size_t)rr * (kFusedWaves + 1) + kFusedWaves) * k + j];
-      tot += v;
-      pre += rr < r ? v : 0;
-    }
-  }
+  const int tot = j < k ? nj_in[j] : 0;
+  const int pre = j < k ? rpre[(size_t)r * k + j] : 0;
   // exclusive prefix over clusters of the totals (members and leaves)
   const int lv = (tot + kLeaf - 1) / kLeaf;
   sa[threadIdx.x] = tot;
@@ -247,7 +289,6 @@ __global__ __launch_bounds__(1024) void scatter_fused(
   const int off = sa[threadIdx.x] - tot;
   if (r == 0) {
     if (j < k) {
-      nj_out[j] = tot;
       off_out[j] = off;
       leaf_off_out[j] = sb[threadIdx.x] - lv;
     }
@@ -487,6 +528,42 @@ __global__ __launch_bounds__(64 * kLeafWaves) void leaf_kernel(
 
 constexpr int kTreeLdsDoubles = 6144;   // 48 KB: trees that fit run in LDS
 
+// First stage of the pairwise tree.  In the bottom-up form (at stride s,
+// node a with a % 2s == 0 absorbs node a + s when a + s < m) every level
+// with 2s <= TB pairs leaves inside one aligned block of TB leaves, so the
+// blocks reduce independently: workgroup (j, y) reduces blocks y, y + Y, ...
+// of cluster j in LDS and leaves each block's sum at its first leaf.  The
+// remaining levels run over the block sums in tree_finalize.
+__global__ __launch_bounds__(256) void tree_block(
+    double* __restrict__ leafsum, const int* __restrict__ leaf_off, int k,
+    int d, int TB, const int* __restrict__ dirty, const int* __restrict__ conv,
+    int iter) {
+  __shared__ double node[kTreeBlockDoubles];
+  SKIP_IF_CONVERGED
+  const int j = blockIdx.x;
+  if (dirty && !dirty[j]) return;
+  const int L0 = leaf_off[j], m = leaf_off[j + 1] - L0;
+  const int mb = (m + TB - 1) / TB;
+  for (int b = blockIdx.y; b < mb; b += gridDim.y) {
+    const int cnt = m - b * TB < TB ? m - b * TB : TB;
+    if (cnt <= 1) continue;                  // uniform over the workgroup
+    double* base = leafsum + (size_t)(L0 + b * TB) * d;
+    for (int e = threadIdx.x; e < cnt * d; e += blockDim.x) node[e] = base[e];
+    __syncthreads();
+    for (int s = 1; s < cnt; s <<= 1) {
+      const int pairs = (cnt - s - 1) / (2 * s) + 1;
+      for (int e = threadIdx.x; e < pairs * d; e += blockDim.x) {
+        const int i = e / d, dim = e - i * d;
+        const int a = i * 2 * s;
+        node[a * d + dim] = __dadd_rn(node[a * d + dim], node[(a + s) * d + dim]);
+      }
+      __syncthreads();
+    }
+    for (int dim = threadIdx.x; dim < d; dim += blockDim.x) base[dim] = node[dim];
+    __syncthreads();
+  }
+}
+
 // One workgroup per cluster: tree over its leaves, mean, operands, drift.
 // Block 0 also closes the iteration: totals of the counters and the
 // stopping rule (#changed <= tol * n).
@@ -496,7 +573,7 @@ __global__ __launch_bounds__(256) void tree_finalize(
     double* C_out, int64_t* __restrict__ counts_out, float* __restrict__ Cm2,
     float* __restrict__ cn, double* __restrict__ CT, int dp,
     uint16_t* __restrict__ Chi, uint16_t* __restrict__ Clo, int dpb,
-    float* __restrict__ drift, int* __restrict__ dirty, IterCtl ctl,
+    float* __restrict__ drift, int* __restrict__ dirty, int TB, IterCtl ctl,
     const int* __restrict__ conv, int iter) {
   __shared__ double red[256];
   __shared__ double cval[kMaxD];
@@ -539,21 +616,28 @@ __global__ __launch_bounds__(256) void tree_finalize(
     if (drift && threadIdx.x == 0) drift[j] = 0.0f;     // centroid unchanged
     return;
   }
+  // the block sums of tree_block sit at leaves 0, TB, 2 TB, ...: node b
   const int m = leaf_off[j + 1] - leaf_off[j];
+  const int mb = (m + TB - 1) / TB;
   double* base = leafsum + (size_t)leaf_off[j] * d;
-  const bool in_lds = (size_t)m * d <= (size_t)kTreeLdsDoubles;
-  double* node = in_lds ? tree : base;
+  const size_t bstride = (size_t)TB * d;
+  const bool in_lds = (size_t)mb * d <= (size_t)kTreeLdsDoubles;
   if (in_lds) {
-    for (int e = threadIdx.x; e < m * d; e += blockDim.x) tree[e] = base[e];
+    for (int e = threadIdx.x; e < mb * d; e += blockDim.x) {
+      const int b = e / d, dim = e - b * d;
+      tree[e] = base[(size_t)b * bstride + dim];
+    }
     __syncthreads();
   }
-  for (int s = 1; s < m; s <<= 1) {
-    const int pairs = (m - s - 1) / (2 * s) + 1;
+  double* node = in_lds ? tree : base;
+  const size_t nstride = in_lds ? (size_t)d : bstride;
+  for (int s = 1; s < mb; s <<= 1) {
+    const int pairs = (mb - s - 1) / (2 * s) + 1;
     for (int e = threadIdx.x; e < pairs * d; e += blockDim.x) {
       int i = e / d, dim = e - i * d;
       int a = i * 2 * s;
-      node[(size_t)a * d + dim] =
-          __dadd_rn(node[(size_t)a * d + dim], node[(size_t)(a + s) * d + dim]);
+      node[(size_t)a * nstride + dim] =
+          __dadd_rn(node[(size_t)a * nstride + dim], node[(size_t)(a + s) * nstride + dim]);
     }
     __syncthreads();
   }
@@ -611,9 +695,11 @@ hipError_t launch_update(const UpdatePlan& p, const void* X, knor_dtype dt,
     const size_t lds = sizeof(int) * (size_t)kFusedWaves * k;
     hipLaunchKernelGGL(hist_fused, dim3(p.nb), dim3(1024), lds, s, labels, p.n,
                        k, p.B, p.blockcnt, conv, iter);
+    hipLaunchKernelGGL(range_scan, dim3(k), dim3(256), 0, s, p.blockcnt, p.nb,
+                       k, p.rpre, p.nj, conv, iter);
     hipLaunchKernelGGL(scatter_fused, dim3(p.nb), dim3(1024), lds, s, labels,
-                       p.n, k, p.B, p.nb, bits, p.blockcnt, dirty, p.perm, p.nj,
-                       p.off, p.leaf_off, conv, iter);
+                       p.n, k, p.B, bits, p.blockcnt, p.rpre, p.nj, dirty,
+                       p.perm, p.off, p.leaf_off, conv, iter);
   } else {
     const size_t lds_k = sizeof(int) * (size_t)k;
     hipLaunchKernelGGL(hist_kernel, dim3(p.nb), dim3(256), lds_k, s, labels,
@@ -647,12 +733,21 @@ hipError_t launch_update(const UpdatePlan& p, const void* X, knor_dtype dt,
       break;
   }
   if (prof) { prof->end(); prof->begin(KNOR_PROF_TREE); }
+  {
+    // blocks per cluster for an even split: twice the mean, at most 256
+    const int64_t blocks = (p.max_leaves + p.tb - 1) / p.tb;
+    int64_t Y = 2 * ((blocks + k - 1) / k);
+    Y = Y < 1 ? 1 : (Y > 256 ? 256 : Y);
+    if (p.tb > 1)
+      hipLaunchKernelGGL(tree_block, dim3(k, (unsigned)Y), dim3(256), 0, s,
+                         p.leafsum, p.leaf_off, k, d, p.tb, dirty, conv, iter);
+  }
   hipLaunchKernelGGL(tree_finalize, dim3(k), dim3(256), 0, s, p.leafsum, p.nj,
                      p.leaf_off, k, d, C_prev, C_out, counts_out,
                      ops ? ops->Cm2 : nullptr, ops ? ops->cn : nullptr,
                      ops ? ops->CT : nullptr, ops ? ops->dp : 0,
                      ops ? ops->Chi : nullptr, ops ? ops->Clo : nullptr,
-                     ops ? ops->dpb : 0, drift, dirty,
+                     ops ? ops->dpb : 0, drift, dirty, p.tb,
                      *ctl, conv, iter);
   if (prof) prof->end();
   return hipGetLastError();
