@@ -90,6 +90,18 @@ typedef struct {
   int64_t* profile_launches; /* HOST, optional: KNOR_NPROF launch counts     */
   int32_t profile_mask; /* bit g set: time kernel group g; 0 = every group.
                            Each timed launch adds two event records          */
+  int32_t tile_blocks;  /* FP32 tile: blocks of 16 points per wave (1, 2 or
+                           4); 0 = tuned or default.  A value the row width
+                           does not allow gives KNOR_ERR_UNSUPPORTED         */
+  int32_t tile_resident;/* FP32 tile: 1 = all centroids resident in LDS
+                           (KNOR_ERR_UNSUPPORTED if they do not fit),
+                           2 = centroids streamed in chunks, 0 = tuned or
+                           default.  The schedule never changes results      */
+  int32_t autotune;     /* 1: knor_fit times the FP32 tile schedules of its
+                           (d, k) class on a sample of X once per process
+                           and keeps the fastest; 0: use the table or the
+                           default (knor_fit_batched always tunes unless a
+                           schedule is forced)                               */
 } knor_opts;
 
 /* Kernel groups timed by opts->profile_ms. */
@@ -171,6 +183,39 @@ knor_status knor_update(const void* X, knor_dtype dt, int64_t n, int32_t d,
                         const int32_t* labels, int32_t k,
                         const double* C_prev, const knor_opts* opts,
                         double* C_out, int64_t* counts_out);
+
+/* One problem of a batch.  All pointers are DEVICE pointers owned by the
+ * caller; C_init NULL selects KNOR_INIT_FORGY with seed opts->seed + the
+ * problem's index. */
+typedef struct {
+  const void* X;          /* n x d, dtype dt                                 */
+  knor_dtype dt;
+  int64_t n;
+  int32_t d, k;
+  const double* C_init;   /* k x d FP64 or NULL                              */
+  int32_t max_iters;
+  double tol;
+  double* C_out;          /* k x d FP64                                      */
+  int32_t* labels_out;    /* n int32                                         */
+} knor_problem;
+
+/* knor_fit_batched: knor_fit on each of `count` independent problems
+ * (restarts, or unrelated data sets), each with exactly the results knor_fit
+ * gives it alone.  The problems run concurrently on the device's hardware
+ * queues, largest work (n k d) first; each FP32 (d, k) class is tuned once
+ * per process unless opts forces a tile schedule.  Work is ordered after
+ * everything already enqueued on opts->stream; the call returns when every
+ * problem is done.
+ *   probs   HOST array of count problems (count >= 0).
+ *   opts    as for knor_fit, except that label_history, iter_counters and
+ *           profile_ms / profile_launches must be NULL.
+ *   st      HOST array of count stats, or NULL.
+ * Every problem is validated before any work starts (an invalid one gives
+ * KNOR_ERR_INVALID_ARG and no output is touched).  A runtime error in one
+ * problem leaves the others' results valid; the first error in problem
+ * order is returned. */
+knor_status knor_fit_batched(const knor_problem* probs, int32_t count,
+                             const knor_opts* opts, knor_stats* st);
 
 /* Human-readable name of a status code (static storage). */
 const char* knor_status_string(knor_status s);

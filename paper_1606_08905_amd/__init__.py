@@ -18,8 +18,8 @@ from __future__ import annotations
 import ctypes
 import os
 
-__all__ = ["fit", "assign", "update", "load", "KnorError", "COUNTERS",
-           "library_path"]
+__all__ = ["fit", "fit_batched", "assign", "update", "load", "KnorError",
+           "COUNTERS", "library_path"]
 
 _PKG = os.path.dirname(os.path.abspath(__file__))
 _LIB = os.path.join(_PKG, "libknor.so")
@@ -47,12 +47,23 @@ class Opts(ctypes.Structure):
                 ("poll_every", ctypes.c_int32),
                 ("profile_ms", ctypes.c_void_p),
                 ("profile_launches", ctypes.c_void_p),
-                ("profile_mask", ctypes.c_int32)]
+                ("profile_mask", ctypes.c_int32),
+                ("tile_blocks", ctypes.c_int32),
+                ("tile_resident", ctypes.c_int32),
+                ("autotune", ctypes.c_int32)]
 
 
 NPROF = 8
 PROF_GROUPS = ("assign_dense", "assign_list", "recheck", "filter", "sort",
                "leaf", "tree", "cc")
+
+
+class Problem(ctypes.Structure):
+    _fields_ = [("X", ctypes.c_void_p), ("dt", ctypes.c_int),
+                ("n", ctypes.c_int64), ("d", ctypes.c_int32),
+                ("k", ctypes.c_int32), ("C_init", ctypes.c_void_p),
+                ("max_iters", ctypes.c_int32), ("tol", ctypes.c_double),
+                ("C_out", ctypes.c_void_p), ("labels_out", ctypes.c_void_p)]
 
 
 class Stats(ctypes.Structure):
@@ -94,6 +105,9 @@ def load():
     L.knor_update.argtypes = [P, ctypes.c_int, i64, i32, P, i32, P,
                               ctypes.POINTER(Opts), P, P]
     L.knor_update.restype = ctypes.c_int
+    L.knor_fit_batched.argtypes = [ctypes.POINTER(Problem), i32,
+                                   ctypes.POINTER(Opts), ctypes.POINTER(Stats)]
+    L.knor_fit_batched.restype = ctypes.c_int
     L.knor_status_string.argtypes = [ctypes.c_int]
     L.knor_status_string.restype = ctypes.c_char_p
     L.knor_version.restype = ctypes.c_int32
@@ -128,7 +142,8 @@ def _raise(rc):
 
 def _opts(prune=True, recheck=1, check_numeric=True, seed=0, stream=None,
           workspace_cap=0, label_history=None, iter_counters=None,
-          poll_every=0, profile=None):
+          poll_every=0, profile=None, tile_blocks=0, tile_resident=0,
+          autotune=False):
     torch = _torch()
     if stream is None:
         stream = torch.cuda.current_stream()
@@ -148,12 +163,16 @@ def _opts(prune=True, recheck=1, check_numeric=True, seed=0, stream=None,
         o.profile_ms = ms.ctypes.data
         o.profile_launches = launches.ctypes.data
         o.profile_mask = int(profile[2]) if len(profile) > 2 else 0
+    o.tile_blocks = int(tile_blocks)
+    o.tile_resident = int(tile_resident)
+    o.autotune = 1 if autotune else 0
     return o
 
 
 def fit(X, k, C0=None, init="given", max_iters=100, tol=0.0, prune=True,
         recheck=1, seed=0, history=False, counters=False, out=None,
-        check_numeric=True, workspace_cap=0, poll_every=0, profile=None):
+        check_numeric=True, workspace_cap=0, poll_every=0, profile=None,
+        tile_blocks=0, tile_resident=0, autotune=False):
     """Lloyd's k-means on the GPU.  Returns (C, labels, stats dict).
 
     history=True adds stats["label_history"]: (iters, n) int32 CUDA tensor of
@@ -162,7 +181,10 @@ def fit(X, k, C0=None, init="given", max_iters=100, tol=0.0, prune=True,
     out=(C, labels) reuses preallocated output tensors.  profile=(ms, launches
     [, mask]) (float64 and int64 numpy arrays of NPROF entries, optional bit
     mask of groups) accumulates per-group GPU time measured with HIP events
-    on the launch stream."""
+    on the launch stream.  tile_blocks / tile_resident force an FP32 tile
+    schedule (1, 2 or 4 blocks of 16 points per wave; 1 resident, 2
+    chunked); autotune=True times the schedules of this (d, k) class once
+    per process.  No schedule changes the results."""
     torch = _torch()
     import numpy as np
     L = load()
@@ -185,7 +207,7 @@ def fit(X, k, C0=None, init="given", max_iters=100, tol=0.0, prune=True,
     hist = torch.empty((max_iters, n), dtype=torch.int32, device=dev) if history else None
     cnt = np.zeros((max_iters, NCOUNTERS), np.int64) if counters else None
     o = _opts(prune, recheck, check_numeric, seed, None, workspace_cap, hist,
-              cnt, poll_every, profile)
+              cnt, poll_every, profile, tile_blocks, tile_resident, autotune)
     st = Stats()
     rc = L.knor_fit(X.data_ptr(), _dtype_code(X), n, d, k, init_code, c0p,
                     max_iters, float(tol), ctypes.byref(o), C.data_ptr(),
@@ -197,6 +219,41 @@ def fit(X, k, C0=None, init="given", max_iters=100, tol=0.0, prune=True,
     if counters:
         s["counters"] = cnt[: st.iters]
     return C, lab, s
+
+
+def fit_batched(problems, prune=True, recheck=1, seed=0, check_numeric=True,
+                workspace_cap=0, tile_blocks=0, tile_resident=0):
+    """knor_fit on each problem of a batch, run concurrently.  problems: list
+    of dicts with keys X, k and optionally C0 (None: Forgy from seed + index),
+    max_iters (default 100), tol (default 0).  Returns a list of
+    (C, labels, stats dict), each equal to what fit() gives on its own."""
+    torch = _torch()
+    L = load()
+    arr = (Problem * max(1, len(problems)))()
+    keep, outs = [], []
+    for i, p in enumerate(problems):
+        X = p["X"]
+        _check_dev(X, "X")
+        n, d = X.shape
+        k = int(p["k"])
+        C = torch.empty((k, d), dtype=torch.float64, device=X.device)
+        lab = torch.empty((n,), dtype=torch.int32, device=X.device)
+        C0 = p.get("C0")
+        if C0 is not None:
+            C0 = torch.as_tensor(C0, dtype=torch.float64, device=X.device).contiguous()
+            keep.append(C0)
+        a = arr[i]
+        a.X = X.data_ptr(); a.dt = _dtype_code(X); a.n = n; a.d = d; a.k = k
+        a.C_init = C0.data_ptr() if C0 is not None else None
+        a.max_iters = int(p.get("max_iters", 100)); a.tol = float(p.get("tol", 0.0))
+        a.C_out = C.data_ptr(); a.labels_out = lab.data_ptr()
+        outs.append((C, lab))
+    o = _opts(prune, recheck, check_numeric, seed, None, workspace_cap,
+              tile_blocks=tile_blocks, tile_resident=tile_resident)
+    sts = (Stats * max(1, len(problems)))()
+    rc = L.knor_fit_batched(arr, len(problems), ctypes.byref(o), sts)
+    _raise(rc)
+    return [(C, lab, sts[i].as_dict()) for i, (C, lab) in enumerate(outs)]
 
 
 def assign(X, C, recheck=1, dist2=False):

@@ -3,9 +3,14 @@
 // Sections "Parallel Lloyd's Algorithm" and "Minimal Triangle Inequality
 // (MTI) Pruning").  Every arithmetic step runs in the kernels of this
 // library; the host only validates, allocates, enqueues and polls.
+#include <algorithm>
+#include <atomic>
 #include <chrono>
+#include <map>
 #include <math.h>
+#include <mutex>
 #include <string.h>
+#include <thread>
 #include <unordered_map>
 #include <vector>
 
@@ -198,6 +203,7 @@ struct Opts {
   double* profile_ms = nullptr;
   int64_t* profile_launches = nullptr;
   int profile_mask = 0;
+  int tile_blocks = 0, tile_resident = 0, autotune = 0;
 };
 
 static knor_status read_opts(const knor_opts* o, Opts* out) {
@@ -219,6 +225,14 @@ static knor_status read_opts(const knor_opts* o, Opts* out) {
   out->profile_launches = o->profile_launches;
   out->profile_mask = o->profile_mask;
   if (o->poll_every > 0) out->poll_every = o->poll_every;
+  if (o->tile_blocks != 0 && o->tile_blocks != 1 && o->tile_blocks != 2 &&
+      o->tile_blocks != 4)
+    return KNOR_ERR_INVALID_ARG;
+  if (o->tile_resident < 0 || o->tile_resident > 2) return KNOR_ERR_INVALID_ARG;
+  if (o->autotune < 0 || o->autotune > 1) return KNOR_ERR_INVALID_ARG;
+  out->tile_blocks = o->tile_blocks;
+  out->tile_resident = o->tile_resident;
+  out->autotune = o->autotune;
   return KNOR_OK;
 }
 
@@ -281,6 +295,143 @@ static int64_t flag_capacity(const CentroidOps& ops, knor_dtype dt, int64_t n,
 }
 
 // ---------------------------------------------------------------------------
+// FP32 tile schedule: default, tuned, or forced
+// ---------------------------------------------------------------------------
+//
+// Every schedule computes the same FP32 values in the same order for every
+// (point, centroid) pair, and undecided points go to the FP64 recheck, so
+// the schedule changes speed only, never labels.  The tune table is the
+// library's only process-wide mutable state; a mutex guards it.
+
+static std::mutex g_tune_mu;
+static std::map<std::pair<int, int>, std::pair<int, int>> g_tune;   // (dp, kpad) -> (pb, resident)
+
+static bool tune_lookup(int dp, int kpad, int* pb, int* res) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  auto it = g_tune.find({dp, kpad});
+  if (it == g_tune.end()) return false;
+  *pb = it->second.first;
+  *res = it->second.second;
+  return true;
+}
+
+static void tune_store(int dp, int kpad, int pb, int res) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tune[{dp, kpad}] = {pb, res};
+}
+
+// schedule candidates of a (dp, kpad) class
+static std::vector<std::pair<int, int>> tile_candidates(int dp, int kpad) {
+  std::vector<std::pair<int, int>> c;
+  for (int res = 1; res >= 0; --res) {
+    if (res && !tile_f32_resident(dp, kpad)) continue;
+    for (int pb : {1, 2, 4})
+      if (tile_f32_pb_ok(dp, pb)) c.push_back({pb, res});
+  }
+  return c;
+}
+
+// Times every candidate schedule of the dense FP32 tile on the first ns
+// points of X against centroids C (k x d FP64, device) and stores the
+// fastest in the table.  Writes only its own scratch.
+static knor_status tune_tile(const float* X, int64_t n, int d, const double* C,
+                             int k, hipStream_t s) {
+  const int kpad = (k + 15) / 16 * 16, dp = pad_dim(d);
+  const int64_t ns = n < (1 << 17) ? n : (1 << 17);
+  const auto cand = tile_candidates(dp, kpad);
+  CentroidOps ops{};
+  ops.k = k; ops.kpad = kpad; ops.d = d; ops.dp = dp; ops.dpb = pad_dim_bf16(d);
+  ops.C64 = const_cast<double*>(C);
+  int64_t fcap = 1;
+  for (auto& c : cand) {
+    const TileGeom g = tile_f32_geometry(dp, kpad, c.first, c.second, ns, false, 1);
+    fcap = std::max(fcap, (int64_t)g.grid * g.cap);
+  }
+  int32_t* lab = nullptr;
+  int *flags = nullptr, *ucnt = nullptr, *conv = nullptr;
+  unsigned long long* row = nullptr;
+  double* Cs = nullptr;
+  int64_t* rows_dev = nullptr;
+  Arena ar;
+  if (!C) {                                  // centroids: the first k rows
+    ar.add((void**)&Cs, sizeof(double) * (size_t)k * d);
+    ar.add((void**)&rows_dev, sizeof(int64_t) * (size_t)k);
+  }
+  ar.add((void**)&ops.Cm2, sizeof(float) * (size_t)kpad * dp);
+  ar.add((void**)&ops.cn, sizeof(float) * (size_t)kpad);
+  ar.add((void**)&lab, sizeof(int32_t) * (size_t)ns);
+  ar.add((void**)&flags, sizeof(int) * (size_t)fcap);
+  ar.add((void**)&ucnt, sizeof(int) * (size_t)kTileMaxGrid);
+  ar.add((void**)&row, sizeof(unsigned long long) * ROW_STRIDE);
+  ar.add((void**)&conv, sizeof(int) * 4);
+  if (knor_status r = ar.alloc(s, 0)) return r;
+  if (!C) {
+    std::vector<int64_t> rows(k);
+    for (int i = 0; i < k; ++i) rows[i] = i;
+    HIPCHK(hipMemcpyAsync(rows_dev, rows.data(), sizeof(int64_t) * k,
+                          hipMemcpyHostToDevice, s));
+    HIPCHK(launch_gather_rows(X, KNOR_F32, d, rows_dev, k, Cs, s));
+    HIPCHK(hipStreamSynchronize(s));        // `rows` leaves scope
+    ops.C64 = Cs;
+  }
+  HIPCHK(launch_prep_centroids(ops, s));
+  HIPCHK(launch_fill_i32(conv, 1, kNotConverged, s));
+  HIPCHK(launch_fill_i32(lab, ns, -1, s));
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  float best_ms = 1e30f;
+  std::pair<int, int> best = cand.front();
+  for (auto& c : cand) {
+    ops.tpb = c.first;
+    ops.tres = c.second;
+    AssignJob job{};
+    job.X = X; job.dt = KNOR_F32; job.n = ns; job.d = d;
+    job.labels = lab; job.flags = flags; job.ucnt = ucnt; job.row = row;
+    job.conv = conv; job.iter = 0;
+    float tmin = 1e30f;
+    for (int rep = 0; rep < 3; ++rep) {     // the first is a warm-up
+      HIPCHK(hipEventRecord(e0, s));
+      HIPCHK(launch_tile_f32(ops, job, s));
+      HIPCHK(hipEventRecord(e1, s));
+      HIPCHK(hipEventSynchronize(e1));
+      float ms = 0.0f;
+      HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+      if (rep > 0) tmin = std::min(tmin, ms);
+    }
+    if (tmin < best_ms) { best_ms = tmin; best = c; }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  HIPCHK(hipStreamSynchronize(s));
+  tune_store(dp, kpad, best.first, best.second);
+  return KNOR_OK;
+}
+
+// The FP32 tile schedule of one call: forced by the options, else tuned
+// (table), else the default.
+static knor_status select_tile(CentroidOps& ops, const Opts& o) {
+  int pb, res;
+  tile_f32_default(ops.dp, ops.kpad, &pb, &res);
+  int tpb, tres;
+  if (tune_lookup(ops.dp, ops.kpad, &tpb, &tres)) { pb = tpb; res = tres; }
+  if (o.tile_resident == 1) {
+    if (!tile_f32_resident(ops.dp, ops.kpad)) return KNOR_ERR_UNSUPPORTED;
+    res = 1;
+  } else if (o.tile_resident == 2) {
+    res = 0;
+  }
+  if (o.tile_blocks) pb = o.tile_blocks;
+  if (!tile_f32_pb_ok(ops.dp, pb)) {
+    if (o.tile_blocks) return KNOR_ERR_UNSUPPORTED;
+    tile_f32_default(ops.dp, ops.kpad, &pb, &tres);   // keep res, fix pb
+  }
+  ops.tpb = pb;
+  ops.tres = res;
+  return KNOR_OK;
+}
+
+// ---------------------------------------------------------------------------
 // fit
 // ---------------------------------------------------------------------------
 
@@ -299,6 +450,7 @@ static knor_status fit_impl(const void* X, knor_dtype dt, int64_t n, int d,
   CentroidOps ops{};
   ops.k = k; ops.kpad = kpad; ops.d = d; ops.dp = dp; ops.dpb = pad_dim_bf16(d);
   ops.C64 = C_out;                 // the output buffer is the working copy
+  if (knor_status r = select_tile(ops, o)) return r;
   UpdatePlan plan{};
   void* upd_ws = nullptr;
   float *u = nullptr, *drift = nullptr, *s_half = nullptr;
@@ -499,8 +651,107 @@ knor_status knor_fit(const void* X, knor_dtype dt, int64_t n, int32_t d,
   } else if (init != KNOR_INIT_FORGY) {
     return KNOR_ERR_INVALID_ARG;
   }
+  if (o.autotune && dt == KNOR_F32 && !o.tile_blocks && !o.tile_resident) {
+    int pb, res;
+    if (!tune_lookup(pad_dim(d), (k + 15) / 16 * 16, &pb, &res))
+      if (knor_status r = tune_tile((const float*)X, n, d,
+                                    init == KNOR_INIT_GIVEN ? C_init : nullptr, k,
+                                    o.stream))
+        return r;
+  }
   return fit_impl(X, dt, n, d, k, init, C_init, max_iters, tol, o, C_out,
                   labels_out, st);
+}
+
+// The batched form: independent fits of many problems, run concurrently on
+// kBatchStreams streams (the device's hardware queues) by as many host
+// threads, largest work (n k d) first.  Each FP32 shape class is tuned once
+// (unless the options force a schedule); the results of every problem are
+// those of knor_fit on it alone.
+constexpr int kBatchStreams = 4;
+
+knor_status knor_fit_batched(const knor_problem* probs, int32_t count,
+                             const knor_opts* opts, knor_stats* st) {
+  Opts o;
+  if (knor_status r = read_opts(opts, &o)) return r;
+  if (count < 0 || (count > 0 && !probs)) return KNOR_ERR_INVALID_ARG;
+  if (o.label_history || o.iter_counters || o.profile_ms || o.profile_launches)
+    return KNOR_ERR_INVALID_ARG;           // per-call arrays: single fits only
+  for (int i = 0; i < count; ++i) {
+    const knor_problem& p = probs[i];
+    if (!p.X || !p.C_out || !p.labels_out || !dtype_ok(p.dt)) return KNOR_ERR_INVALID_ARG;
+    if (p.n < 1 || p.n >= (int64_t)1 << 31 || p.d < 1 || p.d > kMaxD || p.k < 1 ||
+        p.k > kMaxK || (int64_t)p.k > p.n || p.max_iters < 1 ||
+        !(p.tol >= 0.0 && p.tol < 1.0))
+      return KNOR_ERR_INVALID_ARG;
+  }
+  if (count == 0) return KNOR_OK;
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  // tune each FP32 class once, on its largest problem
+  if (!o.tile_blocks && !o.tile_resident) {
+    std::map<std::pair<int, int>, int> rep;
+    for (int i = 0; i < count; ++i) {
+      const knor_problem& p = probs[i];
+      if (p.dt != KNOR_F32) continue;
+      const std::pair<int, int> key{pad_dim(p.d), (p.k + 15) / 16 * 16};
+      auto it = rep.find(key);
+      if (it == rep.end() || probs[it->second].n < p.n) rep[key] = i;
+    }
+    for (auto& kv : rep) {
+      int pb, res;
+      if (tune_lookup(kv.first.first, kv.first.second, &pb, &res)) continue;
+      const knor_problem& p = probs[kv.second];
+      if (knor_status r = tune_tile((const float*)p.X, p.n, p.d, p.C_init, p.k, o.stream))
+        return r;
+    }
+  }
+  // work on the worker streams follows everything already on opts->stream
+  hipEvent_t ready;
+  HIPCHK(hipEventCreateWithFlags(&ready, hipEventDisableTiming));
+  if (hipEventRecord(ready, o.stream) != hipSuccess) {
+    (void)hipEventDestroy(ready);
+    return KNOR_ERR_HIP;
+  }
+  std::vector<int> order(count);
+  for (int i = 0; i < count; ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+    return probs[a].n * (int64_t)probs[a].k * probs[a].d >
+           probs[b].n * (int64_t)probs[b].k * probs[b].d;
+  });
+  std::vector<knor_status> res(count, KNOR_OK);
+  std::atomic<int> next{0};
+  const int nw = count < kBatchStreams ? count : kBatchStreams;
+  auto worker = [&]() {
+    hipStream_t sw = nullptr;
+    if (hipSetDevice(dev) != hipSuccess ||
+        hipStreamCreateWithFlags(&sw, hipStreamNonBlocking) != hipSuccess ||
+        hipStreamWaitEvent(sw, ready, 0) != hipSuccess) {
+      for (int i = next++; i < count; i = next++) res[order[i]] = KNOR_ERR_HIP;
+      if (sw) (void)hipStreamDestroy(sw);
+      return;
+    }
+    for (int i = next++; i < count; i = next++) {
+      const int q = order[i];
+      const knor_problem& p = probs[q];
+      Opts oi = o;
+      oi.stream = sw;
+      oi.seed = o.seed + (uint64_t)q;
+      res[q] = fit_impl(p.X, p.dt, p.n, p.d, p.k,
+                        p.C_init ? KNOR_INIT_GIVEN : KNOR_INIT_FORGY, p.C_init,
+                        p.max_iters, p.tol, oi, p.C_out, p.labels_out,
+                        st ? &st[q] : nullptr);
+    }
+    if (hipStreamSynchronize(sw) != hipSuccess) res[order[0]] = KNOR_ERR_HIP;
+    (void)hipStreamDestroy(sw);
+  };
+  std::vector<std::thread> th;
+  for (int w = 0; w < nw; ++w) th.emplace_back(worker);
+  for (auto& t : th) t.join();
+  (void)hipEventDestroy(ready);
+  for (int i = 0; i < count; ++i)
+    if (res[i] != KNOR_OK) return res[i];
+  return KNOR_OK;
 }
 
 knor_status knor_assign(const void* X, knor_dtype dt, int64_t n, int32_t d,
@@ -517,6 +768,7 @@ knor_status knor_assign(const void* X, knor_dtype dt, int64_t n, int32_t d,
   ops.k = k; ops.kpad = (k + 15) / 16 * 16; ops.d = d; ops.dp = pad_dim(d);
   ops.dpb = pad_dim_bf16(d);
   ops.C64 = const_cast<double*>(C);
+  if (knor_status r = select_tile(ops, o)) return r;
   int* flags = nullptr;
   int* conv = nullptr;
   int* ucnt = nullptr;

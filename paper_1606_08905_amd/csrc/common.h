@@ -214,6 +214,7 @@ struct CentroidOps {
   uint16_t* Chi;   // kpad x dpb BF16 bf16(-2c), zero-padded (BF16 path) or null
   uint16_t* Clo;   // kpad x dpb BF16 bf16(-2c - Chi) (BF16 path) or null
   int k, kpad, d, dp, dpb;
+  int tpb, tres;   // FP32 tile schedule: point blocks of 16 per wave, resident
 };
 
 // The point set one assignment pass covers.
@@ -252,7 +253,10 @@ struct TileGeom {
   bool resident;
 };
 bool tile_f32_resident(int dp, int kpad);
-TileGeom tile_f32_geometry(int dp, int kpad, int64_t n, bool segmented, int nseg);
+bool tile_f32_pb_ok(int dp, int pb);
+void tile_f32_default(int dp, int kpad, int* pb, int* resident);
+TileGeom tile_f32_geometry(int dp, int kpad, int pb, int resident, int64_t n,
+                           bool segmented, int nseg);
 bool tile_bf16_resident(int dpb, int kpad);
 TileGeom tile_bf16_geometry(int dpb, int kpad, int64_t n, bool segmented, int nseg);
 // the geometry of the tile that serves points of type dt

@@ -73,18 +73,34 @@ bool tile_f32_resident(int dp, int kpad) {
   return (size_t)kpad * (dp + 4) * 4 + (size_t)kpad * 4 <= kResidentLds;
 }
 
-TileGeom tile_f32_geometry(int dp, int kpad, int64_t n, bool seg, int nseg) {
+// Point blocks per wave that fit the register budget of a row width.
+bool tile_f32_pb_ok(int dp, int pb) {
+  if (pb != 1 && pb != 2 && pb != 4) return false;
+  if (dp >= 256) return pb == 1;
+  if (dp >= 128) return pb <= 2;
+  return true;
+}
+
+void tile_f32_default(int dp, int kpad, int* pb, int* resident) {
+  *resident = tile_f32_resident(dp, kpad) ? 1 : 0;
+  *pb = *resident ? res_pb(dp) : chk_pb(dp);
+}
+
+TileGeom tile_f32_geometry(int dp, int kpad, int pb, int resident, int64_t n,
+                           bool seg, int nseg) {
+  (void)dp;
+  (void)kpad;
   TileGeom g{};
-  g.resident = tile_f32_resident(dp, kpad);
+  g.resident = resident != 0;
   if (g.resident) {
-    const int wup = 16 * res_pb(dp);
+    const int wup = 16 * pb;
     const int64_t nwu = seg ? (int64_t)nseg * (kSeg / wup) : (n + wup - 1) / wup;
     int64_t blocks = (nwu + 3) / 4;
     g.grid = (int)(blocks < kResidentGrid ? (blocks < 1 ? 1 : blocks) : kResidentGrid);
     const int64_t per_wave = (nwu + 4LL * g.grid - 1) / (4LL * g.grid);
     g.cap = per_wave * 4 * wup;
   } else {
-    const int bup = 64 * chk_pb(dp);
+    const int bup = 64 * pb;
     const int64_t units = seg ? (int64_t)nseg * (kSeg / bup) : (n + bup - 1) / bup;
     g.grid = (int)(units < kChunkedGrid ? (units < 1 ? 1 : units) : kChunkedGrid);
     g.cap = (units + g.grid - 1) / g.grid * bup;
@@ -95,7 +111,7 @@ TileGeom tile_f32_geometry(int dp, int kpad, int64_t n, bool seg, int nseg) {
 TileGeom tile_geometry(const CentroidOps& o, knor_dtype dt, int64_t n,
                        bool seg, int nseg) {
   if (dt == KNOR_BF16) return tile_bf16_geometry(o.dpb, o.kpad, n, seg, nseg);
-  return tile_f32_geometry(o.dp, o.kpad, n, seg, nseg);
+  return tile_f32_geometry(o.dp, o.kpad, o.tpb, o.tres, n, seg, nseg);
 }
 
 int64_t tile_flag_capacity(const CentroidOps& o, knor_dtype dt, int64_t n,
@@ -226,7 +242,7 @@ __device__ __forceinline__ void tile_sweep(WaveState<T>& w, const float* sC,
   }
 }
 
-template <int DP>
+template <int DP, int PB_>
 __global__ __launch_bounds__(kTileThreads) void tile_f32_resident_kernel(
     const float* __restrict__ X, int64_t n, int d,
     const float* __restrict__ Cm2, const float* __restrict__ cn, int k,
@@ -235,7 +251,7 @@ __global__ __launch_bounds__(kTileThreads) void tile_f32_resident_kernel(
     int* __restrict__ flags, int64_t cap, int* __restrict__ ucnt,
     unsigned long long* __restrict__ row, const int* __restrict__ conv,
     int iter, int* __restrict__ dirty, int recheck_all, int vec) {
-  using T = F32Tile<DP, res_pb(DP)>;
+  using T = F32Tile<DP, PB_>;
   constexpr int LDA = T::LDA, PB = T::PB, WUP = T::WUP;
   extern __shared__ __attribute__((aligned(16))) float smem[];
   __shared__ int sFlag;
@@ -282,7 +298,7 @@ __global__ __launch_bounds__(kTileThreads) void tile_f32_resident_kernel(
   if (threadIdx.x == 0) ucnt[blockIdx.x] = sFlag;
 }
 
-template <int DP>
+template <int DP, int PB_>
 __global__ __launch_bounds__(kTileThreads) void tile_f32_chunked_kernel(
     const float* __restrict__ X, int64_t n, int d,
     const float* __restrict__ Cm2, const float* __restrict__ cn, int k,
@@ -291,7 +307,7 @@ __global__ __launch_bounds__(kTileThreads) void tile_f32_chunked_kernel(
     int* __restrict__ flags, int64_t cap, int* __restrict__ ucnt,
     unsigned long long* __restrict__ row, const int* __restrict__ conv,
     int iter, int* __restrict__ dirty, int recheck_all, int vec) {
-  using T = F32Tile<DP, chk_pb(DP)>;
+  using T = F32Tile<DP, PB_>;
   constexpr int LDA = T::LDA, PB = T::PB, CK = T::CK, WUP = T::WUP, BUP = T::BUP;
   __shared__ __attribute__((aligned(16))) float sC[CK * LDA];
   __shared__ __attribute__((aligned(16))) float sN[CK];
@@ -339,28 +355,44 @@ __global__ __launch_bounds__(kTileThreads) void tile_f32_chunked_kernel(
   if (threadIdx.x == 0) ucnt[blockIdx.x] = sFlag;
 }
 
+template <int DP, int PB>
+static hipError_t launch_dp_pb(const CentroidOps& o, const AssignJob& j,
+                               hipStream_t s) {
+  const int vec = (int)(j.d == DP && ((uintptr_t)j.X & 15) == 0);
+  const bool seg = j.seg_cnt != nullptr;
+  const TileGeom g = tile_f32_geometry(DP, o.kpad, PB, o.tres, j.n, seg, j.nseg);
+  if (g.resident) {
+    using T = F32Tile<DP, PB>;
+    const size_t lds = (size_t)o.kpad * T::LDA * 4 + (size_t)o.kpad * 4;
+    hipLaunchKernelGGL((tile_f32_resident_kernel<DP, PB>), dim3(g.grid),
+                       dim3(kTileThreads), lds, s, (const float*)j.X, j.n, j.d,
+                       o.Cm2, o.cn, o.k, o.kpad, j.list, j.seg_cnt, j.nseg,
+                       j.labels, j.u, j.flags, g.cap, j.ucnt, j.row, j.conv,
+                       j.iter, j.dirty, j.recheck_all, vec);
+  } else {
+    hipLaunchKernelGGL((tile_f32_chunked_kernel<DP, PB>), dim3(g.grid),
+                       dim3(kTileThreads), 0, s, (const float*)j.X, j.n, j.d,
+                       o.Cm2, o.cn, o.k, o.kpad, j.list, j.seg_cnt, j.nseg,
+                       j.labels, j.u, j.flags, g.cap, j.ucnt, j.row, j.conv,
+                       j.iter, j.dirty, j.recheck_all, vec);
+  }
+  return hipGetLastError();
+}
+
 template <int DP>
 static hipError_t launch_dp(const CentroidOps& o, const AssignJob& j,
                             hipStream_t s) {
-  const int vec = (int)(j.d == DP && ((uintptr_t)j.X & 15) == 0);
-  const bool seg = j.seg_cnt != nullptr;
-  const TileGeom g = tile_f32_geometry(DP, o.kpad, j.n, seg, j.nseg);
-  if (g.resident) {
-    using T = F32Tile<DP, res_pb(DP)>;
-    const size_t lds = (size_t)o.kpad * T::LDA * 4 + (size_t)o.kpad * 4;
-    hipLaunchKernelGGL(tile_f32_resident_kernel<DP>, dim3(g.grid), dim3(kTileThreads),
-                       lds, s, (const float*)j.X, j.n, j.d, o.Cm2, o.cn, o.k,
-                       o.kpad, j.list, j.seg_cnt, j.nseg, j.labels, j.u, j.flags,
-                       g.cap, j.ucnt, j.row, j.conv, j.iter, j.dirty,
-                       j.recheck_all, vec);
-  } else {
-    hipLaunchKernelGGL(tile_f32_chunked_kernel<DP>, dim3(g.grid), dim3(kTileThreads),
-                       0, s, (const float*)j.X, j.n, j.d, o.Cm2, o.cn, o.k,
-                       o.kpad, j.list, j.seg_cnt, j.nseg, j.labels, j.u, j.flags,
-                       g.cap, j.ucnt, j.row, j.conv, j.iter, j.dirty,
-                       j.recheck_all, vec);
+  if (o.tres && !tile_f32_resident(DP, o.kpad)) return hipErrorInvalidValue;
+  switch (o.tpb) {
+    case 1: return launch_dp_pb<DP, 1>(o, j, s);
+    case 2:
+      if constexpr (DP < 256) return launch_dp_pb<DP, 2>(o, j, s);
+      break;
+    case 4:
+      if constexpr (DP < 128) return launch_dp_pb<DP, 4>(o, j, s);
+      break;
   }
-  return hipGetLastError();
+  return hipErrorInvalidValue;
 }
 
 hipError_t launch_tile_f32(const CentroidOps& o, const AssignJob& j,

@@ -86,3 +86,49 @@ def test_binding_refuses_cpu_tensors():
     X = torch.zeros((10, 4))
     with pytest.raises((ValueError, RuntimeError)):
         knor.fit(X, 2, C0=torch.zeros((2, 4), dtype=torch.float64))
+
+
+def _problem(**kw):
+    p = knor.Problem()
+    p.X = 0x1000; p.dt = 1; p.n = 100; p.d = 8; p.k = 4; p.C_init = 0x1000
+    p.max_iters = 10; p.tol = 0.0; p.C_out = 0x1000; p.labels_out = 0x1000
+    for key, v in kw.items():
+        setattr(p, key, v)
+    return p
+
+
+@pytest.mark.parametrize("kw", [
+    dict(X=None), dict(dt=7), dict(n=0), dict(d=300), dict(k=0), dict(k=200),
+    dict(max_iters=0), dict(tol=1.5), dict(C_out=None), dict(labels_out=None),
+])
+def test_fit_batched_rejects_invalid(L, kw):
+    arr = (knor.Problem * 3)(_problem(), _problem(**kw), _problem())
+    assert L.knor_fit_batched(arr, 3, None, None) == knor.KNOR_ERR_INVALID_ARG
+    assert L.knor_fit_batched(None, 2, None, None) == knor.KNOR_ERR_INVALID_ARG
+    assert L.knor_fit_batched(arr, -1, None, None) == knor.KNOR_ERR_INVALID_ARG
+    assert L.knor_fit_batched(None, 0, None, None) == knor.KNOR_OK
+
+
+@pytest.mark.parametrize("field,value", [("tile_blocks", 3), ("tile_resident", 3),
+                                         ("autotune", 2)])
+def test_tile_options_validated(L, field, value):
+    o = knor.Opts()
+    o.struct_size = ctypes.sizeof(knor.Opts)
+    o.prune = 1
+    o.recheck = 1
+    o.check_numeric = 1
+    setattr(o, field, value)
+    assert _fit(L, opts=ctypes.byref(o)) == knor.KNOR_ERR_INVALID_ARG
+    arr = (knor.Problem * 1)(_problem())
+    assert L.knor_fit_batched(arr, 1, ctypes.byref(o), None) == knor.KNOR_ERR_INVALID_ARG
+
+
+def test_fit_batched_rejects_per_call_arrays(L):
+    o = knor.Opts()
+    o.struct_size = ctypes.sizeof(knor.Opts)
+    o.prune = 1
+    o.recheck = 1
+    o.check_numeric = 1
+    o.label_history = 0x1000
+    arr = (knor.Problem * 1)(_problem())
+    assert L.knor_fit_batched(arr, 1, ctypes.byref(o), None) == knor.KNOR_ERR_INVALID_ARG

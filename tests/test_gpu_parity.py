@@ -317,3 +317,88 @@ def test_fit_config2_full_size():
     st, ref = _fit_compare(w.X, w.dtype, w.C0, w.k, w.max_iters, True,
                            oracle_fit=oracle.mti_fit)
     print("config2 iters", st["iters"], "rechecked", st["rechecked"], flush=True)
+
+
+# ---------------------------------------------------------------------------
+# FP32 tile schedules and the batched form
+# ---------------------------------------------------------------------------
+
+SCHEDULE_SHAPES = [(20000, 16, 50), (12000, 64, 300), (8000, 128, 40), (6000, 32, 2000)]
+
+
+@pytest.mark.parametrize("n,d,k", SCHEDULE_SHAPES)
+def test_tile_schedules_give_identical_results(n, d, k):
+    """Every (blocks per wave, resident/chunked) schedule of the FP32 tile
+    gives the oracle's labels at every iteration and its centroids."""
+    knor = _knor()
+    X, C0 = _data(n, d, k, "f32", seed=n + k)
+    ref = oracle.mti_fit(X.astype(np.float64), C0, 8, history=True)
+    ran = 0
+    for res in (1, 2):
+        for pb in (1, 2, 4):
+            _print_case(test="schedule", n=n, d=d, k=k, pb=pb, res=res)
+            try:
+                C, lab, st = knor.fit(_dev(X, "f32"), k, C0=_dev(C0, "f64"),
+                                      max_iters=8, history=True,
+                                      tile_blocks=pb, tile_resident=res)
+            except knor.KnorError as e:
+                assert e.code == knor.KNOR_ERR_UNSUPPORTED
+                continue
+            ran += 1
+            hist = st["label_history"].cpu().numpy()
+            for t in range(ref.iters):
+                assert (hist[t] == ref.label_hist[t]).all(), (pb, res, t)
+            assert (C.cpu().numpy() == ref.C).all(), (pb, res)
+    assert ran >= 2
+
+
+def test_autotuned_fit_matches_default():
+    knor = _knor()
+    X, C0 = _data(30000, 32, 64, "f32", seed=9)
+    a = knor.fit(_dev(X, "f32"), 64, C0=_dev(C0, "f64"), max_iters=15)
+    b = knor.fit(_dev(X, "f32"), 64, C0=_dev(C0, "f64"), max_iters=15, autotune=True)
+    assert (a[0] == b[0]).all() and (a[1] == b[1]).all()
+
+
+def test_fit_batched_equals_single_fits():
+    """A batch mixing dtypes, shapes, given and Forgy starts: every problem's
+    result equals knor_fit on it alone, and the oracle's."""
+    knor = _knor()
+    specs = [(9000, 8, 12, "f32", True), (20000, 32, 100, "f32", True),
+             (5000, 3, 5, "f64", True), (7000, 64, 40, "bf16", True),
+             (15000, 16, 30, "f32", False), (3000, 33, 17, "f32", True),
+             (12000, 64, 256, "f32", True), (400, 5, 400, "f32", True),
+             (6000, 128, 20, "bf16", False)]
+    probs, data = [], []
+    for i, (n, d, k, dt, given) in enumerate(specs):
+        X, C0 = _data(n, d, k, dt, seed=100 + i)
+        data.append((X, C0, dt))
+        probs.append(dict(X=_dev(X, dt), k=k, C0=_dev(C0, "f64") if given else None,
+                          max_iters=20))
+    _print_case(test="batched", count=len(probs))
+    out = knor.fit_batched(probs, seed=77)
+    for i, ((X, C0, dt), p, (C, lab, st)) in enumerate(zip(data, probs, out)):
+        single = knor.fit(p["X"], p["k"], C0=p["C0"], init="given" if p["C0"] is not None else "forgy",
+                          seed=77 + i, max_iters=20)
+        assert (C == single[0]).all() and (lab == single[1]).all(), i
+        assert st["iters"] == single[2]["iters"], i
+        if p["C0"] is not None:
+            ref = oracle.mti_fit(workloads.to_f64(X, dt), C0, 20)
+            assert (lab.cpu().numpy() == ref.labels).all(), i
+            assert (C.cpu().numpy() == ref.C).all(), i
+
+
+def test_fit_batched_workload_sample():
+    """Eight instances of the batched-restart workload (n scaled by 1/20),
+    each against the FP64 oracle."""
+    knor = _knor()
+    ws = workloads.batched(8, n_scale=0.05)
+    probs = [dict(X=_dev(w.X, "f32"), k=w.k, C0=_dev(w.C0, "f64"),
+                  max_iters=w.max_iters) for w in ws]
+    out = knor.fit_batched(probs)
+    for w, (C, lab, st) in zip(ws, out):
+        _print_case(test="batched-workload", n=w.n, d=w.d, k=w.k)
+        ref = oracle.mti_fit(w.x64(), w.C0, w.max_iters)
+        assert st["iters"] == ref.iters
+        assert (lab.cpu().numpy() == ref.labels).all()
+        assert (C.cpu().numpy() == ref.C).all()
