@@ -102,6 +102,17 @@ typedef struct {
                            and keeps the fastest; 0: use the table or the
                            default (knor_fit_batched always tunes unless a
                            schedule is forced)                               */
+  int32_t learned;      /* 1: learned candidate proposal on MTI survivors
+                           (needs prune = 1): an MLP d -> 256 -> 256 -> k,
+                           trained with train_batches minibatches of 4096
+                           (x, label) pairs after each of iterations
+                           1..train_iters, proposes 16 candidates per
+                           survivor from iteration train_iters + 1 on; a
+                           survivor takes its nearest candidate c* only if
+                           d(x, c*) (1 + eta) < s(c*), else it is scanned
+                           as usual.  Labels do not depend on this option  */
+  int32_t train_iters;  /* default 5 (when 0)                               */
+  int32_t train_batches;/* default 16 (when 0)                              */
 } knor_opts;
 
 /* Kernel groups timed by opts->profile_ms. */
@@ -114,7 +125,8 @@ enum {
   KNOR_PROF_LEAF = 5,         /* update pass 2: leaf sums (gathers X)         */
   KNOR_PROF_TREE = 6,         /* update pass 2: tree, division, operands      */
   KNOR_PROF_CC = 7,           /* MTI centroid-pair bounds s(c)                */
-  KNOR_NPROF = 8
+  KNOR_PROF_LEARNED = 8,      /* proposal MLP: training, proposal, certificate */
+  KNOR_NPROF = 9
 };
 
 /* Per-iteration counters (columns of opts->iter_counters). */
@@ -124,6 +136,7 @@ enum {
   KNOR_CNT_PRUNED_A = 2,  /* MTI: decided by the drift-updated bound          */
   KNOR_CNT_PRUNED_B = 3,  /* MTI: decided after tightening the bound          */
   KNOR_CNT_RECHECKED = 4, /* points recomputed in FP64                        */
+  KNOR_CNT_CERTIFIED = 5, /* survivors decided by a certified proposal        */
   KNOR_NCOUNTERS = 8
 };
 
@@ -139,6 +152,8 @@ typedef struct {
   double objective;       /* sum over points of D(x, c_label) for the final
                              labels and the centroids they were assigned to  */
   double seconds;         /* wall time of the call                           */
+  int64_t certified;      /* sum of KNOR_CNT_CERTIFIED                       */
+  int64_t mlp_queries;    /* survivors sent to the proposal MLP              */
 } knor_stats;
 
 /* knor_fit: Lloyd's algorithm (Sections "Introduction", "Parallel Lloyd's
@@ -216,6 +231,47 @@ typedef struct {
  * order is returned. */
 knor_status knor_fit_batched(const knor_problem* probs, int32_t count,
                              const knor_opts* opts, knor_stats* st);
+
+/* The proposal MLP on its own (used by knor_fit with opts->learned).  The
+ * network d -> h -> h -> k has ReLU hidden layers; its FP32 parameters are
+ * one DEVICE vector of knor_mlp_param_count(d, h, k) floats: W1 (d x h,
+ * row-major, W1[i][j] joins input i to unit j), b1 (h), W2 (h x h), b2 (h),
+ * W3 (h x k), b3 (k).  Every matrix product rounds its operands to BF16
+ * (nearest even) and sums in FP32.  Limits: 1 <= d <= 256, h in {32, 64,
+ * 128, 256}, 1 <= k <= 16384.  The paper has no such network; it serves
+ * only to choose which survivors of the MTI filter skip the k-way scan. */
+
+/* Number of parameters, or -1 if the sizes are out of range. */
+int64_t knor_mlp_param_count(int32_t d, int32_t h, int32_t k);
+
+/* He-uniform initialisation: W[i][j] = (2u - 1) sqrt(6 / fan_in) with u the
+ * next output z of SplitMix64(seed) as (z >> 11) 2^-53, drawn in parameter
+ * order, computed in FP64 and rounded to FP32; biases zero.  Synchronous. */
+knor_status knor_mlp_init(float* params, int32_t d, int32_t h, int32_t k,
+                          uint64_t seed, const knor_opts* opts);
+
+/* One training step on a minibatch: Xs (DEVICE B x d, standardized inputs),
+ * y (DEVICE B labels in [0, k), not checked on the device).  Computes the
+ * mean softmax cross-entropy and its gradient; if grad_out (DEVICE, param
+ * count floats) is given the gradient is written there; with lr > 0 an Adam
+ * step (beta 0.9 / 0.999, eps 1e-8, bias-corrected at step number `step` >= 1)
+ * updates params, adam_m and adam_v (DEVICE, param count floats each).
+ * loss_out (HOST) receives the loss; the call then returns after the step
+ * completes, otherwise it is asynchronous on opts->stream. */
+knor_status knor_mlp_train_step(float* params, float* adam_m, float* adam_v,
+                                int64_t step, int32_t d, int32_t h, int32_t k,
+                                const float* Xs, const int32_t* y, int32_t B,
+                                float lr, float* grad_out, double* loss_out,
+                                const knor_opts* opts);
+
+/* Candidates of m standardized points Xs (DEVICE m x d): cand_out (DEVICE
+ * m x 16 int32) row p holds, for each of 16 fixed class subsets (class j is
+ * in subset 4 ((j mod 16) div 4) + ((j div 16) mod 4)), the class with the
+ * largest logit (earliest on ties), or -1 for a subset without classes.
+ * Asynchronous on opts->stream. */
+knor_status knor_mlp_propose(const float* params, int32_t d, int32_t h,
+                             int32_t k, const float* Xs, int64_t m,
+                             int32_t* cand_out, const knor_opts* opts);
 
 /* Human-readable name of a status code (static storage). */
 const char* knor_status_string(knor_status s);

@@ -19,7 +19,8 @@ import ctypes
 import os
 
 __all__ = ["fit", "fit_batched", "assign", "update", "load", "KnorError",
-           "COUNTERS", "library_path"]
+           "COUNTERS", "library_path", "mlp_param_count", "mlp_init",
+           "mlp_train_step", "mlp_propose"]
 
 _PKG = os.path.dirname(os.path.abspath(__file__))
 _LIB = os.path.join(_PKG, "libknor.so")
@@ -28,7 +29,8 @@ KNOR_OK, KNOR_ERR_INVALID_ARG, KNOR_ERR_OUT_OF_MEMORY, KNOR_ERR_HIP, \
     KNOR_ERR_NUMERIC, KNOR_ERR_UNSUPPORTED = range(6)
 INIT_GIVEN, INIT_FORGY = 0, 1
 NCOUNTERS = 8
-COUNTERS = ("changed", "scanned", "pruned_a", "pruned_b", "rechecked")
+COUNTERS = ("changed", "scanned", "pruned_a", "pruned_b", "rechecked",
+            "certified")
 
 
 class KnorError(RuntimeError):
@@ -50,12 +52,15 @@ class Opts(ctypes.Structure):
                 ("profile_mask", ctypes.c_int32),
                 ("tile_blocks", ctypes.c_int32),
                 ("tile_resident", ctypes.c_int32),
-                ("autotune", ctypes.c_int32)]
+                ("autotune", ctypes.c_int32),
+                ("learned", ctypes.c_int32),
+                ("train_iters", ctypes.c_int32),
+                ("train_batches", ctypes.c_int32)]
 
 
-NPROF = 8
+NPROF = 9
 PROF_GROUPS = ("assign_dense", "assign_list", "recheck", "filter", "sort",
-               "leaf", "tree", "cc")
+               "leaf", "tree", "cc", "learned")
 
 
 class Problem(ctypes.Structure):
@@ -72,7 +77,8 @@ class Stats(ctypes.Structure):
                 ("dists_computed", ctypes.c_int64),
                 ("scanned", ctypes.c_int64), ("pruned_a", ctypes.c_int64),
                 ("pruned_b", ctypes.c_int64), ("rechecked", ctypes.c_int64),
-                ("objective", ctypes.c_double), ("seconds", ctypes.c_double)]
+                ("objective", ctypes.c_double), ("seconds", ctypes.c_double),
+                ("certified", ctypes.c_int64), ("mlp_queries", ctypes.c_int64)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -108,6 +114,16 @@ def load():
     L.knor_fit_batched.argtypes = [ctypes.POINTER(Problem), i32,
                                    ctypes.POINTER(Opts), ctypes.POINTER(Stats)]
     L.knor_fit_batched.restype = ctypes.c_int
+    L.knor_mlp_param_count.argtypes = [i32, i32, i32]
+    L.knor_mlp_param_count.restype = i64
+    L.knor_mlp_init.argtypes = [P, i32, i32, i32, ctypes.c_uint64, ctypes.POINTER(Opts)]
+    L.knor_mlp_init.restype = ctypes.c_int
+    L.knor_mlp_train_step.argtypes = [P, P, P, i64, i32, i32, i32, P, P, i32,
+                                      ctypes.c_float, P, ctypes.POINTER(ctypes.c_double),
+                                      ctypes.POINTER(Opts)]
+    L.knor_mlp_train_step.restype = ctypes.c_int
+    L.knor_mlp_propose.argtypes = [P, i32, i32, i32, P, i64, P, ctypes.POINTER(Opts)]
+    L.knor_mlp_propose.restype = ctypes.c_int
     L.knor_status_string.argtypes = [ctypes.c_int]
     L.knor_status_string.restype = ctypes.c_char_p
     L.knor_version.restype = ctypes.c_int32
@@ -143,7 +159,7 @@ def _raise(rc):
 def _opts(prune=True, recheck=1, check_numeric=True, seed=0, stream=None,
           workspace_cap=0, label_history=None, iter_counters=None,
           poll_every=0, profile=None, tile_blocks=0, tile_resident=0,
-          autotune=False):
+          autotune=False, learned=False, train_iters=0, train_batches=0):
     torch = _torch()
     if stream is None:
         stream = torch.cuda.current_stream()
@@ -166,13 +182,17 @@ def _opts(prune=True, recheck=1, check_numeric=True, seed=0, stream=None,
     o.tile_blocks = int(tile_blocks)
     o.tile_resident = int(tile_resident)
     o.autotune = 1 if autotune else 0
+    o.learned = 1 if learned else 0
+    o.train_iters = int(train_iters)
+    o.train_batches = int(train_batches)
     return o
 
 
 def fit(X, k, C0=None, init="given", max_iters=100, tol=0.0, prune=True,
         recheck=1, seed=0, history=False, counters=False, out=None,
         check_numeric=True, workspace_cap=0, poll_every=0, profile=None,
-        tile_blocks=0, tile_resident=0, autotune=False):
+        tile_blocks=0, tile_resident=0, autotune=False, learned=False,
+        train_iters=0, train_batches=0):
     """Lloyd's k-means on the GPU.  Returns (C, labels, stats dict).
 
     history=True adds stats["label_history"]: (iters, n) int32 CUDA tensor of
@@ -184,7 +204,9 @@ def fit(X, k, C0=None, init="given", max_iters=100, tol=0.0, prune=True,
     on the launch stream.  tile_blocks / tile_resident force an FP32 tile
     schedule (1, 2 or 4 blocks of 16 points per wave; 1 resident, 2
     chunked); autotune=True times the schedules of this (d, k) class once
-    per process.  No schedule changes the results."""
+    per process.  No schedule changes the results.  learned=True adds the
+    certified MLP candidate proposal on MTI survivors (train_iters /
+    train_batches: 0 = library defaults); it never changes the results."""
     torch = _torch()
     import numpy as np
     L = load()
@@ -207,7 +229,8 @@ def fit(X, k, C0=None, init="given", max_iters=100, tol=0.0, prune=True,
     hist = torch.empty((max_iters, n), dtype=torch.int32, device=dev) if history else None
     cnt = np.zeros((max_iters, NCOUNTERS), np.int64) if counters else None
     o = _opts(prune, recheck, check_numeric, seed, None, workspace_cap, hist,
-              cnt, poll_every, profile, tile_blocks, tile_resident, autotune)
+              cnt, poll_every, profile, tile_blocks, tile_resident, autotune,
+              learned, train_iters, train_batches)
     st = Stats()
     rc = L.knor_fit(X.data_ptr(), _dtype_code(X), n, d, k, init_code, c0p,
                     max_iters, float(tol), ctypes.byref(o), C.data_ptr(),
@@ -296,3 +319,52 @@ def update(X, labels, C_prev):
                        cnt.data_ptr())
     _raise(rc)
     return C, cnt
+
+
+# ---------------------------------------------------------------------------
+# the proposal MLP on its own
+# ---------------------------------------------------------------------------
+
+def mlp_param_count(d, h, k):
+    return int(load().knor_mlp_param_count(d, h, k))
+
+
+def mlp_init(d, h, k, seed, device="cuda"):
+    """FP32 parameter vector (CUDA tensor) with the library's initialisation."""
+    torch = _torch()
+    L = load()
+    P = mlp_param_count(d, h, k)
+    if P < 0:
+        raise ValueError("MLP sizes out of range")
+    th = torch.empty((P,), dtype=torch.float32, device=device)
+    _raise(L.knor_mlp_init(th.data_ptr(), d, h, k, int(seed), ctypes.byref(_opts())))
+    return th
+
+
+def mlp_train_step(params, m, v, step, d, h, k, Xs, y, lr=1e-3, grad=None):
+    """One training step; returns the minibatch loss (params, m, v updated in
+    place when lr > 0; grad, if given, receives the gradient)."""
+    torch = _torch()
+    L = load()
+    for t, nm in ((params, "params"), (Xs, "Xs"), (y, "y")):
+        _check_dev(t, nm)
+    loss = ctypes.c_double(0.0)
+    rc = L.knor_mlp_train_step(params.data_ptr(), m.data_ptr() if m is not None else None,
+                               v.data_ptr() if v is not None else None, int(step), d, h, k,
+                               Xs.data_ptr(), y.data_ptr(), int(Xs.shape[0]), float(lr),
+                               grad.data_ptr() if grad is not None else None,
+                               ctypes.byref(loss), ctypes.byref(_opts()))
+    _raise(rc)
+    return loss.value
+
+
+def mlp_propose(params, d, h, k, Xs):
+    """(m, 16) int32 CUDA tensor of candidate classes."""
+    torch = _torch()
+    L = load()
+    _check_dev(Xs, "Xs")
+    m = int(Xs.shape[0])
+    cand = torch.empty((m, 16), dtype=torch.int32, device=Xs.device)
+    _raise(L.knor_mlp_propose(params.data_ptr(), d, h, k, Xs.data_ptr(), m,
+                              cand.data_ptr(), ctypes.byref(_opts())))
+    return cand

@@ -82,6 +82,21 @@ hipError_t launch_copy_i32(const int32_t* a, int32_t* b, int64_t count,
   return hipGetLastError();
 }
 
+__global__ void gather_i32_kernel(const int32_t* __restrict__ a,
+                                  const int* __restrict__ rows, int64_t count,
+                                  int32_t* __restrict__ out) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) out[i] = a[rows[i]];
+}
+
+static hipError_t launch_gather_i32(const int32_t* a, const int* rows, int64_t count,
+                                    int32_t* out, hipStream_t s) {
+  if (count == 0) return hipSuccess;
+  hipLaunchKernelGGL(gather_i32_kernel, dim3((count + 255) / 256), dim3(256), 0, s, a,
+                     rows, count, out);
+  return hipGetLastError();
+}
+
 template <typename T>
 __global__ void gather_rows_kernel(const T* __restrict__ X, int d,
                                    const int64_t* __restrict__ rows, int k,
@@ -204,6 +219,7 @@ struct Opts {
   int64_t* profile_launches = nullptr;
   int profile_mask = 0;
   int tile_blocks = 0, tile_resident = 0, autotune = 0;
+  int learned = 0, train_iters = 5, train_batches = 16;
 };
 
 static knor_status read_opts(const knor_opts* o, Opts* out) {
@@ -230,6 +246,12 @@ static knor_status read_opts(const knor_opts* o, Opts* out) {
     return KNOR_ERR_INVALID_ARG;
   if (o->tile_resident < 0 || o->tile_resident > 2) return KNOR_ERR_INVALID_ARG;
   if (o->autotune < 0 || o->autotune > 1) return KNOR_ERR_INVALID_ARG;
+  if (o->learned < 0 || o->learned > 1 || o->train_iters < 0 ||
+      o->train_batches < 0)
+    return KNOR_ERR_INVALID_ARG;
+  out->learned = o->learned;
+  if (o->train_iters > 0) out->train_iters = o->train_iters;
+  if (o->train_batches > 0) out->train_batches = o->train_batches;
   out->tile_blocks = o->tile_blocks;
   out->tile_resident = o->tile_resident;
   out->autotune = o->autotune;
@@ -481,6 +503,41 @@ static knor_status fit_impl(const void* X, knor_dtype dt, int64_t n, int d,
   ar.add((void**)&dist2, sizeof(double) * (size_t)n);
   ar.add((void**)&sumtmp, sizeof(double) * (size_t)(n / kLeaf + 2));
   ar.add((void**)&objective, sizeof(double));
+  // learned proposal (MTI survivors only)
+  const bool learned = o.learned && mti;
+  const int hM = kMlpHidden;
+  const int kpadM = (k + 63) / 64 * 64;
+  const int Bt = n < kMlpBatch ? (int)n : kMlpBatch;
+  const int64_t chunk = n < kMlpChunk ? n : kMlpChunk;
+  MlpLayout ML{};
+  float *th = nullptr, *am = nullptr, *av = nullptr, *grad = nullptr, *Xs_tr = nullptr;
+  float *Xs_s = nullptr, *H1 = nullptr, *H2 = nullptr;
+  int32_t *y_tr = nullptr, *cand = nullptr;
+  int *rows_tr = nullptr, *dense = nullptr, *seg_off = nullptr, *list2 = nullptr,
+      *seg_cnt2 = nullptr;
+  void* mlp_ws = nullptr;
+  double *mean = nullptr, *istd = nullptr, *loss_dev = nullptr;
+  uint16_t* W3t = nullptr;
+  if (learned) {
+    ML = mlp_layout(d, hM, k);
+    for (float** q : {&th, &am, &av, &grad}) ar.add((void**)q, sizeof(float) * (size_t)ML.P);
+    ar.add(&mlp_ws, mlp_train_workspace(d, hM, k, Bt));
+    ar.add((void**)&Xs_tr, sizeof(float) * (size_t)Bt * d);
+    ar.add((void**)&y_tr, sizeof(int32_t) * (size_t)Bt);
+    ar.add((void**)&rows_tr, sizeof(int) * (size_t)Bt * o.train_batches);
+    ar.add((void**)&mean, sizeof(double) * (size_t)d);
+    ar.add((void**)&istd, sizeof(double) * (size_t)d);
+    ar.add((void**)&loss_dev, sizeof(double));
+    ar.add((void**)&W3t, sizeof(uint16_t) * (size_t)kpadM * hM);
+    ar.add((void**)&dense, sizeof(int) * (size_t)n);
+    ar.add((void**)&seg_off, sizeof(int) * (size_t)(nseg + 1));
+    ar.add((void**)&list2, sizeof(int) * (size_t)nseg * kSeg);
+    ar.add((void**)&seg_cnt2, sizeof(int) * (size_t)nseg);
+    ar.add((void**)&Xs_s, sizeof(float) * (size_t)chunk * d);
+    ar.add((void**)&H1, sizeof(float) * (size_t)chunk * hM);
+    ar.add((void**)&H2, sizeof(float) * (size_t)chunk * hM);
+    ar.add((void**)&cand, sizeof(int32_t) * (size_t)n * kMlpTop);
+  }
   knor_status rs = ar.alloc(s, o.cap);
   if (rs != KNOR_OK) return rs;
   update_plan_init(&plan, n, k, d, upd_ws);
@@ -518,6 +575,17 @@ static knor_status fit_impl(const void* X, knor_dtype dt, int64_t n, int d,
   HIPCHK(launch_prep_centroids(ops, s));
   HIPCHK(launch_fill_i32(labels_out, n, -1, s));   // every label changes at t = 0
   HIPCHK(launch_fill_i32(dirty, k, 1, s));         // every cluster is summed at t = 0
+  if (learned) {
+    HIPCHK(launch_standardize_stats(X, dt, n, d, mean, istd, s));
+    std::vector<float> th0 = mlp_init_host(d, hM, k, o.seed);
+    HIPCHK(hipMemcpyAsync(th, th0.data(), sizeof(float) * th0.size(),
+                          hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemsetAsync(am, 0, sizeof(float) * (size_t)ML.P, s));
+    HIPCHK(hipMemsetAsync(av, 0, sizeof(float) * (size_t)ML.P, s));
+    HIPCHK(hipStreamSynchronize(s));          // `th0` leaves scope
+  }
+  int64_t mlp_step = 0, mlp_queries = 0;
+  bool w3t_ready = false;
 
   Prof prof;
   prof.stream = s;
@@ -544,12 +612,65 @@ static knor_status fit_impl(const void* X, knor_dtype dt, int64_t n, int d,
       job.seg_cnt = seg_cnt;
       job.nseg = nseg;
     }
+    if (learned && seg && t > o.train_iters) {
+      prof.begin(KNOR_PROF_LEARNED);
+      if (!w3t_ready) {
+        HIPCHK(launch_mlp_w3t(th + ML.W3, hM, k, kpadM, W3t, s));
+        w3t_ready = true;
+      }
+      HIPCHK(launch_seg_dense(list, seg_cnt, nseg, seg_off, dense, conv, t, s));
+      int hm[2] = {0, 0};
+      HIPCHK(hipMemcpyAsync(&hm[0], seg_off + nseg, sizeof(int), hipMemcpyDeviceToHost, s));
+      HIPCHK(hipMemcpyAsync(&hm[1], conv, sizeof(int), hipMemcpyDeviceToHost, s));
+      HIPCHK(hipStreamSynchronize(s));
+      if (hm[1] == kNotConverged) {
+        const int m_tot = hm[0];
+        mlp_queries += m_tot;
+        for (int64_t c0 = 0; c0 < m_tot; c0 += chunk) {
+          const int cnt = (int)(m_tot - c0 < chunk ? m_tot - c0 : chunk);
+          HIPCHK(launch_gather_std(X, dt, d, dense + c0, cnt, nullptr, mean, istd, Xs_s, s));
+          GemmArgs g1{};
+          g1.A = Xs_s; g1.lda = d; g1.B = th + ML.W1; g1.ldb = hM; g1.C = H1; g1.ldc = hM;
+          g1.M = cnt; g1.N = hM; g1.K = d; g1.bias = th + ML.b1; g1.relu = 1;
+          HIPCHK(launch_gemm_bf16(g1, s));
+          GemmArgs g2 = g1;
+          g2.A = H1; g2.lda = hM; g2.B = th + ML.W2; g2.C = H2; g2.K = hM; g2.bias = th + ML.b2;
+          HIPCHK(launch_gemm_bf16(g2, s));
+          HIPCHK(launch_mlp_propose(H2, W3t, th + ML.b3, hM, k, kpadM, cnt, nullptr,
+                                    cand + c0 * kMlpTop, s));
+        }
+        HIPCHK(launch_mlp_certify(X, dt, d, C_out, s_half, list, seg_cnt, seg_off, nseg,
+                                  cand, labels_out, u, dirty, list2, seg_cnt2, row, conv,
+                                  t, s));
+        job.list = list2;
+        job.seg_cnt = seg_cnt2;
+      }
+      prof.end();
+    }
     prof.begin(seg ? KNOR_PROF_ASSIGN_LIST : KNOR_PROF_ASSIGN_DENSE);
     HIPCHK(launch_assign(ops, job, s));
     prof.end();
     if (dt != KNOR_F64) {
       prof.begin(KNOR_PROF_RECHECK);
       HIPCHK(launch_recheck(ops, job, s));
+      prof.end();
+    }
+    if (learned && t >= 1 && t <= o.train_iters) {
+      // one pass of train_batches minibatches on (x, this iteration's label)
+      prof.begin(KNOR_PROF_LEARNED);
+      std::vector<int> rows((size_t)Bt * o.train_batches);
+      uint64_t st_r = o.seed ^ (0x9e3779b97f4a7c15ull * (uint64_t)(t + 1));
+      for (auto& r : rows) r = (int)(splitmix64(&st_r) % (uint64_t)n);
+      HIPCHK(hipMemcpyAsync(rows_tr, rows.data(), sizeof(int) * rows.size(),
+                            hipMemcpyHostToDevice, s));
+      for (int b = 0; b < o.train_batches; ++b) {
+        const int* rb = rows_tr + (size_t)b * Bt;
+        HIPCHK(launch_gather_std(X, dt, d, rb, Bt, nullptr, mean, istd, Xs_tr, s));
+        HIPCHK(launch_gather_i32(labels_out, rb, Bt, y_tr, s));
+        HIPCHK(mlp_train_step(th, am, av, ++mlp_step, ML, Xs_tr, y_tr, Bt, kMlpLr, grad,
+                              mlp_ws, loss_dev, s));
+      }
+      HIPCHK(hipStreamSynchronize(s));        // `rows` leaves scope
       prof.end();
     }
     if (o.label_history)
@@ -595,6 +716,7 @@ static knor_status fit_impl(const void* X, knor_dtype dt, int64_t n, int d,
       dst[KNOR_CNT_PRUNED_A] = (int64_t)r[ROW_PRUNED_A];
       dst[KNOR_CNT_PRUNED_B] = (int64_t)r[ROW_PRUNED_B];
       dst[KNOR_CNT_RECHECKED] = (int64_t)r[ROW_FLAG_HEAD];
+      dst[KNOR_CNT_CERTIFIED] = (int64_t)r[ROW_CERTIFIED];
     }
   if (st) {
     memset(st, 0, sizeof(*st));
@@ -607,9 +729,11 @@ static knor_status fit_impl(const void* X, knor_dtype dt, int64_t n, int d,
       st->pruned_a += (int64_t)r[ROW_PRUNED_A];
       st->pruned_b += (int64_t)r[ROW_PRUNED_B];
       st->rechecked += (int64_t)r[ROW_FLAG_HEAD];
+      st->certified += (int64_t)r[ROW_CERTIFIED];
       const int64_t tighten = (mti && i > 0) ? (n - (int64_t)r[ROW_PRUNED_A]) : 0;
       st->dists_computed += ((int64_t)r[ROW_SCANNED] + (int64_t)r[ROW_FLAG_HEAD]) * k + tighten;
     }
+    st->mlp_queries = mlp_queries;
     st->objective = hobj;
     st->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   }
@@ -621,6 +745,92 @@ static knor_status fit_impl(const void* X, knor_dtype dt, int64_t n, int d,
 using namespace knor;
 
 extern "C" {
+
+static bool mlp_sizes_ok(int32_t d, int32_t h, int32_t k) {
+  return d >= 1 && d <= kMaxD && (h == 32 || h == 64 || h == 128 || h == 256) &&
+         k >= 1 && k <= kMaxK;
+}
+
+int64_t knor_mlp_param_count(int32_t d, int32_t h, int32_t k) {
+  return mlp_sizes_ok(d, h, k) ? mlp_layout(d, h, k).P : -1;
+}
+
+knor_status knor_mlp_init(float* params, int32_t d, int32_t h, int32_t k,
+                          uint64_t seed, const knor_opts* opts) {
+  Opts o;
+  if (knor_status r = read_opts(opts, &o)) return r;
+  if (!params || !mlp_sizes_ok(d, h, k)) return KNOR_ERR_INVALID_ARG;
+  std::vector<float> th = mlp_init_host(d, h, k, seed);
+  HIPCHK(hipMemcpyAsync(params, th.data(), sizeof(float) * th.size(),
+                        hipMemcpyHostToDevice, o.stream));
+  HIPCHK(hipStreamSynchronize(o.stream));
+  return KNOR_OK;
+}
+
+knor_status knor_mlp_train_step(float* params, float* adam_m, float* adam_v,
+                                int64_t step, int32_t d, int32_t h, int32_t k,
+                                const float* Xs, const int32_t* y, int32_t B,
+                                float lr, float* grad_out, double* loss_out,
+                                const knor_opts* opts) {
+  Opts o;
+  if (knor_status r = read_opts(opts, &o)) return r;
+  if (!params || !Xs || !y || !mlp_sizes_ok(d, h, k) || B < 1 || !(lr >= 0.0f))
+    return KNOR_ERR_INVALID_ARG;
+  if (lr > 0.0f && (!adam_m || !adam_v || step < 1)) return KNOR_ERR_INVALID_ARG;
+  const MlpLayout L = mlp_layout(d, h, k);
+  hipStream_t s = o.stream;
+  float* grad = grad_out;
+  void* ws = nullptr;
+  double* loss_dev = nullptr;
+  Arena ar;
+  if (!grad) ar.add((void**)&grad, sizeof(float) * (size_t)L.P);
+  ar.add(&ws, mlp_train_workspace(d, h, k, B));
+  ar.add((void**)&loss_dev, sizeof(double));
+  if (knor_status r = ar.alloc(s, o.cap)) return r;
+  HIPCHK(mlp_train_step(params, adam_m, adam_v, step, L, Xs, y, B, lr, grad, ws,
+                        loss_dev, s));
+  if (loss_out) {
+    HIPCHK(hipMemcpyAsync(loss_out, loss_dev, sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+  }
+  return KNOR_OK;
+}
+
+knor_status knor_mlp_propose(const float* params, int32_t d, int32_t h,
+                             int32_t k, const float* Xs, int64_t m,
+                             int32_t* cand_out, const knor_opts* opts) {
+  Opts o;
+  if (knor_status r = read_opts(opts, &o)) return r;
+  if (!params || !Xs || !cand_out || !mlp_sizes_ok(d, h, k) || m < 0 ||
+      m >= ((int64_t)1 << 31))
+    return KNOR_ERR_INVALID_ARG;
+  if (m == 0) return KNOR_OK;
+  const MlpLayout L = mlp_layout(d, h, k);
+  const int kpad = (k + 63) / 64 * 64;
+  const int64_t chunk = m < kMlpChunk ? m : kMlpChunk;
+  hipStream_t s = o.stream;
+  float *H1 = nullptr, *H2 = nullptr;
+  uint16_t* W3t = nullptr;
+  Arena ar;
+  ar.add((void**)&H1, sizeof(float) * (size_t)chunk * h);
+  ar.add((void**)&H2, sizeof(float) * (size_t)chunk * h);
+  ar.add((void**)&W3t, sizeof(uint16_t) * (size_t)kpad * h);
+  if (knor_status r = ar.alloc(s, o.cap)) return r;
+  HIPCHK(launch_mlp_w3t(params + L.W3, h, k, kpad, W3t, s));
+  for (int64_t c0 = 0; c0 < m; c0 += chunk) {
+    const int cnt = (int)(m - c0 < chunk ? m - c0 : chunk);
+    GemmArgs g1{};
+    g1.A = Xs + c0 * d; g1.lda = d; g1.B = params + L.W1; g1.ldb = h; g1.C = H1;
+    g1.ldc = h; g1.M = cnt; g1.N = h; g1.K = d; g1.bias = params + L.b1; g1.relu = 1;
+    HIPCHK(launch_gemm_bf16(g1, s));
+    GemmArgs g2 = g1;
+    g2.A = H1; g2.lda = h; g2.B = params + L.W2; g2.C = H2; g2.K = h; g2.bias = params + L.b2;
+    HIPCHK(launch_gemm_bf16(g2, s));
+    HIPCHK(launch_mlp_propose(H2, W3t, params + L.b3, h, k, kpad, cnt, nullptr,
+                              cand_out + c0 * kMlpTop, s));
+  }
+  return KNOR_OK;
+}
 
 const char* knor_status_string(knor_status s) {
   switch (s) {

@@ -36,8 +36,9 @@ enum {
   SLOT_CHANGED = 0,                          // labels changed
   SLOT_FLAGGED = 1,                          // points sent to the FP64 recheck
   SLOT_CAND = 2,                             // MTI stage-A candidates
-  SLOT_SURV = 3,                             // MTI survivors (tile scans)
-  NSLOTQ = 4,
+  SLOT_SURV = 3,                             // MTI survivors
+  SLOT_CERTIFIED = 4,                        // survivors certified by a proposal
+  NSLOTQ = 5,
   ROW_CHANGED = NSLOTQ * kChgSlots * kSlotStride,   // totals
   ROW_SCANNED = ROW_CHANGED + 1,
   ROW_PRUNED_A = ROW_CHANGED + 2,
@@ -45,6 +46,8 @@ enum {
   ROW_FLAG_HEAD = ROW_CHANGED + 4,           // FP64 rechecked points
   ROW_TIGHTEN = ROW_CHANGED + 5,             // 1 if stage B ran
   ROW_TIGHTEN_NEXT = ROW_CHANGED + 6,        // 1: run stage B next iteration
+  ROW_CERTIFIED = ROW_CHANGED + 7,           // survivors decided by a proposal
+  ROW_SURVIVED = ROW_CHANGED + 8,            // survivors of the MTI filter
   ROW_STRIDE = ROW_CHANGED + 16
 };
 
@@ -369,6 +372,59 @@ hipError_t launch_copy_i32(const int32_t* src, int32_t* dst, int64_t count,
 hipError_t launch_gather_rows(const void* X, knor_dtype dt, int d,
                               const int64_t* rows, int k, double* C64,
                               hipStream_t s);
+
+// Matrix product on the BF16 matrix cores (learned.hip):
+// C[M x N] = op(A)[M x K] op(B)[K x N] (+ bias[N]) (ReLU) (masked by
+// mask > 0); op = transpose when the flag is set; FP32 in memory, operands
+// rounded to BF16 (nearest even), FP32 sums.  Mdev: rows = min(M, *Mdev).
+struct GemmArgs {
+  const float* A; int lda; int transA;
+  const float* B; int ldb; int transB;
+  float* C; int ldc;
+  int M, N, K;
+  const int* Mdev;
+  const float* bias;
+  int relu;
+  const float* mask; int ldm;
+};
+hipError_t launch_gemm_bf16(const GemmArgs& g, hipStream_t s);
+
+// The proposal MLP d -> h -> h -> k: offsets of W1 (d x h), b1, W2 (h x h),
+// b2, W3 (h x k), b3 in the flat FP32 parameter vector of P entries.
+struct MlpLayout {
+  int d, h, k;
+  int64_t W1, b1, W2, b2, W3, b3, P;
+};
+MlpLayout mlp_layout(int d, int h, int k);
+size_t mlp_train_workspace(int d, int h, int k, int B);
+hipError_t mlp_train_step(float* th, float* am, float* av, int64_t step,
+                          const MlpLayout& L, const float* Xs, const int32_t* y,
+                          int B, float lr, float* grad, void* ws, double* loss_dev,
+                          hipStream_t s);
+hipError_t launch_mlp_w3t(const float* W3, int h, int k, int kpad, uint16_t* W3t,
+                          hipStream_t s);
+hipError_t launch_mlp_propose(const float* H2, const uint16_t* W3t, const float* b3,
+                              int h, int k, int kpad, int m, const int* mdev,
+                              int32_t* cand, hipStream_t s);
+hipError_t launch_standardize_stats(const void* X, knor_dtype dt, int64_t n, int d,
+                                    double* mean, double* istd, hipStream_t s);
+hipError_t launch_gather_std(const void* X, knor_dtype dt, int d, const int* rows,
+                             int64_t count, const int* cdev, const double* mean,
+                             const double* istd, float* Xs, hipStream_t s);
+hipError_t launch_seg_dense(const int* list, const int* seg_cnt, int nseg, int* seg_off,
+                            int* dense, const int* conv, int iter, hipStream_t s);
+hipError_t launch_mlp_certify(const void* X, knor_dtype dt, int d, const double* C64,
+                              const float* s_half, const int* list, const int* seg_cnt,
+                              const int* seg_off, int nseg, const int32_t* cand,
+                              int32_t* labels, float* u, int* dirty, int* list2,
+                              int* seg_cnt2, unsigned long long* row, const int* conv,
+                              int iter, hipStream_t s);
+constexpr int kMlpTop = 16;          // candidates per point
+constexpr int kMlpHidden = 256;      // hidden width inside knor_fit
+constexpr int kMlpBatch = 4096;      // training minibatch inside knor_fit
+constexpr int64_t kMlpChunk = 1 << 20;   // proposal rows per pass
+constexpr float kMlpLr = 1e-3f;
+std::vector<float> mlp_init_host(int d, int h, int k, uint64_t seed);
 
 // padded row length of the BF16 tile: a power of two, at least one K-step
 inline int pad_dim_bf16(int d) {

@@ -596,8 +596,10 @@ __global__ __launch_bounds__(256) void tree_finalize(
     }
     row[ROW_CHANGED] = tot[SLOT_CHANGED];
     row[ROW_FLAG_HEAD] = tot[SLOT_FLAGGED];
+    row[ROW_CERTIFIED] = tot[SLOT_CERTIFIED];
     if (ctl.segmented) {
-      row[ROW_SCANNED] = tot[SLOT_SURV];
+      row[ROW_SURVIVED] = tot[SLOT_SURV];
+      row[ROW_SCANNED] = tot[SLOT_SURV] - tot[SLOT_CERTIFIED];
       row[ROW_PRUNED_A] = (unsigned long long)ctl.n - tot[SLOT_CAND];
       row[ROW_PRUNED_B] = tot[SLOT_CAND] - tot[SLOT_SURV];
       // keep tightening while it prunes at least 1/16 of its candidates

@@ -402,3 +402,119 @@ def test_fit_batched_workload_sample():
         assert st["iters"] == ref.iters
         assert (lab.cpu().numpy() == ref.labels).all()
         assert (C.cpu().numpy() == ref.C).all()
+
+
+# ---------------------------------------------------------------------------
+# learned candidate proposal
+# ---------------------------------------------------------------------------
+
+def _mlp_case(d, h, k, B, seed):
+    from oracle import mlp
+    rng = np.random.default_rng(seed)
+    th = mlp.init_params(d, h, k, seed) + rng.normal(size=mlp.param_count(d, h, k)) * 0.02
+    th = th.astype(np.float32).astype(np.float64)
+    Xs = rng.normal(size=(B, d)).astype(np.float32).astype(np.float64)
+    y = rng.integers(0, k, size=B).astype(np.int32)
+    return th, Xs, y
+
+
+def test_mlp_init_matches_reference():
+    from oracle import mlp
+    knor = _knor()
+    for (d, h, k, seed) in [(8, 32, 64, 5), (32, 256, 4096, 1)]:
+        th = knor.mlp_init(d, h, k, seed).cpu().numpy()
+        assert (th == mlp.init_params(d, h, k, seed).astype(np.float32)).all()
+
+
+@pytest.mark.parametrize("d,h,k,B", [(8, 32, 64, 96), (32, 256, 4096, 512), (5, 64, 100, 130)])
+def test_mlp_gradient_matches_reference(d, h, k, B):
+    """Loss and gradient against the FP64 reference on the same BF16-rounded
+    operands.  The GPU sums in FP32 (relative error ~K 2^-24, K <= 4096) and
+    a hidden activation within that error of a BF16 rounding boundary can
+    round one BF16 ulp (2^-8) the other way; both effects stay far below the
+    normwise bound 2e-3 used here, while a wrong index, transpose or term
+    gives errors of order one."""
+    import torch
+    from oracle import mlp
+    knor = _knor()
+    th, Xs, y = _mlp_case(d, h, k, B, seed=d + h + k)
+    loss_o, g_o = mlp.loss_and_grad(th, Xs, y, d, h, k, use_bf16=True)
+    P = th.size
+    thd = torch.from_numpy(th.astype(np.float32)).cuda()
+    grad = torch.zeros(P, dtype=torch.float32, device="cuda")
+    m = torch.zeros(P, dtype=torch.float32, device="cuda")
+    v = torch.zeros(P, dtype=torch.float32, device="cuda")
+    loss = knor.mlp_train_step(thd, m, v, 1, d, h, k,
+                               torch.from_numpy(Xs.astype(np.float32)).cuda(),
+                               torch.from_numpy(y).cuda(), lr=0.0, grad=grad)
+    assert abs(loss - loss_o) <= 1e-4 * abs(loss_o)
+    g = grad.cpu().numpy().astype(np.float64)
+    G, Go = mlp.unflatten(g, d, h, k), mlp.unflatten(g_o, d, h, k)
+    for name in Go:
+        err = np.linalg.norm(G[name] - Go[name]) / max(np.linalg.norm(Go[name]), 1e-30)
+        assert err <= 2e-3, (name, err)
+    # one Adam step, against FP64 Adam applied to the GPU's own gradient
+    loss2 = knor.mlp_train_step(thd, m, v, 1, d, h, k,
+                                torch.from_numpy(Xs.astype(np.float32)).cuda(),
+                                torch.from_numpy(y).cuda(), lr=1e-3, grad=grad)
+    assert loss2 == loss
+    g = grad.cpu().numpy().astype(np.float64)
+    want, m_o, v_o = mlp.adam_step(th, np.zeros(P), np.zeros(P), g, 1)
+    assert np.allclose(thd.cpu().numpy(), want, rtol=2e-6, atol=1e-7)
+    assert np.allclose(m.cpu().numpy(), m_o, rtol=1e-6, atol=1e-30)
+    assert np.allclose(v.cpu().numpy(), v_o, rtol=1e-5, atol=1e-30)
+
+
+@pytest.mark.parametrize("d,h,k,m", [(8, 32, 64, 300), (32, 256, 4096, 700), (16, 64, 100, 257)])
+def test_mlp_propose_matches_reference(d, h, k, m):
+    """Candidates are the per-subset argmax logits; wherever a subset's two
+    largest reference logits differ by more than the FP32-summation
+    tolerance, the GPU must pick the same class."""
+    import torch
+    from oracle import mlp
+    knor = _knor()
+    th, Xs, _ = _mlp_case(d, h, k, m, seed=7 * d + k)
+    _, _, z = mlp.forward(th, Xs, d, h, k, use_bf16=True)
+    cand = knor.mlp_propose(torch.from_numpy(th.astype(np.float32)).cuda(), d, h, k,
+                            torch.from_numpy(Xs.astype(np.float32)).cuda()).cpu().numpy()
+    j = np.arange(k)
+    subset = 4 * ((j % 16) // 4) + (j // 16) % 4
+    compared = agree = 0
+    for sidx in range(16):
+        cls = j[subset == sidx]
+        if cls.size == 0:
+            assert (cand[:, sidx] == -1).all()
+            continue
+        zs = z[:, cls]
+        order = np.argsort(-zs, axis=1, kind="stable")
+        top1 = zs[np.arange(m), order[:, 0]]
+        top2 = zs[np.arange(m), order[:, 1]] if cls.size > 1 else np.full(m, -np.inf)
+        tol = 1e-3 * (np.abs(top1) + 1.0)
+        clear = (top1 - top2) > tol
+        compared += clear.sum()
+        agree += (cand[clear, sidx] == cls[order[clear, 0]]).sum()
+    assert compared >= 0.9 * 16 * m * min(1.0, k / 256)
+    assert agree == compared
+
+
+@pytest.mark.parametrize("k", [128, 100])
+def test_learned_fit_exact_and_certifies(k):
+    """The learned proposal never changes a label: identical label history and
+    centroids to the oracle; and it does decide some survivors."""
+    w = workloads.config(5, n=60000, k=k)
+    _print_case(test="learned-fit", k=k)
+    knor = _knor()
+    ref = oracle.mti_fit(w.x64(), w.C0, 20, history=True)
+    C, lab, st = knor.fit(_dev(w.X, "f32"), k, C0=_dev(w.C0, "f64"), max_iters=20,
+                          history=True, counters=True, learned=True, train_iters=3,
+                          train_batches=4)
+    assert st["iters"] == ref.iters
+    hist = st["label_history"].cpu().numpy()
+    for t in range(ref.iters):
+        assert (hist[t] == ref.label_hist[t]).all(), t
+    assert (C.cpu().numpy() == ref.C).all()
+    if ref.iters > 4:
+        assert st["mlp_queries"] > 0
+        assert st["certified"] > 0
+    print("learned-fit k", k, "queries", st["mlp_queries"], "certified", st["certified"],
+          flush=True)
