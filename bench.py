@@ -70,6 +70,11 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=0,
                     help="oracle iterations for the CPU baseline (0 = whole fit)")
+    ap.add_argument("--form", default="headline",
+                    choices=["headline", "mixed", "batched", "learned"],
+                    help="headline: the benchmark workload (default); the "
+                         "others measure one extended form on its own "
+                         "workload against plain FP32 Lloyd's on this GPU")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="also run one device-to-device copy of this many MiB "
                          "before the timed region (a known-size kernel for "
@@ -77,15 +82,18 @@ def parse():
     return ap.parse_args()
 
 
-def group_work(g, n, d, k, sx, ctr, iters):
+def group_work(g, n, d, k, sx, ctr, iters, mfma_peak=PEAK_FP32_MFMA):
     """Algorithmic work of kernel group g summed over one fit:
     (amount, unit, bound, peak).  ctr: per-iteration counters (iters x 8)."""
     scanned_dense = int(ctr[0, 1]) if iters else 0
     scanned_list = int(ctr[1:iters, 1].sum()) if iters > 1 else 0
     if g == 0:     # dense tile: 2 d flops per point-centroid pair
-        return 2.0 * d * k * scanned_dense, "TFLOP/s", "mfma", PEAK_FP32_MFMA
+        return 2.0 * d * k * scanned_dense, "TFLOP/s", "mfma", mfma_peak
     if g == 1:
-        return 2.0 * d * k * scanned_list, "TFLOP/s", "mfma", PEAK_FP32_MFMA
+        return 2.0 * d * k * scanned_list, "TFLOP/s", "mfma", mfma_peak
+    if g == 2:     # FP64 recheck: subtract, multiply, add per (point, centroid, dim)
+        rech = int(ctr[:iters, 4].sum()) if iters else 0
+        return 3.0 * d * k * rech, "TFLOP/s", "alu", PEAK_FP64_VALU
     if g == 5:     # leaf sums: every row gathered once + perm + leaf sums out
         per_iter = n * d * sx + 4.0 * n + (n / 64.0 + k) * d * 8.0
         return per_iter * iters, "GB/s", "hbm", PEAK_HBM
@@ -100,6 +108,183 @@ def group_work(g, n, d, k, sx, ctr, iters):
     return None
 
 
+def roofline_of(knor, ms, la, g, steps, work):
+    """Roofline entry of kernel group g from event times (ms, launches summed
+    over `steps` fits) and its algorithmic work per fit."""
+    if work is None or not la[g]:
+        return None
+    amount, unit, bound, peak = work
+    per_launch = amount / max(1, la[g] / steps)
+    sec = ms[g] / la[g] / 1e3
+    scale = 1e12 if unit == "TFLOP/s" else 1e9
+    return {"kernel": knor.PROF_GROUPS[g], "bound": bound,
+            "achieved": round(per_launch / sec / scale, 3), "peak": round(peak / scale, 1),
+            "unit": unit, "frac": round(per_launch / sec / peak, 4),
+            "traffic": measured_traffic(knor.PROF_GROUPS[g]),
+            "us_per_launch": round(sec * 1e6, 3)}
+
+
+def cpu_sample_baseline(oracle, w, X64, C0, gpu_labels0, frac, rng_seed=0):
+    """Bounded CPU baseline for the large forms: the oracle's assignment of a
+    random row sample at C0 (one iteration's dominant work), timed and scaled
+    to the full n; its labels are compared with the GPU's iteration-0 labels
+    on the same rows."""
+    import numpy as np
+    rng = np.random.default_rng(rng_seed)
+    m = max(1000, int(frac * w.n))
+    rows = np.sort(rng.choice(w.n, size=m, replace=False))
+    Xs = X64(rows)
+    t = time.perf_counter()
+    lab, _ = oracle.assign(Xs, C0)
+    dt = time.perf_counter() - t
+    sec_per_iter = dt * w.n / m
+    return ({"value": round(1.0 / sec_per_iter, 4), "unit": "iters/s",
+             "cores": oracle.num_threads(), "kind": "oracle",
+             "sample": f"FP64 oracle assignment of {m} random rows at C0 "
+                       f"(one iteration's assignment), scaled to n={w.n}"},
+            bool((lab == gpu_labels0[rows]).all()))
+
+
+def run_form(a):
+    """One extended form on its own workload; one JSON line."""
+    import numpy as np
+    import torch
+
+    import oracle
+    import paper_1606_08905_amd as knor
+    import workloads
+
+    knor.load()
+    t_gen = time.perf_counter()
+    out = {"n_gpus": 1, "steps": a.steps, "warmup": a.warmup, "higher_is_better": True,
+           "scaling": "strong", "vs_baseline": None, "data": "synthetic"}
+
+    def timed(fn):
+        for _ in range(a.warmup):
+            fn()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(a.steps):
+            r = fn()
+        torch.cuda.synchronize()
+        return r, (time.perf_counter() - t) / a.steps
+
+    if a.form in ("mixed", "learned"):
+        cfg = 3 if a.form == "mixed" else 5
+        w = workloads.config(cfg)
+        print(f"# data n={w.n} d={w.d} k={w.k} generated in "
+              f"{time.perf_counter() - t_gen:.1f}s", file=sys.stderr, flush=True)
+        if w.dtype == "bf16":
+            X = torch.from_numpy(w.X.view(np.int16)).cuda().view(torch.bfloat16)
+            Xf = X.float()
+        else:
+            X = torch.from_numpy(w.X).cuda()
+            Xf = X
+        C0 = torch.from_numpy(w.C0).cuda()
+        extra = dict(learned=True) if a.form == "learned" else {}
+
+        def fit(Xt, **kw):
+            return knor.fit(Xt, w.k, C0=C0, max_iters=w.max_iters, tol=w.tol,
+                            counters=True, **kw)
+
+        (C, lab, st), dt = timed(lambda: fit(X, prune=True, **extra))
+        (Cp, labp, stp), dtp = timed(lambda: fit(Xf, prune=False))
+        exact = bool((C == Cp).all() and (lab == labp).all())
+        ref_mti = None
+        if a.form == "learned":
+            (Cm, labm, stm), dtm = timed(lambda: fit(X, prune=True))
+            exact = exact and bool((C == Cm).all() and (lab == labm).all())
+            ref_mti = stm["iters"] / dtm
+        # kernel groups of one more fit, under events
+        ms = np.zeros(knor.NPROF)
+        la = np.zeros(knor.NPROF, np.int64)
+        fit(X, prune=True, profile=(ms, la), **extra)
+        g = int(np.argmax(ms))
+        sx = 2 if w.dtype == "bf16" else 4
+        peak = PEAK_BF16_MFMA if w.dtype == "bf16" else PEAK_FP32_MFMA
+        out.update({
+            "metric": "Lloyd iters/s at exact assignments (labels identical to plain FP32)",
+            "value": round(st["iters"] / dt, 3), "unit": "iters/s",
+            "ms_per_step": round(dt * 1e3, 3),
+            "dtype": "bf16" if w.dtype == "bf16" else "f32",
+            "config": {"workload": (
+                "mixed precision: n=2e7 d=64 k=256 bf16, 95% mixture + 5% uniform "
+                "outliers, k random rows, 30 iters, MTI" if a.form == "mixed" else
+                "learned proposal: n=1e7 d=32 k=4096 f32 mixture, k random rows, "
+                "40 iters, MTI + MLP 32-256-256-4096 trained on iterations 1-5"),
+                "n": w.n, "d": w.d, "k": w.k, "iters_per_fit": st["iters"]},
+            "baseline_fp32_plain": {"value": round(stp["iters"] / dtp, 3), "unit": "iters/s"},
+            "speedup_vs_fp32_plain": round((st["iters"] / dt) / (stp["iters"] / dtp), 3),
+            "exact_vs_fp32_plain": exact,
+            "rechecked_per_fit": st["rechecked"],
+            "roofline": roofline_of(knor, ms, la, g, 1,
+                                    group_work(g, w.n, w.d, w.k, sx, st["counters"],
+                                               st["iters"], peak)),
+            "kernels": {nm: {"ms_per_fit": round(float(ms[i]), 3), "launches": int(la[i])}
+                        for i, nm in enumerate(knor.PROF_GROUPS) if la[i]},
+        })
+        if a.form == "learned":
+            out["baseline_mti"] = {"value": round(ref_mti, 3), "unit": "iters/s"}
+            out["speedup_vs_mti"] = round((st["iters"] / dt) / ref_mti, 3)
+            out["certified_per_fit"] = st["certified"]
+            out["mlp_queries_per_fit"] = st["mlp_queries"]
+        if not a.no_cpu_baseline:
+            h = knor.fit(X, w.k, C0=C0, max_iters=1, history=True)[2]["label_history"]
+            cb, ok = cpu_sample_baseline(oracle, w, lambda r: workloads.to_f64(w.X[r], w.dtype),
+                                         w.C0, h[0].cpu().numpy(), 0.02 if cfg == 5 else 0.05)
+            out["cpu_baseline"] = cb
+            out["cpu_sample_labels_exact"] = ok
+    else:   # batched
+        ws = workloads.batched(64)
+        print(f"# 64 instances, sum n={sum(w.n for w in ws)}, generated in "
+              f"{time.perf_counter() - t_gen:.1f}s", file=sys.stderr, flush=True)
+        probs = [dict(X=torch.from_numpy(w.X).cuda(), k=w.k, C0=torch.from_numpy(w.C0).cuda(),
+                      max_iters=w.max_iters, tol=w.tol) for w in ws]
+        res, dt = timed(lambda: knor.fit_batched(probs))
+        seq, dts = timed(lambda: [knor.fit(p["X"], p["k"], C0=p["C0"], max_iters=p["max_iters"],
+                                           prune=False) for p in probs])
+        iters = sum(r[2]["iters"] for r in res)
+        exact = all(bool((r[0] == q[0]).all() and (r[1] == q[1]).all()) for r, q in zip(res, seq))
+        out.update({
+            "metric": "Lloyd iters/s summed over the batch at exact assignments",
+            "value": round(iters / dt, 3), "unit": "iters/s",
+            "ms_per_step": round(dt * 1e3, 3), "dtype": "f32",
+            "config": {"workload": "batched restarts: 64 instances, n log-uniform in "
+                                   "[1e4, 2e6], d in {8,16,32,64}, k in 8..512, f32, "
+                                   "k random rows, 50 iters, MTI, tuned tile schedules",
+                       "instances": 64, "sum_n": int(sum(w.n for w in ws)),
+                       "iters_per_batch": iters},
+            "baseline_fp32_plain_sequential": {"value": round(iters / dts, 3), "unit": "iters/s"},
+            "speedup_vs_fp32_plain": round(dts / dt, 3),
+            "exact_vs_fp32_plain": exact,
+            "eff_dists_per_s": sum(r[2]["iters"] * w.n * w.k for r, w in zip(res, ws)) / dt,
+        })
+        # roofline: the largest instance's dominant kernel group, under events
+        il = max(range(len(ws)), key=lambda i: ws[i].n * ws[i].k * ws[i].d)
+        wl = ws[il]
+        ms = np.zeros(knor.NPROF)
+        la = np.zeros(knor.NPROF, np.int64)
+        _, _, stl = knor.fit(probs[il]["X"], wl.k, C0=probs[il]["C0"], max_iters=wl.max_iters,
+                             counters=True, profile=(ms, la))
+        g = int(np.argmax(ms))
+        rl = roofline_of(knor, ms, la, g, 1, group_work(g, wl.n, wl.d, wl.k, 4, stl["counters"],
+                                                        stl["iters"]))
+        if rl is not None:
+            rl["instance"] = {"n": wl.n, "d": wl.d, "k": wl.k}
+        out["roofline"] = rl
+        if not a.no_cpu_baseline:
+            i = il
+            w = ws[i]
+            h = knor.fit(probs[i]["X"], w.k, C0=probs[i]["C0"], max_iters=1,
+                         history=True)[2]["label_history"]
+            cb, ok = cpu_sample_baseline(oracle, w, lambda r: w.X[r].astype(np.float64),
+                                         w.C0, h[0].cpu().numpy(), 0.25)
+            cb["sample"] += " (largest instance)"
+            out["cpu_baseline"] = cb
+            out["cpu_sample_labels_exact"] = ok
+    print(json.dumps(out), flush=True)
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -107,6 +292,9 @@ def main():
                           "multi-GPU sharding is described in DESIGN.md",
                           "n_gpus": a.gpus}), flush=True)
         sys.exit(2)
+    if a.form != "headline":
+        run_form(a)
+        return
     import numpy as np
     import torch
 
