@@ -144,6 +144,108 @@ __device__ __forceinline__ void load_x_chunk(const T* __restrict__ x, int i0,
   }
 }
 
+// Throughput path of the FP64 recheck, for workgroups with many near-tie
+// points: tiles of 64 points x 64 centroids, staged dimension-major in LDS
+// (16 dimensions per stage); thread (tp, tc) keeps the 4 x 4 canonical
+// accumulators of points 4tp.. and centroids 4tc.. -- each is the index-order
+// FP64 sum of the definition, one rounding per operation -- then the
+// lexicographic (D, j) minimum over the 16 lanes that share a point.
+constexpr int kRbP = 64, kRbC = 64, kRbD = 16;
+constexpr int kRecheckBlockedMin = 48;
+
+template <typename T, typename PointOf>
+__device__ unsigned long long recheck_blocked(
+    const T* __restrict__ X, int d, const double* __restrict__ C64, int k, int nf,
+    PointOf point_of, int32_t* __restrict__ labels, float* __restrict__ ub,
+    int* __restrict__ dirty) {
+  __shared__ __attribute__((aligned(16))) double sx[kRbD][kRbP];
+  __shared__ __attribute__((aligned(16))) double sc[kRbD][kRbC];
+  __shared__ int sp[kRbP];
+  const int tp = threadIdx.x >> 4, tc = threadIdx.x & 15;
+  unsigned long long changes = 0;
+  for (int f0 = 0; f0 < nf; f0 += kRbP) {
+    __syncthreads();
+    if (threadIdx.x < kRbP) sp[threadIdx.x] = f0 + threadIdx.x < nf ? point_of(f0 + threadIdx.x) : -1;
+    __syncthreads();
+    double best[4];
+    int bj[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) { best[r] = INFINITY; bj[r] = 0x7fffffff; }
+    for (int c0 = 0; c0 < k; c0 += kRbC) {
+      double acc[4][4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) acc[r][q] = 0.0;
+      for (int i0 = 0; i0 < d; i0 += kRbD) {
+        const int lim = d - i0 < kRbD ? d - i0 : kRbD;
+        __syncthreads();
+        for (int e = threadIdx.x; e < kRbD * kRbP; e += 256) {
+          const int pp = e / kRbD, ii = e - pp * kRbD;
+          const int p = sp[pp];
+          sx[ii][pp] = (p >= 0 && ii < lim) ? to_f64<T>(X[(size_t)p * d + i0 + ii]) : 0.0;
+          const int j = c0 + pp;
+          sc[ii][pp] = (j < k && ii < lim) ? C64[(size_t)j * d + i0 + ii] : 0.0;
+        }
+        __syncthreads();
+        for (int ii = 0; ii < lim; ++ii) {
+          double xv[4], cv[4];
+#pragma unroll
+          for (int r = 0; r < 4; ++r) xv[r] = sx[ii][4 * tp + r];
+#pragma unroll
+          for (int q = 0; q < 4; ++q) cv[q] = sc[ii][4 * tc + q];
+#pragma unroll
+          for (int r = 0; r < 4; ++r)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+              const double t = __dsub_rn(xv[r], cv[q]);
+              acc[r][q] = __dadd_rn(acc[r][q], __dmul_rn(t, t));
+            }
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int j = c0 + 4 * tc + q;
+        if (j < k)
+#pragma unroll
+          for (int r = 0; r < 4; ++r)
+            if (acc[r][q] < best[r] || (acc[r][q] == best[r] && j < bj[r])) {
+              best[r] = acc[r][q];
+              bj[r] = j;
+            }
+      }
+    }
+    // minimum over the 16 lanes (tc) of each point group
+#pragma unroll
+    for (int off = 1; off < 16; off <<= 1)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const double ob = __shfl_xor(best[r], off);
+        const int oj = __shfl_xor(bj[r], off);
+        if (ob < best[r] || (ob == best[r] && oj < bj[r])) { best[r] = ob; bj[r] = oj; }
+      }
+    if (tc < 4) {
+      const int r = tc;
+      const int p = sp[4 * tp + r];
+      double bv = best[0];
+      int jv = bj[0];
+#pragma unroll
+      for (int q = 1; q < 4; ++q)
+        if (q == r) { bv = best[q]; jv = bj[q]; }
+      if (p >= 0) {
+        const int32_t old = labels[p];
+        labels[p] = jv;
+        if (old != jv) {
+          ++changes;
+          mark_dirty(dirty, old, jv);
+        }
+        if (ub) ub[p] = f32_up(sqrt(bv) * (1.0 + (double)(d + 4) * 2.220446049250313e-16));
+      }
+    }
+  }
+  return changes;
+}
+
 // The FP64 recheck.  Workgroup b takes the recheck slices [b*S, b*S + S)
 // (one slice per tile workgroup) as one list of nf near-tie points, so that
 // the grid is small enough to be resident at once.  Its 256 threads are
@@ -155,14 +257,14 @@ __device__ __forceinline__ void load_x_chunk(const T* __restrict__ x, int i0,
 // per workgroup (row stride d + 1 doubles); otherwise they are read from the
 // transposed global copy, which makes the threads' reads contiguous.  The
 // lexicographic (D, j) minimum is the lowest-index argmin.
-constexpr int kRecheckSlices = 4;
+constexpr int kRecheckSlices = 4;     // at most
 
 template <typename T, bool LDSC>
 __global__ __launch_bounds__(256) void exact_recheck_unit(
     const T* __restrict__ X, int d, int vec, const double* __restrict__ C64,
     const double* __restrict__ CT, int k,
     int tpf_max, const int* __restrict__ flags, const int* __restrict__ ucnt,
-    int nslices, int64_t cap, int32_t* __restrict__ labels,
+    int nslices, int S, int64_t cap, int32_t* __restrict__ labels,
     float* __restrict__ ub, unsigned long long* __restrict__ row,
     const int* __restrict__ conv, int iter, int* __restrict__ dirty) {
   extern __shared__ __attribute__((aligned(16))) double sC[];
@@ -170,11 +272,11 @@ __global__ __launch_bounds__(256) void exact_recheck_unit(
   __shared__ int red_j[4];
   // this workgroup's slices and the start of each within its list (read
   // together with the convergence flag: one round trip)
-  const int s0 = blockIdx.x * kRecheckSlices;
+  const int s0 = blockIdx.x * S;
   int cnt[kRecheckSlices];
 #pragma unroll
   for (int i = 0; i < kRecheckSlices; ++i)
-    cnt[i] = s0 + i < nslices ? ucnt[s0 + i] : 0;
+    cnt[i] = (i < S && s0 + i < nslices) ? ucnt[s0 + i] : 0;
   if (*conv < iter) return;
   int sstart[kRecheckSlices + 1];
   sstart[0] = 0;
@@ -193,6 +295,14 @@ __global__ __launch_bounds__(256) void exact_recheck_unit(
     for (int i = 1; i < kRecheckSlices; ++i) si += (f >= sstart[i]) ? 1 : 0;
     return flags[(int64_t)(s0 + si) * cap + (f - sstart[si])];
   };
+  if (nf >= kRecheckBlockedMin) {
+    const unsigned long long ch =
+        recheck_blocked<T>(X, d, C64, k, nf, point_of, labels, ub, dirty);
+    const int q1[1] = {SLOT_CHANGED};
+    const unsigned long long v1[1] = {ch};
+    block_add_slots<1>(row, q1, v1);
+    return;
+  }
   // the first pass's point index is fetched before the centroid staging
   int p_next = gsel < nf ? point_of(gsel) : 0;
   const int ldc = d + 1;
@@ -309,16 +419,18 @@ static void launch_recheck_t(const CentroidOps& o, const AssignJob& j,
   const int vec = (int)(((uintptr_t)j.X & 15) == 0 &&
                         ((size_t)j.d * sizeof(T)) % 16 == 0);
   const size_t lds = (size_t)o.k * (j.d + 1) * sizeof(double);
-  const int grid = (g.grid + kRecheckSlices - 1) / kRecheckSlices;
+  // several slices per workgroup when the tile grid alone fills the device
+  const int S = g.grid >= 1024 ? kRecheckSlices : 1;
+  const int grid = (g.grid + S - 1) / S;
   if (lds <= kRecheckLds)
     hipLaunchKernelGGL((exact_recheck_unit<T, true>), dim3(grid), dim3(256),
                        lds, s, (const T*)j.X, j.d, vec, o.C64, o.CT, o.k, tpf,
-                       j.flags, j.ucnt, g.grid, g.cap, j.labels, j.u, j.row, j.conv,
+                       j.flags, j.ucnt, g.grid, S, g.cap, j.labels, j.u, j.row, j.conv,
                        j.iter, j.dirty);
   else
     hipLaunchKernelGGL((exact_recheck_unit<T, false>), dim3(grid), dim3(256),
                        0, s, (const T*)j.X, j.d, vec, o.C64, o.CT, o.k, tpf,
-                       j.flags, j.ucnt, g.grid, g.cap, j.labels, j.u, j.row, j.conv,
+                       j.flags, j.ucnt, g.grid, S, g.cap, j.labels, j.u, j.row, j.conv,
                        j.iter, j.dirty);
 }
 
