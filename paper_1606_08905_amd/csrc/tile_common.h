@@ -12,7 +12,7 @@
 
 #include <math.h>
 
-#include "common.h"
+#include "recheck.h"
 
 namespace knor {
 
@@ -118,15 +118,16 @@ __device__ __forceinline__ void finalize_points(
 
 // Unit -> (range of points) of a dense or segmented pass.  Segmented units
 // are ordered tile-major (all segments' first tiles, then second tiles, ...)
-// so that occupied units spread over the grid.
+// so that occupied units spread over the grid.  sSeg: the segment counts
+// staged in LDS, or null.
 __device__ __forceinline__ bool unit_range(int64_t unit, int up, int64_t n,
                                            const int* __restrict__ seg_cnt,
-                                           int nseg, int64_t& q0, int64_t& m,
-                                           int64_t& base) {
+                                           const int* sSeg, int nseg, int64_t& q0,
+                                           int64_t& m, int64_t& base) {
   if (seg_cnt) {
     const int64_t t = unit / nseg;
     const int s = (int)(unit - t * nseg);
-    m = seg_cnt[s];
+    m = sSeg ? sSeg[s] : seg_cnt[s];
     q0 = t * up;
     base = (int64_t)s * kSeg;
     return q0 < m;
@@ -135,6 +136,67 @@ __device__ __forceinline__ bool unit_range(int64_t unit, int up, int64_t n,
   q0 = unit * up;
   base = 0;
   return true;
+}
+
+// Segmented pass: stage the segment counts in LDS (when there are at most
+// kSegCache segments) and each wave's largest count of occupied units of
+// any segment into sWmax[wave].  After the caller's next barrier,
+// seg_units_bound() gives the number of units worth visiting: units are
+// tile-major, so every unit past (max tiles) x nseg is empty.
+constexpr int kSegCache = 1024;
+
+__device__ __forceinline__ void seg_stage(const int* __restrict__ seg_cnt, int nseg,
+                                          int up, int* sSeg, int* sWmax) {
+  int mx = 0;
+  for (int e = threadIdx.x; e < nseg; e += blockDim.x) {
+    const int c = seg_cnt[e];
+    if (nseg <= kSegCache) sSeg[e] = c;
+    const int t = (c + up - 1) / up;
+    mx = t > mx ? t : mx;
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    const int o = __shfl_xor(mx, off);
+    mx = o > mx ? o : mx;
+  }
+  if ((threadIdx.x & 63) == 0) sWmax[threadIdx.x >> 6] = mx;
+}
+
+__device__ __forceinline__ int64_t seg_units_bound(const int* sWmax, int nseg,
+                                                   int64_t nunits) {
+  int mx = 0;
+  for (int w = 0; w < (int)(blockDim.x >> 6); ++w) mx = sWmax[w] > mx ? sWmax[w] : mx;
+  const int64_t b = (int64_t)mx * nseg;
+  return b < nunits ? b : nunits;
+}
+
+// After its last unit (and a barrier), a tile workgroup with at most
+// fuse_max near-tie points rechecks them itself and reports an empty slice;
+// larger slices are left to the recheck kernel.  Returns the slice length
+// left for that kernel.
+constexpr int kFuseRecheckMax = 64;
+
+// threads per point of the latency path: min(256, pow2 >= k)
+inline int fuse_tpf(int k) {
+  int t = 1;
+  while (t < k && t < 256) t *= 2;
+  return t;
+}
+
+template <typename X_T>
+__device__ __forceinline__ int recheck_own_slice(
+    const X_T* __restrict__ X, int d, int vecx, const double* __restrict__ CT,
+    int k, int tpf_max, int fuse_max, const int* slice, int nf,
+    int32_t* __restrict__ labels, float* __restrict__ ub, int* __restrict__ dirty,
+    unsigned long long* __restrict__ row) {
+  if (nf == 0 || nf > fuse_max || !CT) return nf;
+  const unsigned long long ch = recheck_small<X_T, false, false>(
+      X, d, vecx, nullptr, CT, nullptr, k, tpf_max, nf,
+      [&](int f) { return slice[f]; }, labels, ub, dirty);
+  const int q[1] = {SLOT_CHANGED};
+  const unsigned long long v[1] = {ch};
+  block_add_slots<1>(row, q, v);
+  return 0;
 }
 
 // Append this wave's flagged points to the workgroup's slice.

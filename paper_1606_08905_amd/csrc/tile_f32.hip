@@ -250,7 +250,8 @@ __global__ __launch_bounds__(kTileThreads) void tile_f32_resident_kernel(
     int nseg, int32_t* __restrict__ labels, float* __restrict__ ub,
     int* __restrict__ flags, int64_t cap, int* __restrict__ ucnt,
     unsigned long long* __restrict__ row, const int* __restrict__ conv,
-    int iter, int* __restrict__ dirty, int recheck_all, int vec) {
+    int iter, int* __restrict__ dirty, int recheck_all, int vec,
+    const double* __restrict__ CT, int tpf_max, int fuse_max, int vecx) {
   using T = F32Tile<DP, PB_>;
   constexpr int LDA = T::LDA, PB = T::PB, WUP = T::WUP;
   extern __shared__ __attribute__((aligned(16))) float smem[];
@@ -261,7 +262,9 @@ __global__ __launch_bounds__(kTileThreads) void tile_f32_resident_kernel(
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int col = lane & 15, grp = lane >> 4;
 
+  __shared__ int sSeg[kSegCache], sWmax[kTileThreads / 64];
   if (threadIdx.x == 0) sFlag = 0;
+  if (seg_cnt) seg_stage(seg_cnt, nseg, WUP, sSeg, sWmax);
   for (int e = threadIdx.x; e < kpad * (DP / 4); e += kTileThreads) {
     const int r = e / (DP / 4), q4 = e - r * (DP / 4);
     *reinterpret_cast<float4*>(&sC[r * LDA + q4 * 4]) =
@@ -272,13 +275,15 @@ __global__ __launch_bounds__(kTileThreads) void tile_f32_resident_kernel(
   const float cmax = chunk_cmax(sN, kpad, 0, k, lane);
 
   int* slice = flags + (int64_t)blockIdx.x * cap;
-  const int64_t nwu = seg_cnt ? (int64_t)nseg * (kSeg / WUP) : (n + WUP - 1) / WUP;
+  int64_t nwu = seg_cnt ? (int64_t)nseg * (kSeg / WUP) : (n + WUP - 1) / WUP;
+  if (seg_cnt) nwu = seg_units_bound(sWmax, nseg, nwu);
+  const int* segc = (seg_cnt && nseg <= kSegCache) ? sSeg : nullptr;
   WaveState<T> w;
   unsigned long long tot_flag = 0, tot_chg = 0;
   for (int64_t wu = (int64_t)blockIdx.x * 4 + wave; wu < nwu;
        wu += (int64_t)gridDim.x * 4) {
     int64_t q0, m, base;
-    if (!unit_range(wu, WUP, n, seg_cnt, nseg, q0, m, base)) continue;
+    if (!unit_range(wu, WUP, n, seg_cnt, segc, nseg, q0, m, base)) continue;
     load_points<T>(w, X, d, vec, list, labels, base, q0, m, col, grp);
     tile_sweep<T>(w, sC, sN, kpad, 0, col, grp);
     merge_groups<T>(w);
@@ -295,7 +300,9 @@ __global__ __launch_bounds__(kTileThreads) void tile_f32_resident_kernel(
   const int q[2] = {SLOT_FLAGGED, SLOT_CHANGED};
   const unsigned long long v[2] = {tot_flag, tot_chg};
   block_add_slots<2>(row, q, v);               // includes a barrier
-  if (threadIdx.x == 0) ucnt[blockIdx.x] = sFlag;
+  const int left = recheck_own_slice<float>(X, d, vecx, CT, k, tpf_max, fuse_max, slice,
+                                         sFlag, labels, ub, dirty, row);
+  if (threadIdx.x == 0) ucnt[blockIdx.x] = left;
 }
 
 template <int DP, int PB_>
@@ -306,7 +313,8 @@ __global__ __launch_bounds__(kTileThreads) void tile_f32_chunked_kernel(
     int nseg, int32_t* __restrict__ labels, float* __restrict__ ub,
     int* __restrict__ flags, int64_t cap, int* __restrict__ ucnt,
     unsigned long long* __restrict__ row, const int* __restrict__ conv,
-    int iter, int* __restrict__ dirty, int recheck_all, int vec) {
+    int iter, int* __restrict__ dirty, int recheck_all, int vec,
+    const double* __restrict__ CT, int tpf_max, int fuse_max, int vecx) {
   using T = F32Tile<DP, PB_>;
   constexpr int LDA = T::LDA, PB = T::PB, CK = T::CK, WUP = T::WUP, BUP = T::BUP;
   __shared__ __attribute__((aligned(16))) float sC[CK * LDA];
@@ -315,14 +323,19 @@ __global__ __launch_bounds__(kTileThreads) void tile_f32_chunked_kernel(
   if (*conv < iter) return;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int col = lane & 15, grp = lane >> 4;
-  const int64_t units = seg_cnt ? (int64_t)nseg * (kSeg / BUP) : (n + BUP - 1) / BUP;
+  __shared__ int sSeg[kSegCache], sWmax[kTileThreads / 64];
+  int64_t units = seg_cnt ? (int64_t)nseg * (kSeg / BUP) : (n + BUP - 1) / BUP;
   if (threadIdx.x == 0) { sFlag = 0; sChg = 0; }
+  if (seg_cnt) seg_stage(seg_cnt, nseg, BUP, sSeg, sWmax);
+  __syncthreads();
+  if (seg_cnt) units = seg_units_bound(sWmax, nseg, units);
+  const int* segc = (seg_cnt && nseg <= kSegCache) ? sSeg : nullptr;
 
   int* slice = flags + (int64_t)blockIdx.x * cap;
   WaveState<T> w;
   for (int64_t unit = blockIdx.x; unit < units; unit += gridDim.x) {
     int64_t q0, m, base;
-    if (!unit_range(unit, BUP, n, seg_cnt, nseg, q0, m, base))
+    if (!unit_range(unit, BUP, n, seg_cnt, segc, nseg, q0, m, base))
       continue;                                // uniform over the workgroup
     load_points<T>(w, X, d, vec, list, labels, base, q0 + wave * WUP, m, col, grp);
     float cmax = 0.0f;
@@ -351,30 +364,41 @@ __global__ __launch_bounds__(kTileThreads) void tile_f32_chunked_kernel(
   const int q[2] = {SLOT_FLAGGED, SLOT_CHANGED};
   const unsigned long long v[2] = {threadIdx.x == 0 ? (unsigned long long)sFlag : 0ull,
                                    threadIdx.x == 0 ? (unsigned long long)sChg : 0ull};
-  block_add_slots<2>(row, q, v);
-  if (threadIdx.x == 0) ucnt[blockIdx.x] = sFlag;
+  block_add_slots<2>(row, q, v);               // includes a barrier
+  const int left = recheck_own_slice<float>(X, d, vecx, CT, k, tpf_max, fuse_max, slice,
+                                         sFlag, labels, ub, dirty, row);
+  if (threadIdx.x == 0) ucnt[blockIdx.x] = left;
 }
 
 template <int DP, int PB>
 static hipError_t launch_dp_pb(const CentroidOps& o, const AssignJob& j,
                                hipStream_t s) {
   const int vec = (int)(j.d == DP && ((uintptr_t)j.X & 15) == 0);
+  const int vecx = (int)(j.d % 4 == 0 && ((uintptr_t)j.X & 15) == 0);
   const bool seg = j.seg_cnt != nullptr;
   const TileGeom g = tile_f32_geometry(DP, o.kpad, PB, o.tres, j.n, seg, j.nseg);
   if (g.resident) {
     using T = F32Tile<DP, PB>;
     const size_t lds = (size_t)o.kpad * T::LDA * 4 + (size_t)o.kpad * 4;
+    if (lds > 49152) {   // with the static arrays, past the default 64 KB
+      hipError_t e = hipFuncSetAttribute(
+          reinterpret_cast<const void*>(&tile_f32_resident_kernel<DP, PB>),
+          hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+      if (e != hipSuccess) return e;
+    }
     hipLaunchKernelGGL((tile_f32_resident_kernel<DP, PB>), dim3(g.grid),
                        dim3(kTileThreads), lds, s, (const float*)j.X, j.n, j.d,
                        o.Cm2, o.cn, o.k, o.kpad, j.list, j.seg_cnt, j.nseg,
                        j.labels, j.u, j.flags, g.cap, j.ucnt, j.row, j.conv,
-                       j.iter, j.dirty, j.recheck_all, vec);
+                       j.iter, j.dirty, j.recheck_all, vec, o.CT, fuse_tpf(o.k),
+                       j.recheck_all ? 0 : kFuseRecheckMax, vecx);
   } else {
     hipLaunchKernelGGL((tile_f32_chunked_kernel<DP, PB>), dim3(g.grid),
                        dim3(kTileThreads), 0, s, (const float*)j.X, j.n, j.d,
                        o.Cm2, o.cn, o.k, o.kpad, j.list, j.seg_cnt, j.nseg,
                        j.labels, j.u, j.flags, g.cap, j.ucnt, j.row, j.conv,
-                       j.iter, j.dirty, j.recheck_all, vec);
+                       j.iter, j.dirty, j.recheck_all, vec, o.CT, fuse_tpf(o.k),
+                       j.recheck_all ? 0 : kFuseRecheckMax, vecx);
   }
   return hipGetLastError();
 }
