@@ -518,6 +518,8 @@ static knor_status fit_impl(const void* X, knor_dtype dt, int64_t n, int d,
   void* mlp_ws = nullptr;
   double *mean = nullptr, *istd = nullptr, *loss_dev = nullptr;
   uint16_t* W3t = nullptr;
+  int* nbr_idx = nullptr;
+  float* nbr_half = nullptr;
   if (learned) {
     ML = mlp_layout(d, hM, k);
     for (float** q : {&th, &am, &av, &grad}) ar.add((void**)q, sizeof(float) * (size_t)ML.P);
@@ -537,6 +539,8 @@ static knor_status fit_impl(const void* X, knor_dtype dt, int64_t n, int d,
     ar.add((void**)&H1, sizeof(float) * (size_t)chunk * hM);
     ar.add((void**)&H2, sizeof(float) * (size_t)chunk * hM);
     ar.add((void**)&cand, sizeof(int32_t) * (size_t)n * kMlpTop);
+    ar.add((void**)&nbr_idx, sizeof(int) * (size_t)k * kMlpNbr);
+    ar.add((void**)&nbr_half, sizeof(float) * (size_t)k * kMlpNbr);
   }
   knor_status rs = ar.alloc(s, o.cap);
   if (rs != KNOR_OK) return rs;
@@ -639,9 +643,10 @@ static knor_status fit_impl(const void* X, knor_dtype dt, int64_t n, int d,
           HIPCHK(launch_mlp_propose(H2, W3t, th + ML.b3, hM, k, kpadM, cnt, nullptr,
                                     cand + c0 * kMlpTop, s));
         }
-        HIPCHK(launch_mlp_certify(X, dt, d, C_out, s_half, list, seg_cnt, seg_off, nseg,
-                                  cand, labels_out, u, dirty, list2, seg_cnt2, row, conv,
-                                  t, s));
+        HIPCHK(launch_cc_neighbors(C_out, ops.CT, k, d, nbr_idx, nbr_half, conv, t, s));
+        HIPCHK(launch_mlp_certify(X, dt, d, C_out, nbr_idx, nbr_half, list, seg_cnt, seg_off,
+                                  nseg, cand, labels_out, u, dirty, list2, seg_cnt2, row,
+                                  conv, t, s));
         job.list = list2;
         job.seg_cnt = seg_cnt2;
       }

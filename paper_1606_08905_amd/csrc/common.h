@@ -413,13 +413,18 @@ hipError_t launch_gather_std(const void* X, knor_dtype dt, int d, const int* row
                              const double* istd, float* Xs, hipStream_t s);
 hipError_t launch_seg_dense(const int* list, const int* seg_cnt, int nseg, int* seg_off,
                             int* dense, const int* conv, int iter, hipStream_t s);
-hipError_t launch_mlp_certify(const void* X, knor_dtype dt, int d, const double* C64,
-                              const float* s_half, const int* list, const int* seg_cnt,
-                              const int* seg_off, int nseg, const int32_t* cand,
-                              int32_t* labels, float* u, int* dirty, int* list2,
-                              int* seg_cnt2, unsigned long long* row, const int* conv,
-                              int iter, hipStream_t s);
 constexpr int kMlpTop = 16;          // candidates per point
+constexpr int kMlpNbr = kMlpTop + 1; // sorted neighbours per centroid: one past
+                                     // the other candidates
+hipError_t launch_cc_neighbors(const double* C64, const double* CT, int k, int d,
+                               int* nbr_idx, float* nbr_half, const int* conv, int iter,
+                               hipStream_t s);
+hipError_t launch_mlp_certify(const void* X, knor_dtype dt, int d, const double* C64,
+                              const int* nbr_idx, const float* nbr_half, const int* list,
+                              const int* seg_cnt, const int* seg_off, int nseg,
+                              const int32_t* cand, int32_t* labels, float* u, int* dirty,
+                              int* list2, int* seg_cnt2, unsigned long long* row,
+                              const int* conv, int iter, hipStream_t s);
 constexpr int kMlpHidden = 256;      // hidden width inside knor_fit
 constexpr int kMlpBatch = 4096;      // training minibatch inside knor_fit
 constexpr int64_t kMlpChunk = 1 << 20;   // proposal rows per pass

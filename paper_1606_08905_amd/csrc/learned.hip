@@ -5,10 +5,12 @@
 // (Mhembere et al., HPDC'17, Section "Minimal Triangle Inequality (MTI)
 // Pruning"), it proposes 16 candidate centroids; the nearest candidate c*
 // (FP64 canonical distances, lowest index on ties) is accepted only under
-// the certificate d(x, c*) (1 + eta) < s(c*) = 1/2 min_{j != c*} d(c*, j):
-// then every other centroid is farther by a relative gap of about 2 eta, so
-// c* is the FP64 argmin of the definition.  Points without a certificate go
-// through the full distance tile.  The network therefore never changes a
+// the certificate d(x, c*) (1 + eta) < 1/2 min_{j not a candidate} d(c*, j)
+// (which contains the paper-style test against s(c*) = 1/2 min_{j != c*}
+// d(c*, j) as a special case): every non-candidate is then farther than c*
+// by a relative gap of about 2 eta, and the candidates are compared in the
+// FP64 definition itself, so c* is its argmin.  Points without a
+// certificate go through the full distance tile.  The network therefore never changes a
 // label; it only decides which points skip the k-way scan.
 //
 // Every matrix product runs on v_mfma_f32_16x16x32_bf16: operands are FP32
@@ -166,15 +168,20 @@ __global__ __launch_bounds__(256) void softmax_ce_kernel(float* __restrict__ Z,
   }
 }
 
-// out[c] = sum over rows of D[r][c] (FP32, rows in order)
+// out[c] = sum over rows of D[r][c] (FP32): thread (q, c) of a workgroup of
+// 64 columns sums rows q, q + 4, ...; the four partial sums are then added.
 __global__ __launch_bounds__(256) void colsum_kernel(const float* __restrict__ D,
                                                      int rows, int cols,
                                                      float* __restrict__ out) {
-  const int c = blockIdx.x * 256 + threadIdx.x;
-  if (c >= cols) return;
+  __shared__ float part[4][64];
+  const int cl = threadIdx.x & 63, q = threadIdx.x >> 6;
+  const int c = blockIdx.x * 64 + cl;
   float s = 0.0f;
-  for (int r = 0; r < rows; ++r) s += D[(size_t)r * cols + c];
-  out[c] = s;
+  if (c < cols)
+    for (int r = q; r < rows; r += 4) s += D[(size_t)r * cols + c];
+  part[q][cl] = s;
+  __syncthreads();
+  if (q == 0 && c < cols) out[c] = (part[0][cl] + part[1][cl]) + (part[2][cl] + part[3][cl]);
 }
 
 __global__ __launch_bounds__(256) void mean_kernel(const double* __restrict__ v, int n,
@@ -289,13 +296,13 @@ hipError_t mlp_train_step(float* th, float* am, float* av, int64_t step,
   hipLaunchKernelGGL(mean_kernel, dim3(1), dim3(256), 0, s, lrow, B, loss_dev);
   // backward (Z now holds dZ)
   if ((e = gemm(H2, h, 1, Z, k, 0, grad + L.W3, k, h, k, B, nullptr, 0, nullptr, 0))) return e;
-  hipLaunchKernelGGL(colsum_kernel, dim3((k + 255) / 256), dim3(256), 0, s, Z, B, k, grad + L.b3);
+  hipLaunchKernelGGL(colsum_kernel, dim3((k + 63) / 64), dim3(256), 0, s, Z, B, k, grad + L.b3);
   if ((e = gemm(Z, k, 0, th + L.W3, k, 1, D2, h, B, h, k, nullptr, 0, H2, h))) return e;
   if ((e = gemm(H1, h, 1, D2, h, 0, grad + L.W2, h, h, h, B, nullptr, 0, nullptr, 0))) return e;
-  hipLaunchKernelGGL(colsum_kernel, dim3((h + 255) / 256), dim3(256), 0, s, D2, B, h, grad + L.b2);
+  hipLaunchKernelGGL(colsum_kernel, dim3((h + 63) / 64), dim3(256), 0, s, D2, B, h, grad + L.b2);
   if ((e = gemm(D2, h, 0, th + L.W2, h, 1, D1, h, B, h, h, nullptr, 0, H1, h))) return e;
   if ((e = gemm(Xs, d, 1, D1, h, 0, grad + L.W1, h, d, h, B, nullptr, 0, nullptr, 0))) return e;
-  hipLaunchKernelGGL(colsum_kernel, dim3((h + 255) / 256), dim3(256), 0, s, D1, B, h, grad + L.b1);
+  hipLaunchKernelGGL(colsum_kernel, dim3((h + 63) / 64), dim3(256), 0, s, D1, B, h, grad + L.b1);
   if ((e = hipGetLastError())) return e;
   if (lr > 0.0f) {
     const double c1 = 1.0 / (1.0 - pow(0.9, (double)step));
@@ -584,62 +591,168 @@ hipError_t launch_seg_dense(const int* list, const int* seg_cnt, int nseg, int* 
   return hipGetLastError();
 }
 
-// The certificate.  One workgroup per segment; 16 lanes per survivor, one
-// candidate each: canonical FP64 distance, lexicographic (D, j) minimum over
-// the 16, then the test ub (1 + eta) < s(c*) with ub an upper bound of
-// d(x, c*) rounded up to FP32.  Certified points take c* (and ub as their
-// MTI bound); the others are appended, in segment order, to list2.
+// Each centroid's kMlpNbr nearest other centroids, in increasing (D, j)
+// order, with a rounded-down half of their distance: nbr_idx[i][t],
+// nbr_half[i][t] (index -1 and +inf past the k - 1 others).  One workgroup
+// per centroid: every thread keeps a sorted list of its own nearest
+// kMlpNbr, then kMlpNbr rounds of a workgroup minimum over the list heads.
+__global__ __launch_bounds__(256) void cc_neighbors_kernel(
+    const double* __restrict__ C64, const double* __restrict__ CT, int k, int d,
+    int* __restrict__ nbr_idx, float* __restrict__ nbr_half,
+    const int* __restrict__ conv, int iter) {
+  __shared__ double hd[256];
+  __shared__ int hj[256], hw[256];
+  if (*conv < iter) return;
+  const int i = blockIdx.x;
+  const double* ci = C64 + (size_t)i * d;
+  double ld[kMlpNbr];
+  int lj[kMlpNbr];
+#pragma unroll
+  for (int t = 0; t < kMlpNbr; ++t) { ld[t] = INFINITY; lj[t] = 0x7fffffff; }
+  for (int j = threadIdx.x; j < k; j += 256) {
+    if (j == i) continue;
+    double acc = 0.0;
+    for (int dim = 0; dim < d; ++dim) {
+      const double t = __dsub_rn(ci[dim], CT[(size_t)dim * k + j]);
+      acc = __dadd_rn(acc, __dmul_rn(t, t));
+    }
+    // insert (acc, j) into the sorted list (j increases, so ties keep order)
+    if (acc < ld[kMlpNbr - 1]) {
+#pragma unroll
+      for (int t = kMlpNbr - 1; t >= 0; --t) {
+        const bool above = t > 0 && acc < ld[t - 1];
+        const bool here = acc < ld[t];
+        const double nd = above ? ld[t - 1] : acc;
+        const int nj = above ? lj[t - 1] : j;
+        ld[t] = here ? nd : ld[t];
+        lj[t] = here ? nj : lj[t];
+      }
+    }
+  }
+  int head = 0;
+  for (int r = 0; r < kMlpNbr; ++r) {
+    double v = INFINITY;
+    int vj = 0x7fffffff;
+#pragma unroll
+    for (int t = 0; t < kMlpNbr; ++t)
+      if (t == head) { v = ld[t]; vj = lj[t]; }
+    hd[threadIdx.x] = v;
+    hj[threadIdx.x] = vj;
+    hw[threadIdx.x] = threadIdx.x;
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+      if (threadIdx.x < st) {
+        const double od = hd[threadIdx.x + st];
+        const int oj = hj[threadIdx.x + st];
+        if (od < hd[threadIdx.x] || (od == hd[threadIdx.x] && oj < hj[threadIdx.x])) {
+          hd[threadIdx.x] = od;
+          hj[threadIdx.x] = oj;
+          hw[threadIdx.x] = hw[threadIdx.x + st];
+        }
+      }
+      __syncthreads();
+    }
+    const double m = hd[0];
+    const int mj = hj[0], mw = hw[0];
+    if (threadIdx.x == 0) {
+      const bool ok = m < INFINITY;
+      nbr_idx[(size_t)i * kMlpNbr + r] = ok ? mj : -1;
+      nbr_half[(size_t)i * kMlpNbr + r] =
+          ok ? f32_down(0.5 * sqrt(m) * (1.0 - (double)(d + 8) * 2.220446049250313e-16))
+             : INFINITY;
+    }
+    if (threadIdx.x == mw && m < INFINITY) ++head;
+    __syncthreads();
+  }
+}
+
+hipError_t launch_cc_neighbors(const double* C64, const double* CT, int k, int d,
+                               int* nbr_idx, float* nbr_half, const int* conv, int iter,
+                               hipStream_t s) {
+  hipLaunchKernelGGL(cc_neighbors_kernel, dim3(k), dim3(256), 0, s, C64, CT, k, d,
+                     nbr_idx, nbr_half, conv, iter);
+  return hipGetLastError();
+}
+
+// The certificate.  One workgroup per segment, one lane per survivor (256
+// per pass).  c* = the candidate with the smallest canonical FP64 distance
+// (lowest index on ties); h = the rounded-down half distance from c* to its
+// nearest centroid outside the candidate set (the first such entry of c*'s
+// sorted neighbour list; +inf when every other centroid is a candidate).
+// Accept iff ub (1 + eta) < h, ub an upper bound of d(x, c*) rounded up to
+// FP32: every candidate is compared in the FP64 definition itself, and every
+// other centroid j has d(x, j) >= d(c*, j) - d(x, c*) > ub (1 + 2 eta).
+// Certified points take c* (and ub as their MTI bound); the others are
+// appended, in segment order, to list2.
 template <typename T>
 __global__ __launch_bounds__(256) void mlp_certify_kernel(
     const T* __restrict__ X, int d, const double* __restrict__ C64,
-    const float* __restrict__ s_half, const int* __restrict__ list,
-    const int* __restrict__ seg_cnt, const int* __restrict__ seg_off,
-    const int32_t* __restrict__ cand, int32_t* __restrict__ labels,
-    float* __restrict__ ub_out, int* __restrict__ dirty, int* __restrict__ list2,
-    int* __restrict__ seg_cnt2, unsigned long long* __restrict__ row,
-    const int* __restrict__ conv, int iter) {
+    const int* __restrict__ nbr_idx, const float* __restrict__ nbr_half,
+    const int* __restrict__ list, const int* __restrict__ seg_cnt,
+    const int* __restrict__ seg_off, const int32_t* __restrict__ cand,
+    int32_t* __restrict__ labels, float* __restrict__ ub_out, int* __restrict__ dirty,
+    int* __restrict__ list2, int* __restrict__ seg_cnt2,
+    unsigned long long* __restrict__ row, const int* __restrict__ conv, int iter) {
   __shared__ int wcnt[4];
   __shared__ int run;
   if (*conv < iter) return;
   const int b = blockIdx.x;
   const int cnt = seg_cnt[b], o = seg_off[b];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int slot = threadIdx.x >> 4, c16 = threadIdx.x & 15;
   if (threadIdx.x == 0) run = 0;
   __syncthreads();
   unsigned long long certified = 0, changes = 0;
-  for (int q0 = 0; q0 < cnt; q0 += 16) {
-    const int q = q0 + slot;
+  for (int q0 = 0; q0 < cnt; q0 += 256) {
+    const int q = q0 + threadIdx.x;
     const bool live = q < cnt;
-    const int p = live ? list[(size_t)b * kSeg + q] : 0;
-    const int j = live ? cand[(size_t)(o + q) * 16 + c16] : -1;
-    double D = INFINITY;
-    if (j >= 0) D = dist2_canon<T>(X + (size_t)p * d, C64 + (size_t)j * d, d);
-    int jj = j >= 0 ? j : 0x7fffffff;
-#pragma unroll
-    for (int off = 1; off < 16; off <<= 1) {
-      const double oD = __shfl_xor(D, off);
-      const int oj = __shfl_xor(jj, off);
-      if (oD < D || (oD == D && oj < jj)) { D = oD; jj = oj; }
-    }
     bool cert = false;
-    if (live && c16 == 0 && jj != 0x7fffffff) {
-      const double ub = f32_up(sqrt(D * (1.0 + (double)(d + 8) * 2.220446049250313e-16)) *
-                               (1.0 + 8.881784197001252e-16));
-      cert = ub * (1.0 + kEta) < (double)s_half[jj];
-      if (cert) {
-        const int32_t old = labels[p];
-        labels[p] = jj;
-        ub_out[p] = (float)ub;
-        ++certified;
-        if (old != jj) {
-          ++changes;
-          mark_dirty(dirty, old, jj);
+    int p = 0;
+    if (live) {
+      p = list[(size_t)b * kSeg + q];
+      int cj[kMlpTop];
+      const int4* cr = reinterpret_cast<const int4*>(cand + (size_t)(o + q) * kMlpTop);
+#pragma unroll
+      for (int v = 0; v < kMlpTop / 4; ++v) {
+        const int4 c4 = cr[v];
+        cj[4 * v] = c4.x; cj[4 * v + 1] = c4.y; cj[4 * v + 2] = c4.z; cj[4 * v + 3] = c4.w;
+      }
+      const T* x = X + (size_t)p * d;
+      double best = INFINITY;
+      int bj = 0x7fffffff;
+#pragma unroll 1
+      for (int s = 0; s < kMlpTop; ++s) {
+        const int j = cj[s];
+        if (j < 0) continue;
+        const double D = dist2_canon<T>(x, C64 + (size_t)j * d, d);
+        if (D < best || (D == best && j < bj)) { best = D; bj = j; }
+      }
+      if (bj != 0x7fffffff) {
+        float h = INFINITY;
+        for (int t = 0; t < kMlpNbr; ++t) {
+          const int nb = nbr_idx[(size_t)bj * kMlpNbr + t];
+          if (nb < 0) break;                 // no further centroids
+          bool in = false;
+#pragma unroll
+          for (int s = 0; s < kMlpTop; ++s) in |= cj[s] == nb;
+          if (!in) { h = nbr_half[(size_t)bj * kMlpNbr + t]; break; }
+        }
+        const double ub = f32_up(sqrt(best * (1.0 + (double)(d + 8) * 2.220446049250313e-16)) *
+                                 (1.0 + 8.881784197001252e-16));
+        cert = ub * (1.0 + kEta) < (double)h;
+        if (cert) {
+          const int32_t old = labels[p];
+          labels[p] = bj;
+          ub_out[p] = (float)ub;
+          ++certified;
+          if (old != bj) {
+            ++changes;
+            mark_dirty(dirty, old, bj);
+          }
         }
       }
     }
-    // uncertified survivors, in order: four per wave per pass
-    const bool keep = live && c16 == 0 && !cert;
+    // uncertified survivors, in order
+    const bool keep = live && !cert;
     const uint64_t km = __ballot(keep);
     if (lane == 0) wcnt[wave] = __popcll(km);
     __syncthreads();
@@ -657,26 +770,26 @@ __global__ __launch_bounds__(256) void mlp_certify_kernel(
 }
 
 hipError_t launch_mlp_certify(const void* X, knor_dtype dt, int d, const double* C64,
-                              const float* s_half, const int* list, const int* seg_cnt,
-                              const int* seg_off, int nseg, const int32_t* cand,
-                              int32_t* labels, float* u, int* dirty, int* list2,
-                              int* seg_cnt2, unsigned long long* row, const int* conv,
-                              int iter, hipStream_t s) {
+                              const int* nbr_idx, const float* nbr_half, const int* list,
+                              const int* seg_cnt, const int* seg_off, int nseg,
+                              const int32_t* cand, int32_t* labels, float* u, int* dirty,
+                              int* list2, int* seg_cnt2, unsigned long long* row,
+                              const int* conv, int iter, hipStream_t s) {
   switch (dt) {
     case KNOR_F32:
       hipLaunchKernelGGL(mlp_certify_kernel<float>, dim3(nseg), dim3(256), 0, s,
-                         (const float*)X, d, C64, s_half, list, seg_cnt, seg_off, cand,
-                         labels, u, dirty, list2, seg_cnt2, row, conv, iter);
+                         (const float*)X, d, C64, nbr_idx, nbr_half, list, seg_cnt, seg_off,
+                         cand, labels, u, dirty, list2, seg_cnt2, row, conv, iter);
       break;
     case KNOR_F64:
       hipLaunchKernelGGL(mlp_certify_kernel<double>, dim3(nseg), dim3(256), 0, s,
-                         (const double*)X, d, C64, s_half, list, seg_cnt, seg_off, cand,
-                         labels, u, dirty, list2, seg_cnt2, row, conv, iter);
+                         (const double*)X, d, C64, nbr_idx, nbr_half, list, seg_cnt, seg_off,
+                         cand, labels, u, dirty, list2, seg_cnt2, row, conv, iter);
       break;
     case KNOR_BF16:
       hipLaunchKernelGGL(mlp_certify_kernel<uint16_t>, dim3(nseg), dim3(256), 0, s,
-                         (const uint16_t*)X, d, C64, s_half, list, seg_cnt, seg_off, cand,
-                         labels, u, dirty, list2, seg_cnt2, row, conv, iter);
+                         (const uint16_t*)X, d, C64, nbr_idx, nbr_half, list, seg_cnt, seg_off,
+                         cand, labels, u, dirty, list2, seg_cnt2, row, conv, iter);
       break;
   }
   return hipGetLastError();
