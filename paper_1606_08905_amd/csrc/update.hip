@@ -482,7 +482,8 @@ constexpr int kLeafWaves = 4;
 template <typename T>
 struct LeafCfg {
   static constexpr int DC = 128 / (int)sizeof(T);      // dims per chunk
-  static constexpr int LD = DC + 1;                    // odd row stride
+  static constexpr int LD = DC + 16 / (int)sizeof(T);  // row stride: 16-byte
+                                                       // rows, spread banks
 };
 
 template <typename T>
@@ -490,9 +491,9 @@ __global__ __launch_bounds__(64 * kLeafWaves) void leaf_kernel(
     const T* __restrict__ X, int d, const int* __restrict__ perm,
     const int* __restrict__ nj, const int* __restrict__ off,
     const int* __restrict__ leaf_off, int k, const int* __restrict__ dirty,
-    double* __restrict__ leafsum, const int* __restrict__ conv, int iter) {
+    double* __restrict__ leafsum, const int* __restrict__ conv, int iter, int vec) {
   constexpr int DC = LeafCfg<T>::DC, LD = LeafCfg<T>::LD;
-  __shared__ T tile[kLeafWaves][kLeaf * LD];
+  __shared__ __attribute__((aligned(16))) T tile[kLeafWaves][kLeaf * LD];
   SKIP_IF_CONVERGED
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int total = leaf_off[k];
@@ -510,7 +511,14 @@ __global__ __launch_bounds__(64 * kLeafWaves) void leaf_kernel(
     const int dc = d - c0 < DC ? d - c0 : DC;
     if (lane < cnt) {
       const T* xr = X + (size_t)p * d + c0;
-      for (int i = 0; i < dc; ++i) tl[lane * LD + i] = xr[i];
+      if (vec) {                             // 16-byte pieces of the row
+        const int nv = dc * (int)sizeof(T) / 16;
+        const uint4* src = reinterpret_cast<const uint4*>(xr);
+        uint4* dst = reinterpret_cast<uint4*>(tl + lane * LD);
+        for (int v = 0; v < nv; ++v) dst[v] = src[v];
+      } else {
+        for (int i = 0; i < dc; ++i) tl[lane * LD + i] = xr[i];
+      }
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
@@ -717,21 +725,23 @@ hipError_t launch_update(const UpdatePlan& p, const void* X, knor_dtype dt,
   }
   if (prof) { prof->end(); prof->begin(KNOR_PROF_LEAF); }
   const int64_t lblocks = (p.max_leaves + kLeafWaves - 1) / kLeafWaves;
+  const size_t esz = dt == KNOR_F64 ? 8 : (dt == KNOR_F32 ? 4 : 2);
+  const int vec = (int)(((size_t)d * esz) % 16 == 0 && ((uintptr_t)X & 15) == 0);
   switch (dt) {
     case KNOR_F64:
       hipLaunchKernelGGL(leaf_kernel<double>, dim3(lblocks), dim3(64 * kLeafWaves),
                          0, s, (const double*)X, d, p.perm, p.nj, p.off,
-                         p.leaf_off, k, dirty, p.leafsum, conv, iter);
+                         p.leaf_off, k, dirty, p.leafsum, conv, iter, vec);
       break;
     case KNOR_F32:
       hipLaunchKernelGGL(leaf_kernel<float>, dim3(lblocks), dim3(64 * kLeafWaves),
                          0, s, (const float*)X, d, p.perm, p.nj, p.off,
-                         p.leaf_off, k, dirty, p.leafsum, conv, iter);
+                         p.leaf_off, k, dirty, p.leafsum, conv, iter, vec);
       break;
     case KNOR_BF16:
       hipLaunchKernelGGL(leaf_kernel<uint16_t>, dim3(lblocks), dim3(64 * kLeafWaves),
                          0, s, (const uint16_t*)X, d, p.perm, p.nj, p.off,
-                         p.leaf_off, k, dirty, p.leafsum, conv, iter);
+                         p.leaf_off, k, dirty, p.leafsum, conv, iter, vec);
       break;
   }
   if (prof) { prof->end(); prof->begin(KNOR_PROF_TREE); }
