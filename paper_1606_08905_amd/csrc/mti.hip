@@ -87,7 +87,7 @@ __global__ __launch_bounds__(kFilterThreads) void mti_filter_kernel(
     int* __restrict__ list, int* __restrict__ seg_cnt,
     const unsigned long long* __restrict__ prev_row,
     unsigned long long* __restrict__ row, const int* __restrict__ conv,
-    int iter) {
+    int iter, int vec) {
   __shared__ int candA[kSeg];
   __shared__ int nA, nB;
   if (*conv < iter) return;
@@ -98,26 +98,58 @@ __global__ __launch_bounds__(kFilterThreads) void mti_filter_kernel(
   if (tighten && seg == 0 && threadIdx.x == 0) row[ROW_TIGHTEN] = 1;
   __syncthreads();
 
-  // Clause 1 with the drift-updated bound, for every point of the segment
-  for (int i = 0; i < kSeg / kFilterThreads; ++i) {
-    const int64_t p = p0 + i * kFilterThreads + threadIdx.x;
-    bool cand = false;
-    if (p < n) {
-      const int a = labels[p];
-      const double ub = f32_up(((double)u[p] + (double)drift[a]) * (1.0 + 8.881784197001252e-16));
-      if (ub * (1.0 + kEta) < (double)s_half[a]) {
-        u[p] = (float)ub;
-      } else {
-        cand = true;
+  // Clause 1 with the drift-updated bound, for every point of the segment:
+  // thread t owns points 4t .. 4t + 3 of the segment (16-byte loads of
+  // labels and bounds, then the per-label gathers, then one 16-byte store)
+  static_assert(kSeg == 4 * kFilterThreads, "four points per thread");
+  {
+    const int64_t pb = p0 + 4 * threadIdx.x;
+    int lab[4];
+    float uu[4];
+    // the caller's label array may be only 4-byte aligned
+    const bool full = pb + 3 < n && (((uintptr_t)labels & 15) == 0);
+    if (full) {
+      const int4 l4 = *reinterpret_cast<const int4*>(labels + pb);
+      const float4 u4 = *reinterpret_cast<const float4*>(u + pb);
+      lab[0] = l4.x; lab[1] = l4.y; lab[2] = l4.z; lab[3] = l4.w;
+      uu[0] = u4.x; uu[1] = u4.y; uu[2] = u4.z; uu[3] = u4.w;
+    } else {
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        lab[e] = pb + e < n ? labels[pb + e] : 0;
+        uu[e] = pb + e < n ? u[pb + e] : 0.0f;
       }
     }
-    uint64_t m = __ballot(cand);
-    if (m) {
-      int base = 0;
-      if (lane_id() == __ffsll((unsigned long long)m) - 1)
-        base = atomicAdd(&nA, __popcll(m));            // LDS atomic
-      base = __shfl(base, __ffsll((unsigned long long)m) - 1);
-      if (cand) candA[base + __popcll(m & lanemask_lt())] = (int)p;
+    float dr[4], sh[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) { dr[e] = drift[lab[e]]; sh[e] = s_half[lab[e]]; }
+    bool cand[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      cand[e] = false;
+      if (pb + e < n) {
+        const double ub = f32_up(((double)uu[e] + (double)dr[e]) * (1.0 + 8.881784197001252e-16));
+        if (ub * (1.0 + kEta) < (double)sh[e]) uu[e] = (float)ub;
+        else cand[e] = true;
+      }
+    }
+    if (full) {
+      *reinterpret_cast<float4*>(u + pb) = make_float4(uu[0], uu[1], uu[2], uu[3]);
+    } else {
+#pragma unroll
+      for (int e = 0; e < 4; ++e)
+        if (pb + e < n) u[pb + e] = uu[e];
+    }
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const uint64_t m = __ballot(cand[e]);
+      if (m) {
+        int base = 0;
+        if (lane_id() == __ffsll((unsigned long long)m) - 1)
+          base = atomicAdd(&nA, __popcll(m));          // LDS atomic
+        base = __shfl(base, __ffsll((unsigned long long)m) - 1);
+        if (cand[e]) candA[base + __popcll(m & lanemask_lt())] = (int)(pb + e);
+      }
     }
   }
   __syncthreads();
@@ -148,9 +180,23 @@ __global__ __launch_bounds__(kFilterThreads) void mti_filter_kernel(
     if (live) {
       const T* x = X + (size_t)p * d;
       const double* ca = C64 + (size_t)a * d;
-      for (int dim = r; dim < d; dim += kTightenLanes) {
-        double t = to_f64<T>(x[dim]) - ca[dim];
-        part = part + t * t;
+      constexpr int kE = 16 / (int)sizeof(T);      // elements per 16 bytes
+      if (vec) {
+        // lane r takes the 16-byte pieces r, r + 8, ... of the row
+        for (int v = r; v * kE < d; v += kTightenLanes) {
+          const uint4 w = reinterpret_cast<const uint4*>(x)[v];
+          const T* e = reinterpret_cast<const T*>(&w);
+#pragma unroll
+          for (int q = 0; q < kE; ++q) {
+            const double t = to_f64<T>(e[q]) - ca[v * kE + q];
+            part = part + t * t;
+          }
+        }
+      } else {
+        for (int dim = r; dim < d; dim += kTightenLanes) {
+          const double t = to_f64<T>(x[dim]) - ca[dim];
+          part = part + t * t;
+        }
       }
     }
 #pragma unroll
@@ -189,24 +235,26 @@ hipError_t launch_mti_filter(const void* X, knor_dtype dt, int64_t n, int d,
                              unsigned long long* row, const int* conv,
                              int iter, hipStream_t s) {
   const int nseg = nseg_of_n(n);
+  const size_t esz = dt == KNOR_F64 ? 8 : (dt == KNOR_F32 ? 4 : 2);
+  const int vec = (int)(((size_t)d * esz) % 16 == 0 && ((uintptr_t)X & 15) == 0);
   switch (dt) {
     case KNOR_F64:
       hipLaunchKernelGGL(mti_filter_kernel<double>, dim3(nseg),
                          dim3(kFilterThreads), 0, s, (const double*)X, n, d,
                          C64, labels, u, drift, s_half, list, seg_cnt,
-                         prev_row, row, conv, iter);
+                         prev_row, row, conv, iter, vec);
       break;
     case KNOR_F32:
       hipLaunchKernelGGL(mti_filter_kernel<float>, dim3(nseg),
                          dim3(kFilterThreads), 0, s, (const float*)X, n, d, C64,
                          labels, u, drift, s_half, list, seg_cnt, prev_row, row,
-                         conv, iter);
+                         conv, iter, vec);
       break;
     case KNOR_BF16:
       hipLaunchKernelGGL(mti_filter_kernel<uint16_t>, dim3(nseg),
                          dim3(kFilterThreads), 0, s, (const uint16_t*)X, n, d,
                          C64, labels, u, drift, s_half, list, seg_cnt,
-                         prev_row, row, conv, iter);
+                         prev_row, row, conv, iter, vec);
       break;
   }
   return hipGetLastError();
