@@ -32,6 +32,9 @@
  *    knor_fit returns after it finishes, because it observes convergence.
  *  - Argument errors are detected before any device work is enqueued; on
  *    every error return, the output arrays are left untouched.
+ *  - knor_assign and knor_update accept n = 0 (X and the label array may
+ *    then be NULL): assign does nothing; update copies C_prev to C_out and
+ *    writes zero counts.
  *  - Limits: 1 <= d <= 256, 1 <= k <= 16384, 1 <= n < 2^31, k <= n (fit).
  *  - The library keeps no global mutable state; concurrent calls on
  *    different streams are independent.

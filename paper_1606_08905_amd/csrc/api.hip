@@ -974,7 +974,8 @@ knor_status knor_assign(const void* X, knor_dtype dt, int64_t n, int32_t d,
                         int32_t* labels_out, double* dist2_out) {
   Opts o;
   if (knor_status r = read_opts(opts, &o)) return r;
-  if (!X || !C || !labels_out || !dtype_ok(dt)) return KNOR_ERR_INVALID_ARG;
+  // X and labels_out may be NULL when n == 0
+  if ((n > 0 && (!X || !labels_out)) || !C || !dtype_ok(dt)) return KNOR_ERR_INVALID_ARG;
   if (n < 0 || n >= (int64_t)1 << 31 || d < 1 || d > kMaxD || k < 1 || k > kMaxK)
     return KNOR_ERR_INVALID_ARG;
   if (n == 0) return KNOR_OK;
@@ -1018,7 +1019,8 @@ knor_status knor_update(const void* X, knor_dtype dt, int64_t n, int32_t d,
                         int64_t* counts_out) {
   Opts o;
   if (knor_status r = read_opts(opts, &o)) return r;
-  if (!X || !labels || !C_prev || !C_out || !dtype_ok(dt))
+  // X and labels may be NULL when n == 0
+  if ((n > 0 && (!X || !labels)) || !C_prev || !C_out || !dtype_ok(dt))
     return KNOR_ERR_INVALID_ARG;
   if (n < 0 || n >= (int64_t)1 << 31 || d < 1 || d > kMaxD || k < 1 || k > kMaxK)
     return KNOR_ERR_INVALID_ARG;

@@ -132,3 +132,38 @@ def test_fit_batched_rejects_per_call_arrays(L):
     o.label_history = 0x1000
     arr = (knor.Problem * 1)(_problem())
     assert L.knor_fit_batched(arr, 1, ctypes.byref(o), None) == knor.KNOR_ERR_INVALID_ARG
+
+
+def test_mlp_entry_points_validate(L):
+    P = ctypes.c_void_p(0x1000)
+    assert L.knor_mlp_param_count(32, 256, 4096) == 1126912
+    for bad in [(0, 256, 10), (300, 256, 10), (8, 100, 10), (8, 32, 0), (8, 32, 20000)]:
+        assert L.knor_mlp_param_count(*bad) == -1
+        assert L.knor_mlp_init(P, *bad, 0, None) == knor.KNOR_ERR_INVALID_ARG
+    assert L.knor_mlp_init(None, 8, 32, 10, 0, None) == knor.KNOR_ERR_INVALID_ARG
+    # train step: missing arrays, batch 0, negative lr, Adam without state
+    assert L.knor_mlp_train_step(P, P, P, 1, 8, 32, 10, None, P, 4, 1e-3, None, None,
+                                 None) == knor.KNOR_ERR_INVALID_ARG
+    assert L.knor_mlp_train_step(P, P, P, 1, 8, 32, 10, P, P, 0, 1e-3, None, None,
+                                 None) == knor.KNOR_ERR_INVALID_ARG
+    assert L.knor_mlp_train_step(P, P, P, 1, 8, 32, 10, P, P, 4, -1.0, None, None,
+                                 None) == knor.KNOR_ERR_INVALID_ARG
+    assert L.knor_mlp_train_step(P, None, P, 1, 8, 32, 10, P, P, 4, 1e-3, None, None,
+                                 None) == knor.KNOR_ERR_INVALID_ARG
+    assert L.knor_mlp_train_step(P, P, P, 0, 8, 32, 10, P, P, 4, 1e-3, None, None,
+                                 None) == knor.KNOR_ERR_INVALID_ARG
+    assert L.knor_mlp_propose(P, 8, 32, 10, P, -1, P, None) == knor.KNOR_ERR_INVALID_ARG
+    assert L.knor_mlp_propose(P, 8, 32, 10, P, 0, P, None) == knor.KNOR_OK
+    assert L.knor_mlp_propose(None, 8, 32, 10, P, 5, P, None) == knor.KNOR_ERR_INVALID_ARG
+
+
+def test_learned_needs_valid_options(L):
+    o = knor.Opts()
+    o.struct_size = ctypes.sizeof(knor.Opts)
+    o.prune = 1
+    o.recheck = 1
+    o.check_numeric = 1
+    for field, value in (("learned", 2), ("train_iters", -1), ("train_batches", -3)):
+        setattr(o, field, value)
+        assert _fit(L, opts=ctypes.byref(o)) == knor.KNOR_ERR_INVALID_ARG
+        setattr(o, field, 0)

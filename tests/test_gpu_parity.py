@@ -518,3 +518,46 @@ def test_learned_fit_exact_and_certifies(k):
         assert st["certified"] > 0
     print("learned-fit k", k, "queries", st["mlp_queries"], "certified", st["certified"],
           flush=True)
+
+
+# ---------------------------------------------------------------------------
+# edge cases
+# ---------------------------------------------------------------------------
+
+def test_largest_k():
+    """k = 16384 (the limit): assignment and a short fit against the oracle."""
+    knor = _knor()
+    rng = np.random.default_rng(11)
+    X = rng.normal(size=(40000, 8)).astype(np.float32)
+    C0 = X[:16384].astype(np.float64)
+    lab_o, D_o = oracle.assign(X.astype(np.float64), C0)
+    lab, dd = knor.assign(_dev(X, "f32"), _dev(C0, "f64"), dist2=True)
+    assert (lab.cpu().numpy() == lab_o).all() and (dd.cpu().numpy() == D_o).all()
+    _fit_compare(X, "f32", C0, 16384, 3, True, oracle_fit=oracle.mti_fit)
+
+
+def test_empty_inputs():
+    import torch
+    knor = _knor()
+    for dt in ("f32", "f64", "bf16"):
+        X = _dev(workloads.cast(np.zeros((0, 5)), dt), dt)
+        C = torch.ones((3, 5), dtype=torch.float64, device="cuda")
+        lab = knor.assign(X, C)
+        assert lab.shape == (0,)
+        Cn, cnt = knor.update(X, torch.zeros((0,), dtype=torch.int32, device="cuda"), C)
+        assert (Cn == C).all() and (cnt == 0).all()
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64", "bf16"])
+def test_degenerate_data(dtype):
+    """All points identical (every distance ties), all-zero points, and k=1:
+    labels, centroids and the stopping iteration match the oracle."""
+    rng = np.random.default_rng(12)
+    same = workloads.cast(np.tile(rng.normal(size=(1, 6)), (3000, 1)), dtype)
+    C0 = np.tile(workloads.to_f64(same[:1], dtype), (5, 1))
+    C0[2:] += rng.normal(size=(3, 6))
+    _fit_compare(same, dtype, C0, 5, 10, True, oracle_fit=oracle.mti_fit)
+    zero = workloads.cast(np.zeros((2000, 9)), dtype)
+    _fit_compare(zero, dtype, rng.normal(size=(4, 9)), 4, 10, True, oracle_fit=oracle.mti_fit)
+    X = workloads.cast(rng.normal(size=(5000, 40)) * 3, dtype)
+    _fit_compare(X, dtype, workloads.to_f64(X[:1], dtype), 1, 5, True, oracle_fit=oracle.mti_fit)
