@@ -18,7 +18,7 @@
 // inside the matrix core is covered; sum of magnitudes <= R^2 + 2.02|x|R),
 // the two-term representation of -2c, and subnormals flushed by the matrix
 // core.  The decision rule and the FP64 recheck of undecided points are the
-// FP32 tile's (tile_common.h).
+// FP32 tile's (tile_common.h); the two-candidate pass is not used here.
 //
 // Lane layout: lane l = 16 g + c supplies eight consecutive elements
 // [8g, 8g + 8) of the 32-element K-step for row c of A (a centroid) and
@@ -55,6 +55,42 @@ struct Bf16Tile {
   static constexpr int CK = bf_ck(DP);                 // chunk of centroids
   static constexpr int WUP = 16 * PB;                  // points per wave unit
   static constexpr int BUP = 4 * WUP;                  // points per block unit
+  // lane group g holds dimensions [32 s + 8 g, 32 s + 8 g + 8) of K-step s.
+  // The two-candidate pass stays off: with four point blocks per wave the
+  // third value and second index add registers that cost one wave per SIMD
+  // at dp = 64, which costs more than the full recheck it saves.
+  static constexpr bool PAIR = false;
+  static constexpr int NS = KS, NE = 8;
+  __device__ static constexpr int dim(int s, int g, int e) { return 32 * s + 8 * g + e; }
+  __device__ static double xval(const Frag (&bx)[KS], int s, int e) {
+    const uint4 v = __builtin_bit_cast(uint4, bx[s]);
+    const uint32_t wd = (e >> 1) == 0 ? v.x : ((e >> 1) == 1 ? v.y : ((e >> 1) == 2 ? v.z : v.w));
+    return (double)__uint_as_float((e & 1) ? (wd & 0xffff0000u) : (wd << 16));
+  }
+  // this lane group's dimensions of row p as B fragments (zero past d or
+  // when !valid)
+  __device__ static void load_row(Frag (&bx)[KS], const uint16_t* __restrict__ X,
+                                  int64_t p, int d, int grp, int vec, bool valid) {
+    const uint16_t* xr = X + (size_t)p * d;
+#pragma unroll
+    for (int s = 0; s < KS; ++s) {
+      const int d0 = s * 32 + grp * 8;
+      uint32_t wd[4];
+      if (valid && vec && d0 + 8 <= d) {
+        const uint4 v = *reinterpret_cast<const uint4*>(xr + d0);
+        wd[0] = v.x; wd[1] = v.y; wd[2] = v.z; wd[3] = v.w;
+      } else {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const uint32_t lo = (valid && d0 + 2 * e < d) ? xr[d0 + 2 * e] : 0u;
+          const uint32_t hi = (valid && d0 + 2 * e + 1 < d) ? xr[d0 + 2 * e + 1] : 0u;
+          wd[e] = lo | (hi << 16);
+        }
+      }
+      const uint4 v4 = {wd[0], wd[1], wd[2], wd[3]};
+      bx[s] = __builtin_bit_cast(bf8, v4);
+    }
+  }
   __device__ static double bound(double xn2, double R2, int) {
     const double u24 = 5.9604644775390625e-08;
     const double xn = sqrt(xn2), R = sqrt(R2);
@@ -124,37 +160,17 @@ __device__ __forceinline__ void load_points_bf(
     const int64_t p = w.valid[pb] ? (list ? (int64_t)list[base + q] : q) : 0;
     w.pid[pb] = p;
     w.old[pb] = (w.valid[pb] && (pb & 3) == grp) ? labels[p] : 0;
-    const uint16_t* xr = X + (size_t)p * d;
+    T::load_row(w.bx[pb], X, p, d, grp, vec, w.valid[pb]);
     double acc = 0.0;
 #pragma unroll
-    for (int s = 0; s < KS; ++s) {
-      const int d0 = s * 32 + grp * 8;
-      uint32_t wd[4];
-      if (w.valid[pb] && vec && d0 + 8 <= d) {
-        const uint4 v = *reinterpret_cast<const uint4*>(xr + d0);
-        wd[0] = v.x; wd[1] = v.y; wd[2] = v.z; wd[3] = v.w;
-      } else {
+    for (int s = 0; s < KS; ++s)
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const uint32_t lo = (w.valid[pb] && d0 + 2 * e < d) ? xr[d0 + 2 * e] : 0u;
-          const uint32_t hi = (w.valid[pb] && d0 + 2 * e + 1 < d) ? xr[d0 + 2 * e + 1] : 0u;
-          wd[e] = lo | (hi << 16);
-        }
+      for (int e = 0; e < 8; ++e) {
+        const double v = T::xval(w.bx[pb], s, e);
+        acc = acc + v * v;
       }
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const double a = (double)__uint_as_float(wd[e] << 16);
-        const double b = (double)__uint_as_float(wd[e] & 0xffff0000u);
-        acc = acc + a * a;
-        acc = acc + b * b;
-      }
-      const uint4 v4 = {wd[0], wd[1], wd[2], wd[3]};
-      w.bx[pb][s] = __builtin_bit_cast(bf8, v4);
-    }
     w.xs[pb] = acc;
-    w.b1[pb] = INFINITY;
-    w.b2[pb] = INFINITY;
-    w.i1[pb] = 0;
+    top3_reset(w.b1[pb], w.b2[pb], w.b3[pb], w.i1[pb], w.i2[pb]);
   }
 }
 
@@ -198,13 +214,8 @@ __device__ __forceinline__ void tile_block_bf(WaveState<T>& w,
 #pragma unroll
   for (int pb = 0; pb < PB; ++pb)
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const float y = acc[pb][r];
-      w.b2[pb] = __builtin_amdgcn_fmed3f(w.b1[pb], w.b2[pb], y);
-      const bool lt = y < w.b1[pb];
-      w.i1[pb] = lt ? (jb + r) : w.i1[pb];
-      w.b1[pb] = lt ? y : w.b1[pb];
-    }
+    for (int r = 0; r < 4; ++r)
+      top3_insert(w.b1[pb], w.b2[pb], w.b3[pb], w.i1[pb], w.i2[pb], acc[pb][r], jb + r);
 }
 
 template <class T>
@@ -253,20 +264,23 @@ __global__ __launch_bounds__(kTileThreads) void tile_bf16_resident_kernel(
     int* __restrict__ flags, int64_t cap, int* __restrict__ ucnt,
     unsigned long long* __restrict__ row, const int* __restrict__ conv,
     int iter, int* __restrict__ dirty, int recheck_all, int vec,
-    const double* __restrict__ CT, int tpf_max, int fuse_max, int vecx) {
+    const double* __restrict__ CT, const double* __restrict__ C64, int tpf_max,
+    int fuse_max, int vecx) {
   using T = Bf16Tile<DP>;
   constexpr int LDA = T::LDA, PB = T::PB, WUP = T::WUP;
   extern __shared__ __attribute__((aligned(16))) uint16_t smem_bf[];
-  __shared__ int sFlag;
+  __shared__ int sFlag, sPairN;
+  __shared__ int4 sPair[kPairCap];
   uint16_t* sH = smem_bf;
   uint16_t* sL = smem_bf + (size_t)kpad * LDA;
   float* sN = reinterpret_cast<float*>(smem_bf + (size_t)2 * kpad * LDA);
   if (*conv < iter) return;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int col = lane & 15, grp = lane >> 4;
+  const bool pairs = T::PAIR && C64 != nullptr;
 
   __shared__ int sSeg[kSegCache], sWmax[kTileThreads / 64];
-  if (threadIdx.x == 0) sFlag = 0;
+  if (threadIdx.x == 0) { sFlag = 0; sPairN = 0; }
   if (seg_cnt) seg_stage(seg_cnt, nseg, WUP, sSeg, sWmax);
   stage_bf<DP, LDA>(sH, sL, sN, Chi, Clo, cn, 0, kpad);
   __syncthreads();
@@ -286,8 +300,8 @@ __global__ __launch_bounds__(kTileThreads) void tile_bf16_resident_kernel(
     tile_sweep_bf<T>(w, sH, sL, sN, kpad, 0, col, grp);
     merge_groups<T>(w);
     bool flag[PB], changed;
-    finalize_points<T>(w, cmax, d, grp, recheck_all, labels, ub, dirty, flag,
-                       changed);
+    finalize_points<T>(w, cmax, d, grp, recheck_all, pairs, sPair, &sPairN,
+                       labels, ub, dirty, flag, changed);
     const int nf = append_flags<T>(w, flag, &sFlag, slice, lane);
     const int nc = __popcll(__ballot(changed));
     if (lane == 0) {
@@ -295,8 +309,12 @@ __global__ __launch_bounds__(kTileThreads) void tile_bf16_resident_kernel(
       tot_chg += nc;
     }
   }
+  __syncthreads();
+  const int np = sPairN < kPairCap ? sPairN : kPairCap;
+  if constexpr (T::PAIR)
+    if (np) tot_chg += resolve_pairs<T, uint16_t>(X, d, vec, C64, sPair, np, labels, ub, dirty);
   const int q[2] = {SLOT_FLAGGED, SLOT_CHANGED};
-  const unsigned long long v[2] = {tot_flag, tot_chg};
+  const unsigned long long v[2] = {tot_flag + (threadIdx.x == 0 ? np : 0), tot_chg};
   block_add_slots<2>(row, q, v);               // includes a barrier
   const int left = recheck_own_slice<uint16_t>(X, d, vecx, CT, k, tpf_max, fuse_max, slice,
                                          sFlag, labels, ub, dirty, row);
@@ -313,19 +331,22 @@ __global__ __launch_bounds__(kTileThreads) void tile_bf16_chunked_kernel(
     int* __restrict__ flags, int64_t cap, int* __restrict__ ucnt,
     unsigned long long* __restrict__ row, const int* __restrict__ conv,
     int iter, int* __restrict__ dirty, int recheck_all, int vec,
-    const double* __restrict__ CT, int tpf_max, int fuse_max, int vecx) {
+    const double* __restrict__ CT, const double* __restrict__ C64, int tpf_max,
+    int fuse_max, int vecx) {
   using T = Bf16Tile<DP>;
   constexpr int LDA = T::LDA, PB = T::PB, CK = T::CK, WUP = T::WUP, BUP = T::BUP;
   __shared__ __attribute__((aligned(16))) uint16_t sH[CK * LDA];
   __shared__ __attribute__((aligned(16))) uint16_t sL[CK * LDA];
   __shared__ __attribute__((aligned(16))) float sN[CK];
-  __shared__ int sFlag, sChg;
+  __shared__ int sFlag, sChg, sPairN;
+  __shared__ int4 sPair[kPairCap];
   if (*conv < iter) return;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int col = lane & 15, grp = lane >> 4;
+  const bool pairs = T::PAIR && C64 != nullptr;
   __shared__ int sSeg[kSegCache], sWmax[kTileThreads / 64];
   int64_t units = seg_cnt ? (int64_t)nseg * (kSeg / BUP) : (n + BUP - 1) / BUP;
-  if (threadIdx.x == 0) { sFlag = 0; sChg = 0; }
+  if (threadIdx.x == 0) { sFlag = 0; sChg = 0; sPairN = 0; }
   if (seg_cnt) seg_stage(seg_cnt, nseg, BUP, sSeg, sWmax);
   __syncthreads();
   if (seg_cnt) units = seg_units_bound(sWmax, nseg, units);
@@ -349,16 +370,20 @@ __global__ __launch_bounds__(kTileThreads) void tile_bf16_chunked_kernel(
     }
     merge_groups<T>(w);
     bool flag[PB], changed;
-    finalize_points<T>(w, cmax, d, grp, recheck_all, labels, ub, dirty, flag,
-                       changed);
+    finalize_points<T>(w, cmax, d, grp, recheck_all, pairs, sPair, &sPairN,
+                       labels, ub, dirty, flag, changed);
     append_flags<T>(w, flag, &sFlag, slice, lane);
     const uint64_t cm = __ballot(changed);
     if (cm && lane == 0) atomicAdd(&sChg, __popcll(cm));
   }
   __syncthreads();
+  const int np = sPairN < kPairCap ? sPairN : kPairCap;
+  unsigned long long pch = 0;
+  if constexpr (T::PAIR)
+    if (np) pch = resolve_pairs<T, uint16_t>(X, d, vec, C64, sPair, np, labels, ub, dirty);
   const int q[2] = {SLOT_FLAGGED, SLOT_CHANGED};
-  const unsigned long long v[2] = {threadIdx.x == 0 ? (unsigned long long)sFlag : 0ull,
-                                   threadIdx.x == 0 ? (unsigned long long)sChg : 0ull};
+  const unsigned long long v[2] = {threadIdx.x == 0 ? (unsigned long long)(sFlag + np) : 0ull,
+                                   (threadIdx.x == 0 ? (unsigned long long)sChg : 0ull) + pch};
   block_add_slots<2>(row, q, v);               // includes a barrier
   const int left = recheck_own_slice<uint16_t>(X, d, vecx, CT, k, tpf_max, fuse_max, slice,
                                          sFlag, labels, ub, dirty, row);
@@ -384,14 +409,14 @@ static hipError_t launch_bf_dp(const CentroidOps& o, const AssignJob& j,
                        lds, s, (const uint16_t*)j.X, j.n, j.d, o.Chi, o.Clo, o.cn,
                        o.k, o.kpad, j.list, j.seg_cnt, j.nseg, j.labels, j.u,
                        j.flags, g.cap, j.ucnt, j.row, j.conv, j.iter, j.dirty,
-                       j.recheck_all, vec, o.CT, fuse_tpf(o.k),
+                       j.recheck_all, vec, o.CT, o.C64, fuse_tpf(o.k),
                        j.recheck_all ? 0 : kFuseRecheckMax, vecx);
   } else {
     hipLaunchKernelGGL(tile_bf16_chunked_kernel<DP>, dim3(g.grid), dim3(kTileThreads),
                        0, s, (const uint16_t*)j.X, j.n, j.d, o.Chi, o.Clo, o.cn,
                        o.k, o.kpad, j.list, j.seg_cnt, j.nseg, j.labels, j.u,
                        j.flags, g.cap, j.ucnt, j.row, j.conv, j.iter, j.dirty,
-                       j.recheck_all, vec, o.CT, fuse_tpf(o.k),
+                       j.recheck_all, vec, o.CT, o.C64, fuse_tpf(o.k),
                        j.recheck_all ? 0 : kFuseRecheckMax, vecx);
   }
   return hipGetLastError();

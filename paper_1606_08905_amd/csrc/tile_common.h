@@ -1,5 +1,5 @@
 // Pieces shared by the matrix-core distance tiles (tile_f32.hip,
-// tile_bf16.hip): per-wave top-2 state, the merge of the four lane groups of
+// tile_bf16.hip): per-wave top-3 state, the merge of the four lane groups of
 // a 16x16 MFMA output, the decision of each point against the rounding
 // bound of its tile type, and the unit and recheck-slice bookkeeping.
 //
@@ -7,7 +7,10 @@
 // K-steps per row), Frag (one lane's B operand of one K-step) and
 // bound(xn2, R2) -> E, an upper bound on |y~_j - y_j| for every centroid j,
 // where y_j = |c_j|^2 - 2 x.c_j exactly and y~_j is the tile's value,
-// xn2 >= |x|^2 and R2 >= max_j |c_j|^2.
+// xn2 >= |x|^2 and R2 >= max_j |c_j|^2.  For the two-candidate FP64 pass it
+// also gives the dimension each lane group holds: NS steps of NE elements,
+// dim(s, g, e) and xval(bx, s, e) (the exact point value), such that the
+// order (s, g, e) is increasing dimension order; PAIR enables that pass.
 #pragma once
 
 #include <math.h>
@@ -25,17 +28,45 @@ __device__ __forceinline__ float fmax_nc(float a, float b) {
   return __builtin_amdgcn_fmed3f(a, b, INFINITY);
 }
 
-// Per-wave state for PB blocks of 16 points.
+// Per-wave state for PB blocks of 16 points: per point the three smallest
+// tile values b1 <= b2 <= b3 seen so far, the index of b1 and of b2.
 template <class T>
 struct WaveState {
   typename T::Frag bx[T::PB][T::KS];
   int64_t pid[T::PB];
   bool valid[T::PB];
   double xs[T::PB];
-  float b1[T::PB], b2[T::PB];
-  int i1[T::PB];
+  float b1[T::PB], b2[T::PB], b3[T::PB];
+  int i1[T::PB], i2[T::PB];
   int32_t old[T::PB];     // previous label (loaded with the point)
 };
+
+__device__ __forceinline__ void top3_reset(float& b1, float& b2, float& b3,
+                                           int& i1, int& i2) {
+  b1 = INFINITY; b2 = INFINITY; b3 = INFINITY;
+  i1 = 0; i2 = 0;
+}
+
+// Insert tile value y of centroid j (a lane visits its centroids in
+// increasing index, so a strict "<" keeps the lowest index on ties).
+// b3 and b2 are medians of three (for b1 <= b2 <= b3 the median of
+// (b2, b3, y) is the third smallest of {b1, b2, b3, y}).
+__device__ __forceinline__ void top3_insert(float& b1, float& b2, float& b3,
+                                            int& i1, int& i2, float y, int j) {
+  const bool lt1 = y < b1, lt2 = y < b2;
+  b3 = __builtin_amdgcn_fmed3f(b2, b3, y);
+  b2 = __builtin_amdgcn_fmed3f(b1, b2, y);
+  const int t = lt2 ? j : i2;
+  i2 = lt1 ? i1 : t;
+  i1 = lt1 ? j : i1;
+  b1 = lt1 ? y : b1;
+}
+
+__device__ __forceinline__ int wave_sum(int v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  return v;
+}
 
 // Largest fp32(|c|^2) over the real centroids of a staged chunk.
 __device__ __forceinline__ float chunk_cmax(const float* sN, int cc, int c0,
@@ -49,6 +80,9 @@ __device__ __forceinline__ float chunk_cmax(const float* sN, int cc, int c0,
 }
 
 // Combine the four lane groups (each saw a different quarter of centroids).
+// For two sorted triples a and o the union's second smallest is
+// min(max(a1, o1), a2, o2) and its third smallest is
+// min(a3, o3, max(a2, o1), max(a1, o2)).
 template <class T>
 __device__ __forceinline__ void merge_groups(WaveState<T>& w) {
   constexpr int PB = T::PB;
@@ -56,21 +90,78 @@ __device__ __forceinline__ void merge_groups(WaveState<T>& w) {
   for (int off = 16; off <= 32; off <<= 1) {
 #pragma unroll
     for (int pb = 0; pb < PB; ++pb) {
-      const float ob1 = __shfl_xor(w.b1[pb], off);
-      const float ob2 = __shfl_xor(w.b2[pb], off);
-      const int oi1 = __shfl_xor(w.i1[pb], off);
+      const float a1 = w.b1[pb], a2 = w.b2[pb], a3 = w.b3[pb];
+      const int ia1 = w.i1[pb], ia2 = w.i2[pb];
+      const float o1 = __shfl_xor(a1, off);
+      const float o2 = __shfl_xor(a2, off);
+      const float o3 = __shfl_xor(a3, off);
+      const int io1 = __shfl_xor(ia1, off);
+      const int io2 = __shfl_xor(ia2, off);
       w.xs[pb] += __shfl_xor(w.xs[pb], off);
-      // second best of the union: min(max(b1, ob1), min(b2, ob2))
-      const float hi = w.b1[pb] < ob1 ? ob1 : w.b1[pb];
-      const float lo2 = w.b2[pb] < ob2 ? w.b2[pb] : ob2;
-      const float nb2 = hi < lo2 ? hi : lo2;
-      const bool take = ob1 < w.b1[pb] || (ob1 == w.b1[pb] && oi1 < w.i1[pb]);
-      w.i1[pb] = take ? oi1 : w.i1[pb];
-      w.b1[pb] = take ? ob1 : w.b1[pb];
-      w.b2[pb] = nb2;
+      const bool take = o1 < a1 || (o1 == a1 && io1 < ia1);
+      // second: after a1 comes min(a2, o1); after o1 comes min(a1, o2)
+      const float s_a = o1 < a2 ? o1 : a2;
+      const int is_a = o1 < a2 ? io1 : ia2;
+      const float s_o = a1 <= o2 ? a1 : o2;
+      const int is_o = a1 <= o2 ? ia1 : io2;
+      const float m21 = a2 < o1 ? o1 : a2, m12 = a1 < o2 ? o2 : a1;
+      float t3 = a3 < o3 ? a3 : o3;
+      t3 = t3 < m21 ? t3 : m21;
+      t3 = t3 < m12 ? t3 : m12;
+      w.b1[pb] = take ? o1 : a1;
+      w.i1[pb] = take ? io1 : ia1;
+      w.b2[pb] = take ? s_o : s_a;
+      w.i2[pb] = take ? is_o : is_a;
+      w.b3[pb] = t3;
     }
   }
 }
+
+// Canonical FP64 squared distance D(x, c_j) of the point in column
+// `lane & 15` (every lane returns the value of its column).  The sum runs
+// in increasing dimension order as one chain: the lane group holding the
+// next dimensions continues the running sum, which moves to it with a lane
+// rotation by 16 after each group's part.  Each lane first loads its own
+// dimensions of c_j (one memory round trip).
+template <class T>
+__device__ __forceinline__ double chain_dist(const typename T::Frag (&bx)[T::KS],
+                                             bool need, int j,
+                                             const double* __restrict__ C64, int d,
+                                             int grp, int lane) {
+  constexpr int NS = T::NS, NE = T::NE;
+  double c[NS][NE];
+#pragma unroll
+  for (int s = 0; s < NS; ++s)
+#pragma unroll
+    for (int e = 0; e < NE; ++e) {
+      const int dim = T::dim(s, grp, e);
+      c[s][e] = (need && dim < d) ? C64[(size_t)j * d + dim] : 0.0;
+    }
+  double a = 0.0;
+  const int from = (lane + 48) & 63;          // the lane 16 below, cyclically
+#pragma unroll
+  for (int s = 0; s < NS; ++s)
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+      if (grp == g && need) {
+#pragma unroll
+        for (int e = 0; e < NE; ++e) {
+          if (T::dim(s, g, e) < d) {
+            const double t = __dsub_rn(T::xval(bx, s, e), c[s][e]);
+            a = __dadd_rn(a, __dmul_rn(t, t));
+          }
+        }
+      }
+      a = __shfl(a, from);
+    }
+  // after the last group's part the sum sits in lane group 0
+  return __shfl(a, lane & 15);
+}
+
+// Points resolved from two canonical distances after the workgroup's last
+// unit: (point, best index, second index, previous label), in LDS.  A point
+// that finds the list full goes to the full FP64 recheck instead.
+constexpr int kPairCap = 128;
 
 // Decide each point (lane group g finalises point block pb with pb % 4 == g).
 // With E the tile's error bound, the point is decided iff
@@ -78,12 +169,17 @@ __device__ __forceinline__ void merge_groups(WaveState<T>& w) {
 // every other centroid's exact squared distance then exceeds the chosen
 // one's by more than the FP64 evaluation error of the definition, so the
 // FP64 argmin (with its lowest-index rule) picks the same centroid.
-// Writes labels / bounds of decided points; returns per-block flags.
+// If instead only the third smallest value clears that margin, every
+// centroid other than the two best is excluded the same way, and the FP64
+// argmin over all centroids is the FP64 argmin of those two: the point is
+// queued for resolve_pairs().  Writes labels / bounds of decided points;
+// returns per-block flags for the full FP64 recheck.
 template <class T>
 __device__ __forceinline__ void finalize_points(
-    WaveState<T>& w, float cmax, int d, int grp, int recheck_all,
-    int32_t* __restrict__ labels, float* __restrict__ ub, int* __restrict__ dirty,
-    bool (&flag)[T::PB], bool& changed) {
+    WaveState<T>& w, float cmax, int d, int grp, int recheck_all, bool pairs,
+    int4* sPair, int* sPairN, int32_t* __restrict__ labels,
+    float* __restrict__ ub, int* __restrict__ dirty, bool (&flag)[T::PB],
+    bool& changed) {
   constexpr int PB = T::PB;
   static_assert(PB <= 4, "one finalised point per lane");
   // R2 >= max |c|^2: cmax is the largest fp32(|c|^2), within 2^-24 of it
@@ -93,27 +189,85 @@ __device__ __forceinline__ void finalize_points(
 #pragma unroll
   for (int pb = 0; pb < PB; ++pb) {
     flag[pb] = false;
-    if (!(w.valid[pb] && (pb & 3) == grp)) continue;
-    // xs sums exact squares in FP64: at most (d+4) roundings of 2^-53
-    const double xn2 = w.xs[pb] * (1.0 + (double)(d + 4) * 2.220446049250313e-16);
-    const double E = T::bound(xn2, R2, d);
-    const double y1 = (double)w.b1[pb], y2 = (double)w.b2[pb];
-    double dbest = xn2 + y1 + E;
-    if (!(dbest > 0.0)) dbest = 0.0;
-    const double thr = 2.0 * E + 2.01 * e64 * dbest;
-    const double gap = y2 - y1;
-    flag[pb] = recheck_all || !(gap > thr);
-    if (!flag[pb]) {
-      const int64_t p = w.pid[pb];
-      const int32_t old = w.old[pb];
-      labels[p] = w.i1[pb];
-      if (old != w.i1[pb]) {
-        changed = true;
-        mark_dirty(dirty, old, w.i1[pb]);
+    const bool own = w.valid[pb] && (pb & 3) == grp;
+    bool decided = false, pair = false;
+    double dbest = 0.0;
+    if (own) {
+      // xs sums exact squares in FP64: at most (d+4) roundings of 2^-53
+      const double xn2 = w.xs[pb] * (1.0 + (double)(d + 4) * 2.220446049250313e-16);
+      const double E = T::bound(xn2, R2, d);
+      const double y1 = (double)w.b1[pb];
+      dbest = xn2 + y1 + E;
+      if (!(dbest > 0.0)) dbest = 0.0;
+      const double thr = 2.0 * E + 2.01 * e64 * dbest;
+      decided = !recheck_all && (double)w.b2[pb] - y1 > thr;
+      pair = pairs && !recheck_all && !decided && (double)w.b3[pb] - y1 > thr;
+    }
+    if (pairs) {
+      const uint64_t m = __ballot(pair);
+      if (m) {
+        const int leader = __ffsll((unsigned long long)m) - 1;
+        int base = 0;
+        if (lane_id() == leader) base = atomicAdd(sPairN, __popcll(m));   // LDS
+        base = __shfl(base, leader);
+        if (pair) {
+          const int slot = base + __popcll(m & lanemask_lt());
+          if (slot < kPairCap)
+            sPair[slot] = make_int4((int)w.pid[pb], w.i1[pb], w.i2[pb], w.old[pb]);
+          else
+            pair = false;                      // list full: full recheck
+        }
       }
-      if (ub) ub[p] = f32_up(sqrt(dbest) * (1.0 + 8.881784197001252e-16));
+    }
+    if (!own) continue;
+    flag[pb] = !decided && !pair;
+    if (!decided) continue;
+    const int64_t p = w.pid[pb];
+    const int32_t old = w.old[pb];
+    labels[p] = w.i1[pb];
+    if (old != w.i1[pb]) {
+      changed = true;
+      mark_dirty(dirty, old, w.i1[pb]);
+    }
+    if (ub) ub[p] = f32_up(sqrt(dbest) * (1.0 + 8.881784197001252e-16));
+  }
+}
+
+// The queued two-candidate points (after a barrier; every thread calls this
+// with the same count np <= kPairCap): each wave takes 16 at a time in the
+// tile's lane layout, loads their rows and both centroids' FP64 values, and
+// the owner lane keeps the lower canonical distance (lower index on a tie).
+// Returns this thread's count of changed labels.
+template <class T, typename X_T>
+__device__ __forceinline__ unsigned long long resolve_pairs(
+    const X_T* __restrict__ X, int d, int vec, const double* __restrict__ C64,
+    const int4* sPair, int np, int32_t* __restrict__ labels,
+    float* __restrict__ ub, int* __restrict__ dirty) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int col = lane & 15, grp = lane >> 4;
+  unsigned long long chg = 0;
+  for (int e0 = wave * 16; e0 < np; e0 += kTileThreads / 4) {
+    const int e = e0 + col;
+    const bool need = e < np;
+    const int4 q = need ? sPair[e] : make_int4(0, 0, 0, 0);
+    typename T::Frag bx[T::KS];
+    T::load_row(bx, X, (int64_t)q.x, d, grp, vec, need);
+    const double D1 = chain_dist<T>(bx, need, q.y, C64, d, grp, lane);
+    const double D2 = chain_dist<T>(bx, need, q.z, C64, d, grp, lane);
+    if (need && grp == 0) {
+      const bool second = D2 < D1 || (D2 == D1 && q.z < q.y);
+      const int a = second ? q.z : q.y;
+      labels[q.x] = a;
+      if (q.w != a) {
+        ++chg;
+        mark_dirty(dirty, q.w, a);
+      }
+      if (ub)
+        ub[q.x] = f32_up(sqrt(second ? D2 : D1) *
+                         (1.0 + (double)(d + 4) * 2.220446049250313e-16));
     }
   }
+  return chg;
 }
 
 // Unit -> (range of points) of a dense or segmented pass.  Segmented units

@@ -22,8 +22,11 @@
 // tile iff  y_2nd - y_best > 2E + 2.01 (d+2) 2^-53 (|x|^2 + y_best + E):
 // then every other centroid's exact squared distance exceeds the best one's
 // by more than the FP64 evaluation error of the definition, so the FP64
-// argmin (and its lowest-index rule) must select the same centroid.  Every
-// other point goes to its workgroup's slice of the FP64 recheck list.
+// argmin (and its lowest-index rule) must select the same centroid.  A point
+// for which only the third smallest clears that margin is resolved after
+// the workgroup's last unit from the canonical FP64 distances to its two
+// best centroids.  Every other point goes to its workgroup's slice of the
+// FP64 recheck list.
 //
 // Two schedules:
 //  resident  all centroids fit in LDS: staged once per workgroup, then each
@@ -48,6 +51,24 @@ static_assert(kResidentGrid <= kTileMaxGrid, "grid bound");
 constexpr int res_pb(int dp) { return dp >= 128 ? 1 : 2; }
 constexpr int chk_pb(int dp) { return dp >= 256 ? 1 : (dp >= 128 ? 2 : 4); }
 
+template <int KS>
+__device__ __forceinline__ void load_slice(float (&dst)[KS], const float* src) {
+  if constexpr (KS % 4 == 0) {
+#pragma unroll
+    for (int s = 0; s < KS; s += 4) {
+      float4 v = *reinterpret_cast<const float4*>(src + s);
+      dst[s] = v.x; dst[s + 1] = v.y; dst[s + 2] = v.z; dst[s + 3] = v.w;
+    }
+  } else {
+    static_assert(KS % 2 == 0, "slice width");
+#pragma unroll
+    for (int s = 0; s < KS; s += 2) {
+      float2 v = *reinterpret_cast<const float2*>(src + s);
+      dst[s] = v.x; dst[s + 1] = v.y;
+    }
+  }
+}
+
 template <int DP, int PB_>
 struct F32Tile {
   using Frag = float;
@@ -57,6 +78,27 @@ struct F32Tile {
   static constexpr int CK = (4096 / DP) < 16 ? 16 : (4096 / DP);
   static constexpr int WUP = 16 * PB;                  // points per wave unit
   static constexpr int BUP = 4 * WUP;                  // points per block unit
+  // lane group g holds dimensions [g KS, (g + 1) KS): one step of KS
+  static constexpr bool PAIR = KS <= 16;
+  static constexpr int NS = 1, NE = KS;
+  __device__ static constexpr int dim(int, int g, int e) { return g * KS + e; }
+  __device__ static double xval(const Frag (&bx)[KS], int, int e) {
+    return (double)bx[e];
+  }
+  // this lane group's dimensions of row p (zero past d or when !valid)
+  __device__ static void load_row(Frag (&bx)[KS], const float* __restrict__ X,
+                                  int64_t p, int d, int grp, int vec, bool valid) {
+    const float* xr = X + (size_t)p * d + grp * KS;
+    if (valid && vec) {
+      load_slice<KS>(bx, xr);
+    } else {
+#pragma unroll
+      for (int s = 0; s < KS; ++s) {
+        const int dim = grp * KS + s;
+        bx[s] = (valid && dim < d) ? xr[s] : 0.0f;
+      }
+    }
+  }
   // u = 2^-24.  Rounding c to FP32 (2u|x||c| after the -2 scaling), |c|^2
   // to FP32 (u R^2), each of the d products and d+1 accumulation steps at
   // 2u of the running magnitude; plus 2^-100 (1 + R) for subnormals flushed
@@ -122,24 +164,6 @@ int64_t tile_flag_capacity(const CentroidOps& o, knor_dtype dt, int64_t n,
   return ca > cb ? ca : cb;
 }
 
-template <int KS>
-__device__ __forceinline__ void load_slice(float (&dst)[KS], const float* src) {
-  if constexpr (KS % 4 == 0) {
-#pragma unroll
-    for (int s = 0; s < KS; s += 4) {
-      float4 v = *reinterpret_cast<const float4*>(src + s);
-      dst[s] = v.x; dst[s + 1] = v.y; dst[s + 2] = v.z; dst[s + 3] = v.w;
-    }
-  } else {
-    static_assert(KS % 2 == 0, "slice width");
-#pragma unroll
-    for (int s = 0; s < KS; s += 2) {
-      float2 v = *reinterpret_cast<const float2*>(src + s);
-      dst[s] = v.x; dst[s + 1] = v.y;
-    }
-  }
-}
-
 // Load the wave's points q0 + pb*16 + col (pb < PB) of a range of length m;
 // with a list, point = list[base + q].  The lane group that will finalise a
 // point block also fetches the points' previous labels here, so that the
@@ -159,16 +183,7 @@ __device__ __forceinline__ void load_points(WaveState<T>& w,
     const int64_t p = w.valid[pb] ? (list ? (int64_t)list[base + q] : q) : 0;
     w.pid[pb] = p;
     w.old[pb] = (w.valid[pb] && (pb & 3) == grp) ? labels[p] : 0;
-    const float* xr = X + (size_t)p * d + grp * KS;
-    if (w.valid[pb] && vec) {
-      load_slice<KS>(w.bx[pb], xr);
-    } else {
-#pragma unroll
-      for (int s = 0; s < KS; ++s) {
-        const int dim = grp * KS + s;
-        w.bx[pb][s] = (w.valid[pb] && dim < d) ? xr[s] : 0.0f;
-      }
-    }
+    T::load_row(w.bx[pb], X, p, d, grp, vec, w.valid[pb]);
     double acc = 0.0;
 #pragma unroll
     for (int s = 0; s < KS; ++s) {
@@ -176,9 +191,7 @@ __device__ __forceinline__ void load_points(WaveState<T>& w,
       acc = acc + v * v;
     }
     w.xs[pb] = acc;
-    w.b1[pb] = INFINITY;
-    w.b2[pb] = INFINITY;
-    w.i1[pb] = 0;
+    top3_reset(w.b1[pb], w.b2[pb], w.b3[pb], w.i1[pb], w.i2[pb]);
   }
 }
 
@@ -199,8 +212,8 @@ __device__ __forceinline__ void load_ablock(ABlock<T>& o, const float* arow,
 
 // One block of 16 centroids against the wave's PB point blocks.  The PB
 // accumulation chains are interleaved so consecutive matrix instructions are
-// independent.  Epilogue per value: second-best = med3(best, second, y),
-// then best and its index by one compare and two selects.
+// independent.  Epilogue per value: the three smallest values by two
+// medians of three, and the indices of the two smallest by three selects.
 template <class T>
 __device__ __forceinline__ void tile_block(WaveState<T>& w, const ABlock<T>& o,
                                            int jb) {
@@ -216,13 +229,8 @@ __device__ __forceinline__ void tile_block(WaveState<T>& w, const ABlock<T>& o,
 #pragma unroll
   for (int pb = 0; pb < PB; ++pb)
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const float y = acc[pb][r];
-      w.b2[pb] = __builtin_amdgcn_fmed3f(w.b1[pb], w.b2[pb], y);
-      const bool lt = y < w.b1[pb];
-      w.i1[pb] = lt ? (jb + r) : w.i1[pb];
-      w.b1[pb] = lt ? y : w.b1[pb];
-    }
+    for (int r = 0; r < 4; ++r)
+      top3_insert(w.b1[pb], w.b2[pb], w.b3[pb], w.i1[pb], w.i2[pb], acc[pb][r], jb + r);
 }
 
 // All centroid blocks [c0, c0 + cc) staged at sC/sN, with the next block's
@@ -251,19 +259,22 @@ __global__ __launch_bounds__(kTileThreads) void tile_f32_resident_kernel(
     int* __restrict__ flags, int64_t cap, int* __restrict__ ucnt,
     unsigned long long* __restrict__ row, const int* __restrict__ conv,
     int iter, int* __restrict__ dirty, int recheck_all, int vec,
-    const double* __restrict__ CT, int tpf_max, int fuse_max, int vecx) {
+    const double* __restrict__ CT, const double* __restrict__ C64, int tpf_max,
+    int fuse_max, int vecx) {
   using T = F32Tile<DP, PB_>;
   constexpr int LDA = T::LDA, PB = T::PB, WUP = T::WUP;
   extern __shared__ __attribute__((aligned(16))) float smem[];
-  __shared__ int sFlag;
+  __shared__ int sFlag, sPairN;
+  __shared__ int4 sPair[kPairCap];
   float* sC = smem;
   float* sN = smem + (size_t)kpad * LDA;
   if (*conv < iter) return;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int col = lane & 15, grp = lane >> 4;
+  const bool pairs = T::PAIR && C64 != nullptr;
 
   __shared__ int sSeg[kSegCache], sWmax[kTileThreads / 64];
-  if (threadIdx.x == 0) sFlag = 0;
+  if (threadIdx.x == 0) { sFlag = 0; sPairN = 0; }
   if (seg_cnt) seg_stage(seg_cnt, nseg, WUP, sSeg, sWmax);
   for (int e = threadIdx.x; e < kpad * (DP / 4); e += kTileThreads) {
     const int r = e / (DP / 4), q4 = e - r * (DP / 4);
@@ -288,8 +299,8 @@ __global__ __launch_bounds__(kTileThreads) void tile_f32_resident_kernel(
     tile_sweep<T>(w, sC, sN, kpad, 0, col, grp);
     merge_groups<T>(w);
     bool flag[PB], changed;
-    finalize_points<T>(w, cmax, d, grp, recheck_all, labels, ub, dirty, flag,
-                       changed);
+    finalize_points<T>(w, cmax, d, grp, recheck_all, pairs, sPair, &sPairN,
+                       labels, ub, dirty, flag, changed);
     const int nf = append_flags<T>(w, flag, &sFlag, slice, lane);
     const int nc = __popcll(__ballot(changed));
     if (lane == 0) {
@@ -297,8 +308,12 @@ __global__ __launch_bounds__(kTileThreads) void tile_f32_resident_kernel(
       tot_chg += nc;
     }
   }
+  __syncthreads();
+  const int np = sPairN < kPairCap ? sPairN : kPairCap;
+  if constexpr (T::PAIR)
+    if (np) tot_chg += resolve_pairs<T, float>(X, d, vec, C64, sPair, np, labels, ub, dirty);
   const int q[2] = {SLOT_FLAGGED, SLOT_CHANGED};
-  const unsigned long long v[2] = {tot_flag, tot_chg};
+  const unsigned long long v[2] = {tot_flag + (threadIdx.x == 0 ? np : 0), tot_chg};
   block_add_slots<2>(row, q, v);               // includes a barrier
   const int left = recheck_own_slice<float>(X, d, vecx, CT, k, tpf_max, fuse_max, slice,
                                          sFlag, labels, ub, dirty, row);
@@ -314,18 +329,21 @@ __global__ __launch_bounds__(kTileThreads) void tile_f32_chunked_kernel(
     int* __restrict__ flags, int64_t cap, int* __restrict__ ucnt,
     unsigned long long* __restrict__ row, const int* __restrict__ conv,
     int iter, int* __restrict__ dirty, int recheck_all, int vec,
-    const double* __restrict__ CT, int tpf_max, int fuse_max, int vecx) {
+    const double* __restrict__ CT, const double* __restrict__ C64, int tpf_max,
+    int fuse_max, int vecx) {
   using T = F32Tile<DP, PB_>;
   constexpr int LDA = T::LDA, PB = T::PB, CK = T::CK, WUP = T::WUP, BUP = T::BUP;
   __shared__ __attribute__((aligned(16))) float sC[CK * LDA];
   __shared__ __attribute__((aligned(16))) float sN[CK];
-  __shared__ int sFlag, sChg;
+  __shared__ int sFlag, sChg, sPairN;
+  __shared__ int4 sPair[kPairCap];
   if (*conv < iter) return;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int col = lane & 15, grp = lane >> 4;
+  const bool pairs = T::PAIR && C64 != nullptr;
   __shared__ int sSeg[kSegCache], sWmax[kTileThreads / 64];
   int64_t units = seg_cnt ? (int64_t)nseg * (kSeg / BUP) : (n + BUP - 1) / BUP;
-  if (threadIdx.x == 0) { sFlag = 0; sChg = 0; }
+  if (threadIdx.x == 0) { sFlag = 0; sChg = 0; sPairN = 0; }
   if (seg_cnt) seg_stage(seg_cnt, nseg, BUP, sSeg, sWmax);
   __syncthreads();
   if (seg_cnt) units = seg_units_bound(sWmax, nseg, units);
@@ -354,16 +372,20 @@ __global__ __launch_bounds__(kTileThreads) void tile_f32_chunked_kernel(
     }
     merge_groups<T>(w);
     bool flag[PB], changed;
-    finalize_points<T>(w, cmax, d, grp, recheck_all, labels, ub, dirty, flag,
-                       changed);
+    finalize_points<T>(w, cmax, d, grp, recheck_all, pairs, sPair, &sPairN,
+                       labels, ub, dirty, flag, changed);
     append_flags<T>(w, flag, &sFlag, slice, lane);
     const uint64_t cm = __ballot(changed);
     if (cm && lane == 0) atomicAdd(&sChg, __popcll(cm));
   }
   __syncthreads();
+  const int np = sPairN < kPairCap ? sPairN : kPairCap;
+  unsigned long long pch = 0;
+  if constexpr (T::PAIR)
+    if (np) pch = resolve_pairs<T, float>(X, d, vec, C64, sPair, np, labels, ub, dirty);
   const int q[2] = {SLOT_FLAGGED, SLOT_CHANGED};
-  const unsigned long long v[2] = {threadIdx.x == 0 ? (unsigned long long)sFlag : 0ull,
-                                   threadIdx.x == 0 ? (unsigned long long)sChg : 0ull};
+  const unsigned long long v[2] = {threadIdx.x == 0 ? (unsigned long long)(sFlag + np) : 0ull,
+                                   (threadIdx.x == 0 ? (unsigned long long)sChg : 0ull) + pch};
   block_add_slots<2>(row, q, v);               // includes a barrier
   const int left = recheck_own_slice<float>(X, d, vecx, CT, k, tpf_max, fuse_max, slice,
                                          sFlag, labels, ub, dirty, row);
@@ -390,14 +412,14 @@ static hipError_t launch_dp_pb(const CentroidOps& o, const AssignJob& j,
                        dim3(kTileThreads), lds, s, (const float*)j.X, j.n, j.d,
                        o.Cm2, o.cn, o.k, o.kpad, j.list, j.seg_cnt, j.nseg,
                        j.labels, j.u, j.flags, g.cap, j.ucnt, j.row, j.conv,
-                       j.iter, j.dirty, j.recheck_all, vec, o.CT, fuse_tpf(o.k),
+                       j.iter, j.dirty, j.recheck_all, vec, o.CT, o.C64, fuse_tpf(o.k),
                        j.recheck_all ? 0 : kFuseRecheckMax, vecx);
   } else {
     hipLaunchKernelGGL((tile_f32_chunked_kernel<DP, PB>), dim3(g.grid),
                        dim3(kTileThreads), 0, s, (const float*)j.X, j.n, j.d,
                        o.Cm2, o.cn, o.k, o.kpad, j.list, j.seg_cnt, j.nseg,
                        j.labels, j.u, j.flags, g.cap, j.ucnt, j.row, j.conv,
-                       j.iter, j.dirty, j.recheck_all, vec, o.CT, fuse_tpf(o.k),
+                       j.iter, j.dirty, j.recheck_all, vec, o.CT, o.C64, fuse_tpf(o.k),
                        j.recheck_all ? 0 : kFuseRecheckMax, vecx);
   }
   return hipGetLastError();

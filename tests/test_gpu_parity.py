@@ -93,22 +93,56 @@ def test_assign_far_from_origin(scale, shift, dtype):
 
 
 @pytest.mark.parametrize("dtype", ["f32", "bf16"])
-@pytest.mark.parametrize("d", [16, 64])
-def test_assign_near_bisectors(dtype, d):
+@pytest.mark.parametrize("n,d,k", [(20000, 16, 48), (20000, 64, 48),
+                                   (300000, 16, 48), (20000, 32, 1000)])
+def test_assign_near_bisectors(dtype, n, d, k):
     """Points placed on and near the bisecting hyperplanes of centroid pairs
     (then rounded to the storage type): the squared-distance gaps fall
     around the tile's decision threshold, so a bound that is too small shows
-    up as a label that differs from the oracle."""
+    up as a label that differs from the oracle.  Nearly every point is
+    undecided by the tile with a clear third centroid, so the FP32 tile
+    resolves it from its two best centroids; n = 3e5 puts more such points
+    into a workgroup than its list holds (the rest take the full recheck),
+    k = 1000 runs the chunked schedule."""
     knor = _knor()
-    rng = np.random.default_rng(40 + d)
-    k = 48
+    _print_case(test="near_bisectors", n=n, d=d, k=k, dtype=dtype)
+    rng = np.random.default_rng(40 + d + k)
     C = rng.normal(size=(k, d)) * 4.0
-    a = rng.integers(0, k, size=20000)
-    b = (a + 1 + rng.integers(0, k - 1, size=20000)) % k
+    a = rng.integers(0, k, size=n)
+    b = (a + 1 + rng.integers(0, k - 1, size=n)) % k
     mid = 0.5 * (C[a] + C[b])
-    step = (C[b] - C[a]) * rng.uniform(-1e-3, 1e-3, size=(20000, 1))
+    step = (C[b] - C[a]) * rng.uniform(-1e-3, 1e-3, size=(n, 1))
     X = workloads.cast(mid + step, dtype)
     lab_o, _ = oracle.assign(workloads.to_f64(X, dtype), C)
+    lab = knor.assign(_dev(X, dtype), _dev(C, "f64"))
+    assert (lab.cpu().numpy() == lab_o).all()
+
+
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+def test_assign_near_three_way_ties(dtype):
+    """Points near the circumcentre of three centroids (inside their plane):
+    three squared distances fall within the tile's margin, so even the two
+    best cannot be trusted and the point must take the full FP64 recheck."""
+    knor = _knor()
+    rng = np.random.default_rng(77)
+    k, d, n = 48, 16, 20000
+    C = rng.normal(size=(k, d)) * 4.0
+    a = rng.integers(0, k, size=n)
+    b = (a + 1 + rng.integers(0, k - 1, size=n)) % k
+    c = (b + 1 + rng.integers(0, k - 2, size=n)) % k
+    c = np.where(c == a, (c + 1) % k, c)
+    Ca, Cb, Cc = C[a], C[b], C[c]
+    u, v = Cb - Ca, Cc - Ca
+    # P = Ca + s u + t v with |P - Ca| = |P - Cb| = |P - Cc|
+    uu, uv, vv = (u * u).sum(1), (u * v).sum(1), (v * v).sum(1)
+    r1, r2 = 0.5 * uu, 0.5 * vv
+    det = uu * vv - uv * uv
+    s = (r1 * vv - r2 * uv) / det
+    t = (r2 * uu - r1 * uv) / det
+    P = Ca + s[:, None] * u + t[:, None] * v
+    P += rng.normal(size=P.shape) * 1e-4
+    X = workloads.cast(P, dtype)
+    lab_o, D_o = oracle.assign(workloads.to_f64(X, dtype), C)
     lab = knor.assign(_dev(X, dtype), _dev(C, "f64"))
     assert (lab.cpu().numpy() == lab_o).all()
 
