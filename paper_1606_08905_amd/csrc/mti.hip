@@ -90,36 +90,38 @@ __global__ __launch_bounds__(kFilterThreads) void mti_filter_kernel(
     int iter, int vec) {
   __shared__ int candA[kSeg];
   __shared__ int nA, nB;
-  if (*conv < iter) return;
+  const int cv = *conv;
   const int seg = blockIdx.x;
   const int64_t p0 = (int64_t)seg * kSeg;
   const bool tighten = tighten_now(prev_row, iter);
-  if (threadIdx.x == 0) { nA = 0; nB = 0; }
-  if (tighten && seg == 0 && threadIdx.x == 0) row[ROW_TIGHTEN] = 1;
-  __syncthreads();
 
   // Clause 1 with the drift-updated bound, for every point of the segment:
   // thread t owns points 4t .. 4t + 3 of the segment (16-byte loads of
-  // labels and bounds, then the per-label gathers, then one 16-byte store)
+  // labels and bounds, issued with the convergence test, then the per-label
+  // gathers, then one 16-byte store)
   static_assert(kSeg == 4 * kFilterThreads, "four points per thread");
-  {
-    const int64_t pb = p0 + 4 * threadIdx.x;
-    int lab[4];
-    float uu[4];
-    // the caller's label array may be only 4-byte aligned
-    const bool full = pb + 3 < n && (((uintptr_t)labels & 15) == 0);
-    if (full) {
-      const int4 l4 = *reinterpret_cast<const int4*>(labels + pb);
-      const float4 u4 = *reinterpret_cast<const float4*>(u + pb);
-      lab[0] = l4.x; lab[1] = l4.y; lab[2] = l4.z; lab[3] = l4.w;
-      uu[0] = u4.x; uu[1] = u4.y; uu[2] = u4.z; uu[3] = u4.w;
-    } else {
+  const int64_t pb = p0 + 4 * threadIdx.x;
+  int lab[4];
+  float uu[4];
+  // the caller's label array may be only 4-byte aligned
+  const bool full = pb + 3 < n && (((uintptr_t)labels & 15) == 0);
+  if (full) {
+    const int4 l4 = *reinterpret_cast<const int4*>(labels + pb);
+    const float4 u4 = *reinterpret_cast<const float4*>(u + pb);
+    lab[0] = l4.x; lab[1] = l4.y; lab[2] = l4.z; lab[3] = l4.w;
+    uu[0] = u4.x; uu[1] = u4.y; uu[2] = u4.z; uu[3] = u4.w;
+  } else {
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        lab[e] = pb + e < n ? labels[pb + e] : 0;
-        uu[e] = pb + e < n ? u[pb + e] : 0.0f;
-      }
+    for (int e = 0; e < 4; ++e) {
+      lab[e] = pb + e < n ? labels[pb + e] : 0;
+      uu[e] = pb + e < n ? u[pb + e] : 0.0f;
     }
+  }
+  if (cv < iter) return;
+  if (threadIdx.x == 0) { nA = 0; nB = 0; }
+  if (tighten && seg == 0 && threadIdx.x == 0) row[ROW_TIGHTEN] = 1;
+  __syncthreads();
+  {
     float dr[4], sh[4];
 #pragma unroll
     for (int e = 0; e < 4; ++e) { dr[e] = drift[lab[e]]; sh[e] = s_half[lab[e]]; }

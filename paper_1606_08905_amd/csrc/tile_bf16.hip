@@ -274,7 +274,7 @@ __global__ __launch_bounds__(kTileThreads) void tile_bf16_resident_kernel(
   uint16_t* sH = smem_bf;
   uint16_t* sL = smem_bf + (size_t)kpad * LDA;
   float* sN = reinterpret_cast<float*>(smem_bf + (size_t)2 * kpad * LDA);
-  if (*conv < iter) return;
+  const int cv = *conv;                        // tested after the staging loads
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int col = lane & 15, grp = lane >> 4;
   const bool pairs = T::PAIR && C64 != nullptr;
@@ -283,6 +283,7 @@ __global__ __launch_bounds__(kTileThreads) void tile_bf16_resident_kernel(
   if (threadIdx.x == 0) { sFlag = 0; sPairN = 0; }
   if (seg_cnt) seg_stage(seg_cnt, nseg, WUP, sSeg, sWmax);
   stage_bf<DP, LDA>(sH, sL, sN, Chi, Clo, cn, 0, kpad);
+  if (cv < iter) return;
   __syncthreads();
   const float cmax = chunk_cmax(sN, kpad, 0, k, lane);
 
@@ -340,7 +341,7 @@ __global__ __launch_bounds__(kTileThreads) void tile_bf16_chunked_kernel(
   __shared__ __attribute__((aligned(16))) float sN[CK];
   __shared__ int sFlag, sChg, sPairN;
   __shared__ int4 sPair[kPairCap];
-  if (*conv < iter) return;
+  const int cv = *conv;                        // tested after the first loads
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int col = lane & 15, grp = lane >> 4;
   const bool pairs = T::PAIR && C64 != nullptr;
@@ -348,6 +349,7 @@ __global__ __launch_bounds__(kTileThreads) void tile_bf16_chunked_kernel(
   int64_t units = seg_cnt ? (int64_t)nseg * (kSeg / BUP) : (n + BUP - 1) / BUP;
   if (threadIdx.x == 0) { sFlag = 0; sChg = 0; sPairN = 0; }
   if (seg_cnt) seg_stage(seg_cnt, nseg, BUP, sSeg, sWmax);
+  if (cv < iter) return;
   __syncthreads();
   if (seg_cnt) units = seg_units_bound(sWmax, nseg, units);
   const int* segc = (seg_cnt && nseg <= kSegCache) ? sSeg : nullptr;

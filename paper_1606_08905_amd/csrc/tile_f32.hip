@@ -268,7 +268,7 @@ __global__ __launch_bounds__(kTileThreads) void tile_f32_resident_kernel(
   __shared__ int4 sPair[kPairCap];
   float* sC = smem;
   float* sN = smem + (size_t)kpad * LDA;
-  if (*conv < iter) return;
+  const int cv = *conv;                        // tested after the staging loads
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int col = lane & 15, grp = lane >> 4;
   const bool pairs = T::PAIR && C64 != nullptr;
@@ -282,6 +282,7 @@ __global__ __launch_bounds__(kTileThreads) void tile_f32_resident_kernel(
         *reinterpret_cast<const float4*>(Cm2 + (size_t)r * DP + q4 * 4);
   }
   for (int e = threadIdx.x; e < kpad; e += kTileThreads) sN[e] = cn[e];
+  if (cv < iter) return;
   __syncthreads();
   const float cmax = chunk_cmax(sN, kpad, 0, k, lane);
 
@@ -337,7 +338,7 @@ __global__ __launch_bounds__(kTileThreads) void tile_f32_chunked_kernel(
   __shared__ __attribute__((aligned(16))) float sN[CK];
   __shared__ int sFlag, sChg, sPairN;
   __shared__ int4 sPair[kPairCap];
-  if (*conv < iter) return;
+  const int cv = *conv;                        // tested after the first loads
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int col = lane & 15, grp = lane >> 4;
   const bool pairs = T::PAIR && C64 != nullptr;
@@ -345,6 +346,7 @@ __global__ __launch_bounds__(kTileThreads) void tile_f32_chunked_kernel(
   int64_t units = seg_cnt ? (int64_t)nseg * (kSeg / BUP) : (n + BUP - 1) / BUP;
   if (threadIdx.x == 0) { sFlag = 0; sChg = 0; sPairN = 0; }
   if (seg_cnt) seg_stage(seg_cnt, nseg, BUP, sSeg, sWmax);
+  if (cv < iter) return;
   __syncthreads();
   if (seg_cnt) units = seg_units_bound(sWmax, nseg, units);
   const int* segc = (seg_cnt && nseg <= kSegCache) ? sSeg : nullptr;

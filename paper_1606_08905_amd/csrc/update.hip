@@ -20,8 +20,9 @@
 // Pass 1 has two schedules.  For k <= kFusedMaxK, one workgroup of 16 waves
 // owns a range of points; each wave owns a sub-range and a private running
 // table in LDS, and every workgroup derives its own offsets from the range
-// totals (two kernels).  For larger k, per-block counts go through a
-// segmented column scan (four kernels).
+// totals (two kernels, or three when the table of range totals is too large
+// for the scatter to take its own prefix).  For larger k, per-block counts
+// go through a segmented column scan (four kernels).
 #include <math.h>
 
 #include "common.h"
@@ -37,6 +38,15 @@ constexpr int kFusedMaxRanges = 1024;
 // ---------------------------------------------------------------------------
 
 static bool fused_sort(int k) { return k <= kFusedMaxK; }
+
+// The scatter computes the prefix over ranges itself when each of its
+// threads sums at most kScatterPrefix range totals (the 1024 threads split
+// as floor(1024 / k) parts per cluster); otherwise range_scan runs first.
+constexpr int kScatterPrefix = 24;
+static bool scatter_prefix(int nb, int k) {
+  const int parts = 1024 / k;
+  return (nb + parts - 1) / parts <= kScatterPrefix;
+}
 
 static int choose_block(int64_t n, int k) {
   if (fused_sort(k)) {
@@ -193,16 +203,33 @@ __global__ __launch_bounds__(1024) void hist_fused(const int32_t* __restrict__ l
                                                    const int* __restrict__ conv,
                                                    int iter) {
   extern __shared__ int tab[];               // kFusedWaves x k
-  SKIP_IF_CONVERGED
+  const int cv = *conv;
   const int r = blockIdx.x, wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  for (int e = threadIdx.x; e < kFusedWaves * k; e += blockDim.x) tab[e] = 0;
-  __syncthreads();
   const int64_t p0 = ((int64_t)r * kFusedWaves + wave) * SB;
   const int64_t p1 = p0 + SB < n ? p0 + SB : n;
+  // the labels of kAhead chunks of 64 are loaded together (the first batch
+  // before the convergence test, so the two waits overlap)
+  constexpr int kAhead = 16;
+  int labs[kAhead];
+#pragma unroll
+  for (int q = 0; q < kAhead; ++q) {
+    const int64_t p = p0 + q * 64 + lane;
+    labs[q] = p < p1 ? labels[p] : -1;
+  }
+  for (int e = threadIdx.x; e < kFusedWaves * k; e += blockDim.x) tab[e] = 0;
+  if (cv < iter) return;
+  __syncthreads();
   int* t = tab + wave * k;
-  for (int64_t p = p0 + lane; p < p1; p += 64) {
-    const unsigned lab = (unsigned)labels[p];
-    if (lab < (unsigned)k) atomicAdd(&t[lab], 1);   // LDS; order-free count
+  for (int64_t c0 = p0; c0 < p1; c0 += 64 * kAhead) {
+    if (c0 != p0)
+#pragma unroll
+      for (int q = 0; q < kAhead; ++q) {
+        const int64_t p = c0 + q * 64 + lane;
+        labs[q] = p < p1 ? labels[p] : -1;
+      }
+#pragma unroll
+    for (int q = 0; q < kAhead; ++q)
+      if ((unsigned)labs[q] < (unsigned)k) atomicAdd(&t[labs[q]], 1);   // LDS; order-free
   }
   __syncthreads();
   int* out = cnt + (size_t)r * (kFusedWaves + 1) * k;
@@ -226,7 +253,7 @@ __global__ __launch_bounds__(256) void range_scan(const int* __restrict__ cnt,
                                                   const int* __restrict__ conv,
                                                   int iter) {
   __shared__ int part[256];
-  SKIP_IF_CONVERGED
+  const int cv = *conv;
   const int j = blockIdx.x;
   const int per = (nr + 255) / 256;
   const int r0 = threadIdx.x * per;
@@ -242,6 +269,7 @@ __global__ __launch_bounds__(256) void range_scan(const int* __restrict__ cnt,
 #pragma unroll
     for (int u = 0; u < 4; ++u) local += v[u];
   }
+  if (cv < iter) return;
   part[threadIdx.x] = local;
   __syncthreads();
   for (int s = 1; s < 256; s <<= 1) {
@@ -260,19 +288,74 @@ __global__ __launch_bounds__(256) void range_scan(const int* __restrict__ cnt,
   if (threadIdx.x == 255) nj[j] = part[255];
 }
 
+// Exclusive prefix over ranges of the range totals: from range_scan (rpre
+// and nj), or, with in_prefix, computed here: thread (q, c) = (t / k, t % k)
+// sums the totals of cluster c over ranges q, q + Q, ... (Q = 1024 / k
+// parts), over all ranges and over the ranges before this one, and range 0
+// stores the cluster totals in nj.
 __global__ __launch_bounds__(1024) void scatter_fused(
     const int32_t* __restrict__ labels, int64_t n, int k, int SB,
     int bits, const int* __restrict__ cnt, const int* __restrict__ rpre,
-    const int* __restrict__ nj_in, const int* __restrict__ dirty,
+    int* __restrict__ nj, int in_prefix, const int* __restrict__ dirty,
     int* __restrict__ perm, int* __restrict__ off_out,
     int* __restrict__ leaf_off_out, const int* __restrict__ conv, int iter) {
   extern __shared__ int run[];               // kFusedWaves x k
   __shared__ int sa[1024], sb[1024];
-  SKIP_IF_CONVERGED
+  __shared__ int sDirty[kFusedMaxK];         // the dirty flags, read per point
+  const int cv = *conv;
   const int r = blockIdx.x, wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int j = threadIdx.x;                 // k <= 1024: one cluster per thread
-  const int tot = j < k ? nj_in[j] : 0;
-  const int pre = j < k ? rpre[(size_t)r * k + j] : 0;
+  int tot = 0, pre = 0;
+  int part_all = 0, part_before = 0;
+  if (in_prefix) {
+    const int Q = 1024 / k, q = threadIdx.x / k, c = threadIdx.x - q * k;
+    if (q < Q) {
+      int v[kScatterPrefix];
+#pragma unroll
+      for (int u = 0; u < kScatterPrefix; ++u) {
+        const int rr = q + u * Q;
+        v[u] = rr < (int)gridDim.x
+                   ? cnt[((size_t)rr * (kFusedWaves + 1) + kFusedWaves) * k + c] : 0;
+      }
+#pragma unroll
+      for (int u = 0; u < kScatterPrefix; ++u) {
+        part_all += v[u];
+        if (q + u * Q < r) part_before += v[u];
+      }
+    }
+  } else if (j < k) {
+    tot = nj[j];
+    pre = rpre[(size_t)r * k + j];
+  }
+  // this range's per-wave counts
+  int wcnt[kFusedWaves];
+  const int* mine = cnt + (size_t)r * (kFusedWaves + 1) * k;
+#pragma unroll
+  for (int w = 0; w < kFusedWaves; ++w) wcnt[w] = j < k ? mine[(size_t)w * k + j] : 0;
+  if (j < k) sDirty[j] = dirty ? dirty[j] : 1;
+  // the first kAhead chunks of this wave's labels, loaded with the above
+  const int64_t p0 = ((int64_t)r * kFusedWaves + wave) * SB;
+  const int64_t p1 = p0 + SB < n ? p0 + SB : n;
+  constexpr int kAhead = 16;
+  int labs[kAhead];
+#pragma unroll
+  for (int q = 0; q < kAhead; ++q) {
+    const int64_t p = p0 + q * 64 + lane;
+    labs[q] = p < p1 ? labels[p] : -1;
+  }
+  if (cv < iter) return;
+  if (in_prefix) {
+    sa[threadIdx.x] = part_all;
+    sb[threadIdx.x] = part_before;
+    __syncthreads();
+    if (j < k)
+      for (int q = 0; q < 1024 / k; ++q) {
+        tot += sa[q * k + j];
+        pre += sb[q * k + j];
+      }
+    if (r == 0 && j < k) nj[j] = tot;
+    __syncthreads();
+  }
   // exclusive prefix over clusters of the totals (members and leaves)
   const int lv = (tot + kLeaf - 1) / kLeaf;
   sa[threadIdx.x] = tot;
@@ -299,10 +382,10 @@ __global__ __launch_bounds__(1024) void scatter_fused(
   }
   if (j < k) {
     int base = off + pre;
-    const int* mine = cnt + (size_t)r * (kFusedWaves + 1) * k;
+#pragma unroll
     for (int w = 0; w < kFusedWaves; ++w) {
       run[w * k + j] = base;
-      base += mine[(size_t)w * k + j];
+      base += wcnt[w];
     }
   }
   __syncthreads();
@@ -310,16 +393,13 @@ __global__ __launch_bounds__(1024) void scatter_fused(
   // labels of 16 chunks are loaded ahead so the walk only waits on LDS
   int* t = run + wave * k;
   const uint64_t lt = lanemask_lt();
-  const int64_t p0 = ((int64_t)r * kFusedWaves + wave) * SB;
-  const int64_t p1 = p0 + SB < n ? p0 + SB : n;
-  constexpr int kAhead = 16;
   for (int64_t c0 = p0; c0 < p1; c0 += 64 * kAhead) {
-    int labs[kAhead];
+    if (c0 != p0)
 #pragma unroll
-    for (int q = 0; q < kAhead; ++q) {
-      const int64_t p = c0 + q * 64 + lane;
-      labs[q] = p < p1 ? labels[p] : -1;
-    }
+      for (int q = 0; q < kAhead; ++q) {
+        const int64_t p = c0 + q * 64 + lane;
+        labs[q] = p < p1 ? labels[p] : -1;
+      }
 #pragma unroll
     for (int q = 0; q < kAhead; ++q) {
       const int64_t p = c0 + q * 64 + lane;
@@ -333,7 +413,7 @@ __global__ __launch_bounds__(1024) void scatter_fused(
       if (valid) pos = t[lab] + rank;
       __builtin_amdgcn_wave_barrier();
       if (valid) {
-        if (!dirty || dirty[lab]) perm[pos] = (int)p;
+        if (sDirty[lab]) perm[pos] = (int)p;
         if (rank == cntl - 1) t[lab] = pos + 1;
       }
       __builtin_amdgcn_wave_barrier();
@@ -464,8 +544,7 @@ __global__ __launch_bounds__(64) void scatter_kernel(
 // pass 2: leaf sums, tree, finalize
 // ---------------------------------------------------------------------------
 
-__device__ __forceinline__ int cluster_of_leaf(const int* __restrict__ leaf_off,
-                                               int k, int g) {
+__device__ __forceinline__ int cluster_of_leaf(const int* leaf_off, int k, int g) {
   int lo = 0, hi = k - 1;      // largest j with leaf_off[j] <= g
   while (lo < hi) {
     int mid = (lo + hi + 1) >> 1;
@@ -476,8 +555,20 @@ __device__ __forceinline__ int cluster_of_leaf(const int* __restrict__ leaf_off,
 
 // One wave per leaf.  Lane m loads member m's row (a chunk of DC dimensions
 // at a time) into the wave's LDS tile, then lane i sums dimension i over the
-// members in order (left to right, starting from the first member).
+// members in order (left to right, starting from the first member).  For
+// k <= kLeafStageK the workgroup first stages the leaf offsets and the dirty
+// flags (one bit per cluster) in LDS, so a wave finds its cluster by a
+// binary search in LDS instead of a chain of dependent global reads.
 constexpr int kLeafWaves = 4;
+constexpr int kLeafStageK = 4096;
+
+// k + 1 offsets, rounded up to an even count (8-byte alignment of the bits)
+__host__ __device__ constexpr int leaf_stage_ints(int k) { return (k + 2) & ~1; }
+static size_t leaf_stage_bytes(int k) {
+  return k <= kLeafStageK
+             ? sizeof(int) * (size_t)leaf_stage_ints(k) + sizeof(uint64_t) * (size_t)((k + 63) / 64)
+             : 0;
+}
 
 template <typename T>
 struct LeafCfg {
@@ -494,14 +585,29 @@ __global__ __launch_bounds__(64 * kLeafWaves) void leaf_kernel(
     double* __restrict__ leafsum, const int* __restrict__ conv, int iter, int vec) {
   constexpr int DC = LeafCfg<T>::DC, LD = LeafCfg<T>::LD;
   __shared__ __attribute__((aligned(16))) T tile[kLeafWaves][kLeaf * LD];
-  SKIP_IF_CONVERGED
+  // dynamic: leaf_stage_bytes(k) when k <= kLeafStageK
+  extern __shared__ __attribute__((aligned(16))) int sLo[];
+  uint64_t* sDm = reinterpret_cast<uint64_t*>(sLo + leaf_stage_ints(k));
+  const int cv = *conv;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int total = leaf_off[k];
+  const bool staged = k <= kLeafStageK;
+  if (staged) {
+    for (int e = threadIdx.x; e <= k; e += blockDim.x) sLo[e] = leaf_off[e];
+    for (int e0 = wave * 64; e0 < k; e0 += blockDim.x) {
+      const int e = e0 + lane;
+      const uint64_t m = __ballot(e < k && (!dirty || dirty[e]));
+      if (lane == 0) sDm[e0 >> 6] = m;
+    }
+  }
+  if (cv < iter) return;
+  if (staged) __syncthreads();
+  const int* lo_tab = staged ? sLo : leaf_off;
+  const int total = lo_tab[k];
   const int g = blockIdx.x * kLeafWaves + wave;
-  if (g >= total) return;                    // per wave; no block barrier used
-  const int j = cluster_of_leaf(leaf_off, k, g);
-  if (dirty && !dirty[j]) return;
-  const int L = g - leaf_off[j];
+  if (g >= total) return;                    // per wave; no later block barrier
+  const int j = cluster_of_leaf(lo_tab, k, g);
+  if (staged ? !((sDm[j >> 6] >> (j & 63)) & 1) : (dirty && !dirty[j])) return;
+  const int L = g - lo_tab[j];
   const int m0 = off[j] + L * kLeaf;
   int cnt = nj[j] - L * kLeaf;
   if (cnt > kLeaf) cnt = kLeaf;
@@ -547,10 +653,11 @@ __global__ __launch_bounds__(256) void tree_block(
     int d, int TB, const int* __restrict__ dirty, const int* __restrict__ conv,
     int iter) {
   __shared__ double node[kTreeBlockDoubles];
-  SKIP_IF_CONVERGED
+  const int cv = *conv;
   const int j = blockIdx.x;
-  if (dirty && !dirty[j]) return;
+  const int dj = dirty ? dirty[j] : 1;
   const int L0 = leaf_off[j], m = leaf_off[j + 1] - L0;
+  if (cv < iter || !dj) return;
   const int mb = (m + TB - 1) / TB;
   for (int b = blockIdx.y; b < mb; b += gridDim.y) {
     const int cnt = m - b * TB < TB ? m - b * TB : TB;
@@ -586,8 +693,12 @@ __global__ __launch_bounds__(256) void tree_finalize(
   __shared__ double red[256];
   __shared__ double cval[kMaxD];
   __shared__ double tree[kTreeLdsDoubles];
-  SKIP_IF_CONVERGED
+  const int cv = *conv;
   const int j = blockIdx.x;
+  const int cntj = nj[j];
+  const int dj = dirty ? dirty[j] : 1;
+  const int lo0 = leaf_off[j], lo1 = leaf_off[j + 1];
+  if (cv < iter) return;
 
   if (j == 0 && ctl.row) {
     // fold the spread slots: thread (q, i) loads slot i of quantity q
@@ -620,16 +731,15 @@ __global__ __launch_bounds__(256) void tree_finalize(
     }
   }
 
-  const int cntj = nj[j];
   if (counts_out && threadIdx.x == 0) counts_out[j] = cntj;
-  if (dirty && !dirty[j]) {
+  if (!dj) {
     if (drift && threadIdx.x == 0) drift[j] = 0.0f;     // centroid unchanged
     return;
   }
   // the block sums of tree_block sit at leaves 0, TB, 2 TB, ...: node b
-  const int m = leaf_off[j + 1] - leaf_off[j];
+  const int m = lo1 - lo0;
   const int mb = (m + TB - 1) / TB;
-  double* base = leafsum + (size_t)leaf_off[j] * d;
+  double* base = leafsum + (size_t)lo0 * d;
   const size_t bstride = (size_t)TB * d;
   const bool in_lds = (size_t)mb * d <= (size_t)kTreeLdsDoubles;
   if (in_lds) {
@@ -705,11 +815,13 @@ hipError_t launch_update(const UpdatePlan& p, const void* X, knor_dtype dt,
     const size_t lds = sizeof(int) * (size_t)kFusedWaves * k;
     hipLaunchKernelGGL(hist_fused, dim3(p.nb), dim3(1024), lds, s, labels, p.n,
                        k, p.B, p.blockcnt, conv, iter);
-    hipLaunchKernelGGL(range_scan, dim3(k), dim3(256), 0, s, p.blockcnt, p.nb,
-                       k, p.rpre, p.nj, conv, iter);
+    const int in_prefix = scatter_prefix(p.nb, k) ? 1 : 0;
+    if (!in_prefix)
+      hipLaunchKernelGGL(range_scan, dim3(k), dim3(256), 0, s, p.blockcnt, p.nb,
+                         k, p.rpre, p.nj, conv, iter);
     hipLaunchKernelGGL(scatter_fused, dim3(p.nb), dim3(1024), lds, s, labels,
-                       p.n, k, p.B, bits, p.blockcnt, p.rpre, p.nj, dirty,
-                       p.perm, p.off, p.leaf_off, conv, iter);
+                       p.n, k, p.B, bits, p.blockcnt, p.rpre, p.nj, in_prefix,
+                       dirty, p.perm, p.off, p.leaf_off, conv, iter);
   } else {
     const size_t lds_k = sizeof(int) * (size_t)k;
     hipLaunchKernelGGL(hist_kernel, dim3(p.nb), dim3(256), lds_k, s, labels,
@@ -730,17 +842,17 @@ hipError_t launch_update(const UpdatePlan& p, const void* X, knor_dtype dt,
   switch (dt) {
     case KNOR_F64:
       hipLaunchKernelGGL(leaf_kernel<double>, dim3(lblocks), dim3(64 * kLeafWaves),
-                         0, s, (const double*)X, d, p.perm, p.nj, p.off,
+                         leaf_stage_bytes(k), s, (const double*)X, d, p.perm, p.nj, p.off,
                          p.leaf_off, k, dirty, p.leafsum, conv, iter, vec);
       break;
     case KNOR_F32:
       hipLaunchKernelGGL(leaf_kernel<float>, dim3(lblocks), dim3(64 * kLeafWaves),
-                         0, s, (const float*)X, d, p.perm, p.nj, p.off,
+                         leaf_stage_bytes(k), s, (const float*)X, d, p.perm, p.nj, p.off,
                          p.leaf_off, k, dirty, p.leafsum, conv, iter, vec);
       break;
     case KNOR_BF16:
       hipLaunchKernelGGL(leaf_kernel<uint16_t>, dim3(lblocks), dim3(64 * kLeafWaves),
-                         0, s, (const uint16_t*)X, d, p.perm, p.nj, p.off,
+                         leaf_stage_bytes(k), s, (const uint16_t*)X, d, p.perm, p.nj, p.off,
                          p.leaf_off, k, dirty, p.leafsum, conv, iter, vec);
       break;
   }
