@@ -300,10 +300,11 @@ __global__ __launch_bounds__(kTileThreads) void tile_bf16_resident_kernel(
     load_points_bf<T>(w, X, d, vec, list, labels, base, q0, m, col, grp);
     tile_sweep_bf<T>(w, sH, sL, sN, kpad, 0, col, grp);
     merge_groups<T>(w);
-    bool flag[PB], changed;
+    bool flag, changed;
+    int fp;
     finalize_points<T>(w, cmax, d, grp, recheck_all, pairs, sPair, &sPairN,
-                       labels, ub, dirty, flag, changed);
-    const int nf = append_flags<T>(w, flag, &sFlag, slice, lane);
+                       labels, ub, dirty, flag, fp, changed);
+    const int nf = append_flags(flag, fp, &sFlag, slice, lane);
     const int nc = __popcll(__ballot(changed));
     if (lane == 0) {
       tot_flag += nf;
@@ -371,10 +372,11 @@ __global__ __launch_bounds__(kTileThreads) void tile_bf16_chunked_kernel(
       tile_sweep_bf<T>(w, sH, sL, sN, cc, c0, col, grp);
     }
     merge_groups<T>(w);
-    bool flag[PB], changed;
+    bool flag, changed;
+    int fp;
     finalize_points<T>(w, cmax, d, grp, recheck_all, pairs, sPair, &sPairN,
-                       labels, ub, dirty, flag, changed);
-    append_flags<T>(w, flag, &sFlag, slice, lane);
+                       labels, ub, dirty, flag, fp, changed);
+    append_flags(flag, fp, &sFlag, slice, lane);
     const uint64_t cm = __ballot(changed);
     if (cm && lane == 0) atomicAdd(&sChg, __popcll(cm));
   }

@@ -163,7 +163,9 @@ __device__ __forceinline__ double chain_dist(const typename T::Frag (&bx)[T::KS]
 // that finds the list full goes to the full FP64 recheck instead.
 constexpr int kPairCap = 128;
 
-// Decide each point (lane group g finalises point block pb with pb % 4 == g).
+// Decide each point: lane group g finalises point block g (g < PB; the
+// merged values are equal in every group), so the bound arithmetic runs
+// once per lane instead of once per block.
 // With E the tile's error bound, the point is decided iff
 //   y_2nd - y_best > 2E + 2.01 (d+2) 2^-53 (|x|^2 + y_best + E):
 // every other centroid's exact squared distance then exceeds the chosen
@@ -173,64 +175,80 @@ constexpr int kPairCap = 128;
 // centroid other than the two best is excluded the same way, and the FP64
 // argmin over all centroids is the FP64 argmin of those two: the point is
 // queued for resolve_pairs().  Writes labels / bounds of decided points;
-// returns per-block flags for the full FP64 recheck.
+// returns the lane's flag for the full FP64 recheck (and its point).
 template <class T>
 __device__ __forceinline__ void finalize_points(
     WaveState<T>& w, float cmax, int d, int grp, int recheck_all, bool pairs,
     int4* sPair, int* sPairN, int32_t* __restrict__ labels,
-    float* __restrict__ ub, int* __restrict__ dirty, bool (&flag)[T::PB],
+    float* __restrict__ ub, int* __restrict__ dirty, bool& flag, int& pid,
     bool& changed) {
   constexpr int PB = T::PB;
   static_assert(PB <= 4, "one finalised point per lane");
-  // R2 >= max |c|^2: cmax is the largest fp32(|c|^2), within 2^-24 of it
-  const double R2 = (double)cmax * (1.0 + 2.384185791015625e-07);  // 1+2^-22
-  const double e64 = (double)(d + 2) * 1.1102230246251565e-16;     // (d+2)2^-53
-  changed = false;
+  // this lane's block
+  bool valid = w.valid[0];
+  double xs = w.xs[0];
+  float b1 = w.b1[0], b2 = w.b2[0], b3 = w.b3[0];
+  int i1 = w.i1[0], i2 = w.i2[0];
+  int64_t p = w.pid[0];
+  int32_t old = w.old[0];
 #pragma unroll
-  for (int pb = 0; pb < PB; ++pb) {
-    flag[pb] = false;
-    const bool own = w.valid[pb] && (pb & 3) == grp;
-    bool decided = false, pair = false;
-    double dbest = 0.0;
-    if (own) {
-      // xs sums exact squares in FP64: at most (d+4) roundings of 2^-53
-      const double xn2 = w.xs[pb] * (1.0 + (double)(d + 4) * 2.220446049250313e-16);
-      const double E = T::bound(xn2, R2, d);
-      const double y1 = (double)w.b1[pb];
-      dbest = xn2 + y1 + E;
-      if (!(dbest > 0.0)) dbest = 0.0;
-      const double thr = 2.0 * E + 2.01 * e64 * dbest;
-      decided = !recheck_all && (double)w.b2[pb] - y1 > thr;
-      pair = pairs && !recheck_all && !decided && (double)w.b3[pb] - y1 > thr;
-    }
-    if (pairs) {
-      const uint64_t m = __ballot(pair);
-      if (m) {
-        const int leader = __ffsll((unsigned long long)m) - 1;
-        int base = 0;
-        if (lane_id() == leader) base = atomicAdd(sPairN, __popcll(m));   // LDS
-        base = __shfl(base, leader);
-        if (pair) {
-          const int slot = base + __popcll(m & lanemask_lt());
-          if (slot < kPairCap)
-            sPair[slot] = make_int4((int)w.pid[pb], w.i1[pb], w.i2[pb], w.old[pb]);
-          else
-            pair = false;                      // list full: full recheck
-        }
+  for (int pb = 1; pb < PB; ++pb) {
+    const bool m = grp == pb;                  // selects, not an indexed copy
+    valid = m ? w.valid[pb] : valid;
+    xs = m ? w.xs[pb] : xs;
+    b1 = m ? w.b1[pb] : b1;
+    b2 = m ? w.b2[pb] : b2;
+    b3 = m ? w.b3[pb] : b3;
+    i1 = m ? w.i1[pb] : i1;
+    i2 = m ? w.i2[pb] : i2;
+    p = m ? w.pid[pb] : p;
+    old = m ? w.old[pb] : old;
+  }
+  const bool own = grp < PB && valid;
+  pid = (int)p;
+  changed = false;
+  flag = false;
+  bool decided = false, pair = false;
+  double dbest = 0.0;
+  if (own) {
+    // R2 >= max |c|^2: cmax is the largest fp32(|c|^2), within 2^-24 of it
+    const double R2 = (double)cmax * (1.0 + 2.384185791015625e-07);  // 1+2^-22
+    const double e64 = (double)(d + 2) * 1.1102230246251565e-16;     // (d+2)2^-53
+    // xs sums exact squares in FP64: at most (d+4) roundings of 2^-53
+    const double xn2 = xs * (1.0 + (double)(d + 4) * 2.220446049250313e-16);
+    const double E = T::bound(xn2, R2, d);
+    const double y1 = (double)b1;
+    dbest = xn2 + y1 + E;
+    if (!(dbest > 0.0)) dbest = 0.0;
+    const double thr = 2.0 * E + 2.01 * e64 * dbest;
+    decided = !recheck_all && (double)b2 - y1 > thr;
+    pair = pairs && !recheck_all && !decided && (double)b3 - y1 > thr;
+  }
+  if (pairs) {
+    const uint64_t m = __ballot(pair);
+    if (m) {
+      const int leader = __ffsll((unsigned long long)m) - 1;
+      int base = 0;
+      if (lane_id() == leader) base = atomicAdd(sPairN, __popcll(m));   // LDS
+      base = __shfl(base, leader);
+      if (pair) {
+        const int slot = base + __popcll(m & lanemask_lt());
+        if (slot < kPairCap)
+          sPair[slot] = make_int4(pid, i1, i2, old);
+        else
+          pair = false;                        // list full: full recheck
       }
     }
-    if (!own) continue;
-    flag[pb] = !decided && !pair;
-    if (!decided) continue;
-    const int64_t p = w.pid[pb];
-    const int32_t old = w.old[pb];
-    labels[p] = w.i1[pb];
-    if (old != w.i1[pb]) {
-      changed = true;
-      mark_dirty(dirty, old, w.i1[pb]);
-    }
-    if (ub) ub[p] = f32_up(sqrt(dbest) * (1.0 + 8.881784197001252e-16));
   }
+  if (!own) return;
+  flag = !decided && !pair;
+  if (!decided) return;
+  labels[p] = i1;
+  if (old != i1) {
+    changed = true;
+    mark_dirty(dirty, old, i1);
+  }
+  if (ub) ub[p] = f32_up(sqrt(dbest) * (1.0 + 8.881784197001252e-16));
 }
 
 // The queued two-candidate points (after a barrier; every thread calls this
@@ -354,24 +372,15 @@ __device__ __forceinline__ int recheck_own_slice(
 }
 
 // Append this wave's flagged points to the workgroup's slice.
-template <class T>
-__device__ __forceinline__ int append_flags(const WaveState<T>& w,
-                                            const bool (&flag)[T::PB],
-                                            int* sFlag, int* __restrict__ slice,
-                                            int lane) {
-  int total = 0;
-#pragma unroll
-  for (int pb = 0; pb < T::PB; ++pb) total += __popcll(__ballot(flag[pb]));
-  if (total == 0) return 0;
+__device__ __forceinline__ int append_flags(bool flag, int pid, int* sFlag,
+                                            int* __restrict__ slice, int lane) {
+  const uint64_t fm = __ballot(flag);
+  if (fm == 0) return 0;
+  const int total = __popcll(fm);
   int base = 0;
   if (lane == 0) base = atomicAdd(sFlag, total);           // LDS
   base = __shfl(base, 0);
-#pragma unroll
-  for (int pb = 0; pb < T::PB; ++pb) {
-    const uint64_t fm = __ballot(flag[pb]);
-    if (flag[pb]) slice[base + __popcll(fm & lanemask_lt())] = (int)w.pid[pb];
-    base += __popcll(fm);
-  }
+  if (flag) slice[base + __popcll(fm & lanemask_lt())] = pid;
   return total;
 }
 
