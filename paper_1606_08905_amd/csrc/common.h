@@ -140,6 +140,28 @@ __device__ __forceinline__ void wave_count_changed(bool pred,
 
 // Workgroup-wide sums of up to four per-thread counters, added once per
 // workgroup into the spread slots q0..q0+nq-1 of `row` (all threads call).
+// Workgroup copy of `count` elements: thread t handles elements t, t + nt,
+// ... in batches of B, issuing a batch's B loads before its first store, so
+// a batch costs one memory round trip (a plain strided loop waits on each
+// load before the next).  ld(e) returns element e; st(e, v) stores it.
+template <int B, typename V, typename Ld, typename St>
+__device__ __forceinline__ void stage_batched(int count, Ld ld, St st) {
+  const int nt = (int)blockDim.x;
+  for (int e0 = (int)threadIdx.x; e0 < count; e0 += B * nt) {
+    V v[B];
+#pragma unroll
+    for (int u = 0; u < B; ++u) {
+      const int e = e0 + u * nt;
+      if (e < count) v[u] = ld(e);
+    }
+#pragma unroll
+    for (int u = 0; u < B; ++u) {
+      const int e = e0 + u * nt;
+      if (e < count) st(e, v[u]);
+    }
+  }
+}
+
 template <int NQ>
 __device__ __forceinline__ void block_add_slots(unsigned long long* row,
                                                 const int (&q)[NQ],

@@ -234,8 +234,9 @@ __device__ __forceinline__ void tile_sweep_bf(WaveState<T>& w, const uint16_t* s
   }
 }
 
-// rows [0, cc) of the global hi/lo copies (row stride DP) into LDS (row
-// stride LDA), 16 bytes per step, and their norms
+// rows [c0, c0 + cc) of the global hi/lo copies (row stride DP) into LDS
+// (row stride LDA), 16 bytes per piece with four pieces of each copy per
+// thread in flight, and their norms
 template <int DP, int LDA>
 __device__ __forceinline__ void stage_bf(uint16_t* sH, uint16_t* sL, float* sN,
                                          const uint16_t* __restrict__ Chi,
@@ -243,15 +244,22 @@ __device__ __forceinline__ void stage_bf(uint16_t* sH, uint16_t* sL, float* sN,
                                          const float* __restrict__ cn, int c0,
                                          int cc) {
   constexpr int Q = DP / 8;
-  for (int e = threadIdx.x; e < cc * Q; e += kTileThreads) {
-    const int r = e / Q, q8 = e - r * Q;
-    const size_t src = (size_t)(c0 + r) * DP + q8 * 8;
-    *reinterpret_cast<uint4*>(&sH[r * LDA + q8 * 8]) =
-        *reinterpret_cast<const uint4*>(Chi + src);
-    *reinterpret_cast<uint4*>(&sL[r * LDA + q8 * 8]) =
-        *reinterpret_cast<const uint4*>(Clo + src);
-  }
-  for (int e = threadIdx.x; e < cc; e += kTileThreads) sN[e] = cn[c0 + e];
+  struct HL { uint4 h, l; };
+  stage_batched<4, HL>(
+      cc * Q,
+      [&](int e) {
+        const int r = e / Q, q8 = e - r * Q;
+        const size_t src = (size_t)(c0 + r) * DP + q8 * 8;
+        return HL{*reinterpret_cast<const uint4*>(Chi + src),
+                  *reinterpret_cast<const uint4*>(Clo + src)};
+      },
+      [&](int e, HL v) {
+        const int r = e / Q, q8 = e - r * Q;
+        *reinterpret_cast<uint4*>(&sH[r * LDA + q8 * 8]) = v.h;
+        *reinterpret_cast<uint4*>(&sL[r * LDA + q8 * 8]) = v.l;
+      });
+  stage_batched<8, float>(
+      cc, [&](int e) { return cn[c0 + e]; }, [&](int e, float v) { sN[e] = v; });
 }
 
 template <int DP>

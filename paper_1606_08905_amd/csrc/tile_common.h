@@ -68,6 +68,16 @@ __device__ __forceinline__ int wave_sum(int v) {
   return v;
 }
 
+// The same without the second index (three values, best index).
+__device__ __forceinline__ void top3_insert_lite(float& b1, float& b2, float& b3,
+                                                 int& i1, float y, int j) {
+  const bool lt1 = y < b1;
+  b3 = __builtin_amdgcn_fmed3f(b2, b3, y);
+  b2 = __builtin_amdgcn_fmed3f(b1, b2, y);
+  i1 = lt1 ? j : i1;
+  b1 = lt1 ? y : b1;
+}
+
 // Largest fp32(|c|^2) over the real centroids of a staged chunk.
 __device__ __forceinline__ float chunk_cmax(const float* sN, int cc, int c0,
                                             int k, int lane) {
@@ -83,7 +93,7 @@ __device__ __forceinline__ float chunk_cmax(const float* sN, int cc, int c0,
 // For two sorted triples a and o the union's second smallest is
 // min(max(a1, o1), a2, o2) and its third smallest is
 // min(a3, o3, max(a2, o1), max(a1, o2)).
-template <class T>
+template <class T, bool I2 = true>
 __device__ __forceinline__ void merge_groups(WaveState<T>& w) {
   constexpr int PB = T::PB;
 #pragma unroll
@@ -91,12 +101,12 @@ __device__ __forceinline__ void merge_groups(WaveState<T>& w) {
 #pragma unroll
     for (int pb = 0; pb < PB; ++pb) {
       const float a1 = w.b1[pb], a2 = w.b2[pb], a3 = w.b3[pb];
-      const int ia1 = w.i1[pb], ia2 = w.i2[pb];
+      const int ia1 = w.i1[pb], ia2 = I2 ? w.i2[pb] : 0;
       const float o1 = __shfl_xor(a1, off);
       const float o2 = __shfl_xor(a2, off);
       const float o3 = __shfl_xor(a3, off);
       const int io1 = __shfl_xor(ia1, off);
-      const int io2 = __shfl_xor(ia2, off);
+      const int io2 = I2 ? __shfl_xor(ia2, off) : 0;
       w.xs[pb] += __shfl_xor(w.xs[pb], off);
       const bool take = o1 < a1 || (o1 == a1 && io1 < ia1);
       // second: after a1 comes min(a2, o1); after o1 comes min(a1, o2)
@@ -111,7 +121,7 @@ __device__ __forceinline__ void merge_groups(WaveState<T>& w) {
       w.b1[pb] = take ? o1 : a1;
       w.i1[pb] = take ? io1 : ia1;
       w.b2[pb] = take ? s_o : s_a;
-      w.i2[pb] = take ? is_o : is_a;
+      if (I2) w.i2[pb] = take ? is_o : is_a;
       w.b3[pb] = t3;
     }
   }
@@ -163,20 +173,60 @@ __device__ __forceinline__ double chain_dist(const typename T::Frag (&bx)[T::KS]
 // that finds the list full goes to the full FP64 recheck instead.
 constexpr int kPairCap = 128;
 
-// Decide each point: lane group g finalises point block g (g < PB; the
-// merged values are equal in every group), so the bound arithmetic runs
-// once per lane instead of once per block.
-// With E the tile's error bound, the point is decided iff
+// The tile's decision for one point from its three smallest values (xs:
+// the FP64 sum of its squares, cmax: the largest fp32(|c|^2)).  With E the
+// tile's error bound, the point is decided iff
 //   y_2nd - y_best > 2E + 2.01 (d+2) 2^-53 (|x|^2 + y_best + E):
 // every other centroid's exact squared distance then exceeds the chosen
 // one's by more than the FP64 evaluation error of the definition, so the
 // FP64 argmin (with its lowest-index rule) picks the same centroid.
 // If instead only the third smallest value clears that margin, every
 // centroid other than the two best is excluded the same way, and the FP64
-// argmin over all centroids is the FP64 argmin of those two: the point is
-// queued for resolve_pairs().  Writes labels / bounds of decided points;
-// returns the lane's flag for the full FP64 recheck (and its point).
+// argmin over all centroids is the FP64 argmin of those two ("pair").
+// dbest bounds the squared distance to the best centroid from above.
+struct Decision {
+  bool decided, pair;
+  double dbest;
+};
+
 template <class T>
+__device__ __forceinline__ Decision decide_point(double xs, float b1, float b2,
+                                                 float b3, float cmax, int d,
+                                                 bool recheck_all, bool pairs) {
+  // R2 >= max |c|^2: cmax is the largest fp32(|c|^2), within 2^-24 of it
+  const double R2 = (double)cmax * (1.0 + 2.384185791015625e-07);  // 1+2^-22
+  const double e64 = (double)(d + 2) * 1.1102230246251565e-16;     // (d+2)2^-53
+  // xs sums exact squares in FP64: at most (d+4) roundings of 2^-53
+  const double xn2 = xs * (1.0 + (double)(d + 4) * 2.220446049250313e-16);
+  const double E = T::bound(xn2, R2, d);
+  const double y1 = (double)b1;
+  Decision r;
+  r.dbest = xn2 + y1 + E;
+  if (!(r.dbest > 0.0)) r.dbest = 0.0;
+  const double thr = 2.0 * E + 2.01 * e64 * r.dbest;
+  r.decided = !recheck_all && (double)b2 - y1 > thr;
+  r.pair = pairs && !recheck_all && !r.decided && (double)b3 - y1 > thr;
+  return r;
+}
+
+// Write a decided point's label and bound.
+__device__ __forceinline__ bool commit_label(int64_t p, int32_t old, int32_t a,
+                                             float bnd, int32_t* __restrict__ labels,
+                                             float* __restrict__ ub,
+                                             int* __restrict__ dirty) {
+  labels[p] = a;
+  if (ub) ub[p] = bnd;
+  if (old == a) return false;
+  mark_dirty(dirty, old, a);
+  return true;
+}
+
+// Decide each point: lane group g finalises point block g (g < PB; the
+// merged values are equal in every group), so the bound arithmetic runs
+// once per lane instead of once per block.  Decided points get their label
+// and bound; pair points are queued for the tail (with the second index
+// when I2); the rest are flagged for the full FP64 recheck.
+template <class T, bool I2 = true>
 __device__ __forceinline__ void finalize_points(
     WaveState<T>& w, float cmax, int d, int grp, int recheck_all, bool pairs,
     int4* sPair, int* sPairN, int32_t* __restrict__ labels,
@@ -188,7 +238,7 @@ __device__ __forceinline__ void finalize_points(
   bool valid = w.valid[0];
   double xs = w.xs[0];
   float b1 = w.b1[0], b2 = w.b2[0], b3 = w.b3[0];
-  int i1 = w.i1[0], i2 = w.i2[0];
+  int i1 = w.i1[0], i2 = I2 ? w.i2[0] : -1;
   int64_t p = w.pid[0];
   int32_t old = w.old[0];
 #pragma unroll
@@ -200,7 +250,7 @@ __device__ __forceinline__ void finalize_points(
     b2 = m ? w.b2[pb] : b2;
     b3 = m ? w.b3[pb] : b3;
     i1 = m ? w.i1[pb] : i1;
-    i2 = m ? w.i2[pb] : i2;
+    if (I2) i2 = m ? w.i2[pb] : i2;
     p = m ? w.pid[pb] : p;
     old = m ? w.old[pb] : old;
   }
@@ -208,22 +258,9 @@ __device__ __forceinline__ void finalize_points(
   pid = (int)p;
   changed = false;
   flag = false;
-  bool decided = false, pair = false;
-  double dbest = 0.0;
-  if (own) {
-    // R2 >= max |c|^2: cmax is the largest fp32(|c|^2), within 2^-24 of it
-    const double R2 = (double)cmax * (1.0 + 2.384185791015625e-07);  // 1+2^-22
-    const double e64 = (double)(d + 2) * 1.1102230246251565e-16;     // (d+2)2^-53
-    // xs sums exact squares in FP64: at most (d+4) roundings of 2^-53
-    const double xn2 = xs * (1.0 + (double)(d + 4) * 2.220446049250313e-16);
-    const double E = T::bound(xn2, R2, d);
-    const double y1 = (double)b1;
-    dbest = xn2 + y1 + E;
-    if (!(dbest > 0.0)) dbest = 0.0;
-    const double thr = 2.0 * E + 2.01 * e64 * dbest;
-    decided = !recheck_all && (double)b2 - y1 > thr;
-    pair = pairs && !recheck_all && !decided && (double)b3 - y1 > thr;
-  }
+  Decision dc{false, false, 0.0};
+  if (own) dc = decide_point<T>(xs, b1, b2, b3, cmax, d, recheck_all, pairs);
+  bool pair = dc.pair;
   if (pairs) {
     const uint64_t m = __ballot(pair);
     if (m) {
@@ -241,14 +278,15 @@ __device__ __forceinline__ void finalize_points(
     }
   }
   if (!own) return;
-  flag = !decided && !pair;
-  if (!decided) return;
-  labels[p] = i1;
-  if (old != i1) {
-    changed = true;
-    mark_dirty(dirty, old, i1);
-  }
-  if (ub) ub[p] = f32_up(sqrt(dbest) * (1.0 + 8.881784197001252e-16));
+  flag = !dc.decided && !pair;
+  if (!dc.decided) return;
+  changed = commit_label(p, old, i1, f32_up(sqrt(dc.dbest) * (1.0 + 8.881784197001252e-16)),
+                         labels, ub, dirty);
+}
+
+// Upper bound on the distance from a canonical FP64 squared distance.
+__device__ __forceinline__ float pair_bound(double D, int d) {
+  return f32_up(sqrt(D) * (1.0 + (double)(d + 4) * 2.220446049250313e-16));
 }
 
 // The queued two-candidate points (after a barrier; every thread calls this
@@ -274,15 +312,8 @@ __device__ __forceinline__ unsigned long long resolve_pairs(
     const double D2 = chain_dist<T>(bx, need, q.z, C64, d, grp, lane);
     if (need && grp == 0) {
       const bool second = D2 < D1 || (D2 == D1 && q.z < q.y);
-      const int a = second ? q.z : q.y;
-      labels[q.x] = a;
-      if (q.w != a) {
-        ++chg;
-        mark_dirty(dirty, q.w, a);
-      }
-      if (ub)
-        ub[q.x] = f32_up(sqrt(second ? D2 : D1) *
-                         (1.0 + (double)(d + 4) * 2.220446049250313e-16));
+      chg += commit_label(q.x, q.w, second ? q.z : q.y,
+                          pair_bound(second ? D2 : D1, d), labels, ub, dirty);
     }
   }
   return chg;
@@ -320,12 +351,13 @@ constexpr int kSegCache = 1024;
 __device__ __forceinline__ void seg_stage(const int* __restrict__ seg_cnt, int nseg,
                                           int up, int* sSeg, int* sWmax) {
   int mx = 0;
-  for (int e = threadIdx.x; e < nseg; e += blockDim.x) {
-    const int c = seg_cnt[e];
-    if (nseg <= kSegCache) sSeg[e] = c;
-    const int t = (c + up - 1) / up;
-    mx = t > mx ? t : mx;
-  }
+  stage_batched<8, int>(
+      nseg, [&](int e) { return seg_cnt[e]; },
+      [&](int e, int c) {
+        if (nseg <= kSegCache) sSeg[e] = c;
+        const int t = (c + up - 1) / up;
+        mx = t > mx ? t : mx;
+      });
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) {
     const int o = __shfl_xor(mx, off);

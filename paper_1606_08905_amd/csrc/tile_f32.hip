@@ -213,8 +213,9 @@ __device__ __forceinline__ void load_ablock(ABlock<T>& o, const float* arow,
 // One block of 16 centroids against the wave's PB point blocks.  The PB
 // accumulation chains are interleaved so consecutive matrix instructions are
 // independent.  Epilogue per value: the three smallest values by two
-// medians of three, and the indices of the two smallest by three selects.
-template <class T>
+// medians of three, and the index of the smallest (I2: of the two smallest)
+// by selects.
+template <class T, bool I2>
 __device__ __forceinline__ void tile_block(WaveState<T>& w, const ABlock<T>& o,
                                            int jb) {
   constexpr int KS = T::KS, PB = T::PB;
@@ -229,13 +230,17 @@ __device__ __forceinline__ void tile_block(WaveState<T>& w, const ABlock<T>& o,
 #pragma unroll
   for (int pb = 0; pb < PB; ++pb)
 #pragma unroll
-    for (int r = 0; r < 4; ++r)
-      top3_insert(w.b1[pb], w.b2[pb], w.b3[pb], w.i1[pb], w.i2[pb], acc[pb][r], jb + r);
+    for (int r = 0; r < 4; ++r) {
+      if (I2)
+        top3_insert(w.b1[pb], w.b2[pb], w.b3[pb], w.i1[pb], w.i2[pb], acc[pb][r], jb + r);
+      else
+        top3_insert_lite(w.b1[pb], w.b2[pb], w.b3[pb], w.i1[pb], acc[pb][r], jb + r);
+    }
 }
 
 // All centroid blocks [c0, c0 + cc) staged at sC/sN, with the next block's
 // operands loaded from LDS before the current block's matrix work.
-template <class T>
+template <class T, bool I2>
 __device__ __forceinline__ void tile_sweep(WaveState<T>& w, const float* sC,
                                            const float* sN, int cc, int c0,
                                            int col, int grp) {
@@ -245,9 +250,93 @@ __device__ __forceinline__ void tile_sweep(WaveState<T>& w, const float* sC,
   for (int cb = 0; cb < cc; cb += 16) {
     if (cb + 16 < cc)
       load_ablock<T>(nxt, &sC[(cb + 16 + col) * LDA + grp * KS], &sN[cb + 16 + 4 * grp]);
-    tile_block<T>(w, cur, c0 + cb + 4 * grp);
+    tile_block<T, I2>(w, cur, c0 + cb + 4 * grp);
     cur = nxt;
   }
+}
+
+// Rows [c0, c0 + cc) of -2c (row stride DP) into LDS (row stride LDA) and
+// their norms, B 16-byte loads per thread in flight.
+template <class T, int B>
+__device__ __forceinline__ void stage_cents(float* sC, float* sN,
+                                            const float* __restrict__ Cm2,
+                                            const float* __restrict__ cn, int c0,
+                                            int cc) {
+  constexpr int Q = T::KS;                     // 16-byte pieces per row (DP / 4)
+  stage_batched<B, float4>(
+      cc * Q,
+      [&](int e) {
+        const int r = e / Q, q4 = e - r * Q;
+        return *reinterpret_cast<const float4*>(Cm2 + (size_t)(c0 + r) * (4 * Q) + q4 * 4);
+      },
+      [&](int e, float4 v) {
+        const int r = e / Q, q4 = e - r * Q;
+        *reinterpret_cast<float4*>(&sC[r * T::LDA + q4 * 4]) = v;
+      });
+  stage_batched<B, float>(
+      cc, [&](int e) { return cn[c0 + e]; }, [&](int e, float v) { sN[e] = v; });
+}
+
+// Two-candidate points of the resident schedule, whose main loop keeps no
+// second index: each wave takes 16 queued points, sweeps them again over
+// the staged centroids with the full state, and decides them again from
+// those values; pairs are resolved from their two canonical FP64 distances,
+// and a point that no longer qualifies is decided or appended to the
+// recheck slice.  Returns this thread's count of changed labels.
+template <int DP>
+__device__ __forceinline__ unsigned long long resweep_pairs(
+    const float* __restrict__ X, int d, int vec, const double* __restrict__ C64,
+    const float* sC, const float* sN, int kpad, float cmax, const int4* sPair,
+    int np, int* sFlag, int* __restrict__ slice, int32_t* __restrict__ labels,
+    float* __restrict__ ub, int* __restrict__ dirty) {
+  using T1 = F32Tile<DP, 1>;
+  constexpr int KS = T1::KS;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int col = lane & 15, grp = lane >> 4;
+  unsigned long long chg = 0;
+  for (int e0 = wave * 16; e0 < np; e0 += kTileThreads / 4) {
+    const int e = e0 + col;
+    const bool need = e < np;
+    const int4 q = need ? sPair[e] : make_int4(0, 0, 0, 0);
+    WaveState<T1> w;
+    T1::load_row(w.bx[0], X, (int64_t)q.x, d, grp, vec, need);
+    double acc = 0.0;
+#pragma unroll
+    for (int s = 0; s < KS; ++s) {
+      const double v = (double)w.bx[0][s];
+      acc = acc + v * v;
+    }
+    w.xs[0] = acc;
+    top3_reset(w.b1[0], w.b2[0], w.b3[0], w.i1[0], w.i2[0]);
+    tile_sweep<T1, true>(w, sC, sN, kpad, 0, col, grp);
+    merge_groups<T1, true>(w);
+    const bool own = need && grp == 0;
+    Decision dc{false, false, 0.0};
+    if (own) dc = decide_point<T1>(w.xs[0], w.b1[0], w.b2[0], w.b3[0], cmax, d, false, true);
+    // the chain runs over the four lanes of a column
+    const bool pr = __shfl(dc.pair ? 1 : 0, col) != 0;
+    double D1 = 0.0, D2 = 0.0;
+    if (__ballot(pr)) {
+      D1 = chain_dist<T1>(w.bx[0], pr, w.i1[0], C64, d, grp, lane);
+      D2 = chain_dist<T1>(w.bx[0], pr, w.i2[0], C64, d, grp, lane);
+    }
+    bool flag = false;
+    if (own) {
+      if (dc.decided) {
+        chg += commit_label(q.x, q.w, w.i1[0],
+                            f32_up(sqrt(dc.dbest) * (1.0 + 8.881784197001252e-16)),
+                            labels, ub, dirty);
+      } else if (dc.pair) {
+        const bool second = D2 < D1 || (D2 == D1 && w.i2[0] < w.i1[0]);
+        chg += commit_label(q.x, q.w, second ? w.i2[0] : w.i1[0],
+                            pair_bound(second ? D2 : D1, d), labels, ub, dirty);
+      } else {
+        flag = true;
+      }
+    }
+    append_flags(flag, q.x, sFlag, slice, lane);
+  }
+  return chg;
 }
 
 template <int DP, int PB_>
@@ -276,12 +365,7 @@ __global__ __launch_bounds__(kTileThreads) void tile_f32_resident_kernel(
   __shared__ int sSeg[kSegCache], sWmax[kTileThreads / 64];
   if (threadIdx.x == 0) { sFlag = 0; sPairN = 0; }
   if (seg_cnt) seg_stage(seg_cnt, nseg, WUP, sSeg, sWmax);
-  for (int e = threadIdx.x; e < kpad * (DP / 4); e += kTileThreads) {
-    const int r = e / (DP / 4), q4 = e - r * (DP / 4);
-    *reinterpret_cast<float4*>(&sC[r * LDA + q4 * 4]) =
-        *reinterpret_cast<const float4*>(Cm2 + (size_t)r * DP + q4 * 4);
-  }
-  for (int e = threadIdx.x; e < kpad; e += kTileThreads) sN[e] = cn[e];
+  stage_cents<T, 8>(sC, sN, Cm2, cn, 0, kpad);
   if (cv < iter) return;
   __syncthreads();
   const float cmax = chunk_cmax(sN, kpad, 0, k, lane);
@@ -297,12 +381,12 @@ __global__ __launch_bounds__(kTileThreads) void tile_f32_resident_kernel(
     int64_t q0, m, base;
     if (!unit_range(wu, WUP, n, seg_cnt, segc, nseg, q0, m, base)) continue;
     load_points<T>(w, X, d, vec, list, labels, base, q0, m, col, grp);
-    tile_sweep<T>(w, sC, sN, kpad, 0, col, grp);
-    merge_groups<T>(w);
+    tile_sweep<T, false>(w, sC, sN, kpad, 0, col, grp);
+    merge_groups<T, false>(w);
     bool flag, changed;
     int fp;
-    finalize_points<T>(w, cmax, d, grp, recheck_all, pairs, sPair, &sPairN,
-                       labels, ub, dirty, flag, fp, changed);
+    finalize_points<T, false>(w, cmax, d, grp, recheck_all, pairs, sPair, &sPairN,
+                              labels, ub, dirty, flag, fp, changed);
     const int nf = append_flags(flag, fp, &sFlag, slice, lane);
     const int nc = __popcll(__ballot(changed));
     if (lane == 0) {
@@ -313,7 +397,9 @@ __global__ __launch_bounds__(kTileThreads) void tile_f32_resident_kernel(
   __syncthreads();
   const int np = sPairN < kPairCap ? sPairN : kPairCap;
   if constexpr (T::PAIR)
-    if (np) tot_chg += resolve_pairs<T, float>(X, d, vec, C64, sPair, np, labels, ub, dirty);
+    if (np)
+      tot_chg += resweep_pairs<DP>(X, d, vec, C64, sC, sN, kpad, cmax, sPair, np,
+                                   &sFlag, slice, labels, ub, dirty);
   const int q[2] = {SLOT_FLAGGED, SLOT_CHANGED};
   const unsigned long long v[2] = {tot_flag + (threadIdx.x == 0 ? np : 0), tot_chg};
   block_add_slots<2>(row, q, v);               // includes a barrier
@@ -363,15 +449,10 @@ __global__ __launch_bounds__(kTileThreads) void tile_f32_chunked_kernel(
     for (int c0 = 0; c0 < kpad; c0 += CK) {
       const int cc = (kpad - c0) < CK ? (kpad - c0) : CK;
       __syncthreads();
-      for (int e = threadIdx.x; e < cc * (DP / 4); e += kTileThreads) {
-        const int r = e / (DP / 4), q4 = e - r * (DP / 4);
-        *reinterpret_cast<float4*>(&sC[r * LDA + q4 * 4]) =
-            *reinterpret_cast<const float4*>(Cm2 + (size_t)(c0 + r) * DP + q4 * 4);
-      }
-      for (int e = threadIdx.x; e < cc; e += kTileThreads) sN[e] = cn[c0 + e];
+      stage_cents<T, 2>(sC, sN, Cm2, cn, c0, cc);     // point state is live here
       __syncthreads();
       cmax = fmax_nc(cmax, chunk_cmax(sN, cc, c0, k, lane));
-      tile_sweep<T>(w, sC, sN, cc, c0, col, grp);
+      tile_sweep<T, true>(w, sC, sN, cc, c0, col, grp);
     }
     merge_groups<T>(w);
     bool flag, changed;

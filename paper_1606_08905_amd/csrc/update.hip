@@ -592,11 +592,30 @@ __global__ __launch_bounds__(64 * kLeafWaves) void leaf_kernel(
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const bool staged = k <= kLeafStageK;
   if (staged) {
-    for (int e = threadIdx.x; e <= k; e += blockDim.x) sLo[e] = leaf_off[e];
-    for (int e0 = wave * 64; e0 < k; e0 += blockDim.x) {
-      const int e = e0 + lane;
+    // dirty bits: wave w packs the 64-cluster words w, w + 4, ...
+    if (k < (int)blockDim.x) {
+      if ((int)threadIdx.x <= k) sLo[threadIdx.x] = leaf_off[threadIdx.x];
+      const int e = wave * 64 + lane;
       const uint64_t m = __ballot(e < k && (!dirty || dirty[e]));
-      if (lane == 0) sDm[e0 >> 6] = m;
+      if (wave * 64 < k && lane == 0) sDm[wave] = m;
+    } else {
+      stage_batched<8, int>(
+          k + 1, [&](int e) { return leaf_off[e]; }, [&](int e, int v) { sLo[e] = v; });
+      constexpr int kB = 4;
+      for (int e0 = wave * 64; e0 < k; e0 += kB * (int)blockDim.x) {
+        int f[kB];
+#pragma unroll
+        for (int u = 0; u < kB; ++u) {
+          const int e = e0 + u * (int)blockDim.x + lane;
+          f[u] = e < k ? (dirty ? dirty[e] : 1) : 0;
+        }
+#pragma unroll
+        for (int u = 0; u < kB; ++u) {
+          const int w0 = e0 + u * (int)blockDim.x;   // uniform over the wave
+          const uint64_t m = __ballot(f[u] != 0);
+          if (w0 < k && lane == 0) sDm[w0 >> 6] = m;
+        }
+      }
     }
   }
   if (cv < iter) return;
@@ -663,7 +682,8 @@ __global__ __launch_bounds__(256) void tree_block(
     const int cnt = m - b * TB < TB ? m - b * TB : TB;
     if (cnt <= 1) continue;                  // uniform over the workgroup
     double* base = leafsum + (size_t)(L0 + b * TB) * d;
-    for (int e = threadIdx.x; e < cnt * d; e += blockDim.x) node[e] = base[e];
+    stage_batched<8, double>(
+        cnt * d, [&](int e) { return base[e]; }, [&](int e, double v) { node[e] = v; });
     __syncthreads();
     for (int s = 1; s < cnt; s <<= 1) {
       const int pairs = (cnt - s - 1) / (2 * s) + 1;
