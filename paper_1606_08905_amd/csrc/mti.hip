@@ -88,7 +88,11 @@ __global__ __launch_bounds__(kFilterThreads) void mti_filter_kernel(
     const unsigned long long* __restrict__ prev_row,
     unsigned long long* __restrict__ row, const int* __restrict__ conv,
     int iter, int vec) {
+  // stage-A candidates: point, its label and s(label) (stage B reads the
+  // last two from here instead of global memory)
   __shared__ int candA[kSeg];
+  __shared__ int candL[kSeg];
+  __shared__ float candS[kSeg];
   __shared__ int nA, nB;
   const int cv = *conv;
   const int seg = blockIdx.x;
@@ -150,7 +154,12 @@ __global__ __launch_bounds__(kFilterThreads) void mti_filter_kernel(
         if (lane_id() == __ffsll((unsigned long long)m) - 1)
           base = atomicAdd(&nA, __popcll(m));          // LDS atomic
         base = __shfl(base, __ffsll((unsigned long long)m) - 1);
-        if (cand[e]) candA[base + __popcll(m & lanemask_lt())] = (int)(pb + e);
+        if (cand[e]) {
+          const int slot = base + __popcll(m & lanemask_lt());
+          candA[slot] = (int)(pb + e);
+          candL[slot] = lab[e];
+          candS[slot] = sh[e];
+        }
       }
     }
   }
@@ -177,7 +186,7 @@ __global__ __launch_bounds__(kFilterThreads) void mti_filter_kernel(
     const int c = c0 + slot;
     const bool live = c < na;
     const int p = live ? candA[c] : 0;
-    const int a = live ? labels[p] : 0;
+    const int a = live ? candL[c] : 0;
     double part = 0.0;
     if (live) {
       const T* x = X + (size_t)p * d;
@@ -210,7 +219,7 @@ __global__ __launch_bounds__(kFilterThreads) void mti_filter_kernel(
       const double ub = f32_up(sqrt(part * (1.0 + (double)(d + 8) * 2.220446049250313e-16)) *
                                (1.0 + 8.881784197001252e-16));
       u[p] = (float)ub;
-      surv = !(ub * (1.0 + kEta) < (double)s_half[a]);
+      surv = !(ub * (1.0 + kEta) < (double)candS[c]);
     }
     uint64_t m = __ballot(surv);
     if (m) {
