@@ -36,10 +36,12 @@ PEAK_FP64_VALU = 78.6e12
 # is reported only while the kernel sources it was measured on are unchanged.
 MEASURED_TRAFFIC = {
     "assign_list": {
-        "bytes": (39695.8 + 7542.2) * 1024,
+        "bytes": (48286.0 + 7150.1) * 1024,
         "sources": {
-            "tile_f32.hip": "16b5beb74478542c900fca0683866aa6a62bfe82e17c62eed060fba303f92508",
-            "common.h": "e319868d6f43accd7e8752a544a1ee98906d8454174194c561409a60b3a85dc9",
+            "tile_f32.hip": "2612d89d6dc47fbd775b81bd9ce49294ad3a4d247af1c3305ac012019ea8ca94",
+            "tile_common.h": "208a2d868f991aa4158f135ad044dfc08bbe3bffd9259f2d02bddd769813b5c3",
+            "recheck.h": "cdd421f2b40c729a29f70a8c818d95f62f97c9fad5a0e4854d07f66baacaf0ad",
+            "common.h": "e931dc59dcd9a24cc364eb138422d22fe28b0ca7c61df19c9da743fc675efa3d",
         },
     },
 }
@@ -57,6 +59,9 @@ def measured_traffic(group):
                 return None
     return m["bytes"]
 
+
+# iterations whose dominant-group launches are timed inside the timed region
+PROFILE_EVERY = 10
 
 METRIC = ("Lloyd iters/s and point·centroid dists/s (% MFMA peak) "
           "at exact assignments")
@@ -82,29 +87,35 @@ def parse():
     return ap.parse_args()
 
 
-def group_work(g, n, d, k, sx, ctr, iters, mfma_peak=PEAK_FP32_MFMA):
-    """Algorithmic work of kernel group g summed over one fit:
-    (amount, unit, bound, peak).  ctr: per-iteration counters (iters x 8)."""
-    scanned_dense = int(ctr[0, 1]) if iters else 0
-    scanned_list = int(ctr[1:iters, 1].sum()) if iters > 1 else 0
+def group_work(g, n, d, k, sx, ctr, iters, mfma_peak=PEAK_FP32_MFMA, its=None):
+    """Algorithmic work of kernel group g summed over the iterations `its` of
+    one fit (default: all), and the group's launches among them:
+    (amount, launches, unit, bound, peak).  ctr: per-iteration counters
+    (iters x 8).  The dense tile runs at iteration 0; the survivor tile and
+    the filter at iterations >= 1; the other groups every iteration."""
+    its = list(range(iters)) if its is None else [t for t in its if t < iters]
+    after0 = [t for t in its if t >= 1]
     if g == 0:     # dense tile: 2 d flops per point-centroid pair
-        return 2.0 * d * k * scanned_dense, "TFLOP/s", "mfma", mfma_peak
+        at0 = [t for t in its if t == 0]
+        return (2.0 * d * k * sum(int(ctr[t, 1]) for t in at0), len(at0),
+                "TFLOP/s", "mfma", mfma_peak)
     if g == 1:
-        return 2.0 * d * k * scanned_list, "TFLOP/s", "mfma", mfma_peak
+        return (2.0 * d * k * sum(int(ctr[t, 1]) for t in after0), len(after0),
+                "TFLOP/s", "mfma", mfma_peak)
     if g == 2:     # FP64 recheck: subtract, multiply, add per (point, centroid, dim)
-        rech = int(ctr[:iters, 4].sum()) if iters else 0
-        return 3.0 * d * k * rech, "TFLOP/s", "alu", PEAK_FP64_VALU
+        rech = sum(int(ctr[t, 4]) for t in its)
+        return 3.0 * d * k * rech, len(its), "TFLOP/s", "alu", PEAK_FP64_VALU
     if g == 5:     # leaf sums: every row gathered once + perm + leaf sums out
         per_iter = n * d * sx + 4.0 * n + (n / 64.0 + k) * d * 8.0
-        return per_iter * iters, "GB/s", "hbm", PEAK_HBM
+        return per_iter * len(its), len(its), "GB/s", "hbm", PEAK_HBM
     if g == 3:     # filter: label, bound in/out, survivor index; rows tightened
         tot = 0.0
-        for t in range(1, iters):
+        for t in after0:
             pa = int(ctr[t, 2])
             tot += 12.0 * n + (n - pa) * (d * sx) + 4.0 * int(ctr[t, 1])
-        return tot, "GB/s", "hbm", PEAK_HBM
+        return tot, len(after0), "GB/s", "hbm", PEAK_HBM
     if g == 4:     # sort: labels read twice, perm written, block counts
-        return (12.0 * n) * iters, "GB/s", "hbm", PEAK_HBM
+        return (12.0 * n) * len(its), len(its), "GB/s", "hbm", PEAK_HBM
     return None
 
 
@@ -113,8 +124,8 @@ def roofline_of(knor, ms, la, g, steps, work):
     over `steps` fits) and its algorithmic work per fit."""
     if work is None or not la[g]:
         return None
-    amount, unit, bound, peak = work
-    per_launch = amount / max(1, la[g] / steps)
+    amount, launches, unit, bound, peak = work
+    per_launch = amount / max(1, launches)
     sec = ms[g] / la[g] / 1e3
     scale = 1e12 if unit == "TFLOP/s" else 1e9
     return {"kernel": knor.PROF_GROUPS[g], "bound": bound,
@@ -335,8 +346,9 @@ def main():
     step(profile=(cal_ms, cal_n))
     g_dom = int(np.argmax(cal_ms))
 
-    # timed region: K fits; only the dominant group is bracketed by HIP
-    # events (two event records per launch of that group)
+    # timed region: K fits; the dominant group's launches in iterations
+    # t % PROFILE_EVERY == 0 are bracketed by HIP events (each record costs
+    # the stream a few microseconds, so not every launch is timed)
     prof_ms = np.zeros(knor.NPROF)
     prof_n = np.zeros(knor.NPROF, np.int64)
     iters_total = 0
@@ -344,7 +356,7 @@ def main():
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(a.steps):
-        C, lab, st = step(profile=(prof_ms, prof_n, 1 << g_dom))
+        C, lab, st = step(profile=(prof_ms, prof_n, 1 << g_dom, PROFILE_EVERY))
         iters_total += st["iters"]
         stats.append(st)
     torch.cuda.synchronize()
@@ -364,10 +376,12 @@ def main():
                              "launches": int(cal_n[g]),
                              "us_per_launch": round(1e3 * cal_ms[g] / cal_n[g], 3)}
     roof = None
-    wk = group_work(g_dom, n, d, k, 4, ctr, iters)
+    sampled = [t for t in range(iters) if t % PROFILE_EVERY == 0]
+    wk = group_work(g_dom, n, d, k, 4, ctr, iters, its=sampled)
     if wk is not None and prof_n[g_dom]:
-        amount, unit, bound, peak = wk
-        per_launch = amount / max(1, prof_n[g_dom] / a.steps)
+        amount, launches, unit, bound, peak = wk
+        assert launches * a.steps == prof_n[g_dom], (launches, prof_n[g_dom])
+        per_launch = amount / max(1, launches)
         sec_per_launch = prof_ms[g_dom] / prof_n[g_dom] / 1e3
         achieved = per_launch / sec_per_launch
         scale = 1e12 if unit == "TFLOP/s" else 1e9

@@ -116,6 +116,9 @@ typedef struct {
                            as usual.  Labels do not depend on this option  */
   int32_t train_iters;  /* default 5 (when 0)                               */
   int32_t train_batches;/* default 16 (when 0)                              */
+  int32_t profile_every;/* time the groups of profile_mask only in iterations
+                           t with t % profile_every == 0 (fewer event
+                           records); 0 or 1 = every iteration               */
 } knor_opts;
 
 /* Kernel groups timed by opts->profile_ms. */

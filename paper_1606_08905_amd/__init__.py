@@ -55,7 +55,8 @@ class Opts(ctypes.Structure):
                 ("autotune", ctypes.c_int32),
                 ("learned", ctypes.c_int32),
                 ("train_iters", ctypes.c_int32),
-                ("train_batches", ctypes.c_int32)]
+                ("train_batches", ctypes.c_int32),
+                ("profile_every", ctypes.c_int32)]
 
 
 NPROF = 9
@@ -179,6 +180,7 @@ def _opts(prune=True, recheck=1, check_numeric=True, seed=0, stream=None,
         o.profile_ms = ms.ctypes.data
         o.profile_launches = launches.ctypes.data
         o.profile_mask = int(profile[2]) if len(profile) > 2 else 0
+        o.profile_every = int(profile[3]) if len(profile) > 3 else 0
     o.tile_blocks = int(tile_blocks)
     o.tile_resident = int(tile_resident)
     o.autotune = 1 if autotune else 0

@@ -135,7 +135,7 @@ hipError_t launch_gather_rows(const void* X, knor_dtype dt, int d,
 
 void Prof::begin(int g) {
   open = false;
-  if (!on || !((mask >> g) & 1)) return;
+  if (!on || !((mask >> g) & 1) || iter % every != 0) return;
   hipEvent_t a = nullptr, b = nullptr;
   if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) {
     (void)hipGetLastError();
@@ -217,7 +217,7 @@ struct Opts {
   int64_t* iter_counters = nullptr;
   double* profile_ms = nullptr;
   int64_t* profile_launches = nullptr;
-  int profile_mask = 0;
+  int profile_mask = 0, profile_every = 1;
   int tile_blocks = 0, tile_resident = 0, autotune = 0;
   int learned = 0, train_iters = 5, train_batches = 16;
 };
@@ -240,6 +240,8 @@ static knor_status read_opts(const knor_opts* o, Opts* out) {
   out->profile_ms = o->profile_ms;
   out->profile_launches = o->profile_launches;
   out->profile_mask = o->profile_mask;
+  if (o->profile_every < 0) return KNOR_ERR_INVALID_ARG;
+  if (o->profile_every > 0) out->profile_every = o->profile_every;
   if (o->poll_every > 0) out->poll_every = o->poll_every;
   if (o->tile_blocks != 0 && o->tile_blocks != 1 && o->tile_blocks != 2 &&
       o->tile_blocks != 4)
@@ -595,10 +597,12 @@ static knor_status fit_impl(const void* X, knor_dtype dt, int64_t n, int d,
   prof.stream = s;
   prof.on = o.profile_ms != nullptr || o.profile_launches != nullptr;
   prof.mask = o.profile_mask ? o.profile_mask : ~0;
+  prof.every = o.profile_every;
   Prof* pp = prof.on ? &prof : nullptr;
   const double tol_n = tol * (double)n;
   int hconv = kNotConverged;
   for (int t = 0; t < max_iters; ++t) {
+    prof.iter = t;
     unsigned long long* row = ctr + (size_t)t * ROW_STRIDE;
     AssignJob job{};
     job.X = X; job.dt = dt; job.n = n; job.d = d;

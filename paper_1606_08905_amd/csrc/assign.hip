@@ -96,8 +96,8 @@ __global__ __launch_bounds__(256) void exact_assign_lane(
         if (D < best) { best = D; a = j; }
       }
       int32_t old = labels[p];
-      labels[p] = a;
-      if (old != a) {
+      if (old != a) {                        // unchanged labels are not rewritten
+        labels[p] = a;
         changed = true;
         mark_dirty(dirty, old, a);
       }

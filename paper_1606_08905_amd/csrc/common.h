@@ -311,6 +311,7 @@ struct Prof {
   hipStream_t stream = nullptr;
   bool on = false;
   int mask = ~0;
+  int every = 1, iter = 0;   // time only iterations with iter % every == 0
   bool open = false;
   std::vector<int> groups;
   std::vector<hipEvent_t> starts, ends;

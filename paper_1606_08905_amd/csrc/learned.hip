@@ -741,10 +741,10 @@ __global__ __launch_bounds__(256) void mlp_certify_kernel(
         cert = ub * (1.0 + kEta) < (double)h;
         if (cert) {
           const int32_t old = labels[p];
-          labels[p] = bj;
           ub_out[p] = (float)ub;
           ++certified;
-          if (old != bj) {
+          if (old != bj) {                   // unchanged labels are not rewritten
+            labels[p] = bj;
             ++changes;
             mark_dirty(dirty, old, bj);
           }

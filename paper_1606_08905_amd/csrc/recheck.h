@@ -140,8 +140,8 @@ __device__ unsigned long long recheck_blocked(
         if (q == r) { bv = best[q]; jv = bj[q]; }
       if (p >= 0) {
         const int32_t old = labels[p];
-        labels[p] = jv;
-        if (old != jv) {
+        if (old != jv) {                     // unchanged labels are not rewritten
+          labels[p] = jv;
           ++changes;
           mark_dirty(dirty, old, jv);
         }
@@ -254,8 +254,8 @@ __device__ unsigned long long recheck_small(
       }
     }
     if (live_f && t == 0) {
-      labels[p] = a;
-      if (old != a) {
+      if (old != a) {                        // unchanged labels are not rewritten
+        labels[p] = a;
         ++changes;
         mark_dirty(dirty, old, a);
       }

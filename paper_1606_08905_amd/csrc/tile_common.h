@@ -209,14 +209,15 @@ __device__ __forceinline__ Decision decide_point(double xs, float b1, float b2,
   return r;
 }
 
-// Write a decided point's label and bound.
+// Write a decided point's bound, and its label when it changed (old is the
+// label the point had before this pass).
 __device__ __forceinline__ bool commit_label(int64_t p, int32_t old, int32_t a,
                                              float bnd, int32_t* __restrict__ labels,
                                              float* __restrict__ ub,
                                              int* __restrict__ dirty) {
-  labels[p] = a;
   if (ub) ub[p] = bnd;
   if (old == a) return false;
+  labels[p] = a;
   mark_dirty(dirty, old, a);
   return true;
 }
