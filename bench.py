@@ -30,10 +30,11 @@ PEAK_BF16_MFMA = 2516.6e12
 PEAK_HBM = 8.0e12              # bytes/s
 PEAK_FP64_VALU = 78.6e12
 
-# HBM bytes per launch of a kernel group, from rocprofv3 FETCH_SIZE and
-# WRITE_SIZE runs on this workload (medians over launches), each scaled by what
-# the counter reads for a 2 GiB device copy (fetch x2.0, write x1.0).  A figure
-# is reported only while the kernel sources it was measured on are unchanged.
+# HBM bytes per launch of a kernel group on the headline workload, from
+# rocprofv3 FETCH_SIZE and WRITE_SIZE runs (medians over launches), each scaled
+# by what the counter reads for a 2 GiB device copy (fetch x2.0, write x1.0).
+# A figure is reported only for that workload and only while the kernel
+# sources it was measured on are unchanged; the extended forms report null.
 MEASURED_TRAFFIC = {
     "assign_list": {
         "bytes": (48286.0 + 7150.1) * 1024,
@@ -121,7 +122,8 @@ def group_work(g, n, d, k, sx, ctr, iters, mfma_peak=PEAK_FP32_MFMA, its=None):
 
 def roofline_of(knor, ms, la, g, steps, work):
     """Roofline entry of kernel group g from event times (ms, launches summed
-    over `steps` fits) and its algorithmic work per fit."""
+    over `steps` fits) and its algorithmic work per fit (extended forms: no
+    measured traffic for their workloads)."""
     if work is None or not la[g]:
         return None
     amount, launches, unit, bound, peak = work
@@ -131,7 +133,7 @@ def roofline_of(knor, ms, la, g, steps, work):
     return {"kernel": knor.PROF_GROUPS[g], "bound": bound,
             "achieved": round(per_launch / sec / scale, 3), "peak": round(peak / scale, 1),
             "unit": unit, "frac": round(per_launch / sec / peak, 4),
-            "traffic": measured_traffic(knor.PROF_GROUPS[g]),
+            "traffic": None,
             "us_per_launch": round(sec * 1e6, 3)}
 
 

@@ -69,6 +69,9 @@ def test_fit_rejects_bad_opts(L):
     o.prune = 1
     o.recheck = 7
     assert _fit(L, opts=ctypes.byref(o)) == knor.KNOR_ERR_INVALID_ARG
+    o.recheck = 1
+    o.profile_every = -1
+    assert _fit(L, opts=ctypes.byref(o)) == knor.KNOR_ERR_INVALID_ARG
 
 
 def test_assign_update_reject_invalid(L):

@@ -319,6 +319,24 @@ def test_fit_workspace_cap():
     assert e.value.code == knor.KNOR_ERR_OUT_OF_MEMORY
 
 
+def test_profile_every_samples_iterations():
+    """profile=(ms, launches, mask, every) times the masked groups only in
+    iterations t with t % every == 0; the results do not change."""
+    knor = _knor()
+    w = workloads.config(2, n=30000, k=50, seed=1)
+    Xd, C0d = _dev(w.X, "f32"), _dev(w.C0, "f64")
+    ms = np.zeros(knor.NPROF)
+    la = np.zeros(knor.NPROF, np.int64)
+    list_g = knor.PROF_GROUPS.index("assign_list")
+    C, lab, st = knor.fit(Xd, 50, C0=C0d, max_iters=25, profile=(ms, la, 1 << list_g, 2))
+    sampled = [t for t in range(st["iters"]) if t >= 1 and t % 2 == 0]
+    assert len(sampled) >= 1
+    assert la[list_g] == len(sampled) and la.sum() == la[list_g]
+    assert ms[list_g] > 0
+    C2, lab2, _ = knor.fit(Xd, 50, C0=C0d, max_iters=25)
+    assert (C == C2).all() and (lab == lab2).all()
+
+
 def test_fit_deterministic_repeat():
     knor = _knor()
     w = workloads.config(2, n=30000, k=50, seed=1)
