@@ -42,7 +42,7 @@ static bool fused_sort(int k) { return k <= kFusedMaxK; }
 // The scatter computes the prefix over ranges itself when each of its
 // threads sums at most kScatterPrefix range totals (the 1024 threads split
 // as floor(1024 / k) parts per cluster); otherwise range_scan runs first.
-constexpr int kScatterPrefix = 24;
+constexpr int kScatterPrefix = 32;
 static bool scatter_prefix(int nb, int k) {
   const int parts = 1024 / k;
   return (nb + parts - 1) / parts <= kScatterPrefix;
@@ -50,10 +50,10 @@ static bool scatter_prefix(int nb, int k) {
 
 static int choose_block(int64_t n, int k) {
   if (fused_sort(k)) {
-    // sub-range per wave (a multiple of 64 points, about 512); a workgroup
-    // covers kFusedWaves sub-ranges; up to kFusedMaxRanges workgroups, whose
-    // prefixes over earlier ranges come from a separate column scan
-    int64_t ranges = (n + kFusedWaves * 512 - 1) / (kFusedWaves * 512);
+    // sub-range per wave (a multiple of 64 points, about 256, so that a
+    // million points spread over all CUs); a workgroup covers kFusedWaves
+    // sub-ranges; up to kFusedMaxRanges workgroups
+    int64_t ranges = (n + kFusedWaves * 256 - 1) / (kFusedWaves * 256);
     if (ranges > kFusedMaxRanges) ranges = kFusedMaxRanges;
     if (ranges < 1) ranges = 1;
     int64_t sb = (n + kFusedWaves * ranges - 1) / (kFusedWaves * ranges);
@@ -296,10 +296,10 @@ __global__ __launch_bounds__(256) void range_scan(const int* __restrict__ cnt,
 __global__ __launch_bounds__(1024) void scatter_fused(
     const int32_t* __restrict__ labels, int64_t n, int k, int SB,
     int bits, const int* __restrict__ cnt, const int* __restrict__ rpre,
-    int* __restrict__ nj, int in_prefix, const int* __restrict__ dirty,
+    int* __restrict__ nj, int in_prefix, int lab_lds, const int* __restrict__ dirty,
     int* __restrict__ perm, int* __restrict__ off_out,
     int* __restrict__ leaf_off_out, const int* __restrict__ conv, int iter) {
-  extern __shared__ int run[];               // kFusedWaves x k
+  extern __shared__ int run[];               // kFusedWaves x k (+ the range's labels)
   __shared__ int sa[1024], sb[1024];
   __shared__ int sDirty[kFusedMaxK];         // the dirty flags, read per point
   const int cv = *conv;
@@ -333,15 +333,17 @@ __global__ __launch_bounds__(1024) void scatter_fused(
 #pragma unroll
   for (int w = 0; w < kFusedWaves; ++w) wcnt[w] = j < k ? mine[(size_t)w * k + j] : 0;
   if (j < k) sDirty[j] = dirty ? dirty[j] : 1;
-  // the first kAhead chunks of this wave's labels, loaded with the above
   const int64_t p0 = ((int64_t)r * kFusedWaves + wave) * SB;
   const int64_t p1 = p0 + SB < n ? p0 + SB : n;
-  constexpr int kAhead = 16;
-  int labs[kAhead];
-#pragma unroll
-  for (int q = 0; q < kAhead; ++q) {
-    const int64_t p = p0 + q * 64 + lane;
-    labs[q] = p < p1 ? labels[p] : -1;
+  // with lab_lds the range's labels are staged in LDS here (their loads
+  // overlap the loads above), so the walk below waits only on LDS
+  int* sLab = run + kFusedWaves * k;
+  if (lab_lds) {
+    const int64_t r0 = (int64_t)r * kFusedWaves * SB;
+    const int64_t rn = n - r0 < (int64_t)kFusedWaves * SB ? n - r0 : (int64_t)kFusedWaves * SB;
+    stage_batched<4, int>(
+        (int)(rn > 0 ? rn : 0), [&](int e) { return labels[r0 + e]; },
+        [&](int e, int v) { sLab[e] = v; });
   }
   if (cv < iter) return;
   if (in_prefix) {
@@ -393,13 +395,14 @@ __global__ __launch_bounds__(1024) void scatter_fused(
   // labels of 16 chunks are loaded ahead so the walk only waits on LDS
   int* t = run + wave * k;
   const uint64_t lt = lanemask_lt();
+  constexpr int kAhead = 16;
   for (int64_t c0 = p0; c0 < p1; c0 += 64 * kAhead) {
-    if (c0 != p0)
+    int labs[kAhead];
 #pragma unroll
-      for (int q = 0; q < kAhead; ++q) {
-        const int64_t p = c0 + q * 64 + lane;
-        labs[q] = p < p1 ? labels[p] : -1;
-      }
+    for (int q = 0; q < kAhead; ++q) {
+      const int64_t p = c0 + q * 64 + lane;
+      labs[q] = p < p1 ? (lab_lds ? sLab[p - (int64_t)r * kFusedWaves * SB] : labels[p]) : -1;
+    }
 #pragma unroll
     for (int q = 0; q < kAhead; ++q) {
       const int64_t p = c0 + q * 64 + lane;
@@ -839,9 +842,12 @@ hipError_t launch_update(const UpdatePlan& p, const void* X, knor_dtype dt,
     if (!in_prefix)
       hipLaunchKernelGGL(range_scan, dim3(k), dim3(256), 0, s, p.blockcnt, p.nb,
                          k, p.rpre, p.nj, conv, iter);
-    hipLaunchKernelGGL(scatter_fused, dim3(p.nb), dim3(1024), lds, s, labels,
+    // the range's labels in LDS next to the running tables, within 48 KB
+    const int lab_lds = (size_t)kFusedWaves * (k + p.B) * sizeof(int) <= 49152 ? 1 : 0;
+    const size_t lds_s = lds + (lab_lds ? sizeof(int) * (size_t)kFusedWaves * p.B : 0);
+    hipLaunchKernelGGL(scatter_fused, dim3(p.nb), dim3(1024), lds_s, s, labels,
                        p.n, k, p.B, bits, p.blockcnt, p.rpre, p.nj, in_prefix,
-                       dirty, p.perm, p.off, p.leaf_off, conv, iter);
+                       lab_lds, dirty, p.perm, p.off, p.leaf_off, conv, iter);
   } else {
     const size_t lds_k = sizeof(int) * (size_t)k;
     hipLaunchKernelGGL(hist_kernel, dim3(p.nb), dim3(256), lds_k, s, labels,
