@@ -16,6 +16,9 @@ Functions and the passage each follows (Mhembere et al., HPDC'17):
   mti_fit          Lloyd's with MTI Clauses 1-3   -- Section "Minimal Triangle
                                                      Inequality (MTI) Pruning"
   cc_bounds        s(c) = 1/2 min_{j!=c} d(c, j)  -- same section
+  update_exact,    the member mean rounded once   -- Phase II, second reading:
+  exact_mean,      (ties to even) from an exact      the mean itself, free of
+  fit_exact_mean   fixed-point sum                   any summation order
   canonical_sum    the fixed summation order used for sums of many terms
 """
 from __future__ import annotations
@@ -96,6 +99,12 @@ class Oracle:
         for fn in (L.oracle_fit, L.oracle_mti_fit):
             fn.argtypes = [P, i64, ctypes.c_int, ctypes.c_int, P, ctypes.c_int,
                            f64, P, P, ctypes.POINTER(_Trace)]
+        L.oracle_update_exact.argtypes = [P, i64, ctypes.c_int, P, ctypes.c_int, P, P, P]
+        L.oracle_exact_mean.argtypes = [P, i64]
+        L.oracle_exact_mean.restype = f64
+        L.oracle_fit_ex.argtypes = [P, i64, ctypes.c_int, ctypes.c_int, P, ctypes.c_int,
+                                    f64, ctypes.c_int, ctypes.c_int, P, P,
+                                    ctypes.POINTER(_Trace)]
         L.oracle_cc_bounds.argtypes = [P, ctypes.c_int, ctypes.c_int, P]
         L.oracle_canonical_sum.argtypes = [P, i64]
         L.oracle_canonical_sum.restype = f64
@@ -134,6 +143,22 @@ class Oracle:
                                     _ptr(C_prev), _ptr(C), _ptr(cnt)), "update")
         return C, cnt
 
+    def update_exact(self, X, labels, C_prev):
+        """(C_new, counts) with each centroid the exactly rounded mean."""
+        X, C_prev = _f64(X), _f64(C_prev)
+        labels = np.ascontiguousarray(labels, dtype=np.int32)
+        n, d = X.shape
+        k = C_prev.shape[0]
+        C = np.empty((k, d), np.float64)
+        cnt = np.empty(k, np.int64)
+        _check(self.L.oracle_update_exact(_ptr(X), n, d, _ptr(labels), k,
+                                          _ptr(C_prev), _ptr(C), _ptr(cnt)), "update_exact")
+        return C, cnt
+
+    def exact_mean(self, v) -> float:
+        v = _f64(v)
+        return float(self.L.oracle_exact_mean(_ptr(v), v.size))
+
     def canonical_sum(self, v) -> float:
         v = _f64(v)
         return float(self.L.oracle_canonical_sum(_ptr(v), v.size))
@@ -153,7 +178,7 @@ class Oracle:
         _check(self.L.oracle_cc_bounds(_ptr(C), k, d, _ptr(s)), "cc_bounds")
         return s
 
-    def _fit(self, fn, X, C0, max_iters, tol, history, objective):
+    def _fit(self, fn, X, C0, max_iters, tol, history, objective, extra=()):
         X, C0 = _f64(X), _f64(C0)
         n, d = X.shape
         k = C0.shape[0]
@@ -168,7 +193,7 @@ class Oracle:
                     ob.ctypes.data if ob is not None else None,
                     nd.ctypes.data, p1.ctypes.data,
                     hist.ctypes.data if hist is not None else None, 0)
-        _check(fn(_ptr(X), n, d, k, _ptr(C0), max_iters, float(tol), _ptr(C),
+        _check(fn(_ptr(X), n, d, k, _ptr(C0), max_iters, float(tol), *extra, _ptr(C),
                   _ptr(lab), ctypes.byref(tr)), "fit")
         it = tr.iters
         return FitResult(C=C, labels=lab, iters=it,
@@ -183,10 +208,20 @@ class Oracle:
         return self._fit(self.L.oracle_fit, X, C0, max_iters, tol, history,
                          objective)
 
-    def mti_fit(self, X, C0, max_iters, tol=0.0, history=False, objective=True):
-        """FP64 Lloyd's with MTI Clauses 1-3 (labels equal plain Lloyd's)."""
+    def mti_fit(self, X, C0, max_iters, tol=0.0, history=False, objective=True,
+                exact_mean=False):
+        """FP64 Lloyd's with MTI Clauses 1-3 (labels equal plain Lloyd's);
+        exact_mean=True: centroids are exactly rounded means."""
+        if exact_mean:
+            return self._fit(self.L.oracle_fit_ex, X, C0, max_iters, tol, history,
+                             objective, extra=(1, 1))
         return self._fit(self.L.oracle_mti_fit, X, C0, max_iters, tol, history,
                          objective)
+
+    def fit_exact_mean(self, X, C0, max_iters, tol=0.0, history=False, objective=True):
+        """Plain FP64 Lloyd's with exactly rounded means."""
+        return self._fit(self.L.oracle_fit_ex, X, C0, max_iters, tol, history,
+                         objective, extra=(0, 1))
 
 
 _default = None
@@ -219,6 +254,14 @@ def update(X, labels, C_prev):
     return default().update(X, labels, C_prev)
 
 
+def update_exact(X, labels, C_prev):
+    return default().update_exact(X, labels, C_prev)
+
+
+def exact_mean(v):
+    return default().exact_mean(v)
+
+
 def canonical_sum(v):
     return default().canonical_sum(v)
 
@@ -235,5 +278,9 @@ def fit(X, C0, max_iters, tol=0.0, history=False, objective=True):
     return default().fit(X, C0, max_iters, tol, history, objective)
 
 
-def mti_fit(X, C0, max_iters, tol=0.0, history=False, objective=True):
-    return default().mti_fit(X, C0, max_iters, tol, history, objective)
+def mti_fit(X, C0, max_iters, tol=0.0, history=False, objective=True, exact_mean=False):
+    return default().mti_fit(X, C0, max_iters, tol, history, objective, exact_mean)
+
+
+def fit_exact_mean(X, C0, max_iters, tol=0.0, history=False, objective=True):
+    return default().fit_exact_mean(X, C0, max_iters, tol, history, objective)

@@ -25,7 +25,9 @@
  *    starting from the first member's value, leaf sums combined by the
  *    pairwise tree Pair(s[0:m]) = Pair(s[0:h]) + Pair(s[h:m]), h the largest
  *    power of two below m; then one correctly rounded division by the count.
- *    An empty cluster keeps its previous centroid.
+ *    An empty cluster keeps its previous centroid.  A second reading,
+ *    oracle_update_exact, rounds the exact mean once (ties to even), which
+ *    makes the centroid independent of any summation order.
  *  - loop: stop when #changed labels <= tol * n, or after max_iters.
  *  - MTI (Section "Minimal Triangle Inequality (MTI) Pruning"): one upper
  *    bound u per point, drift f(c) = d(c^t, c^{t-1}), centroid-pair distances
@@ -191,6 +193,149 @@ int oracle_update(const double* X, int64_t n, int d, const int32_t* labels,
 }
 
 /* ------------------------------------------------------------------------ */
+/* update, second reading: the exactly rounded mean                          */
+/* ------------------------------------------------------------------------ */
+
+/* The centroid as the mean of its members with a single rounding: the
+ * exact sum of the members' values divided by their count, rounded to the
+ * nearest double (ties to even).  Unlike the canonical sum above it does not
+ * depend on the order of the members.
+ *
+ * The exact sum is kept as two non-negative fixed-point integers (the sums
+ * of the positive and of the negative terms) in units of 2^-1074, the
+ * spacing of the smallest doubles: every finite double is an integer in
+ * these units below 2^2098, and XW 64-bit words leave room for 2^63 terms. */
+#define XW 34
+
+typedef struct {
+  uint64_t pos[XW], neg[XW];
+} xacc;
+
+/* w += m * 2^shift (m < 2^64) */
+static void xw_add_shifted(uint64_t* w, uint64_t m, int64_t shift) {
+  int64_t i = shift / 64;
+  int off = (int)(shift % 64);
+  uint64_t lo = m << off;
+  uint64_t hi = off ? (m >> (64 - off)) : 0;
+  uint64_t carry = 0;
+  for (int64_t j = i; j < XW; ++j) {
+    uint64_t add = (j == i) ? lo : (j == i + 1 ? hi : 0);
+    uint64_t t = w[j] + add;
+    uint64_t c1 = t < add;
+    uint64_t t2 = t + carry;
+    uint64_t c2 = t2 < carry;
+    w[j] = t2;
+    carry = c1 | c2;
+    if (j > i && !carry && j >= i + 1) break;
+  }
+}
+
+static void xacc_add(xacc* a, double v) {
+  if (v == 0.0) return;
+  int e;
+  double f = frexp(fabs(v), &e);              /* |v| = f 2^e, f in [0.5, 1) */
+  uint64_t m = (uint64_t)ldexp(f, 53);        /* |v| = m 2^(e-53), exactly  */
+  int64_t shift = (int64_t)e - 53 + 1074;     /* in units of 2^-1074        */
+  if (shift < 0) {                            /* subnormal: the low bits of */
+    m >>= -shift;                             /* m are zero                 */
+    shift = 0;
+  }
+  xw_add_shifted(v > 0 ? a->pos : a->neg, m, shift);
+}
+
+/* Bit b of a little-endian word array. */
+static int xw_bit(const uint64_t* w, int64_t b) {
+  return (int)((w[b / 64] >> (b % 64)) & 1u);
+}
+
+/* RN((pos - neg) * 2^-1074 / n), n >= 1. */
+static double xacc_mean(const xacc* a, int64_t n) {
+  uint64_t mag[XW];
+  /* mag = |pos - neg|, sign from the comparison */
+  int cmp = 0;
+  for (int j = XW - 1; j >= 0 && cmp == 0; --j)
+    cmp = a->pos[j] > a->neg[j] ? 1 : (a->pos[j] < a->neg[j] ? -1 : 0);
+  if (cmp == 0) return 0.0;
+  const uint64_t* big = cmp > 0 ? a->pos : a->neg;
+  const uint64_t* small = cmp > 0 ? a->neg : a->pos;
+  uint64_t borrow = 0;
+  for (int j = 0; j < XW; ++j) {
+    uint64_t t = big[j] - small[j];
+    uint64_t b1 = big[j] < small[j];
+    uint64_t t2 = t - borrow;
+    uint64_t b2 = t < borrow;
+    mag[j] = t2;
+    borrow = b1 | b2;
+  }
+  /* q = floor(mag * 2^128 / n), units 2^-1202; rem != 0 marks a remainder */
+  enum { QW = XW + 2 };
+  uint64_t num[QW], q[QW];
+  num[0] = 0;
+  num[1] = 0;
+  for (int j = 0; j < XW; ++j) num[j + 2] = mag[j];
+  unsigned __int128 rem = 0;
+  for (int j = QW - 1; j >= 0; --j) {
+    unsigned __int128 cur = (rem << 64) | num[j];
+    q[j] = (uint64_t)(cur / (uint64_t)n);
+    rem = cur % (uint64_t)n;
+  }
+  int64_t top = -1;
+  for (int64_t b = (int64_t)QW * 64 - 1; b >= 0; --b)
+    if (xw_bit(q, b)) { top = b; break; }
+  if (top < 0) return cmp > 0 ? 0.0 : -0.0;   /* below half of 2^-1202 ... */
+  /* result ulp: 2^(top - 52) in q's units, at least 2^-1074 = 2^128 units */
+  int64_t sh = top - 52 > 128 ? top - 52 : 128;
+  uint64_t mant = 0;
+  for (int64_t b = top; b >= sh; --b) mant = (mant << 1) | (uint64_t)xw_bit(q, b);
+  int round = sh >= 1 ? xw_bit(q, sh - 1) : 0;
+  int sticky = rem != 0;
+  for (int64_t b = sh - 2; b >= 0 && !sticky; --b) sticky = xw_bit(q, b);
+  if (round && (sticky || (mant & 1u))) mant += 1;
+  double r = ldexp((double)mant, (int)(sh - 1202));
+  return cmp > 0 ? r : -r;
+}
+
+/* C_out[j] = the exactly rounded mean of the rows with labels == j; an empty
+ * cluster copies C_prev[j].  counts (may be NULL) gets |members|. */
+int oracle_update_exact(const double* X, int64_t n, int d, const int32_t* labels,
+                        int k, const double* C_prev, double* C_out,
+                        int64_t* counts) {
+  if (!X || !labels || !C_prev || !C_out || n < 0 || d < 1 || k < 1)
+    return OR_ERR_ARG;
+  for (int64_t p = 0; p < n; ++p)
+    if (labels[p] < 0 || labels[p] >= k) return OR_ERR_ARG;
+  int64_t* cnt = (int64_t*)calloc((size_t)k, sizeof(int64_t));
+  if (!cnt) return OR_ERR_MEM;
+  for (int64_t p = 0; p < n; ++p) cnt[labels[p]]++;
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int j = 0; j < k; ++j) {
+    double* c = C_out + (size_t)j * d;
+    if (cnt[j] == 0) {                       /* empty: keep the previous */
+      for (int i = 0; i < d; ++i) c[i] = C_prev[(size_t)j * d + i];
+      continue;
+    }
+    xacc* acc = (xacc*)calloc((size_t)d, sizeof(xacc));
+    for (int64_t p = 0; p < n; ++p)
+      if (labels[p] == j)
+        for (int i = 0; i < d; ++i) xacc_add(&acc[i], X[(size_t)p * d + i]);
+    for (int i = 0; i < d; ++i) c[i] = xacc_mean(&acc[i], cnt[j]);
+    free(acc);
+  }
+  if (counts)
+    for (int j = 0; j < k; ++j) counts[j] = cnt[j];
+  free(cnt);
+  return OR_OK;
+}
+
+/* The exactly rounded mean of v[0..n) (n >= 1). */
+double oracle_exact_mean(const double* v, int64_t n) {
+  xacc a;
+  memset(&a, 0, sizeof a);
+  for (int64_t i = 0; i < n; ++i) xacc_add(&a, v[i]);
+  return xacc_mean(&a, n);
+}
+
+/* ------------------------------------------------------------------------ */
 /* Lloyd's loop                                                              */
 /* ------------------------------------------------------------------------ */
 
@@ -209,18 +354,28 @@ typedef struct {
 
 static int fit_common(const double* X, int64_t n, int d, int k,
                       const double* C0, int max_iters, double tol, int mti,
-                      double* C_out, int32_t* labels_out, oracle_trace* tr);
+                      int exact_mean, double* C_out, int32_t* labels_out,
+                      oracle_trace* tr);
 
 int oracle_fit(const double* X, int64_t n, int d, int k, const double* C0,
                int max_iters, double tol, double* C_out, int32_t* labels_out,
                oracle_trace* tr) {
-  return fit_common(X, n, d, k, C0, max_iters, tol, 0, C_out, labels_out, tr);
+  return fit_common(X, n, d, k, C0, max_iters, tol, 0, 0, C_out, labels_out, tr);
 }
 
 int oracle_mti_fit(const double* X, int64_t n, int d, int k, const double* C0,
                    int max_iters, double tol, double* C_out,
                    int32_t* labels_out, oracle_trace* tr) {
-  return fit_common(X, n, d, k, C0, max_iters, tol, 1, C_out, labels_out, tr);
+  return fit_common(X, n, d, k, C0, max_iters, tol, 1, 0, C_out, labels_out, tr);
+}
+
+/* Either loop with either update: exact_mean = 1 takes the exactly rounded
+ * mean (oracle_update_exact) instead of the canonical sum. */
+int oracle_fit_ex(const double* X, int64_t n, int d, int k, const double* C0,
+                  int max_iters, double tol, int mti, int exact_mean,
+                  double* C_out, int32_t* labels_out, oracle_trace* tr) {
+  return fit_common(X, n, d, k, C0, max_iters, tol, mti ? 1 : 0,
+                    exact_mean ? 1 : 0, C_out, labels_out, tr);
 }
 
 /* MTI assignment of one point for iteration t >= 1 (Clauses 1-3).
@@ -278,7 +433,8 @@ static int64_t mti_point(const double* x, const double* C, int d, int k,
 
 static int fit_common(const double* X, int64_t n, int d, int k,
                       const double* C0, int max_iters, double tol, int mti,
-                      double* C_out, int32_t* labels_out, oracle_trace* tr) {
+                      int exact_mean, double* C_out, int32_t* labels_out,
+                      oracle_trace* tr) {
   if (!X || !C0 || !C_out || !labels_out || n < 1 || d < 1 || k < 1 ||
       k > n || max_iters < 1 || !(tol >= 0.0 && tol < 1.0))
     return OR_ERR_ARG;
@@ -345,7 +501,10 @@ static int fit_common(const double* X, int64_t n, int d, int k,
       if (tr->label_hist)
         memcpy(tr->label_hist + (size_t)t * n, a, sizeof(int32_t) * (size_t)n);
     }
-    oracle_update(X, n, d, a, k, C, Cn, NULL);
+    if (exact_mean)
+      oracle_update_exact(X, n, d, a, k, C, Cn, NULL);
+    else
+      oracle_update(X, n, d, a, k, C, Cn, NULL);
     if (mti) {
       /* drift f(c) = d(c^{t+1}, c^t); centroid-pair distances; s(c). */
       for (int j = 0; j < k; ++j)

@@ -14,6 +14,7 @@ import tempfile
 import pytest
 
 import oracle
+import tests.test_oracle_exact_mean as xm
 import tests.test_oracle_pins as pins
 
 SRC = os.path.join(os.path.dirname(oracle.__file__), "knor_oracle.c")
@@ -38,6 +39,18 @@ MUTANTS = [
      "s[i] = m;\n      }\n      for (int64_t p"),
     ("no-drift", "for (int64_t p = 0; p < n; ++p) u[p] = u[p] + drift[a[p]];",
      "for (int64_t p = 0; p < n; ++p) u[p] = u[p];"),
+    ("exact-ties-away", "if (round && (sticky || (mant & 1u))) mant += 1;",
+     "if (round) mant += 1;"),
+    ("exact-truncate", "if (round && (sticky || (mant & 1u))) mant += 1;", ""),
+    ("exact-sign-lost", "xw_add_shifted(v > 0 ? a->pos : a->neg, m, shift);",
+     "xw_add_shifted(a->pos, m, shift);"),
+    ("exact-carry-dropped", "    carry = c1 | c2;\n", "    carry = 0;\n"),
+    ("exact-unit", "int64_t shift = (int64_t)e - 53 + 1074;",
+     "int64_t shift = (int64_t)e - 52 + 1074;"),
+    ("exact-subnormal-lost", "m >>= -shift;", "m = 0;"),
+    ("exact-empty-to-zero",
+     "for (int i = 0; i < d; ++i) c[i] = C_prev[(size_t)j * d + i];",
+     "for (int i = 0; i < d; ++i) c[i] = 0.0;"),
     ("clause2-no-half", "0.5 * CC[(size_t)a * k + j] * (1.0 - ETA)) continue;\n    if",
      "1.0 * CC[(size_t)a * k + j] * (1.0 - ETA)) continue;\n    if"),
 ]
@@ -58,6 +71,11 @@ CHECKS = [
     (pins.test_mti_equals_plain_every_iteration, {"case": "cfg2"}),
     (pins.test_mti_equals_plain_every_iteration, {"case": "uniform"}),
     (pins.test_mti_equals_plain_every_iteration, {"case": "dups"}),
+    (xm.test_exact_mean_is_correctly_rounded, {"seed": 0}),
+    (xm.test_exact_mean_ties_to_even, {}),
+    (xm.test_exact_mean_subnormal_and_extreme, {}),
+    (xm.test_exact_mean_many_terms_carry, {}),
+    (xm.test_update_exact_against_rationals, {"seed": 0}),
 ]
 
 
