@@ -119,6 +119,19 @@ typedef struct {
   int32_t profile_every;/* time the groups of profile_mask only in iterations
                            t with t % profile_every == 0 (fewer event
                            records); 0 or 1 = every iteration               */
+  int32_t update;       /* centroid update of knor_fit, knor_fit_batched and
+                           knor_update.  0 (default): the member sum in the
+                           canonical order (members by point index, leaves
+                           of 64 summed left to right, pairwise tree over
+                           the leaves), then one division.  1: the exact
+                           mean of the members, rounded once to nearest
+                           (ties to even), which no summation order changes;
+                           inside a fit only the points whose label changed
+                           move between the clusters' exact sums when few
+                           do.  1 needs FP32 or BF16 points (FP64:
+                           KNOR_ERR_UNSUPPORTED).  The two readings may
+                           differ in the last bit of a centroid and so,
+                           rarely, in a later label                          */
 } knor_opts;
 
 /* Kernel groups timed by opts->profile_ms. */

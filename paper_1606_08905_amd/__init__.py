@@ -56,7 +56,8 @@ class Opts(ctypes.Structure):
                 ("learned", ctypes.c_int32),
                 ("train_iters", ctypes.c_int32),
                 ("train_batches", ctypes.c_int32),
-                ("profile_every", ctypes.c_int32)]
+                ("profile_every", ctypes.c_int32),
+                ("update", ctypes.c_int32)]
 
 
 NPROF = 9
@@ -160,7 +161,8 @@ def _raise(rc):
 def _opts(prune=True, recheck=1, check_numeric=True, seed=0, stream=None,
           workspace_cap=0, label_history=None, iter_counters=None,
           poll_every=0, profile=None, tile_blocks=0, tile_resident=0,
-          autotune=False, learned=False, train_iters=0, train_batches=0):
+          autotune=False, learned=False, train_iters=0, train_batches=0,
+          update="canonical"):
     torch = _torch()
     if stream is None:
         stream = torch.cuda.current_stream()
@@ -187,14 +189,24 @@ def _opts(prune=True, recheck=1, check_numeric=True, seed=0, stream=None,
     o.learned = 1 if learned else 0
     o.train_iters = int(train_iters)
     o.train_batches = int(train_batches)
+    o.update = _update_code(update)
     return o
+
+
+UPDATES = {"canonical": 0, "exact": 1}
+
+
+def _update_code(update):
+    if update not in UPDATES:
+        raise ValueError(f"update must be one of {sorted(UPDATES)}")
+    return UPDATES[update]
 
 
 def fit(X, k, C0=None, init="given", max_iters=100, tol=0.0, prune=True,
         recheck=1, seed=0, history=False, counters=False, out=None,
         check_numeric=True, workspace_cap=0, poll_every=0, profile=None,
         tile_blocks=0, tile_resident=0, autotune=False, learned=False,
-        train_iters=0, train_batches=0):
+        train_iters=0, train_batches=0, update="canonical"):
     """Lloyd's k-means on the GPU.  Returns (C, labels, stats dict).
 
     history=True adds stats["label_history"]: (iters, n) int32 CUDA tensor of
@@ -208,7 +220,10 @@ def fit(X, k, C0=None, init="given", max_iters=100, tol=0.0, prune=True,
     chunked); autotune=True times the schedules of this (d, k) class once
     per process.  No schedule changes the results.  learned=True adds the
     certified MLP candidate proposal on MTI survivors (train_iters /
-    train_batches: 0 = library defaults); it never changes the results."""
+    train_batches: 0 = library defaults); it never changes the results.
+    update="exact" takes each centroid as the exact member mean rounded once
+    (FP32 / BF16 points), moving only changed points between sums when few
+    change; "canonical" (default) sums in the canonical order."""
     torch = _torch()
     import numpy as np
     L = load()
@@ -232,7 +247,7 @@ def fit(X, k, C0=None, init="given", max_iters=100, tol=0.0, prune=True,
     cnt = np.zeros((max_iters, NCOUNTERS), np.int64) if counters else None
     o = _opts(prune, recheck, check_numeric, seed, None, workspace_cap, hist,
               cnt, poll_every, profile, tile_blocks, tile_resident, autotune,
-              learned, train_iters, train_batches)
+              learned, train_iters, train_batches, update)
     st = Stats()
     rc = L.knor_fit(X.data_ptr(), _dtype_code(X), n, d, k, init_code, c0p,
                     max_iters, float(tol), ctypes.byref(o), C.data_ptr(),
@@ -247,7 +262,7 @@ def fit(X, k, C0=None, init="given", max_iters=100, tol=0.0, prune=True,
 
 
 def fit_batched(problems, prune=True, recheck=1, seed=0, check_numeric=True,
-                workspace_cap=0, tile_blocks=0, tile_resident=0):
+                workspace_cap=0, tile_blocks=0, tile_resident=0, update="canonical"):
     """knor_fit on each problem of a batch, run concurrently.  problems: list
     of dicts with keys X, k and optionally C0 (None: Forgy from seed + index),
     max_iters (default 100), tol (default 0).  Returns a list of
@@ -274,7 +289,7 @@ def fit_batched(problems, prune=True, recheck=1, seed=0, check_numeric=True,
         a.C_out = C.data_ptr(); a.labels_out = lab.data_ptr()
         outs.append((C, lab))
     o = _opts(prune, recheck, check_numeric, seed, None, workspace_cap,
-              tile_blocks=tile_blocks, tile_resident=tile_resident)
+              tile_blocks=tile_blocks, tile_resident=tile_resident, update=update)
     sts = (Stats * max(1, len(problems)))()
     rc = L.knor_fit_batched(arr, len(problems), ctypes.byref(o), sts)
     _raise(rc)
@@ -302,8 +317,9 @@ def assign(X, C, recheck=1, dist2=False):
     return (lab, dd) if dist2 else lab
 
 
-def update(X, labels, C_prev):
-    """Centroids as member means (empty clusters keep C_prev) and counts."""
+def update(X, labels, C_prev, mode="canonical"):
+    """Centroids as member means (empty clusters keep C_prev) and counts.
+    mode="exact": the exact mean rounded once (FP32 / BF16 points)."""
     torch = _torch()
     L = load()
     _check_dev(X, "X")
@@ -315,7 +331,7 @@ def update(X, labels, C_prev):
     k = C_prev.shape[0]
     C = torch.empty_like(C_prev)
     cnt = torch.empty((k,), dtype=torch.int64, device=X.device)
-    o = _opts()
+    o = _opts(update=mode)
     rc = L.knor_update(X.data_ptr(), _dtype_code(X), n, d, labels.data_ptr(), k,
                        C_prev.data_ptr(), ctypes.byref(o), C.data_ptr(),
                        cnt.data_ptr())

@@ -220,6 +220,7 @@ struct Opts {
   int profile_mask = 0, profile_every = 1;
   int tile_blocks = 0, tile_resident = 0, autotune = 0;
   int learned = 0, train_iters = 5, train_batches = 16;
+  int update = 0;
 };
 
 static knor_status read_opts(const knor_opts* o, Opts* out) {
@@ -254,6 +255,8 @@ static knor_status read_opts(const knor_opts* o, Opts* out) {
   out->learned = o->learned;
   if (o->train_iters > 0) out->train_iters = o->train_iters;
   if (o->train_batches > 0) out->train_batches = o->train_batches;
+  if (o->update < 0 || o->update > 1) return KNOR_ERR_INVALID_ARG;
+  out->update = o->update;
   out->tile_blocks = o->tile_blocks;
   out->tile_resident = o->tile_resident;
   out->autotune = o->autotune;
@@ -502,6 +505,10 @@ static knor_status fit_impl(const void* X, knor_dtype dt, int64_t n, int d,
   ar.add((void**)&flagbuf, sizeof(int) * 8);   // conv, bad
   ar.add((void**)&rows_dev, sizeof(int64_t) * (size_t)k);
   ar.add(&upd_ws, update_workspace_bytes(n, k, d));
+  const bool exact = o.update == 1;
+  if (exact && dt == KNOR_F64) return KNOR_ERR_UNSUPPORTED;
+  void* exact_ws = nullptr;
+  if (exact) ar.add(&exact_ws, exact_workspace_bytes(n, k, d));
   ar.add((void**)&dist2, sizeof(double) * (size_t)n);
   ar.add((void**)&sumtmp, sizeof(double) * (size_t)(n / kLeaf + 2));
   ar.add((void**)&objective, sizeof(double));
@@ -547,6 +554,8 @@ static knor_status fit_impl(const void* X, knor_dtype dt, int64_t n, int d,
   knor_status rs = ar.alloc(s, o.cap);
   if (rs != KNOR_OK) return rs;
   update_plan_init(&plan, n, k, d, upd_ws);
+  ExactPlan xplan{};
+  if (exact) exact_plan_init(&xplan, n, k, d, exact_ws);
   int* conv = flagbuf;
   int* bad = flagbuf + 1;
   HIPCHK(update_plan_reset(plan, s));
@@ -581,6 +590,7 @@ static knor_status fit_impl(const void* X, knor_dtype dt, int64_t n, int d,
   HIPCHK(launch_prep_centroids(ops, s));
   HIPCHK(launch_fill_i32(labels_out, n, -1, s));   // every label changes at t = 0
   HIPCHK(launch_fill_i32(dirty, k, 1, s));         // every cluster is summed at t = 0
+  if (exact) HIPCHK(launch_fill_i32(xplan.prev, n, -1, s));
   if (learned) {
     HIPCHK(launch_standardize_stats(X, dt, n, d, mean, istd, s));
     std::vector<float> th0 = mlp_init_host(d, hM, k, o.seed);
@@ -688,8 +698,12 @@ static knor_status fit_impl(const void* X, knor_dtype dt, int64_t n, int d,
     IterCtl ctl;
     ctl.row = row; ctl.conv = conv; ctl.iter = t; ctl.tol_n = tol_n;
     ctl.segmented = seg; ctl.n = n;
-    HIPCHK(launch_update(plan, X, dt, labels_out, C_out, C_out, nullptr, &ops,
-                         mti ? drift : nullptr, dirty, &ctl, s, pp));
+    if (exact)
+      HIPCHK(launch_update_exact(plan, xplan, X, dt, labels_out, C_out, C_out, nullptr, &ops,
+                                 mti ? drift : nullptr, dirty, &ctl, s, pp));
+    else
+      HIPCHK(launch_update(plan, X, dt, labels_out, C_out, C_out, nullptr, &ops,
+                           mti ? drift : nullptr, dirty, &ctl, s, pp));
     if (mti) {
       prof.begin(KNOR_PROF_CC);
       HIPCHK(launch_cc_bounds(ops, s_half, conv, t, s));
@@ -870,6 +884,7 @@ knor_status knor_fit(const void* X, knor_dtype dt, int64_t n, int32_t d,
   } else if (init != KNOR_INIT_FORGY) {
     return KNOR_ERR_INVALID_ARG;
   }
+  if (o.update == 1 && dt == KNOR_F64) return KNOR_ERR_UNSUPPORTED;
   if (o.autotune && dt == KNOR_F32 && !o.tile_blocks && !o.tile_resident) {
     int pb, res;
     if (!tune_lookup(pad_dim(d), (k + 15) / 16 * 16, &pb, &res))
@@ -904,6 +919,9 @@ knor_status knor_fit_batched(const knor_problem* probs, int32_t count,
         !(p.tol >= 0.0 && p.tol < 1.0))
       return KNOR_ERR_INVALID_ARG;
   }
+  if (o.update == 1)
+    for (int i = 0; i < count; ++i)
+      if (probs[i].dt == KNOR_F64) return KNOR_ERR_UNSUPPORTED;
   if (count == 0) return KNOR_OK;
   int dev = 0;
   HIPCHK(hipGetDevice(&dev));
@@ -1028,6 +1046,7 @@ knor_status knor_update(const void* X, knor_dtype dt, int64_t n, int32_t d,
     return KNOR_ERR_INVALID_ARG;
   if (n < 0 || n >= (int64_t)1 << 31 || d < 1 || d > kMaxD || k < 1 || k > kMaxK)
     return KNOR_ERR_INVALID_ARG;
+  if (o.update == 1 && dt == KNOR_F64) return KNOR_ERR_UNSUPPORTED;
   hipStream_t s = o.stream;
   if (n == 0) {
     if (C_out != C_prev)
@@ -1037,9 +1056,12 @@ knor_status knor_update(const void* X, knor_dtype dt, int64_t n, int32_t d,
     return KNOR_OK;
   }
   void* ws = nullptr;
+  void* xws = nullptr;
   int* conv = nullptr;
+  const bool exact = o.update == 1;
   Arena ar;
   ar.add(&ws, update_workspace_bytes(n, k, d));
+  if (exact) ar.add(&xws, exact_workspace_bytes(n, k, d));
   ar.add((void**)&conv, sizeof(int) * 4);
   if (knor_status r = ar.alloc(s, o.cap)) return r;
   UpdatePlan plan{};
@@ -1048,8 +1070,15 @@ knor_status knor_update(const void* X, knor_dtype dt, int64_t n, int32_t d,
   HIPCHK(launch_fill_i32(conv, 1, kNotConverged, s));
   IterCtl ctl;
   ctl.conv = conv;
-  HIPCHK(launch_update(plan, X, dt, labels, C_prev, C_out, counts_out, nullptr,
-                       nullptr, nullptr, &ctl, s));
+  if (exact) {
+    ExactPlan xplan{};
+    exact_plan_init(&xplan, n, k, d, xws);
+    HIPCHK(launch_update_exact(plan, xplan, X, dt, labels, C_prev, C_out, counts_out, nullptr,
+                               nullptr, nullptr, &ctl, s));
+  } else {
+    HIPCHK(launch_update(plan, X, dt, labels, C_prev, C_out, counts_out, nullptr,
+                         nullptr, nullptr, &ctl, s));
+  }
   return KNOR_OK;
 }
 

@@ -374,6 +374,34 @@ hipError_t launch_update(const UpdatePlan& p, const void* X, knor_dtype dt,
                          const IterCtl* ctl /* may be null */, hipStream_t s,
                          Prof* prof = nullptr);
 
+// Pass 1 of the update alone: the stable counting sort (perm, nj, off,
+// leaf_off), skipped when *conv < iter.
+hipError_t launch_sort(const UpdatePlan& p, const int32_t* labels, int* dirty,
+                       const int* conv, int iter, hipStream_t s);
+
+// Exact update (FP32 and BF16 points): per (cluster, dimension) kXD signed
+// 64-bit digits of weight 2^(32 s - 149); centroids are the exact member
+// means rounded once.  Inside a fit (ctl->row set, dirty required) only the
+// points whose label changed move between clusters when few do; outside a
+// fit (ctl->row null, dirty null) every cluster is summed from scratch.
+constexpr int kXD = 10;
+struct ExactPlan {
+  int64_t n;
+  int k, d;
+  unsigned long long* slots;   // k x kXD x d digits
+  int32_t* prev;               // n: labels at the last update (-1 at start)
+  int* gate;                   // this iteration's mode (kNotConverged: full)
+  int delta_max;               // most changed labels moved one by one
+};
+size_t exact_workspace_bytes(int64_t n, int k, int d);
+void exact_plan_init(ExactPlan* p, int64_t n, int k, int d, void* ws);
+hipError_t launch_update_exact(const UpdatePlan& p, const ExactPlan& xp, const void* X,
+                               knor_dtype dt, const int32_t* labels, const double* C_prev,
+                               double* C_out, int64_t* counts_out,
+                               CentroidOps* ops /* may be null */,
+                               float* drift /* may be null */, int* dirty,
+                               const IterCtl* ctl, hipStream_t s, Prof* prof = nullptr);
+
 // MTI.
 hipError_t launch_cc_bounds(const CentroidOps& ops, float* s_half,
                             const int* conv, int iter, hipStream_t s);

@@ -1,0 +1,410 @@
+// Exact centroid update: each centroid is the exact mean of its members'
+// values, rounded once to the nearest double (ties to even).  This takes the
+// member mean of Phase II (Section "Parallel Lloyd's Algorithm") as an exact
+// quantity: no summation order can change it, so sums may be kept across
+// iterations and moved point by point, the "running totals" of the paper's
+// merge and its no-I/O-for-pruned-rows idea (Section "Minimal Triangle
+// Inequality (MTI) Pruning", semi-external memory).
+//
+// Representation.  Every FP32 or BF16 value is m 2^(sh - 149) with m < 2^24
+// and 0 <= sh <= 253, an integer in units of 2^-149 below 2^277.  The sum of
+// a cluster's values in one dimension is kept as kXD signed 64-bit digits of
+// weight 2^(32 s) in those units (carry-save: a digit may leave [0, 2^32)
+// between normalisations).  A value adds (m << (sh mod 32)) split into its
+// low and high 32 bits to digits sh/32 and sh/32 + 1, with the value's sign.
+// One normalisation per update keeps every digit below (n + 1) 2^32 in
+// magnitude, inside int64 for n < 2^31.
+//
+// Per iteration of a fit (labels of the previous update in `prev`):
+//   exact_delta    counts this iteration's changed labels and chooses the
+//                  mode in a gate word.  Delta mode (few changes): for each
+//                  changed point, its value leaves the old cluster's digits
+//                  and enters the new one's (64-bit atomic adds, order-free)
+//                  and the member counts move by one.  Full mode: the digits
+//                  of every dirty cluster are cleared.
+//   sort           the canonical counting sort (full mode only, via the gate)
+//   exact_leaf     full mode: a wave walks a run of leaves (64 members of one
+//                  cluster each), sums each dimension's digits in LDS and
+//                  adds them to the cluster's digits when the cluster ends
+//   exact_finalize every dirty cluster: normalise the digits, divide by the
+//                  member count with one rounding, write the centroid and
+//                  its derived operands; close the iteration.
+#include <math.h>
+
+#include "common.h"
+#include "update_common.h"
+
+namespace knor {
+
+constexpr int kExactRun = 8;          // leaves per wave in the full pass
+constexpr int kExactWaves = 4;
+constexpr int kDeltaAtomics = 1 << 19; // delta mode up to this many digit adds
+
+size_t exact_workspace_bytes(int64_t n, int k, int d) {
+  const size_t a = ((size_t)k * kXD * d * sizeof(unsigned long long) + 255) & ~(size_t)255;
+  const size_t b = ((size_t)n * sizeof(int32_t) + 255) & ~(size_t)255;
+  return a + b + 256;
+}
+
+void exact_plan_init(ExactPlan* p, int64_t n, int k, int d, void* ws) {
+  char* c = (char*)ws;
+  p->n = n;
+  p->k = k;
+  p->d = d;
+  p->slots = (unsigned long long*)c;
+  c += ((size_t)k * kXD * d * sizeof(unsigned long long) + 255) & ~(size_t)255;
+  p->prev = (int32_t*)c;
+  c += ((size_t)n * sizeof(int32_t) + 255) & ~(size_t)255;
+  p->gate = (int*)c;
+  int dm = kDeltaAtomics / (4 * d);
+  p->delta_max = dm < 256 ? 256 : dm;
+}
+
+template <typename T>
+__device__ __forceinline__ uint32_t f32_bits(T v);
+template <>
+__device__ __forceinline__ uint32_t f32_bits<float>(float v) { return __float_as_uint(v); }
+template <>
+__device__ __forceinline__ uint32_t f32_bits<uint16_t>(uint16_t v) { return (uint32_t)v << 16; }
+
+// The value with FP32 bit pattern u as digit adds: lo to digit idx, hi to
+// digit idx + 1, both with the value's sign (two's complement in 64 bits).
+struct FixedAdd {
+  int idx;
+  unsigned long long lo, hi;
+};
+__device__ __forceinline__ FixedAdd fixed_of(uint32_t u) {
+  const uint32_t ef = (u >> 23) & 255u;
+  const uint32_t m = (u & 0x7fffffu) | (ef ? 0x800000u : 0u);
+  const int sh = ef ? (int)ef - 1 : 0;
+  const unsigned long long v = (unsigned long long)m << (sh & 31);
+  FixedAdd f;
+  f.idx = sh >> 5;
+  const unsigned long long lo = v & 0xffffffffull, hi = v >> 32;
+  const bool neg = (u >> 31) != 0;
+  f.lo = neg ? 0ull - lo : lo;
+  f.hi = neg ? 0ull - hi : hi;
+  return f;
+}
+
+// ---------------------------------------------------------------------------
+// mode choice, delta moves, prev labels
+// ---------------------------------------------------------------------------
+
+template <typename T>
+__global__ __launch_bounds__(256) void exact_delta(
+    const T* __restrict__ X, int64_t n, int d, const int32_t* __restrict__ labels,
+    int32_t* __restrict__ prev, int k, unsigned long long* __restrict__ slots,
+    int* __restrict__ nj, const int* __restrict__ dirty,
+    const unsigned long long* __restrict__ row, int* __restrict__ gate,
+    int delta_max, const int* __restrict__ conv, int iter) {
+  const int cv = *conv;
+  const int lane = threadIdx.x & 63;
+  // this iteration's changed labels, from the spread counter slots
+  unsigned long long c =
+      lane < kChgSlots ? row[(SLOT_CHANGED * kChgSlots + lane) * kSlotStride] : 0ull;
+  for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o);
+  const bool full = iter == 0 || c > (unsigned long long)delta_max;
+  if (blockIdx.x == 0 && threadIdx.x == 0)
+    *gate = cv < iter ? cv : (full ? kNotConverged : -1);
+  if (cv < iter) return;
+  const int64_t nthreads = (int64_t)gridDim.x * blockDim.x;
+  const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (full) {
+    const int64_t ns = (int64_t)k * kXD * d;
+    for (int64_t e = tid; e < ns; e += nthreads)
+      if (dirty[e / ((int64_t)kXD * d)]) slots[e] = 0ull;
+    for (int64_t p = tid; p < n; p += nthreads) {
+      const int32_t a = labels[p];
+      if (prev[p] != a) prev[p] = a;
+    }
+    return;
+  }
+  // delta: the wave takes 64 consecutive points at a time; each changed
+  // point is moved by the whole wave, one dimension per lane
+  const int64_t wave0 = tid - lane;
+  for (int64_t b = wave0; b < n; b += nthreads) {
+    const int64_t p = b + lane;
+    const int32_t a = p < n ? labels[p] : 0;
+    const int32_t o = p < n ? prev[p] : 0;
+    uint64_t mask = __ballot(p < n && a != o);
+    if (p < n && a != o) prev[p] = a;
+    while (mask) {
+      const int l = __builtin_ctzll(mask);
+      mask &= mask - 1;
+      const int64_t q = b + l;
+      const int32_t na = __shfl(a, l), oa = __shfl(o, l);
+      if (lane == 0) {
+        atomicAdd(&nj[na], 1);
+        if (oa >= 0) atomicSub(&nj[oa], 1);
+      }
+      for (int dim = lane; dim < d; dim += 64) {
+        const FixedAdd f = fixed_of(f32_bits<T>(X[(size_t)q * d + dim]));
+        unsigned long long* sn = slots + ((size_t)na * kXD + f.idx) * d + dim;
+        if (f.lo) atomicAdd(sn, f.lo);
+        if (f.hi) atomicAdd(sn + d, f.hi);
+        if (oa >= 0) {
+          unsigned long long* so = slots + ((size_t)oa * kXD + f.idx) * d + dim;
+          if (f.lo) atomicAdd(so, 0ull - f.lo);
+          if (f.hi) atomicAdd(so + d, 0ull - f.hi);
+        }
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// full pass: runs of leaves
+// ---------------------------------------------------------------------------
+
+// Wave w of block b walks leaves [g0, g0 + kExactRun) of the canonical leaf
+// list (consecutive leaves, cluster by cluster), skipping clean clusters.
+// For d <= 32 lane (r, i) = (lane / 32, lane mod 32) takes dimension i of
+// every second member starting at r; otherwise lane i takes dimension
+// c0 + i for each chunk c0 of 64.  Each lane owns one column of kXD digits
+// in LDS; when the run leaves a cluster (and at the end) the columns are
+// added to the cluster's digits in memory.
+template <typename T>
+__global__ __launch_bounds__(64 * kExactWaves) void exact_leaf(
+    const T* __restrict__ X, int d, const int* __restrict__ perm,
+    const int* __restrict__ nj, const int* __restrict__ off,
+    const int* __restrict__ leaf_off, int k, const int* __restrict__ dirty,
+    unsigned long long* __restrict__ slots, const int* __restrict__ gate, int iter) {
+  __shared__ long long acc[kExactWaves][kXD * 64];
+  if (*gate < iter) return;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int total = leaf_off[k];
+  const int g0 = (blockIdx.x * kExactWaves + wave) * kExactRun;
+  if (g0 >= total) return;                     // per wave; no block barrier below
+  const int g1 = g0 + kExactRun < total ? g0 + kExactRun : total;
+  long long* A = acc[wave];
+  const bool two = d <= 32;
+  const int r = two ? lane >> 5 : 0;           // member offset of this lane
+  const int step = two ? 2 : 1;
+  const int j0 = cluster_of_leaf(leaf_off, k, g0);
+  for (int c0 = 0; c0 < d; c0 += 64) {
+    const int dim = c0 + (two ? (lane & 31) : lane);
+    const bool on = dim < d;
+#pragma unroll
+    for (int s = 0; s < kXD; ++s) A[s * 64 + lane] = 0;
+    auto flush = [&](int jc) {
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+      for (int s = 0; s < kXD; ++s) {
+        long long v = A[s * 64 + lane];
+        if (two) v += A[s * 64 + (lane ^ 32)];
+        if (on && (!two || lane < 32) && v != 0)
+          atomicAdd(&slots[((size_t)jc * kXD + s) * d + dim], (unsigned long long)v);
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+      for (int s = 0; s < kXD; ++s) A[s * 64 + lane] = 0;
+    };
+    int j = j0, cur = -1;
+    for (int g = g0; g < g1; ++g) {
+      while (leaf_off[j + 1] <= g) ++j;        // uniform over the wave
+      if (dirty && !dirty[j]) continue;
+      if (j != cur) {
+        if (cur >= 0) flush(cur);
+        cur = j;
+      }
+      const int L = g - leaf_off[j];
+      const int m0 = off[j] + L * kLeaf;
+      int cnt = nj[j] - L * kLeaf;
+      if (cnt > kLeaf) cnt = kLeaf;
+      const int pl = lane < cnt ? perm[m0 + lane] : 0;
+      for (int m = 0; m < cnt; m += 8 * step) {
+        uint32_t u[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          const int mm = m + q * step + r;
+          const int pq = __shfl(pl, mm & 63);
+          u[q] = (on && mm < cnt) ? f32_bits<T>(X[(size_t)pq * d + dim]) : 0u;
+        }
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          if ((u[q] << 1) == 0u) continue;     // +-0 adds nothing
+          const FixedAdd f = fixed_of(u[q]);
+          A[f.idx * 64 + lane] += (long long)f.lo;
+          A[(f.idx + 1) * 64 + lane] += (long long)f.hi;
+        }
+      }
+    }
+    if (cur >= 0) flush(cur);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// finalize
+// ---------------------------------------------------------------------------
+
+// Normalise the kXD digits at p (stride d) in place: digits 0..kXD-2 in
+// [0, 2^32), the top digit signed.  Returns the top digit.
+__device__ __forceinline__ void normalise_digits(unsigned long long* p, int d,
+                                                 uint32_t* dig, long long& top) {
+  long long carry = 0;
+#pragma unroll
+  for (int s = 0; s < kXD - 1; ++s) {
+    const long long v = (long long)p[(size_t)s * d] + carry;
+    dig[s] = (uint32_t)((unsigned long long)v & 0xffffffffull);
+    carry = v >> 32;                            // arithmetic shift: floor
+  }
+  top = (long long)p[(size_t)(kXD - 1) * d] + carry;
+#pragma unroll
+  for (int s = 0; s < kXD - 1; ++s) p[(size_t)s * d] = dig[s];
+  p[(size_t)(kXD - 1) * d] = (unsigned long long)top;
+}
+
+// RN(V / cnt) for V = sum_s dig[s] 2^(32 s - 149) + top 2^(32 (kXD-1) - 149),
+// cnt >= 1: the magnitude's long division by cnt with three 32-bit guard
+// digits, then 53 bits, a round bit and a sticky bit (remainder included).
+// Every mean of FP32 values lies in [2^-180, 2^128]: a normal double.
+__device__ __forceinline__ double exact_quotient(const uint32_t* dig, long long top,
+                                                 int cnt) {
+  constexpr int G = 3;                          // guard digits
+  constexpr int W = kXD + G;
+  uint32_t a[W];
+  const bool neg = top < 0;
+  // magnitude digits (two's complement negation when negative)
+#pragma unroll
+  for (int s = 0; s < G; ++s) a[s] = 0u;
+  unsigned long long borrow = neg ? 1ull : 0ull;   // ~x + 1
+#pragma unroll
+  for (int s = 0; s < kXD - 1; ++s) {
+    const unsigned long long v = (unsigned long long)(neg ? ~dig[s] : dig[s]) + borrow;
+    a[G + s] = (uint32_t)v;
+    borrow = v >> 32;
+  }
+  const unsigned long long tmag = neg ? (unsigned long long)(~top) + borrow
+                                      : (unsigned long long)top;
+  a[W - 1] = (uint32_t)tmag;                    // |V| < 2^308: the top fits
+  // long division, most significant digit first
+  const unsigned long long n = (unsigned long long)cnt;
+  unsigned long long rem = 0;
+  uint32_t q[W];
+#pragma unroll
+  for (int s = W - 1; s >= 0; --s) {
+    const unsigned long long cur = (rem << 32) | a[s];
+    q[s] = (uint32_t)(cur / n);
+    rem = cur - (unsigned long long)q[s] * n;
+  }
+  int t = W - 1;
+  while (t > 0 && q[t] == 0u) --t;
+  if (q[t] == 0u) return 0.0;                   // V == 0
+  // t >= 2 whenever V != 0: |V| 2^96 / cnt >= 2^65
+  const int lz = __clz((int)q[t]);
+  const unsigned long long hi64 = ((unsigned long long)q[t] << 32) | q[t - 1];
+  const uint32_t lo32 = q[t - 2];
+  const unsigned long long w = lz ? (hi64 << lz) | ((unsigned long long)lo32 >> (32 - lz)) : hi64;
+  unsigned long long mant = w >> 11;            // 53 bits, leading one at bit 52
+  const unsigned long long rbit = (w >> 10) & 1ull;
+  bool sticky = (w & 0x3ffull) != 0ull || rem != 0ull ||
+                (lz ? (uint32_t)(lo32 << lz) != 0u : lo32 != 0u);
+  for (int s = t - 3; s >= 0 && !sticky; --s) sticky = q[s] != 0u;
+  if (rbit && (sticky || (mant & 1ull))) mant += 1ull;
+  // the leading one sits at bit b = 32 t + 31 - lz of q, in units of
+  // 2^-(149 + 32 G); mant's last bit has weight 2^(b - 52)
+  const int b = 32 * t + 31 - lz;
+  const double r = ldexp((double)mant, b - 52 - 149 - 32 * G);
+  return neg ? -r : r;
+}
+
+__global__ __launch_bounds__(256) void exact_finalize(
+    unsigned long long* __restrict__ slots, const int* __restrict__ nj, int k, int d,
+    const double* C_prev, double* C_out, int64_t* __restrict__ counts_out,
+    float* __restrict__ Cm2, float* __restrict__ cn, double* __restrict__ CT, int dp,
+    uint16_t* __restrict__ Chi, uint16_t* __restrict__ Clo, int dpb,
+    float* __restrict__ drift, int* __restrict__ dirty, IterCtl ctl,
+    const int* __restrict__ conv, int iter) {
+  const int cv = *conv;
+  const int j = blockIdx.x;
+  const int cntj = nj[j];
+  const int dj = dirty ? dirty[j] : 1;
+  if (cv < iter) return;
+  if (j == 0 && ctl.row) close_iteration(ctl, iter);
+  if (counts_out && threadIdx.x == 0) counts_out[j] = cntj;
+  if (!dj) {
+    if (drift && threadIdx.x == 0) drift[j] = 0.0f;     // centroid unchanged
+    return;
+  }
+  unsigned long long* base = slots + (size_t)j * kXD * d;
+  if (cntj == 0)      // no members: keep the digits of the value 0 normalised
+    for (int dim = threadIdx.x; dim < d; dim += blockDim.x) {
+      uint32_t dig[kXD - 1];
+      long long top;
+      normalise_digits(base + dim, d, dig, top);
+    }
+  write_centroid(
+      j, k, d, cntj,
+      [&](int dim) {
+        uint32_t dig[kXD - 1];
+        long long top;
+        normalise_digits(base + dim, d, dig, top);
+        return exact_quotient(dig, top, cntj);
+      },
+      C_prev, C_out, CT, Cm2, cn, dp, Chi, Clo, dpb, drift, dirty);
+}
+
+// ---------------------------------------------------------------------------
+// launch
+// ---------------------------------------------------------------------------
+
+hipError_t launch_update_exact(const UpdatePlan& p, const ExactPlan& xp, const void* X,
+                               knor_dtype dt, const int32_t* labels, const double* C_prev,
+                               double* C_out, int64_t* counts_out, CentroidOps* ops,
+                               float* drift, int* dirty, const IterCtl* ctl, hipStream_t s,
+                               Prof* prof) {
+  if (dt != KNOR_F32 && dt != KNOR_BF16) return hipErrorInvalidValue;
+  const int k = p.k, d = p.d;
+  const int* conv = ctl->conv;
+  const int iter = ctl->iter;
+  // one update outside a fit (no counter row): every cluster from scratch
+  const bool one_shot = ctl->row == nullptr;
+  const int* gate = conv;
+  if (prof) prof->begin(KNOR_PROF_SORT);
+  if (one_shot) {
+    if (dirty) return hipErrorInvalidValue;
+    hipError_t e = launch_fill_i32((int32_t*)xp.slots, (int64_t)k * kXD * d * 2, 0, s);
+    if (e != hipSuccess) return e;
+  } else {
+    if (!dirty) return hipErrorInvalidValue;
+    int64_t blocks = (p.n + 255) / 256;
+    if (blocks > 2048) blocks = 2048;
+    if (blocks < 1) blocks = 1;
+    if (dt == KNOR_F32)
+      hipLaunchKernelGGL(exact_delta<float>, dim3((unsigned)blocks), dim3(256), 0, s,
+                         (const float*)X, p.n, d, labels, xp.prev, k, xp.slots, p.nj, dirty,
+                         ctl->row, xp.gate, xp.delta_max, conv, iter);
+    else
+      hipLaunchKernelGGL(exact_delta<uint16_t>, dim3((unsigned)blocks), dim3(256), 0, s,
+                         (const uint16_t*)X, p.n, d, labels, xp.prev, k, xp.slots, p.nj, dirty,
+                         ctl->row, xp.gate, xp.delta_max, conv, iter);
+    gate = xp.gate;
+  }
+  if (hipError_t e = launch_sort(p, labels, dirty, gate, iter, s)) return e;
+  if (prof) { prof->end(); prof->begin(KNOR_PROF_LEAF); }
+  const int64_t waves = (p.max_leaves + kExactRun - 1) / kExactRun;
+  const int64_t lblocks = (waves + kExactWaves - 1) / kExactWaves;
+  if (dt == KNOR_F32)
+    hipLaunchKernelGGL(exact_leaf<float>, dim3((unsigned)lblocks), dim3(64 * kExactWaves), 0, s,
+                       (const float*)X, d, p.perm, p.nj, p.off, p.leaf_off, k, dirty, xp.slots,
+                       gate, iter);
+  else
+    hipLaunchKernelGGL(exact_leaf<uint16_t>, dim3((unsigned)lblocks), dim3(64 * kExactWaves), 0,
+                       s, (const uint16_t*)X, d, p.perm, p.nj, p.off, p.leaf_off, k, dirty,
+                       xp.slots, gate, iter);
+  if (prof) { prof->end(); prof->begin(KNOR_PROF_TREE); }
+  hipLaunchKernelGGL(exact_finalize, dim3(k), dim3(256), 0, s, xp.slots, p.nj, k, d, C_prev,
+                     C_out, counts_out, ops ? ops->Cm2 : nullptr, ops ? ops->cn : nullptr,
+                     ops ? ops->CT : nullptr, ops ? ops->dp : 0, ops ? ops->Chi : nullptr,
+                     ops ? ops->Clo : nullptr, ops ? ops->dpb : 0, drift, dirty, *ctl, conv,
+                     iter);
+  if (prof) prof->end();
+  return hipGetLastError();
+}
+
+}  // namespace knor

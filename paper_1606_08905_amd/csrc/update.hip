@@ -26,6 +26,7 @@
 #include <math.h>
 
 #include "common.h"
+#include "update_common.h"
 
 namespace knor {
 
@@ -547,15 +548,6 @@ __global__ __launch_bounds__(64) void scatter_kernel(
 // pass 2: leaf sums, tree, finalize
 // ---------------------------------------------------------------------------
 
-__device__ __forceinline__ int cluster_of_leaf(const int* leaf_off, int k, int g) {
-  int lo = 0, hi = k - 1;      // largest j with leaf_off[j] <= g
-  while (lo < hi) {
-    int mid = (lo + hi + 1) >> 1;
-    if (leaf_off[mid] <= g) lo = mid; else hi = mid - 1;
-  }
-  return lo;
-}
-
 // One wave per leaf.  Lane m loads member m's row (a chunk of DC dimensions
 // at a time) into the wave's LDS tile, then lane i sums dimension i over the
 // members in order (left to right, starting from the first member).  For
@@ -713,8 +705,6 @@ __global__ __launch_bounds__(256) void tree_finalize(
     uint16_t* __restrict__ Chi, uint16_t* __restrict__ Clo, int dpb,
     float* __restrict__ drift, int* __restrict__ dirty, int TB, IterCtl ctl,
     const int* __restrict__ conv, int iter) {
-  __shared__ double red[256];
-  __shared__ double cval[kMaxD];
   __shared__ double tree[kTreeLdsDoubles];
   const int cv = *conv;
   const int j = blockIdx.x;
@@ -723,36 +713,7 @@ __global__ __launch_bounds__(256) void tree_finalize(
   const int lo0 = leaf_off[j], lo1 = leaf_off[j + 1];
   if (cv < iter) return;
 
-  if (j == 0 && ctl.row) {
-    // fold the spread slots: thread (q, i) loads slot i of quantity q
-    __shared__ unsigned long long slot[NSLOTQ * kChgSlots];
-    unsigned long long* row = ctl.row;
-    if (threadIdx.x < NSLOTQ * kChgSlots) slot[threadIdx.x] = row[threadIdx.x * kSlotStride];
-    __syncthreads();
-    if (threadIdx.x == 0) {
-    unsigned long long tot[NSLOTQ];
-    for (int q = 0; q < NSLOTQ; ++q) {
-      unsigned long long s = 0;
-      for (int i = 0; i < kChgSlots; ++i) s += slot[q * kChgSlots + i];
-      tot[q] = s;
-    }
-    row[ROW_CHANGED] = tot[SLOT_CHANGED];
-    row[ROW_FLAG_HEAD] = tot[SLOT_FLAGGED];
-    row[ROW_CERTIFIED] = tot[SLOT_CERTIFIED];
-    if (ctl.segmented) {
-      row[ROW_SURVIVED] = tot[SLOT_SURV];
-      row[ROW_SCANNED] = tot[SLOT_SURV] - tot[SLOT_CERTIFIED];
-      row[ROW_PRUNED_A] = (unsigned long long)ctl.n - tot[SLOT_CAND];
-      row[ROW_PRUNED_B] = tot[SLOT_CAND] - tot[SLOT_SURV];
-      // keep tightening while it prunes at least 1/16 of its candidates
-      row[ROW_TIGHTEN_NEXT] =
-          row[ROW_TIGHTEN] && 16 * (tot[SLOT_CAND] - tot[SLOT_SURV]) >= tot[SLOT_CAND];
-    } else {
-      row[ROW_SCANNED] = (unsigned long long)ctl.n;
-    }
-    if ((double)tot[SLOT_CHANGED] <= ctl.tol_n) *ctl.conv = iter;
-    }
-  }
+  if (j == 0 && ctl.row) close_iteration(ctl, iter);
 
   if (counts_out && threadIdx.x == 0) counts_out[j] = cntj;
   if (!dj) {
@@ -784,56 +745,15 @@ __global__ __launch_bounds__(256) void tree_finalize(
     }
     __syncthreads();
   }
-  double diff2 = 0.0;
-  for (int dim = threadIdx.x; dim < d; dim += blockDim.x) {
-    double old = C_prev[(size_t)j * d + dim];
-    double c = cntj > 0 ? __ddiv_rn(node[dim], (double)cntj) : old;
-    C_out[(size_t)j * d + dim] = c;
-    if (CT) CT[(size_t)dim * k + j] = c;
-    cval[dim] = c;
-    double t = __dsub_rn(c, old);
-    diff2 = __dadd_rn(diff2, __dmul_rn(t, t));
-  }
-  red[threadIdx.x] = diff2;
-  __syncthreads();
-  for (int s = 128; s > 0; s >>= 1) {
-    if (threadIdx.x < s) red[threadIdx.x] = __dadd_rn(red[threadIdx.x], red[threadIdx.x + s]);
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) {
-    if (drift)
-      drift[j] = f32_up(sqrt(red[0]) * (1.0 + (double)(d + 8) * 2.220446049250313e-16));
-    if (cn) {
-      double ss = 0.0;
-      for (int dim = 0; dim < d; ++dim) ss = __dadd_rn(ss, __dmul_rn(cval[dim], cval[dim]));
-      cn[j] = (float)ss;
-    }
-    if (dirty) dirty[j] = 0;
-  }
-  if (Cm2)
-    for (int dim = threadIdx.x; dim < dp; dim += blockDim.x)
-      Cm2[(size_t)j * dp + dim] = dim < d ? -2.0f * (float)cval[dim] : 0.0f;
-  if (Chi)
-    for (int dim = threadIdx.x; dim < dpb; dim += blockDim.x) {
-      uint16_t h, l;
-      bf16_split_m2(dim < d ? cval[dim] : 0.0, h, l);
-      Chi[(size_t)j * dpb + dim] = h;
-      Clo[(size_t)j * dpb + dim] = l;
-    }
+  write_centroid(j, k, d, cntj, [&](int dim) { return __ddiv_rn(node[dim], (double)cntj); },
+                 C_prev, C_out, CT, Cm2, cn, dp, Chi, Clo, dpb, drift, dirty);
 }
 
-hipError_t launch_update(const UpdatePlan& p, const void* X, knor_dtype dt,
-                         const int32_t* labels, const double* C_prev,
-                         double* C_out, int64_t* counts_out, CentroidOps* ops,
-                         float* drift, int* dirty, const IterCtl* ctl,
-                         hipStream_t s, Prof* prof) {
-  // ctl->conv must point at device memory (max int when no fit is running)
-  const int k = p.k, d = p.d;
-  const int* conv = ctl->conv;
-  const int iter = ctl->iter;
+hipError_t launch_sort(const UpdatePlan& p, const int32_t* labels, int* dirty,
+                       const int* conv, int iter, hipStream_t s) {
+  const int k = p.k;
   int bits = 0;
   while ((1 << bits) < k) ++bits;
-  if (prof) prof->begin(KNOR_PROF_SORT);
   if (fused_sort(k)) {
     const size_t lds = sizeof(int) * (size_t)kFusedWaves * k;
     hipLaunchKernelGGL(hist_fused, dim3(p.nb), dim3(1024), lds, s, labels, p.n,
@@ -861,6 +781,20 @@ hipError_t launch_update(const UpdatePlan& p, const void* X, knor_dtype dt,
                        p.n, k, p.B, bits, p.seglen, p.blockcnt, p.segsum, p.off,
                        dirty, p.perm, conv, iter);
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_update(const UpdatePlan& p, const void* X, knor_dtype dt,
+                         const int32_t* labels, const double* C_prev,
+                         double* C_out, int64_t* counts_out, CentroidOps* ops,
+                         float* drift, int* dirty, const IterCtl* ctl,
+                         hipStream_t s, Prof* prof) {
+  // ctl->conv must point at device memory (max int when no fit is running)
+  const int k = p.k, d = p.d;
+  const int* conv = ctl->conv;
+  const int iter = ctl->iter;
+  if (prof) prof->begin(KNOR_PROF_SORT);
+  if (hipError_t e = launch_sort(p, labels, dirty, conv, iter, s)) return e;
   if (prof) { prof->end(); prof->begin(KNOR_PROF_LEAF); }
   const int64_t lblocks = (p.max_leaves + kLeafWaves - 1) / kLeafWaves;
   const size_t esz = dt == KNOR_F64 ? 8 : (dt == KNOR_F32 ? 4 : 2);
