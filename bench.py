@@ -77,7 +77,7 @@ def parse():
     ap.add_argument("--cpu-iters", type=int, default=0,
                     help="oracle iterations for the CPU baseline (0 = whole fit)")
     ap.add_argument("--form", default="headline",
-                    choices=["headline", "mixed", "batched", "learned"],
+                    choices=["headline", "mixed", "batched", "learned", "incremental"],
                     help="headline: the benchmark workload (default); the "
                          "others measure one extended form on its own "
                          "workload against plain FP32 Lloyd's on this GPU")
@@ -247,6 +247,61 @@ def run_form(a):
                                          w.C0, h[0].cpu().numpy(), 0.02 if cfg == 5 else 0.05)
             out["cpu_baseline"] = cb
             out["cpu_sample_labels_exact"] = ok
+    elif a.form == "incremental":
+        w = workloads.config(2)
+        print(f"# data n={w.n} d={w.d} k={w.k} generated in "
+              f"{time.perf_counter() - t_gen:.1f}s", file=sys.stderr, flush=True)
+        X = torch.from_numpy(w.X).cuda()
+        C0 = torch.from_numpy(w.C0).cuda()
+
+        def fit(update, **kw):
+            return knor.fit(X, w.k, C0=C0, max_iters=w.max_iters, tol=w.tol, prune=True,
+                            counters=True, update=update, **kw)
+
+        (C, lab, st), dt = timed(lambda: fit("exact"))
+        (Cc, labc, stc), dtc = timed(lambda: fit("canonical"))
+        groups = {}
+        for upd in ("exact", "canonical"):
+            ms = np.zeros(knor.NPROF)
+            la = np.zeros(knor.NPROF, np.int64)
+            fit(upd, profile=(ms, la))
+            groups[upd] = (ms, la)
+        ms, la = groups["exact"]
+        g = int(np.argmax(ms))
+        upd_groups = [knor.PROF_GROUPS.index(nm) for nm in ("sort", "leaf", "tree")]
+        out.update({
+            "metric": "Lloyd iters/s at exact assignments, exact-mean incremental update",
+            "value": round(st["iters"] / dt, 3), "unit": "iters/s",
+            "ms_per_step": round(dt * 1e3, 3), "dtype": "f32",
+            "config": {"workload": "gaussian-mixture n=1e6 d=32 k=100 f32 MTI k-means++ "
+                                   "max_iters=100 tol=0, update=exact (changed points moved "
+                                   "one by one when few change)",
+                       "n": w.n, "d": w.d, "k": w.k, "iters_per_fit": st["iters"]},
+            "baseline_canonical_update": {"value": round(stc["iters"] / dtc, 3),
+                                          "unit": "iters/s", "iters_per_fit": stc["iters"]},
+            "speedup_vs_canonical_update": round((st["iters"] / dt) / (stc["iters"] / dtc), 3),
+            "update_ms_per_fit": {u: round(float(sum(groups[u][0][i] for i in upd_groups)), 3)
+                                  for u in groups},
+            "roofline": roofline_of(knor, ms, la, g, 1,
+                                    group_work(g, w.n, w.d, w.k, 4, st["counters"],
+                                               st["iters"]) if g in (0, 1, 2, 3) else None),
+            "kernels": {nm: {"ms_per_fit": round(float(ms[i]), 3), "launches": int(la[i])}
+                        for i, nm in enumerate(knor.PROF_GROUPS) if la[i]},
+        })
+        if not a.no_cpu_baseline:
+            hist = fit("exact", history=True)[2]["label_history"].cpu().numpy()
+            tc = time.perf_counter()
+            ref = oracle.mti_fit(w.x64(), w.C0, w.max_iters, tol=w.tol, history=True,
+                                 objective=False, exact_mean=True)
+            tcpu = time.perf_counter() - tc
+            out["cpu_baseline"] = {
+                "value": round(ref.iters / tcpu, 4), "unit": "iters/s",
+                "cores": oracle.num_threads(), "kind": "oracle",
+                "sample": f"FP64 MTI oracle with the exactly rounded mean, same workload "
+                          f"and C0, {ref.iters} iterations (whole fit)"}
+            out["exact"] = bool(ref.iters == st["iters"] and hist.shape[0] == ref.iters and
+                                (hist == ref.label_hist).all() and
+                                (C.cpu().numpy() == ref.C).all())
     else:   # batched
         ws = workloads.batched(64)
         print(f"# 64 instances, sum n={sum(w.n for w in ws)}, generated in "

@@ -698,6 +698,7 @@ static knor_status fit_impl(const void* X, knor_dtype dt, int64_t n, int d,
     IterCtl ctl;
     ctl.row = row; ctl.conv = conv; ctl.iter = t; ctl.tol_n = tol_n;
     ctl.segmented = seg; ctl.n = n;
+    if (seg) { ctl.list = list; ctl.seg_cnt = seg_cnt; ctl.nseg = nseg; }
     if (exact)
       HIPCHK(launch_update_exact(plan, xplan, X, dt, labels_out, C_out, C_out, nullptr, &ops,
                                  mti ? drift : nullptr, dirty, &ctl, s, pp));

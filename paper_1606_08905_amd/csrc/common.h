@@ -363,6 +363,11 @@ struct IterCtl {
   double tol_n = 0.0;
   int segmented = 0;                  // MTI survivors were scanned
   int64_t n = 0;
+  // MTI survivors of this iteration (every point whose label may have
+  // changed): list[s * kSeg + i] for i < seg_cnt[s], s < nseg; null: all
+  const int* list = nullptr;
+  const int* seg_cnt = nullptr;
+  int nseg = 0;
 };
 
 hipError_t launch_update(const UpdatePlan& p, const void* X, knor_dtype dt,
@@ -375,9 +380,11 @@ hipError_t launch_update(const UpdatePlan& p, const void* X, knor_dtype dt,
                          Prof* prof = nullptr);
 
 // Pass 1 of the update alone: the stable counting sort (perm, nj, off,
-// leaf_off), skipped when *conv < iter.
+// leaf_off), skipped when *conv < iter.  early = 1: every kernel tests that
+// before its first load (for a gate that often skips the sort); early = 0:
+// the test overlaps the first loads.
 hipError_t launch_sort(const UpdatePlan& p, const int32_t* labels, int* dirty,
-                       const int* conv, int iter, hipStream_t s);
+                       const int* conv, int iter, hipStream_t s, int early);
 
 // Exact update (FP32 and BF16 points): per (cluster, dimension) kXD signed
 // 64-bit digits of weight 2^(32 s - 149); centroids are the exact member

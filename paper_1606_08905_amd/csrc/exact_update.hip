@@ -17,15 +17,17 @@
 //
 // Per iteration of a fit (labels of the previous update in `prev`):
 //   exact_delta    counts this iteration's changed labels and chooses the
-//                  mode in a gate word.  Delta mode (few changes): for each
-//                  changed point, its value leaves the old cluster's digits
-//                  and enters the new one's (64-bit atomic adds, order-free)
-//                  and the member counts move by one.  Full mode: the digits
-//                  of every dirty cluster are cleared.
+//                  mode in a gate word; it visits every point, or under MTI
+//                  only the survivors (no other label can change), and
+//                  copies changed labels to prev.  Delta mode (few changes):
+//                  each changed point leaves the old cluster's digits and
+//                  enters the new one's (64-bit atomic adds, order-free) and
+//                  the member counts move by one.  Full mode: the digits of
+//                  every dirty cluster are cleared.
 //   sort           the canonical counting sort (full mode only, via the gate)
 //   exact_leaf     full mode: a wave walks a run of leaves (64 members of one
-//                  cluster each), sums each dimension's digits in LDS and
-//                  adds them to the cluster's digits when the cluster ends
+//                  cluster each), sums each dimension's digits and adds them
+//                  to the cluster's digits when the cluster ends
 //   exact_finalize every dirty cluster: normalise the digits, divide by the
 //                  member count with one rounding, write the centroid and
 //                  its derived operands; close the iteration.
@@ -36,14 +38,15 @@
 
 namespace knor {
 
-constexpr int kExactRun = 8;          // leaves per wave in the full pass
+constexpr int kExactRun = 4;           // leaves per wave in the full pass
 constexpr int kExactWaves = 4;
-constexpr int kDeltaAtomics = 1 << 19; // delta mode up to this many digit adds
+constexpr int kDeltaAtomics = 1 << 20; // delta mode up to about this many digit adds
+
+static size_t al256(size_t b) { return (b + 255) & ~(size_t)255; }
 
 size_t exact_workspace_bytes(int64_t n, int k, int d) {
-  const size_t a = ((size_t)k * kXD * d * sizeof(unsigned long long) + 255) & ~(size_t)255;
-  const size_t b = ((size_t)n * sizeof(int32_t) + 255) & ~(size_t)255;
-  return a + b + 256;
+  return al256((size_t)k * kXD * d * sizeof(unsigned long long)) +
+         al256((size_t)n * sizeof(int32_t)) + al256(sizeof(int) * 4);
 }
 
 void exact_plan_init(ExactPlan* p, int64_t n, int k, int d, void* ws) {
@@ -52,11 +55,13 @@ void exact_plan_init(ExactPlan* p, int64_t n, int k, int d, void* ws) {
   p->k = k;
   p->d = d;
   p->slots = (unsigned long long*)c;
-  c += ((size_t)k * kXD * d * sizeof(unsigned long long) + 255) & ~(size_t)255;
+  c += al256((size_t)k * kXD * d * sizeof(unsigned long long));
   p->prev = (int32_t*)c;
-  c += ((size_t)n * sizeof(int32_t) + 255) & ~(size_t)255;
+  c += al256((size_t)n * sizeof(int32_t));
   p->gate = (int*)c;
-  int dm = kDeltaAtomics / (4 * d);
+  // each moved point costs about 4 d digit adds (low and high digit, old
+  // and new cluster)
+  const int dm = kDeltaAtomics / (4 * d);
   p->delta_max = dm < 256 ? 256 : dm;
 }
 
@@ -91,13 +96,29 @@ __device__ __forceinline__ FixedAdd fixed_of(uint32_t u) {
 // mode choice, delta moves, prev labels
 // ---------------------------------------------------------------------------
 
+// Every point whose label may have changed: all n, or the MTI survivors
+// list[s * kSeg + i] for i < seg_cnt[s].
+struct DeltaSrc {
+  int64_t n;
+  const int* list;
+  const int* seg_cnt;
+  int nseg;
+};
+
+// Block b takes block b of points: survivor segment b, or points
+// [b kSeg, (b + 1) kSeg); each thread loads its kSeg / 256 points at once.
+// In delta mode each wave then moves its changed points: two at a time when
+// d <= 32 (one per half wave), one dimension per lane, with order-free
+// 64-bit atomic adds to the digits of the new (+x) and old (-x) cluster.
+constexpr int kDeltaPer = kSeg / 256;
+
 template <typename T>
 __global__ __launch_bounds__(256) void exact_delta(
-    const T* __restrict__ X, int64_t n, int d, const int32_t* __restrict__ labels,
-    int32_t* __restrict__ prev, int k, unsigned long long* __restrict__ slots,
+    const T* __restrict__ X, DeltaSrc src, const int32_t* __restrict__ labels,
+    int32_t* __restrict__ prev, int k, int d, unsigned long long* __restrict__ slots,
     int* __restrict__ nj, const int* __restrict__ dirty,
-    const unsigned long long* __restrict__ row, int* __restrict__ gate,
-    int delta_max, const int* __restrict__ conv, int iter) {
+    const unsigned long long* __restrict__ row, int* __restrict__ gate, int delta_max,
+    const int* __restrict__ conv, int iter) {
   const int cv = *conv;
   const int lane = threadIdx.x & 63;
   // this iteration's changed labels, from the spread counter slots
@@ -108,45 +129,70 @@ __global__ __launch_bounds__(256) void exact_delta(
   if (blockIdx.x == 0 && threadIdx.x == 0)
     *gate = cv < iter ? cv : (full ? kNotConverged : -1);
   if (cv < iter) return;
-  const int64_t nthreads = (int64_t)gridDim.x * blockDim.x;
-  const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (full) {
     const int64_t ns = (int64_t)k * kXD * d;
-    for (int64_t e = tid; e < ns; e += nthreads)
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < ns;
+         e += (int64_t)gridDim.x * blockDim.x)
       if (dirty[e / ((int64_t)kXD * d)]) slots[e] = 0ull;
-    for (int64_t p = tid; p < n; p += nthreads) {
-      const int32_t a = labels[p];
-      if (prev[p] != a) prev[p] = a;
-    }
-    return;
   }
-  // delta: the wave takes 64 consecutive points at a time; each changed
-  // point is moved by the whole wave, one dimension per lane
-  const int64_t wave0 = tid - lane;
-  for (int64_t b = wave0; b < n; b += nthreads) {
-    const int64_t p = b + lane;
-    const int32_t a = p < n ? labels[p] : 0;
-    const int32_t o = p < n ? prev[p] : 0;
-    uint64_t mask = __ballot(p < n && a != o);
-    if (p < n && a != o) prev[p] = a;
-    while (mask) {
-      const int l = __builtin_ctzll(mask);
-      mask &= mask - 1;
-      const int64_t q = b + l;
-      const int32_t na = __shfl(a, l), oa = __shfl(o, l);
-      if (lane == 0) {
-        atomicAdd(&nj[na], 1);
-        if (oa >= 0) atomicSub(&nj[oa], 1);
+  const bool two = d <= 32;
+  const int half = two ? lane >> 5 : 0;
+  const int dl = two ? (lane & 31) : lane;
+  const int dstep = two ? 32 : 64;
+  const int nblk = src.list ? src.nseg : (int)((src.n + kSeg - 1) / kSeg);
+  for (int b = blockIdx.x; b < nblk; b += gridDim.x) {
+    const int64_t b0 = (int64_t)b * kSeg;
+    const int cnt = src.list ? src.seg_cnt[b]
+                             : (int)(src.n - b0 < kSeg ? src.n - b0 : kSeg);
+    int pt[kDeltaPer], a[kDeltaPer], o[kDeltaPer];
+#pragma unroll
+    for (int q = 0; q < kDeltaPer; ++q) {
+      const int i = q * (int)blockDim.x + (int)threadIdx.x;
+      pt[q] = i < cnt ? (src.list ? src.list[(size_t)b * kSeg + i] : (int)(b0 + i)) : -1;
+    }
+#pragma unroll
+    for (int q = 0; q < kDeltaPer; ++q) {
+      a[q] = pt[q] >= 0 ? labels[pt[q]] : 0;
+      o[q] = pt[q] >= 0 ? prev[pt[q]] : 0;
+    }
+    uint32_t mv = 0;
+#pragma unroll
+    for (int q = 0; q < kDeltaPer; ++q)
+      if (pt[q] >= 0 && a[q] != o[q]) {
+        prev[pt[q]] = a[q];
+        mv |= 1u << q;
       }
-      for (int dim = lane; dim < d; dim += 64) {
-        const FixedAdd f = fixed_of(f32_bits<T>(X[(size_t)q * d + dim]));
-        unsigned long long* sn = slots + ((size_t)na * kXD + f.idx) * d + dim;
-        if (f.lo) atomicAdd(sn, f.lo);
-        if (f.hi) atomicAdd(sn + d, f.hi);
-        if (oa >= 0) {
-          unsigned long long* so = slots + ((size_t)oa * kXD + f.idx) * d + dim;
-          if (f.lo) atomicAdd(so, 0ull - f.lo);
-          if (f.hi) atomicAdd(so + d, 0ull - f.hi);
+    if (full) continue;                         // uniform over the grid
+#pragma unroll
+    for (int q = 0; q < kDeltaPer; ++q) {
+      uint64_t mask = __ballot((mv >> q) & 1u);
+      while (mask) {
+        const int l0 = __builtin_ctzll(mask);
+        mask &= mask - 1;
+        int l1 = -1;
+        if (two && mask) {
+          l1 = __builtin_ctzll(mask);
+          mask &= mask - 1;
+        }
+        const int l = half ? l1 : l0;
+        const int ls = l < 0 ? l0 : l;
+        const int pq = __shfl(pt[q], ls);
+        const int32_t na = __shfl(a[q], ls), oa = __shfl(o[q], ls);
+        if (l < 0) continue;                    // second half without a point
+        if (dl == 0) {
+          atomicAdd(&nj[na], 1);
+          if (oa >= 0) atomicSub(&nj[oa], 1);
+        }
+        for (int dim = dl; dim < d; dim += dstep) {
+          const FixedAdd f = fixed_of(f32_bits<T>(X[(size_t)pq * d + dim]));
+          unsigned long long* sn = slots + ((size_t)na * kXD + f.idx) * d + dim;
+          if (f.lo) atomicAdd(sn, f.lo);
+          if (f.hi) atomicAdd(sn + d, f.hi);
+          if (oa >= 0) {
+            unsigned long long* so = slots + ((size_t)oa * kXD + f.idx) * d + dim;
+            if (f.lo) atomicAdd(so, 0ull - f.lo);
+            if (f.hi) atomicAdd(so + d, 0ull - f.hi);
+          }
         }
       }
     }
@@ -187,7 +233,18 @@ __global__ __launch_bounds__(64 * kExactWaves) void exact_leaf(
     const bool on = dim < d;
 #pragma unroll
     for (int s = 0; s < kXD; ++s) A[s * 64 + lane] = 0;
+    // digits base .. base + 2 of the lane's column in registers; a value
+    // whose digits fall outside goes to its LDS column directly
+    long long w0 = 0, w1 = 0, w2 = 0;
+    int base = -1;
     auto flush = [&](int jc) {
+      if (base >= 0) {
+        A[base * 64 + lane] += w0;
+        A[(base + 1) * 64 + lane] += w1;
+        A[(base + 2) * 64 + lane] += w2;
+      }
+      w0 = w1 = w2 = 0;
+      base = -1;
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -217,20 +274,31 @@ __global__ __launch_bounds__(64 * kExactWaves) void exact_leaf(
       int cnt = nj[j] - L * kLeaf;
       if (cnt > kLeaf) cnt = kLeaf;
       const int pl = lane < cnt ? perm[m0 + lane] : 0;
-      for (int m = 0; m < cnt; m += 8 * step) {
-        uint32_t u[8];
+      // the lane's members r, r + step, ... of the leaf: kBatch loads in
+      // flight before the first is used (the whole leaf when d <= 32)
+      constexpr int kBatch = 32;
+      for (int m = 0; m < cnt; m += kBatch * step) {
+        uint32_t u[kBatch];
 #pragma unroll
-        for (int q = 0; q < 8; ++q) {
+        for (int q = 0; q < kBatch; ++q) {
           const int mm = m + q * step + r;
           const int pq = __shfl(pl, mm & 63);
           u[q] = (on && mm < cnt) ? f32_bits<T>(X[(size_t)pq * d + dim]) : 0u;
         }
 #pragma unroll
-        for (int q = 0; q < 8; ++q) {
+        for (int q = 0; q < kBatch; ++q) {
           if ((u[q] << 1) == 0u) continue;     // +-0 adds nothing
           const FixedAdd f = fixed_of(u[q]);
-          A[f.idx * 64 + lane] += (long long)f.lo;
-          A[(f.idx + 1) * 64 + lane] += (long long)f.hi;
+          if (base < 0) base = f.idx;          // idx <= 7: base + 2 < kXD
+          const bool in0 = f.idx == base, in1 = f.idx == base + 1;
+          const long long lo = (long long)f.lo, hi = (long long)f.hi;
+          w0 += in0 ? lo : 0ll;
+          w1 += in0 ? hi : (in1 ? lo : 0ll);
+          w2 += in1 ? hi : 0ll;
+          if (!in0 && !in1) {
+            A[f.idx * 64 + lane] += lo;
+            A[(f.idx + 1) * 64 + lane] += hi;
+          }
         }
       }
     }
@@ -243,9 +311,9 @@ __global__ __launch_bounds__(64 * kExactWaves) void exact_leaf(
 // ---------------------------------------------------------------------------
 
 // Normalise the kXD digits at p (stride d) in place: digits 0..kXD-2 in
-// [0, 2^32), the top digit signed.  Returns the top digit.
-__device__ __forceinline__ void normalise_digits(unsigned long long* p, int d,
-                                                 uint32_t* dig, long long& top) {
+// [0, 2^32), the top digit signed.
+__device__ __forceinline__ void normalise_digits(unsigned long long* p, int d, uint32_t* dig,
+                                                 long long& top) {
   long long carry = 0;
 #pragma unroll
   for (int s = 0; s < kXD - 1; ++s) {
@@ -282,15 +350,23 @@ __device__ __forceinline__ double exact_quotient(const uint32_t* dig, long long 
   const unsigned long long tmag = neg ? (unsigned long long)(~top) + borrow
                                       : (unsigned long long)top;
   a[W - 1] = (uint32_t)tmag;                    // |V| < 2^308: the top fits
-  // long division, most significant digit first
+  // long division, most significant digit first.  Each quotient digit is
+  // cur / cnt < 2^32; the FP64 estimate cur * (1 / cnt) has relative error
+  // below 2^-50, so its truncation is off by at most one, fixed from the
+  // sign and size of the remainder.
   const unsigned long long n = (unsigned long long)cnt;
+  const double rn = 1.0 / (double)cnt;
   unsigned long long rem = 0;
   uint32_t q[W];
 #pragma unroll
   for (int s = W - 1; s >= 0; --s) {
     const unsigned long long cur = (rem << 32) | a[s];
-    q[s] = (uint32_t)(cur / n);
-    rem = cur - (unsigned long long)q[s] * n;
+    unsigned long long qd = (unsigned long long)((double)cur * rn);
+    long long r = (long long)(cur - qd * n);
+    if (r < 0) { qd -= 1; r += (long long)n; }
+    else if (r >= (long long)n) { qd += 1; r -= (long long)n; }
+    q[s] = (uint32_t)qd;
+    rem = (unsigned long long)r;
   }
   int t = W - 1;
   while (t > 0 && q[t] == 0u) --t;
@@ -320,6 +396,7 @@ __global__ __launch_bounds__(256) void exact_finalize(
     uint16_t* __restrict__ Chi, uint16_t* __restrict__ Clo, int dpb,
     float* __restrict__ drift, int* __restrict__ dirty, IterCtl ctl,
     const int* __restrict__ conv, int iter) {
+  __shared__ double mean[kMaxD];
   const int cv = *conv;
   const int j = blockIdx.x;
   const int cntj = nj[j];
@@ -331,22 +408,16 @@ __global__ __launch_bounds__(256) void exact_finalize(
     if (drift && threadIdx.x == 0) drift[j] = 0.0f;     // centroid unchanged
     return;
   }
+  // normalise and divide; each thread keeps its dimensions' means
   unsigned long long* base = slots + (size_t)j * kXD * d;
-  if (cntj == 0)      // no members: keep the digits of the value 0 normalised
-    for (int dim = threadIdx.x; dim < d; dim += blockDim.x) {
-      uint32_t dig[kXD - 1];
-      long long top;
-      normalise_digits(base + dim, d, dig, top);
-    }
-  write_centroid(
-      j, k, d, cntj,
-      [&](int dim) {
-        uint32_t dig[kXD - 1];
-        long long top;
-        normalise_digits(base + dim, d, dig, top);
-        return exact_quotient(dig, top, cntj);
-      },
-      C_prev, C_out, CT, Cm2, cn, dp, Chi, Clo, dpb, drift, dirty);
+  for (int dim = threadIdx.x; dim < d; dim += blockDim.x) {
+    uint32_t dig[kXD - 1];
+    long long top;
+    normalise_digits(base + dim, d, dig, top);
+    mean[dim] = cntj > 0 ? exact_quotient(dig, top, cntj) : 0.0;
+  }
+  write_centroid(j, k, d, cntj, [&](int dim) { return mean[dim]; }, C_prev, C_out, CT,
+                 Cm2, cn, dp, Chi, Clo, dpb, drift, dirty);
 }
 
 // ---------------------------------------------------------------------------
@@ -372,20 +443,21 @@ hipError_t launch_update_exact(const UpdatePlan& p, const ExactPlan& xp, const v
     if (e != hipSuccess) return e;
   } else {
     if (!dirty) return hipErrorInvalidValue;
-    int64_t blocks = (p.n + 255) / 256;
-    if (blocks > 2048) blocks = 2048;
+    DeltaSrc src{p.n, ctl->list, ctl->seg_cnt, ctl->nseg};
+    int64_t blocks = ctl->list ? ctl->nseg : (p.n + kSeg - 1) / kSeg;
+    if (blocks > (1 << 20)) blocks = 1 << 20;
     if (blocks < 1) blocks = 1;
     if (dt == KNOR_F32)
       hipLaunchKernelGGL(exact_delta<float>, dim3((unsigned)blocks), dim3(256), 0, s,
-                         (const float*)X, p.n, d, labels, xp.prev, k, xp.slots, p.nj, dirty,
+                         (const float*)X, src, labels, xp.prev, k, d, xp.slots, p.nj, dirty,
                          ctl->row, xp.gate, xp.delta_max, conv, iter);
     else
       hipLaunchKernelGGL(exact_delta<uint16_t>, dim3((unsigned)blocks), dim3(256), 0, s,
-                         (const uint16_t*)X, p.n, d, labels, xp.prev, k, xp.slots, p.nj, dirty,
-                         ctl->row, xp.gate, xp.delta_max, conv, iter);
+                         (const uint16_t*)X, src, labels, xp.prev, k, d, xp.slots, p.nj,
+                         dirty, ctl->row, xp.gate, xp.delta_max, conv, iter);
     gate = xp.gate;
   }
-  if (hipError_t e = launch_sort(p, labels, dirty, gate, iter, s)) return e;
+  if (hipError_t e = launch_sort(p, labels, dirty, gate, iter, s, one_shot ? 0 : 1)) return e;
   if (prof) { prof->end(); prof->begin(KNOR_PROF_LEAF); }
   const int64_t waves = (p.max_leaves + kExactRun - 1) / kExactRun;
   const int64_t lblocks = (waves + kExactWaves - 1) / kExactWaves;

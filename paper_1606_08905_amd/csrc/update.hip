@@ -202,9 +202,10 @@ __global__ __launch_bounds__(1024) void hist_fused(const int32_t* __restrict__ l
                                                    int64_t n, int k, int SB,
                                                    int* __restrict__ cnt,
                                                    const int* __restrict__ conv,
-                                                   int iter) {
+                                                   int iter, int early) {
   extern __shared__ int tab[];               // kFusedWaves x k
   const int cv = *conv;
+  if (early && cv < iter) return;            // gated: nothing loaded yet
   const int r = blockIdx.x, wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int64_t p0 = ((int64_t)r * kFusedWaves + wave) * SB;
   const int64_t p1 = p0 + SB < n ? p0 + SB : n;
@@ -252,9 +253,10 @@ __global__ __launch_bounds__(256) void range_scan(const int* __restrict__ cnt,
                                                   int* __restrict__ rpre,
                                                   int* __restrict__ nj,
                                                   const int* __restrict__ conv,
-                                                  int iter) {
+                                                  int iter, int early) {
   __shared__ int part[256];
   const int cv = *conv;
+  if (early && cv < iter) return;
   const int j = blockIdx.x;
   const int per = (nr + 255) / 256;
   const int r0 = threadIdx.x * per;
@@ -299,11 +301,12 @@ __global__ __launch_bounds__(1024) void scatter_fused(
     int bits, const int* __restrict__ cnt, const int* __restrict__ rpre,
     int* __restrict__ nj, int in_prefix, int lab_lds, const int* __restrict__ dirty,
     int* __restrict__ perm, int* __restrict__ off_out,
-    int* __restrict__ leaf_off_out, const int* __restrict__ conv, int iter) {
+    int* __restrict__ leaf_off_out, const int* __restrict__ conv, int iter, int early) {
   extern __shared__ int run[];               // kFusedWaves x k (+ the range's labels)
   __shared__ int sa[1024], sb[1024];
   __shared__ int sDirty[kFusedMaxK];         // the dirty flags, read per point
   const int cv = *conv;
+  if (early && cv < iter) return;
   const int r = blockIdx.x, wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int j = threadIdx.x;                 // k <= 1024: one cluster per thread
   int tot = 0, pre = 0;
@@ -750,24 +753,24 @@ __global__ __launch_bounds__(256) void tree_finalize(
 }
 
 hipError_t launch_sort(const UpdatePlan& p, const int32_t* labels, int* dirty,
-                       const int* conv, int iter, hipStream_t s) {
+                       const int* conv, int iter, hipStream_t s, int early) {
   const int k = p.k;
   int bits = 0;
   while ((1 << bits) < k) ++bits;
   if (fused_sort(k)) {
     const size_t lds = sizeof(int) * (size_t)kFusedWaves * k;
     hipLaunchKernelGGL(hist_fused, dim3(p.nb), dim3(1024), lds, s, labels, p.n,
-                       k, p.B, p.blockcnt, conv, iter);
+                       k, p.B, p.blockcnt, conv, iter, early);
     const int in_prefix = scatter_prefix(p.nb, k) ? 1 : 0;
     if (!in_prefix)
       hipLaunchKernelGGL(range_scan, dim3(k), dim3(256), 0, s, p.blockcnt, p.nb,
-                         k, p.rpre, p.nj, conv, iter);
+                         k, p.rpre, p.nj, conv, iter, early);
     // the range's labels in LDS next to the running tables, within 48 KB
     const int lab_lds = (size_t)kFusedWaves * (k + p.B) * sizeof(int) <= 49152 ? 1 : 0;
     const size_t lds_s = lds + (lab_lds ? sizeof(int) * (size_t)kFusedWaves * p.B : 0);
     hipLaunchKernelGGL(scatter_fused, dim3(p.nb), dim3(1024), lds_s, s, labels,
                        p.n, k, p.B, bits, p.blockcnt, p.rpre, p.nj, in_prefix,
-                       lab_lds, dirty, p.perm, p.off, p.leaf_off, conv, iter);
+                       lab_lds, dirty, p.perm, p.off, p.leaf_off, conv, iter, early);
   } else {
     const size_t lds_k = sizeof(int) * (size_t)k;
     hipLaunchKernelGGL(hist_kernel, dim3(p.nb), dim3(256), lds_k, s, labels,
@@ -794,7 +797,7 @@ hipError_t launch_update(const UpdatePlan& p, const void* X, knor_dtype dt,
   const int* conv = ctl->conv;
   const int iter = ctl->iter;
   if (prof) prof->begin(KNOR_PROF_SORT);
-  if (hipError_t e = launch_sort(p, labels, dirty, conv, iter, s)) return e;
+  if (hipError_t e = launch_sort(p, labels, dirty, conv, iter, s, 0)) return e;
   if (prof) { prof->end(); prof->begin(KNOR_PROF_LEAF); }
   const int64_t lblocks = (p.max_leaves + kLeafWaves - 1) / kLeafWaves;
   const size_t esz = dt == KNOR_F64 ? 8 : (dt == KNOR_F32 ? 4 : 2);

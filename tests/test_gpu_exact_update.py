@@ -35,7 +35,7 @@ def _print_case(**kw):
 
 def _delta_max(d):
     # changed labels up to which the library moves points one by one
-    return max(256, (1 << 19) // (4 * d))
+    return max(256, (1 << 20) // (4 * d))
 
 
 # ---------------------------------------------------------------------------
@@ -147,7 +147,7 @@ def _fit_exact_compare(X, dtype, C0, k, iters, prune, tol=0.0):
 def test_exact_fit_config2_modes(prune):
     """Early iterations change more labels than the delta limit (full mode),
     later ones fewer (delta mode)."""
-    w = workloads.config(2, n=200000, seed=1)
+    w = workloads.config(2, n=500000, seed=1)
     _print_case(test="exact-fit-config2", prune=prune)
     st, ref = _fit_exact_compare(w.X, w.dtype, w.C0, w.k, 60, prune)
     lim = _delta_max(w.X.shape[1])
