@@ -198,14 +198,15 @@ __device__ void cluster_scan_block(const int* __restrict__ nj, int k,
 // cnt layout per range r: kFusedWaves rows of per-wave counts, then one row
 // of range totals: cnt[(r * (W + 1) + w) * k + j].
 
+template <bool EARLY>
 __global__ __launch_bounds__(1024) void hist_fused(const int32_t* __restrict__ labels,
                                                    int64_t n, int k, int SB,
                                                    int* __restrict__ cnt,
                                                    const int* __restrict__ conv,
-                                                   int iter, int early) {
+                                                   int iter) {
   extern __shared__ int tab[];               // kFusedWaves x k
   const int cv = *conv;
-  if (early && cv < iter) return;            // gated: nothing loaded yet
+  if (EARLY && cv < iter) return;            // gated: nothing loaded yet
   const int r = blockIdx.x, wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int64_t p0 = ((int64_t)r * kFusedWaves + wave) * SB;
   const int64_t p1 = p0 + SB < n ? p0 + SB : n;
@@ -248,15 +249,16 @@ __global__ __launch_bounds__(1024) void hist_fused(const int32_t* __restrict__ l
 
 // Per cluster j (one workgroup each): exclusive prefix over the ranges of
 // the range totals, rpre[r * k + j], and the cluster total nj[j].
+template <bool EARLY>
 __global__ __launch_bounds__(256) void range_scan(const int* __restrict__ cnt,
                                                   int nr, int k,
                                                   int* __restrict__ rpre,
                                                   int* __restrict__ nj,
                                                   const int* __restrict__ conv,
-                                                  int iter, int early) {
+                                                  int iter) {
   __shared__ int part[256];
   const int cv = *conv;
-  if (early && cv < iter) return;
+  if (EARLY && cv < iter) return;
   const int j = blockIdx.x;
   const int per = (nr + 255) / 256;
   const int r0 = threadIdx.x * per;
@@ -296,17 +298,18 @@ __global__ __launch_bounds__(256) void range_scan(const int* __restrict__ cnt,
 // sums the totals of cluster c over ranges q, q + Q, ... (Q = 1024 / k
 // parts), over all ranges and over the ranges before this one, and range 0
 // stores the cluster totals in nj.
+template <bool EARLY>
 __global__ __launch_bounds__(1024) void scatter_fused(
     const int32_t* __restrict__ labels, int64_t n, int k, int SB,
     int bits, const int* __restrict__ cnt, const int* __restrict__ rpre,
     int* __restrict__ nj, int in_prefix, int lab_lds, const int* __restrict__ dirty,
     int* __restrict__ perm, int* __restrict__ off_out,
-    int* __restrict__ leaf_off_out, const int* __restrict__ conv, int iter, int early) {
+    int* __restrict__ leaf_off_out, const int* __restrict__ conv, int iter) {
   extern __shared__ int run[];               // kFusedWaves x k (+ the range's labels)
   __shared__ int sa[1024], sb[1024];
   __shared__ int sDirty[kFusedMaxK];         // the dirty flags, read per point
   const int cv = *conv;
-  if (early && cv < iter) return;
+  if (EARLY && cv < iter) return;
   const int r = blockIdx.x, wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int j = threadIdx.x;                 // k <= 1024: one cluster per thread
   int tot = 0, pre = 0;
@@ -759,18 +762,21 @@ hipError_t launch_sort(const UpdatePlan& p, const int32_t* labels, int* dirty,
   while ((1 << bits) < k) ++bits;
   if (fused_sort(k)) {
     const size_t lds = sizeof(int) * (size_t)kFusedWaves * k;
-    hipLaunchKernelGGL(hist_fused, dim3(p.nb), dim3(1024), lds, s, labels, p.n,
-                       k, p.B, p.blockcnt, conv, iter, early);
+    auto hist = early ? hist_fused<true> : hist_fused<false>;
+    auto rscan = early ? range_scan<true> : range_scan<false>;
+    auto scat = early ? scatter_fused<true> : scatter_fused<false>;
+    hipLaunchKernelGGL(hist, dim3(p.nb), dim3(1024), lds, s, labels, p.n,
+                       k, p.B, p.blockcnt, conv, iter);
     const int in_prefix = scatter_prefix(p.nb, k) ? 1 : 0;
     if (!in_prefix)
-      hipLaunchKernelGGL(range_scan, dim3(k), dim3(256), 0, s, p.blockcnt, p.nb,
-                         k, p.rpre, p.nj, conv, iter, early);
+      hipLaunchKernelGGL(rscan, dim3(k), dim3(256), 0, s, p.blockcnt, p.nb,
+                         k, p.rpre, p.nj, conv, iter);
     // the range's labels in LDS next to the running tables, within 48 KB
     const int lab_lds = (size_t)kFusedWaves * (k + p.B) * sizeof(int) <= 49152 ? 1 : 0;
     const size_t lds_s = lds + (lab_lds ? sizeof(int) * (size_t)kFusedWaves * p.B : 0);
-    hipLaunchKernelGGL(scatter_fused, dim3(p.nb), dim3(1024), lds_s, s, labels,
+    hipLaunchKernelGGL(scat, dim3(p.nb), dim3(1024), lds_s, s, labels,
                        p.n, k, p.B, bits, p.blockcnt, p.rpre, p.nj, in_prefix,
-                       lab_lds, dirty, p.perm, p.off, p.leaf_off, conv, iter, early);
+                       lab_lds, dirty, p.perm, p.off, p.leaf_off, conv, iter);
   } else {
     const size_t lds_k = sizeof(int) * (size_t)k;
     hipLaunchKernelGGL(hist_kernel, dim3(p.nb), dim3(256), lds_k, s, labels,
