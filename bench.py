@@ -81,6 +81,9 @@ def parse():
                     help="headline: the benchmark workload (default); the "
                          "others measure one extended form on its own "
                          "workload against plain FP32 Lloyd's on this GPU")
+    ap.add_argument("--config", type=int, default=2, choices=[2, 3, 5],
+                    help="--form incremental: workload (2 = headline, 3 = mixed "
+                         "precision, 5 = large k)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="also run one device-to-device copy of this many MiB "
                          "before the timed region (a known-size kernel for "
@@ -248,10 +251,13 @@ def run_form(a):
             out["cpu_baseline"] = cb
             out["cpu_sample_labels_exact"] = ok
     elif a.form == "incremental":
-        w = workloads.config(2)
+        w = workloads.config(a.config)
         print(f"# data n={w.n} d={w.d} k={w.k} generated in "
               f"{time.perf_counter() - t_gen:.1f}s", file=sys.stderr, flush=True)
-        X = torch.from_numpy(w.X).cuda()
+        if w.dtype == "bf16":
+            X = torch.from_numpy(w.X.view(np.int16)).cuda().view(torch.bfloat16)
+        else:
+            X = torch.from_numpy(w.X).cuda()
         C0 = torch.from_numpy(w.C0).cuda()
 
         def fit(update, **kw):
@@ -268,14 +274,19 @@ def run_form(a):
             groups[upd] = (ms, la)
         ms, la = groups["exact"]
         g = int(np.argmax(ms))
+        sx = 2 if w.dtype == "bf16" else 4
+        peak = PEAK_BF16_MFMA if w.dtype == "bf16" else PEAK_FP32_MFMA
         upd_groups = [knor.PROF_GROUPS.index(nm) for nm in ("sort", "leaf", "tree")]
+        names = {2: "gaussian-mixture n=1e6 d=32 k=100 f32 MTI k-means++ max_iters=100 tol=0",
+                 3: "mixed precision: n=2e7 d=64 k=256 bf16, 95% mixture + 5% uniform "
+                    "outliers, k random rows, 30 iters, MTI",
+                 5: "large k: n=1e7 d=32 k=4096 f32 mixture, k random rows, 40 iters, MTI"}
         out.update({
             "metric": "Lloyd iters/s at exact assignments, exact-mean incremental update",
             "value": round(st["iters"] / dt, 3), "unit": "iters/s",
-            "ms_per_step": round(dt * 1e3, 3), "dtype": "f32",
-            "config": {"workload": "gaussian-mixture n=1e6 d=32 k=100 f32 MTI k-means++ "
-                                   "max_iters=100 tol=0, update=exact (changed points moved "
-                                   "one by one when few change)",
+            "ms_per_step": round(dt * 1e3, 3), "dtype": "bf16" if w.dtype == "bf16" else "f32",
+            "config": {"workload": names[a.config] + ", update=exact (changed points moved "
+                                                     "one by one when few change)",
                        "n": w.n, "d": w.d, "k": w.k, "iters_per_fit": st["iters"]},
             "baseline_canonical_update": {"value": round(stc["iters"] / dtc, 3),
                                           "unit": "iters/s", "iters_per_fit": stc["iters"]},
@@ -283,12 +294,12 @@ def run_form(a):
             "update_ms_per_fit": {u: round(float(sum(groups[u][0][i] for i in upd_groups)), 3)
                                   for u in groups},
             "roofline": roofline_of(knor, ms, la, g, 1,
-                                    group_work(g, w.n, w.d, w.k, 4, st["counters"],
-                                               st["iters"]) if g in (0, 1, 2, 3) else None),
+                                    group_work(g, w.n, w.d, w.k, sx, st["counters"],
+                                               st["iters"], peak) if g in (0, 1, 2, 3) else None),
             "kernels": {nm: {"ms_per_fit": round(float(ms[i]), 3), "launches": int(la[i])}
                         for i, nm in enumerate(knor.PROF_GROUPS) if la[i]},
         })
-        if not a.no_cpu_baseline:
+        if not a.no_cpu_baseline and a.config == 2:
             hist = fit("exact", history=True)[2]["label_history"].cpu().numpy()
             tc = time.perf_counter()
             ref = oracle.mti_fit(w.x64(), w.C0, w.max_iters, tol=w.tol, history=True,
@@ -302,6 +313,23 @@ def run_form(a):
             out["exact"] = bool(ref.iters == st["iters"] and hist.shape[0] == ref.iters and
                                 (hist == ref.label_hist).all() and
                                 (C.cpu().numpy() == ref.C).all())
+        elif not a.no_cpu_baseline:
+            # the final centroids of 8 random clusters against the oracle's
+            # exactly rounded mean of their final members
+            h = knor.fit(X, w.k, C0=C0, max_iters=1, history=True)[2]["label_history"]
+            cb, ok = cpu_sample_baseline(oracle, w, lambda r: workloads.to_f64(w.X[r], w.dtype),
+                                         w.C0, h[0].cpu().numpy(), 0.02 if a.config == 5 else 0.05)
+            out["cpu_baseline"] = cb
+            labs = lab.cpu().numpy()
+            Cg = C.cpu().numpy()
+            js = np.random.default_rng(0).choice(w.k, size=8, replace=False)
+            rows = np.nonzero(np.isin(labs, js))[0]
+            remap = np.full(w.k, -1, np.int32)
+            remap[js] = np.arange(8)
+            Co, _ = oracle.update_exact(workloads.to_f64(w.X[rows], w.dtype), remap[labs[rows]],
+                                        Cg[js])
+            out["exact_update_check"] = {"clusters": 8, "members": int(rows.size),
+                                         "equal": bool((Co == Cg[js]).all())}
     else:   # batched
         ws = workloads.batched(64)
         print(f"# 64 instances, sum n={sum(w.n for w in ws)}, generated in "
