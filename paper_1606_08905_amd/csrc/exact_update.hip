@@ -203,106 +203,169 @@ __global__ __launch_bounds__(256) void exact_delta(
 // full pass: runs of leaves
 // ---------------------------------------------------------------------------
 
+// Add the FP64 value s (exact, an integer multiple of 2^-149 below 2^285)
+// to the digits of (cluster jc, dimension dim): its 53-bit significand
+// lands on three consecutive digits.
+__device__ __forceinline__ void add_f64_digits(unsigned long long* slots, int jc, int d, int dim,
+                                               double s) {
+  if (s == 0.0) return;
+  const unsigned long long u = (unsigned long long)__double_as_longlong(s);
+  const int e = (int)((u >> 52) & 0x7ff);                 // |s| >= 2^-149: normal
+  unsigned long long mant = (u & 0xfffffffffffffull) | (1ull << 52);
+  int shift = e - 1075 + 149;                              // |s| = mant 2^shift units
+  if (shift < 0) {                                         // low bits are zero
+    mant >>= -shift;
+    shift = 0;
+  }
+  const int idx = shift >> 5, off = shift & 31;
+  const unsigned long long lo = mant << off;
+  const unsigned long long hi = off ? mant >> (64 - off) : 0ull;
+  const bool neg = (u >> 63) != 0;
+  const unsigned long long dg[3] = {lo & 0xffffffffull, lo >> 32, hi};
+  unsigned long long* p = slots + ((size_t)jc * kXD + idx) * d + dim;
+#pragma unroll
+  for (int t = 0; t < 3; ++t)
+    if (dg[t]) atomicAdd(p + (size_t)t * d, neg ? 0ull - dg[t] : dg[t]);
+}
+
 // Wave w of block b walks leaves [g0, g0 + kExactRun) of the canonical leaf
 // list (consecutive leaves, cluster by cluster), skipping clean clusters.
-// For d <= 32 lane (r, i) = (lane / 32, lane mod 32) takes dimension i of
-// every second member starting at r; otherwise lane i takes dimension
-// c0 + i for each chunk c0 of 64.  Each lane owns one column of kXD digits
-// in LDS; when the run leaves a cluster (and at the end) the columns are
-// added to the cluster's digits in memory.
+// For each chunk of DC dimensions, lane m copies member m's row piece into
+// the wave's LDS tile (16-byte pieces when rows allow), then each lane takes
+// one dimension: for chunks of at most 32 dimensions lane (r, i) =
+// (lane / 32, lane mod 32) takes dimension i of every second member
+// starting at r, otherwise lane i takes dimension i of every member.  Each
+// lane sums its values of a cluster in FP64 and tracks the lowest set bit L
+// and the top bit bound M of those values (units of 2^-149).  Every value
+// is a multiple of 2^L and every partial sum is below count 2^M, so when
+// M - L + ceil(log2 count) <= 53 each partial sum is a double and the FP64
+// sum is exact; it then goes to the cluster's digits as one 53-bit
+// significand.  Otherwise the lane's values of that cluster are walked
+// again and added digit by digit.
+template <typename T>
+struct ExactCfg {
+  static constexpr int DC = 128 / (int)sizeof(T);      // dimensions per chunk
+  static constexpr int LD = DC + 16 / (int)sizeof(T);  // row stride in the tile
+};
+
 template <typename T>
 __global__ __launch_bounds__(64 * kExactWaves) void exact_leaf(
     const T* __restrict__ X, int d, const int* __restrict__ perm,
     const int* __restrict__ nj, const int* __restrict__ off,
     const int* __restrict__ leaf_off, int k, const int* __restrict__ dirty,
-    unsigned long long* __restrict__ slots, const int* __restrict__ gate, int iter) {
-  __shared__ long long acc[kExactWaves][kXD * 64];
+    unsigned long long* __restrict__ slots, const int* __restrict__ gate, int iter,
+    int vec) {
+  constexpr int DC = ExactCfg<T>::DC, LD = ExactCfg<T>::LD;
+  __shared__ __attribute__((aligned(16))) T tile[kExactWaves][kLeaf * LD];
   if (*gate < iter) return;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int total = leaf_off[k];
   const int g0 = (blockIdx.x * kExactWaves + wave) * kExactRun;
   if (g0 >= total) return;                     // per wave; no block barrier below
   const int g1 = g0 + kExactRun < total ? g0 + kExactRun : total;
-  long long* A = acc[wave];
-  const bool two = d <= 32;
-  const int r = two ? lane >> 5 : 0;           // member offset of this lane
-  const int step = two ? 2 : 1;
   const int j0 = cluster_of_leaf(leaf_off, k, g0);
-  for (int c0 = 0; c0 < d; c0 += 64) {
-    const int dim = c0 + (two ? (lane & 31) : lane);
-    const bool on = dim < d;
-#pragma unroll
-    for (int s = 0; s < kXD; ++s) A[s * 64 + lane] = 0;
-    // digits base .. base + 2 of the lane's column in registers; a value
-    // whose digits fall outside goes to its LDS column directly
-    long long w0 = 0, w1 = 0, w2 = 0;
-    int base = -1;
-    auto flush = [&](int jc) {
-      if (base >= 0) {
-        A[base * 64 + lane] += w0;
-        A[(base + 1) * 64 + lane] += w1;
-        A[(base + 2) * 64 + lane] += w2;
-      }
-      w0 = w1 = w2 = 0;
-      base = -1;
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-#pragma unroll
-      for (int s = 0; s < kXD; ++s) {
-        long long v = A[s * 64 + lane];
-        if (two) v += A[s * 64 + (lane ^ 32)];
-        if (on && (!two || lane < 32) && v != 0)
-          atomicAdd(&slots[((size_t)jc * kXD + s) * d + dim], (unsigned long long)v);
-      }
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-#pragma unroll
-      for (int s = 0; s < kXD; ++s) A[s * 64 + lane] = 0;
-    };
-    int j = j0, cur = -1;
-    for (int g = g0; g < g1; ++g) {
-      while (leaf_off[j + 1] <= g) ++j;        // uniform over the wave
-      if (dirty && !dirty[j]) continue;
-      if (j != cur) {
-        if (cur >= 0) flush(cur);
-        cur = j;
-      }
+  T* tl = tile[wave];
+  for (int c0 = 0; c0 < d; c0 += DC) {
+    const int dc = d - c0 < DC ? d - c0 : DC;
+    const bool two = dc <= 32;
+    const int r = two ? lane >> 5 : 0;         // member offset of this lane
+    const int step = two ? 2 : 1;
+    const int dl = two ? (lane & 31) : lane;
+    const int dim = c0 + dl;
+    const bool on = dl < dc;
+    // the lane's values of leaf g of cluster j: fn(u) for each (every lane
+    // of the wave calls this together)
+    auto walk_leaf = [&](int j, int g, auto&& fn) {
       const int L = g - leaf_off[j];
       const int m0 = off[j] + L * kLeaf;
       int cnt = nj[j] - L * kLeaf;
       if (cnt > kLeaf) cnt = kLeaf;
-      const int pl = lane < cnt ? perm[m0 + lane] : 0;
-      // the lane's members r, r + step, ... of the leaf: kBatch loads in
-      // flight before the first is used (the whole leaf when d <= 32)
-      constexpr int kBatch = 32;
-      for (int m = 0; m < cnt; m += kBatch * step) {
-        uint32_t u[kBatch];
-#pragma unroll
-        for (int q = 0; q < kBatch; ++q) {
-          const int mm = m + q * step + r;
-          const int pq = __shfl(pl, mm & 63);
-          u[q] = (on && mm < cnt) ? f32_bits<T>(X[(size_t)pq * d + dim]) : 0u;
-        }
-#pragma unroll
-        for (int q = 0; q < kBatch; ++q) {
-          if ((u[q] << 1) == 0u) continue;     // +-0 adds nothing
-          const FixedAdd f = fixed_of(u[q]);
-          if (base < 0) base = f.idx;          // idx <= 7: base + 2 < kXD
-          const bool in0 = f.idx == base, in1 = f.idx == base + 1;
-          const long long lo = (long long)f.lo, hi = (long long)f.hi;
-          w0 += in0 ? lo : 0ll;
-          w1 += in0 ? hi : (in1 ? lo : 0ll);
-          w2 += in1 ? hi : 0ll;
-          if (!in0 && !in1) {
-            A[f.idx * 64 + lane] += lo;
-            A[(f.idx + 1) * 64 + lane] += hi;
-          }
+      if (lane < cnt) {
+        const T* xr = X + (size_t)perm[m0 + lane] * d + c0;
+        if (vec) {
+          const int nv = dc * (int)sizeof(T) / 16;
+          const uint4* src = reinterpret_cast<const uint4*>(xr);
+          uint4* dst = reinterpret_cast<uint4*>(tl + lane * LD);
+          for (int v = 0; v < nv; ++v) dst[v] = src[v];
+        } else {
+          for (int i = 0; i < dc; ++i) tl[lane * LD + i] = xr[i];
         }
       }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      if (on)
+        for (int m = r; m < cnt; m += step) {
+          const uint32_t u = f32_bits<T>(tl[m * LD + dl]);
+          if ((u << 1) != 0u) fn(u);           // +-0 adds nothing
+        }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    };
+    int j = j0, cur = -1, gs = g0;
+    double sacc = 0.0;
+    int Lm = 1 << 30, Mm = -1, cntv = 0;
+    auto flush = [&](int jc, int gend) {       // leaves [gs, gend) of cluster jc
+      int lg = 0;
+      while ((1 << lg) < cntv) ++lg;
+      const bool has = on && cntv > 0;
+      const bool need = has && Mm - Lm + lg > 53;
+      if (has && !need) add_f64_digits(slots, jc, d, dim, sacc);
+      // rare: lanes whose sum may have rounded add their values digit by
+      // digit; the walk runs on the whole wave (it stages rows for every
+      // lane), and only those lanes accumulate
+      if (__ballot(need)) {
+        unsigned long long w0 = 0, w1 = 0, w2 = 0;
+        int base = -1;
+        const int gl = leaf_off[jc + 1] < gend ? leaf_off[jc + 1] : gend;
+        for (int g = gs; g < gl; ++g)
+          walk_leaf(jc, g, [&](uint32_t u) {
+            if (!need) return;
+            const FixedAdd f = fixed_of(u);
+            if (base < 0) base = f.idx;        // idx <= 7: base + 2 < kXD
+            const bool in0 = f.idx == base, in1 = f.idx == base + 1;
+            w0 += in0 ? f.lo : 0ull;
+            w1 += in0 ? f.hi : (in1 ? f.lo : 0ull);
+            w2 += in1 ? f.hi : 0ull;
+            if (!in0 && !in1) {
+              unsigned long long* q = slots + ((size_t)jc * kXD + f.idx) * d + dim;
+              if (f.lo) atomicAdd(q, f.lo);
+              if (f.hi) atomicAdd(q + d, f.hi);
+            }
+          });
+        if (need && base >= 0) {
+          unsigned long long* q = slots + ((size_t)jc * kXD + base) * d + dim;
+          if (w0) atomicAdd(q, w0);
+          if (w1) atomicAdd(q + d, w1);
+          if (w2) atomicAdd(q + 2 * d, w2);
+        }
+      }
+      sacc = 0.0;
+      Lm = 1 << 30;
+      Mm = -1;
+      cntv = 0;
+    };
+    for (int g = g0; g < g1; ++g) {
+      while (leaf_off[j + 1] <= g) ++j;        // uniform over the wave
+      if (dirty && !dirty[j]) continue;
+      if (j != cur) {
+        if (cur >= 0) flush(cur, g);
+        cur = j;
+        gs = g;
+      }
+      walk_leaf(j, g, [&](uint32_t u) {
+        const uint32_t ef = (u >> 23) & 255u;
+        const uint32_t m = (u & 0x7fffffu) | (ef ? 0x800000u : 0u);
+        const int sh = ef ? (int)ef - 1 : 0;
+        const int lo = sh + __builtin_ctz(m);
+        Lm = lo < Lm ? lo : Lm;
+        Mm = sh + 24 > Mm ? sh + 24 : Mm;
+        ++cntv;
+        sacc += (double)__uint_as_float(u);
+      });
     }
-    if (cur >= 0) flush(cur);
+    if (cur >= 0) flush(cur, g1);
   }
 }
 
@@ -461,14 +524,16 @@ hipError_t launch_update_exact(const UpdatePlan& p, const ExactPlan& xp, const v
   if (prof) { prof->end(); prof->begin(KNOR_PROF_LEAF); }
   const int64_t waves = (p.max_leaves + kExactRun - 1) / kExactRun;
   const int64_t lblocks = (waves + kExactWaves - 1) / kExactWaves;
+  const size_t esz = dt == KNOR_F32 ? 4 : 2;
+  const int vec = (int)(((size_t)d * esz) % 16 == 0 && ((uintptr_t)X & 15) == 0);
   if (dt == KNOR_F32)
     hipLaunchKernelGGL(exact_leaf<float>, dim3((unsigned)lblocks), dim3(64 * kExactWaves), 0, s,
                        (const float*)X, d, p.perm, p.nj, p.off, p.leaf_off, k, dirty, xp.slots,
-                       gate, iter);
+                       gate, iter, vec);
   else
     hipLaunchKernelGGL(exact_leaf<uint16_t>, dim3((unsigned)lblocks), dim3(64 * kExactWaves), 0,
                        s, (const uint16_t*)X, d, p.perm, p.nj, p.off, p.leaf_off, k, dirty,
-                       xp.slots, gate, iter);
+                       xp.slots, gate, iter, vec);
   if (prof) { prof->end(); prof->begin(KNOR_PROF_TREE); }
   hipLaunchKernelGGL(exact_finalize, dim3(k), dim3(256), 0, s, xp.slots, p.nj, k, d, C_prev,
                      C_out, counts_out, ops ? ops->Cm2 : nullptr, ops ? ops->cn : nullptr,
