@@ -38,7 +38,7 @@
 
 namespace knor {
 
-constexpr int kExactRun = 4;           // leaves per wave in the full pass
+constexpr int kExactWavesTarget = 16384; // full pass: waves wanted (runs of 4..32 leaves)
 constexpr int kExactWaves = 4;
 constexpr int kDeltaAtomics = 1 << 20; // delta mode up to about this many digit adds
 
@@ -228,7 +228,7 @@ __device__ __forceinline__ void add_f64_digits(unsigned long long* slots, int jc
     if (dg[t]) atomicAdd(p + (size_t)t * d, neg ? 0ull - dg[t] : dg[t]);
 }
 
-// Wave w of block b walks leaves [g0, g0 + kExactRun) of the canonical leaf
+// Wave w of block b walks leaves [g0, g0 + run) of the canonical leaf
 // list (consecutive leaves, cluster by cluster), skipping clean clusters.
 // For each chunk of DC dimensions, lane m copies member m's row piece into
 // the wave's LDS tile (16-byte pieces when rows allow), then each lane takes
@@ -254,15 +254,15 @@ __global__ __launch_bounds__(64 * kExactWaves) void exact_leaf(
     const int* __restrict__ nj, const int* __restrict__ off,
     const int* __restrict__ leaf_off, int k, const int* __restrict__ dirty,
     unsigned long long* __restrict__ slots, const int* __restrict__ gate, int iter,
-    int vec) {
+    int vec, int run) {
   constexpr int DC = ExactCfg<T>::DC, LD = ExactCfg<T>::LD;
   __shared__ __attribute__((aligned(16))) T tile[kExactWaves][kLeaf * LD];
   if (*gate < iter) return;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int total = leaf_off[k];
-  const int g0 = (blockIdx.x * kExactWaves + wave) * kExactRun;
+  const int g0 = (blockIdx.x * kExactWaves + wave) * run;
   if (g0 >= total) return;                     // per wave; no block barrier below
-  const int g1 = g0 + kExactRun < total ? g0 + kExactRun : total;
+  const int g1 = g0 + run < total ? g0 + run : total;
   const int j0 = cluster_of_leaf(leaf_off, k, g0);
   T* tl = tile[wave];
   for (int c0 = 0; c0 < d; c0 += DC) {
@@ -306,11 +306,26 @@ __global__ __launch_bounds__(64 * kExactWaves) void exact_leaf(
     int j = j0, cur = -1, gs = g0;
     double sacc = 0.0;
     int Lm = 1 << 30, Mm = -1, cntv = 0;
-    auto flush = [&](int jc, int gend) {       // leaves [gs, gend) of cluster jc
+    auto bound_ok = [](int L, int M, int c) {
       int lg = 0;
-      while ((1 << lg) < cntv) ++lg;
-      const bool has = on && cntv > 0;
-      const bool need = has && Mm - Lm + lg > 53;
+      while ((1 << lg) < c) ++lg;
+      return c == 0 || M - L + lg <= 53;
+    };
+    auto flush = [&](int jc, int gend) {       // leaves [gs, gend) of cluster jc
+      // the two lanes of a dimension merge their sums when the merged
+      // bound still holds (the FP64 sum of the two is then exact too)
+      bool merged = false;
+      if (two) {
+        const double so = __shfl_xor(sacc, 32);
+        const int Lo = __shfl_xor(Lm, 32), Mo = __shfl_xor(Mm, 32), co = __shfl_xor(cntv, 32);
+        const int L2 = Lo < Lm ? Lo : Lm, M2 = Mo > Mm ? Mo : Mm;
+        if (bound_ok(L2, M2, cntv + co)) {
+          merged = true;
+          if (on && r == 0 && cntv + co > 0) add_f64_digits(slots, jc, d, dim, sacc + so);
+        }
+      }
+      const bool has = on && cntv > 0 && !merged;
+      const bool need = has && !bound_ok(Lm, Mm, cntv);
       if (has && !need) add_f64_digits(slots, jc, d, dim, sacc);
       // rare: lanes whose sum may have rounded add their values digit by
       // digit; the walk runs on the whole wave (it stages rows for every
@@ -522,18 +537,21 @@ hipError_t launch_update_exact(const UpdatePlan& p, const ExactPlan& xp, const v
   }
   if (hipError_t e = launch_sort(p, labels, dirty, gate, iter, s, one_shot ? 0 : 1)) return e;
   if (prof) { prof->end(); prof->begin(KNOR_PROF_LEAF); }
-  const int64_t waves = (p.max_leaves + kExactRun - 1) / kExactRun;
+  // longer runs at large n: fewer flushes of partial digits (global adds)
+  int64_t run = p.max_leaves / kExactWavesTarget;
+  run = run < 4 ? 4 : (run > 32 ? 32 : run);
+  const int64_t waves = (p.max_leaves + run - 1) / run;
   const int64_t lblocks = (waves + kExactWaves - 1) / kExactWaves;
   const size_t esz = dt == KNOR_F32 ? 4 : 2;
   const int vec = (int)(((size_t)d * esz) % 16 == 0 && ((uintptr_t)X & 15) == 0);
   if (dt == KNOR_F32)
     hipLaunchKernelGGL(exact_leaf<float>, dim3((unsigned)lblocks), dim3(64 * kExactWaves), 0, s,
                        (const float*)X, d, p.perm, p.nj, p.off, p.leaf_off, k, dirty, xp.slots,
-                       gate, iter, vec);
+                       gate, iter, vec, (int)run);
   else
     hipLaunchKernelGGL(exact_leaf<uint16_t>, dim3((unsigned)lblocks), dim3(64 * kExactWaves), 0,
                        s, (const uint16_t*)X, d, p.perm, p.nj, p.off, p.leaf_off, k, dirty,
-                       xp.slots, gate, iter, vec);
+                       xp.slots, gate, iter, vec, (int)run);
   if (prof) { prof->end(); prof->begin(KNOR_PROF_TREE); }
   hipLaunchKernelGGL(exact_finalize, dim3(k), dim3(256), 0, s, xp.slots, p.nj, k, d, C_prev,
                      C_out, counts_out, ops ? ops->Cm2 : nullptr, ops ? ops->cn : nullptr,
