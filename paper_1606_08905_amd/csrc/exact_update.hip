@@ -282,10 +282,18 @@ __global__ __launch_bounds__(64 * kExactWaves) void exact_leaf(
       if (cnt > kLeaf) cnt = kLeaf;
       if (lane < cnt) {
         const T* xr = X + (size_t)perm[m0 + lane] * d + c0;
-        if (vec) {
+        uint4* dst = reinterpret_cast<uint4*>(tl + lane * LD);
+        const uint4* src = reinterpret_cast<const uint4*>(xr);
+        constexpr int NV = DC * (int)sizeof(T) / 16;
+        if (vec && dc == DC) {
+          // a full chunk: all loads in flight before the first store
+          uint4 t0 = src[0], t1 = src[1], t2 = src[2], t3 = src[3];
+          uint4 t4 = src[4], t5 = src[5], t6 = src[6], t7 = src[7];
+          static_assert(NV == 8, "128-byte chunks");
+          dst[0] = t0; dst[1] = t1; dst[2] = t2; dst[3] = t3;
+          dst[4] = t4; dst[5] = t5; dst[6] = t6; dst[7] = t7;
+        } else if (vec) {
           const int nv = dc * (int)sizeof(T) / 16;
-          const uint4* src = reinterpret_cast<const uint4*>(xr);
-          uint4* dst = reinterpret_cast<uint4*>(tl + lane * LD);
           for (int v = 0; v < nv; ++v) dst[v] = src[v];
         } else {
           for (int i = 0; i < dc; ++i) tl[lane * LD + i] = xr[i];
