@@ -207,6 +207,10 @@ knor_status knor_assign(const void* X, knor_dtype dt, int64_t n, int32_t d,
                         int32_t* labels_out, double* dist2_out);
 
 /* knor_update: one centroid update (Phase II; the merge of Algorithm 1).
+ * With opts->update = 0 (default) each centroid is the canonical-order
+ * member sum divided once by the count; with opts->update = 1 it is the
+ * exact member mean rounded once (FP32 / BF16 points only, else
+ * KNOR_ERR_UNSUPPORTED before any device work).
  *   labels     DEVICE n int32, each in [0, k).  A label outside that range
  *              is not detected on the device; the caller guarantees range.
  *   C_prev     DEVICE k x d FP64: kept for clusters without members.

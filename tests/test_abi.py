@@ -170,3 +170,42 @@ def test_learned_needs_valid_options(L):
         setattr(o, field, value)
         assert _fit(L, opts=ctypes.byref(o)) == knor.KNOR_ERR_INVALID_ARG
         setattr(o, field, 0)
+
+
+def _opts_update(v):
+    o = knor.Opts()
+    o.struct_size = ctypes.sizeof(knor.Opts)
+    o.prune = 1
+    o.recheck = 1
+    o.check_numeric = 1
+    o.update = v
+    return o
+
+
+@pytest.mark.parametrize("v", [-1, 2])
+def test_update_option_validated(L, v):
+    o = _opts_update(v)
+    assert _fit(L, opts=ctypes.byref(o)) == knor.KNOR_ERR_INVALID_ARG
+    P = FAKE
+    assert L.knor_update(P, 1, 10, 4, P, 2, P, ctypes.byref(o), P, None) == \
+        knor.KNOR_ERR_INVALID_ARG
+    arr = (knor.Problem * 1)(_problem())
+    assert L.knor_fit_batched(arr, 1, ctypes.byref(o), None) == knor.KNOR_ERR_INVALID_ARG
+
+
+def test_exact_update_rejects_f64_points(L):
+    # the exact mean covers FP32 and BF16 points; FP64 is refused before any
+    # device work (the pointers are never dereferenced)
+    o = _opts_update(1)
+    assert _fit(L, dt=0, opts=ctypes.byref(o)) == knor.KNOR_ERR_UNSUPPORTED
+    P = FAKE
+    assert L.knor_update(P, 0, 10, 4, P, 2, P, ctypes.byref(o), P, None) == \
+        knor.KNOR_ERR_UNSUPPORTED
+    arr = (knor.Problem * 2)(_problem(), _problem(dt=0))
+    assert L.knor_fit_batched(arr, 2, ctypes.byref(o), None) == knor.KNOR_ERR_UNSUPPORTED
+
+
+def test_binding_update_names():
+    with pytest.raises(ValueError):
+        knor._update_code("sorted")
+    assert knor._update_code("canonical") == 0 and knor._update_code("exact") == 1
