@@ -387,11 +387,11 @@ hipError_t launch_sort(const UpdatePlan& p, const int32_t* labels, int* dirty,
                        const int* conv, int iter, hipStream_t s, int early);
 
 // Exact update (FP32 and BF16 points): per (cluster, dimension) kXD signed
-// 64-bit digits of weight 2^(32 s - 149); centroids are the exact member
+// 64-bit digits of weight 2^(16 s - 149); centroids are the exact member
 // means rounded once.  Inside a fit (ctl->row set, dirty required) only the
 // points whose label changed move between clusters when few do; outside a
 // fit (ctl->row null, dirty null) every cluster is summed from scratch.
-constexpr int kXD = 10;
+constexpr int kXD = 20;
 struct ExactPlan {
   int64_t n;
   int k, d;

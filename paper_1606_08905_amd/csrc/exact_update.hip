@@ -8,12 +8,14 @@
 //
 // Representation.  Every FP32 or BF16 value is m 2^(sh - 149) with m < 2^24
 // and 0 <= sh <= 253, an integer in units of 2^-149 below 2^277.  The sum of
-// a cluster's values in one dimension is kept as kXD signed 64-bit digits of
-// weight 2^(32 s) in those units (carry-save: a digit may leave [0, 2^32)
-// between normalisations).  A value adds (m << (sh mod 32)) split into its
-// low and high 32 bits to digits sh/32 and sh/32 + 1, with the value's sign.
-// One normalisation per update keeps every digit below (n + 1) 2^32 in
-// magnitude, inside int64 for n < 2^31.
+// a cluster's values in one dimension is kept as kXD = 20 signed 64-bit
+// digits of weight 2^(16 s) in those units (carry-save: a digit may leave
+// [0, 2^16) between normalisations).  A value adds m << (sh mod 16), below
+// 2^39, to digit sh/16 with the value's sign: one add per value in the delta
+// mode, which moves at most 2^18 points per iteration (below 2^57 per digit).
+// The full pass adds pieces below 2^32, at most one per digit per value or
+// per flushed sum, so a digit stays below n 2^32 < 2^63.  Each update
+// normalises the dirty clusters' digits.
 //
 // Per iteration of a fit (labels of the previous update in `prev`):
 //   exact_delta    counts this iteration's changed labels and chooses the
@@ -26,11 +28,12 @@
 //                  every dirty cluster are cleared.
 //   sort           the canonical counting sort (full mode only, via the gate)
 //   exact_leaf     full mode: a wave walks a run of leaves (64 members of one
-//                  cluster each), sums each dimension's digits and adds them
-//                  to the cluster's digits when the cluster ends
-//   exact_finalize every dirty cluster: normalise the digits, divide by the
-//                  member count with one rounding, write the centroid and
-//                  its derived operands; close the iteration.
+//                  cluster each), sums each dimension in FP64 (exact under a
+//                  bound checked per lane, else digit by digit) and adds the
+//                  sums to the cluster's digits when the cluster ends
+//   exact_finalize every dirty cluster: normalise the digits (through LDS),
+//                  divide by the member count with one rounding, write the
+//                  centroid and its derived operands; close the iteration.
 #include <math.h>
 
 #include "common.h"
@@ -59,8 +62,8 @@ void exact_plan_init(ExactPlan* p, int64_t n, int k, int d, void* ws) {
   p->prev = (int32_t*)c;
   c += al256((size_t)n * sizeof(int32_t));
   p->gate = (int*)c;
-  // each moved point costs about 4 d digit adds (low and high digit, old
-  // and new cluster)
+  // each moved point costs 2 d digit adds (old and new cluster); the limit
+  // leaves room for twice that
   const int dm = kDeltaAtomics / (4 * d);
   p->delta_max = dm < 256 ? 256 : dm;
 }
@@ -72,23 +75,20 @@ __device__ __forceinline__ uint32_t f32_bits<float>(float v) { return __float_as
 template <>
 __device__ __forceinline__ uint32_t f32_bits<uint16_t>(uint16_t v) { return (uint32_t)v << 16; }
 
-// The value with FP32 bit pattern u as digit adds: lo to digit idx, hi to
-// digit idx + 1, both with the value's sign (two's complement in 64 bits).
+// The value with FP32 bit pattern u as one digit add: v to digit idx, with
+// the value's sign (two's complement in 64 bits).
 struct FixedAdd {
   int idx;
-  unsigned long long lo, hi;
+  unsigned long long v;
 };
 __device__ __forceinline__ FixedAdd fixed_of(uint32_t u) {
   const uint32_t ef = (u >> 23) & 255u;
   const uint32_t m = (u & 0x7fffffu) | (ef ? 0x800000u : 0u);
   const int sh = ef ? (int)ef - 1 : 0;
-  const unsigned long long v = (unsigned long long)m << (sh & 31);
+  const unsigned long long v = (unsigned long long)m << (sh & 15);
   FixedAdd f;
-  f.idx = sh >> 5;
-  const unsigned long long lo = v & 0xffffffffull, hi = v >> 32;
-  const bool neg = (u >> 31) != 0;
-  f.lo = neg ? 0ull - lo : lo;
-  f.hi = neg ? 0ull - hi : hi;
+  f.idx = sh >> 4;                              // <= 15
+  f.v = (u >> 31) ? 0ull - v : v;
   return f;
 }
 
@@ -185,13 +185,9 @@ __global__ __launch_bounds__(256) void exact_delta(
         }
         for (int dim = dl; dim < d; dim += dstep) {
           const FixedAdd f = fixed_of(f32_bits<T>(X[(size_t)pq * d + dim]));
-          unsigned long long* sn = slots + ((size_t)na * kXD + f.idx) * d + dim;
-          if (f.lo) atomicAdd(sn, f.lo);
-          if (f.hi) atomicAdd(sn + d, f.hi);
-          if (oa >= 0) {
-            unsigned long long* so = slots + ((size_t)oa * kXD + f.idx) * d + dim;
-            if (f.lo) atomicAdd(so, 0ull - f.lo);
-            if (f.hi) atomicAdd(so + d, 0ull - f.hi);
+          if (f.v) {
+            atomicAdd(slots + ((size_t)na * kXD + f.idx) * d + dim, f.v);
+            if (oa >= 0) atomicAdd(slots + ((size_t)oa * kXD + f.idx) * d + dim, 0ull - f.v);
           }
         }
       }
@@ -203,9 +199,24 @@ __global__ __launch_bounds__(256) void exact_delta(
 // full pass: runs of leaves
 // ---------------------------------------------------------------------------
 
+// Add the signed amount w (|w| < 2^62) to digit idx of (cluster jc,
+// dimension dim) in two pieces below 2^32, on digits idx and idx + 2 (so
+// that no digit takes more than one piece per value or flush).
+__device__ __forceinline__ void add_split(unsigned long long* slots, int jc, int d, int dim,
+                                          int idx, long long w) {
+  if (w == 0) return;
+  const bool neg = w < 0;
+  const unsigned long long m = neg ? 0ull - (unsigned long long)w : (unsigned long long)w;
+  unsigned long long* p = slots + ((size_t)jc * kXD + idx) * d + dim;
+  const unsigned long long pc[2] = {m & 0xffffffffull, m >> 32};
+#pragma unroll
+  for (int t = 0; t < 2; ++t)
+    if (pc[t] && idx + 2 * t < kXD) atomicAdd(p + (size_t)(2 * t) * d, neg ? 0ull - pc[t] : pc[t]);
+}
+
 // Add the FP64 value s (exact, an integer multiple of 2^-149 below 2^285)
-// to the digits of (cluster jc, dimension dim): its 53-bit significand
-// lands on three consecutive digits.
+// to the digits of (cluster jc, dimension dim): its 53-bit significand, in
+// 32-bit pieces, lands on digits idx, idx + 2 and idx + 4 (idx <= 14).
 __device__ __forceinline__ void add_f64_digits(unsigned long long* slots, int jc, int d, int dim,
                                                double s) {
   if (s == 0.0) return;
@@ -217,7 +228,8 @@ __device__ __forceinline__ void add_f64_digits(unsigned long long* slots, int jc
     mant >>= -shift;
     shift = 0;
   }
-  const int idx = shift >> 5, off = shift & 31;
+  // mant 2^off (off < 16) in 32-bit pieces on digits idx, idx + 2, idx + 4
+  const int idx = shift >> 4, off = shift & 15;
   const unsigned long long lo = mant << off;
   const unsigned long long hi = off ? mant >> (64 - off) : 0ull;
   const bool neg = (u >> 63) != 0;
@@ -225,7 +237,7 @@ __device__ __forceinline__ void add_f64_digits(unsigned long long* slots, int jc
   unsigned long long* p = slots + ((size_t)jc * kXD + idx) * d + dim;
 #pragma unroll
   for (int t = 0; t < 3; ++t)
-    if (dg[t]) atomicAdd(p + (size_t)t * d, neg ? 0ull - dg[t] : dg[t]);
+    if (dg[t]) atomicAdd(p + (size_t)(2 * t) * d, neg ? 0ull - dg[t] : dg[t]);
 }
 
 // Wave w of block b walks leaves [g0, g0 + run) of the canonical leaf
@@ -339,29 +351,22 @@ __global__ __launch_bounds__(64 * kExactWaves) void exact_leaf(
       // digit; the walk runs on the whole wave (it stages rows for every
       // lane), and only those lanes accumulate
       if (__ballot(need)) {
-        unsigned long long w0 = 0, w1 = 0, w2 = 0;
+        unsigned long long w0 = 0, w1 = 0;
         int base = -1;
         const int gl = leaf_off[jc + 1] < gend ? leaf_off[jc + 1] : gend;
         for (int g = gs; g < gl; ++g)
           walk_leaf(jc, g, [&](uint32_t u) {
             if (!need) return;
             const FixedAdd f = fixed_of(u);
-            if (base < 0) base = f.idx;        // idx <= 7: base + 2 < kXD
+            if (base < 0) base = f.idx;        // idx <= 15: base + 1 < kXD
             const bool in0 = f.idx == base, in1 = f.idx == base + 1;
-            w0 += in0 ? f.lo : 0ull;
-            w1 += in0 ? f.hi : (in1 ? f.lo : 0ull);
-            w2 += in1 ? f.hi : 0ull;
-            if (!in0 && !in1) {
-              unsigned long long* q = slots + ((size_t)jc * kXD + f.idx) * d + dim;
-              if (f.lo) atomicAdd(q, f.lo);
-              if (f.hi) atomicAdd(q + d, f.hi);
-            }
+            w0 += in0 ? f.v : 0ull;
+            w1 += in1 ? f.v : 0ull;
+            if (!in0 && !in1) add_split(slots, jc, d, dim, f.idx, (long long)f.v);
           });
         if (need && base >= 0) {
-          unsigned long long* q = slots + ((size_t)jc * kXD + base) * d + dim;
-          if (w0) atomicAdd(q, w0);
-          if (w1) atomicAdd(q + d, w1);
-          if (w2) atomicAdd(q + 2 * d, w2);
+          add_split(slots, jc, d, dim, base, (long long)w0);
+          add_split(slots, jc, d, dim, base + 1, (long long)w1);
         }
       }
       sacc = 0.0;
@@ -397,30 +402,36 @@ __global__ __launch_bounds__(64 * kExactWaves) void exact_leaf(
 // ---------------------------------------------------------------------------
 
 // Normalise the kXD digits at p (stride d) in place: digits 0..kXD-2 in
-// [0, 2^32), the top digit signed.
+// [0, 2^16), the top digit signed.  Returns the value as kQ - 1 digits of
+// 32 bits (dig) and a signed top of weight 2^(32 (kQ - 1)).
+constexpr int kQ = kXD / 2;
 __device__ __forceinline__ void normalise_digits(unsigned long long* p, int d, uint32_t* dig,
                                                  long long& top) {
   long long carry = 0;
+  uint32_t h[kXD - 1];
 #pragma unroll
   for (int s = 0; s < kXD - 1; ++s) {
     const long long v = (long long)p[(size_t)s * d] + carry;
-    dig[s] = (uint32_t)((unsigned long long)v & 0xffffffffull);
-    carry = v >> 32;                            // arithmetic shift: floor
+    h[s] = (uint32_t)((unsigned long long)v & 0xffffull);
+    carry = v >> 16;                            // arithmetic shift: floor
   }
-  top = (long long)p[(size_t)(kXD - 1) * d] + carry;
+  const long long t16 = (long long)p[(size_t)(kXD - 1) * d] + carry;
 #pragma unroll
-  for (int s = 0; s < kXD - 1; ++s) p[(size_t)s * d] = dig[s];
-  p[(size_t)(kXD - 1) * d] = (unsigned long long)top;
+  for (int s = 0; s < kXD - 1; ++s) p[(size_t)s * d] = h[s];
+  p[(size_t)(kXD - 1) * d] = (unsigned long long)t16;
+#pragma unroll
+  for (int t = 0; t < kQ - 1; ++t) dig[t] = h[2 * t] | (h[2 * t + 1] << 16);
+  top = t16 * 65536 + (long long)h[kXD - 2];    // |V| < 2^308: no overflow
 }
 
-// RN(V / cnt) for V = sum_s dig[s] 2^(32 s - 149) + top 2^(32 (kXD-1) - 149),
+// RN(V / cnt) for V = sum_s dig[s] 2^(32 s - 149) + top 2^(32 (kQ-1) - 149),
 // cnt >= 1: the magnitude's long division by cnt with three 32-bit guard
 // digits, then 53 bits, a round bit and a sticky bit (remainder included).
 // Every mean of FP32 values lies in [2^-180, 2^128]: a normal double.
 __device__ __forceinline__ double exact_quotient(const uint32_t* dig, long long top,
                                                  int cnt) {
   constexpr int G = 3;                          // guard digits
-  constexpr int W = kXD + G;
+  constexpr int W = kQ + G;
   uint32_t a[W];
   const bool neg = top < 0;
   // magnitude digits (two's complement negation when negative)
@@ -428,7 +439,7 @@ __device__ __forceinline__ double exact_quotient(const uint32_t* dig, long long 
   for (int s = 0; s < G; ++s) a[s] = 0u;
   unsigned long long borrow = neg ? 1ull : 0ull;   // ~x + 1
 #pragma unroll
-  for (int s = 0; s < kXD - 1; ++s) {
+  for (int s = 0; s < kQ - 1; ++s) {
     const unsigned long long v = (unsigned long long)(neg ? ~dig[s] : dig[s]) + borrow;
     a[G + s] = (uint32_t)v;
     borrow = v >> 32;
@@ -483,6 +494,7 @@ __global__ __launch_bounds__(256) void exact_finalize(
     float* __restrict__ drift, int* __restrict__ dirty, IterCtl ctl,
     const int* __restrict__ conv, int iter) {
   __shared__ double mean[kMaxD];
+  __shared__ unsigned long long sdig[kXD * kMaxD];
   const int cv = *conv;
   const int j = blockIdx.x;
   const int cntj = nj[j];
@@ -494,14 +506,21 @@ __global__ __launch_bounds__(256) void exact_finalize(
     if (drift && threadIdx.x == 0) drift[j] = 0.0f;     // centroid unchanged
     return;
   }
-  // normalise and divide; each thread keeps its dimensions' means
+  // the cluster's kXD x d digits (contiguous) through LDS: loaded and
+  // stored back by the whole workgroup; normalise and divide per dimension
   unsigned long long* base = slots + (size_t)j * kXD * d;
+  const int nd = kXD * d;
+  stage_batched<8, unsigned long long>(
+      nd, [&](int e) { return base[e]; }, [&](int e, unsigned long long v) { sdig[e] = v; });
+  __syncthreads();
   for (int dim = threadIdx.x; dim < d; dim += blockDim.x) {
-    uint32_t dig[kXD - 1];
+    uint32_t dig[kQ - 1];
     long long top;
-    normalise_digits(base + dim, d, dig, top);
+    normalise_digits(sdig + dim, d, dig, top);
     mean[dim] = cntj > 0 ? exact_quotient(dig, top, cntj) : 0.0;
   }
+  __syncthreads();
+  for (int e = threadIdx.x; e < nd; e += blockDim.x) base[e] = sdig[e];
   write_centroid(j, k, d, cntj, [&](int dim) { return mean[dim]; }, C_prev, C_out, CT,
                  Cm2, cn, dp, Chi, Clo, dpb, drift, dirty);
 }
