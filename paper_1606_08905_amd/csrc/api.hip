@@ -611,6 +611,7 @@ static knor_status fit_impl(const void* X, knor_dtype dt, int64_t n, int d,
   Prof* pp = prof.on ? &prof : nullptr;
   const double tol_n = tol * (double)n;
   int hconv = kNotConverged;
+  int ctl_delta_only = 0;
   for (int t = 0; t < max_iters; ++t) {
     prof.iter = t;
     unsigned long long* row = ctr + (size_t)t * ROW_STRIDE;
@@ -699,6 +700,7 @@ static knor_status fit_impl(const void* X, knor_dtype dt, int64_t n, int d,
     ctl.row = row; ctl.conv = conv; ctl.iter = t; ctl.tol_n = tol_n;
     ctl.segmented = seg; ctl.n = n;
     if (seg) { ctl.list = list; ctl.seg_cnt = seg_cnt; ctl.nseg = nseg; }
+    ctl.delta_only = ctl_delta_only;
     if (exact)
       HIPCHK(launch_update_exact(plan, xplan, X, dt, labels_out, C_out, C_out, nullptr, &ops,
                                  mti ? drift : nullptr, dirty, &ctl, s, pp));
@@ -711,9 +713,16 @@ static knor_status fit_impl(const void* X, knor_dtype dt, int64_t n, int d,
       prof.end();
     }
     if ((t + 1) % o.poll_every == 0 || t + 1 == max_iters) {
+      unsigned long long hch = 0;
       HIPCHK(hipMemcpyAsync(&hconv, conv, sizeof(int), hipMemcpyDeviceToHost, s));
+      if (exact && !ctl_delta_only)
+        HIPCHK(hipMemcpyAsync(&hch, row + ROW_CHANGED, sizeof(hch), hipMemcpyDeviceToHost, s));
       HIPCHK(hipStreamSynchronize(s));
       if (hconv != kNotConverged) break;
+      // the exact update: once few labels change, stop launching the full
+      // pass (both modes give the same centroids; this only saves launches)
+      if (exact && !ctl_delta_only && hch <= (unsigned long long)xplan.delta_max)
+        ctl_delta_only = 1;
     }
   }
 

@@ -368,6 +368,7 @@ struct IterCtl {
   const int* list = nullptr;
   const int* seg_cnt = nullptr;
   int nseg = 0;
+  int delta_only = 0;                 // exact update: moved points only
 };
 
 hipError_t launch_update(const UpdatePlan& p, const void* X, knor_dtype dt,

@@ -11,11 +11,17 @@
 // a cluster's values in one dimension is kept as kXD = 20 signed 64-bit
 // digits of weight 2^(16 s) in those units (carry-save: a digit may leave
 // [0, 2^16) between normalisations).  A value adds m << (sh mod 16), below
-// 2^39, to digit sh/16 with the value's sign: one add per value in the delta
-// mode, which moves at most 2^18 points per iteration (below 2^57 per digit).
-// The full pass adds pieces below 2^32, at most one per digit per value or
-// per flushed sum, so a digit stays below n 2^32 < 2^63.  Each update
-// normalises the dirty clusters' digits.
+// 2^39, to digit sh/16 with the value's sign: one add per value when fewer
+// than 2^23 points move in an iteration (below 2^62 per digit), else two
+// pieces below 2^32 on digits sh/16 and sh/16 + 2.  The full pass adds
+// pieces below 2^32, at most one per digit per value or per flushed sum, so
+// a digit stays below n 2^32 < 2^63.  Each update normalises the dirty
+// clusters' digits.
+//
+// The mode is chosen on the device each iteration (the full pass is gated
+// by a word the delta kernel writes); once the caller has seen an iteration
+// with few changes it stops launching the full pass, and every later
+// iteration moves points (both modes give the same centroids).
 //
 // Per iteration of a fit (labels of the previous update in `prev`):
 //   exact_delta    counts this iteration's changed labels and chooses the
@@ -92,6 +98,21 @@ __device__ __forceinline__ FixedAdd fixed_of(uint32_t u) {
   return f;
 }
 
+// Add the signed amount w (|w| < 2^62) to digit idx of (cluster jc,
+// dimension dim) in two pieces below 2^32, on digits idx and idx + 2 (so
+// that no digit takes more than one piece per value or flush).
+__device__ __forceinline__ void add_split(unsigned long long* slots, int jc, int d, int dim,
+                                          int idx, long long w) {
+  if (w == 0) return;
+  const bool neg = w < 0;
+  const unsigned long long m = neg ? 0ull - (unsigned long long)w : (unsigned long long)w;
+  unsigned long long* p = slots + ((size_t)jc * kXD + idx) * d + dim;
+  const unsigned long long pc[2] = {m & 0xffffffffull, m >> 32};
+#pragma unroll
+  for (int t = 0; t < 2; ++t)
+    if (pc[t] && idx + 2 * t < kXD) atomicAdd(p + (size_t)(2 * t) * d, neg ? 0ull - pc[t] : pc[t]);
+}
+
 // ---------------------------------------------------------------------------
 // mode choice, delta moves, prev labels
 // ---------------------------------------------------------------------------
@@ -118,14 +139,17 @@ __global__ __launch_bounds__(256) void exact_delta(
     int32_t* __restrict__ prev, int k, int d, unsigned long long* __restrict__ slots,
     int* __restrict__ nj, const int* __restrict__ dirty,
     const unsigned long long* __restrict__ row, int* __restrict__ gate, int delta_max,
-    const int* __restrict__ conv, int iter) {
+    int delta_only, const int* __restrict__ conv, int iter) {
   const int cv = *conv;
   const int lane = threadIdx.x & 63;
   // this iteration's changed labels, from the spread counter slots
   unsigned long long c =
       lane < kChgSlots ? row[(SLOT_CHANGED * kChgSlots + lane) * kSlotStride] : 0ull;
   for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o);
-  const bool full = iter == 0 || c > (unsigned long long)delta_max;
+  const bool full = iter == 0 || (!delta_only && c > (unsigned long long)delta_max);
+  // with the full pass not launched, many moves are possible: a digit then
+  // takes two pieces below 2^32 per value instead of one add below 2^39
+  const bool split = c >= (1ull << 23);
   if (blockIdx.x == 0 && threadIdx.x == 0)
     *gate = cv < iter ? cv : (full ? kNotConverged : -1);
   if (cv < iter) return;
@@ -185,7 +209,11 @@ __global__ __launch_bounds__(256) void exact_delta(
         }
         for (int dim = dl; dim < d; dim += dstep) {
           const FixedAdd f = fixed_of(f32_bits<T>(X[(size_t)pq * d + dim]));
-          if (f.v) {
+          if (!f.v) continue;
+          if (split) {
+            add_split(slots, na, d, dim, f.idx, (long long)f.v);
+            if (oa >= 0) add_split(slots, oa, d, dim, f.idx, -(long long)f.v);
+          } else {
             atomicAdd(slots + ((size_t)na * kXD + f.idx) * d + dim, f.v);
             if (oa >= 0) atomicAdd(slots + ((size_t)oa * kXD + f.idx) * d + dim, 0ull - f.v);
           }
@@ -198,21 +226,6 @@ __global__ __launch_bounds__(256) void exact_delta(
 // ---------------------------------------------------------------------------
 // full pass: runs of leaves
 // ---------------------------------------------------------------------------
-
-// Add the signed amount w (|w| < 2^62) to digit idx of (cluster jc,
-// dimension dim) in two pieces below 2^32, on digits idx and idx + 2 (so
-// that no digit takes more than one piece per value or flush).
-__device__ __forceinline__ void add_split(unsigned long long* slots, int jc, int d, int dim,
-                                          int idx, long long w) {
-  if (w == 0) return;
-  const bool neg = w < 0;
-  const unsigned long long m = neg ? 0ull - (unsigned long long)w : (unsigned long long)w;
-  unsigned long long* p = slots + ((size_t)jc * kXD + idx) * d + dim;
-  const unsigned long long pc[2] = {m & 0xffffffffull, m >> 32};
-#pragma unroll
-  for (int t = 0; t < 2; ++t)
-    if (pc[t] && idx + 2 * t < kXD) atomicAdd(p + (size_t)(2 * t) * d, neg ? 0ull - pc[t] : pc[t]);
-}
 
 // Add the FP64 value s (exact, an integer multiple of 2^-149 below 2^285)
 // to the digits of (cluster jc, dimension dim): its 53-bit significand, in
@@ -552,17 +565,22 @@ hipError_t launch_update_exact(const UpdatePlan& p, const ExactPlan& xp, const v
     int64_t blocks = ctl->list ? ctl->nseg : (p.n + kSeg - 1) / kSeg;
     if (blocks > (1 << 20)) blocks = 1 << 20;
     if (blocks < 1) blocks = 1;
+    const int donly = ctl->delta_only && iter > 0 ? 1 : 0;
     if (dt == KNOR_F32)
       hipLaunchKernelGGL(exact_delta<float>, dim3((unsigned)blocks), dim3(256), 0, s,
                          (const float*)X, src, labels, xp.prev, k, d, xp.slots, p.nj, dirty,
-                         ctl->row, xp.gate, xp.delta_max, conv, iter);
+                         ctl->row, xp.gate, xp.delta_max, donly, conv, iter);
     else
       hipLaunchKernelGGL(exact_delta<uint16_t>, dim3((unsigned)blocks), dim3(256), 0, s,
                          (const uint16_t*)X, src, labels, xp.prev, k, d, xp.slots, p.nj,
-                         dirty, ctl->row, xp.gate, xp.delta_max, conv, iter);
+                         dirty, ctl->row, xp.gate, xp.delta_max, donly, conv, iter);
     gate = xp.gate;
   }
-  if (hipError_t e = launch_sort(p, labels, dirty, gate, iter, s, one_shot ? 0 : 1)) return e;
+  // the full pass: gated on the device, or not launched at all once the
+  // caller knows that only moved points remain (delta_only)
+  const bool full_pass = one_shot || !(ctl->delta_only && iter > 0);
+  if (full_pass)
+    if (hipError_t e = launch_sort(p, labels, dirty, gate, iter, s, one_shot ? 0 : 1)) return e;
   if (prof) { prof->end(); prof->begin(KNOR_PROF_LEAF); }
   // longer runs at large n: fewer flushes of partial digits (global adds)
   int64_t run = p.max_leaves / kExactWavesTarget;
@@ -571,7 +589,9 @@ hipError_t launch_update_exact(const UpdatePlan& p, const ExactPlan& xp, const v
   const int64_t lblocks = (waves + kExactWaves - 1) / kExactWaves;
   const size_t esz = dt == KNOR_F32 ? 4 : 2;
   const int vec = (int)(((size_t)d * esz) % 16 == 0 && ((uintptr_t)X & 15) == 0);
-  if (dt == KNOR_F32)
+  if (!full_pass) {
+    // nothing to launch
+  } else if (dt == KNOR_F32)
     hipLaunchKernelGGL(exact_leaf<float>, dim3((unsigned)lblocks), dim3(64 * kExactWaves), 0, s,
                        (const float*)X, d, p.perm, p.nj, p.off, p.leaf_off, k, dirty, xp.slots,
                        gate, iter, vec, (int)run);

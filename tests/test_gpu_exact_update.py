@@ -170,6 +170,22 @@ def test_exact_fit_shapes(n, d, k, seed, dtype):
     _fit_exact_compare(X, dtype, C0, k, 15, True)
 
 
+@pytest.mark.parametrize("poll_every", [1, 3])
+def test_exact_fit_delta_only_after_poll(poll_every):
+    """The host stops launching the full pass at the first convergence poll
+    that sees few changes; centroids and labels are unchanged."""
+    knor = _knor()
+    w = workloads.config(2, n=100000, seed=5)
+    ref = oracle.mti_fit(w.x64(), w.C0, 40, history=True, exact_mean=True)
+    C, lab, st = knor.fit(_dev(w.X, "f32"), w.k, C0=_dev(w.C0, "f64"), max_iters=40,
+                          history=True, update="exact", poll_every=poll_every)
+    assert st["iters"] == ref.iters
+    hist = st["label_history"].cpu().numpy()
+    for t in range(ref.iters):
+        assert (hist[t] == ref.label_hist[t]).all(), f"iteration {t}"
+    assert (C.cpu().numpy() == ref.C).all()
+
+
 def test_exact_fit_mixed_magnitudes():
     """Coordinates spanning 40 decades (tiny ones near FP32's subnormal
     range) move between clusters in delta mode."""
