@@ -68,10 +68,15 @@ void exact_plan_init(ExactPlan* p, int64_t n, int k, int d, void* ws) {
   p->prev = (int32_t*)c;
   c += al256((size_t)n * sizeof(int32_t));
   p->gate = (int*)c;
-  // each moved point costs 2 d digit adds (old and new cluster); the limit
-  // leaves room for twice that
-  const int dm = kDeltaAtomics / (4 * d);
-  p->delta_max = dm < 256 ? 256 : dm;
+  // each moved point costs 2 d digit adds (old and new cluster) at about
+  // 15 G adds/s, while the full pass re-sums every member of the dirty
+  // clusters at about 10^12 values/s: moving points pays up to about n / 128
+  // changes, and at least up to kDeltaAtomics / (4 d); at most 2^22 (single
+  // adds stay below 2^62 per digit)
+  int64_t dm = kDeltaAtomics / (4 * d);
+  if (n / 128 > dm) dm = n / 128;
+  if (dm > (1 << 22)) dm = 1 << 22;
+  p->delta_max = dm < 256 ? 256 : (int)dm;
 }
 
 template <typename T>

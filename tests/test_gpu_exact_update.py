@@ -33,9 +33,9 @@ def _print_case(**kw):
     print("CASE", kw, flush=True)
 
 
-def _delta_max(d):
+def _delta_max(n, d):
     # changed labels up to which the library moves points one by one
-    return max(256, (1 << 20) // (4 * d))
+    return max(256, min(1 << 22, max((1 << 20) // (4 * d), n // 128)))
 
 
 # ---------------------------------------------------------------------------
@@ -150,7 +150,7 @@ def test_exact_fit_config2_modes(prune):
     w = workloads.config(2, n=500000, seed=1)
     _print_case(test="exact-fit-config2", prune=prune)
     st, ref = _fit_exact_compare(w.X, w.dtype, w.C0, w.k, 60, prune)
-    lim = _delta_max(w.X.shape[1])
+    lim = _delta_max(*w.X.shape)
     ch = ref.changed.tolist()
     assert any(c > lim for c in ch[1:]) and any(0 < c <= lim for c in ch[1:]), ch
 
