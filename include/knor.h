@@ -299,7 +299,9 @@ knor_status knor_mlp_propose(const float* params, int32_t d, int32_t h,
 /* Human-readable name of a status code (static storage). */
 const char* knor_status_string(knor_status s);
 
-/* Library version as major*10000 + minor*100 + patch. */
+/* Library version as major*10000 + minor*100 + patch.  0.2.0 added
+ * knor_opts.update (so sizeof(knor_opts), which struct_size must equal,
+ * changed). */
 int32_t knor_version(void);
 
 #ifdef __cplusplus

@@ -877,7 +877,7 @@ const char* knor_status_string(knor_status s) {
   return "unknown status";
 }
 
-int32_t knor_version(void) { return 100; }
+int32_t knor_version(void) { return 200; }
 
 knor_status knor_fit(const void* X, knor_dtype dt, int64_t n, int32_t d,
                      int32_t k, knor_init init, const double* C_init,
