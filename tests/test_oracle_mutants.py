@@ -53,11 +53,20 @@ MUTANTS = [
      "for (int i = 0; i < d; ++i) c[i] = 0.0;"),
     ("clause2-no-half", "0.5 * CC[(size_t)a * k + j] * (1.0 - ETA)) continue;\n    if",
      "1.0 * CC[(size_t)a * k + j] * (1.0 - ETA)) continue;\n    if"),
+    ("objective-wrong-centroid",
+     "D[p] = oracle_dist2(X + (size_t)p * d, C + (size_t)labels[p] * d, d);",
+     "D[p] = oracle_dist2(X + (size_t)p * d, C, d);"),
+    ("objective-plain-order",
+     "double s = oracle_canonical_sum(D, n);\n  free(D);",
+     "double s = 0.0;\n  for (int64_t p = 0; p < n; ++p) s += D[p];\n  free(D);"),
 ]
 
 CHECKS = [
     (pins.test_golden_2d_integer_assign_update_fit, {}),
     (pins.test_golden_1d_threshold, {}),
+    (pins.test_objective_golden_2d_integer, {}),
+    (pins.test_objective_summation_order_golden, {}),
+    (pins.test_objective_bruteforce_integer, {"seed": 0}),
     (pins.test_golden_canonical_order, {}),
     (pins.test_dist2_integer_exact, {}),
     (pins.test_tie_lowest_index, {}),

@@ -48,6 +48,56 @@ def test_golden_2d_integer_assign_update_fit(orc):
         assert r.objective.tolist() == g["objective"]
 
 
+def test_objective_golden_2d_integer(orc):
+    """The objective J = sum_p D(x_p, c_label(p)) on the hand-derived fixture:
+    16 at (C0, iteration-0 labels), 9 at the converged state, and 106 when
+    every point is charged to centroid 1 (the second column of the
+    fixture's iteration-0 distance table)."""
+    g = _gold("lloyd_2d_integer.json")
+    X = np.array(g["X"], float)
+    C0 = np.array(g["C0"], float)
+    assert orc.objective(X, C0, np.array(g["iter0_labels"])) == g["objective"][0] == 16
+    Cf = np.array(g["final_centroids"], float)
+    assert orc.objective(X, Cf, np.array(g["final_labels"])) == g["objective"][-1] == 9
+    col1 = sum(row[1] for row in g["iter0_dist2_to_each"])
+    assert col1 == 106
+    assert orc.objective(X, C0, np.ones(5, np.int32)) == col1
+
+
+def test_objective_summation_order_golden(orc):
+    """The objective sums its n terms in the fixed canonical order: the
+    193-term fixture (2^53 at member 0, 1 at members 128 and 192) gives
+    2^53 + 2, where a left-to-right sum would give 2^53.  The terms are
+    realised as squared distances of integer points to the origin."""
+    g = _gold("canonical_order_sum.json")
+    m = g["m"]
+    X = np.zeros((m, 2))
+    X[0] = (2.0 ** 26, 2.0 ** 26)                 # D = 2^52 + 2^52 = 2^53
+    X[128] = (1.0, 0.0)
+    X[192] = (0.0, 1.0)
+    C = np.array([[0.0, 0.0], [7.0, 7.0]])
+    lab = np.zeros(m, np.int32)
+    assert orc.objective(X, C, lab) == g["canonical_sum"] != g["sequential_sum"]
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_objective_bruteforce_integer(orc, seed):
+    """Integer points, centroids and arbitrary labels: every FP64 step is
+    exact, so the objective equals the exact integer sum, computed here in
+    Python integers term by term."""
+    rng = np.random.default_rng(100 + seed)
+    n, d, k = 301, 3, 5
+    X = rng.integers(-40, 41, size=(n, d))
+    C = rng.integers(-40, 41, size=(k, d))
+    lab = rng.integers(0, k, size=n).astype(np.int32)
+    exact = 0
+    for p in range(n):
+        for i in range(d):
+            t = int(X[p, i]) - int(C[lab[p], i])
+            exact += t * t
+    assert orc.objective(X.astype(float), C.astype(float), lab) == float(exact)
+
+
 def test_golden_1d_threshold(orc):
     g = _gold("lloyd_1d_threshold.json")
     X = np.array(g["X"], float)
