@@ -1,24 +1,38 @@
 #!/usr/bin/env python3
-"""Benchmark of the k-means hot path on one MI355X.
+"""Benchmark of the k-means hot path on one MI355X: one JSON line.
 
-One step = one complete fit (Lloyd's with MTI pruning, every iteration until
-no label changes or max_iters) of the workload below, inputs resident in HBM.
-value = Lloyd iterations per second over the timed steps.
+One step = one complete fit (every Lloyd iteration until no label changes or
+max_iters) of the selected workload, inputs resident in HBM.  value = Lloyd
+iterations per second over the timed steps.
 
-Workload (default): n = 1,000,000 points, d = 32, k = 100, FP32 points from a
-100-component Gaussian mixture (means U[-20,20]^d, sigma U[0.5,2], Dirichlet
-weights), k-means++ seeding, max_iters = 100, tol = 0.
+Workloads (--config, seeded synthetic Gaussian mixtures, see workloads/):
+  5 (default, the largest single-GPU configuration): learned candidate
+    proposal, n=1e7, d=32, k=4096, FP32, 40 iterations, MTI + MLP
+    32-256-256-4096 trained on the labels of MTI iterations 1-5, top-16
+    candidates, certificate, MTI scan for the rest;
+  1: plain Lloyd's, FP64, n=1e4, d=16, k=10, 50 iterations;
+  2: MTI, FP32, n=1e6, d=32, k=100, k-means++ seeding, 100 iterations;
+  3: mixed precision, BF16 points, n=2e7, d=64, k=256, 30 iterations;
+  4: 64 batched restarts (uneven n, d, k), FP32, 50 iterations each.
 
-Also reported, measured in the same run:
+Every line also reports, measured in the same run:
+  baselines     the same workload on this GPU without the form (plain FP32
+                Lloyd's; for 3 and 5 also FP32 + MTI; for 4 sequential fits
+                with the same options), with the speedups
   roofline      for the kernel group with the largest GPU time, from HIP
                 events on the launch stream over the timed steps
-  cpu_baseline  the FP64 oracle (MTI variant, OpenMP) timed on the host on
-                the same workload and C0; its labels are compared with the
-                GPU's at every iteration ("exact" in the output)
+  exact         labels of a row sample at every iteration equal the FP64
+                oracle's assignment under that iteration's centroids, and the
+                centroids of the first and last update equal the oracle's
+                update of all rows (per-iteration centroids come from the
+                fit's centroid history)
+  cpu_baseline  the FP64 oracle timed on this host (whole fit for 1 and 2,
+                else one iteration's assignment of a row sample, scaled)
 """
 import argparse
 import json
 import os
+import subprocess
 import sys
 import time
 
@@ -30,13 +44,13 @@ PEAK_BF16_MFMA = 2516.6e12
 PEAK_HBM = 8.0e12              # bytes/s
 PEAK_FP64_VALU = 78.6e12
 
-# HBM bytes per launch of a kernel group on the headline workload, from
-# rocprofv3 FETCH_SIZE and WRITE_SIZE runs (medians over launches), each scaled
-# by what the counter reads for a 2 GiB device copy (fetch x2.0, write x1.0).
-# A figure is reported only for that workload and only while the kernel
-# sources it was measured on are unchanged; the extended forms report null.
+# HBM bytes per launch of a kernel group on one workload, from rocprofv3
+# FETCH_SIZE and WRITE_SIZE runs (medians over launches), each scaled by what
+# the counter reads for a 2 GiB device copy (fetch x2.0, write x1.0).  A
+# figure is reported only for its workload and only while the kernel sources
+# it was measured on are unchanged.
 MEASURED_TRAFFIC = {
-    "assign_list": {
+    (2, "assign_list"): {
         "bytes": (48329.6 + 7175.5) * 1024,
         "sources": {
             "tile_f32.hip": "2612d89d6dc47fbd775b81bd9ce49294ad3a4d247af1c3305ac012019ea8ca94",
@@ -47,10 +61,125 @@ MEASURED_TRAFFIC = {
     },
 }
 
+# iterations whose dominant-group launches are timed inside the timed region
+PROFILE_EVERY = 10
 
-def measured_traffic(group):
+METRIC = ("Lloyd iters/s and point·centroid dists/s (% MFMA peak) "
+          "at exact assignments")
+
+WORKLOAD_NAMES = {
+    1: "plain Lloyd's: n=1e4 d=16 k=10 f64 Gaussian mixture (10 comps), first k of a "
+       "seeded shuffle, 50 iters, tol=0",
+    2: "MTI: n=1e6 d=32 k=100 f32 Gaussian mixture (100 comps, Dirichlet weights), "
+       "k-means++ seeding, 100 iters, tol=0",
+    3: "mixed precision: n=2e7 d=64 k=256 bf16 points, 95% mixture (256 comps) + 5% "
+       "uniform outliers, k random rows, 30 iters, MTI, BF16 MFMA + FP64 recheck",
+    4: "batched restarts: 64 instances, n log-uniform in [1e4, 2e6], d in {8,16,32,64}, "
+       "k in 8..512, f32, k random rows, 50 iters each, MTI, tuned tile schedules",
+    5: "learned proposal: n=1e7 d=32 k=4096 f32 Gaussian mixture (4096 comps, "
+       "mu~N(0,100I), sigma~U[0.5,3]), k random rows, 40 iters, MTI + MLP "
+       "32-256-256-4096 (BF16 operands, FP32 sums) trained on the labels of MTI "
+       "iterations 1-5, top-16 candidates, certificate, MTI scan otherwise",
+}
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--config", type=int, default=5, choices=[1, 2, 3, 4, 5])
+    ap.add_argument("--update", default="canonical", choices=["canonical", "exact"],
+                    help="centroid update of the measured fits")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-exact", action="store_true",
+                    help="skip the oracle comparison (profiling runs)")
+    ap.add_argument("--no-baselines", action="store_true",
+                    help="skip the comparison fits (profiling runs)")
+    ap.add_argument("--exact-rows", type=int, default=20000,
+                    help="rows whose labels are compared with the oracle per iteration")
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="also run one device-to-device copy of this many MiB "
+                         "before the timed region (a known-size kernel for "
+                         "scaling HBM byte counters)")
+    return ap.parse_args()
+
+
+def log(msg):
+    print("# " + msg, file=sys.stderr, flush=True)
+
+
+# ---------------------------------------------------------------------------
+# algorithmic work of the kernel groups
+# ---------------------------------------------------------------------------
+
+MLP_H = 256
+MLP_BATCH = 4096
+
+
+def group_work(g, w, sx, ctr, iters, its, train_iters=5, train_batches=16):
+    """Algorithmic work of kernel group g summed over the iterations `its` of
+    one fit, and the group's launches among them: (amount, launches, unit,
+    bound, peak).  ctr: per-iteration counters (iters x 8)."""
+    n, d, k = w.n, w.d, w.k
+    its = [t for t in its if t < iters]
+    after0 = [t for t in its if t >= 1]
+    mfma_peak = PEAK_BF16_MFMA if w.dtype == "bf16" else PEAK_FP32_MFMA
+    if g == 0:     # dense tile: 2 d flops per point-centroid pair
+        at0 = [t for t in its if t == 0]
+        return (2.0 * d * k * sum(int(ctr[t, 1]) for t in at0), len(at0),
+                "TFLOP/s", "mfma", mfma_peak)
+    if g == 1:     # survivor tile
+        return (2.0 * d * k * sum(int(ctr[t, 1]) for t in after0), len(after0),
+                "TFLOP/s", "mfma", mfma_peak)
+    if g == 2:     # FP64 recheck: subtract, multiply, add per (point, centroid, dim)
+        rech = sum(int(ctr[t, 4]) for t in its)
+        return 3.0 * d * k * rech, len(its), "TFLOP/s", "alu", PEAK_FP64_VALU
+    if g == 3:     # filter: label, bound in/out, survivor index; rows tightened
+        tot = 0.0
+        for t in after0:
+            pa = int(ctr[t, 2])
+            tot += 12.0 * n + (n - pa) * (d * sx) + 4.0 * int(ctr[t, 1])
+        return tot, len(after0), "GB/s", "hbm", PEAK_HBM
+    if g == 4:     # sort: labels read twice, perm written, block counts
+        return (12.0 * n) * len(its), len(its), "GB/s", "hbm", PEAK_HBM
+    if g == 5:     # leaf sums: every row gathered once + perm + leaf sums out
+        per_iter = n * d * sx + 4.0 * n + (n / 64.0 + k) * d * 8.0
+        return per_iter * len(its), len(its), "GB/s", "hbm", PEAK_HBM
+    if g == 8:     # MLP on the BF16 matrix cores: forward of every query, and
+        # training (forward + two backward products ~ 3x forward per row)
+        fwd = 2.0 * (d * MLP_H + MLP_H * MLP_H + MLP_H * k)
+        tot, launches = 0.0, 0
+        for t in its:
+            q = int(ctr[t, 6])
+            tot += fwd * q
+            if 1 <= t <= train_iters:
+                tot += 3.0 * fwd * MLP_BATCH * train_batches
+            if q or 1 <= t <= train_iters:
+                launches += 1
+        return tot, launches, "TFLOP/s", "mfma", PEAK_BF16_MFMA
+    return None
+
+
+def roofline(knor, g, ms, la, work, traffic, fits=1):
+    """Roofline entry of group g: its algorithmic work over the GPU time the
+    HIP events measured (ms, la: summed over `fits` fits, each timed over the
+    iterations `work` covers), i.e. work per launch / mean launch time."""
+    if work is None or not la[g] or ms[g] <= 0.0:
+        return None
+    amount, launches, unit, bound, peak = work
+    ach = amount * fits / (ms[g] / 1e3)
+    scale = 1e12 if unit == "TFLOP/s" else 1e9
+    return {"kernel": knor.PROF_GROUPS[g], "bound": bound,
+            "achieved": round(ach / scale, 3), "peak": round(peak / scale, 1),
+            "unit": unit, "frac": round(ach / peak, 4),
+            "traffic": traffic, "us_per_launch": round(ms[g] / la[g] * 1e3, 3),
+            "work_per_launch": amount * fits / la[g]}
+
+
+def measured_traffic(cfg, group):
     import hashlib
-    m = MEASURED_TRAFFIC.get(group)
+    m = MEASURED_TRAFFIC.get((cfg, group))
     if m is None:
         return None
     csrc = os.path.join(ROOT, "paper_1606_08905_amd", "csrc")
@@ -61,109 +190,336 @@ def measured_traffic(group):
     return m["bytes"]
 
 
-# iterations whose dominant-group launches are timed inside the timed region
-PROFILE_EVERY = 10
+# ---------------------------------------------------------------------------
+# timing
+# ---------------------------------------------------------------------------
 
-METRIC = ("Lloyd iters/s and point·centroid dists/s (% MFMA peak) "
-          "at exact assignments")
-
-
-def parse():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-iters", type=int, default=0,
-                    help="oracle iterations for the CPU baseline (0 = whole fit)")
-    ap.add_argument("--form", default="headline",
-                    choices=["headline", "mixed", "batched", "learned", "incremental"],
-                    help="headline: the benchmark workload (default); the "
-                         "others measure one extended form on its own "
-                         "workload against plain FP32 Lloyd's on this GPU")
-    ap.add_argument("--config", type=int, default=2, choices=[2, 3, 5],
-                    help="--form incremental: workload (2 = headline, 3 = mixed "
-                         "precision, 5 = large k)")
-    ap.add_argument("--copy-calibration-mib", type=int, default=0,
-                    help="also run one device-to-device copy of this many MiB "
-                         "before the timed region (a known-size kernel for "
-                         "scaling HBM byte counters)")
-    return ap.parse_args()
-
-
-def group_work(g, n, d, k, sx, ctr, iters, mfma_peak=PEAK_FP32_MFMA, its=None):
-    """Algorithmic work of kernel group g summed over the iterations `its` of
-    one fit (default: all), and the group's launches among them:
-    (amount, launches, unit, bound, peak).  ctr: per-iteration counters
-    (iters x 8).  The dense tile runs at iteration 0; the survivor tile and
-    the filter at iterations >= 1; the other groups every iteration."""
-    its = list(range(iters)) if its is None else [t for t in its if t < iters]
-    after0 = [t for t in its if t >= 1]
-    if g == 0:     # dense tile: 2 d flops per point-centroid pair
-        at0 = [t for t in its if t == 0]
-        return (2.0 * d * k * sum(int(ctr[t, 1]) for t in at0), len(at0),
-                "TFLOP/s", "mfma", mfma_peak)
-    if g == 1:
-        return (2.0 * d * k * sum(int(ctr[t, 1]) for t in after0), len(after0),
-                "TFLOP/s", "mfma", mfma_peak)
-    if g == 2:     # FP64 recheck: subtract, multiply, add per (point, centroid, dim)
-        rech = sum(int(ctr[t, 4]) for t in its)
-        return 3.0 * d * k * rech, len(its), "TFLOP/s", "alu", PEAK_FP64_VALU
-    if g == 5:     # leaf sums: every row gathered once + perm + leaf sums out
-        per_iter = n * d * sx + 4.0 * n + (n / 64.0 + k) * d * 8.0
-        return per_iter * len(its), len(its), "GB/s", "hbm", PEAK_HBM
-    if g == 3:     # filter: label, bound in/out, survivor index; rows tightened
-        tot = 0.0
-        for t in after0:
-            pa = int(ctr[t, 2])
-            tot += 12.0 * n + (n - pa) * (d * sx) + 4.0 * int(ctr[t, 1])
-        return tot, len(after0), "GB/s", "hbm", PEAK_HBM
-    if g == 4:     # sort: labels read twice, perm written, block counts
-        return (12.0 * n) * len(its), len(its), "GB/s", "hbm", PEAK_HBM
-    return None
-
-
-def roofline_of(knor, ms, la, g, steps, work):
-    """Roofline entry of kernel group g from event times (ms, launches summed
-    over `steps` fits) and its algorithmic work per fit (extended forms: no
-    measured traffic for their workloads)."""
-    if work is None or not la[g]:
-        return None
-    amount, launches, unit, bound, peak = work
-    per_launch = amount / max(1, launches)
-    sec = ms[g] / la[g] / 1e3
-    scale = 1e12 if unit == "TFLOP/s" else 1e9
-    return {"kernel": knor.PROF_GROUPS[g], "bound": bound,
-            "achieved": round(per_launch / sec / scale, 3), "peak": round(peak / scale, 1),
-            "unit": unit, "frac": round(per_launch / sec / peak, 4),
-            "traffic": None,
-            "us_per_launch": round(sec * 1e6, 3)}
-
-
-def cpu_sample_baseline(oracle, w, X64, C0, gpu_labels0, frac, rng_seed=0):
-    """Bounded CPU baseline for the large forms: the oracle's assignment of a
-    random row sample at C0 (one iteration's dominant work), timed and scaled
-    to the full n; its labels are compared with the GPU's iteration-0 labels
-    on the same rows."""
-    import numpy as np
-    rng = np.random.default_rng(rng_seed)
-    m = max(1000, int(frac * w.n))
-    rows = np.sort(rng.choice(w.n, size=m, replace=False))
-    Xs = X64(rows)
+def timed(fn, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
     t = time.perf_counter()
-    lab, _ = oracle.assign(Xs, C0)
-    dt = time.perf_counter() - t
-    sec_per_iter = dt * w.n / m
-    return ({"value": round(1.0 / sec_per_iter, 4), "unit": "iters/s",
-             "cores": oracle.num_threads(), "kind": "oracle",
-             "sample": f"FP64 oracle assignment of {m} random rows at C0 "
-                       f"(one iteration's assignment), scaled to n={w.n}"},
-            bool((lab == gpu_labels0[rows]).all()))
+    outs = [fn() for _ in range(steps)]
+    torch.cuda.synchronize()
+    return outs, (time.perf_counter() - t) / steps
 
 
-def run_form(a):
-    """One extended form on its own workload; one JSON line."""
+def measure(knor, fit, steps, warmup):
+    """Warm-up fits, one untimed calibration fit with every kernel group under
+    HIP events (the breakdown, and which group dominates), then `steps` timed
+    fits in which the dominant group's launches of every PROFILE_EVERY-th
+    iteration are bracketed by events."""
     import numpy as np
+    import torch
+    for _ in range(warmup):
+        fit()
+    torch.cuda.synchronize()
+    cal_ms = np.zeros(knor.NPROF)
+    cal_n = np.zeros(knor.NPROF, np.int64)
+    fit(profile=(cal_ms, cal_n))
+    g = int(np.argmax(cal_ms))
+    ms = np.zeros(knor.NPROF)
+    la = np.zeros(knor.NPROF, np.int64)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    outs = [fit(profile=(ms, la, 1 << g, PROFILE_EVERY)) for _ in range(steps)]
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    iters = sum(o[2]["iters"] for o in outs)
+    log(f"timed {steps} fits in {dt:.3f}s ({iters} iterations)")
+    return dict(outs=outs, sec=dt, iters=iters, value=iters / dt, g=g, ms=ms, la=la,
+                cal_ms=cal_ms, cal_n=cal_n)
+
+
+def kernels_table(knor, m):
+    out = {}
+    for i, nm in enumerate(knor.PROF_GROUPS):
+        if m["cal_n"][i]:
+            out[nm] = {"ms_per_fit": round(float(m["cal_ms"][i]), 4),
+                       "launches": int(m["cal_n"][i]),
+                       "us_per_launch": round(1e3 * m["cal_ms"][i] / m["cal_n"][i], 3)}
+    return out
+
+
+def rate(fit, steps, warmup):
+    outs, dt = timed(fit, steps, warmup)
+    return outs[-1], outs[-1][2]["iters"] / dt
+
+
+# ---------------------------------------------------------------------------
+# exactness and the CPU baseline
+# ---------------------------------------------------------------------------
+
+def check_exact(oracle, workloads, w, fit, nrows, update="canonical", seed=0):
+    """One more fit with label and centroid histories: at every iteration the
+    labels of `nrows` random rows equal the oracle's assignment under that
+    iteration's centroids; the first and the last update equal the oracle's
+    update of all rows."""
+    import numpy as np
+    C, lab, st = fit(history=True, centroid_history=True)
+    iters = st["iters"]
+    H = st["label_history"]
+    CH = st["centroid_history"].cpu().numpy()
+    rng = np.random.default_rng(seed)
+    m = min(nrows, w.n)
+    rows = np.sort(rng.choice(w.n, size=m, replace=False))
+    import torch
+    Hs = H[:, torch.from_numpy(rows).to(H.device)].cpu().numpy()
+    Xs = workloads.to_f64(w.X[rows], w.dtype)
+    t0 = time.perf_counter()
+    labels_ok = True
+    for t in range(iters):
+        lo, _ = oracle.assign(Xs, CH[t])
+        if not (lo == Hs[t]).all():
+            labels_ok = False
+            log(f"exact: labels differ at iteration {t}")
+            break
+    upd = oracle.update_exact if update == "exact" else oracle.update
+    X64 = w.x64()
+    upd_ok = True
+    for t in sorted({0, iters - 1}):
+        Ht = H[t].cpu().numpy()
+        Co, _ = upd(X64, Ht, CH[t])
+        nxt = CH[t + 1] if t + 1 < iters else C.cpu().numpy()
+        if not (Co == nxt).all():
+            upd_ok = False
+            log(f"exact: centroids differ after iteration {t}")
+    del X64
+    log(f"exactness check in {time.perf_counter() - t0:.1f}s")
+    return {"exact": bool(labels_ok and upd_ok),
+            "exact_check": f"labels of {m} random rows at each of {iters} iterations vs the "
+                           f"FP64 oracle's assignment under that iteration's centroids; "
+                           f"centroids of updates {sorted({0, iters - 1})} vs the oracle's "
+                           f"update of all {w.n} rows"}
+
+
+def host_info():
+    info = {}
+    try:
+        txt = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in txt.splitlines():
+            key, _, val = line.partition(":")
+            key = key.strip()
+            if key in ("Model name", "Socket(s)", "Core(s) per socket",
+                       "Thread(s) per core", "CPU(s)"):
+                info[key] = val.strip()
+    except Exception:
+        pass
+    info["affinity"] = len(os.sched_getaffinity(0))
+    info["OMP_NUM_THREADS"] = os.environ.get("OMP_NUM_THREADS")
+    return info
+
+
+def cpu_whole_fit(oracle, w, mti, update="canonical"):
+    """The oracle's whole fit on the same workload and C0 (all threads, then
+    one thread): iterations per second each."""
+    X64 = w.x64()
+
+    def run():
+        t = time.perf_counter()
+        if mti:
+            r = oracle.mti_fit(X64, w.C0, w.max_iters, tol=w.tol, history=False,
+                               objective=False, exact_mean=update == "exact")
+        else:
+            r = oracle.fit(X64, w.C0, w.max_iters, tol=w.tol, history=False, objective=False)
+        return r.iters / (time.perf_counter() - t), r.iters
+
+    nt = oracle.num_threads()
+    v, iters = run()
+    oracle.set_threads(1)
+    v1, _ = run()
+    oracle.set_threads(nt)
+    return {"value": round(v, 4), "unit": "iters/s", "cores": nt, "kind": "oracle",
+            "sample": f"FP64 {'MTI ' if mti else ''}oracle, same workload and C0, "
+                      f"{iters} iterations (whole fit)",
+            "one_thread": {"value": round(v1, 4), "unit": "iters/s", "cores": 1},
+            "host": host_info()}
+
+
+def cpu_sample(oracle, workloads, w, C0, rows_frac, seed=0):
+    """The oracle's assignment of a random row sample at C0 (one iteration's
+    dominant work), timed and scaled to n."""
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    m = max(1000, int(rows_frac * w.n))
+    rows = np.sort(rng.choice(w.n, size=m, replace=False))
+    Xs = workloads.to_f64(w.X[rows], w.dtype)
+    t = time.perf_counter()
+    oracle.assign(Xs, C0)
+    dt = time.perf_counter() - t
+    return {"value": round(m / (dt * w.n), 5), "unit": "iters/s",
+            "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": f"FP64 oracle assignment of {m} random rows at C0 (one iteration's "
+                      f"assignment, {dt:.1f}s), scaled to n={w.n}",
+            "host": host_info()}
+
+
+# ---------------------------------------------------------------------------
+# the workloads
+# ---------------------------------------------------------------------------
+
+def device_points(w):
+    import numpy as np
+    import torch
+    if w.dtype == "bf16":
+        return torch.from_numpy(w.X.view(np.int16)).cuda().view(torch.bfloat16)
+    return torch.from_numpy(w.X).cuda()
+
+
+def single_config(a, knor, oracle, workloads):
+    import torch
+    cfg = a.config
+    t_gen = time.perf_counter()
+    w = workloads.config(cfg)
+    log(f"data n={w.n} d={w.d} k={w.k} {w.dtype} generated in "
+        f"{time.perf_counter() - t_gen:.1f}s")
+    X = device_points(w)
+    C0 = torch.from_numpy(w.C0).cuda()
+    torch.cuda.synchronize()
+    form = {1: {"prune": False}, 2: {"prune": True}, 3: {"prune": True},
+            5: {"prune": True, "learned": True}}[cfg]
+
+    def fit(Xt=X, **kw):
+        opts = dict(form)
+        opts.update(kw)
+        return knor.fit(Xt, w.k, C0=C0, max_iters=w.max_iters, tol=w.tol, counters=True,
+                        update=a.update, **opts)
+
+    m = measure(knor, fit, a.steps, a.warmup)
+    st = m["outs"][-1][2]
+    ctr, iters = st["counters"], st["iters"]
+    sx = {"f64": 8, "f32": 4, "bf16": 2}[w.dtype]
+    sampled = [t for t in range(iters) if t % PROFILE_EVERY == 0]
+    g = m["g"]
+    work = group_work(g, w, sx, ctr, iters, sampled)
+    out = {
+        "metric": METRIC, "value": round(m["value"], 3), "unit": "iters/s",
+        "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
+        "ms_per_step": round(1e3 * m["sec"] / a.steps, 3),
+        "higher_is_better": True, "scaling": "strong", "vs_baseline": None,
+        "dtype": w.dtype, "data": "synthetic",
+        "config": {"workload": WORKLOAD_NAMES[cfg] +
+                   (", update=exact" if a.update == "exact" else ""),
+                   "n": w.n, "d": w.d, "k": w.k, "iters_per_fit": iters},
+        "eff_dists_per_s": m["iters"] * w.n * w.k / m["sec"],
+        "computed_dists_per_s": sum(o[2]["dists_computed"] for o in m["outs"]) / m["sec"],
+        "roofline": roofline(knor, g, m["ms"], m["la"], work,
+                             measured_traffic(cfg, knor.PROF_GROUPS[g]), a.steps),
+        "kernels": kernels_table(knor, m),
+        "rechecked_per_fit": st["rechecked"],
+    }
+    if cfg == 5:
+        out["certified_per_fit"] = st["certified"]
+        out["mlp_queries_per_fit"] = st["mlp_queries"]
+    if m["cal_n"][0] and cfg != 1:
+        fl = group_work(0, w, sx, ctr, iters, [0])[0]
+        sec = m["cal_ms"][0] / m["cal_n"][0] / 1e3
+        peak = PEAK_BF16_MFMA if w.dtype == "bf16" else PEAK_FP32_MFMA
+        out["dense_tile"] = {"tflops": round(fl / sec / 1e12, 2),
+                             "frac_mfma_peak": round(fl / sec / peak, 4),
+                             "us": round(sec * 1e6, 2)}
+    # the same workload on this GPU without the form
+    if not a.no_baselines and cfg != 1:
+        base = {}
+        (Cb, lb, sb), v = rate(lambda: fit(X if w.dtype != "bf16" else X.float(), prune=False,
+                                           learned=False), max(1, a.steps - 1), 1)
+        base["fp32_plain"] = {"value": round(v, 3), "unit": "iters/s",
+                              "iters_per_fit": sb["iters"]}
+        C, lab = m["outs"][-1][0], m["outs"][-1][1]
+        same = bool((C == Cb).all() and (lab == lb).all())
+        if cfg in (3, 5):
+            Xf = X.float() if w.dtype == "bf16" else X
+            (Cm, lm, sm), vm = rate(lambda: fit(Xf, prune=True, learned=False),
+                                    max(1, a.steps - 1), 1)
+            base["fp32_mti"] = {"value": round(vm, 3), "unit": "iters/s",
+                                "iters_per_fit": sm["iters"]}
+            same = same and bool((C == Cm).all() and (lab == lm).all())
+        for key in base:
+            base[key]["speedup"] = round(m["value"] / base[key]["value"], 3)
+        out["baselines"] = base
+        out["same_results_as_baselines"] = same
+    if not a.no_exact:
+        out.update(check_exact(oracle, workloads, w, fit, a.exact_rows, a.update))
+    if not a.no_cpu_baseline:
+        if cfg in (1, 2):
+            out["cpu_baseline"] = cpu_whole_fit(oracle, w, mti=cfg == 2, update=a.update)
+        else:
+            out["cpu_baseline"] = cpu_sample(oracle, workloads, w, w.C0,
+                                             {3: 0.05, 5: 0.02}[cfg])
+    return out
+
+
+def batched_config(a, knor, oracle, workloads):
+    import numpy as np
+    import torch
+    t_gen = time.perf_counter()
+    ws = workloads.batched(64)
+    log(f"64 instances, sum n={sum(w.n for w in ws)}, generated in "
+        f"{time.perf_counter() - t_gen:.1f}s")
+    probs = [dict(X=torch.from_numpy(w.X).cuda(), k=w.k, C0=torch.from_numpy(w.C0).cuda(),
+                  max_iters=w.max_iters, tol=w.tol) for w in ws]
+    res, dt = timed(lambda: knor.fit_batched(probs, update=a.update), a.steps, a.warmup)
+    res = res[-1]
+    iters = sum(r[2]["iters"] for r in res)
+    out = {
+        "metric": METRIC, "value": round(iters / dt, 3), "unit": "iters/s",
+        "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
+        "ms_per_step": round(dt * 1e3, 3), "higher_is_better": True, "scaling": "strong",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": WORKLOAD_NAMES[4], "instances": 64,
+                   "sum_n": int(sum(w.n for w in ws)), "iters_per_batch": iters},
+        "eff_dists_per_s": sum(r[2]["iters"] * w.n * w.k for r, w in zip(res, ws)) / dt,
+    }
+    if not a.no_baselines:
+        def seq(prune):
+            return [knor.fit(p["X"], p["k"], C0=p["C0"], max_iters=p["max_iters"],
+                             prune=prune, update=a.update) for p in probs]
+        sm, dsm = timed(lambda: seq(True), 1, 0)
+        sp, dsp = timed(lambda: seq(False), 1, 0)
+        sm, sp = sm[-1], sp[-1]
+        out["baselines"] = {
+            "sequential_mti": {"value": round(iters / dsm, 3), "unit": "iters/s",
+                               "speedup": round(dsm / dt, 3)},
+            "sequential_fp32_plain": {"value": round(iters / dsp, 3), "unit": "iters/s",
+                                      "speedup": round(dsp / dt, 3)}}
+        out["same_results_as_baselines"] = all(
+            bool((r[0] == q[0]).all() and (r[1] == q[1]).all() and (r[0] == u[0]).all())
+            for r, q, u in zip(res, sm, sp))
+    # roofline: the largest instance's dominant kernel group, under events
+    il = max(range(len(ws)), key=lambda i: ws[i].n * ws[i].k * ws[i].d)
+    wl = ws[il]
+    ms = np.zeros(knor.NPROF)
+    la = np.zeros(knor.NPROF, np.int64)
+    _, _, stl = knor.fit(probs[il]["X"], wl.k, C0=probs[il]["C0"], max_iters=wl.max_iters,
+                         counters=True, profile=(ms, la), update=a.update)
+    g = int(np.argmax(ms))
+    rl = roofline(knor, g, ms, la, group_work(g, wl, 4, stl["counters"], stl["iters"],
+                                               range(stl["iters"])), None)
+    if rl is not None:
+        rl["instance"] = {"n": wl.n, "d": wl.d, "k": wl.k}
+    out["roofline"] = rl
+    if not a.no_exact:
+        p = probs[il]
+        fit = lambda **kw: knor.fit(p["X"], wl.k, C0=p["C0"], max_iters=wl.max_iters,
+                                    update=a.update, **kw)
+        ex = check_exact(oracle, workloads, wl, fit, a.exact_rows, a.update)
+        ex["exact_check"] += " (largest instance)"
+        out.update(ex)
+    if not a.no_cpu_baseline:
+        cb = cpu_sample(oracle, workloads, wl, wl.C0, 0.25)
+        cb["sample"] += " (largest instance)"
+        out["cpu_baseline"] = cb
+    return out
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; the sharding "
+                                   "design is described in DESIGN.md",
+                          "n_gpus": a.gpus}), flush=True)
+        sys.exit(2)
     import torch
 
     import oracle
@@ -171,356 +527,18 @@ def run_form(a):
     import workloads
 
     knor.load()
-    t_gen = time.perf_counter()
-    out = {"n_gpus": 1, "steps": a.steps, "warmup": a.warmup, "higher_is_better": True,
-           "scaling": "strong", "vs_baseline": None, "data": "synthetic"}
-
-    def timed(fn):
-        for _ in range(a.warmup):
-            fn()
-        torch.cuda.synchronize()
-        t = time.perf_counter()
-        for _ in range(a.steps):
-            r = fn()
-        torch.cuda.synchronize()
-        return r, (time.perf_counter() - t) / a.steps
-
-    if a.form in ("mixed", "learned"):
-        cfg = 3 if a.form == "mixed" else 5
-        w = workloads.config(cfg)
-        print(f"# data n={w.n} d={w.d} k={w.k} generated in "
-              f"{time.perf_counter() - t_gen:.1f}s", file=sys.stderr, flush=True)
-        if w.dtype == "bf16":
-            X = torch.from_numpy(w.X.view(np.int16)).cuda().view(torch.bfloat16)
-            Xf = X.float()
-        else:
-            X = torch.from_numpy(w.X).cuda()
-            Xf = X
-        C0 = torch.from_numpy(w.C0).cuda()
-        extra = dict(learned=True) if a.form == "learned" else {}
-
-        def fit(Xt, **kw):
-            return knor.fit(Xt, w.k, C0=C0, max_iters=w.max_iters, tol=w.tol,
-                            counters=True, **kw)
-
-        (C, lab, st), dt = timed(lambda: fit(X, prune=True, **extra))
-        (Cp, labp, stp), dtp = timed(lambda: fit(Xf, prune=False))
-        exact = bool((C == Cp).all() and (lab == labp).all())
-        ref_mti = None
-        if a.form == "learned":
-            (Cm, labm, stm), dtm = timed(lambda: fit(X, prune=True))
-            exact = exact and bool((C == Cm).all() and (lab == labm).all())
-            ref_mti = stm["iters"] / dtm
-        # kernel groups of one more fit, under events
-        ms = np.zeros(knor.NPROF)
-        la = np.zeros(knor.NPROF, np.int64)
-        fit(X, prune=True, profile=(ms, la), **extra)
-        g = int(np.argmax(ms))
-        sx = 2 if w.dtype == "bf16" else 4
-        peak = PEAK_BF16_MFMA if w.dtype == "bf16" else PEAK_FP32_MFMA
-        out.update({
-            "metric": "Lloyd iters/s at exact assignments (labels identical to plain FP32)",
-            "value": round(st["iters"] / dt, 3), "unit": "iters/s",
-            "ms_per_step": round(dt * 1e3, 3),
-            "dtype": "bf16" if w.dtype == "bf16" else "f32",
-            "config": {"workload": (
-                "mixed precision: n=2e7 d=64 k=256 bf16, 95% mixture + 5% uniform "
-                "outliers, k random rows, 30 iters, MTI" if a.form == "mixed" else
-                "learned proposal: n=1e7 d=32 k=4096 f32 mixture, k random rows, "
-                "40 iters, MTI + MLP 32-256-256-4096 trained on iterations 1-5"),
-                "n": w.n, "d": w.d, "k": w.k, "iters_per_fit": st["iters"]},
-            "baseline_fp32_plain": {"value": round(stp["iters"] / dtp, 3), "unit": "iters/s"},
-            "speedup_vs_fp32_plain": round((st["iters"] / dt) / (stp["iters"] / dtp), 3),
-            "exact_vs_fp32_plain": exact,
-            "rechecked_per_fit": st["rechecked"],
-            "roofline": roofline_of(knor, ms, la, g, 1,
-                                    group_work(g, w.n, w.d, w.k, sx, st["counters"],
-                                               st["iters"], peak)),
-            "kernels": {nm: {"ms_per_fit": round(float(ms[i]), 3), "launches": int(la[i])}
-                        for i, nm in enumerate(knor.PROF_GROUPS) if la[i]},
-        })
-        if a.form == "learned":
-            out["baseline_mti"] = {"value": round(ref_mti, 3), "unit": "iters/s"}
-            out["speedup_vs_mti"] = round((st["iters"] / dt) / ref_mti, 3)
-            out["certified_per_fit"] = st["certified"]
-            out["mlp_queries_per_fit"] = st["mlp_queries"]
-        if not a.no_cpu_baseline:
-            h = knor.fit(X, w.k, C0=C0, max_iters=1, history=True)[2]["label_history"]
-            cb, ok = cpu_sample_baseline(oracle, w, lambda r: workloads.to_f64(w.X[r], w.dtype),
-                                         w.C0, h[0].cpu().numpy(), 0.02 if cfg == 5 else 0.05)
-            out["cpu_baseline"] = cb
-            out["cpu_sample_labels_exact"] = ok
-    elif a.form == "incremental":
-        w = workloads.config(a.config)
-        print(f"# data n={w.n} d={w.d} k={w.k} generated in "
-              f"{time.perf_counter() - t_gen:.1f}s", file=sys.stderr, flush=True)
-        if w.dtype == "bf16":
-            X = torch.from_numpy(w.X.view(np.int16)).cuda().view(torch.bfloat16)
-        else:
-            X = torch.from_numpy(w.X).cuda()
-        C0 = torch.from_numpy(w.C0).cuda()
-
-        def fit(update, **kw):
-            return knor.fit(X, w.k, C0=C0, max_iters=w.max_iters, tol=w.tol, prune=True,
-                            counters=True, update=update, **kw)
-
-        (C, lab, st), dt = timed(lambda: fit("exact"))
-        (Cc, labc, stc), dtc = timed(lambda: fit("canonical"))
-        groups = {}
-        for upd in ("exact", "canonical"):
-            ms = np.zeros(knor.NPROF)
-            la = np.zeros(knor.NPROF, np.int64)
-            fit(upd, profile=(ms, la))
-            groups[upd] = (ms, la)
-        ms, la = groups["exact"]
-        g = int(np.argmax(ms))
-        sx = 2 if w.dtype == "bf16" else 4
-        peak = PEAK_BF16_MFMA if w.dtype == "bf16" else PEAK_FP32_MFMA
-        upd_groups = [knor.PROF_GROUPS.index(nm) for nm in ("sort", "leaf", "tree")]
-        names = {2: "gaussian-mixture n=1e6 d=32 k=100 f32 MTI k-means++ max_iters=100 tol=0",
-                 3: "mixed precision: n=2e7 d=64 k=256 bf16, 95% mixture + 5% uniform "
-                    "outliers, k random rows, 30 iters, MTI",
-                 5: "large k: n=1e7 d=32 k=4096 f32 mixture, k random rows, 40 iters, MTI"}
-        out.update({
-            "metric": "Lloyd iters/s at exact assignments, exact-mean incremental update",
-            "value": round(st["iters"] / dt, 3), "unit": "iters/s",
-            "ms_per_step": round(dt * 1e3, 3), "dtype": "bf16" if w.dtype == "bf16" else "f32",
-            "config": {"workload": names[a.config] + ", update=exact (changed points moved "
-                                                     "one by one when few change)",
-                       "n": w.n, "d": w.d, "k": w.k, "iters_per_fit": st["iters"]},
-            "baseline_canonical_update": {"value": round(stc["iters"] / dtc, 3),
-                                          "unit": "iters/s", "iters_per_fit": stc["iters"]},
-            "speedup_vs_canonical_update": round((st["iters"] / dt) / (stc["iters"] / dtc), 3),
-            "update_ms_per_fit": {u: round(float(sum(groups[u][0][i] for i in upd_groups)), 3)
-                                  for u in groups},
-            "roofline": roofline_of(knor, ms, la, g, 1,
-                                    group_work(g, w.n, w.d, w.k, sx, st["counters"],
-                                               st["iters"], peak) if g in (0, 1, 2, 3) else None),
-            "kernels": {nm: {"ms_per_fit": round(float(ms[i]), 3), "launches": int(la[i])}
-                        for i, nm in enumerate(knor.PROF_GROUPS) if la[i]},
-        })
-        if not a.no_cpu_baseline and a.config == 2:
-            hist = fit("exact", history=True)[2]["label_history"].cpu().numpy()
-            tc = time.perf_counter()
-            ref = oracle.mti_fit(w.x64(), w.C0, w.max_iters, tol=w.tol, history=True,
-                                 objective=False, exact_mean=True)
-            tcpu = time.perf_counter() - tc
-            out["cpu_baseline"] = {
-                "value": round(ref.iters / tcpu, 4), "unit": "iters/s",
-                "cores": oracle.num_threads(), "kind": "oracle",
-                "sample": f"FP64 MTI oracle with the exactly rounded mean, same workload "
-                          f"and C0, {ref.iters} iterations (whole fit)"}
-            out["exact"] = bool(ref.iters == st["iters"] and hist.shape[0] == ref.iters and
-                                (hist == ref.label_hist).all() and
-                                (C.cpu().numpy() == ref.C).all())
-        elif not a.no_cpu_baseline:
-            # the final centroids of 8 random clusters against the oracle's
-            # exactly rounded mean of their final members
-            h = knor.fit(X, w.k, C0=C0, max_iters=1, history=True)[2]["label_history"]
-            cb, ok = cpu_sample_baseline(oracle, w, lambda r: workloads.to_f64(w.X[r], w.dtype),
-                                         w.C0, h[0].cpu().numpy(), 0.02 if a.config == 5 else 0.05)
-            out["cpu_baseline"] = cb
-            labs = lab.cpu().numpy()
-            Cg = C.cpu().numpy()
-            js = np.random.default_rng(0).choice(w.k, size=8, replace=False)
-            rows = np.nonzero(np.isin(labs, js))[0]
-            remap = np.full(w.k, -1, np.int32)
-            remap[js] = np.arange(8)
-            Co, _ = oracle.update_exact(workloads.to_f64(w.X[rows], w.dtype), remap[labs[rows]],
-                                        Cg[js])
-            out["exact_update_check"] = {"clusters": 8, "members": int(rows.size),
-                                         "equal": bool((Co == Cg[js]).all())}
-    else:   # batched
-        ws = workloads.batched(64)
-        print(f"# 64 instances, sum n={sum(w.n for w in ws)}, generated in "
-              f"{time.perf_counter() - t_gen:.1f}s", file=sys.stderr, flush=True)
-        probs = [dict(X=torch.from_numpy(w.X).cuda(), k=w.k, C0=torch.from_numpy(w.C0).cuda(),
-                      max_iters=w.max_iters, tol=w.tol) for w in ws]
-        res, dt = timed(lambda: knor.fit_batched(probs))
-        seq, dts = timed(lambda: [knor.fit(p["X"], p["k"], C0=p["C0"], max_iters=p["max_iters"],
-                                           prune=False) for p in probs])
-        iters = sum(r[2]["iters"] for r in res)
-        exact = all(bool((r[0] == q[0]).all() and (r[1] == q[1]).all()) for r, q in zip(res, seq))
-        out.update({
-            "metric": "Lloyd iters/s summed over the batch at exact assignments",
-            "value": round(iters / dt, 3), "unit": "iters/s",
-            "ms_per_step": round(dt * 1e3, 3), "dtype": "f32",
-            "config": {"workload": "batched restarts: 64 instances, n log-uniform in "
-                                   "[1e4, 2e6], d in {8,16,32,64}, k in 8..512, f32, "
-                                   "k random rows, 50 iters, MTI, tuned tile schedules",
-                       "instances": 64, "sum_n": int(sum(w.n for w in ws)),
-                       "iters_per_batch": iters},
-            "baseline_fp32_plain_sequential": {"value": round(iters / dts, 3), "unit": "iters/s"},
-            "speedup_vs_fp32_plain": round(dts / dt, 3),
-            "exact_vs_fp32_plain": exact,
-            "eff_dists_per_s": sum(r[2]["iters"] * w.n * w.k for r, w in zip(res, ws)) / dt,
-        })
-        # roofline: the largest instance's dominant kernel group, under events
-        il = max(range(len(ws)), key=lambda i: ws[i].n * ws[i].k * ws[i].d)
-        wl = ws[il]
-        ms = np.zeros(knor.NPROF)
-        la = np.zeros(knor.NPROF, np.int64)
-        _, _, stl = knor.fit(probs[il]["X"], wl.k, C0=probs[il]["C0"], max_iters=wl.max_iters,
-                             counters=True, profile=(ms, la))
-        g = int(np.argmax(ms))
-        rl = roofline_of(knor, ms, la, g, 1, group_work(g, wl.n, wl.d, wl.k, 4, stl["counters"],
-                                                        stl["iters"]))
-        if rl is not None:
-            rl["instance"] = {"n": wl.n, "d": wl.d, "k": wl.k}
-        out["roofline"] = rl
-        if not a.no_cpu_baseline:
-            i = il
-            w = ws[i]
-            h = knor.fit(probs[i]["X"], w.k, C0=probs[i]["C0"], max_iters=1,
-                         history=True)[2]["label_history"]
-            cb, ok = cpu_sample_baseline(oracle, w, lambda r: w.X[r].astype(np.float64),
-                                         w.C0, h[0].cpu().numpy(), 0.25)
-            cb["sample"] += " (largest instance)"
-            out["cpu_baseline"] = cb
-            out["cpu_sample_labels_exact"] = ok
-    print(json.dumps(out), flush=True)
-
-
-def main():
-    a = parse()
-    if a.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; "
-                          "multi-GPU sharding is described in DESIGN.md",
-                          "n_gpus": a.gpus}), flush=True)
-        sys.exit(2)
-    if a.form != "headline":
-        run_form(a)
-        return
-    import numpy as np
-    import torch
-
-    import paper_1606_08905_amd as knor
-    import workloads
-
-    knor.load()
-    t_gen = time.perf_counter()
-    w = workloads.config(2)
-    n, d, k = w.n, w.d, w.k
-    print(f"# data n={n} d={d} k={k} generated in {time.perf_counter() - t_gen:.1f}s",
-          file=sys.stderr, flush=True)
-    X = torch.from_numpy(w.X).cuda()
-    C0 = torch.from_numpy(w.C0).cuda()
-    torch.cuda.synchronize()
-
-    def step(profile=None, history=False):
-        return knor.fit(X, k, C0=C0, max_iters=w.max_iters, tol=w.tol,
-                        prune=True, counters=True, profile=profile,
-                        history=history)
-
-    for _ in range(a.warmup):
-        step()
-    torch.cuda.synchronize()
     if a.copy_calibration_mib > 0:
         nel = a.copy_calibration_mib << 18            # float32 elements
-        src = torch.ones(nel, dtype=torch.float32, device=X.device)
+        src = torch.ones(nel, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
         torch.cuda.synchronize()
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-
-    # untimed calibration fit with every kernel group under HIP events: the
-    # per-group breakdown, and which group dominates
-    cal_ms = np.zeros(knor.NPROF)
-    cal_n = np.zeros(knor.NPROF, np.int64)
-    step(profile=(cal_ms, cal_n))
-    g_dom = int(np.argmax(cal_ms))
-
-    # timed region: K fits; the dominant group's launches in iterations
-    # t % PROFILE_EVERY == 0 are bracketed by HIP events (each record costs
-    # the stream a few microseconds, so not every launch is timed)
-    prof_ms = np.zeros(knor.NPROF)
-    prof_n = np.zeros(knor.NPROF, np.int64)
-    iters_total = 0
-    stats = []
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(a.steps):
-        C, lab, st = step(profile=(prof_ms, prof_n, 1 << g_dom, PROFILE_EVERY))
-        iters_total += st["iters"]
-        stats.append(st)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    print(f"# timed {a.steps} fits in {dt:.3f}s", file=sys.stderr, flush=True)
-
-    value = iters_total / dt
-    iters = stats[-1]["iters"]
-    ctr = stats[-1]["counters"]
-    dists_eff = iters_total * n * k / dt
-    dists_done = sum(s["dists_computed"] for s in stats) / dt
-
-    kernels = {}
-    for g, name in enumerate(knor.PROF_GROUPS):
-        if cal_n[g]:
-            kernels[name] = {"ms_per_fit": round(float(cal_ms[g]), 4),
-                             "launches": int(cal_n[g]),
-                             "us_per_launch": round(1e3 * cal_ms[g] / cal_n[g], 3)}
-    roof = None
-    sampled = [t for t in range(iters) if t % PROFILE_EVERY == 0]
-    wk = group_work(g_dom, n, d, k, 4, ctr, iters, its=sampled)
-    if wk is not None and prof_n[g_dom]:
-        amount, launches, unit, bound, peak = wk
-        assert launches * a.steps == prof_n[g_dom], (launches, prof_n[g_dom])
-        per_launch = amount / max(1, launches)
-        sec_per_launch = prof_ms[g_dom] / prof_n[g_dom] / 1e3
-        achieved = per_launch / sec_per_launch
-        scale = 1e12 if unit == "TFLOP/s" else 1e9
-        roof = {"kernel": knor.PROF_GROUPS[g_dom], "bound": bound,
-                "achieved": round(achieved / scale, 3),
-                "peak": round(peak / scale, 1), "unit": unit,
-                "frac": round(achieved / peak, 4),
-                "traffic": measured_traffic(knor.PROF_GROUPS[g_dom]),
-                "us_per_launch": round(sec_per_launch * 1e6, 3)}
-    # the dense distance tile (iteration 0), whatever dominates
-    tile = None
-    if cal_n[0]:
-        fl = group_work(0, n, d, k, 4, ctr, iters)[0]
-        sec = cal_ms[0] / cal_n[0] / 1e3
-        tile = {"tflops": round(fl / sec / 1e12, 2),
-                "frac_fp32_mfma_peak": round(fl / sec / PEAK_FP32_MFMA, 4),
-                "us": round(sec * 1e6, 2)}
-
-    out = {
-        "metric": METRIC, "value": round(value, 3), "unit": "iters/s",
-        "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
-        "ms_per_step": round(1e3 * dt / a.steps, 3),
-        "higher_is_better": True, "scaling": "strong", "vs_baseline": None,
-        "dtype": "f32", "data": "synthetic",
-        "config": {"workload": "gaussian-mixture n=1e6 d=32 k=100 f32 MTI "
-                               "k-means++ max_iters=100 tol=0",
-                   "n": n, "d": d, "k": k, "iters_per_fit": iters,
-                   "prune": "MTI"},
-        "eff_dists_per_s": dists_eff, "computed_dists_per_s": dists_done,
-        "dense_tile": tile, "roofline": roof, "kernels": kernels,
-        "rechecked_per_fit": stats[-1]["rechecked"],
-    }
-
-    # CPU baseline: the FP64 oracle on the same inputs, plus exactness check
-    if not a.no_cpu_baseline:
-        import oracle
-        _, _, sth = step(history=True)
-        hist = sth["label_history"].cpu().numpy()
-        X64 = w.x64()
-        its = a.cpu_iters if a.cpu_iters > 0 else w.max_iters
-        tc = time.perf_counter()
-        ref = oracle.mti_fit(X64, w.C0, its, tol=w.tol, history=True,
-                             objective=False)
-        tcpu = time.perf_counter() - tc
-        m = min(ref.iters, hist.shape[0])
-        exact = bool((hist[:m] == ref.label_hist[:m]).all()) and (
-            ref.iters == sth["iters"] or its < w.max_iters)
-        out["cpu_baseline"] = {
-            "value": round(ref.iters / tcpu, 4), "unit": "iters/s",
-            "cores": oracle.num_threads(), "kind": "oracle",
-            "sample": f"FP64 MTI oracle, same workload and C0, {ref.iters} "
-                      f"iterations ({'whole fit' if its >= w.max_iters else 'first iterations'})"}
-        out["exact"] = exact
-        out["exact_iters_compared"] = int(m)
+    if a.config == 4:
+        out = batched_config(a, knor, oracle, workloads)
+    else:
+        out = single_config(a, knor, oracle, workloads)
     print(json.dumps(out), flush=True)
 
 

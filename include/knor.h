@@ -36,8 +36,13 @@
  *    then be NULL): assign does nothing; update copies C_prev to C_out and
  *    writes zero counts.
  *  - Limits: 1 <= d <= 256, 1 <= k <= 16384, 1 <= n < 2^31, k <= n (fit).
- *  - The library keeps no global mutable state; concurrent calls on
- *    different streams are independent.
+ *  - Process-wide state: one table of FP32 tile schedules per (padded d,
+ *    padded k) class, filled by the timing-based tuner (opts->autotune,
+ *    knor_fit_batched) and read by later calls, behind a mutex.  A schedule
+ *    changes speed only, never a result, so concurrent calls on different
+ *    streams give the same results as the same calls made one at a time;
+ *    which schedule the tuner keeps can depend on concurrent load.
+ *    opts->tile_blocks / tile_resident force a schedule and bypass the table.
  */
 #ifndef KNOR_H
 #define KNOR_H
@@ -62,12 +67,30 @@ typedef enum {
 typedef enum { KNOR_F64 = 0, KNOR_F32 = 1, KNOR_BF16 = 2 } knor_dtype;
 
 /* Initial centroids.  The paper does not specify initialisation. */
+/* Every mode other than GIVEN is a deterministic function of opts->seed and
+ * the values of X (SplitMix64, Steele, Lea and Flood 2014, seeded with
+ * opts->seed; next() is its next 64-bit output); C_init is then ignored. */
 typedef enum {
   KNOR_INIT_GIVEN = 0, /* C_init holds the k x d FP64 initial centroids      */
-  KNOR_INIT_FORGY = 1  /* k distinct rows of X chosen from opts->seed: the
-                          first k entries of a Fisher-Yates shuffle of 0..n-1
-                          driven by SplitMix64(seed), j = next() % (i + 1)
-                          for i = n-1 down to 1                              */
+  KNOR_INIT_FORGY = 1, /* k distinct rows of X: a Fisher-Yates pass over
+                          slots i = n-1 down to n-k, j = next() % (i + 1),
+                          swap slots i and j; centroid r is the row that
+                          lands in slot n-1-r                                */
+  KNOR_INIT_SHUFFLE_FIRSTK = 2, /* the first k entries of a front-to-back
+                          Fisher-Yates shuffle of 0..n-1: for i = 0..k-1,
+                          j = i + next() % (n - i), swap slots i and j;
+                          centroid i is the row in slot i                    */
+  KNOR_INIT_KMEANSPP = 3 /* k-means++ (D^2) seeding on the device: centroid 0
+                          is row floor(r_0 n / 2^64); draw t >= 1 weights
+                          every point p by w(p) = floor(D(p) 2^(B - e)),
+                          D(p) the canonical FP64 squared distance to the
+                          nearest centroid so far, e the exponent with
+                          max_p D(p) < 2^e, B = 63 - ceil(log2 n), and takes
+                          the point whose weight interval contains
+                          floor(r_t W / 2^64), W = sum of the weights
+                          (integers, so no summation order matters); W = 0
+                          takes row floor(r_t n / 2^64).  r_t = the t-th
+                          output of next().  Costs k - 1 passes over X   */
 } knor_init;
 
 typedef struct {
@@ -77,7 +100,7 @@ typedef struct {
   int32_t recheck;      /* 1: FP64 recheck of near-tie points only (default);
                            2: FP64 recheck of every point (validation mode)  */
   int32_t check_numeric;/* 1: reject NaN/Inf in X and C (default 1)         */
-  uint64_t seed;        /* KNOR_INIT_FORGY seed                              */
+  uint64_t seed;        /* seed of the non-GIVEN init modes                  */
   void* stream;         /* hipStream_t; NULL = null stream                   */
   size_t workspace_cap; /* bytes of device workspace allowed; 0 = unlimited  */
   int32_t* label_history; /* DEVICE, optional: max_iters x n; row t receives
@@ -132,6 +155,9 @@ typedef struct {
                            KNOR_ERR_UNSUPPORTED).  The two readings may
                            differ in the last bit of a centroid and so,
                            rarely, in a later label                          */
+  double* centroid_history; /* DEVICE, optional: max_iters x k x d FP64; row
+                               t receives the centroids that iteration t's
+                               assignment used (row 0: the initial ones)    */
 } knor_opts;
 
 /* Kernel groups timed by opts->profile_ms. */
@@ -144,8 +170,9 @@ enum {
   KNOR_PROF_LEAF = 5,         /* update pass 2: leaf sums (gathers X)         */
   KNOR_PROF_TREE = 6,         /* update pass 2: tree, division, operands      */
   KNOR_PROF_CC = 7,           /* MTI centroid-pair bounds s(c)                */
-  KNOR_PROF_LEARNED = 8,      /* proposal MLP: training, proposal, certificate */
-  KNOR_NPROF = 9
+  KNOR_PROF_LEARNED = 8,      /* proposal MLP: training and forward pass   */
+  KNOR_PROF_CERTIFY = 9,      /* proposal certificate and its neighbour lists */
+  KNOR_NPROF = 10
 };
 
 /* Per-iteration counters (columns of opts->iter_counters). */
@@ -156,6 +183,7 @@ enum {
   KNOR_CNT_PRUNED_B = 3,  /* MTI: decided after tightening the bound          */
   KNOR_CNT_RECHECKED = 4, /* points recomputed in FP64                        */
   KNOR_CNT_CERTIFIED = 5, /* survivors decided by a certified proposal        */
+  KNOR_CNT_QUERIED = 6,   /* survivors sent to the proposal MLP               */
   KNOR_NCOUNTERS = 8
 };
 
@@ -245,8 +273,9 @@ typedef struct {
  * everything already enqueued on opts->stream; the call returns when every
  * problem is done.
  *   probs   HOST array of count problems (count >= 0).
- *   opts    as for knor_fit, except that label_history, iter_counters and
- *           profile_ms / profile_launches must be NULL.
+ *   opts    as for knor_fit, except that label_history, iter_counters,
+ *           centroid_history and profile_ms / profile_launches must be
+ *           NULL.
  *   st      HOST array of count stats, or NULL.
  * Every problem is validated before any work starts (an invalid one gives
  * KNOR_ERR_INVALID_ARG and no output is touched).  A runtime error in one
@@ -300,8 +329,10 @@ knor_status knor_mlp_propose(const float* params, int32_t d, int32_t h,
 const char* knor_status_string(knor_status s);
 
 /* Library version as major*10000 + minor*100 + patch.  0.2.0 added
- * knor_opts.update (so sizeof(knor_opts), which struct_size must equal,
- * changed). */
+ * knor_opts.update, 0.3.0 knor_opts.centroid_history, the init modes
+ * SHUFFLE_FIRSTK and KMEANSPP and the kernel group KNOR_PROF_CERTIFY (so
+ * profile arrays hold KNOR_NPROF = 10 entries; each new field changed
+ * sizeof(knor_opts), which struct_size must equal). */
 int32_t knor_version(void);
 
 #ifdef __cplusplus

@@ -109,12 +109,16 @@ class Oracle:
         L.oracle_canonical_sum.argtypes = [P, i64]
         L.oracle_canonical_sum.restype = f64
         L.oracle_num_threads.restype = ctypes.c_int
+        L.oracle_set_threads.argtypes = [ctypes.c_int]
         L.oracle_objective.argtypes = [P, i64, ctypes.c_int, P, P]
         L.oracle_objective.restype = f64
         self.L = L
 
     def num_threads(self) -> int:
         return int(self.L.oracle_num_threads())
+
+    def set_threads(self, t: int) -> None:
+        self.L.oracle_set_threads(int(t))
 
     def dist2(self, x, c) -> float:
         x, c = _f64(x), _f64(c)
@@ -240,6 +244,10 @@ def lib():
 
 def num_threads():
     return default().num_threads()
+
+
+def set_threads(t):
+    default().set_threads(t)
 
 
 def dist2(x, c):

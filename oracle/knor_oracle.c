@@ -569,6 +569,16 @@ double oracle_objective(const double* X, int64_t n, int d, const double* C,
   return s;
 }
 
+/* Thread count of the later parallel regions (no effect on any result: every
+ * loop is statically scheduled over fixed point blocks or per cluster). */
+void oracle_set_threads(int t) {
+#ifdef _OPENMP
+  if (t > 0) omp_set_num_threads(t);
+#else
+  (void)t;
+#endif
+}
+
 int oracle_num_threads(void) {
 #ifdef _OPENMP
   return omp_get_max_threads();

@@ -27,10 +27,12 @@ _LIB = os.path.join(_PKG, "libknor.so")
 
 KNOR_OK, KNOR_ERR_INVALID_ARG, KNOR_ERR_OUT_OF_MEMORY, KNOR_ERR_HIP, \
     KNOR_ERR_NUMERIC, KNOR_ERR_UNSUPPORTED = range(6)
-INIT_GIVEN, INIT_FORGY = 0, 1
+INIT_GIVEN, INIT_FORGY, INIT_SHUFFLE_FIRSTK, INIT_KMEANSPP = 0, 1, 2, 3
+INITS = {"given": INIT_GIVEN, "forgy": INIT_FORGY,
+         "shuffle_first_k": INIT_SHUFFLE_FIRSTK, "kmeans++": INIT_KMEANSPP}
 NCOUNTERS = 8
 COUNTERS = ("changed", "scanned", "pruned_a", "pruned_b", "rechecked",
-            "certified")
+            "certified", "queried")
 
 
 class KnorError(RuntimeError):
@@ -57,12 +59,13 @@ class Opts(ctypes.Structure):
                 ("train_iters", ctypes.c_int32),
                 ("train_batches", ctypes.c_int32),
                 ("profile_every", ctypes.c_int32),
-                ("update", ctypes.c_int32)]
+                ("update", ctypes.c_int32),
+                ("centroid_history", ctypes.c_void_p)]
 
 
-NPROF = 9
+NPROF = 10
 PROF_GROUPS = ("assign_dense", "assign_list", "recheck", "filter", "sort",
-               "leaf", "tree", "cc", "learned")
+               "leaf", "tree", "cc", "learned", "certify")
 
 
 class Problem(ctypes.Structure):
@@ -162,7 +165,7 @@ def _opts(prune=True, recheck=1, check_numeric=True, seed=0, stream=None,
           workspace_cap=0, label_history=None, iter_counters=None,
           poll_every=0, profile=None, tile_blocks=0, tile_resident=0,
           autotune=False, learned=False, train_iters=0, train_batches=0,
-          update="canonical"):
+          update="canonical", centroid_history=None):
     torch = _torch()
     if stream is None:
         stream = torch.cuda.current_stream()
@@ -190,6 +193,8 @@ def _opts(prune=True, recheck=1, check_numeric=True, seed=0, stream=None,
     o.train_iters = int(train_iters)
     o.train_batches = int(train_batches)
     o.update = _update_code(update)
+    o.centroid_history = (centroid_history.data_ptr()
+                          if centroid_history is not None else None)
     return o
 
 
@@ -206,11 +211,17 @@ def fit(X, k, C0=None, init="given", max_iters=100, tol=0.0, prune=True,
         recheck=1, seed=0, history=False, counters=False, out=None,
         check_numeric=True, workspace_cap=0, poll_every=0, profile=None,
         tile_blocks=0, tile_resident=0, autotune=False, learned=False,
-        train_iters=0, train_batches=0, update="canonical"):
+        train_iters=0, train_batches=0, update="canonical",
+        centroid_history=False):
     """Lloyd's k-means on the GPU.  Returns (C, labels, stats dict).
 
+    init: "given" (C0), "forgy", "shuffle_first_k" or "kmeans++" (the last
+    three are deterministic functions of seed and X; see include/knor.h).
+
     history=True adds stats["label_history"]: (iters, n) int32 CUDA tensor of
-    the labels each iteration's assignment produced.  counters=True adds
+    the labels each iteration's assignment produced; centroid_history=True
+    adds stats["centroid_history"]: (iters, k, d) float64 CUDA tensor of the
+    centroids each iteration's assignment used.  counters=True adds
     stats["counters"]: (iters, 8) int64 numpy array (KNOR_CNT_* columns).
     out=(C, labels) reuses preallocated output tensors.  profile=(ms, launches
     [, mask]) (float64 and int64 numpy arrays of NPROF entries, optional bit
@@ -235,7 +246,9 @@ def fit(X, k, C0=None, init="given", max_iters=100, tol=0.0, prune=True,
         lab = torch.empty((n,), dtype=torch.int32, device=dev)
     else:
         C, lab = out
-    init_code = INIT_GIVEN if init == "given" else INIT_FORGY
+    if init not in INITS:
+        raise ValueError(f"init must be one of {sorted(INITS)}")
+    init_code = INITS[init]
     if init_code == INIT_GIVEN:
         if C0 is None:
             raise ValueError("init='given' needs C0")
@@ -244,10 +257,12 @@ def fit(X, k, C0=None, init="given", max_iters=100, tol=0.0, prune=True,
     else:
         c0p = None
     hist = torch.empty((max_iters, n), dtype=torch.int32, device=dev) if history else None
+    chist = (torch.empty((max_iters, k, d), dtype=torch.float64, device=dev)
+             if centroid_history else None)
     cnt = np.zeros((max_iters, NCOUNTERS), np.int64) if counters else None
     o = _opts(prune, recheck, check_numeric, seed, None, workspace_cap, hist,
               cnt, poll_every, profile, tile_blocks, tile_resident, autotune,
-              learned, train_iters, train_batches, update)
+              learned, train_iters, train_batches, update, chist)
     st = Stats()
     rc = L.knor_fit(X.data_ptr(), _dtype_code(X), n, d, k, init_code, c0p,
                     max_iters, float(tol), ctypes.byref(o), C.data_ptr(),
@@ -258,6 +273,8 @@ def fit(X, k, C0=None, init="given", max_iters=100, tol=0.0, prune=True,
         s["label_history"] = hist[: st.iters]
     if counters:
         s["counters"] = cnt[: st.iters]
+    if centroid_history:
+        s["centroid_history"] = chist[: st.iters]
     return C, lab, s
 
 

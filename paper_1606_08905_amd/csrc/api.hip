@@ -221,6 +221,7 @@ struct Opts {
   int tile_blocks = 0, tile_resident = 0, autotune = 0;
   int learned = 0, train_iters = 5, train_batches = 16;
   int update = 0;
+  double* centroid_history = nullptr;
 };
 
 static knor_status read_opts(const knor_opts* o, Opts* out) {
@@ -257,6 +258,7 @@ static knor_status read_opts(const knor_opts* o, Opts* out) {
   if (o->train_batches > 0) out->train_batches = o->train_batches;
   if (o->update < 0 || o->update > 1) return KNOR_ERR_INVALID_ARG;
   out->update = o->update;
+  out->centroid_history = o->centroid_history;
   out->tile_blocks = o->tile_blocks;
   out->tile_resident = o->tile_resident;
   out->autotune = o->autotune;
@@ -299,6 +301,26 @@ static std::vector<int64_t> forgy_rows(int64_t n, int k, uint64_t seed) {
     swapped[i] = vj;
     swapped[j] = vi;
     rows[r] = vj;
+  }
+  return rows;
+}
+
+// The first k entries of a front-to-back Fisher-Yates shuffle of 0..n-1:
+// for i = 0 .. k-1, j = i + next() % (n - i), swap slots i and j.
+static std::vector<int64_t> shuffle_first_k(int64_t n, int k, uint64_t seed) {
+  std::unordered_map<int64_t, int64_t> swapped;
+  auto at = [&](int64_t i) {
+    auto it = swapped.find(i);
+    return it == swapped.end() ? i : it->second;
+  };
+  uint64_t st = seed;
+  std::vector<int64_t> rows(k);
+  for (int i = 0; i < k; ++i) {
+    const int64_t j = i + (int64_t)(splitmix64(&st) % (uint64_t)(n - i));
+    const int64_t vi = at(i), vj = at(j);
+    swapped[i] = vj;
+    swapped[j] = vi;
+    rows[i] = vj;
   }
   return rows;
 }
@@ -551,6 +573,12 @@ static knor_status fit_impl(const void* X, knor_dtype dt, int64_t n, int d,
     ar.add((void**)&nbr_idx, sizeof(int) * (size_t)k * kMlpNbr);
     ar.add((void**)&nbr_half, sizeof(float) * (size_t)k * kMlpNbr);
   }
+  void* pp_ws = nullptr;
+  unsigned long long* pp_rnd = nullptr;
+  if (init == KNOR_INIT_KMEANSPP) {
+    ar.add(&pp_ws, kmeanspp_workspace_bytes(n, k));
+    ar.add((void**)&pp_rnd, sizeof(unsigned long long) * (size_t)k);
+  }
   knor_status rs = ar.alloc(s, o.cap);
   if (rs != KNOR_OK) return rs;
   update_plan_init(&plan, n, k, d, upd_ws);
@@ -580,8 +608,17 @@ static knor_status fit_impl(const void* X, knor_dtype dt, int64_t n, int d,
     if (C_init != C_out)
       HIPCHK(hipMemcpyAsync(C_out, C_init, sizeof(double) * (size_t)k * d,
                             hipMemcpyDeviceToDevice, s));
+  } else if (init == KNOR_INIT_KMEANSPP) {
+    std::vector<unsigned long long> rnd(k);
+    uint64_t st_r = o.seed;
+    for (auto& r : rnd) r = splitmix64(&st_r);
+    HIPCHK(hipMemcpyAsync(pp_rnd, rnd.data(), sizeof(unsigned long long) * k,
+                          hipMemcpyHostToDevice, s));
+    HIPCHK(launch_kmeanspp(X, dt, n, d, k, pp_rnd, C_out, pp_ws, s));
+    HIPCHK(hipStreamSynchronize(s));   // `rnd` leaves scope
   } else {
-    std::vector<int64_t> rows = forgy_rows(n, k, o.seed);
+    std::vector<int64_t> rows = init == KNOR_INIT_FORGY ? forgy_rows(n, k, o.seed)
+                                                        : shuffle_first_k(n, k, o.seed);
     HIPCHK(hipMemcpyAsync(rows_dev, rows.data(), sizeof(int64_t) * k,
                           hipMemcpyHostToDevice, s));
     HIPCHK(launch_gather_rows(X, dt, d, rows_dev, k, C_out, s));
@@ -601,6 +638,7 @@ static knor_status fit_impl(const void* X, knor_dtype dt, int64_t n, int d,
     HIPCHK(hipStreamSynchronize(s));          // `th0` leaves scope
   }
   int64_t mlp_step = 0, mlp_queries = 0;
+  std::vector<int64_t> queried((size_t)max_iters, 0);   // survivors sent to the MLP
   bool w3t_ready = false;
 
   Prof prof;
@@ -615,6 +653,9 @@ static knor_status fit_impl(const void* X, knor_dtype dt, int64_t n, int d,
   for (int t = 0; t < max_iters; ++t) {
     prof.iter = t;
     unsigned long long* row = ctr + (size_t)t * ROW_STRIDE;
+    if (o.centroid_history)
+      HIPCHK(hipMemcpyAsync(o.centroid_history + (size_t)t * k * d, C_out,
+                            sizeof(double) * (size_t)k * d, hipMemcpyDeviceToDevice, s));
     AssignJob job{};
     job.X = X; job.dt = dt; job.n = n; job.d = d;
     job.labels = labels_out; job.u = mti ? u : nullptr;
@@ -645,6 +686,7 @@ static knor_status fit_impl(const void* X, knor_dtype dt, int64_t n, int d,
       if (hm[1] == kNotConverged) {
         const int m_tot = hm[0];
         mlp_queries += m_tot;
+        queried[t] = m_tot;
         for (int64_t c0 = 0; c0 < m_tot; c0 += chunk) {
           const int cnt = (int)(m_tot - c0 < chunk ? m_tot - c0 : chunk);
           HIPCHK(launch_gather_std(X, dt, d, dense + c0, cnt, nullptr, mean, istd, Xs_s, s));
@@ -658,6 +700,8 @@ static knor_status fit_impl(const void* X, knor_dtype dt, int64_t n, int d,
           HIPCHK(launch_mlp_propose(H2, W3t, th + ML.b3, hM, k, kpadM, cnt, nullptr,
                                     cand + c0 * kMlpTop, s));
         }
+        prof.end();
+        prof.begin(KNOR_PROF_CERTIFY);
         HIPCHK(launch_cc_neighbors(C_out, ops.CT, k, d, nbr_idx, nbr_half, conv, t, s));
         HIPCHK(launch_mlp_certify(X, dt, d, C_out, nbr_idx, nbr_half, list, seg_cnt, seg_off,
                                   nseg, cand, labels_out, u, dirty, list2, seg_cnt2, row,
@@ -750,6 +794,7 @@ static knor_status fit_impl(const void* X, knor_dtype dt, int64_t n, int d,
       dst[KNOR_CNT_PRUNED_B] = (int64_t)r[ROW_PRUNED_B];
       dst[KNOR_CNT_RECHECKED] = (int64_t)r[ROW_FLAG_HEAD];
       dst[KNOR_CNT_CERTIFIED] = (int64_t)r[ROW_CERTIFIED];
+      dst[KNOR_CNT_QUERIED] = queried[(size_t)i];
     }
   if (st) {
     memset(st, 0, sizeof(*st));
@@ -877,7 +922,7 @@ const char* knor_status_string(knor_status s) {
   return "unknown status";
 }
 
-int32_t knor_version(void) { return 200; }
+int32_t knor_version(void) { return 300; }
 
 knor_status knor_fit(const void* X, knor_dtype dt, int64_t n, int32_t d,
                      int32_t k, knor_init init, const double* C_init,
@@ -891,7 +936,8 @@ knor_status knor_fit(const void* X, knor_dtype dt, int64_t n, int32_t d,
     return KNOR_ERR_INVALID_ARG;
   if (init == KNOR_INIT_GIVEN) {
     if (!C_init) return KNOR_ERR_INVALID_ARG;
-  } else if (init != KNOR_INIT_FORGY) {
+  } else if (init != KNOR_INIT_FORGY && init != KNOR_INIT_SHUFFLE_FIRSTK &&
+             init != KNOR_INIT_KMEANSPP) {
     return KNOR_ERR_INVALID_ARG;
   }
   if (o.update == 1 && dt == KNOR_F64) return KNOR_ERR_UNSUPPORTED;
@@ -919,7 +965,8 @@ knor_status knor_fit_batched(const knor_problem* probs, int32_t count,
   Opts o;
   if (knor_status r = read_opts(opts, &o)) return r;
   if (count < 0 || (count > 0 && !probs)) return KNOR_ERR_INVALID_ARG;
-  if (o.label_history || o.iter_counters || o.profile_ms || o.profile_launches)
+  if (o.label_history || o.iter_counters || o.profile_ms || o.profile_launches ||
+      o.centroid_history)
     return KNOR_ERR_INVALID_ARG;           // per-call arrays: single fits only
   for (int i = 0; i < count; ++i) {
     const knor_problem& p = probs[i];

@@ -432,6 +432,13 @@ hipError_t launch_gather_rows(const void* X, knor_dtype dt, int d,
                               const int64_t* rows, int k, double* C64,
                               hipStream_t s);
 
+// k-means++ seeding (init.hip): rnd holds k SplitMix64 outputs, C receives
+// k x d FP64 centroids; ws has kmeanspp_workspace_bytes(n, k) bytes.
+size_t kmeanspp_workspace_bytes(int64_t n, int k);
+hipError_t launch_kmeanspp(const void* X, knor_dtype dt, int64_t n, int d, int k,
+                           const unsigned long long* rnd, double* C, void* ws,
+                           hipStream_t s);
+
 // Matrix product on the BF16 matrix cores (learned.hip):
 // C[M x N] = op(A)[M x K] op(B)[K x N] (+ bias[N]) (ReLU) (masked by
 // mask > 0); op = transpose when the flag is set; FP32 in memory, operands

@@ -36,7 +36,7 @@ def test_exports_every_declared_symbol(L):
 def test_status_strings(L):
     for code in range(6):
         assert L.knor_status_string(code)
-    assert L.knor_version() >= 200
+    assert L.knor_version() >= 300
 
 
 FAKE = ctypes.c_void_p(0x1000)   # never dereferenced: validation fails first
@@ -53,7 +53,8 @@ def _fit(L, **kw):
 @pytest.mark.parametrize("kw", [
     dict(X=None), dict(dt=9), dict(n=0), dict(d=0), dict(d=257), dict(k=0),
     dict(k=101), dict(k=20000, n=30000), dict(it=0), dict(tol=1.0),
-    dict(tol=-0.1), dict(tol=float("nan")), dict(init=0, C=None), dict(init=5),
+    dict(tol=-0.1), dict(tol=float("nan")), dict(init=0, C=None), dict(init=4),
+    dict(init=-1),
     dict(Cout=None), dict(lab=None), dict(n=1 << 31),
 ])
 def test_fit_rejects_invalid(L, kw):
@@ -209,3 +210,18 @@ def test_binding_update_names():
     with pytest.raises(ValueError):
         knor._update_code("sorted")
     assert knor._update_code("canonical") == 0 and knor._update_code("exact") == 1
+
+
+def test_fit_batched_rejects_centroid_history(L):
+    o = knor.Opts()
+    o.struct_size = ctypes.sizeof(knor.Opts)
+    o.prune = 1
+    o.recheck = 1
+    o.check_numeric = 1
+    o.centroid_history = 0x1000
+    arr = (knor.Problem * 1)(_problem())
+    assert L.knor_fit_batched(arr, 1, ctypes.byref(o), None) == knor.KNOR_ERR_INVALID_ARG
+
+
+def test_binding_init_names():
+    assert knor.INITS == {"given": 0, "forgy": 1, "shuffle_first_k": 2, "kmeans++": 3}

@@ -2,11 +2,10 @@
 outputs the FP64 oracle can compute one by one, and on properties that hold
 at any size:
 
-  labels of iteration t on random rows == the oracle's assignment of those
-  rows at the centroids iteration t used (C_t from fits stopped after t
-  iterations; labels do not depend on where a fit stops);
-  the centroids after iteration 0 == the oracle's canonical update of the
-  full data (exact FP64 means, every row);
+  at every iteration t of a whole fit, the labels of 20000 random rows ==
+  the oracle's assignment of those rows under the centroids C_t iteration t
+  used (from the fit's centroid history), and C_{t+1} == the oracle's
+  canonical update of every row from (labels_t, C_t), bit for bit;
   the returned centroids are the means of the returned labels (the oracle's
   update reproduces them bit for bit);
   a converged fit's labels are a fixed point of the oracle's assignment.
@@ -37,55 +36,54 @@ def _sample(n, m, seed):
     return np.sort(np.random.default_rng(seed).choice(n, size=m, replace=False))
 
 
-def _check_iterations(knor, w, Xd, C0d, iters, rows, **kw):
-    """Labels of iterations 0..iters-1 on `rows` against the oracle, and the
-    first update against the oracle's full canonical update."""
-    _, _, st = knor.fit(Xd, w.k, C0=C0d, max_iters=iters, history=True, **kw)
-    hist = st["label_history"].cpu().numpy()
-    X64s = workloads.to_f64(w.X[rows], w.dtype)
-    C_t = w.C0
-    for t in range(min(iters, st["iters"])):
-        lab_o, _ = oracle.assign(X64s, C_t)
-        assert (hist[t][rows] == lab_o).all(), t
-        if t + 1 < iters:
-            C_t = knor.fit(Xd, w.k, C0=C0d, max_iters=t + 1, **kw)[0].cpu().numpy()
-            if t == 0:
-                C1_o, _ = oracle.update(w.x64(), hist[0], w.C0)
-                assert (C_t == C1_o).all()
-    return st
+def _check_whole_fit(knor, w, Xd, C0d, rows, **kw):
+    """Every iteration t of one fit: the labels of `rows` equal the oracle's
+    assignment under the centroids C_t the iteration used, and C_{t+1} equals
+    the oracle's canonical update of all rows from (labels_t, C_t), bit for
+    bit (C_t from the fit's centroid history)."""
+    C, lab, st = knor.fit(Xd, w.k, C0=C0d, max_iters=w.max_iters, history=True,
+                          centroid_history=True, **kw)
+    iters = st["iters"]
+    H = st["label_history"]
+    CH = st["centroid_history"].cpu().numpy()
+    assert (CH[0] == w.C0).all()
+    X64 = w.x64()
+    X64s = X64[rows]
+    Cfin = C.cpu().numpy()
+    for t in range(iters):
+        Ht = H[t].cpu().numpy()
+        lab_o, _ = oracle.assign(X64s, CH[t])
+        assert (Ht[rows] == lab_o).all(), t
+        Cn, _ = oracle.update(X64, Ht, CH[t])
+        nxt = CH[t + 1] if t + 1 < iters else Cfin
+        assert (nxt == Cn).all(), t
+    assert (lab.cpu().numpy() == H[iters - 1].cpu().numpy()).all()
+    return C, lab, st
 
 
 def test_mixed_precision_full_size():
-    """BF16, n=2e7, d=64, k=256, MTI: three iterations sampled."""
+    """BF16, n=2e7, d=64, k=256, MTI: all 30 iterations."""
     knor = _knor()
     w = workloads.config(3)
     print("CASE mixed full", w.n, flush=True)
     rows = _sample(w.n, 20000, 3)
-    _check_iterations(knor, w, _dev(w.X, "bf16"), _dev(w.C0, "f64"), 3, rows)
+    _, _, st = _check_whole_fit(knor, w, _dev(w.X, "bf16"), _dev(w.C0, "f64"), rows)
+    assert st["iters"] == w.max_iters or st["converged"]
 
 
 def test_learned_full_size():
     """FP32, n=1e7, d=32, k=4096, MTI + learned proposal (trained on
-    iterations 1-5, proposing from iteration 6): iterations 0, 1, 6 sampled;
-    the whole fit equals the one without the proposal."""
+    iterations 1-5, proposing from iteration 6): all 40 iterations; the
+    whole fit equals the one without the proposal."""
     knor = _knor()
     w = workloads.config(5)
     print("CASE learned full", w.n, flush=True)
     Xd, C0d = _dev(w.X, "f32"), _dev(w.C0, "f64")
-    rows = _sample(w.n, 8000, 5)
-    X64s = w.X[rows].astype(np.float64)
-    C, lab, st = knor.fit(Xd, w.k, C0=C0d, max_iters=7, history=True, learned=True)
-    hist = st["label_history"].cpu().numpy()
-    for t in (0, 1, 6):
-        C_t = w.C0 if t == 0 else knor.fit(Xd, w.k, C0=C0d, max_iters=t,
-                                           learned=True)[0].cpu().numpy()
-        lab_o, _ = oracle.assign(X64s, C_t)
-        assert (hist[t][rows] == lab_o).all(), t
-    C1_o, _ = oracle.update(w.x64(), hist[0], w.C0)
-    assert (knor.fit(Xd, w.k, C0=C0d, max_iters=1)[0].cpu().numpy() == C1_o).all()
-    Cm, labm, _ = knor.fit(Xd, w.k, C0=C0d, max_iters=7)
+    rows = _sample(w.n, 20000, 5)
+    C, lab, st = _check_whole_fit(knor, w, Xd, C0d, rows, learned=True)
+    assert st["mlp_queries"] > 0 and st["certified"] > 0
+    Cm, labm, _ = knor.fit(Xd, w.k, C0=C0d, max_iters=w.max_iters)
     assert (C == Cm).all() and (lab == labm).all()
-    assert st["mlp_queries"] > 0
 
 
 def test_batched_full_size():
