@@ -446,7 +446,7 @@ def single_config(a, knor, oracle, workloads):
             out["cpu_baseline"] = cpu_whole_fit(oracle, w, mti=cfg == 2, update=a.update)
         else:
             out["cpu_baseline"] = cpu_sample(oracle, workloads, w, w.C0,
-                                             {3: 0.05, 5: 0.02}[cfg])
+                                             {3: 0.1, 5: 0.3}[cfg])
     return out
 
 
