@@ -158,6 +158,15 @@ typedef struct {
   double* centroid_history; /* DEVICE, optional: max_iters x k x d FP64; row
                                t receives the centroids that iteration t's
                                assignment used (row 0: the initial ones)    */
+  int32_t clause2;      /* MTI Clause 2 (skip centroid j for a point of
+                           cluster a when u (1 + eta) < 1/2 d(c_a, c_j))
+                           applied per block of 64 survivors of one cluster,
+                           sorted by bound: each block scans only its
+                           candidate centroids.  0: on for FP32 points with
+                           1024 <= k <= 8192 (default); 1: off; 2: on for
+                           any k <= 8192 (FP32 points with prune = 1, else
+                           KNOR_ERR_UNSUPPORTED).  Needs k x k FP32 of
+                           workspace.  Labels do not depend on this option */
 } knor_opts;
 
 /* Kernel groups timed by opts->profile_ms. */
@@ -184,6 +193,8 @@ enum {
   KNOR_CNT_RECHECKED = 4, /* points recomputed in FP64                        */
   KNOR_CNT_CERTIFIED = 5, /* survivors decided by a certified proposal        */
   KNOR_CNT_QUERIED = 6,   /* survivors sent to the proposal MLP               */
+  KNOR_CNT_DISTS = 7,     /* point-centroid distances evaluated (tiles, FP64
+                             rechecks, Clause-3 tightening)                   */
   KNOR_NCOUNTERS = 8
 };
 

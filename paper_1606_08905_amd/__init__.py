@@ -32,7 +32,8 @@ INITS = {"given": INIT_GIVEN, "forgy": INIT_FORGY,
          "shuffle_first_k": INIT_SHUFFLE_FIRSTK, "kmeans++": INIT_KMEANSPP}
 NCOUNTERS = 8
 COUNTERS = ("changed", "scanned", "pruned_a", "pruned_b", "rechecked",
-            "certified", "queried")
+            "certified", "queried", "dists")
+CLAUSE2 = {"auto": 0, "off": 1, "on": 2}
 
 
 class KnorError(RuntimeError):
@@ -60,7 +61,8 @@ class Opts(ctypes.Structure):
                 ("train_batches", ctypes.c_int32),
                 ("profile_every", ctypes.c_int32),
                 ("update", ctypes.c_int32),
-                ("centroid_history", ctypes.c_void_p)]
+                ("centroid_history", ctypes.c_void_p),
+                ("clause2", ctypes.c_int32)]
 
 
 NPROF = 10
@@ -113,6 +115,9 @@ def load():
     L.knor_assign.argtypes = [P, ctypes.c_int, i64, i32, P, i32,
                               ctypes.POINTER(Opts), P, P]
     L.knor_assign.restype = ctypes.c_int
+    L.knor_tile_values.argtypes = [P, ctypes.c_int, i64, i32, P, i32,
+                                   ctypes.POINTER(Opts), P, P]
+    L.knor_tile_values.restype = ctypes.c_int
     L.knor_update.argtypes = [P, ctypes.c_int, i64, i32, P, i32, P,
                               ctypes.POINTER(Opts), P, P]
     L.knor_update.restype = ctypes.c_int
@@ -165,7 +170,7 @@ def _opts(prune=True, recheck=1, check_numeric=True, seed=0, stream=None,
           workspace_cap=0, label_history=None, iter_counters=None,
           poll_every=0, profile=None, tile_blocks=0, tile_resident=0,
           autotune=False, learned=False, train_iters=0, train_batches=0,
-          update="canonical", centroid_history=None):
+          update="canonical", centroid_history=None, clause2="auto"):
     torch = _torch()
     if stream is None:
         stream = torch.cuda.current_stream()
@@ -195,6 +200,9 @@ def _opts(prune=True, recheck=1, check_numeric=True, seed=0, stream=None,
     o.update = _update_code(update)
     o.centroid_history = (centroid_history.data_ptr()
                           if centroid_history is not None else None)
+    if clause2 not in CLAUSE2:
+        raise ValueError(f"clause2 must be one of {sorted(CLAUSE2)}")
+    o.clause2 = CLAUSE2[clause2]
     return o
 
 
@@ -212,7 +220,7 @@ def fit(X, k, C0=None, init="given", max_iters=100, tol=0.0, prune=True,
         check_numeric=True, workspace_cap=0, poll_every=0, profile=None,
         tile_blocks=0, tile_resident=0, autotune=False, learned=False,
         train_iters=0, train_batches=0, update="canonical",
-        centroid_history=False):
+        centroid_history=False, clause2="auto"):
     """Lloyd's k-means on the GPU.  Returns (C, labels, stats dict).
 
     init: "given" (C0), "forgy", "shuffle_first_k" or "kmeans++" (the last
@@ -232,6 +240,8 @@ def fit(X, k, C0=None, init="given", max_iters=100, tol=0.0, prune=True,
     per process.  No schedule changes the results.  learned=True adds the
     certified MLP candidate proposal on MTI survivors (train_iters /
     train_batches: 0 = library defaults); it never changes the results.
+    clause2="auto" | "off" | "on": MTI Clause 2 per block of survivors (see
+    include/knor.h; "auto" uses it for FP32 points with 1024 <= k <= 8192).
     update="exact" takes each centroid as the exact member mean rounded once
     (FP32 / BF16 points), moving only changed points between sums when few
     change; "canonical" (default) sums in the canonical order."""
@@ -262,7 +272,7 @@ def fit(X, k, C0=None, init="given", max_iters=100, tol=0.0, prune=True,
     cnt = np.zeros((max_iters, NCOUNTERS), np.int64) if counters else None
     o = _opts(prune, recheck, check_numeric, seed, None, workspace_cap, hist,
               cnt, poll_every, profile, tile_blocks, tile_resident, autotune,
-              learned, train_iters, train_batches, update, chist)
+              learned, train_iters, train_batches, update, chist, clause2)
     st = Stats()
     rc = L.knor_fit(X.data_ptr(), _dtype_code(X), n, d, k, init_code, c0p,
                     max_iters, float(tol), ctypes.byref(o), C.data_ptr(),
@@ -279,7 +289,8 @@ def fit(X, k, C0=None, init="given", max_iters=100, tol=0.0, prune=True,
 
 
 def fit_batched(problems, prune=True, recheck=1, seed=0, check_numeric=True,
-                workspace_cap=0, tile_blocks=0, tile_resident=0, update="canonical"):
+                workspace_cap=0, tile_blocks=0, tile_resident=0, update="canonical",
+                clause2="auto"):
     """knor_fit on each problem of a batch, run concurrently.  problems: list
     of dicts with keys X, k and optionally C0 (None: Forgy from seed + index),
     max_iters (default 100), tol (default 0).  Returns a list of
@@ -306,7 +317,8 @@ def fit_batched(problems, prune=True, recheck=1, seed=0, check_numeric=True,
         a.C_out = C.data_ptr(); a.labels_out = lab.data_ptr()
         outs.append((C, lab))
     o = _opts(prune, recheck, check_numeric, seed, None, workspace_cap,
-              tile_blocks=tile_blocks, tile_resident=tile_resident, update=update)
+              tile_blocks=tile_blocks, tile_resident=tile_resident, update=update,
+              clause2=clause2)
     sts = (Stats * max(1, len(problems)))()
     rc = L.knor_fit_batched(arr, len(problems), ctypes.byref(o), sts)
     _raise(rc)

@@ -179,16 +179,31 @@ Prof::~Prof() {
 // ---------------------------------------------------------------------------
 
 struct Arena {
+  static constexpr int kMaxPieces = 64;
   size_t bytes = 0;
-  std::vector<std::pair<void**, size_t>> want;
-  void add(void** slot, size_t b) {
-    want.push_back({slot, b});
+  int npieces = 0;
+  void** slot[kMaxPieces];
+  size_t size[kMaxPieces];
+  bool overflow = false;
+  void add(void** s, size_t b) {
+    if (npieces == kMaxPieces) { overflow = true; return; }
+    slot[npieces] = s;
+    size[npieces++] = b;
     bytes += (b + 255) & ~(size_t)255;
   }
   char* base = nullptr;
+  bool owned = false;
   hipStream_t stream = nullptr;
+  void place(char* c) {
+    for (int i = 0; i < npieces; ++i) {
+      *slot[i] = c;
+      c += (size[i] + 255) & ~(size_t)255;
+    }
+  }
+  // one stream-ordered allocation, freed (stream-ordered) with the arena
   knor_status alloc(hipStream_t s, size_t cap) {
     stream = s;
+    if (overflow) return KNOR_ERR_INVALID_ARG;
     if (cap && bytes > cap) return KNOR_ERR_OUT_OF_MEMORY;
     if (bytes == 0) return KNOR_OK;
     if (hipMallocAsync((void**)&base, bytes, s) != hipSuccess) {
@@ -196,15 +211,12 @@ struct Arena {
       base = nullptr;
       return KNOR_ERR_OUT_OF_MEMORY;
     }
-    char* c = base;
-    for (auto& w : want) {
-      *w.first = c;
-      c += (w.second + 255) & ~(size_t)255;
-    }
+    owned = true;
+    place(base);
     return KNOR_OK;
   }
   ~Arena() {
-    if (base) (void)hipFreeAsync(base, stream);
+    if (owned && base) (void)hipFreeAsync(base, stream);
   }
 };
 
@@ -222,6 +234,7 @@ struct Opts {
   int learned = 0, train_iters = 5, train_batches = 16;
   int update = 0;
   double* centroid_history = nullptr;
+  int clause2 = 0;
 };
 
 static knor_status read_opts(const knor_opts* o, Opts* out) {
@@ -259,6 +272,8 @@ static knor_status read_opts(const knor_opts* o, Opts* out) {
   if (o->update < 0 || o->update > 1) return KNOR_ERR_INVALID_ARG;
   out->update = o->update;
   out->centroid_history = o->centroid_history;
+  if (o->clause2 < 0 || o->clause2 > 2) return KNOR_ERR_INVALID_ARG;
+  out->clause2 = o->clause2;
   out->tile_blocks = o->tile_blocks;
   out->tile_resident = o->tile_resident;
   out->autotune = o->autotune;
@@ -484,6 +499,14 @@ static knor_status select_tile(CentroidOps& ops, const Opts& o) {
 // fit
 // ---------------------------------------------------------------------------
 
+// Whether a fit's survivor passes use the Clause-2 candidate-list tile:
+// MTI on FP32 points with k <= kCandMaxK, by default from kCandMinK
+// centroids on (below that a survivor's scan of all k is short already).
+static bool cand_enabled(const Opts& o, knor_dtype dt, int k) {
+  if (o.prune != 1 || dt != KNOR_F32 || k > kCandMaxK || o.clause2 == 1) return false;
+  return o.clause2 == 2 || k >= kCandMinK;
+}
+
 static knor_status fit_impl(const void* X, knor_dtype dt, int64_t n, int d,
                             int k, knor_init init, const double* C_init,
                             int max_iters, double tol, const Opts& o,
@@ -495,6 +518,8 @@ static knor_status fit_impl(const void* X, knor_dtype dt, int64_t n, int d,
   const int dp = pad_dim(d);
   const bool mti = o.prune == 1;
   const int nseg = nseg_of_n(n);
+  // Clause 2 per block of survivors (FP32 points, large k by default)
+  const bool use_cand = cand_enabled(o, dt, k);
 
   CentroidOps ops{};
   ops.k = k; ops.kpad = kpad; ops.d = d; ops.dp = dp; ops.dpb = pad_dim_bf16(d);
@@ -531,26 +556,27 @@ static knor_status fit_impl(const void* X, knor_dtype dt, int64_t n, int d,
   if (exact && dt == KNOR_F64) return KNOR_ERR_UNSUPPORTED;
   void* exact_ws = nullptr;
   if (exact) ar.add(&exact_ws, exact_workspace_bytes(n, k, d));
+  // learned proposal (MTI survivors only)
+  const bool learned = o.learned && mti;
+  // the centroids' neighbour rows: the candidate lists and the certificate
+  const bool need_rows = use_cand || learned;
+  float* ccrows = nullptr;
+  void* cand_ws = nullptr;
+  if (need_rows) ar.add((void**)&ccrows, sizeof(float) * (size_t)k * k);
+  if (use_cand) ar.add(&cand_ws, cand_workspace_bytes(n, k));
   ar.add((void**)&dist2, sizeof(double) * (size_t)n);
   ar.add((void**)&sumtmp, sizeof(double) * (size_t)(n / kLeaf + 2));
   ar.add((void**)&objective, sizeof(double));
-  // learned proposal (MTI survivors only)
-  const bool learned = o.learned && mti;
   const int hM = kMlpHidden;
-  const int kpadM = (k + 63) / 64 * 64;
   const int Bt = n < kMlpBatch ? (int)n : kMlpBatch;
-  const int64_t chunk = n < kMlpChunk ? n : kMlpChunk;
   MlpLayout ML{};
+  MlpPacked MP{};
   float *th = nullptr, *am = nullptr, *av = nullptr, *grad = nullptr, *Xs_tr = nullptr;
-  float *Xs_s = nullptr, *H1 = nullptr, *H2 = nullptr;
   int32_t *y_tr = nullptr, *cand = nullptr;
   int *rows_tr = nullptr, *dense = nullptr, *seg_off = nullptr, *list2 = nullptr,
       *seg_cnt2 = nullptr;
-  void* mlp_ws = nullptr;
-  double *mean = nullptr, *istd = nullptr, *loss_dev = nullptr;
-  uint16_t* W3t = nullptr;
-  int* nbr_idx = nullptr;
-  float* nbr_half = nullptr;
+  void *mlp_ws = nullptr, *pack_ws = nullptr;
+  double *mean = nullptr, *istd = nullptr, *loss_dev = nullptr, *stat_part = nullptr;
   if (learned) {
     ML = mlp_layout(d, hM, k);
     for (float** q : {&th, &am, &av, &grad}) ar.add((void**)q, sizeof(float) * (size_t)ML.P);
@@ -561,17 +587,13 @@ static knor_status fit_impl(const void* X, knor_dtype dt, int64_t n, int d,
     ar.add((void**)&mean, sizeof(double) * (size_t)d);
     ar.add((void**)&istd, sizeof(double) * (size_t)d);
     ar.add((void**)&loss_dev, sizeof(double));
-    ar.add((void**)&W3t, sizeof(uint16_t) * (size_t)kpadM * hM);
+    ar.add((void**)&stat_part, standardize_workspace(d));
+    ar.add(&pack_ws, mlp_pack_bytes(d, hM, k));
     ar.add((void**)&dense, sizeof(int) * (size_t)n);
     ar.add((void**)&seg_off, sizeof(int) * (size_t)(nseg + 1));
     ar.add((void**)&list2, sizeof(int) * (size_t)nseg * kSeg);
     ar.add((void**)&seg_cnt2, sizeof(int) * (size_t)nseg);
-    ar.add((void**)&Xs_s, sizeof(float) * (size_t)chunk * d);
-    ar.add((void**)&H1, sizeof(float) * (size_t)chunk * hM);
-    ar.add((void**)&H2, sizeof(float) * (size_t)chunk * hM);
     ar.add((void**)&cand, sizeof(int32_t) * (size_t)n * kMlpTop);
-    ar.add((void**)&nbr_idx, sizeof(int) * (size_t)k * kMlpNbr);
-    ar.add((void**)&nbr_half, sizeof(float) * (size_t)k * kMlpNbr);
   }
   void* pp_ws = nullptr;
   unsigned long long* pp_rnd = nullptr;
@@ -582,6 +604,7 @@ static knor_status fit_impl(const void* X, knor_dtype dt, int64_t n, int d,
   knor_status rs = ar.alloc(s, o.cap);
   if (rs != KNOR_OK) return rs;
   update_plan_init(&plan, n, k, d, upd_ws);
+  if (learned) MP = mlp_pack_layout(d, hM, k, pack_ws);
   ExactPlan xplan{};
   if (exact) exact_plan_init(&xplan, n, k, d, exact_ws);
   int* conv = flagbuf;
@@ -629,7 +652,7 @@ static knor_status fit_impl(const void* X, knor_dtype dt, int64_t n, int d,
   HIPCHK(launch_fill_i32(dirty, k, 1, s));         // every cluster is summed at t = 0
   if (exact) HIPCHK(launch_fill_i32(xplan.prev, n, -1, s));
   if (learned) {
-    HIPCHK(launch_standardize_stats(X, dt, n, d, mean, istd, s));
+    HIPCHK(launch_standardize_stats(X, dt, n, d, mean, istd, stat_part, s));
     std::vector<float> th0 = mlp_init_host(d, hM, k, o.seed);
     HIPCHK(hipMemcpyAsync(th, th0.data(), sizeof(float) * th0.size(),
                           hipMemcpyHostToDevice, s));
@@ -639,7 +662,8 @@ static knor_status fit_impl(const void* X, knor_dtype dt, int64_t n, int d,
   }
   int64_t mlp_step = 0, mlp_queries = 0;
   std::vector<int64_t> queried((size_t)max_iters, 0);   // survivors sent to the MLP
-  bool w3t_ready = false;
+  std::vector<char> cand_used((size_t)max_iters, 0);     // candidate-list tile ran
+  bool packed = false;
 
   Prof prof;
   prof.stream = s;
@@ -666,7 +690,8 @@ static knor_status fit_impl(const void* X, knor_dtype dt, int64_t n, int d,
     if (seg) {
       prof.begin(KNOR_PROF_FILTER);
       HIPCHK(launch_mti_filter(X, dt, n, d, C_out, labels_out, u, drift, s_half,
-                               list, seg_cnt, row - ROW_STRIDE, row, conv, t, s));
+                               list, seg_cnt, row - ROW_STRIDE, row, conv, t,
+                               use_cand ? 1 : 0, s));
       prof.end();
       job.list = list;
       job.seg_cnt = seg_cnt;
@@ -674,9 +699,9 @@ static knor_status fit_impl(const void* X, knor_dtype dt, int64_t n, int d,
     }
     if (learned && seg && t > o.train_iters) {
       prof.begin(KNOR_PROF_LEARNED);
-      if (!w3t_ready) {
-        HIPCHK(launch_mlp_w3t(th + ML.W3, hM, k, kpadM, W3t, s));
-        w3t_ready = true;
+      if (!packed) {                          // training is over
+        HIPCHK(launch_mlp_pack(th, ML, MP, s));
+        packed = true;
       }
       HIPCHK(launch_seg_dense(list, seg_cnt, nseg, seg_off, dense, conv, t, s));
       int hm[2] = {0, 0};
@@ -687,23 +712,11 @@ static knor_status fit_impl(const void* X, knor_dtype dt, int64_t n, int d,
         const int m_tot = hm[0];
         mlp_queries += m_tot;
         queried[t] = m_tot;
-        for (int64_t c0 = 0; c0 < m_tot; c0 += chunk) {
-          const int cnt = (int)(m_tot - c0 < chunk ? m_tot - c0 : chunk);
-          HIPCHK(launch_gather_std(X, dt, d, dense + c0, cnt, nullptr, mean, istd, Xs_s, s));
-          GemmArgs g1{};
-          g1.A = Xs_s; g1.lda = d; g1.B = th + ML.W1; g1.ldb = hM; g1.C = H1; g1.ldc = hM;
-          g1.M = cnt; g1.N = hM; g1.K = d; g1.bias = th + ML.b1; g1.relu = 1;
-          HIPCHK(launch_gemm_bf16(g1, s));
-          GemmArgs g2 = g1;
-          g2.A = H1; g2.lda = hM; g2.B = th + ML.W2; g2.C = H2; g2.K = hM; g2.bias = th + ML.b2;
-          HIPCHK(launch_gemm_bf16(g2, s));
-          HIPCHK(launch_mlp_propose(H2, W3t, th + ML.b3, hM, k, kpadM, cnt, nullptr,
-                                    cand + c0 * kMlpTop, s));
-        }
+        HIPCHK(launch_mlp_forward(X, dt, d, dense, m_tot, nullptr, mean, istd, th, ML, MP,
+                                  cand, s));
         prof.end();
         prof.begin(KNOR_PROF_CERTIFY);
-        HIPCHK(launch_cc_neighbors(C_out, ops.CT, k, d, nbr_idx, nbr_half, conv, t, s));
-        HIPCHK(launch_mlp_certify(X, dt, d, C_out, nbr_idx, nbr_half, list, seg_cnt, seg_off,
+        HIPCHK(launch_mlp_certify(X, dt, d, C_out, k, ccrows, list, seg_cnt, seg_off,
                                   nseg, cand, labels_out, u, dirty, list2, seg_cnt2, row,
                                   conv, t, s));
         job.list = list2;
@@ -711,10 +724,21 @@ static knor_status fit_impl(const void* X, knor_dtype dt, int64_t n, int d,
       }
       prof.end();
     }
+    const bool cand_t = seg && use_cand;
+    cand_used[t] = cand_t ? 1 : 0;
+    if (cand_t && exact) {
+      // the exact update keeps no member order between iterations
+      prof.begin(KNOR_PROF_SORT);
+      HIPCHK(launch_sort(plan, labels_out, nullptr, conv, t, s, 0));
+      prof.end();
+    }
     prof.begin(seg ? KNOR_PROF_ASSIGN_LIST : KNOR_PROF_ASSIGN_DENSE);
-    HIPCHK(launch_assign(ops, job, s));
+    if (cand_t)
+      HIPCHK(launch_tile_cand(ops, job, plan.perm, plan.off, ccrows, cand_ws, s));
+    else
+      HIPCHK(launch_assign(ops, job, s));
     prof.end();
-    if (dt != KNOR_F64) {
+    if (dt != KNOR_F64 && !cand_t) {
       prof.begin(KNOR_PROF_RECHECK);
       HIPCHK(launch_recheck(ops, job, s));
       prof.end();
@@ -745,6 +769,7 @@ static knor_status fit_impl(const void* X, knor_dtype dt, int64_t n, int d,
     ctl.segmented = seg; ctl.n = n;
     if (seg) { ctl.list = list; ctl.seg_cnt = seg_cnt; ctl.nseg = nseg; }
     ctl.delta_only = ctl_delta_only;
+    ctl.full_perm = use_cand ? 1 : 0;
     if (exact)
       HIPCHK(launch_update_exact(plan, xplan, X, dt, labels_out, C_out, C_out, nullptr, &ops,
                                  mti ? drift : nullptr, dirty, &ctl, s, pp));
@@ -753,7 +778,7 @@ static knor_status fit_impl(const void* X, knor_dtype dt, int64_t n, int d,
                            mti ? drift : nullptr, dirty, &ctl, s, pp));
     if (mti) {
       prof.begin(KNOR_PROF_CC);
-      HIPCHK(launch_cc_bounds(ops, s_half, conv, t, s));
+      HIPCHK(launch_cc_bounds(ops, s_half, need_rows ? ccrows : nullptr, conv, t, s));
       prof.end();
     }
     if ((t + 1) % o.poll_every == 0 || t + 1 == max_iters) {
@@ -784,6 +809,14 @@ static knor_status fit_impl(const void* X, knor_dtype dt, int64_t n, int d,
   const int converged = hconv != kNotConverged;
   const int hiters = converged ? hconv + 1 : max_iters;
 
+  // distances evaluated in iteration i: the tiles and FP64 rechecks (all k
+  // per point, or the candidate lists), and Clause-3 tightening
+  auto dists_of = [&](int i) {
+    const unsigned long long* r = &hc[(size_t)i * ROW_STRIDE];
+    const int64_t tighten = (mti && i > 0) ? (n - (int64_t)r[ROW_PRUNED_A]) : 0;
+    if (cand_used[(size_t)i]) return (int64_t)r[ROW_DISTS] + tighten;
+    return ((int64_t)r[ROW_SCANNED] + (int64_t)r[ROW_FLAG_HEAD]) * k + tighten;
+  };
   if (o.iter_counters)
     for (int i = 0; i < hiters; ++i) {
       const unsigned long long* r = &hc[(size_t)i * ROW_STRIDE];
@@ -795,6 +828,7 @@ static knor_status fit_impl(const void* X, knor_dtype dt, int64_t n, int d,
       dst[KNOR_CNT_RECHECKED] = (int64_t)r[ROW_FLAG_HEAD];
       dst[KNOR_CNT_CERTIFIED] = (int64_t)r[ROW_CERTIFIED];
       dst[KNOR_CNT_QUERIED] = queried[(size_t)i];
+      dst[KNOR_CNT_DISTS] = dists_of(i);
     }
   if (st) {
     memset(st, 0, sizeof(*st));
@@ -808,8 +842,7 @@ static knor_status fit_impl(const void* X, knor_dtype dt, int64_t n, int d,
       st->pruned_b += (int64_t)r[ROW_PRUNED_B];
       st->rechecked += (int64_t)r[ROW_FLAG_HEAD];
       st->certified += (int64_t)r[ROW_CERTIFIED];
-      const int64_t tighten = (mti && i > 0) ? (n - (int64_t)r[ROW_PRUNED_A]) : 0;
-      st->dists_computed += ((int64_t)r[ROW_SCANNED] + (int64_t)r[ROW_FLAG_HEAD]) * k + tighten;
+      st->dists_computed += dists_of(i);
     }
     st->mlp_queries = mlp_queries;
     st->objective = hobj;
@@ -884,29 +917,16 @@ knor_status knor_mlp_propose(const float* params, int32_t d, int32_t h,
     return KNOR_ERR_INVALID_ARG;
   if (m == 0) return KNOR_OK;
   const MlpLayout L = mlp_layout(d, h, k);
-  const int kpad = (k + 63) / 64 * 64;
-  const int64_t chunk = m < kMlpChunk ? m : kMlpChunk;
   hipStream_t s = o.stream;
-  float *H1 = nullptr, *H2 = nullptr;
-  uint16_t* W3t = nullptr;
+  void* pack_ws = nullptr;
   Arena ar;
-  ar.add((void**)&H1, sizeof(float) * (size_t)chunk * h);
-  ar.add((void**)&H2, sizeof(float) * (size_t)chunk * h);
-  ar.add((void**)&W3t, sizeof(uint16_t) * (size_t)kpad * h);
+  ar.add(&pack_ws, mlp_pack_bytes(d, h, k));
   if (knor_status r = ar.alloc(s, o.cap)) return r;
-  HIPCHK(launch_mlp_w3t(params + L.W3, h, k, kpad, W3t, s));
-  for (int64_t c0 = 0; c0 < m; c0 += chunk) {
-    const int cnt = (int)(m - c0 < chunk ? m - c0 : chunk);
-    GemmArgs g1{};
-    g1.A = Xs + c0 * d; g1.lda = d; g1.B = params + L.W1; g1.ldb = h; g1.C = H1;
-    g1.ldc = h; g1.M = cnt; g1.N = h; g1.K = d; g1.bias = params + L.b1; g1.relu = 1;
-    HIPCHK(launch_gemm_bf16(g1, s));
-    GemmArgs g2 = g1;
-    g2.A = H1; g2.lda = h; g2.B = params + L.W2; g2.C = H2; g2.K = h; g2.bias = params + L.b2;
-    HIPCHK(launch_gemm_bf16(g2, s));
-    HIPCHK(launch_mlp_propose(H2, W3t, params + L.b3, h, k, kpad, cnt, nullptr,
-                              cand_out + c0 * kMlpTop, s));
-  }
+  const MlpPacked P = mlp_pack_layout(d, h, k, pack_ws);
+  HIPCHK(launch_mlp_pack(params, L, P, s));
+  // Xs is already standardized: no row list, no mean / scale
+  HIPCHK(launch_mlp_forward(Xs, KNOR_F32, d, nullptr, (int)m, nullptr, nullptr, nullptr,
+                            params, L, P, cand_out, s));
   return KNOR_OK;
 }
 
@@ -941,6 +961,8 @@ knor_status knor_fit(const void* X, knor_dtype dt, int64_t n, int32_t d,
     return KNOR_ERR_INVALID_ARG;
   }
   if (o.update == 1 && dt == KNOR_F64) return KNOR_ERR_UNSUPPORTED;
+  if (o.clause2 == 2 && (o.prune != 1 || dt != KNOR_F32 || k > kCandMaxK))
+    return KNOR_ERR_UNSUPPORTED;
   if (o.autotune && dt == KNOR_F32 && !o.tile_blocks && !o.tile_resident) {
     int pb, res;
     if (!tune_lookup(pad_dim(d), (k + 15) / 16 * 16, &pb, &res))
@@ -979,6 +1001,10 @@ knor_status knor_fit_batched(const knor_problem* probs, int32_t count,
   if (o.update == 1)
     for (int i = 0; i < count; ++i)
       if (probs[i].dt == KNOR_F64) return KNOR_ERR_UNSUPPORTED;
+  if (o.clause2 == 2)
+    for (int i = 0; i < count; ++i)
+      if (o.prune != 1 || probs[i].dt != KNOR_F32 || probs[i].k > kCandMaxK)
+        return KNOR_ERR_UNSUPPORTED;
   if (count == 0) return KNOR_OK;
   int dev = 0;
   HIPCHK(hipGetDevice(&dev));
@@ -1089,6 +1115,32 @@ knor_status knor_assign(const void* X, knor_dtype dt, int64_t n, int32_t d,
   HIPCHK(launch_recheck(ops, job, s));
   if (dist2_out)
     HIPCHK(launch_exact_dist2(X, dt, n, d, C, labels_out, dist2_out, s));
+  return KNOR_OK;
+}
+
+knor_status knor_tile_values(const void* X, knor_dtype dt, int64_t n, int32_t d,
+                             const double* C, int32_t k, const knor_opts* opts, float* Y,
+                             double* E) {
+  Opts o;
+  if (knor_status r = read_opts(opts, &o)) return r;
+  if ((n > 0 && (!X || !Y || !E)) || !C || !dtype_ok(dt)) return KNOR_ERR_INVALID_ARG;
+  if (n < 0 || n >= (int64_t)1 << 31 || d < 1 || d > kMaxD || k < 1 || k > kMaxK)
+    return KNOR_ERR_INVALID_ARG;
+  if (dt == KNOR_F64) return KNOR_ERR_UNSUPPORTED;    // FP64 points use no tile
+  if (n == 0) return KNOR_OK;
+  hipStream_t s = o.stream;
+  CentroidOps ops{};
+  ops.k = k; ops.kpad = (k + 15) / 16 * 16; ops.d = d; ops.dp = pad_dim(d);
+  ops.dpb = pad_dim_bf16(d);
+  ops.C64 = const_cast<double*>(C);
+  Arena ar;
+  add_operands(ar, ops, dt);
+  if (knor_status r = ar.alloc(s, o.cap)) return r;
+  HIPCHK(launch_prep_centroids(ops, s));
+  if (dt == KNOR_F32)
+    HIPCHK(launch_tile_values_f32(ops, (const float*)X, n, d, Y, E, s));
+  else
+    HIPCHK(launch_tile_values_bf16(ops, (const uint16_t*)X, n, d, Y, E, s));
   return KNOR_OK;
 }
 

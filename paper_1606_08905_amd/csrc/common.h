@@ -38,7 +38,8 @@ enum {
   SLOT_CAND = 2,                             // MTI stage-A candidates
   SLOT_SURV = 3,                             // MTI survivors
   SLOT_CERTIFIED = 4,                        // survivors certified by a proposal
-  NSLOTQ = 5,
+  SLOT_DISTS = 5,                            // distances of the candidate-list tile
+  NSLOTQ = 6,
   ROW_CHANGED = NSLOTQ * kChgSlots * kSlotStride,   // totals
   ROW_SCANNED = ROW_CHANGED + 1,
   ROW_PRUNED_A = ROW_CHANGED + 2,
@@ -48,6 +49,7 @@ enum {
   ROW_TIGHTEN_NEXT = ROW_CHANGED + 6,        // 1: run stage B next iteration
   ROW_CERTIFIED = ROW_CHANGED + 7,           // survivors decided by a proposal
   ROW_SURVIVED = ROW_CHANGED + 8,            // survivors of the MTI filter
+  ROW_DISTS = ROW_CHANGED + 9,               // distances of the candidate-list tile
   ROW_STRIDE = ROW_CHANGED + 16
 };
 
@@ -87,6 +89,29 @@ __device__ __forceinline__ double dist2_canon(const T* __restrict__ x,
     double t = __dsub_rn(to_f64<T>(x[i]), c[i]);
     double t2 = __dmul_rn(t, t);
     acc = __dadd_rn(acc, t2);
+  }
+  return acc;
+}
+
+// The same value for FP32 rows with d % 4 == 0 (x 16-byte aligned, c
+// 16-byte aligned): four dimensions per step from 16-byte loads, issued
+// ahead of the FP64 chain, which still runs in index order.
+__device__ __forceinline__ double dist2_canon_f32x4(const float* __restrict__ x,
+                                                    const double* __restrict__ c, int d) {
+  double acc = 0.0;
+#pragma unroll 4
+  for (int i = 0; i < d; i += 4) {
+    const float4 xv = *reinterpret_cast<const float4*>(x + i);
+    const double2 c01 = *reinterpret_cast<const double2*>(c + i);
+    const double2 c23 = *reinterpret_cast<const double2*>(c + i + 2);
+    const double t0 = __dsub_rn((double)xv.x, c01.x);
+    acc = __dadd_rn(acc, __dmul_rn(t0, t0));
+    const double t1 = __dsub_rn((double)xv.y, c01.y);
+    acc = __dadd_rn(acc, __dmul_rn(t1, t1));
+    const double t2 = __dsub_rn((double)xv.z, c23.x);
+    acc = __dadd_rn(acc, __dmul_rn(t2, t2));
+    const double t3 = __dsub_rn((double)xv.w, c23.y);
+    acc = __dadd_rn(acc, __dmul_rn(t3, t3));
   }
   return acc;
 }
@@ -294,6 +319,21 @@ hipError_t launch_tile_f32(const CentroidOps& o, const AssignJob& j,
                            hipStream_t s);
 hipError_t launch_tile_bf16(const CentroidOps& o, const AssignJob& j,
                             hipStream_t s);
+// The tiles' FP32 values and bounds (for checking the bound): Y (n x k),
+// E (n); operands as prepared by launch_prep_centroids.
+hipError_t launch_tile_values_f32(const CentroidOps& o, const float* X, int64_t n, int d,
+                                  float* Y, double* E, hipStream_t s);
+hipError_t launch_tile_values_bf16(const CentroidOps& o, const uint16_t* X, int64_t n,
+                                   int d, float* Y, double* E, hipStream_t s);
+// The survivor pass with Clause 2 per block of survivors (tile_cand.hip):
+// FP32 points, k <= kCandMaxK; perm/off: members sorted by (label, index)
+// for every cluster; rows: the neighbour rows of launch_cc_bounds;
+// survivors carry a set sign bit in u; ws: cand_workspace_bytes(n, k).
+constexpr int kCandMaxK = 8192;
+constexpr int kCandMinK = 1024;      // default use from this many centroids
+size_t cand_workspace_bytes(int64_t n, int k);
+hipError_t launch_tile_cand(const CentroidOps& o, const AssignJob& j, const int* perm,
+                            const int* off, const float* rows, void* ws, hipStream_t s);
 
 hipError_t launch_prep_centroids(const CentroidOps& ops, hipStream_t s);
 hipError_t launch_assign(const CentroidOps& ops, const AssignJob& job,
@@ -369,6 +409,7 @@ struct IterCtl {
   const int* seg_cnt = nullptr;
   int nseg = 0;
   int delta_only = 0;                 // exact update: moved points only
+  int full_perm = 0;                  // sort writes every cluster's members
 };
 
 hipError_t launch_update(const UpdatePlan& p, const void* X, knor_dtype dt,
@@ -411,15 +452,22 @@ hipError_t launch_update_exact(const UpdatePlan& p, const ExactPlan& xp, const v
                                const IterCtl* ctl, hipStream_t s, Prof* prof = nullptr);
 
 // MTI.
-hipError_t launch_cc_bounds(const CentroidOps& ops, float* s_half,
+// rows (optional, k x k): row i lists every centroid j (i included) by
+// increasing 1/2 d(c_i, c_j) as float keys: the half distance rounded down,
+// its low cc_rows_bits(k) mantissa bits replaced by j; key & ~mask is a
+// lower bound of the half distance, key & mask the index.
+int cc_rows_bits(int k);
+hipError_t launch_cc_bounds(const CentroidOps& ops, float* s_half, float* rows,
                             const int* conv, int iter, hipStream_t s);
+// mark = 1: survivors leave the pass with the sign bit of their bound set
+// (the candidate-list tile finds them by it), and Clause 3 runs every time.
 hipError_t launch_mti_filter(const void* X, knor_dtype dt, int64_t n, int d,
                              const double* C64, const int32_t* labels,
                              float* u, const float* drift, const float* s_half,
                              int* list, int* seg_cnt,
                              const unsigned long long* prev_row,
                              unsigned long long* row, const int* conv,
-                             int iter, hipStream_t s);
+                             int iter, int mark, hipStream_t s);
 
 // Misc.
 hipError_t launch_check_finite(const void* p, knor_dtype dt, int64_t count,
@@ -467,33 +515,42 @@ hipError_t mlp_train_step(float* th, float* am, float* av, int64_t step,
                           const MlpLayout& L, const float* Xs, const int32_t* y,
                           int B, float lr, float* grad, void* ws, double* loss_dev,
                           hipStream_t s);
-hipError_t launch_mlp_w3t(const float* W3, int h, int k, int kpad, uint16_t* W3t,
-                          hipStream_t s);
-hipError_t launch_mlp_propose(const float* H2, const uint16_t* W3t, const float* b3,
-                              int h, int k, int kpad, int m, const int* mdev,
+// The forward pass with the top-16 epilogue (BF16 copies of the weights in
+// the layout mlp_pack_layout describes, packed by launch_mlp_pack).
+struct MlpPacked {
+  int d, h, k, kpad, KP1;
+  uint16_t *W1b, *W2b, *W3b;
+  float* b3p;
+};
+int mlp_kpad(int k);
+size_t mlp_pack_bytes(int d, int h, int k);
+MlpPacked mlp_pack_layout(int d, int h, int k, void* ws);
+hipError_t launch_mlp_pack(const float* th, const MlpLayout& L, const MlpPacked& P,
+                           hipStream_t s);
+// cand (m x 16): points rows[q] (or q) of X standardized by mean / istd
+// (or taken as they are when null); m = min(m, *mdev) when mdev is given.
+hipError_t launch_mlp_forward(const void* X, knor_dtype dt, int d, const int* rows, int m,
+                              const int* mdev, const double* mean, const double* istd,
+                              const float* th, const MlpLayout& L, const MlpPacked& P,
                               int32_t* cand, hipStream_t s);
+size_t standardize_workspace(int d);
 hipError_t launch_standardize_stats(const void* X, knor_dtype dt, int64_t n, int d,
-                                    double* mean, double* istd, hipStream_t s);
+                                    double* mean, double* istd, double* part, hipStream_t s);
 hipError_t launch_gather_std(const void* X, knor_dtype dt, int d, const int* rows,
                              int64_t count, const int* cdev, const double* mean,
                              const double* istd, float* Xs, hipStream_t s);
 hipError_t launch_seg_dense(const int* list, const int* seg_cnt, int nseg, int* seg_off,
                             int* dense, const int* conv, int iter, hipStream_t s);
 constexpr int kMlpTop = 16;          // candidates per point
-constexpr int kMlpNbr = kMlpTop + 1; // sorted neighbours per centroid: one past
-                                     // the other candidates
-hipError_t launch_cc_neighbors(const double* C64, const double* CT, int k, int d,
-                               int* nbr_idx, float* nbr_half, const int* conv, int iter,
-                               hipStream_t s);
+// nrows: the k x k neighbour rows of launch_cc_bounds
 hipError_t launch_mlp_certify(const void* X, knor_dtype dt, int d, const double* C64,
-                              const int* nbr_idx, const float* nbr_half, const int* list,
+                              int k, const float* nrows, const int* list,
                               const int* seg_cnt, const int* seg_off, int nseg,
                               const int32_t* cand, int32_t* labels, float* u, int* dirty,
                               int* list2, int* seg_cnt2, unsigned long long* row,
                               const int* conv, int iter, hipStream_t s);
 constexpr int kMlpHidden = 256;      // hidden width inside knor_fit
 constexpr int kMlpBatch = 4096;      // training minibatch inside knor_fit
-constexpr int64_t kMlpChunk = 1 << 20;   // proposal rows per pass
 constexpr float kMlpLr = 1e-3f;
 std::vector<float> mlp_init_host(int d, int h, int k, uint64_t seed);
 

@@ -168,20 +168,42 @@ __global__ __launch_bounds__(256) void softmax_ce_kernel(float* __restrict__ Z,
   }
 }
 
-// out[c] = sum over rows of D[r][c] (FP32): thread (q, c) of a workgroup of
-// 64 columns sums rows q, q + 4, ...; the four partial sums are then added.
-__global__ __launch_bounds__(256) void colsum_kernel(const float* __restrict__ D,
-                                                     int rows, int cols,
-                                                     float* __restrict__ out) {
-  __shared__ float part[4][64];
+// out[c] = sum over rows of D[r][c] (FP32) in two stages: workgroup (cb, rb)
+// sums rows rb, rb + kColRB, ... of 64 columns (four row lanes, added in a
+// fixed order) into part[rb][c]; the kColRB partial sums of a column are
+// then added in order.
+constexpr int kColRB = 32;
+
+__global__ __launch_bounds__(256) void colsum_part_kernel(const float* __restrict__ D,
+                                                          int rows, int cols,
+                                                          float* __restrict__ part) {
+  __shared__ float red[4][64];
   const int cl = threadIdx.x & 63, q = threadIdx.x >> 6;
-  const int c = blockIdx.x * 64 + cl;
+  const int c = blockIdx.x * 64 + cl, rb = blockIdx.y;
   float s = 0.0f;
   if (c < cols)
-    for (int r = q; r < rows; r += 4) s += D[(size_t)r * cols + c];
-  part[q][cl] = s;
+    for (int r = rb + kColRB * q; r < rows; r += 4 * kColRB) s += D[(size_t)r * cols + c];
+  red[q][cl] = s;
   __syncthreads();
-  if (q == 0 && c < cols) out[c] = (part[0][cl] + part[1][cl]) + (part[2][cl] + part[3][cl]);
+  if (q == 0 && c < cols)
+    part[(size_t)rb * cols + c] = (red[0][cl] + red[1][cl]) + (red[2][cl] + red[3][cl]);
+}
+
+__global__ __launch_bounds__(256) void colsum_final_kernel(const float* __restrict__ part,
+                                                           int cols, float* __restrict__ out) {
+  const int c = blockIdx.x * 256 + threadIdx.x;
+  if (c >= cols) return;
+  float s = 0.0f;
+  for (int rb = 0; rb < kColRB; ++rb) s += part[(size_t)rb * cols + c];
+  out[c] = s;
+}
+
+static void launch_colsum(const float* D, int rows, int cols, float* part, float* out,
+                          hipStream_t s) {
+  hipLaunchKernelGGL(colsum_part_kernel, dim3((cols + 63) / 64, kColRB), dim3(256), 0, s, D,
+                     rows, cols, part);
+  hipLaunchKernelGGL(colsum_final_kernel, dim3((cols + 255) / 256), dim3(256), 0, s, part, cols,
+                     out);
 }
 
 __global__ __launch_bounds__(256) void mean_kernel(const double* __restrict__ v, int n,
@@ -259,7 +281,7 @@ std::vector<float> mlp_init_host(int d, int h, int k, uint64_t seed) {
 size_t mlp_train_workspace(int d, int h, int k, int B) {
   (void)d;
   return sizeof(float) * ((size_t)B * h * 4 + (size_t)B * k) + sizeof(double) * ((size_t)B + 1) +
-         4096;
+         sizeof(float) * (size_t)kColRB * (k > h ? k : h) + 8192;
 }
 
 // One minibatch: forward, softmax cross-entropy, backward into grad, Adam
@@ -275,7 +297,9 @@ hipError_t mlp_train_step(float* th, float* am, float* av, int64_t step,
   float* D2 = (float*)c; c += sizeof(float) * (size_t)B * h;
   float* D1 = (float*)c; c += sizeof(float) * (size_t)B * h;
   float* Z = (float*)c; c += sizeof(float) * (size_t)B * k;
-  double* lrow = (double*)c;
+  double* lrow = (double*)c; c += sizeof(double) * ((size_t)B + 1);
+  c = (char*)(((uintptr_t)c + 255) & ~(uintptr_t)255);
+  float* cpart = (float*)c;
   hipError_t e;
   auto gemm = [&](const float* A, int lda, int tA, const float* Bm, int ldb, int tB,
                   float* C, int ldc, int M, int N, int K, const float* bias, int relu,
@@ -296,13 +320,13 @@ hipError_t mlp_train_step(float* th, float* am, float* av, int64_t step,
   hipLaunchKernelGGL(mean_kernel, dim3(1), dim3(256), 0, s, lrow, B, loss_dev);
   // backward (Z now holds dZ)
   if ((e = gemm(H2, h, 1, Z, k, 0, grad + L.W3, k, h, k, B, nullptr, 0, nullptr, 0))) return e;
-  hipLaunchKernelGGL(colsum_kernel, dim3((k + 63) / 64), dim3(256), 0, s, Z, B, k, grad + L.b3);
+  launch_colsum(Z, B, k, cpart, grad + L.b3, s);
   if ((e = gemm(Z, k, 0, th + L.W3, k, 1, D2, h, B, h, k, nullptr, 0, H2, h))) return e;
   if ((e = gemm(H1, h, 1, D2, h, 0, grad + L.W2, h, h, h, B, nullptr, 0, nullptr, 0))) return e;
-  hipLaunchKernelGGL(colsum_kernel, dim3((h + 63) / 64), dim3(256), 0, s, D2, B, h, grad + L.b2);
+  launch_colsum(D2, B, h, cpart, grad + L.b2, s);
   if ((e = gemm(D2, h, 0, th + L.W2, h, 1, D1, h, B, h, h, nullptr, 0, H1, h))) return e;
   if ((e = gemm(Xs, d, 1, D1, h, 0, grad + L.W1, h, d, h, B, nullptr, 0, nullptr, 0))) return e;
-  hipLaunchKernelGGL(colsum_kernel, dim3((h + 63) / 64), dim3(256), 0, s, D1, B, h, grad + L.b1);
+  launch_colsum(D1, B, h, cpart, grad + L.b1, s);
   if ((e = hipGetLastError())) return e;
   if (lr > 0.0f) {
     const double c1 = 1.0 / (1.0 - pow(0.9, (double)step));
@@ -314,190 +338,507 @@ hipError_t mlp_train_step(float* th, float* am, float* av, int64_t step,
 }
 
 // ---------------------------------------------------------------------------
-// proposal: last layer on the matrix cores with the subset-argmax epilogue
+// proposal: the whole forward pass in one kernel, top-16 in its epilogue
 // ---------------------------------------------------------------------------
+//
+// Layout of v_mfma_f32_16x16x32_bf16 used by every layer: lane (col, g)
+// (col = lane % 16, g = lane / 16) supplies row col of the A operand and
+// column col of the B operand at K positions 8g .. 8g + 7 of each 32-wide
+// K-step, and receives D[4g + r][col], r = 0..3.  A holds weight rows
+// (output units), B the points' activations (one point per column), so a
+// lane ends a layer with units 16b + 4g + r of its point for every block b.
+// The next layer's B fragment of K-step s is formed in place from blocks
+// 2s and 2s + 1 -- element e of lane group g is unit
+//   perm_unit(32 s + 8 g + e) = 32 s + 16 (e / 4) + 4 g + (e % 4)
+// -- and the BF16 copies of W2 and W3 store their K columns in that order,
+// so no activation crosses lanes.  W3 streams through LDS in chunks of 64
+// classes shared by the workgroup's eight waves.
+//
+// Top-16: a logit z of class j becomes the key z with its low B mantissa
+// bits replaced by (2^B - 1 - j), 2^B >= the padded class count; keys
+// compare as floats, i.e. by z rounded to its leading 23 - B mantissa bits
+// (towards zero), then by the code.  Each lane keeps the 16 largest keys of
+// the classes it sees (a quarter of them) in a descending list updated with
+// one median-of-three per entry; the four lists of a point are merged
+// through LDS into its 16 largest keys.  Candidates are their classes, in
+// decreasing key order (-1 for padding past k).
 
-// W3t[j][i] = bf16(W3[i][j]) (k x h, row stride h), classes past k zero
-__global__ __launch_bounds__(256) void mlp_w3t_kernel(const float* __restrict__ W3,
-                                                      int h, int k, int kpad,
-                                                      uint16_t* __restrict__ W3t) {
-  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (e >= (int64_t)kpad * h) return;
-  const int j = (int)(e / h), i = (int)(e - (int64_t)j * h);
-  W3t[e] = j < k ? f32_bf16_rne(W3[(size_t)i * k + j]) : (uint16_t)0;
+__host__ __device__ constexpr int perm_unit(int pos) {
+  return 32 * (pos >> 5) + 16 * ((pos & 7) >> 2) + 4 * ((pos >> 3) & 3) + (pos & 3);
 }
 
-constexpr int kPropWaves = 8;
-constexpr int kPropCK = 64;        // classes per LDS chunk
+constexpr int kFwdWaves = 8;
+constexpr int kFwdPB = 2;                        // blocks of 16 points per wave
+constexpr int kFwdPoints = kFwdWaves * 16 * kFwdPB;
+constexpr int kFwdRows = 64;                     // weight rows per LDS chunk
+constexpr float kPadLogit = -3.0e38f;            // classes past k
 
-// 16*PB points per wave (rows of H2, m of them); A = W3t rows (classes),
-// B = the points' h2 (BF16 fragments), accumulator seeded with b3.  Lane
-// (c, g) sees classes 4g + r of every block of 16; tracker t = block mod 4.
-template <int KS, int PB>
-__global__ __launch_bounds__(64 * kPropWaves) void mlp_propose_kernel(
-    const float* __restrict__ H2, const uint16_t* __restrict__ W3t,
-    const float* __restrict__ b3, int k, int kpad, int m, const int* __restrict__ mdev,
+// W1b (h x KP1, KP1 = 32 KD >= d; input dims in natural order, zero past d),
+// W2b (h x h) and W3b (kpad x h), both with permuted K columns; b3p (kpad)
+// with kPadLogit past k.
+__global__ __launch_bounds__(256) void mlp_pack_kernel(
+    const float* __restrict__ th, int d, int h, int k, int kpad, int KP1, int64_t oW1,
+    int64_t oW2, int64_t oW3, int64_t ob3, uint16_t* __restrict__ W1b,
+    uint16_t* __restrict__ W2b, uint16_t* __restrict__ W3b, float* __restrict__ b3p) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t n1 = (int64_t)h * KP1, n2 = (int64_t)h * h, n3 = (int64_t)kpad * h;
+  if (e < n1) {
+    const int u = (int)(e / KP1), c = (int)(e - (int64_t)u * KP1);
+    W1b[e] = c < d ? f32_bf16_rne(th[oW1 + (int64_t)c * h + u]) : (uint16_t)0;
+  } else if (e < n1 + n2) {
+    const int64_t q = e - n1;
+    const int v = (int)(q / h), pos = (int)(q - (int64_t)v * h);
+    W2b[q] = f32_bf16_rne(th[oW2 + (int64_t)perm_unit(pos) * h + v]);
+  } else if (e < n1 + n2 + n3) {
+    const int64_t q = e - n1 - n2;
+    const int cl = (int)(q / h), pos = (int)(q - (int64_t)cl * h);
+    W3b[q] = cl < k ? f32_bf16_rne(th[oW3 + (int64_t)perm_unit(pos) * k + cl]) : (uint16_t)0;
+  } else if (e < n1 + n2 + n3 + kpad) {
+    const int cl = (int)(e - n1 - n2 - n3);
+    b3p[cl] = cl < k ? th[ob3 + cl] : kPadLogit;
+  }
+}
+
+// two FP32 values -> one word of two BF16 (nearest even)
+__device__ __forceinline__ uint32_t bf16x2(float lo, float hi) {
+  return (uint32_t)f32_bf16_rne(lo) | ((uint32_t)f32_bf16_rne(hi) << 16);
+}
+
+__device__ __forceinline__ bf8l frag_of(const uint32_t (&w)[4]) {
+  const uint4 v = {w[0], w[1], w[2], w[3]};
+  return __builtin_bit_cast(bf8l, v);
+}
+
+// D-layout block b of a hidden layer (values of units 16b + 4g + r, after
+// bias) -> words of the next layer's B fragment (ReLU, BF16)
+__device__ __forceinline__ void put_block(uint32_t (&w)[4], int half, const f4l& v) {
+  const float a0 = v[0] > 0.f ? v[0] : 0.f, a1 = v[1] > 0.f ? v[1] : 0.f;
+  const float a2 = v[2] > 0.f ? v[2] : 0.f, a3 = v[3] > 0.f ? v[3] : 0.f;
+  w[2 * half] = bf16x2(a0, a1);
+  w[2 * half + 1] = bf16x2(a2, a3);
+}
+
+// Rows [r0, r0 + 64) of a BF16 matrix with row stride H into LDS (row
+// stride H + 8), through registers: load() issues the global loads, store()
+// writes them; rows past nrows read as zero.
+template <int KH>
+struct RowStage {
+  static constexpr int H = 32 * KH, LD = H + 8;
+  static constexpr int PIECES = kFwdRows * H / 8;                 // 16-byte pieces
+  static constexpr int PER = (PIECES + 64 * kFwdWaves - 1) / (64 * kFwdWaves);
+  uint4 v[PER];
+  __device__ void load(const uint16_t* __restrict__ W, int r0, int nrows) {
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      const int e = threadIdx.x + i * 64 * kFwdWaves;
+      const int r = e / (H / 8), q = e - r * (H / 8);
+      v[i] = (e < PIECES && r0 + r < nrows)
+                 ? *reinterpret_cast<const uint4*>(W + (size_t)(r0 + r) * H + q * 8)
+                 : make_uint4(0u, 0u, 0u, 0u);
+    }
+  }
+  __device__ void store(uint16_t* buf) const {
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      const int e = threadIdx.x + i * 64 * kFwdWaves;
+      const int r = e / (H / 8), q = e - r * (H / 8);
+      if (e < PIECES) *reinterpret_cast<uint4*>(&buf[r * LD + q * 8]) = v[i];
+    }
+  }
+};
+
+// descending top-16 list: insert key y (one median of three per entry)
+__device__ __forceinline__ void top16_insert(float (&L)[16], float y) {
+#pragma unroll
+  for (int i = 15; i >= 1; --i) L[i] = __builtin_amdgcn_fmed3f(L[i - 1], L[i], y);
+  L[0] = L[0] > y ? L[0] : y;
+}
+
+// The forward pass of m points (rows[q], or q when rows is null) with the
+// top-16 epilogue.  Inputs are standardized as (x - mean) istd in FP64
+// (mean / istd null: taken as they are), rounded to FP32, then to BF16.
+template <int KD, int KH, typename T>
+__global__ __launch_bounds__(64 * kFwdWaves) void mlp_forward_kernel(
+    const T* __restrict__ X, int d, const int* __restrict__ rows, int m,
+    const int* __restrict__ mdev, const double* __restrict__ mean,
+    const double* __restrict__ istd, const uint16_t* __restrict__ W1b,
+    const float* __restrict__ b1, const uint16_t* __restrict__ W2b,
+    const float* __restrict__ b2, const uint16_t* __restrict__ W3b,
+    const float* __restrict__ b3p, int k, int kpad, int cbits,
     int32_t* __restrict__ cand) {
-  constexpr int H = KS * 32, LD = H + 8;
-  __shared__ __attribute__((aligned(16))) uint16_t sW[kPropCK * LD];
-  __shared__ float sb[kPropCK];
+  constexpr int H = 32 * KH, LD = H + 8, KP1 = 32 * KD, PB = kFwdPB;
+  using RS = RowStage<KH>;
+  extern __shared__ __attribute__((aligned(16))) uint16_t sW[];   // 2 x 64 x LD
   const int mm = mdev ? (m < *mdev ? m : *mdev) : m;
+  const int q0 = blockIdx.x * kFwdPoints;
+  if (q0 >= mm) return;                                           // uniform
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int col = lane & 15, grp = lane >> 4;
-  const int64_t p0 = ((int64_t)blockIdx.x * kPropWaves + wave) * 16 * PB;
-  if ((int64_t)blockIdx.x * kPropWaves * 16 * PB >= mm) return;   // uniform
-  bf8l bx[PB][KS];
+  uint16_t* buf0 = sW;
+  uint16_t* buf1 = sW + kFwdRows * LD;
+
+  // prefetch the first W2 chunk while the inputs and layer 1 run
+  RS pre;
+  pre.load(W2b, 0, H);
+
+  // inputs: K-step s of lane group g holds dims 32 s + 8 g + e
+  bf8l bx[PB][KD];
   bool valid[PB];
 #pragma unroll
   for (int pb = 0; pb < PB; ++pb) {
-    const int64_t p = p0 + pb * 16 + col;
-    valid[pb] = p < mm;
-    const float* hr = H2 + (size_t)(valid[pb] ? p : 0) * H;
+    const int q = q0 + wave * 16 * PB + pb * 16 + col;
+    valid[pb] = q < mm;
+    const int p = valid[pb] ? (rows ? rows[q] : q) : 0;
+    const T* xr = X + (size_t)p * d;
 #pragma unroll
-    for (int s = 0; s < KS; ++s) {
+    for (int s = 0; s < KD; ++s) {
       uint32_t w[4];
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const float lo = valid[pb] ? hr[s * 32 + grp * 8 + 2 * e] : 0.0f;
-        const float hi = valid[pb] ? hr[s * 32 + grp * 8 + 2 * e + 1] : 0.0f;
-        w[e] = (uint32_t)f32_bf16_rne(lo) | ((uint32_t)f32_bf16_rne(hi) << 16);
+      for (int e2 = 0; e2 < 4; ++e2) {
+        float f[2];
+#pragma unroll
+        for (int h2 = 0; h2 < 2; ++h2) {
+          const int c = 32 * s + 8 * grp + 2 * e2 + h2;
+          double v = 0.0;
+          if (valid[pb] && c < d) {
+            v = to_f64<T>(xr[c]);
+            if (mean) v = (v - mean[c]) * istd[c];
+          }
+          f[h2] = (float)v;
+        }
+        w[e2] = bf16x2(f[0], f[1]);
       }
-      const uint4 v4 = {w[0], w[1], w[2], w[3]};
-      bx[pb][s] = __builtin_bit_cast(bf8l, v4);
+      bx[pb][s] = frag_of(w);
     }
   }
-  float best[PB][4];
-  int idx[PB][4];
+
+  // layer 1: W1b rows straight from memory (small; cached)
+  uint32_t h1w[PB][KH][4];
+#pragma unroll
+  for (int ub = 0; ub < H / 16; ++ub) {
+    bf8l a[KD];
+#pragma unroll
+    for (int s = 0; s < KD; ++s)
+      a[s] = *reinterpret_cast<const bf8l*>(W1b + (size_t)(16 * ub + col) * KP1 + 32 * s + 8 * grp);
+    const f4l init = *reinterpret_cast<const f4l*>(b1 + 16 * ub + 4 * grp);
+#pragma unroll
+    for (int pb = 0; pb < PB; ++pb) {
+      f4l acc = init;
+#pragma unroll
+      for (int s = 0; s < KD; ++s)
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[s], bx[pb][s], acc, 0, 0, 0);
+      put_block(h1w[pb][ub >> 1], ub & 1, acc);
+    }
+  }
+  bf8l h1f[PB][KH];
 #pragma unroll
   for (int pb = 0; pb < PB; ++pb)
 #pragma unroll
-    for (int t = 0; t < 4; ++t) { best[pb][t] = -INFINITY; idx[pb][t] = -1; }
-  for (int c0 = 0; c0 < kpad; c0 += kPropCK) {
-    __syncthreads();
-    for (int e = threadIdx.x; e < kPropCK * (H / 8); e += 64 * kPropWaves) {
-      const int r = e / (H / 8), q = e - r * (H / 8);
-      *reinterpret_cast<uint4*>(&sW[r * LD + q * 8]) =
-          *reinterpret_cast<const uint4*>(W3t + (size_t)(c0 + r) * H + q * 8);
+    for (int s = 0; s < KH; ++s) h1f[pb][s] = frag_of(h1w[pb][s]);
+
+  // layer 2: W2b through LDS in chunks of 64 rows
+  uint32_t h2w[PB][KH][4];
+  pre.store(buf0);
+  __syncthreads();
+  constexpr int NC2 = (H + kFwdRows - 1) / kFwdRows;
+#pragma unroll
+  for (int c = 0; c < NC2; ++c) {
+    uint16_t* cur = (c & 1) ? buf1 : buf0;
+    uint16_t* nxt = (c & 1) ? buf0 : buf1;
+    // the next chunk: W2b's next rows, or after the last the first W3b rows
+    if (c + 1 < NC2) pre.load(W2b, (c + 1) * kFwdRows, H);
+    else pre.load(W3b, 0, kpad);
+#pragma unroll
+    for (int bb = 0; bb < kFwdRows / 16; ++bb) {
+      const int vb = c * (kFwdRows / 16) + bb;             // unit block
+      if (vb < H / 16) {
+        bf8l a[KH];
+#pragma unroll
+        for (int s = 0; s < KH; ++s)
+          a[s] = *reinterpret_cast<const bf8l*>(&cur[(16 * bb + col) * LD + 32 * s + 8 * grp]);
+        const f4l init = *reinterpret_cast<const f4l*>(b2 + 16 * vb + 4 * grp);
+#pragma unroll
+        for (int pb = 0; pb < PB; ++pb) {
+          f4l acc = init;
+#pragma unroll
+          for (int s = 0; s < KH; ++s)
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[s], h1f[pb][s], acc, 0, 0, 0);
+          put_block(h2w[pb][vb >> 1], vb & 1, acc);
+        }
+      }
     }
-    for (int e = threadIdx.x; e < kPropCK; e += 64 * kPropWaves)
-      sb[e] = c0 + e < k ? b3[c0 + e] : -INFINITY;
+    pre.store(nxt);
     __syncthreads();
+  }
+  bf8l h2f[PB][KH];
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {            // block t of the chunk: tracker t
-      const int jb = c0 + t * 16;
-      bf8l a[KS];
+  for (int pb = 0; pb < PB; ++pb)
 #pragma unroll
-      for (int s = 0; s < KS; ++s)
-        a[s] = *reinterpret_cast<const bf8l*>(&sW[(t * 16 + col) * LD + s * 32 + grp * 8]);
-      const f4l init = *reinterpret_cast<const f4l*>(&sb[t * 16 + 4 * grp]);
+    for (int s = 0; s < KH; ++s) h2f[pb][s] = frag_of(h2w[pb][s]);
+
+  // layer 3 with the top-16 epilogue; the first W3b chunk is in buffer NC2 & 1
+  float L[PB][16];
+#pragma unroll
+  for (int pb = 0; pb < PB; ++pb)
+#pragma unroll
+    for (int i = 0; i < 16; ++i) L[pb][i] = -INFINITY;
+  const uint32_t cmask = (1u << cbits) - 1u;
+  const int NC3 = kpad / kFwdRows;
+#pragma unroll 1
+  for (int c = 0; c < NC3; ++c) {
+    const int slot = (c + NC2) & 1;
+    uint16_t* cur = slot ? buf1 : buf0;
+    uint16_t* nxt = slot ? buf0 : buf1;
+    if (c + 1 < NC3) pre.load(W3b, (c + 1) * kFwdRows, kpad);
+#pragma unroll
+    for (int bb = 0; bb < kFwdRows / 16; ++bb) {
+      const int cl0 = c * kFwdRows + 16 * bb;
+      bf8l a[KH];
+#pragma unroll
+      for (int s = 0; s < KH; ++s)
+        a[s] = *reinterpret_cast<const bf8l*>(&cur[(16 * bb + col) * LD + 32 * s + 8 * grp]);
+      const f4l init = *reinterpret_cast<const f4l*>(b3p + cl0 + 4 * grp);
       f4l acc[PB];
 #pragma unroll
       for (int pb = 0; pb < PB; ++pb) acc[pb] = init;
 #pragma unroll
-      for (int s = 0; s < KS; ++s)
+      for (int s = 0; s < KH; ++s)
 #pragma unroll
         for (int pb = 0; pb < PB; ++pb)
-          acc[pb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[s], bx[pb][s], acc[pb], 0, 0, 0);
+          acc[pb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[s], h2f[pb][s], acc[pb], 0, 0, 0);
 #pragma unroll
-      for (int pb = 0; pb < PB; ++pb)
+      for (int r = 0; r < 4; ++r) {
+        const uint32_t code = cmask - (uint32_t)(cl0 + 4 * grp + r);
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const float v = acc[pb][r];
-          const bool gt = v > best[pb][t];
-          best[pb][t] = gt ? v : best[pb][t];
-          idx[pb][t] = gt ? jb + 4 * grp + r : idx[pb][t];
+        for (int pb = 0; pb < PB; ++pb) {
+          const float key = __uint_as_float((__float_as_uint(acc[pb][r]) & ~cmask) | code);
+          top16_insert(L[pb], key);
         }
+      }
     }
+    if (c + 1 < NC3) pre.store(nxt);
+    __syncthreads();
   }
+
+  // merge the four lane groups' lists of each point through LDS
+  float* sK = reinterpret_cast<float*>(sW);      // [wave][pb][col][g][16]
 #pragma unroll
   for (int pb = 0; pb < PB; ++pb) {
-    if (!valid[pb]) continue;
-    const int64_t p = p0 + pb * 16 + col;
+    float* dst = sK + ((((size_t)wave * PB + pb) * 16 + col) * 4 + grp) * 16;
 #pragma unroll
-    for (int t = 0; t < 4; ++t) cand[(size_t)p * 16 + 4 * grp + t] = idx[pb][t];
+    for (int i = 0; i < 16; i += 4)
+      *reinterpret_cast<float4*>(dst + i) = make_float4(L[pb][i], L[pb][i + 1], L[pb][i + 2],
+                                                        L[pb][i + 3]);
+  }
+  __syncthreads();
+  if (lane < 16 * PB) {
+    const int pb = lane >> 4, cc = lane & 15;
+    const int q = q0 + wave * 16 * PB + pb * 16 + cc;
+    if (q < mm) {
+      const float* src = sK + (((size_t)wave * PB + pb) * 16 + cc) * 4 * 16;
+      int hd[4] = {0, 0, 0, 0};
+      int32_t out[16];
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        float best = -INFINITY;
+        int bg = 0;
+#pragma unroll
+        for (int g = 0; g < 4; ++g) {
+          const float v = hd[g] < 16 ? src[g * 16 + hd[g]] : -INFINITY;
+          if (v > best) { best = v; bg = g; }
+        }
+#pragma unroll
+        for (int g = 0; g < 4; ++g) hd[g] += (g == bg) ? 1 : 0;
+        const int j = (int)(cmask - (__float_as_uint(best) & cmask));
+        out[i] = (best == -INFINITY || j >= k) ? -1 : j;
+      }
+      int4* o4 = reinterpret_cast<int4*>(cand + (size_t)q * kMlpTop);
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+        o4[i] = make_int4(out[4 * i], out[4 * i + 1], out[4 * i + 2], out[4 * i + 3]);
+    }
   }
 }
 
-hipError_t launch_mlp_propose(const float* H2, const uint16_t* W3t, const float* b3,
-                              int h, int k, int kpad, int m, const int* mdev,
+// padded class count and code bits of the proposal
+int mlp_kpad(int k) { return (k + kFwdRows - 1) / kFwdRows * kFwdRows; }
+static int code_bits(int kpad) {
+  int b = 0;
+  while ((1 << b) < kpad) ++b;
+  return b;
+}
+static int kd_of(int d) {
+  int kd = 1;
+  while (32 * kd < d) kd *= 2;
+  return kd;
+}
+
+size_t mlp_pack_bytes(int d, int h, int k) {
+  const int kpad = mlp_kpad(k), KP1 = 32 * kd_of(d);
+  auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
+  return al(sizeof(uint16_t) * (size_t)h * KP1) + al(sizeof(uint16_t) * (size_t)h * h) +
+         al(sizeof(uint16_t) * (size_t)kpad * h) + al(sizeof(float) * (size_t)kpad);
+}
+
+MlpPacked mlp_pack_layout(int d, int h, int k, void* ws) {
+  MlpPacked P{};
+  P.d = d; P.h = h; P.k = k; P.kpad = mlp_kpad(k); P.KP1 = 32 * kd_of(d);
+  auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
+  char* c = (char*)ws;
+  P.W1b = (uint16_t*)c; c += al(sizeof(uint16_t) * (size_t)h * P.KP1);
+  P.W2b = (uint16_t*)c; c += al(sizeof(uint16_t) * (size_t)h * h);
+  P.W3b = (uint16_t*)c; c += al(sizeof(uint16_t) * (size_t)P.kpad * h);
+  P.b3p = (float*)c;
+  return P;
+}
+
+hipError_t launch_mlp_pack(const float* th, const MlpLayout& L, const MlpPacked& P,
+                           hipStream_t s) {
+  const int64_t tot = (int64_t)L.h * P.KP1 + (int64_t)L.h * L.h + (int64_t)P.kpad * L.h + P.kpad;
+  hipLaunchKernelGGL(mlp_pack_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s,
+                     th, L.d, L.h, L.k, P.kpad, P.KP1, L.W1, L.W2, L.W3, L.b3, P.W1b, P.W2b,
+                     P.W3b, P.b3p);
+  return hipGetLastError();
+}
+
+template <int KD, int KH, typename T>
+static hipError_t fwd_launch(const T* X, int d, const int* rows, int m, const int* mdev,
+                             const double* mean, const double* istd, const float* th,
+                             const MlpLayout& L, const MlpPacked& P, int32_t* cand,
+                             hipStream_t s) {
+  constexpr int LD = 32 * KH + 8;
+  const size_t lds_w = sizeof(uint16_t) * 2 * kFwdRows * LD;
+  const size_t lds_k = sizeof(float) * kFwdWaves * kFwdPB * 16 * 4 * 16;
+  const size_t lds = lds_w > lds_k ? lds_w : lds_k;
+  hipError_t e = hipFuncSetAttribute(
+      reinterpret_cast<const void*>(&mlp_forward_kernel<KD, KH, T>),
+      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  const int grid = (m + kFwdPoints - 1) / kFwdPoints;
+  hipLaunchKernelGGL((mlp_forward_kernel<KD, KH, T>), dim3(grid), dim3(64 * kFwdWaves), lds, s,
+                     X, d, rows, m, mdev, mean, istd, P.W1b, th + L.b1, P.W2b, th + L.b2,
+                     P.W3b, P.b3p, L.k, P.kpad, code_bits(P.kpad), cand);
+  return hipGetLastError();
+}
+
+template <int KD, typename T>
+static hipError_t fwd_kh(const T* X, int d, const int* rows, int m, const int* mdev,
+                         const double* mean, const double* istd, const float* th,
+                         const MlpLayout& L, const MlpPacked& P, int32_t* cand, hipStream_t s) {
+  switch (L.h) {
+    case 32: return fwd_launch<KD, 1, T>(X, d, rows, m, mdev, mean, istd, th, L, P, cand, s);
+    case 64: return fwd_launch<KD, 2, T>(X, d, rows, m, mdev, mean, istd, th, L, P, cand, s);
+    case 128: return fwd_launch<KD, 4, T>(X, d, rows, m, mdev, mean, istd, th, L, P, cand, s);
+    case 256: return fwd_launch<KD, 8, T>(X, d, rows, m, mdev, mean, istd, th, L, P, cand, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+template <typename T>
+static hipError_t fwd_kd(const T* X, int d, const int* rows, int m, const int* mdev,
+                         const double* mean, const double* istd, const float* th,
+                         const MlpLayout& L, const MlpPacked& P, int32_t* cand, hipStream_t s) {
+  switch (P.KP1 / 32) {
+    case 1: return fwd_kh<1, T>(X, d, rows, m, mdev, mean, istd, th, L, P, cand, s);
+    case 2: return fwd_kh<2, T>(X, d, rows, m, mdev, mean, istd, th, L, P, cand, s);
+    case 4: return fwd_kh<4, T>(X, d, rows, m, mdev, mean, istd, th, L, P, cand, s);
+    case 8: return fwd_kh<8, T>(X, d, rows, m, mdev, mean, istd, th, L, P, cand, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_mlp_forward(const void* X, knor_dtype dt, int d, const int* rows, int m,
+                              const int* mdev, const double* mean, const double* istd,
+                              const float* th, const MlpLayout& L, const MlpPacked& P,
                               int32_t* cand, hipStream_t s) {
-  constexpr int PB = 2;
-  const int per_wg = kPropWaves * 16 * PB;
-  const int grid = (m + per_wg - 1) / per_wg;
-  if (grid <= 0) return hipSuccess;
-  switch (h) {
-    case 32: hipLaunchKernelGGL((mlp_propose_kernel<1, PB>), dim3(grid), dim3(64 * kPropWaves), 0, s, H2, W3t, b3, k, kpad, m, mdev, cand); break;
-    case 64: hipLaunchKernelGGL((mlp_propose_kernel<2, PB>), dim3(grid), dim3(64 * kPropWaves), 0, s, H2, W3t, b3, k, kpad, m, mdev, cand); break;
-    case 128: hipLaunchKernelGGL((mlp_propose_kernel<4, PB>), dim3(grid), dim3(64 * kPropWaves), 0, s, H2, W3t, b3, k, kpad, m, mdev, cand); break;
-    case 256: hipLaunchKernelGGL((mlp_propose_kernel<8, PB>), dim3(grid), dim3(64 * kPropWaves), 0, s, H2, W3t, b3, k, kpad, m, mdev, cand); break;
-    default: return hipErrorInvalidValue;
+  if (m <= 0) return hipSuccess;
+  switch (dt) {
+    case KNOR_F32:
+      return fwd_kd<float>((const float*)X, d, rows, m, mdev, mean, istd, th, L, P, cand, s);
+    case KNOR_F64:
+      return fwd_kd<double>((const double*)X, d, rows, m, mdev, mean, istd, th, L, P, cand, s);
+    case KNOR_BF16:
+      return fwd_kd<uint16_t>((const uint16_t*)X, d, rows, m, mdev, mean, istd, th, L, P, cand,
+                              s);
   }
-  return hipGetLastError();
-}
-
-hipError_t launch_mlp_w3t(const float* W3, int h, int k, int kpad, uint16_t* W3t,
-                          hipStream_t s) {
-  const int64_t tot = (int64_t)kpad * h;
-  hipLaunchKernelGGL(mlp_w3t_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s,
-                     W3, h, k, kpad, W3t);
-  return hipGetLastError();
+  return hipErrorInvalidValue;
 }
 
 // ---------------------------------------------------------------------------
 // inputs of the proposal and the certificate
 // ---------------------------------------------------------------------------
 
-// mean and 1/std per dimension in FP64 (population std; 0 -> 1): one
-// workgroup per dimension.
+// mean and 1/std per dimension in FP64 (population std; 0 -> 1), in two
+// passes over X (sum, then sum of squared deviations), each split over a
+// fixed grid of row ranges: thread (rl, c) of a workgroup sums dimension c
+// over rows rl, rl + RL, ... of its range; the RL partial sums of the
+// workgroup, then the workgroups' sums, are added in a fixed order, so the
+// result does not depend on scheduling.
+constexpr int kStatBlocks = 1024;
+
 template <typename T>
-__global__ __launch_bounds__(256) void standardize_stats_kernel(
-    const T* __restrict__ X, int64_t n, int d, double* __restrict__ mean,
-    double* __restrict__ istd) {
+__global__ __launch_bounds__(256) void stats_partial_kernel(
+    const T* __restrict__ X, int64_t n, int d, const double* __restrict__ mean,
+    double* __restrict__ part) {
   __shared__ double red[256];
-  const int i = blockIdx.x;
+  const int RL = 256 / d;                      // d <= 256
+  const int rl = threadIdx.x / d, c = threadIdx.x - rl * d;
+  const int64_t per = (n + gridDim.x - 1) / gridDim.x;
+  const int64_t r0 = (int64_t)blockIdx.x * per;
+  const int64_t r1 = r0 + per < n ? r0 + per : n;
   double s = 0.0;
-  for (int64_t p = threadIdx.x; p < n; p += 256) s += to_f64<T>(X[(size_t)p * d + i]);
+  if (rl < RL) {
+    const double mu = mean ? mean[c] : 0.0;
+    for (int64_t r = r0 + rl; r < r1; r += RL) {
+      const double v = to_f64<T>(X[(size_t)r * d + c]);
+      s += mean ? (v - mu) * (v - mu) : v;
+    }
+  }
   red[threadIdx.x] = s;
   __syncthreads();
-  for (int st = 128; st > 0; st >>= 1) {
-    if (threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
-    __syncthreads();
-  }
-  const double mu = red[0] / (double)n;
-  __syncthreads();
-  double q = 0.0;
-  for (int64_t p = threadIdx.x; p < n; p += 256) {
-    const double t = to_f64<T>(X[(size_t)p * d + i]) - mu;
-    q += t * t;
-  }
-  red[threadIdx.x] = q;
-  __syncthreads();
-  for (int st = 128; st > 0; st >>= 1) {
-    if (threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) {
-    const double sd = sqrt(red[0] / (double)n);
-    mean[i] = mu;
-    istd[i] = sd > 0.0 ? 1.0 / sd : 1.0;
+  if (threadIdx.x < d) {
+    double t = 0.0;
+    for (int q = 0; q < RL; ++q) t += red[q * d + threadIdx.x];
+    part[(size_t)blockIdx.x * d + threadIdx.x] = t;
   }
 }
 
+// mode 0: mean[c] = sum / n; mode 1: istd[c] = 1 / sqrt(sum / n) (1 if 0)
+__global__ __launch_bounds__(256) void stats_final_kernel(const double* __restrict__ part,
+                                                          int nb, int d, int64_t n, int mode,
+                                                          double* __restrict__ out) {
+  const int c = threadIdx.x;
+  if (c >= d) return;
+  double t = 0.0;
+  for (int b = 0; b < nb; ++b) t += part[(size_t)b * d + c];
+  if (mode == 0) {
+    out[c] = t / (double)n;
+  } else {
+    const double sd = sqrt(t / (double)n);
+    out[c] = sd > 0.0 ? 1.0 / sd : 1.0;
+  }
+}
+
+size_t standardize_workspace(int d) { return sizeof(double) * (size_t)kStatBlocks * d; }
+
+template <typename T>
+static void stats_t(const T* X, int64_t n, int d, double* mean, double* istd, double* part,
+                    hipStream_t s) {
+  const int nb = (int)(n < kStatBlocks ? (n < 1 ? 1 : n) : kStatBlocks);
+  hipLaunchKernelGGL(stats_partial_kernel<T>, dim3(nb), dim3(256), 0, s, X, n, d,
+                     (const double*)nullptr, part);
+  hipLaunchKernelGGL(stats_final_kernel, dim3(1), dim3(256), 0, s, part, nb, d, n, 0, mean);
+  hipLaunchKernelGGL(stats_partial_kernel<T>, dim3(nb), dim3(256), 0, s, X, n, d,
+                     (const double*)mean, part);
+  hipLaunchKernelGGL(stats_final_kernel, dim3(1), dim3(256), 0, s, part, nb, d, n, 1, istd);
+}
+
 hipError_t launch_standardize_stats(const void* X, knor_dtype dt, int64_t n, int d,
-                                    double* mean, double* istd, hipStream_t s) {
+                                    double* mean, double* istd, double* part, hipStream_t s) {
   switch (dt) {
-    case KNOR_F32:
-      hipLaunchKernelGGL(standardize_stats_kernel<float>, dim3(d), dim3(256), 0, s,
-                         (const float*)X, n, d, mean, istd);
-      break;
-    case KNOR_F64:
-      hipLaunchKernelGGL(standardize_stats_kernel<double>, dim3(d), dim3(256), 0, s,
-                         (const double*)X, n, d, mean, istd);
-      break;
-    case KNOR_BF16:
-      hipLaunchKernelGGL(standardize_stats_kernel<uint16_t>, dim3(d), dim3(256), 0, s,
-                         (const uint16_t*)X, n, d, mean, istd);
-      break;
+    case KNOR_F32: stats_t((const float*)X, n, d, mean, istd, part, s); break;
+    case KNOR_F64: stats_t((const double*)X, n, d, mean, istd, part, s); break;
+    case KNOR_BF16: stats_t((const uint16_t*)X, n, d, mean, istd, part, s); break;
   }
   return hipGetLastError();
 }
@@ -591,178 +932,129 @@ hipError_t launch_seg_dense(const int* list, const int* seg_cnt, int nseg, int* 
   return hipGetLastError();
 }
 
-// Each centroid's kMlpNbr nearest other centroids, in increasing (D, j)
-// order, with a rounded-down half of their distance: nbr_idx[i][t],
-// nbr_half[i][t] (index -1 and +inf past the k - 1 others).  One workgroup
-// per centroid: every thread keeps a sorted list of its own nearest
-// kMlpNbr, then kMlpNbr rounds of a workgroup minimum over the list heads.
-__global__ __launch_bounds__(256) void cc_neighbors_kernel(
-    const double* __restrict__ C64, const double* __restrict__ CT, int k, int d,
-    int* __restrict__ nbr_idx, float* __restrict__ nbr_half,
-    const int* __restrict__ conv, int iter) {
-  __shared__ double hd[256];
-  __shared__ int hj[256], hw[256];
-  if (*conv < iter) return;
-  const int i = blockIdx.x;
-  const double* ci = C64 + (size_t)i * d;
-  double ld[kMlpNbr];
-  int lj[kMlpNbr];
-#pragma unroll
-  for (int t = 0; t < kMlpNbr; ++t) { ld[t] = INFINITY; lj[t] = 0x7fffffff; }
-  for (int j = threadIdx.x; j < k; j += 256) {
-    if (j == i) continue;
-    double acc = 0.0;
-    for (int dim = 0; dim < d; ++dim) {
-      const double t = __dsub_rn(ci[dim], CT[(size_t)dim * k + j]);
-      acc = __dadd_rn(acc, __dmul_rn(t, t));
-    }
-    // insert (acc, j) into the sorted list (j increases, so ties keep order)
-    if (acc < ld[kMlpNbr - 1]) {
-#pragma unroll
-      for (int t = kMlpNbr - 1; t >= 0; --t) {
-        const bool above = t > 0 && acc < ld[t - 1];
-        const bool here = acc < ld[t];
-        const double nd = above ? ld[t - 1] : acc;
-        const int nj = above ? lj[t - 1] : j;
-        ld[t] = here ? nd : ld[t];
-        lj[t] = here ? nj : lj[t];
-      }
-    }
-  }
-  int head = 0;
-  for (int r = 0; r < kMlpNbr; ++r) {
-    double v = INFINITY;
-    int vj = 0x7fffffff;
-#pragma unroll
-    for (int t = 0; t < kMlpNbr; ++t)
-      if (t == head) { v = ld[t]; vj = lj[t]; }
-    hd[threadIdx.x] = v;
-    hj[threadIdx.x] = vj;
-    hw[threadIdx.x] = threadIdx.x;
-    __syncthreads();
-    for (int st = 128; st > 0; st >>= 1) {
-      if (threadIdx.x < st) {
-        const double od = hd[threadIdx.x + st];
-        const int oj = hj[threadIdx.x + st];
-        if (od < hd[threadIdx.x] || (od == hd[threadIdx.x] && oj < hj[threadIdx.x])) {
-          hd[threadIdx.x] = od;
-          hj[threadIdx.x] = oj;
-          hw[threadIdx.x] = hw[threadIdx.x + st];
-        }
-      }
-      __syncthreads();
-    }
-    const double m = hd[0];
-    const int mj = hj[0], mw = hw[0];
-    if (threadIdx.x == 0) {
-      const bool ok = m < INFINITY;
-      nbr_idx[(size_t)i * kMlpNbr + r] = ok ? mj : -1;
-      nbr_half[(size_t)i * kMlpNbr + r] =
-          ok ? f32_down(0.5 * sqrt(m) * (1.0 - (double)(d + 8) * 2.220446049250313e-16))
-             : INFINITY;
-    }
-    if (threadIdx.x == mw && m < INFINITY) ++head;
-    __syncthreads();
-  }
-}
-
-hipError_t launch_cc_neighbors(const double* C64, const double* CT, int k, int d,
-                               int* nbr_idx, float* nbr_half, const int* conv, int iter,
-                               hipStream_t s) {
-  hipLaunchKernelGGL(cc_neighbors_kernel, dim3(k), dim3(256), 0, s, C64, CT, k, d,
-                     nbr_idx, nbr_half, conv, iter);
-  return hipGetLastError();
-}
-
-// The certificate.  One workgroup per segment, one lane per survivor (256
-// per pass).  c* = the candidate with the smallest canonical FP64 distance
-// (lowest index on ties); h = the rounded-down half distance from c* to its
-// nearest centroid outside the candidate set (the first such entry of c*'s
-// sorted neighbour list; +inf when every other centroid is a candidate).
-// Accept iff ub (1 + eta) < h, ub an upper bound of d(x, c*) rounded up to
-// FP32: every candidate is compared in the FP64 definition itself, and every
-// other centroid j has d(x, j) >= d(c*, j) - d(x, c*) > ub (1 + 2 eta).
+// The certificate.  One workgroup per segment; a wave takes 4 survivors at a
+// time, 16 lanes per survivor, one lane per candidate: each lane evaluates
+// its candidate's canonical FP64 distance, the 16 lanes reduce to c* (the
+// smallest distance, lowest index on ties).  c*'s neighbour row (every
+// centroid by increasing lower bound of its half distance to c*, c* itself
+// first or among its exact duplicates) is then read from the front: lane t
+// tests entry t (lanes 0 and 1 also entries 16 and 17) against the
+// candidate set, which contains c*; h = the bound of the first entry that
+// is not a candidate (+inf when the row ends first: every centroid is a
+// candidate).  With 16 candidates, 18 entries always reach one.  Accept iff
+// ub (1 + eta) < h, ub an upper bound of d(x, c*) rounded up to FP32: every
+// candidate is compared in the FP64 definition itself, and every other
+// centroid j has d(x, j) >= d(c*, j) - d(x, c*) > ub (1 + 2 eta).
 // Certified points take c* (and ub as their MTI bound); the others are
-// appended, in segment order, to list2.
+// appended to list2 (order within a segment is immaterial to every later
+// pass).
 template <typename T>
 __global__ __launch_bounds__(256) void mlp_certify_kernel(
     const T* __restrict__ X, int d, const double* __restrict__ C64,
-    const int* __restrict__ nbr_idx, const float* __restrict__ nbr_half,
+    int k, const float* __restrict__ nrows, int ib,
     const int* __restrict__ list, const int* __restrict__ seg_cnt,
     const int* __restrict__ seg_off, const int32_t* __restrict__ cand,
     int32_t* __restrict__ labels, float* __restrict__ ub_out, int* __restrict__ dirty,
     int* __restrict__ list2, int* __restrict__ seg_cnt2,
-    unsigned long long* __restrict__ row, const int* __restrict__ conv, int iter) {
-  __shared__ int wcnt[4];
+    unsigned long long* __restrict__ row, const int* __restrict__ conv, int iter, int vec4) {
   __shared__ int run;
   if (*conv < iter) return;
   const int b = blockIdx.x;
   const int cnt = seg_cnt[b], o = seg_off[b];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int ps = lane >> 4, cs = lane & 15;
+  const uint64_t lt = lanemask_lt();
   if (threadIdx.x == 0) run = 0;
   __syncthreads();
   unsigned long long certified = 0, changes = 0;
-  for (int q0 = 0; q0 < cnt; q0 += 256) {
-    const int q = q0 + threadIdx.x;
+  for (int q0 = wave * 4; q0 < cnt; q0 += 16) {
+    const int q = q0 + ps;
     const bool live = q < cnt;
+    const int p = live ? list[(size_t)b * kSeg + q] : 0;
+    const int j = live ? cand[(size_t)(o + q) * kMlpTop + cs] : -1;
+    double D = INFINITY;
+    if (j >= 0) {
+      if constexpr (sizeof(T) == 4) {
+        if (vec4)
+          D = dist2_canon_f32x4(reinterpret_cast<const float*>(X) + (size_t)p * d,
+                                C64 + (size_t)j * d, d);
+        else
+          D = dist2_canon<T>(X + (size_t)p * d, C64 + (size_t)j * d, d);
+      } else {
+        D = dist2_canon<T>(X + (size_t)p * d, C64 + (size_t)j * d, d);
+      }
+    }
+    double best = D;
+    int bj = j >= 0 ? j : 0x7fffffff;
+#pragma unroll
+    for (int off = 1; off < 16; off <<= 1) {
+      const double ob = __shfl_xor(best, off);
+      const int oj = __shfl_xor(bj, off);
+      if (ob < best || (ob == best && oj < bj)) { best = ob; bj = oj; }
+    }
+    const bool have = live && bj != 0x7fffffff;
+    // entries cs and (lanes 0, 1 of the slot) 16 + cs of c*'s row:
+    // status 0 = a candidate, 1 = not a candidate, 2 = past the row's end
+    const uint32_t mask = (1u << ib) - 1u;
+    const float* nr = nrows + (size_t)(have ? bj : 0) * k;
+    const int e0 = cs, e1 = cs < 2 ? 16 + cs : -1;
+    const float k0 = (have && e0 < k) ? nr[e0] : INFINITY;
+    const float k1 = (have && e1 >= 0 && e1 < k) ? nr[e1] : INFINITY;
+    const int nb0 = (have && e0 < k) ? (int)(__float_as_uint(k0) & mask) : -1;
+    const int nb1 = (have && e1 >= 0 && e1 < k) ? (int)(__float_as_uint(k1) & mask) : -1;
+    bool in0 = false, in1 = false;
+#pragma unroll
+    for (int u = 0; u < kMlpTop; ++u) {      // every lane takes part
+      const int cu = __shfl(j, (lane & ~15) + u);
+      in0 |= cu == nb0;
+      in1 |= cu == nb1;
+    }
+    const bool end0 = !(have && e0 < k), end1 = !(have && e1 >= 0 && e1 < k);
+    const int st0 = !have ? 0 : (end0 ? 2 : (in0 ? 0 : 1));
+    const int st1 = !have || e1 < 0 ? 0 : (end1 ? 2 : (in1 ? 0 : 1));
+    const float h0 = st0 == 1 ? __uint_as_float(__float_as_uint(k0) & ~mask) : INFINITY;
+    const float h1 = st1 == 1 ? __uint_as_float(__float_as_uint(k1) & ~mask) : INFINITY;
+    // the first entry in row order whose status is not "candidate": among
+    // entries 0..15, else entry 16, else entry 17 (which cannot be a
+    // candidate when the first 17 entries all were: rejected if it were)
+    const uint64_t stop = __ballot(st0 != 0);
+    const uint64_t stop1 = __ballot(st1 != 0);
+    const uint32_t mine = (uint32_t)((stop >> (lane & ~15)) & 0xffffu);
+    const uint32_t mine1 = (uint32_t)((stop1 >> (lane & ~15)) & 0x3u);
+    const int src = mine ? (lane & ~15) + (__ffs((int)mine) - 1) : (lane & ~15);
+    const int src1 = (lane & ~15) + ((mine1 & 1u) ? 0 : 1);
+    const float hs0 = __shfl(h0, src);
+    const float hs1 = __shfl(h1, src1);
+    const float hs = mine ? hs0 : (mine1 ? hs1 : 0.0f);
+    const float h = hs;                        // +inf when that entry ends the row
     bool cert = false;
-    int p = 0;
-    if (live) {
-      p = list[(size_t)b * kSeg + q];
-      int cj[kMlpTop];
-      const int4* cr = reinterpret_cast<const int4*>(cand + (size_t)(o + q) * kMlpTop);
-#pragma unroll
-      for (int v = 0; v < kMlpTop / 4; ++v) {
-        const int4 c4 = cr[v];
-        cj[4 * v] = c4.x; cj[4 * v + 1] = c4.y; cj[4 * v + 2] = c4.z; cj[4 * v + 3] = c4.w;
-      }
-      const T* x = X + (size_t)p * d;
-      double best = INFINITY;
-      int bj = 0x7fffffff;
-#pragma unroll 1
-      for (int s = 0; s < kMlpTop; ++s) {
-        const int j = cj[s];
-        if (j < 0) continue;
-        const double D = dist2_canon<T>(x, C64 + (size_t)j * d, d);
-        if (D < best || (D == best && j < bj)) { best = D; bj = j; }
-      }
-      if (bj != 0x7fffffff) {
-        float h = INFINITY;
-        for (int t = 0; t < kMlpNbr; ++t) {
-          const int nb = nbr_idx[(size_t)bj * kMlpNbr + t];
-          if (nb < 0) break;                 // no further centroids
-          bool in = false;
-#pragma unroll
-          for (int s = 0; s < kMlpTop; ++s) in |= cj[s] == nb;
-          if (!in) { h = nbr_half[(size_t)bj * kMlpNbr + t]; break; }
-        }
-        const double ub = f32_up(sqrt(best * (1.0 + (double)(d + 8) * 2.220446049250313e-16)) *
-                                 (1.0 + 8.881784197001252e-16));
-        cert = ub * (1.0 + kEta) < (double)h;
-        if (cert) {
-          const int32_t old = labels[p];
-          ub_out[p] = (float)ub;
-          ++certified;
-          if (old != bj) {                   // unchanged labels are not rewritten
-            labels[p] = bj;
-            ++changes;
-            mark_dirty(dirty, old, bj);
-          }
+    if (have && cs == 0) {
+      const double ub = f32_up(sqrt(best * (1.0 + (double)(d + 8) * 2.220446049250313e-16)) *
+                               (1.0 + 8.881784197001252e-16));
+      cert = ub * (1.0 + kEta) < (double)h;
+      if (cert) {
+        const int32_t old = labels[p];
+        ub_out[p] = (float)ub;
+        ++certified;
+        if (old != bj) {                     // unchanged labels are not rewritten
+          labels[p] = bj;
+          ++changes;
+          mark_dirty(dirty, old, bj);
         }
       }
     }
-    // uncertified survivors, in order
-    const bool keep = live && !cert;
+    // uncertified survivors (one lane per point)
+    const bool keep = live && cs == 0 && !cert;
     const uint64_t km = __ballot(keep);
-    if (lane == 0) wcnt[wave] = __popcll(km);
-    __syncthreads();
-    int base = run;
-    for (int w = 0; w < wave; ++w) base += wcnt[w];
-    if (keep) list2[(size_t)b * kSeg + base + __popcll(km & lanemask_lt())] = p;
-    __syncthreads();
-    if (threadIdx.x == 0) run += wcnt[0] + wcnt[1] + wcnt[2] + wcnt[3];
-    __syncthreads();
+    if (km) {
+      const int leader = __ffsll((unsigned long long)km) - 1;
+      int base = 0;
+      if (lane == leader) base = atomicAdd(&run, __popcll(km));     // LDS
+      base = __shfl(base, leader);
+      if (keep) list2[(size_t)b * kSeg + base + __popcll(km & lt)] = p;
+    }
   }
+  __syncthreads();
   if (threadIdx.x == 0) seg_cnt2[b] = run;
   const int qs[2] = {SLOT_CERTIFIED, SLOT_CHANGED};
   const unsigned long long v[2] = {certified, changes};
@@ -770,26 +1062,27 @@ __global__ __launch_bounds__(256) void mlp_certify_kernel(
 }
 
 hipError_t launch_mlp_certify(const void* X, knor_dtype dt, int d, const double* C64,
-                              const int* nbr_idx, const float* nbr_half, const int* list,
+                              int k, const float* nrows, const int* list,
                               const int* seg_cnt, const int* seg_off, int nseg,
                               const int32_t* cand, int32_t* labels, float* u, int* dirty,
                               int* list2, int* seg_cnt2, unsigned long long* row,
                               const int* conv, int iter, hipStream_t s) {
+  const int vec4 = (int)(d % 4 == 0 && ((uintptr_t)X & 15) == 0 && ((uintptr_t)C64 & 15) == 0);
   switch (dt) {
     case KNOR_F32:
       hipLaunchKernelGGL(mlp_certify_kernel<float>, dim3(nseg), dim3(256), 0, s,
-                         (const float*)X, d, C64, nbr_idx, nbr_half, list, seg_cnt, seg_off,
-                         cand, labels, u, dirty, list2, seg_cnt2, row, conv, iter);
+                         (const float*)X, d, C64, k, nrows, cc_rows_bits(k), list, seg_cnt, seg_off,
+                         cand, labels, u, dirty, list2, seg_cnt2, row, conv, iter, vec4);
       break;
     case KNOR_F64:
       hipLaunchKernelGGL(mlp_certify_kernel<double>, dim3(nseg), dim3(256), 0, s,
-                         (const double*)X, d, C64, nbr_idx, nbr_half, list, seg_cnt, seg_off,
-                         cand, labels, u, dirty, list2, seg_cnt2, row, conv, iter);
+                         (const double*)X, d, C64, k, nrows, cc_rows_bits(k), list, seg_cnt, seg_off,
+                         cand, labels, u, dirty, list2, seg_cnt2, row, conv, iter, vec4);
       break;
     case KNOR_BF16:
       hipLaunchKernelGGL(mlp_certify_kernel<uint16_t>, dim3(nseg), dim3(256), 0, s,
-                         (const uint16_t*)X, d, C64, nbr_idx, nbr_half, list, seg_cnt, seg_off,
-                         cand, labels, u, dirty, list2, seg_cnt2, row, conv, iter);
+                         (const uint16_t*)X, d, C64, k, nrows, cc_rows_bits(k), list, seg_cnt, seg_off,
+                         cand, labels, u, dirty, list2, seg_cnt2, row, conv, iter, vec4);
       break;
   }
   return hipGetLastError();

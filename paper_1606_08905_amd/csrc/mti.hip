@@ -13,7 +13,10 @@
 //              Clause 1 again with the tight bound.
 // Each filter block owns one segment of kSeg consecutive points and writes
 // its survivors to its own slice of the list (no global atomics); the
-// assignment tile then scans the survivors against every centroid.
+// assignment tile then scans the survivors against every centroid.  With
+// mark, Clause 3 runs every iteration and a survivor's tightened bound is
+// stored negated (sign bit set) for the candidate-list tile, which finds
+// the survivors of a cluster through it and writes a positive bound back.
 // The strict test with margin eta keeps every pruned centroid farther than
 // the kept one by a relative gap of about 4 eta, far above FP64 rounding, so
 // the labels equal the unpruned FP64 argmin.
@@ -23,25 +26,45 @@
 
 namespace knor {
 
+// Half of sqrt(D) rounded down to FP32, D a squared distance summed in FP64
+// (any order: relative error below (d + 2) 2^-53, covered with room).
+__device__ __forceinline__ float half_dist_down(double D, int d) {
+  return f32_down(0.5 * sqrt(D) * (1.0 - (double)(d + 8) * 2.220446049250313e-16));
+}
+
 // s_half[i] = rounded-down 1/2 min_{j != i} d(c_i, c_j).  One block per i;
 // threads over j read the transposed copy CT (contiguous across lanes).
+// With rows, row i of the neighbour table as well: for every j (i itself
+// included, at half distance 0) the key 1/2 d(c_i, c_j), rounded down, with
+// its low ib mantissa bits replaced by j (2^ib >= k), sorted in increasing
+// order.  Keys order by the half distance rounded down to its leading
+// 23 - ib mantissa bits, then by index, and the value of a key with its low
+// ib bits cleared is still a lower bound of the half distance.  The row is
+// sorted in LDS (bitonic, padded with +inf to kp2 = the next power of two).
 __global__ __launch_bounds__(256) void cc_bounds_kernel(
     const double* __restrict__ C64, const double* __restrict__ CT, int k,
-    int d, float* __restrict__ s_half, const int* __restrict__ conv,
-    int iter) {
+    int d, float* __restrict__ s_half, float* __restrict__ rows, int ib, int kp2,
+    const int* __restrict__ conv, int iter) {
+  extern __shared__ float sKey[];                    // kp2 keys (rows only)
   __shared__ double red[256];
   if (*conv < iter) return;
   const int i = blockIdx.x;
   const double* ci = C64 + (size_t)i * d;
+  const uint32_t mask = (1u << ib) - 1u;
   double best = INFINITY;
   for (int j = threadIdx.x; j < k; j += blockDim.x) {
-    if (j == i) continue;
+    if (j == i) {
+      if (rows) sKey[j] = __uint_as_float((uint32_t)j);   // half distance 0
+      continue;
+    }
     double acc = 0.0;
 #pragma unroll 8
     for (int dim = 0; dim < d; ++dim) {
       double t = __dsub_rn(ci[dim], CT[(size_t)dim * k + j]);
       acc = __dadd_rn(acc, __dmul_rn(t, t));
     }
+    if (rows)
+      sKey[j] = __uint_as_float((__float_as_uint(half_dist_down(acc, d)) & ~mask) | (uint32_t)j);
     best = acc < best ? acc : best;
   }
   red[threadIdx.x] = best;
@@ -53,16 +76,42 @@ __global__ __launch_bounds__(256) void cc_bounds_kernel(
   }
   if (threadIdx.x == 0) {
     double m = red[0];
-    s_half[i] = m < INFINITY
-                    ? f32_down(0.5 * sqrt(m) * (1.0 - (double)(d + 8) * 2.220446049250313e-16))
-                    : INFINITY;
+    s_half[i] = m < INFINITY ? half_dist_down(m, d) : INFINITY;
   }
+  if (!rows) return;                                 // uniform
+  for (int j = k + (int)threadIdx.x; j < kp2; j += blockDim.x) sKey[j] = INFINITY;
+  __syncthreads();
+  for (int size = 2; size <= kp2; size <<= 1)
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      for (int t = threadIdx.x; t < (kp2 >> 1); t += blockDim.x) {
+        const int lo = ((t / stride) * 2 * stride) + (t % stride), hi = lo + stride;
+        const bool asc = (lo & size) == 0;
+        const float x = sKey[lo], y = sKey[hi];
+        if ((x > y) == asc) { sKey[lo] = y; sKey[hi] = x; }
+      }
+      __syncthreads();
+    }
+  for (int j = threadIdx.x; j < k; j += blockDim.x) rows[(size_t)i * k + j] = sKey[j];
 }
 
-hipError_t launch_cc_bounds(const CentroidOps& o, float* s_half,
+int cc_rows_bits(int k) {
+  int ib = 0;
+  while ((1 << ib) < k) ++ib;
+  return ib;
+}
+
+hipError_t launch_cc_bounds(const CentroidOps& o, float* s_half, float* rows,
                             const int* conv, int iter, hipStream_t s) {
-  hipLaunchKernelGGL(cc_bounds_kernel, dim3(o.k), dim3(256), 0, s, o.C64, o.CT,
-                     o.k, o.d, s_half, conv, iter);
+  int kp2 = 1;
+  while (kp2 < o.k) kp2 <<= 1;
+  const size_t lds = rows ? sizeof(float) * (size_t)kp2 : 0;
+  if (lds) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&cc_bounds_kernel),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(cc_bounds_kernel, dim3(o.k), dim3(256), lds, s, o.C64, o.CT,
+                     o.k, o.d, s_half, rows, cc_rows_bits(o.k), kp2, conv, iter);
   return hipGetLastError();
 }
 
@@ -87,7 +136,7 @@ __global__ __launch_bounds__(kFilterThreads) void mti_filter_kernel(
     int* __restrict__ list, int* __restrict__ seg_cnt,
     const unsigned long long* __restrict__ prev_row,
     unsigned long long* __restrict__ row, const int* __restrict__ conv,
-    int iter, int vec) {
+    int iter, int vec, int mark) {
   // stage-A candidates: point, its label and s(label) (stage B reads the
   // last two from here instead of global memory)
   __shared__ int candA[kSeg];
@@ -97,7 +146,7 @@ __global__ __launch_bounds__(kFilterThreads) void mti_filter_kernel(
   const int cv = *conv;
   const int seg = blockIdx.x;
   const int64_t p0 = (int64_t)seg * kSeg;
-  const bool tighten = tighten_now(prev_row, iter);
+  const bool tighten = mark || tighten_now(prev_row, iter);
 
   // Clause 1 with the drift-updated bound, for every point of the segment:
   // thread t owns points 4t .. 4t + 3 of the segment (16-byte loads of
@@ -218,8 +267,8 @@ __global__ __launch_bounds__(kFilterThreads) void mti_filter_kernel(
       // (d + 2) 2^-53; inflate to an upper bound of the exact distance
       const double ub = f32_up(sqrt(part * (1.0 + (double)(d + 8) * 2.220446049250313e-16)) *
                                (1.0 + 8.881784197001252e-16));
-      u[p] = (float)ub;
       surv = !(ub * (1.0 + kEta) < (double)candS[c]);
+      u[p] = (mark && surv) ? -(float)ub : (float)ub;
     }
     uint64_t m = __ballot(surv);
     if (m) {
@@ -244,7 +293,7 @@ hipError_t launch_mti_filter(const void* X, knor_dtype dt, int64_t n, int d,
                              int* list, int* seg_cnt,
                              const unsigned long long* prev_row,
                              unsigned long long* row, const int* conv,
-                             int iter, hipStream_t s) {
+                             int iter, int mark, hipStream_t s) {
   const int nseg = nseg_of_n(n);
   const size_t esz = dt == KNOR_F64 ? 8 : (dt == KNOR_F32 ? 4 : 2);
   const int vec = (int)(((size_t)d * esz) % 16 == 0 && ((uintptr_t)X & 15) == 0);
@@ -253,19 +302,19 @@ hipError_t launch_mti_filter(const void* X, knor_dtype dt, int64_t n, int d,
       hipLaunchKernelGGL(mti_filter_kernel<double>, dim3(nseg),
                          dim3(kFilterThreads), 0, s, (const double*)X, n, d,
                          C64, labels, u, drift, s_half, list, seg_cnt,
-                         prev_row, row, conv, iter, vec);
+                         prev_row, row, conv, iter, vec, mark);
       break;
     case KNOR_F32:
       hipLaunchKernelGGL(mti_filter_kernel<float>, dim3(nseg),
                          dim3(kFilterThreads), 0, s, (const float*)X, n, d, C64,
                          labels, u, drift, s_half, list, seg_cnt, prev_row, row,
-                         conv, iter, vec);
+                         conv, iter, vec, mark);
       break;
     case KNOR_BF16:
       hipLaunchKernelGGL(mti_filter_kernel<uint16_t>, dim3(nseg),
                          dim3(kFilterThreads), 0, s, (const uint16_t*)X, n, d,
                          C64, labels, u, drift, s_half, list, seg_cnt,
-                         prev_row, row, conv, iter, vec);
+                         prev_row, row, conv, iter, vec, mark);
       break;
   }
   return hipGetLastError();

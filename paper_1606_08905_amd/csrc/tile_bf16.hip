@@ -195,22 +195,30 @@ __device__ __forceinline__ void load_ablock_bf(ABlockBf<T>& o, const uint16_t* h
 // One block of 16 centroids against the wave's PB point blocks: the small
 // (lo) terms first, then the hi terms, with the PB chains interleaved.
 template <class T>
-__device__ __forceinline__ void tile_block_bf(WaveState<T>& w,
-                                              const ABlockBf<T>& o, int jb) {
+__device__ __forceinline__ void tile_block_bf_acc(f4 (&acc)[T::PB],
+                                                  const bf8 (&bx)[T::PB][T::KS],
+                                                  const ABlockBf<T>& o) {
   constexpr int KS = T::KS, PB = T::PB;
-  f4 acc[PB];
 #pragma unroll
   for (int pb = 0; pb < PB; ++pb) acc[pb] = o.init;
 #pragma unroll
   for (int s = 0; s < KS; ++s)
 #pragma unroll
     for (int pb = 0; pb < PB; ++pb)
-      acc[pb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(o.lo[s], w.bx[pb][s], acc[pb], 0, 0, 0);
+      acc[pb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(o.lo[s], bx[pb][s], acc[pb], 0, 0, 0);
 #pragma unroll
   for (int s = 0; s < KS; ++s)
 #pragma unroll
     for (int pb = 0; pb < PB; ++pb)
-      acc[pb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(o.hi[s], w.bx[pb][s], acc[pb], 0, 0, 0);
+      acc[pb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(o.hi[s], bx[pb][s], acc[pb], 0, 0, 0);
+}
+
+template <class T>
+__device__ __forceinline__ void tile_block_bf(WaveState<T>& w,
+                                              const ABlockBf<T>& o, int jb) {
+  constexpr int PB = T::PB;
+  f4 acc[PB];
+  tile_block_bf_acc<T>(acc, w.bx, o);
 #pragma unroll
   for (int pb = 0; pb < PB; ++pb)
 #pragma unroll
@@ -443,6 +451,90 @@ hipError_t launch_tile_bf16(const CentroidOps& o, const AssignJob& j,
     case 256: return launch_bf_dp<256>(o, j, s);
     default: return hipErrorInvalidValue;
   }
+}
+
+// ---------------------------------------------------------------------------
+// the tile's values and bound, for checking the bound (knor_tile_values)
+// ---------------------------------------------------------------------------
+
+// Y[p][j] = the tile's FP32 value of |c_j|^2 - 2 x_p.c_j (the same operands
+// and accumulation as every pass above), E[p] = the bound its decision uses
+// with R^2 taken over all k centroids.  One wave per 16 * PB points.
+template <int DP>
+__global__ __launch_bounds__(256) void tile_values_bf16_kernel(
+    const uint16_t* __restrict__ X, int64_t n, int d, const uint16_t* __restrict__ Chi,
+    const uint16_t* __restrict__ Clo, const float* __restrict__ cn, int k, int kpad,
+    float* __restrict__ Y, double* __restrict__ E, int vec) {
+  using T = Bf16Tile<DP>;
+  constexpr int PB = T::PB, KS = T::KS;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int col = lane & 15, grp = lane >> 4;
+  const int64_t p0 = ((int64_t)blockIdx.x * 4 + wave) * 16 * PB;
+  if (p0 >= n) return;
+  float cmax = 0.0f;
+  for (int j = lane; j < k; j += 64) cmax = fmax_nc(cmax, cn[j]);
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) cmax = fmax_nc(cmax, __shfl_xor(cmax, o));
+  bf8 bx[PB][KS];
+  double xs[PB];
+#pragma unroll
+  for (int pb = 0; pb < PB; ++pb) {
+    const int64_t p = p0 + pb * 16 + col;
+    T::load_row(bx[pb], X, p < n ? p : 0, d, grp, vec, p < n);
+    double acc = 0.0;
+#pragma unroll
+    for (int s = 0; s < KS; ++s)
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const double v = T::xval(bx[pb], s, e);
+        acc = acc + v * v;
+      }
+    acc += __shfl_xor(acc, 16);
+    acc += __shfl_xor(acc, 32);
+    xs[pb] = acc;
+  }
+  for (int jb = 0; jb < kpad; jb += 16) {
+    ABlockBf<T> o;
+    load_ablock_bf<T>(o, Chi + (size_t)(jb + col) * DP + grp * 8,
+                      Clo + (size_t)(jb + col) * DP + grp * 8, cn + jb + 4 * grp);
+    f4 acc[PB];
+    tile_block_bf_acc<T>(acc, bx, o);
+#pragma unroll
+    for (int pb = 0; pb < PB; ++pb) {
+      const int64_t p = p0 + pb * 16 + col;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int j = jb + 4 * grp + r;
+        if (p < n && j < k) Y[(size_t)p * k + j] = acc[pb][r];
+      }
+    }
+  }
+  if (grp == 0) {
+    const double R2 = (double)cmax * (1.0 + 2.384185791015625e-07);
+#pragma unroll
+    for (int pb = 0; pb < PB; ++pb) {
+      const int64_t p = p0 + pb * 16 + col;
+      if (p < n) E[p] = T::bound(xs[pb] * (1.0 + (double)(d + 4) * 2.220446049250313e-16), R2, d);
+    }
+  }
+}
+
+hipError_t launch_tile_values_bf16(const CentroidOps& o, const uint16_t* X, int64_t n,
+                                   int d, float* Y, double* E, hipStream_t s) {
+  const int vec = (int)(((uintptr_t)X & 15) == 0 && d % 8 == 0);
+  auto go = [&](auto kern, int pb) {
+    const int64_t per = 64LL * pb;
+    hipLaunchKernelGGL(kern, dim3((unsigned)((n + per - 1) / per)), dim3(256), 0, s, X, n, d,
+                       o.Chi, o.Clo, o.cn, o.k, o.kpad, Y, E, vec);
+    return hipGetLastError();
+  };
+  switch (o.dpb) {
+    case 32: return go(tile_values_bf16_kernel<32>, bf_pb(32));
+    case 64: return go(tile_values_bf16_kernel<64>, bf_pb(64));
+    case 128: return go(tile_values_bf16_kernel<128>, bf_pb(128));
+    case 256: return go(tile_values_bf16_kernel<256>, bf_pb(256));
+  }
+  return hipErrorInvalidValue;
 }
 
 }  // namespace knor

@@ -1,0 +1,355 @@
+// Assignment of the MTI survivors with the paper's Clause 2 applied at the
+// granularity of a matrix-core tile (Mhembere et al., HPDC'17, Section
+// "Minimal Triangle Inequality (MTI) Pruning", Clauses 2 and 3).
+//
+// Clause 2: a point x with current centroid a and upper bound u >= d(x, c_a)
+// need not be compared with centroid j when u (1 + eta) < 1/2 d(c_a, c_j).
+// Then d(x, c_j) >= d(c_a, c_j) - d(x, c_a) > u (1 + 2 eta) >= d(x, c_a)
+// (1 + 2 eta): j is farther than a by a relative gap of 2 eta, far above the
+// FP64 evaluation error of the canonical distance, so j is neither the FP64
+// argmin nor tied with it.  Every centroid that can be the argmin is
+// therefore in C(x) = {j : !(u (1 + eta) < h(a, j))}, h(a, j) any lower
+// bound of 1/2 d(c_a, c_j); C(x) always holds a (h(a, a) = 0).
+//
+// The centroid-pair pass of the previous update leaves, for every centroid
+// a, its neighbour row: all centroids in increasing order of a lower bound
+// h(a, j) (a float key that also carries j), so C(x) is a prefix of a's row.
+//
+// Work is split into tasks of at most kTaskMembers members of one cluster
+// (in the update's sorted member order).  A task keeps the members the
+// filter marked as survivors (sign bit of their bound; Clause 3 has
+// tightened the bound to the exact distance rounded up), sorts them by
+// bound in LDS and takes them 64 at a time in increasing bound: the 64
+// share the prefix of a's row that the largest of their bounds needs.  The
+// FP32 tile runs over the gathered candidate rows with the top-3 epilogue
+// of the dense tile; a point is decided by the same rounding-bound test (its
+// R^2 taken over the candidates, the only centroids whose values it
+// compares).  The order in which candidates are visited decides no label:
+// a decided point has a strict gap to every other value, and two-candidate
+// and undecided points are resolved from canonical FP64 distances with the
+// lowest-index rule -- undecided ones over the block's whole candidate list,
+// which contains the FP64 argmin and every centroid tied with it.
+#include <math.h>
+
+#include "tile_f32.h"
+
+namespace knor {
+
+constexpr int kTaskMembers = 2048;  // members per task (all may survive)
+constexpr int kCandBlock = 64;      // survivors per candidate prefix (4 waves x 16)
+constexpr int kSlotBits = 11;       // survivor slot in a sort key
+// the largest finite float on the grid of rounded bounds; a bound that
+// rounds up to it or beyond is taken as unbounded (every centroid competes)
+constexpr uint32_t kTopKey = 0x7f7ff800u;
+static_assert((1 << kSlotBits) == kTaskMembers, "slot field holds a task's members");
+static_assert(kCandBlock == 4 * 16, "one 16-point block per wave");
+
+template <int DP>
+struct CandTile {
+  using T = F32Tile<DP, 1>;
+  static constexpr int CK = (4096 / DP) < 16 ? 16 : ((4096 / DP) > 128 ? 128 : (4096 / DP));
+  static constexpr int Q = T::KS;                           // 16-byte pieces per row
+  static constexpr int PER = (CK * Q + kTileThreads - 1) / kTileThreads;
+};
+
+// Task table: task t of cluster a covers members [c kTaskMembers, ...) of
+// a, c < ceil(n_a / kTaskMembers); tasks are numbered cluster by cluster.
+// One workgroup of 1024 threads: an exclusive scan of the per-cluster task
+// counts, then each thread writes the tasks of its clusters.
+__global__ __launch_bounds__(1024) void cand_tasks_kernel(const int* __restrict__ off, int k,
+                                                          int2* __restrict__ tasks,
+                                                          int* __restrict__ ntask,
+                                                          const int* __restrict__ conv,
+                                                          int iter) {
+  __shared__ int part[1024];
+  if (*conv < iter) return;
+  const int per = (k + 1023) / 1024;
+  const int a0 = threadIdx.x * per;
+  int loc = 0;
+  for (int a = a0; a < a0 + per && a < k; ++a)
+    loc += (off[a + 1] - off[a] + kTaskMembers - 1) / kTaskMembers;
+  part[threadIdx.x] = loc;
+  __syncthreads();
+  for (int s = 1; s < 1024; s <<= 1) {
+    const int t = threadIdx.x >= (unsigned)s ? part[threadIdx.x - s] : 0;
+    __syncthreads();
+    part[threadIdx.x] += t;
+    __syncthreads();
+  }
+  int t = part[threadIdx.x] - loc;
+  for (int a = a0; a < a0 + per && a < k; ++a) {
+    const int nt = (off[a + 1] - off[a] + kTaskMembers - 1) / kTaskMembers;
+    for (int c = 0; c < nt; ++c) tasks[t++] = make_int2(a, c);
+  }
+  if (threadIdx.x == 1023) *ntask = part[1023];
+}
+
+template <int DP>
+__global__ __launch_bounds__(kTileThreads) void tile_f32_cand_kernel(
+    const float* __restrict__ X, int d, const float* __restrict__ Cm2,
+    const float* __restrict__ cn, const double* __restrict__ C64, int k,
+    const int* __restrict__ perm, const int* __restrict__ off,
+    const float* __restrict__ rows, int ib, const int2* __restrict__ tasks,
+    const int* __restrict__ ntask, float* __restrict__ u, int32_t* __restrict__ labels,
+    int* __restrict__ dirty, unsigned long long* __restrict__ row,
+    const int* __restrict__ conv, int iter, int vec, int vec4) {
+  using G = CandTile<DP>;
+  using T = typename G::T;
+  constexpr int LDA = T::LDA, CK = G::CK, KS = T::KS, Q = G::Q;
+  extern __shared__ __attribute__((aligned(16))) float sRow[];   // a's neighbour row
+  __shared__ __attribute__((aligned(16))) float sC[CK * LDA];
+  __shared__ __attribute__((aligned(16))) float sN[CK];
+  __shared__ int sP[kTaskMembers];
+  __shared__ float sKey[kTaskMembers];
+  __shared__ int sFl[kCandBlock];
+  __shared__ int4 sPair[kPairCap];
+  __shared__ int sCnt, sFlN, sPairN;
+  if (*conv < iter || (int)blockIdx.x >= *ntask) return;     // uniform
+  const int2 tk = tasks[blockIdx.x];
+  const int a = tk.x;
+  const int m0 = off[a] + tk.y * kTaskMembers;
+  const int m1 = off[a + 1] < m0 + kTaskMembers ? off[a + 1] : m0 + kTaskMembers;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int col = lane & 15, grp = lane >> 4;
+  const uint64_t lt = lanemask_lt();
+  const uint32_t mask = (1u << ib) - 1u;
+  if (threadIdx.x == 0) { sCnt = 0; sFlN = 0; sPairN = 0; }
+  // a's neighbour row into LDS (its loads overlap the member walk below)
+  stage_batched<8, float>(
+      k, [&](int e) { return rows[(size_t)a * k + e]; }, [&](int e, float v) { sRow[e] = v; });
+  __syncthreads();
+  // the survivors among the task's members: all member indices first, then
+  // all their bounds (two memory round trips)
+  {
+    constexpr int E = kTaskMembers / kTileThreads;
+    int p[E];
+    float uu[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int i = m0 + (int)threadIdx.x + e * kTileThreads;
+      p[e] = i < m1 ? perm[i] : 0;
+    }
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int i = m0 + (int)threadIdx.x + e * kTileThreads;
+      uu[e] = i < m1 ? u[p[e]] : 0.0f;
+    }
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int i = m0 + (int)threadIdx.x + e * kTileThreads;
+      const bool surv = i < m1 && (__float_as_uint(uu[e]) >> 31) != 0u;
+      const uint64_t m = __ballot(surv);
+      if (m) {
+        const int leader = __ffsll((unsigned long long)m) - 1;
+        int base = 0;
+        if (lane == leader) base = atomicAdd(&sCnt, __popcll(m));   // LDS
+        base = __shfl(base, leader);
+        if (surv) {
+          const int slot = base + __popcll(m & lt);
+          sP[slot] = p[e];
+          // the bound rounded up to 12 significant bits, then the slot
+          const uint32_t ub = __float_as_uint(-uu[e]);
+          uint32_t up = (ub + ((1u << kSlotBits) - 1u)) & ~((1u << kSlotBits) - 1u);
+          if (up > kTopKey) up = kTopKey;           // stands for "unbounded"
+          sKey[slot] = __uint_as_float(up | (uint32_t)slot);
+        }
+      }
+    }
+  }
+  __syncthreads();
+  const int nS = sCnt;
+  if (nS == 0) return;                                        // uniform
+  // sort the survivors by rounded bound (bitonic, padded with +inf)
+  int N2 = 1;
+  while (N2 < nS) N2 <<= 1;
+  for (int i = nS + (int)threadIdx.x; i < N2; i += kTileThreads) sKey[i] = INFINITY;
+  __syncthreads();
+  for (int size = 2; size <= N2; size <<= 1)
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      for (int i = threadIdx.x; i < (N2 >> 1); i += kTileThreads) {
+        const int lo = ((i / stride) * 2 * stride) + (i % stride), hi = lo + stride;
+        const bool asc = (lo & size) == 0;
+        const float x = sKey[lo], y = sKey[hi];
+        if ((x > y) == asc) { sKey[lo] = y; sKey[hi] = x; }
+      }
+      __syncthreads();
+    }
+
+  unsigned long long chg = 0, nflag = 0, ndist = 0;
+  const uint32_t smask = (1u << kSlotBits) - 1u;
+  for (int b0 = 0; b0 < nS; b0 += kCandBlock) {
+    const int last = b0 + kCandBlock - 1 < nS ? b0 + kCandBlock - 1 : nS - 1;
+    // the block's largest bound (rounded up), and its prefix of a's row:
+    // L = the number of entries whose lower bound h passes !(thr < h)
+    const uint32_t tb = __float_as_uint(sKey[last]) & ~smask;
+    const double thr = tb >= kTopKey ? (double)INFINITY
+                                     : (double)__uint_as_float(tb) * (1.0 + kEta);
+    int lo = 0, hi = k;                         // first entry with h > thr
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      const double h = (double)__uint_as_float(__float_as_uint(sRow[mid]) & ~mask);
+      if (thr < h) hi = mid; else lo = mid + 1;
+    }
+    const int L = lo;                           // >= 1: a itself has h = 0
+    const int Lpad = (L + 15) / 16 * 16;
+    auto cand_of = [&](int pos) {
+      return pos < L ? (int)(__float_as_uint(sRow[pos]) & mask) : -1;
+    };
+    // the wave's 16 points
+    WaveState<T> w;
+    {
+      const int q = b0 + wave * 16 + col;
+      const bool valid = q < nS;
+      const int p = valid ? sP[__float_as_uint(sKey[q]) & smask] : 0;
+      w.valid[0] = valid;
+      w.pid[0] = p;
+      w.old[0] = a;
+      T::load_row(w.bx[0], X, p, d, grp, vec, valid);
+      double acc = 0.0;
+#pragma unroll
+      for (int s = 0; s < KS; ++s) {
+        const double v = (double)w.bx[0][s];
+        acc = acc + v * v;
+      }
+      w.xs[0] = acc;
+      top3_reset(w.b1[0], w.b2[0], w.b3[0], w.i1[0], w.i2[0]);
+    }
+    // candidate rows, CK at a time; the next chunk's loads are issued
+    // before the current chunk's matrix work
+    float4 pre[G::PER];
+    float pn = INFINITY;
+    auto load_chunk = [&](int c0) {
+      const int cc = (Lpad - c0) < CK ? (Lpad - c0) : CK;
+#pragma unroll
+      for (int i = 0; i < G::PER; ++i) {
+        const int e = threadIdx.x + i * kTileThreads;
+        const int r = e / Q, q4 = e - r * Q;
+        const int j = (e < cc * Q) ? cand_of(c0 + r) : -1;
+        pre[i] = j >= 0 ? *reinterpret_cast<const float4*>(Cm2 + (size_t)j * DP + q4 * 4)
+                        : make_float4(0.f, 0.f, 0.f, 0.f);
+      }
+      const int jn = (int)threadIdx.x < cc ? cand_of(c0 + threadIdx.x) : -1;
+      pn = jn >= 0 ? cn[jn] : INFINITY;
+    };
+    auto store_chunk = [&](int c0) {
+      const int cc = (Lpad - c0) < CK ? (Lpad - c0) : CK;
+#pragma unroll
+      for (int i = 0; i < G::PER; ++i) {
+        const int e = threadIdx.x + i * kTileThreads;
+        const int r = e / Q, q4 = e - r * Q;
+        if (e < cc * Q) *reinterpret_cast<float4*>(&sC[r * LDA + q4 * 4]) = pre[i];
+      }
+      if ((int)threadIdx.x < cc) sN[threadIdx.x] = pn;
+    };
+    float cmax = 0.0f;
+    load_chunk(0);
+    for (int c0 = 0; c0 < Lpad; c0 += CK) {
+      const int cc = (Lpad - c0) < CK ? (Lpad - c0) : CK;
+      __syncthreads();                          // the previous chunk is consumed
+      store_chunk(c0);
+      __syncthreads();
+      if (c0 + CK < Lpad) load_chunk(c0 + CK);
+      float mx = 0.0f;
+      for (int e = lane; e < cc; e += 64)
+        if (c0 + e < L) mx = fmax_nc(mx, sN[e]);
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) mx = fmax_nc(mx, __shfl_xor(mx, o));
+      cmax = fmax_nc(cmax, mx);
+      tile_sweep<T, true>(w, sC, sN, cc, c0, col, grp);
+    }
+    merge_groups<T>(w);
+    {
+      const int j1 = cand_of(w.i1[0]);
+      const int j2 = cand_of(w.i2[0]);
+      w.i1[0] = j1;
+      w.i2[0] = j2 >= 0 ? j2 : j1;
+    }
+    bool flag, changed;
+    int fp;
+    finalize_points<T>(w, cmax, d, grp, 0, true, sPair, &sPairN, labels, u, dirty,
+                       flag, fp, changed);
+    chg += changed ? 1 : 0;
+    if (flag) sFl[atomicAdd(&sFlN, 1)] = fp;   // at most one per point of the block
+    __syncthreads();
+    const int nfl = sFlN;
+    // near-tie points: canonical FP64 distances to every candidate, one
+    // wave per point, lowest index among equal distances
+    for (int f = wave; f < nfl; f += 4) {
+      const int p = sFl[f];
+      double best = INFINITY;
+      int bj = 0x7fffffff;
+      for (int q = lane; q < L; q += 64) {
+        const int j = cand_of(q);
+        const double D = vec4 ? dist2_canon_f32x4(X + (size_t)p * d, C64 + (size_t)j * d, d)
+                              : dist2_canon<float>(X + (size_t)p * d, C64 + (size_t)j * d, d);
+        if (D < best || (D == best && j < bj)) { best = D; bj = j; }
+      }
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) {
+        const double ob = __shfl_xor(best, o);
+        const int oj = __shfl_xor(bj, o);
+        if (ob < best || (ob == best && oj < bj)) { best = ob; bj = oj; }
+      }
+      if (lane == 0)
+        chg += commit_label(p, a, bj, pair_bound(best, d), labels, u, dirty) ? 1 : 0;
+    }
+    if (threadIdx.x == 0) {
+      const int nv = (nS - b0) < kCandBlock ? (nS - b0) : kCandBlock;
+      ndist += (unsigned long long)(nv + nfl) * (unsigned long long)L;
+      nflag += (unsigned long long)nfl;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) sFlN = 0;
+  }
+  __syncthreads();
+  const int np = sPairN < kPairCap ? sPairN : kPairCap;
+  if (np) chg += resolve_pairs<T, float>(X, d, vec, C64, sPair, np, labels, u, dirty);
+  const int qs[3] = {SLOT_CHANGED, SLOT_FLAGGED, SLOT_DISTS};
+  const unsigned long long v[3] = {chg, nflag, ndist};
+  block_add_slots<3>(row, qs, v);
+}
+
+size_t cand_workspace_bytes(int64_t n, int k) {
+  return sizeof(int2) * (size_t)(n / kTaskMembers + k + 1) + 256;
+}
+
+template <int DP>
+static hipError_t launch_cand_dp(const CentroidOps& o, const AssignJob& j, const int* perm,
+                                 const int* off, const float* rows, void* ws,
+                                 hipStream_t s) {
+  const int vec = (int)(j.d == DP && ((uintptr_t)j.X & 15) == 0);
+  const int vec4 = (int)(j.d % 4 == 0 && ((uintptr_t)j.X & 15) == 0 &&
+                         ((uintptr_t)o.C64 & 15) == 0);
+  const size_t lds = sizeof(float) * (size_t)o.k;
+  // with the static arrays the total can pass the default 64 KB
+  hipError_t e = hipFuncSetAttribute(
+      reinterpret_cast<const void*>(&tile_f32_cand_kernel<DP>),
+      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  int* ntask = (int*)ws;
+  int2* tasks = (int2*)((char*)ws + 256);
+  hipLaunchKernelGGL(cand_tasks_kernel, dim3(1), dim3(1024), 0, s, off, o.k, tasks, ntask,
+                     j.conv, j.iter);
+  const int64_t grid = j.n / kTaskMembers + o.k + 1;      // >= the number of tasks
+  hipLaunchKernelGGL((tile_f32_cand_kernel<DP>), dim3((unsigned)grid), dim3(kTileThreads), lds,
+                     s, (const float*)j.X, j.d, o.Cm2, o.cn, o.C64, o.k, perm, off, rows,
+                     cc_rows_bits(o.k), tasks, ntask, j.u, j.labels, j.dirty, j.row, j.conv,
+                     j.iter, vec, vec4);
+  return hipGetLastError();
+}
+
+hipError_t launch_tile_cand(const CentroidOps& o, const AssignJob& j, const int* perm,
+                            const int* off, const float* rows, void* ws, hipStream_t s) {
+  if (j.dt != KNOR_F32 || o.k > kCandMaxK) return hipErrorInvalidValue;
+  switch (o.dp) {
+    case 8: return launch_cand_dp<8>(o, j, perm, off, rows, ws, s);
+    case 16: return launch_cand_dp<16>(o, j, perm, off, rows, ws, s);
+    case 32: return launch_cand_dp<32>(o, j, perm, off, rows, ws, s);
+    case 64: return launch_cand_dp<64>(o, j, perm, off, rows, ws, s);
+    case 128: return launch_cand_dp<128>(o, j, perm, off, rows, ws, s);
+    case 256: return launch_cand_dp<256>(o, j, perm, off, rows, ws, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace knor

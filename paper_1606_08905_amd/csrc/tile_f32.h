@@ -89,18 +89,30 @@ __device__ __forceinline__ void load_ablock(ABlock<T>& o, const float* arow,
 // independent.  Epilogue per value: the three smallest values by two
 // medians of three, and the index of the smallest (I2: of the two smallest)
 // by selects.
-template <class T, bool I2>
-__device__ __forceinline__ void tile_block(WaveState<T>& w, const ABlock<T>& o,
-                                           int jb) {
+// The tile values of one block of 16 centroids for PB point blocks: the
+// accumulator seeded with fp32(|c|^2), then one MFMA per K-step in order.
+// Every pass of the tile (and the bound check's value dump) uses this, so a
+// pair's value depends on nothing but its two operands.
+template <class T>
+__device__ __forceinline__ void tile_block_acc(f4 (&acc)[T::PB],
+                                               const typename T::Frag (&bx)[T::PB][T::KS],
+                                               const ABlock<T>& o) {
   constexpr int KS = T::KS, PB = T::PB;
-  f4 acc[PB];
 #pragma unroll
   for (int pb = 0; pb < PB; ++pb) acc[pb] = o.init;
 #pragma unroll
   for (int s = 0; s < KS; ++s)
 #pragma unroll
     for (int pb = 0; pb < PB; ++pb)
-      acc[pb] = __builtin_amdgcn_mfma_f32_16x16x4f32(o.a[s], w.bx[pb][s], acc[pb], 0, 0, 0);
+      acc[pb] = __builtin_amdgcn_mfma_f32_16x16x4f32(o.a[s], bx[pb][s], acc[pb], 0, 0, 0);
+}
+
+template <class T, bool I2>
+__device__ __forceinline__ void tile_block(WaveState<T>& w, const ABlock<T>& o,
+                                           int jb) {
+  constexpr int PB = T::PB;
+  f4 acc[PB];
+  tile_block_acc<T>(acc, w.bx, o);
 #pragma unroll
   for (int pb = 0; pb < PB; ++pb)
 #pragma unroll

@@ -397,4 +397,73 @@ hipError_t launch_tile_f32(const CentroidOps& o, const AssignJob& j,
   }
 }
 
+// ---------------------------------------------------------------------------
+// the tile's values and bound, for checking the bound (knor_tile_values)
+// ---------------------------------------------------------------------------
+
+// Y[p][j] = the tile's FP32 value of |c_j|^2 - 2 x_p.c_j (the same operands
+// and accumulation as every pass above), E[p] = the bound its decision uses
+// with R^2 taken over all k centroids.  One wave per 16 points.
+template <int DP>
+__global__ __launch_bounds__(256) void tile_values_f32_kernel(
+    const float* __restrict__ X, int64_t n, int d, const float* __restrict__ Cm2,
+    const float* __restrict__ cn, int k, int kpad, float* __restrict__ Y,
+    double* __restrict__ E, int vec) {
+  using T = F32Tile<DP, 1>;
+  constexpr int KS = T::KS;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int col = lane & 15, grp = lane >> 4;
+  const int64_t p = ((int64_t)blockIdx.x * 4 + wave) * 16 + col;
+  if (((int64_t)blockIdx.x * 4 + wave) * 16 >= n) return;
+  float cmax = 0.0f;
+  for (int j = lane; j < k; j += 64) cmax = fmax_nc(cmax, cn[j]);
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) cmax = fmax_nc(cmax, __shfl_xor(cmax, o));
+  float bx[1][KS];
+  T::load_row(bx[0], X, p < n ? p : 0, d, grp, vec, p < n);
+  double xs = 0.0;
+#pragma unroll
+  for (int s = 0; s < KS; ++s) {
+    const double v = (double)bx[0][s];
+    xs = xs + v * v;
+  }
+  xs += __shfl_xor(xs, 16);
+  xs += __shfl_xor(xs, 32);
+  for (int jb = 0; jb < kpad; jb += 16) {
+    ABlock<T> o;
+    load_ablock<T>(o, Cm2 + (size_t)(jb + col) * DP + grp * KS, cn + jb + 4 * grp);
+    f4 acc[1];
+    tile_block_acc<T>(acc, bx, o);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int j = jb + 4 * grp + r;
+      if (p < n && j < k) Y[(size_t)p * k + j] = acc[0][r];
+    }
+  }
+  if (grp == 0 && p < n) {
+    const double R2 = (double)cmax * (1.0 + 2.384185791015625e-07);
+    E[p] = T::bound(xs * (1.0 + (double)(d + 4) * 2.220446049250313e-16), R2, d);
+  }
+}
+
+hipError_t launch_tile_values_f32(const CentroidOps& o, const float* X, int64_t n, int d,
+                                  float* Y, double* E, hipStream_t s) {
+  const dim3 grid((unsigned)((n + 63) / 64));
+  auto go = [&](auto kern, int DP) {
+    const int vec = (int)(d == DP && ((uintptr_t)X & 15) == 0);
+    hipLaunchKernelGGL(kern, grid, dim3(256), 0, s, X, n, d, o.Cm2, o.cn, o.k, o.kpad, Y, E,
+                       vec);
+    return hipGetLastError();
+  };
+  switch (o.dp) {
+    case 8: return go(tile_values_f32_kernel<8>, 8);
+    case 16: return go(tile_values_f32_kernel<16>, 16);
+    case 32: return go(tile_values_f32_kernel<32>, 32);
+    case 64: return go(tile_values_f32_kernel<64>, 64);
+    case 128: return go(tile_values_f32_kernel<128>, 128);
+    case 256: return go(tile_values_f32_kernel<256>, 256);
+  }
+  return hipErrorInvalidValue;
+}
+
 }  // namespace knor

@@ -36,6 +36,7 @@ __device__ __forceinline__ void close_iteration(const IterCtl& ctl, int iter) {
     row[ROW_CHANGED] = tot[SLOT_CHANGED];
     row[ROW_FLAG_HEAD] = tot[SLOT_FLAGGED];
     row[ROW_CERTIFIED] = tot[SLOT_CERTIFIED];
+    row[ROW_DISTS] = tot[SLOT_DISTS];
     if (ctl.segmented) {
       row[ROW_SURVIVED] = tot[SLOT_SURV];
       row[ROW_SCANNED] = tot[SLOT_SURV] - tot[SLOT_CERTIFIED];

@@ -225,3 +225,21 @@ def test_fit_batched_rejects_centroid_history(L):
 
 def test_binding_init_names():
     assert knor.INITS == {"given": 0, "forgy": 1, "shuffle_first_k": 2, "kmeans++": 3}
+
+
+def test_clause2_option_validated(L):
+    o = knor.Opts()
+    o.struct_size = ctypes.sizeof(knor.Opts)
+    o.prune = 1
+    o.recheck = 1
+    o.check_numeric = 1
+    o.clause2 = 3
+    assert _fit(L, opts=ctypes.byref(o)) == knor.KNOR_ERR_INVALID_ARG
+    o.clause2 = 2                      # FP64 points: not served by the tile
+    assert _fit(L, dt=0, opts=ctypes.byref(o)) == knor.KNOR_ERR_UNSUPPORTED
+    o.prune = 0                        # needs MTI
+    assert _fit(L, opts=ctypes.byref(o)) == knor.KNOR_ERR_UNSUPPORTED
+    o.prune = 1
+    assert _fit(L, k=9000, n=20000, opts=ctypes.byref(o)) == knor.KNOR_ERR_UNSUPPORTED
+    arr = (knor.Problem * 1)(_problem(dt=2))
+    assert L.knor_fit_batched(arr, 1, ctypes.byref(o), None) == knor.KNOR_ERR_UNSUPPORTED

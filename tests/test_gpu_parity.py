@@ -517,36 +517,43 @@ def test_mlp_gradient_matches_reference(d, h, k, B):
     assert np.allclose(v.cpu().numpy(), v_o, rtol=1e-5, atol=1e-30)
 
 
-@pytest.mark.parametrize("d,h,k,m", [(8, 32, 64, 300), (32, 256, 4096, 700), (16, 64, 100, 257)])
+@pytest.mark.parametrize("d,h,k,m", [(8, 32, 64, 300), (32, 256, 4096, 700), (16, 64, 100, 257),
+                                     (40, 128, 1000, 513), (5, 256, 20, 64)])
 def test_mlp_propose_matches_reference(d, h, k, m):
-    """Candidates are the per-subset argmax logits; wherever a subset's two
-    largest reference logits differ by more than the FP32-summation
-    tolerance, the GPU must pick the same class."""
+    """Candidates are the 16 largest logits (each rounded towards zero to its
+    leading mantissa bits, ties by class), in decreasing order.  Against the
+    FP64 reference on the same BF16 operands: every class whose reference
+    logit clears the 17th largest by more than the tolerance is proposed,
+    and every proposed class is within the tolerance of the 16th largest.
+    The tolerance covers FP32 summation, an occasional hidden activation
+    rounding one BF16 ulp the other way, and the key rounding."""
     import torch
     from oracle import mlp
     knor = _knor()
+    _print_case(test="mlp-propose", d=d, h=h, k=k, m=m)
     th, Xs, _ = _mlp_case(d, h, k, m, seed=7 * d + k)
     _, _, z = mlp.forward(th, Xs, d, h, k, use_bf16=True)
     cand = knor.mlp_propose(torch.from_numpy(th.astype(np.float32)).cuda(), d, h, k,
                             torch.from_numpy(Xs.astype(np.float32)).cuda()).cpu().numpy()
-    j = np.arange(k)
-    subset = 4 * ((j % 16) // 4) + (j // 16) % 4
-    compared = agree = 0
-    for sidx in range(16):
-        cls = j[subset == sidx]
-        if cls.size == 0:
-            assert (cand[:, sidx] == -1).all()
-            continue
-        zs = z[:, cls]
-        order = np.argsort(-zs, axis=1, kind="stable")
-        top1 = zs[np.arange(m), order[:, 0]]
-        top2 = zs[np.arange(m), order[:, 1]] if cls.size > 1 else np.full(m, -np.inf)
-        tol = 1e-3 * (np.abs(top1) + 1.0)
-        clear = (top1 - top2) > tol
-        compared += clear.sum()
-        agree += (cand[clear, sidx] == cls[order[clear, 0]]).sum()
-    assert compared >= 0.9 * 16 * m * min(1.0, k / 256)
-    assert agree == compared
+    assert cand.shape == (m, 16)
+    nreal = min(16, k)
+    assert (cand[:, nreal:] == -1).all()
+    c = cand[:, :nreal]
+    assert ((c >= 0) & (c < k)).all()
+    assert all(len(set(row)) == nreal for row in c)
+    zs = -np.sort(-z, axis=1)
+    z16 = zs[:, nreal - 1]
+    z17 = zs[:, nreal] if k > nreal else np.full(m, -np.inf)
+    tol = 4e-3 * (np.abs(z16) + 1.0)
+    zc = np.take_along_axis(z, c, axis=1)
+    assert (zc >= (z16 - tol)[:, None]).all()
+    must = z > (z17 + tol)[:, None]
+    for r in range(m):
+        assert set(np.nonzero(must[r])[0]) <= set(c[r].tolist()), r
+    # decreasing order (up to the tolerance)
+    assert (np.diff(zc, axis=1) <= tol[:, None]).all()
+    # the check is not vacuous: most of the top 16 clear the tolerance
+    assert must.sum() >= 0.5 * nreal * m
 
 
 @pytest.mark.parametrize("k", [128, 100])
