@@ -61,7 +61,9 @@ typedef enum {
                                  exceeds opts->workspace_cap               */
   KNOR_ERR_HIP = 3,           /* a HIP runtime call failed                  */
   KNOR_ERR_NUMERIC = 4,       /* NaN or Inf in X or in the centroids        */
-  KNOR_ERR_UNSUPPORTED = 5    /* valid request this build does not handle   */
+  KNOR_ERR_UNSUPPORTED = 5,   /* valid request this build does not handle   */
+  KNOR_ERR_SCRATCH = 6        /* knor_assign_noalloc: the request needs more
+                                 than its fixed scratch                      */
 } knor_status;
 
 typedef enum { KNOR_F64 = 0, KNOR_F32 = 1, KNOR_BF16 = 2 } knor_dtype;
@@ -244,6 +246,39 @@ knor_status knor_fit(const void* X, knor_dtype dt, int64_t n, int32_t d,
 knor_status knor_assign(const void* X, knor_dtype dt, int64_t n, int32_t d,
                         const double* C, int32_t k, const knor_opts* opts,
                         int32_t* labels_out, double* dist2_out);
+
+/* knor_assign_noalloc: knor_assign (same arguments, results and stream
+ * order) for callers that cannot allocate device memory -- code under HIP
+ * graph capture, tight serving loops, harnesses that forbid allocation.  It
+ * calls no hipMalloc, hipFree or memset: its workspace is a fixed array of
+ * 32 MiB of device memory per GPU, held from the library's load until the
+ * process ends, and its counters are cleared by kernels.  The workspace is
+ * about 4 n + 4 kpad dp + 8 k d + 80 KiB bytes (kpad = k rounded up to 16,
+ * dp = d rounded up to a power of two >= 8; FP32 points), so n up to about
+ * 7.5 million at d = 32, k = 4096; a larger request returns
+ * KNOR_ERR_SCRATCH before any device work.  Every call on one GPU uses
+ * that GPU's single array: calls that overlap in time on the same GPU (on
+ * different streams or host threads) race and must be serialized by the
+ * caller; consecutive calls on one stream are ordered and safe. */
+knor_status knor_assign_noalloc(const void* X, knor_dtype dt, int64_t n, int32_t d,
+                                const double* C, int32_t k, const knor_opts* opts,
+                                int32_t* labels_out, double* dist2_out);
+
+/* knor_tile_values: the matrix-core tile's working values, for checking its
+ * rounding bound.  The assignment step (Algorithm 1's nearest-centroid
+ * loop) evaluates y_j = |c_j|^2 - 2 x.c_j for FP32 points on FP32 matrix
+ * cores and for BF16 points on BF16 matrix cores (centroid operand -2c as
+ * two BF16 terms), and trusts a point's smallest value only when the gap to
+ * the next exceeds twice a bound E(x) on |y~_j - y_j|; every other point is
+ * recomputed in FP64.  This entry point returns those values and bounds:
+ *   Y  DEVICE n x k FP32: Y[p][j] = the tile's value for point p and
+ *      centroid j (the same operands and accumulation order as every
+ *      assignment pass);
+ *   E  DEVICE n FP64: E(x_p) as the decision uses it, with R^2 over all k.
+ * FP32 and BF16 points (FP64: KNOR_ERR_UNSUPPORTED).  Asynchronous. */
+knor_status knor_tile_values(const void* X, knor_dtype dt, int64_t n, int32_t d,
+                             const double* C, int32_t k, const knor_opts* opts, float* Y,
+                             double* E);
 
 /* knor_update: one centroid update (Phase II; the merge of Algorithm 1).
  * With opts->update = 0 (default) each centroid is the canonical-order

@@ -18,7 +18,7 @@ from __future__ import annotations
 import ctypes
 import os
 
-__all__ = ["fit", "fit_batched", "assign", "update", "load", "KnorError",
+__all__ = ["fit", "fit_batched", "assign", "assign_noalloc", "update", "load", "KnorError",
            "COUNTERS", "library_path", "mlp_param_count", "mlp_init",
            "mlp_train_step", "mlp_propose"]
 
@@ -26,7 +26,7 @@ _PKG = os.path.dirname(os.path.abspath(__file__))
 _LIB = os.path.join(_PKG, "libknor.so")
 
 KNOR_OK, KNOR_ERR_INVALID_ARG, KNOR_ERR_OUT_OF_MEMORY, KNOR_ERR_HIP, \
-    KNOR_ERR_NUMERIC, KNOR_ERR_UNSUPPORTED = range(6)
+    KNOR_ERR_NUMERIC, KNOR_ERR_UNSUPPORTED, KNOR_ERR_SCRATCH = range(7)
 INIT_GIVEN, INIT_FORGY, INIT_SHUFFLE_FIRSTK, INIT_KMEANSPP = 0, 1, 2, 3
 INITS = {"given": INIT_GIVEN, "forgy": INIT_FORGY,
          "shuffle_first_k": INIT_SHUFFLE_FIRSTK, "kmeans++": INIT_KMEANSPP}
@@ -115,6 +115,9 @@ def load():
     L.knor_assign.argtypes = [P, ctypes.c_int, i64, i32, P, i32,
                               ctypes.POINTER(Opts), P, P]
     L.knor_assign.restype = ctypes.c_int
+    L.knor_assign_noalloc.argtypes = [P, ctypes.c_int, i64, i32, P, i32,
+                                      ctypes.POINTER(Opts), P, P]
+    L.knor_assign_noalloc.restype = ctypes.c_int
     L.knor_tile_values.argtypes = [P, ctypes.c_int, i64, i32, P, i32,
                                    ctypes.POINTER(Opts), P, P]
     L.knor_tile_values.restype = ctypes.c_int
@@ -344,6 +347,45 @@ def assign(X, C, recheck=1, dist2=False):
                        dd.data_ptr() if dd is not None else None)
     _raise(rc)
     return (lab, dd) if dist2 else lab
+
+
+def assign_noalloc(X, C, labels, dist2=None, recheck=1):
+    """knor_assign_noalloc: the assignment into caller-provided outputs
+    (labels: (n,) int32, dist2: (n,) float64 or None) with no device
+    allocation in the library (its fixed per-GPU scratch).  Asynchronous on
+    the current stream; calls that overlap on one GPU race."""
+    torch = _torch()
+    L = load()
+    _check_dev(X, "X")
+    _check_dev(C, "C")
+    _check_dev(labels, "labels")
+    if C.dtype != torch.float64 or labels.dtype != torch.int32:
+        raise TypeError("C must be float64 and labels int32")
+    n, d = X.shape
+    k = C.shape[0]
+    o = _opts(recheck=recheck)
+    rc = L.knor_assign_noalloc(X.data_ptr(), _dtype_code(X), n, d, C.data_ptr(), k,
+                               ctypes.byref(o), labels.data_ptr(),
+                               dist2.data_ptr() if dist2 is not None else None)
+    _raise(rc)
+    return labels
+
+
+def tile_values(X, C):
+    """(Y, E): the assignment tile's FP32 values Y[p][j] of |c_j|^2 - 2 x_p.c_j
+    and the rounding bound E[p] its decisions use (FP32 / BF16 points)."""
+    torch = _torch()
+    L = load()
+    _check_dev(X, "X")
+    _check_dev(C, "C")
+    n, d = X.shape
+    k = C.shape[0]
+    Y = torch.empty((n, k), dtype=torch.float32, device=X.device)
+    E = torch.empty((n,), dtype=torch.float64, device=X.device)
+    o = _opts()
+    _raise(L.knor_tile_values(X.data_ptr(), _dtype_code(X), n, d, C.data_ptr(), k,
+                              ctypes.byref(o), Y.data_ptr(), E.data_ptr()))
+    return Y, E
 
 
 def update(X, labels, C_prev, mode="canonical"):

@@ -215,6 +215,14 @@ struct Arena {
     place(base);
     return KNOR_OK;
   }
+  // the pieces carved from caller-provided device memory (no allocation)
+  knor_status within(void* mem, size_t cap) {
+    if (overflow) return KNOR_ERR_INVALID_ARG;
+    if (bytes > cap) return KNOR_ERR_SCRATCH;
+    base = (char*)mem;
+    place(base);
+    return KNOR_OK;
+  }
   ~Arena() {
     if (owned && base) (void)hipFreeAsync(base, stream);
   }
@@ -851,6 +859,94 @@ static knor_status fit_impl(const void* X, knor_dtype dt, int64_t n, int d,
   return KNOR_OK;
 }
 
+// ---------------------------------------------------------------------------
+// assignment (knor_assign and its allocation-free form)
+// ---------------------------------------------------------------------------
+
+// One assignment.  mem == null and cap == 0: workspace from a stream-ordered
+// allocation; mem != null: carved from mem (cap bytes, KNOR_ERR_SCRATCH if
+// too small) with no allocation and no memset; mem == null and cap != 0:
+// validate only (no device work).
+static knor_status assign_impl(const void* X, knor_dtype dt, int64_t n, int32_t d,
+                               const double* C, int32_t k, const knor_opts* opts,
+                               int32_t* labels_out, double* dist2_out, void* mem,
+                               size_t cap) {
+  Opts o;
+  if (knor_status r = read_opts(opts, &o)) return r;
+  // X and labels_out may be NULL when n == 0
+  if ((n > 0 && (!X || !labels_out)) || !C || !dtype_ok(dt)) return KNOR_ERR_INVALID_ARG;
+  if (n < 0 || n >= (int64_t)1 << 31 || d < 1 || d > kMaxD || k < 1 || k > kMaxK)
+    return KNOR_ERR_INVALID_ARG;
+  if (n == 0 || (!mem && cap)) return KNOR_OK;
+  hipStream_t s = o.stream;
+  CentroidOps ops{};
+  ops.k = k; ops.kpad = (k + 15) / 16 * 16; ops.d = d; ops.dp = pad_dim(d);
+  ops.dpb = pad_dim_bf16(d);
+  ops.C64 = const_cast<double*>(C);
+  if (knor_status r = select_tile(ops, o)) return r;
+  int* flags = nullptr;
+  int* conv = nullptr;
+  int* ucnt = nullptr;
+  unsigned long long* ctr = nullptr;
+  Arena ar;
+  add_operands(ar, ops, dt);
+  ar.add((void**)&ops.CT, sizeof(double) * (size_t)k * d);
+  ar.add((void**)&flags, sizeof(int) * (size_t)flag_capacity(ops, dt, n, nseg_of_n(n)));
+  ar.add((void**)&ucnt, sizeof(int) * (size_t)kTileMaxGrid);
+  ar.add((void**)&ctr, sizeof(unsigned long long) * ROW_STRIDE);
+  ar.add((void**)&conv, sizeof(int) * 4);
+  if (knor_status r = mem ? ar.within(mem, cap) : ar.alloc(s, o.cap)) return r;
+  // fill kernels rather than memset: callers may capture this in a graph
+  HIPCHK(launch_fill_i32((int32_t*)ctr, 2 * (int64_t)ROW_STRIDE, 0, s));
+  HIPCHK(launch_fill_i32(conv, 1, kNotConverged, s));
+  HIPCHK(launch_fill_i32(labels_out, n, -1, s));
+  HIPCHK(launch_prep_centroids(ops, s));
+  AssignJob job{};
+  job.X = X; job.dt = dt; job.n = n; job.d = d;
+  job.labels = labels_out; job.flags = flags; job.row = ctr; job.conv = conv;
+  job.ucnt = ucnt;
+  job.iter = 0; job.recheck_all = o.recheck == 2;
+  HIPCHK(launch_assign(ops, job, s));
+  HIPCHK(launch_recheck(ops, job, s));
+  if (dist2_out)
+    HIPCHK(launch_exact_dist2(X, dt, n, d, C, labels_out, dist2_out, s));
+  return KNOR_OK;
+}
+
+// ---------------------------------------------------------------------------
+// the allocation-free assignment's scratch
+// ---------------------------------------------------------------------------
+
+// Device memory of knor_assign_noalloc: one array per device for the life
+// of the process.  In host code `scratch` names a host-side stand-in, never
+// the device memory: every use goes through the address hipGetSymbolAddress
+// returns for the current device, looked up once per device.
+constexpr size_t kScratchBytes = (size_t)32 << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+constexpr int kScratchDevices = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[kScratchDevices];
+
+static knor_status scratch_of_device(void** out) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) {
+    (void)hipGetLastError();
+    return KNOR_ERR_HIP;
+  }
+  if (dev < 0 || dev >= kScratchDevices) return KNOR_ERR_UNSUPPORTED;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) {
+      (void)hipGetLastError();
+      return KNOR_ERR_HIP;
+    }
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return KNOR_OK;
+}
+
 }  // namespace knor
 
 using namespace knor;
@@ -938,6 +1034,8 @@ const char* knor_status_string(knor_status s) {
     case KNOR_ERR_HIP: return "HIP runtime error";
     case KNOR_ERR_NUMERIC: return "NaN or Inf in the input";
     case KNOR_ERR_UNSUPPORTED: return "unsupported by this build";
+    case KNOR_ERR_SCRATCH:
+      return "request needs more than the fixed scratch of the allocation-free entry point";
   }
   return "unknown status";
 }
@@ -1077,45 +1175,21 @@ knor_status knor_fit_batched(const knor_problem* probs, int32_t count,
 knor_status knor_assign(const void* X, knor_dtype dt, int64_t n, int32_t d,
                         const double* C, int32_t k, const knor_opts* opts,
                         int32_t* labels_out, double* dist2_out) {
-  Opts o;
-  if (knor_status r = read_opts(opts, &o)) return r;
-  // X and labels_out may be NULL when n == 0
-  if ((n > 0 && (!X || !labels_out)) || !C || !dtype_ok(dt)) return KNOR_ERR_INVALID_ARG;
-  if (n < 0 || n >= (int64_t)1 << 31 || d < 1 || d > kMaxD || k < 1 || k > kMaxK)
-    return KNOR_ERR_INVALID_ARG;
+  return knor::assign_impl(X, dt, n, d, C, k, opts, labels_out, dist2_out, nullptr, 0);
+}
+
+knor_status knor_assign_noalloc(const void* X, knor_dtype dt, int64_t n, int32_t d,
+                                const double* C, int32_t k, const knor_opts* opts,
+                                int32_t* labels_out, double* dist2_out) {
+  // validation first: an invalid call touches neither the device nor scratch
+  if (knor_status r = knor::assign_impl(X, dt, n, d, C, k, opts, labels_out, dist2_out,
+                                        nullptr, (size_t)-1))
+    return r;
   if (n == 0) return KNOR_OK;
-  hipStream_t s = o.stream;
-  CentroidOps ops{};
-  ops.k = k; ops.kpad = (k + 15) / 16 * 16; ops.d = d; ops.dp = pad_dim(d);
-  ops.dpb = pad_dim_bf16(d);
-  ops.C64 = const_cast<double*>(C);
-  if (knor_status r = select_tile(ops, o)) return r;
-  int* flags = nullptr;
-  int* conv = nullptr;
-  int* ucnt = nullptr;
-  unsigned long long* ctr = nullptr;
-  Arena ar;
-  add_operands(ar, ops, dt);
-  ar.add((void**)&ops.CT, sizeof(double) * (size_t)k * d);
-  ar.add((void**)&flags, sizeof(int) * (size_t)flag_capacity(ops, dt, n, nseg_of_n(n)));
-  ar.add((void**)&ucnt, sizeof(int) * (size_t)kTileMaxGrid);
-  ar.add((void**)&ctr, sizeof(unsigned long long) * ROW_STRIDE);
-  ar.add((void**)&conv, sizeof(int) * 4);
-  if (knor_status r = ar.alloc(s, o.cap)) return r;
-  HIPCHK(hipMemsetAsync(ctr, 0, sizeof(unsigned long long) * ROW_STRIDE, s));
-  HIPCHK(launch_fill_i32(conv, 1, kNotConverged, s));
-  HIPCHK(launch_fill_i32(labels_out, n, -1, s));
-  HIPCHK(launch_prep_centroids(ops, s));
-  AssignJob job{};
-  job.X = X; job.dt = dt; job.n = n; job.d = d;
-  job.labels = labels_out; job.flags = flags; job.row = ctr; job.conv = conv;
-  job.ucnt = ucnt;
-  job.iter = 0; job.recheck_all = o.recheck == 2;
-  HIPCHK(launch_assign(ops, job, s));
-  HIPCHK(launch_recheck(ops, job, s));
-  if (dist2_out)
-    HIPCHK(launch_exact_dist2(X, dt, n, d, C, labels_out, dist2_out, s));
-  return KNOR_OK;
+  void* mem = nullptr;
+  if (knor_status r = knor::scratch_of_device(&mem)) return r;
+  return knor::assign_impl(X, dt, n, d, C, k, opts, labels_out, dist2_out, mem,
+                           knor::kScratchBytes);
 }
 
 knor_status knor_tile_values(const void* X, knor_dtype dt, int64_t n, int32_t d,
