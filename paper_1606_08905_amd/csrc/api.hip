@@ -596,7 +596,7 @@ static knor_status fit_impl(const void* X, knor_dtype dt, int64_t n, int d,
     ar.add((void**)&istd, sizeof(double) * (size_t)d);
     ar.add((void**)&loss_dev, sizeof(double));
     ar.add((void**)&stat_part, standardize_workspace(d));
-    ar.add(&pack_ws, mlp_pack_bytes(d, hM, k));
+    ar.add(&pack_ws, mlp_pack_bytes(d, hM, k, n));
     ar.add((void**)&dense, sizeof(int) * (size_t)n);
     ar.add((void**)&seg_off, sizeof(int) * (size_t)(nseg + 1));
     ar.add((void**)&list2, sizeof(int) * (size_t)nseg * kSeg);
@@ -612,7 +612,7 @@ static knor_status fit_impl(const void* X, knor_dtype dt, int64_t n, int d,
   knor_status rs = ar.alloc(s, o.cap);
   if (rs != KNOR_OK) return rs;
   update_plan_init(&plan, n, k, d, upd_ws);
-  if (learned) MP = mlp_pack_layout(d, hM, k, pack_ws);
+  if (learned) MP = mlp_pack_layout(d, hM, k, n, pack_ws);
   ExactPlan xplan{};
   if (exact) exact_plan_init(&xplan, n, k, d, exact_ws);
   int* conv = flagbuf;
@@ -1016,9 +1016,9 @@ knor_status knor_mlp_propose(const float* params, int32_t d, int32_t h,
   hipStream_t s = o.stream;
   void* pack_ws = nullptr;
   Arena ar;
-  ar.add(&pack_ws, mlp_pack_bytes(d, h, k));
+  ar.add(&pack_ws, mlp_pack_bytes(d, h, k, m));
   if (knor_status r = ar.alloc(s, o.cap)) return r;
-  const MlpPacked P = mlp_pack_layout(d, h, k, pack_ws);
+  const MlpPacked P = mlp_pack_layout(d, h, k, m, pack_ws);
   HIPCHK(launch_mlp_pack(params, L, P, s));
   // Xs is already standardized: no row list, no mean / scale
   HIPCHK(launch_mlp_forward(Xs, KNOR_F32, d, nullptr, (int)m, nullptr, nullptr, nullptr,

@@ -521,10 +521,11 @@ struct MlpPacked {
   int d, h, k, kpad, KP1;
   uint16_t *W1b, *W2b, *W3b;
   float* b3p;
+  int *fl_rows, *fl_pos, *fl_cnt;   // points the short-list pass defers (<= mmax)
 };
 int mlp_kpad(int k);
-size_t mlp_pack_bytes(int d, int h, int k);
-MlpPacked mlp_pack_layout(int d, int h, int k, void* ws);
+size_t mlp_pack_bytes(int d, int h, int k, int64_t mmax);
+MlpPacked mlp_pack_layout(int d, int h, int k, int64_t mmax, void* ws);
 hipError_t launch_mlp_pack(const float* th, const MlpLayout& L, const MlpPacked& P,
                            hipStream_t s);
 // cand (m x 16): points rows[q] (or q) of X standardized by mean / istd

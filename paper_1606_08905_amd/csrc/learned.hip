@@ -372,6 +372,7 @@ constexpr int kFwdPB = 2;                        // blocks of 16 points per wave
 constexpr int kFwdPoints = kFwdWaves * 16 * kFwdPB;
 constexpr int kFwdRows = 64;                     // weight rows per LDS chunk
 constexpr float kPadLogit = -3.0e38f;            // classes past k
+constexpr int kFwdList = 10;                     // keys per lane in the first pass
 
 // W1b (h x KP1, KP1 = 32 KD >= d; input dims in natural order, zero past d),
 // W2b (h x h) and W3b (kpad x h), both with permuted K columns; b3p (kpad)
@@ -447,17 +448,28 @@ struct RowStage {
   }
 };
 
-// descending top-16 list: insert key y (one median of three per entry)
-__device__ __forceinline__ void top16_insert(float (&L)[16], float y) {
+// descending list of the TL largest keys: insert key y (one median of three
+// per entry)
+template <int TL>
+__device__ __forceinline__ void topk_insert(float (&L)[TL], float y) {
 #pragma unroll
-  for (int i = 15; i >= 1; --i) L[i] = __builtin_amdgcn_fmed3f(L[i - 1], L[i], y);
+  for (int i = TL - 1; i >= 1; --i) L[i] = __builtin_amdgcn_fmed3f(L[i - 1], L[i], y);
   L[0] = L[0] > y ? L[0] : y;
 }
 
 // The forward pass of m points (rows[q], or q when rows is null) with the
-// top-16 epilogue.  Inputs are standardized as (x - mean) istd in FP64
-// (mean / istd null: taken as they are), rounded to FP32, then to BF16.
-template <int KD, int KH, typename T>
+// top-16 epilogue; point q's candidates go to row outpos[q] (or q) of cand.
+// Inputs are standardized as (x - mean) istd in FP64 (mean / istd null:
+// taken as they are), rounded to FP32, then to BF16.
+//
+// Each lane keeps the TL largest keys of its quarter of the classes.  With
+// TL = 16 the merged list is the top 16 outright.  With TL < 16 it is the top
+// 16 unless some quarter holds more than TL of them; then that quarter's
+// whole list is in the merged top 16 (its TL-th key is not below the 16th),
+// and the point is appended to (fl_rows, fl_pos) for a TL = 16 pass, which
+// overwrites its row.  A quarter holds more than 10 of 16 keys for about 0.3%
+// of points with classes in random order.
+template <int KD, int KH, int TL, typename T>
 __global__ __launch_bounds__(64 * kFwdWaves) void mlp_forward_kernel(
     const T* __restrict__ X, int d, const int* __restrict__ rows, int m,
     const int* __restrict__ mdev, const double* __restrict__ mean,
@@ -465,7 +477,9 @@ __global__ __launch_bounds__(64 * kFwdWaves) void mlp_forward_kernel(
     const float* __restrict__ b1, const uint16_t* __restrict__ W2b,
     const float* __restrict__ b2, const uint16_t* __restrict__ W3b,
     const float* __restrict__ b3p, int k, int kpad, int cbits,
-    int32_t* __restrict__ cand) {
+    int32_t* __restrict__ cand, const int* __restrict__ outpos, int* __restrict__ fl_rows,
+    int* __restrict__ fl_pos, int* __restrict__ fl_cnt) {
+  static_assert(TL >= 1 && TL <= 16, "list length");
   constexpr int H = 32 * KH, LD = H + 8, KP1 = 32 * KD, PB = kFwdPB;
   using RS = RowStage<KH>;
   extern __shared__ __attribute__((aligned(16))) uint16_t sW[];   // 2 x 64 x LD
@@ -577,11 +591,11 @@ __global__ __launch_bounds__(64 * kFwdWaves) void mlp_forward_kernel(
     for (int s = 0; s < KH; ++s) h2f[pb][s] = frag_of(h2w[pb][s]);
 
   // layer 3 with the top-16 epilogue; the first W3b chunk is in buffer NC2 & 1
-  float L[PB][16];
+  float L[PB][TL];
 #pragma unroll
   for (int pb = 0; pb < PB; ++pb)
 #pragma unroll
-    for (int i = 0; i < 16; ++i) L[pb][i] = -INFINITY;
+    for (int i = 0; i < TL; ++i) L[pb][i] = -INFINITY;
   const uint32_t cmask = (1u << cbits) - 1u;
   const int NC3 = kpad / kFwdRows;
 #pragma unroll 1
@@ -590,7 +604,7 @@ __global__ __launch_bounds__(64 * kFwdWaves) void mlp_forward_kernel(
     uint16_t* cur = slot ? buf1 : buf0;
     uint16_t* nxt = slot ? buf0 : buf1;
     if (c + 1 < NC3) pre.load(W3b, (c + 1) * kFwdRows, kpad);
-#pragma unroll
+#pragma unroll 1
     for (int bb = 0; bb < kFwdRows / 16; ++bb) {
       const int cl0 = c * kFwdRows + 16 * bb;
       bf8l a[KH];
@@ -612,7 +626,7 @@ __global__ __launch_bounds__(64 * kFwdWaves) void mlp_forward_kernel(
 #pragma unroll
         for (int pb = 0; pb < PB; ++pb) {
           const float key = __uint_as_float((__float_as_uint(acc[pb][r]) & ~cmask) | code);
-          top16_insert(L[pb], key);
+          topk_insert<TL>(L[pb], key);
         }
       }
     }
@@ -626,9 +640,7 @@ __global__ __launch_bounds__(64 * kFwdWaves) void mlp_forward_kernel(
   for (int pb = 0; pb < PB; ++pb) {
     float* dst = sK + ((((size_t)wave * PB + pb) * 16 + col) * 4 + grp) * 16;
 #pragma unroll
-    for (int i = 0; i < 16; i += 4)
-      *reinterpret_cast<float4*>(dst + i) = make_float4(L[pb][i], L[pb][i + 1], L[pb][i + 2],
-                                                        L[pb][i + 3]);
+    for (int i = 0; i < TL; ++i) dst[i] = L[pb][i];
   }
   __syncthreads();
   if (lane < 16 * PB) {
@@ -638,13 +650,14 @@ __global__ __launch_bounds__(64 * kFwdWaves) void mlp_forward_kernel(
       const float* src = sK + (((size_t)wave * PB + pb) * 16 + cc) * 4 * 16;
       int hd[4] = {0, 0, 0, 0};
       int32_t out[16];
+      float best = -INFINITY;
 #pragma unroll
       for (int i = 0; i < 16; ++i) {
-        float best = -INFINITY;
+        best = -INFINITY;
         int bg = 0;
 #pragma unroll
         for (int g = 0; g < 4; ++g) {
-          const float v = hd[g] < 16 ? src[g * 16 + hd[g]] : -INFINITY;
+          const float v = hd[g] < TL ? src[g * 16 + hd[g]] : -INFINITY;
           if (v > best) { best = v; bg = g; }
         }
 #pragma unroll
@@ -652,7 +665,22 @@ __global__ __launch_bounds__(64 * kFwdWaves) void mlp_forward_kernel(
         const int j = (int)(cmask - (__float_as_uint(best) & cmask));
         out[i] = (best == -INFINITY || j >= k) ? -1 : j;
       }
-      int4* o4 = reinterpret_cast<int4*>(cand + (size_t)q * kMlpTop);
+      if constexpr (TL < 16) {
+        // best is now the 16th largest merged key
+        bool full = false;
+#pragma unroll
+        for (int g = 0; g < 4; ++g) {
+          const float lastg = src[g * 16 + TL - 1];
+          full |= lastg > -INFINITY && lastg >= best;
+        }
+        if (full) {
+          const int slot = atomicAdd(fl_cnt, 1);
+          fl_rows[slot] = rows ? rows[q] : q;
+          fl_pos[slot] = outpos ? outpos[q] : q;
+        }
+      }
+      const int qo = outpos ? outpos[q] : q;
+      int4* o4 = reinterpret_cast<int4*>(cand + (size_t)qo * kMlpTop);
 #pragma unroll
       for (int i = 0; i < 4; ++i)
         o4[i] = make_int4(out[4 * i], out[4 * i + 1], out[4 * i + 2], out[4 * i + 3]);
@@ -673,14 +701,15 @@ static int kd_of(int d) {
   return kd;
 }
 
-size_t mlp_pack_bytes(int d, int h, int k) {
+size_t mlp_pack_bytes(int d, int h, int k, int64_t mmax) {
   const int kpad = mlp_kpad(k), KP1 = 32 * kd_of(d);
   auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
   return al(sizeof(uint16_t) * (size_t)h * KP1) + al(sizeof(uint16_t) * (size_t)h * h) +
-         al(sizeof(uint16_t) * (size_t)kpad * h) + al(sizeof(float) * (size_t)kpad);
+         al(sizeof(uint16_t) * (size_t)kpad * h) + al(sizeof(float) * (size_t)kpad) +
+         2 * al(sizeof(int) * (size_t)mmax) + al(sizeof(int));
 }
 
-MlpPacked mlp_pack_layout(int d, int h, int k, void* ws) {
+MlpPacked mlp_pack_layout(int d, int h, int k, int64_t mmax, void* ws) {
   MlpPacked P{};
   P.d = d; P.h = h; P.k = k; P.kpad = mlp_kpad(k); P.KP1 = 32 * kd_of(d);
   auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
@@ -688,7 +717,10 @@ MlpPacked mlp_pack_layout(int d, int h, int k, void* ws) {
   P.W1b = (uint16_t*)c; c += al(sizeof(uint16_t) * (size_t)h * P.KP1);
   P.W2b = (uint16_t*)c; c += al(sizeof(uint16_t) * (size_t)h * h);
   P.W3b = (uint16_t*)c; c += al(sizeof(uint16_t) * (size_t)P.kpad * h);
-  P.b3p = (float*)c;
+  P.b3p = (float*)c; c += al(sizeof(float) * (size_t)P.kpad);
+  P.fl_rows = (int*)c; c += al(sizeof(int) * (size_t)mmax);
+  P.fl_pos = (int*)c; c += al(sizeof(int) * (size_t)mmax);
+  P.fl_cnt = (int*)c;
   return P;
 }
 
@@ -710,14 +742,26 @@ static hipError_t fwd_launch(const T* X, int d, const int* rows, int m, const in
   const size_t lds_w = sizeof(uint16_t) * 2 * kFwdRows * LD;
   const size_t lds_k = sizeof(float) * kFwdWaves * kFwdPB * 16 * 4 * 16;
   const size_t lds = lds_w > lds_k ? lds_w : lds_k;
-  hipError_t e = hipFuncSetAttribute(
-      reinterpret_cast<const void*>(&mlp_forward_kernel<KD, KH, T>),
-      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  for (const void* kp : {reinterpret_cast<const void*>(&mlp_forward_kernel<KD, KH, kFwdList, T>),
+                         reinterpret_cast<const void*>(&mlp_forward_kernel<KD, KH, 16, T>)}) {
+    hipError_t e = hipFuncSetAttribute(kp, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  // first pass with short lists; the points it flags again with full lists
+  // (the second grid covers every point; workgroups past the flagged count
+  // return at once)
+  hipError_t e = launch_fill_i32(P.fl_cnt, 1, 0, s);
   if (e != hipSuccess) return e;
   const int grid = (m + kFwdPoints - 1) / kFwdPoints;
-  hipLaunchKernelGGL((mlp_forward_kernel<KD, KH, T>), dim3(grid), dim3(64 * kFwdWaves), lds, s,
-                     X, d, rows, m, mdev, mean, istd, P.W1b, th + L.b1, P.W2b, th + L.b2,
-                     P.W3b, P.b3p, L.k, P.kpad, code_bits(P.kpad), cand);
+  hipLaunchKernelGGL((mlp_forward_kernel<KD, KH, kFwdList, T>), dim3(grid), dim3(64 * kFwdWaves),
+                     lds, s, X, d, rows, m, mdev, mean, istd, P.W1b, th + L.b1, P.W2b,
+                     th + L.b2, P.W3b, P.b3p, L.k, P.kpad, code_bits(P.kpad), cand,
+                     (const int*)nullptr, P.fl_rows, P.fl_pos, P.fl_cnt);
+  hipLaunchKernelGGL((mlp_forward_kernel<KD, KH, 16, T>), dim3(grid), dim3(64 * kFwdWaves),
+                     lds, s, X, d, (const int*)P.fl_rows, m, (const int*)P.fl_cnt, mean, istd,
+                     P.W1b, th + L.b1, P.W2b, th + L.b2, P.W3b, P.b3p, L.k, P.kpad,
+                     code_bits(P.kpad), cand, (const int*)P.fl_pos, (int*)nullptr,
+                     (int*)nullptr, (int*)nullptr);
   return hipGetLastError();
 }
 
