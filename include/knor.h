@@ -237,6 +237,67 @@ knor_status knor_fit(const void* X, knor_dtype dt, int64_t n, int32_t d,
                      int32_t max_iters, double tol, const knor_opts* opts,
                      double* C_out, int32_t* labels_out, knor_stats* st);
 
+/* Host-link counters of knor_fit_streamed, per iteration. */
+enum {
+  KNOR_IO_COPIED = 0,   /* rows copied from host memory in whole batches (full
+                           passes: iteration 0, every iteration without MTI,
+                           and the objective)                               */
+  KNOR_IO_GATHERED = 1, /* rows read from host memory one by one: points
+                           that fail MTI Clause 1 and are not in the cache  */
+  KNOR_IO_CACHED = 2,   /* rows of such points served by the row cache      */
+  KNOR_IO_ADMITTED = 3, /* rows written into the row cache (refresh)        */
+  KNOR_NIO = 4
+};
+
+typedef struct {
+  uint32_t struct_size;   /* sizeof(knor_stream_opts); 0 selects defaults    */
+  int64_t batch_rows;     /* rows per batch, rounded up to a multiple of
+                             4096; 0 = min(n, 2^22) rounded up.  The device
+                             holds two batches of rows for staging          */
+  int64_t cache_rows;     /* row cache capacity in rows (0 = no cache).  The
+                             device holds two regions of this many rows     */
+  int32_t cache_interval; /* I: the cache refreshes at iterations I, 3I, 7I,
+                             15I, ... (each gap twice the previous); 0 = 5   */
+  int32_t skip_objective; /* 1: leave st->objective at 0 (saves the final
+                             pass over X); 0 (default): compute it          */
+  int64_t* io_counters;   /* HOST, optional: max_iters x KNOR_NIO; row t
+                             receives iteration t's counters; the objective
+                             pass adds to the last iteration's row          */
+} knor_stream_opts;
+
+/* knor_fit_streamed: knor_fit for data that stays in host memory (the
+ * paper's semi-external-memory mode, Section "Semi-External Memory": I/O
+ * minimization and the partitioned row cache).  Same iteration, same
+ * results as knor_fit with opts->update = 1 on the same values.  Each
+ * iteration runs over batches of batch_rows consecutive rows; a batch's
+ * rows reach the device whole (a DMA copy) when every point needs its
+ * distances (iteration 0, or prune = 0), and otherwise only for the points
+ * that fail MTI Clause 1: a point that Clause 1 keeps has no row read.  A
+ * needed row comes from the device row cache if the cache holds it (the
+ * rows active at the last refresh iteration, lowest point indices first up
+ * to cache_rows), else from host memory, read by the kernel over the host
+ * link.
+ *   X          HOST n x d, dtype KNOR_F32 or KNOR_BF16, in page-locked
+ *              memory the device can read (hipHostMalloc, or a pinned
+ *              torch tensor); anything else gives KNOR_ERR_INVALID_ARG.
+ *              Must not change during the call.
+ *   opts       as for knor_fit, with update = 1 required (the exact mean,
+ *              which no order of the passes changes; 0 gives
+ *              KNOR_ERR_UNSUPPORTED); learned = 1, clause2 = 2, init =
+ *              KNOR_INIT_KMEANSPP, autotune, profile_ms and
+ *              profile_launches give KNOR_ERR_UNSUPPORTED.  Convergence is
+ *              polled after every iteration (poll_every is ignored).
+ *   sopts      may be NULL (defaults).
+ *   C_init, C_out, labels_out, st: as for knor_fit (C_init, C_out and
+ *              labels_out in DEVICE memory).
+ * Uses one extra stream (default priority) for the transfers.  Blocks
+ * until the fit is complete. */
+knor_status knor_fit_streamed(const void* X, knor_dtype dt, int64_t n, int32_t d,
+                              int32_t k, knor_init init, const double* C_init,
+                              int32_t max_iters, double tol, const knor_opts* opts,
+                              const knor_stream_opts* sopts, double* C_out,
+                              int32_t* labels_out, knor_stats* st);
+
 /* knor_assign: one assignment step (Algorithm 1, nearest-centroid loop).
  *   C          DEVICE k x d FP64.
  *   labels_out DEVICE n int32: the nearest centroid of every point.
@@ -363,10 +424,12 @@ knor_status knor_mlp_train_step(float* params, float* adam_m, float* adam_v,
                                 const knor_opts* opts);
 
 /* Candidates of m standardized points Xs (DEVICE m x d): cand_out (DEVICE
- * m x 16 int32) row p holds, for each of 16 fixed class subsets (class j is
- * in subset 4 ((j mod 16) div 4) + ((j div 16) mod 4)), the class with the
- * largest logit (earliest on ties), or -1 for a subset without classes.
- * Asynchronous on opts->stream. */
+ * m x 16 int32) row p holds the 16 classes with the largest keys, in
+ * decreasing key order.  The key of class j is its FP32 logit with the low
+ * B mantissa bits replaced by 2^B - 1 - j, where 2^B >= k rounded up to a
+ * multiple of 64 (so value and class share one float; among logits that
+ * agree in their leading bits the code decides).  When k < 16 the entries
+ * past the k real classes are -1.  Asynchronous on opts->stream. */
 knor_status knor_mlp_propose(const float* params, int32_t d, int32_t h,
                              int32_t k, const float* Xs, int64_t m,
                              int32_t* cand_out, const knor_opts* opts);
@@ -378,7 +441,8 @@ const char* knor_status_string(knor_status s);
  * knor_opts.update, 0.3.0 knor_opts.centroid_history, the init modes
  * SHUFFLE_FIRSTK and KMEANSPP and the kernel group KNOR_PROF_CERTIFY (so
  * profile arrays hold KNOR_NPROF = 10 entries; each new field changed
- * sizeof(knor_opts), which struct_size must equal). */
+ * sizeof(knor_opts), which struct_size must equal); 0.4.0 added
+ * knor_fit_streamed and knor_stream_opts. */
 int32_t knor_version(void);
 
 #ifdef __cplusplus

@@ -94,6 +94,17 @@ class Stats(ctypes.Structure):
 _lib = None
 
 
+class StreamOpts(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_uint32), ("batch_rows", ctypes.c_int64),
+                ("cache_rows", ctypes.c_int64), ("cache_interval", ctypes.c_int32),
+                ("skip_objective", ctypes.c_int32), ("io_counters", ctypes.c_void_p)]
+
+
+# columns of the streamed fit's per-iteration I/O counters (KNOR_IO_*)
+IO_COUNTERS = ["copied", "gathered", "cached", "admitted"]
+NIO = len(IO_COUNTERS)
+
+
 def library_path() -> str:
     return _LIB
 
@@ -124,6 +135,10 @@ def load():
     L.knor_update.argtypes = [P, ctypes.c_int, i64, i32, P, i32, P,
                               ctypes.POINTER(Opts), P, P]
     L.knor_update.restype = ctypes.c_int
+    L.knor_fit_streamed.argtypes = [P, ctypes.c_int, i64, i32, i32, ctypes.c_int, P, i32,
+                                    f64, ctypes.POINTER(Opts), ctypes.POINTER(StreamOpts),
+                                    P, P, ctypes.POINTER(Stats)]
+    L.knor_fit_streamed.restype = ctypes.c_int
     L.knor_fit_batched.argtypes = [ctypes.POINTER(Problem), i32,
                                    ctypes.POINTER(Opts), ctypes.POINTER(Stats)]
     L.knor_fit_batched.restype = ctypes.c_int
@@ -282,6 +297,75 @@ def fit(X, k, C0=None, init="given", max_iters=100, tol=0.0, prune=True,
                     lab.data_ptr(), ctypes.byref(st))
     _raise(rc)
     s = st.as_dict()
+    if history:
+        s["label_history"] = hist[: st.iters]
+    if counters:
+        s["counters"] = cnt[: st.iters]
+    if centroid_history:
+        s["centroid_history"] = chist[: st.iters]
+    return C, lab, s
+
+
+def fit_streamed(X, k, C0=None, init="given", max_iters=100, tol=0.0, prune=True,
+                 recheck=1, seed=0, history=False, counters=False, check_numeric=True,
+                 workspace_cap=0, tile_blocks=0, tile_resident=0, batch_rows=0,
+                 cache_rows=0, cache_interval=0, objective=True, centroid_history=False,
+                 device=None):
+    """Lloyd's k-means with the rows in host memory (knor_fit_streamed).
+
+    X: a CPU tensor in pinned memory (torch.Tensor.pin_memory()), float32
+    or bfloat16.  The outputs live on `device` (default: the current CUDA
+    device).  Same results as fit(..., update="exact") on the same values.
+    batch_rows / cache_rows / cache_interval: 0 = library defaults (2^22
+    rows per batch, no row cache, refresh interval 5).  objective=False
+    skips the final pass that computes stats["objective"].  Returns (C,
+    labels, stats dict) with stats["io"]: (iters, 4) int64 numpy array of
+    rows copied whole, gathered one by one, served by the row cache, and
+    admitted to it (IO_COUNTERS), plus the options of fit()."""
+    torch = _torch()
+    import numpy as np
+    L = load()
+    if X.is_cuda or not X.is_pinned():
+        raise ValueError("X must be a pinned CPU tensor (X.pin_memory())")
+    if not X.is_contiguous():
+        raise ValueError("X must be contiguous")
+    n, d = X.shape
+    dev = torch.device(device) if device is not None else torch.device(
+        "cuda", torch.cuda.current_device())
+    C = torch.empty((k, d), dtype=torch.float64, device=dev)
+    lab = torch.empty((n,), dtype=torch.int32, device=dev)
+    if init not in INITS:
+        raise ValueError(f"init must be one of {sorted(INITS)}")
+    init_code = INITS[init]
+    if init_code == INIT_GIVEN:
+        if C0 is None:
+            raise ValueError("init='given' needs C0")
+        C0 = torch.as_tensor(C0, dtype=torch.float64, device=dev).contiguous()
+        c0p = C0.data_ptr()
+    else:
+        c0p = None
+    hist = torch.empty((max_iters, n), dtype=torch.int32, device=dev) if history else None
+    chist = (torch.empty((max_iters, k, d), dtype=torch.float64, device=dev)
+             if centroid_history else None)
+    cnt = np.zeros((max_iters, NCOUNTERS), np.int64) if counters else None
+    io = np.zeros((max_iters, NIO), np.int64)
+    o = _opts(prune, recheck, check_numeric, seed, None, workspace_cap, hist, cnt, 0,
+              None, tile_blocks, tile_resident, False, False, 0, 0, "exact", chist, "auto")
+    so = StreamOpts()
+    so.struct_size = ctypes.sizeof(StreamOpts)
+    so.batch_rows = int(batch_rows)
+    so.cache_rows = int(cache_rows)
+    so.cache_interval = int(cache_interval)
+    so.skip_objective = 0 if objective else 1
+    so.io_counters = io.ctypes.data
+    st = Stats()
+    with torch.cuda.device(dev):
+        rc = L.knor_fit_streamed(X.data_ptr(), _dtype_code(X), n, d, k, init_code, c0p,
+                                 max_iters, float(tol), ctypes.byref(o), ctypes.byref(so),
+                                 C.data_ptr(), lab.data_ptr(), ctypes.byref(st))
+    _raise(rc)
+    s = st.as_dict()
+    s["io"] = io[: st.iters]
     if history:
         s["label_history"] = hist[: st.iters]
     if counters:

@@ -515,6 +515,49 @@ static bool cand_enabled(const Opts& o, knor_dtype dt, int k) {
   return o.clause2 == 2 || k >= kCandMinK;
 }
 
+// Per-iteration counters (iter_counters) and their sums (st) from the
+// device's counter rows of the first hiters iterations.  Distances
+// evaluated in iteration i: the tiles and FP64 rechecks (all k per point,
+// or the candidate lists), and Clause-3 tightening.
+static void report_counters(const std::vector<unsigned long long>& hc, int hiters, int64_t n,
+                            int k, bool mti, const std::vector<char>& cand_used,
+                            const std::vector<int64_t>& queried, int64_t* iter_counters,
+                            knor_stats* st) {
+  auto dists_of = [&](int i) {
+    const unsigned long long* r = &hc[(size_t)i * ROW_STRIDE];
+    const int64_t tighten = (mti && i > 0) ? (n - (int64_t)r[ROW_PRUNED_A]) : 0;
+    if (cand_used[(size_t)i]) return (int64_t)r[ROW_DISTS] + tighten;
+    return ((int64_t)r[ROW_SCANNED] + (int64_t)r[ROW_FLAG_HEAD]) * k + tighten;
+  };
+  if (iter_counters)
+    for (int i = 0; i < hiters; ++i) {
+      const unsigned long long* r = &hc[(size_t)i * ROW_STRIDE];
+      int64_t* dst = iter_counters + (size_t)i * KNOR_NCOUNTERS;
+      dst[KNOR_CNT_CHANGED] = (int64_t)r[ROW_CHANGED];
+      dst[KNOR_CNT_SCANNED] = (int64_t)r[ROW_SCANNED];
+      dst[KNOR_CNT_PRUNED_A] = (int64_t)r[ROW_PRUNED_A];
+      dst[KNOR_CNT_PRUNED_B] = (int64_t)r[ROW_PRUNED_B];
+      dst[KNOR_CNT_RECHECKED] = (int64_t)r[ROW_FLAG_HEAD];
+      dst[KNOR_CNT_CERTIFIED] = (int64_t)r[ROW_CERTIFIED];
+      dst[KNOR_CNT_QUERIED] = queried[(size_t)i];
+      dst[KNOR_CNT_DISTS] = dists_of(i);
+    }
+  if (st) {
+    memset(st, 0, sizeof(*st));
+    st->iters = hiters;
+    st->changed_last = (int64_t)hc[(size_t)(hiters - 1) * ROW_STRIDE + ROW_CHANGED];
+    for (int i = 0; i < hiters; ++i) {
+      const unsigned long long* r = &hc[(size_t)i * ROW_STRIDE];
+      st->scanned += (int64_t)r[ROW_SCANNED];
+      st->pruned_a += (int64_t)r[ROW_PRUNED_A];
+      st->pruned_b += (int64_t)r[ROW_PRUNED_B];
+      st->rechecked += (int64_t)r[ROW_FLAG_HEAD];
+      st->certified += (int64_t)r[ROW_CERTIFIED];
+      st->dists_computed += dists_of(i);
+    }
+  }
+}
+
 static knor_status fit_impl(const void* X, knor_dtype dt, int64_t n, int d,
                             int k, knor_init init, const double* C_init,
                             int max_iters, double tol, const Opts& o,
@@ -817,41 +860,9 @@ static knor_status fit_impl(const void* X, knor_dtype dt, int64_t n, int d,
   const int converged = hconv != kNotConverged;
   const int hiters = converged ? hconv + 1 : max_iters;
 
-  // distances evaluated in iteration i: the tiles and FP64 rechecks (all k
-  // per point, or the candidate lists), and Clause-3 tightening
-  auto dists_of = [&](int i) {
-    const unsigned long long* r = &hc[(size_t)i * ROW_STRIDE];
-    const int64_t tighten = (mti && i > 0) ? (n - (int64_t)r[ROW_PRUNED_A]) : 0;
-    if (cand_used[(size_t)i]) return (int64_t)r[ROW_DISTS] + tighten;
-    return ((int64_t)r[ROW_SCANNED] + (int64_t)r[ROW_FLAG_HEAD]) * k + tighten;
-  };
-  if (o.iter_counters)
-    for (int i = 0; i < hiters; ++i) {
-      const unsigned long long* r = &hc[(size_t)i * ROW_STRIDE];
-      int64_t* dst = o.iter_counters + (size_t)i * KNOR_NCOUNTERS;
-      dst[KNOR_CNT_CHANGED] = (int64_t)r[ROW_CHANGED];
-      dst[KNOR_CNT_SCANNED] = (int64_t)r[ROW_SCANNED];
-      dst[KNOR_CNT_PRUNED_A] = (int64_t)r[ROW_PRUNED_A];
-      dst[KNOR_CNT_PRUNED_B] = (int64_t)r[ROW_PRUNED_B];
-      dst[KNOR_CNT_RECHECKED] = (int64_t)r[ROW_FLAG_HEAD];
-      dst[KNOR_CNT_CERTIFIED] = (int64_t)r[ROW_CERTIFIED];
-      dst[KNOR_CNT_QUERIED] = queried[(size_t)i];
-      dst[KNOR_CNT_DISTS] = dists_of(i);
-    }
+  report_counters(hc, hiters, n, k, mti, cand_used, queried, o.iter_counters, st);
   if (st) {
-    memset(st, 0, sizeof(*st));
-    st->iters = hiters;
     st->converged = converged;
-    st->changed_last = (int64_t)hc[(size_t)(hiters - 1) * ROW_STRIDE + ROW_CHANGED];
-    for (int i = 0; i < hiters; ++i) {
-      const unsigned long long* r = &hc[(size_t)i * ROW_STRIDE];
-      st->scanned += (int64_t)r[ROW_SCANNED];
-      st->pruned_a += (int64_t)r[ROW_PRUNED_A];
-      st->pruned_b += (int64_t)r[ROW_PRUNED_B];
-      st->rechecked += (int64_t)r[ROW_FLAG_HEAD];
-      st->certified += (int64_t)r[ROW_CERTIFIED];
-      st->dists_computed += dists_of(i);
-    }
     st->mlp_queries = mlp_queries;
     st->objective = hobj;
     st->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
@@ -1040,7 +1051,7 @@ const char* knor_status_string(knor_status s) {
   return "unknown status";
 }
 
-int32_t knor_version(void) { return 300; }
+int32_t knor_version(void) { return 400; }
 
 knor_status knor_fit(const void* X, knor_dtype dt, int64_t n, int32_t d,
                      int32_t k, knor_init init, const double* C_init,
@@ -1170,6 +1181,382 @@ knor_status knor_fit_batched(const knor_problem* probs, int32_t count,
   for (int i = 0; i < count; ++i)
     if (res[i] != KNOR_OK) return res[i];
   return KNOR_OK;
+}
+
+// ---------------------------------------------------------------------------
+// streamed fit: rows in host memory
+// ---------------------------------------------------------------------------
+
+// The row cache's refresh iterations: I, then each gap twice the previous
+// one (I, 3I, 7I, 15I, ...).
+static bool cache_refresh_at(int t, int I) {
+  int64_t r = I, gap = 2 * (int64_t)I;
+  while (r < t) {
+    r += gap;
+    gap *= 2;
+  }
+  return r == t;
+}
+
+// The device's address of page-locked host memory X.
+static knor_status host_rows_on_device(const void* X, const void** xd) {
+  hipPointerAttribute_t a{};
+  if (hipPointerGetAttributes(&a, X) != hipSuccess) {
+    (void)hipGetLastError();
+    return KNOR_ERR_INVALID_ARG;
+  }
+  if (a.type != hipMemoryTypeHost) return KNOR_ERR_INVALID_ARG;
+  void* p = nullptr;
+  if (hipHostGetDevicePointer(&p, const_cast<void*>(X), 0) != hipSuccess || !p) {
+    (void)hipGetLastError();
+    return KNOR_ERR_INVALID_ARG;
+  }
+  *xd = p;
+  return KNOR_OK;
+}
+
+// The transfer stream and its events.  Declared after the workspace, so it
+// is drained before the workspace is released.
+struct CopyLane {
+  hipStream_t cs = nullptr;
+  hipEvent_t ready[2] = {nullptr, nullptr}, done[2] = {nullptr, nullptr};
+  hipEvent_t start = nullptr;
+  hipError_t init() {
+    hipError_t e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+    for (int i = 0; i < 2 && e == hipSuccess; ++i) {
+      e = hipEventCreateWithFlags(&ready[i], hipEventDisableTiming);
+      if (e == hipSuccess) e = hipEventCreateWithFlags(&done[i], hipEventDisableTiming);
+    }
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&start, hipEventDisableTiming);
+    return e;
+  }
+  ~CopyLane() {
+    if (cs) (void)hipStreamSynchronize(cs);
+    for (hipEvent_t e : {ready[0], ready[1], done[0], done[1], start})
+      if (e) (void)hipEventDestroy(e);
+    if (cs) (void)hipStreamDestroy(cs);
+    (void)hipGetLastError();
+  }
+};
+
+struct StreamCfg {
+  int64_t batch = 0;       // rows per batch (multiple of kSeg)
+  int64_t cache = 0;       // cache capacity in rows
+  int interval = 5;
+  int skip_objective = 0;
+  int64_t* io_out = nullptr;
+};
+
+// One iteration of the streamed fit visits the batches in order.  Batch b's
+// rows go to staging buffer b mod 2 on the transfer stream (a DMA copy of
+// the whole batch, or the fetch kernel for the points that fail Clause 1)
+// while the compute stream works on batch b - 1 from the other buffer; the
+// compute stream then runs the in-memory iteration's kernels on the batch's
+// views (filter, tile, recheck, and the exact update's moves).  After the
+// last batch: the exact update's division, the cache switch (refresh
+// iterations), s(c), and the convergence poll.
+static knor_status fit_streamed_impl(const void* X, const void* Xd, knor_dtype dt, int64_t n,
+                                     int d, int k, knor_init init, const double* C_init,
+                                     int max_iters, double tol, const Opts& o,
+                                     const StreamCfg& sc, double* C_out, int32_t* labels_out,
+                                     knor_stats* st) {
+  auto t0 = std::chrono::steady_clock::now();
+  hipStream_t s = o.stream;
+  const int kpad = (k + 15) / 16 * 16;
+  const bool mti = o.prune == 1;
+  const bool use_cache = mti && sc.cache > 0;
+  const size_t rb = (size_t)d * (dt == KNOR_F32 ? 4 : 2);
+  const int64_t B = sc.batch;
+  const int nsegB = nseg_of_n(B);
+  const int nseg = nseg_of_n(n);
+  const int nbat = (int)((n + B - 1) / B);
+  const bool need_obj = st && !sc.skip_objective;
+
+  CentroidOps ops{};
+  ops.k = k; ops.kpad = kpad; ops.d = d; ops.dp = pad_dim(d); ops.dpb = pad_dim_bf16(d);
+  ops.C64 = C_out;
+  if (knor_status r = select_tile(ops, o)) return r;
+  float *u = nullptr, *drift = nullptr, *s_half = nullptr;
+  int *list = nullptr, *seg_cnt = nullptr, *flags = nullptr, *ucnt = nullptr;
+  int *flagbuf = nullptr, *dirty = nullptr, *nj = nullptr;
+  unsigned long long *ctr = nullptr, *io = nullptr;
+  int64_t* rows_dev = nullptr;
+  void* exact_ws = nullptr;
+  void* stage[2] = {nullptr, nullptr};
+  void* creg[2] = {nullptr, nullptr};
+  int* cpts[2] = {nullptr, nullptr};
+  int *pslot = nullptr, *segc = nullptr;
+  int64_t *abase = nullptr, *rcnt = nullptr;
+  double *dist2 = nullptr, *sumtmp = nullptr, *objective = nullptr;
+
+  Arena ar;
+  add_operands(ar, ops, dt);
+  ar.add((void**)&ops.CT, sizeof(double) * (size_t)k * d);
+  ar.add((void**)&drift, sizeof(float) * (size_t)k);
+  ar.add((void**)&s_half, sizeof(float) * (size_t)k);
+  ar.add((void**)&dirty, sizeof(int) * (size_t)k);
+  ar.add((void**)&nj, sizeof(int) * (size_t)k);
+  ar.add((void**)&flags, sizeof(int) * (size_t)flag_capacity(ops, dt, B, nsegB));
+  ar.add((void**)&ucnt, sizeof(int) * (size_t)kTileMaxGrid);
+  if (mti) {
+    ar.add((void**)&u, sizeof(float) * (size_t)n);
+    ar.add((void**)&list, sizeof(int) * (size_t)nsegB * kSeg);
+    ar.add((void**)&seg_cnt, sizeof(int) * (size_t)nsegB);
+  }
+  const size_t ctr_bytes = sizeof(unsigned long long) * ROW_STRIDE * (size_t)max_iters;
+  const size_t io_bytes = sizeof(unsigned long long) * KNOR_NIO * (size_t)max_iters;
+  ar.add((void**)&ctr, ctr_bytes);
+  ar.add((void**)&io, io_bytes);
+  ar.add((void**)&flagbuf, sizeof(int) * 8);
+  ar.add((void**)&rows_dev, sizeof(int64_t) * (size_t)k);
+  ar.add(&exact_ws, exact_workspace_bytes(n, k, d));
+  for (int i = 0; i < 2; ++i) ar.add(&stage[i], rb * (size_t)B);
+  if (use_cache) {
+    for (int i = 0; i < 2; ++i) {
+      ar.add(&creg[i], rb * (size_t)sc.cache);
+      ar.add((void**)&cpts[i], sizeof(int) * (size_t)sc.cache);
+    }
+    ar.add((void**)&pslot, sizeof(int) * (size_t)n);
+    ar.add((void**)&segc, sizeof(int) * (size_t)nseg);
+    ar.add((void**)&abase, sizeof(int64_t) * (size_t)(nseg + 1));
+    ar.add((void**)&rcnt, sizeof(int64_t) * 2);
+  }
+  if (need_obj) {
+    ar.add((void**)&dist2, sizeof(double) * (size_t)n);
+    ar.add((void**)&sumtmp, sizeof(double) * (size_t)(n / kLeaf + 2));
+    ar.add((void**)&objective, sizeof(double));
+  }
+  if (knor_status r = ar.alloc(s, o.cap)) return r;
+  ExactPlan xplan{};
+  exact_plan_init(&xplan, n, k, d, exact_ws);
+  int* conv = flagbuf;
+  int* bad = flagbuf + 1;
+  HIPCHK(hipMemsetAsync(flagbuf, 0, sizeof(int) * 8, s));
+  HIPCHK(launch_fill_i32(conv, 1, kNotConverged, s));
+  HIPCHK(hipMemsetAsync(ctr, 0, ctr_bytes, s));
+  HIPCHK(hipMemsetAsync(io, 0, io_bytes, s));
+
+  // numeric check before anything is written to the outputs (one read of
+  // X over the host link)
+  if (o.check_numeric) {
+    HIPCHK(launch_check_finite(Xd, dt, n * (int64_t)d, bad, s));
+    if (init == KNOR_INIT_GIVEN)
+      HIPCHK(launch_check_finite(C_init, KNOR_F64, (int64_t)k * d, bad, s));
+    int hbad = 0;
+    HIPCHK(hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (hbad) return KNOR_ERR_NUMERIC;
+  }
+  if (init == KNOR_INIT_GIVEN) {
+    if (C_init != C_out)
+      HIPCHK(hipMemcpyAsync(C_out, C_init, sizeof(double) * (size_t)k * d,
+                            hipMemcpyDeviceToDevice, s));
+  } else {
+    std::vector<int64_t> rows = init == KNOR_INIT_FORGY ? forgy_rows(n, k, o.seed)
+                                                        : shuffle_first_k(n, k, o.seed);
+    HIPCHK(hipMemcpyAsync(rows_dev, rows.data(), sizeof(int64_t) * k,
+                          hipMemcpyHostToDevice, s));
+    HIPCHK(launch_gather_rows(Xd, dt, d, rows_dev, k, C_out, s));   // k rows over the link
+    HIPCHK(hipStreamSynchronize(s));   // `rows` leaves scope
+  }
+  HIPCHK(launch_prep_centroids(ops, s));
+  HIPCHK(launch_fill_i32(labels_out, n, -1, s));
+  HIPCHK(launch_fill_i32(dirty, k, 1, s));
+  HIPCHK(launch_fill_i32(nj, k, 0, s));
+  HIPCHK(launch_fill_i32(xplan.prev, n, -1, s));
+  HIPCHK(launch_fill_i32((int32_t*)xplan.slots, (int64_t)k * kXD * d * 2, 0, s));
+  if (use_cache) {
+    HIPCHK(launch_fill_i32(pslot, n, -1, s));
+    HIPCHK(launch_fill_i32((int32_t*)rcnt, 4, 0, s));
+  }
+
+  CopyLane cl;
+  HIPCHK(cl.init());
+  for (hipEvent_t e : cl.done) HIPCHK(hipEventRecord(e, s));   // both buffers free
+  // the iteration's moves stay below 2^23 unless n is that large
+  const int split = n >= ((int64_t)1 << 23) ? 1 : 0;
+  const double tol_n = tol * (double)n;
+  std::vector<int64_t> copied((size_t)max_iters, 0);
+  int cur = 0;                                   // the cache region in use
+  int hconv = kNotConverged;
+  int t_last = 0;
+  for (int t = 0; t < max_iters; ++t) {
+    t_last = t;
+    unsigned long long* row = ctr + (size_t)t * ROW_STRIDE;
+    unsigned long long* io_t = io + (size_t)t * KNOR_NIO;
+    if (o.centroid_history)
+      HIPCHK(hipMemcpyAsync(o.centroid_history + (size_t)t * k * d, C_out,
+                            sizeof(double) * (size_t)k * d, hipMemcpyDeviceToDevice, s));
+    const bool full = !mti || t == 0;
+    const bool refresh = use_cache && !full && cache_refresh_at(t, sc.interval);
+    // the transfer stream starts after the previous iteration's bounds
+    HIPCHK(hipEventRecord(cl.start, s));
+    HIPCHK(hipStreamWaitEvent(cl.cs, cl.start, 0));
+    if (refresh) {
+      StreamFetch f;
+      f.Xh = Xd; f.dt = dt; f.n = n; f.d = d; f.labels = labels_out; f.u = u;
+      f.drift = drift; f.s_half = s_half; f.seg_count = segc; f.io = io_t;
+      f.conv = conv; f.iter = t;
+      HIPCHK(launch_stream_fetch(f, cl.cs));
+      HIPCHK(launch_stream_scan(segc, nseg, abase, conv, t, cl.cs));
+    }
+    for (int b = 0; b < nbat; ++b) {
+      const int64_t r0 = (int64_t)b * B;
+      const int64_t nb = n - r0 < B ? n - r0 : B;
+      const int nsb = nseg_of_n(nb);
+      const int buf = b & 1;
+      HIPCHK(hipStreamWaitEvent(cl.cs, cl.done[buf], 0));
+      if (full) {
+        HIPCHK(hipMemcpyAsync(stage[buf], (const char*)X + (size_t)r0 * rb, (size_t)nb * rb,
+                              hipMemcpyHostToDevice, cl.cs));
+        copied[(size_t)t] += nb;
+      } else {
+        StreamFetch f;
+        f.Xh = (const char*)Xd + (size_t)r0 * rb; f.dt = dt; f.n = nb; f.d = d;
+        f.labels = labels_out + r0; f.u = u + r0; f.drift = drift; f.s_half = s_half;
+        if (use_cache) {
+          f.pslot = pslot + r0;
+          f.cache = creg[cur];
+          if (refresh) {
+            f.adm_rows = creg[cur ^ 1];
+            f.adm_pts = cpts[cur ^ 1];
+            f.adm_base = abase + r0 / kSeg;
+            f.adm_cap = sc.cache;
+            f.gid0 = r0;
+          }
+        }
+        f.stage = stage[buf]; f.io = io_t; f.conv = conv; f.iter = t;
+        HIPCHK(launch_stream_fetch(f, cl.cs));
+      }
+      HIPCHK(hipEventRecord(cl.ready[buf], cl.cs));
+      HIPCHK(hipStreamWaitEvent(s, cl.ready[buf], 0));
+      AssignJob job{};
+      job.X = stage[buf]; job.dt = dt; job.n = nb; job.d = d;
+      job.labels = labels_out + r0; job.u = mti ? u + r0 : nullptr;
+      job.flags = flags; job.row = row; job.conv = conv; job.iter = t;
+      job.ucnt = ucnt; job.dirty = dirty; job.recheck_all = o.recheck == 2;
+      if (!full) {
+        HIPCHK(launch_mti_filter(stage[buf], dt, nb, d, C_out, labels_out + r0, u + r0, drift,
+                                 s_half, list, seg_cnt, row - ROW_STRIDE, row, conv, t, 0, s));
+        job.list = list;
+        job.seg_cnt = seg_cnt;
+        job.nseg = nsb;
+      }
+      HIPCHK(launch_assign(ops, job, s));
+      HIPCHK(launch_recheck(ops, job, s));
+      HIPCHK(launch_exact_enter(xplan, nj, stage[buf], dt, nb, full ? nullptr : list,
+                                full ? nullptr : seg_cnt, full ? 0 : nsb, labels_out + r0,
+                                xplan.prev + r0, dirty, row, conv, t, split, s));
+      HIPCHK(hipEventRecord(cl.done[buf], s));
+    }
+    IterCtl ctl;
+    ctl.row = row; ctl.conv = conv; ctl.iter = t; ctl.tol_n = tol_n;
+    ctl.segmented = full ? 0 : 1; ctl.n = n;
+    HIPCHK(launch_exact_finalize(xplan, nj, C_out, C_out, nullptr, &ops, mti ? drift : nullptr,
+                                 dirty, ctl, s));
+    if (refresh) {
+      HIPCHK(launch_stream_remap(pslot, cpts[cur], rcnt + cur, cpts[cur ^ 1], abase + nseg,
+                                 sc.cache, rcnt + (cur ^ 1), conv, t, s));
+      cur ^= 1;
+    }
+    if (mti) HIPCHK(launch_cc_bounds(ops, s_half, nullptr, conv, t, s));
+    if (o.label_history)
+      HIPCHK(launch_copy_i32(labels_out, o.label_history + (size_t)t * n, n, conv, t, s));
+    HIPCHK(hipMemcpyAsync(&hconv, conv, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (hconv != kNotConverged) break;
+  }
+
+  // final objective: one more pass over the rows
+  double hobj = 0.0;
+  if (need_obj) {
+    HIPCHK(hipEventRecord(cl.start, s));
+    HIPCHK(hipStreamWaitEvent(cl.cs, cl.start, 0));
+    for (int b = 0; b < nbat; ++b) {
+      const int64_t r0 = (int64_t)b * B;
+      const int64_t nb = n - r0 < B ? n - r0 : B;
+      const int buf = b & 1;
+      HIPCHK(hipStreamWaitEvent(cl.cs, cl.done[buf], 0));
+      HIPCHK(hipMemcpyAsync(stage[buf], (const char*)X + (size_t)r0 * rb, (size_t)nb * rb,
+                            hipMemcpyHostToDevice, cl.cs));
+      HIPCHK(hipEventRecord(cl.ready[buf], cl.cs));
+      HIPCHK(hipStreamWaitEvent(s, cl.ready[buf], 0));
+      HIPCHK(launch_exact_dist2(stage[buf], dt, nb, d, C_out, labels_out + r0, dist2 + r0, s));
+      HIPCHK(hipEventRecord(cl.done[buf], s));
+    }
+    copied[(size_t)t_last] += n;
+    HIPCHK(launch_canonical_sum(dist2, n, sumtmp, objective, s));
+    HIPCHK(hipMemcpyAsync(&hobj, objective, sizeof(double), hipMemcpyDeviceToHost, s));
+  }
+  std::vector<unsigned long long> hc((size_t)ROW_STRIDE * max_iters);
+  std::vector<unsigned long long> hio((size_t)KNOR_NIO * max_iters);
+  HIPCHK(hipMemcpyAsync(&hconv, conv, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(hc.data(), ctr, ctr_bytes, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(hio.data(), io, io_bytes, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  const int converged = hconv != kNotConverged;
+  const int hiters = converged ? hconv + 1 : max_iters;
+  if (sc.io_out)
+    for (int i = 0; i < hiters; ++i) {
+      int64_t* dst = sc.io_out + (size_t)i * KNOR_NIO;
+      const unsigned long long* r = &hio[(size_t)i * KNOR_NIO];
+      dst[KNOR_IO_COPIED] = copied[(size_t)i];
+      dst[KNOR_IO_GATHERED] = (int64_t)r[1];
+      dst[KNOR_IO_CACHED] = (int64_t)r[2];
+      dst[KNOR_IO_ADMITTED] = (int64_t)r[3];
+    }
+  std::vector<char> cand_used((size_t)max_iters, 0);
+  std::vector<int64_t> queried((size_t)max_iters, 0);
+  report_counters(hc, hiters, n, k, mti, cand_used, queried, o.iter_counters, st);
+  if (st) {
+    st->converged = converged;
+    st->objective = hobj;
+    st->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  }
+  return KNOR_OK;
+}
+
+knor_status knor_fit_streamed(const void* X, knor_dtype dt, int64_t n, int32_t d, int32_t k,
+                              knor_init init, const double* C_init, int32_t max_iters,
+                              double tol, const knor_opts* opts, const knor_stream_opts* sopts,
+                              double* C_out, int32_t* labels_out, knor_stats* st) {
+  Opts o;
+  if (knor_status r = read_opts(opts, &o)) return r;
+  if (!X || !C_out || !labels_out || (dt != KNOR_F32 && dt != KNOR_BF16))
+    return KNOR_ERR_INVALID_ARG;
+  if (n < 1 || n >= (int64_t)1 << 31 || d < 1 || d > kMaxD || k < 1 || k > kMaxK ||
+      (int64_t)k > n || max_iters < 1 || !(tol >= 0.0 && tol < 1.0))
+    return KNOR_ERR_INVALID_ARG;
+  if (init == KNOR_INIT_GIVEN) {
+    if (!C_init) return KNOR_ERR_INVALID_ARG;
+  } else if (init != KNOR_INIT_FORGY && init != KNOR_INIT_SHUFFLE_FIRSTK &&
+             init != KNOR_INIT_KMEANSPP) {
+    return KNOR_ERR_INVALID_ARG;
+  }
+  StreamCfg sc;
+  if (sopts && sopts->struct_size != 0) {
+    if (sopts->struct_size != sizeof(knor_stream_opts)) return KNOR_ERR_INVALID_ARG;
+    if (sopts->batch_rows < 0 || sopts->cache_rows < 0 || sopts->cache_interval < 0 ||
+        sopts->skip_objective < 0 || sopts->skip_objective > 1)
+      return KNOR_ERR_INVALID_ARG;
+    sc.batch = sopts->batch_rows;
+    sc.cache = sopts->cache_rows;
+    if (sopts->cache_interval > 0) sc.interval = sopts->cache_interval;
+    sc.skip_objective = sopts->skip_objective;
+    sc.io_out = sopts->io_counters;
+  }
+  const int64_t nr = (n + kSeg - 1) / kSeg * kSeg;
+  if (sc.batch == 0) sc.batch = (int64_t)1 << 22;
+  sc.batch = (sc.batch + kSeg - 1) / kSeg * kSeg;
+  if (sc.batch > nr) sc.batch = nr;
+  if (sc.cache > n) sc.cache = n;
+  if (o.update != 1 || o.learned || o.clause2 == 2 || o.autotune ||
+      init == KNOR_INIT_KMEANSPP || o.profile_ms || o.profile_launches)
+    return KNOR_ERR_UNSUPPORTED;
+  const void* Xd = nullptr;
+  if (knor_status r = host_rows_on_device(X, &Xd)) return r;
+  return fit_streamed_impl(X, Xd, dt, n, d, k, init, C_init, max_iters, tol, o, sc, C_out,
+                           labels_out, st);
 }
 
 knor_status knor_assign(const void* X, knor_dtype dt, int64_t n, int32_t d,

@@ -123,6 +123,16 @@ __device__ __forceinline__ float f32_up(double v) {
   return f;
 }
 
+// MTI Clause 1 with the drift-updated bound (Section "Minimal Triangle
+// Inequality (MTI) Pruning"): *ub = u + f(c_a), rounded up; true when
+// ub (1 + eta) < s(c_a), i.e. the point keeps its centroid without any
+// distance.  The filter and the streamed fetch both decide through this.
+__device__ __forceinline__ bool clause1_keeps(float u, float drift, float s_half, float* ub) {
+  const double b = f32_up(((double)u + (double)drift) * (1.0 + 8.881784197001252e-16));
+  *ub = (float)b;
+  return b * (1.0 + kEta) < (double)s_half;
+}
+
 // Largest float <= v (v >= 0).
 __device__ __forceinline__ float f32_down(double v) {
   float f = (float)v;
@@ -443,6 +453,20 @@ struct ExactPlan {
   int delta_max;               // most changed labels moved one by one
 };
 size_t exact_workspace_bytes(int64_t n, int k, int d);
+// The pieces of an exact update, for callers that see an iteration's points
+// in several passes: enter moves the changed points of one pass (labels and
+// prev are that pass's views; rows of X are the pass's rows) into their new
+// clusters' digits (and out of the old ones), never choosing the full pass;
+// split = 1 whenever the iteration as a whole may move 2^23 or more points.
+// finalize divides every dirty cluster's digits once all passes are in.
+hipError_t launch_exact_enter(const ExactPlan& xp, int* nj, const void* X, knor_dtype dt,
+                              int64_t n, const int* list, const int* seg_cnt, int nseg,
+                              const int32_t* labels, int32_t* prev, const int* dirty,
+                              const unsigned long long* row, const int* conv, int iter,
+                              int split, hipStream_t s);
+hipError_t launch_exact_finalize(const ExactPlan& xp, const int* nj, const double* C_prev,
+                                 double* C_out, int64_t* counts_out, CentroidOps* ops,
+                                 float* drift, int* dirty, const IterCtl& ctl, hipStream_t s);
 void exact_plan_init(ExactPlan* p, int64_t n, int k, int d, void* ws);
 hipError_t launch_update_exact(const UpdatePlan& p, const ExactPlan& xp, const void* X,
                                knor_dtype dt, const int32_t* labels, const double* C_prev,
@@ -568,5 +592,37 @@ inline int pad_dim(int d) {
 }
 
 inline int nseg_of_n(int64_t n) { return (int)((n + kSeg - 1) / kSeg); }
+
+// One fetch pass of a streamed fit over a batch of rows (stream.hip).  All
+// per-point arrays are views of the batch (point 0 = the batch's first row).
+struct StreamFetch {
+  const void* Xh = nullptr;            // the batch's rows in host memory (device-visible)
+  knor_dtype dt = KNOR_F32;
+  int64_t n = 0;                       // points in the batch
+  int d = 0;
+  const int32_t* labels = nullptr;
+  const float* u = nullptr;
+  const float* drift = nullptr;        // per cluster
+  const float* s_half = nullptr;       // per cluster
+  int all = 0;                         // 1: every point is a candidate
+  const int* pslot = nullptr;          // point -> cache slot (-1: not cached), or null
+  const void* cache = nullptr;         // rows of the current cache region
+  void* stage = nullptr;               // out: row of point p at p
+  void* adm_rows = nullptr;            // refresh: rows of the new cache region, or null
+  int* adm_pts = nullptr;              // refresh: global point index of each new slot
+  const int64_t* adm_base = nullptr;   // refresh: first new slot of each segment
+  int64_t adm_cap = 0;                 // cache capacity in rows
+  int64_t gid0 = 0;                    // global index of the batch's point 0
+  int* seg_count = nullptr;            // count mode: candidates per segment (no copies)
+  unsigned long long* io = nullptr;    // this iteration's I/O counters
+  const int* conv = nullptr;
+  int iter = 0;
+};
+hipError_t launch_stream_fetch(const StreamFetch& f, hipStream_t s);
+hipError_t launch_stream_scan(const int* cnt, int nseg, int64_t* base, const int* conv,
+                              int iter, hipStream_t s);
+hipError_t launch_stream_remap(int* pslot, const int* old_pts, const int64_t* old_cnt,
+                               const int* new_pts, const int64_t* total, int64_t cap,
+                               int64_t* new_cnt, const int* conv, int iter, hipStream_t s);
 
 }  // namespace knor

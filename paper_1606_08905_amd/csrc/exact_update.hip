@@ -137,6 +137,10 @@ struct DeltaSrc {
 // d <= 32 (one per half wave), one dimension per lane, with order-free
 // 64-bit atomic adds to the digits of the new (+x) and old (-x) cluster.
 constexpr int kDeltaPer = kSeg / 256;
+// exact_delta's choice of mode: full pass at t = 0 and after many changes;
+// full pass at t = 0 only; never (the points of a streamed pass enter their
+// clusters one by one, starting from digits the caller cleared)
+constexpr int kDeltaAuto = 0, kDeltaOnly = 1, kDeltaStream = 2;
 
 template <typename T>
 __global__ __launch_bounds__(256) void exact_delta(
@@ -144,17 +148,20 @@ __global__ __launch_bounds__(256) void exact_delta(
     int32_t* __restrict__ prev, int k, int d, unsigned long long* __restrict__ slots,
     int* __restrict__ nj, const int* __restrict__ dirty,
     const unsigned long long* __restrict__ row, int* __restrict__ gate, int delta_max,
-    int delta_only, const int* __restrict__ conv, int iter) {
+    int mode, int force_split, const int* __restrict__ conv, int iter) {
   const int cv = *conv;
   const int lane = threadIdx.x & 63;
   // this iteration's changed labels, from the spread counter slots
   unsigned long long c =
       lane < kChgSlots ? row[(SLOT_CHANGED * kChgSlots + lane) * kSlotStride] : 0ull;
   for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o);
-  const bool full = iter == 0 || (!delta_only && c > (unsigned long long)delta_max);
+  const bool full = mode != kDeltaStream &&
+                    (iter == 0 || (mode == kDeltaAuto && c > (unsigned long long)delta_max));
   // with the full pass not launched, many moves are possible: a digit then
-  // takes two pieces below 2^32 per value instead of one add below 2^39
-  const bool split = c >= (1ull << 23);
+  // takes two pieces below 2^32 per value instead of one add below 2^39.
+  // A streamed pass sees the iteration in pieces, so its caller decides
+  // from a bound on the iteration's moves.
+  const bool split = mode == kDeltaStream ? force_split != 0 : c >= (1ull << 23);
   if (blockIdx.x == 0 && threadIdx.x == 0)
     *gate = cv < iter ? cv : (full ? kNotConverged : -1);
   if (cv < iter) return;
@@ -570,15 +577,15 @@ hipError_t launch_update_exact(const UpdatePlan& p, const ExactPlan& xp, const v
     int64_t blocks = ctl->list ? ctl->nseg : (p.n + kSeg - 1) / kSeg;
     if (blocks > (1 << 20)) blocks = 1 << 20;
     if (blocks < 1) blocks = 1;
-    const int donly = ctl->delta_only && iter > 0 ? 1 : 0;
+    const int mode = ctl->delta_only && iter > 0 ? kDeltaOnly : kDeltaAuto;
     if (dt == KNOR_F32)
       hipLaunchKernelGGL(exact_delta<float>, dim3((unsigned)blocks), dim3(256), 0, s,
                          (const float*)X, src, labels, xp.prev, k, d, xp.slots, p.nj, dirty,
-                         ctl->row, xp.gate, xp.delta_max, donly, conv, iter);
+                         ctl->row, xp.gate, xp.delta_max, mode, 0, conv, iter);
     else
       hipLaunchKernelGGL(exact_delta<uint16_t>, dim3((unsigned)blocks), dim3(256), 0, s,
                          (const uint16_t*)X, src, labels, xp.prev, k, d, xp.slots, p.nj,
-                         dirty, ctl->row, xp.gate, xp.delta_max, donly, conv, iter);
+                         dirty, ctl->row, xp.gate, xp.delta_max, mode, 0, conv, iter);
     gate = xp.gate;
   }
   // the full pass: gated on the device, or not launched at all once the
@@ -605,12 +612,41 @@ hipError_t launch_update_exact(const UpdatePlan& p, const ExactPlan& xp, const v
                        s, (const uint16_t*)X, d, p.perm, p.nj, p.off, p.leaf_off, k, dirty,
                        xp.slots, gate, iter, vec, (int)run);
   if (prof) { prof->end(); prof->begin(KNOR_PROF_TREE); }
-  hipLaunchKernelGGL(exact_finalize, dim3(k), dim3(256), 0, s, xp.slots, p.nj, k, d, C_prev,
-                     C_out, counts_out, ops ? ops->Cm2 : nullptr, ops ? ops->cn : nullptr,
-                     ops ? ops->CT : nullptr, ops ? ops->dp : 0, ops ? ops->Chi : nullptr,
-                     ops ? ops->Clo : nullptr, ops ? ops->dpb : 0, drift, dirty, *ctl, conv,
-                     iter);
+  hipError_t e = launch_exact_finalize(xp, p.nj, C_prev, C_out, counts_out, ops, drift, dirty,
+                                       *ctl, s);
   if (prof) prof->end();
+  return e;
+}
+
+hipError_t launch_exact_finalize(const ExactPlan& xp, const int* nj, const double* C_prev,
+                                 double* C_out, int64_t* counts_out, CentroidOps* ops,
+                                 float* drift, int* dirty, const IterCtl& ctl, hipStream_t s) {
+  hipLaunchKernelGGL(exact_finalize, dim3(xp.k), dim3(256), 0, s, xp.slots, nj, xp.k, xp.d,
+                     C_prev, C_out, counts_out, ops ? ops->Cm2 : nullptr,
+                     ops ? ops->cn : nullptr, ops ? ops->CT : nullptr, ops ? ops->dp : 0,
+                     ops ? ops->Chi : nullptr, ops ? ops->Clo : nullptr, ops ? ops->dpb : 0,
+                     drift, dirty, ctl, ctl.conv, ctl.iter);
+  return hipGetLastError();
+}
+
+hipError_t launch_exact_enter(const ExactPlan& xp, int* nj, const void* X, knor_dtype dt,
+                              int64_t n, const int* list, const int* seg_cnt, int nseg,
+                              const int32_t* labels, int32_t* prev, const int* dirty,
+                              const unsigned long long* row, const int* conv, int iter,
+                              int split, hipStream_t s) {
+  if (dt != KNOR_F32 && dt != KNOR_BF16) return hipErrorInvalidValue;
+  DeltaSrc src{n, list, seg_cnt, nseg};
+  int64_t blocks = list ? nseg : (n + kSeg - 1) / kSeg;
+  if (blocks > (1 << 20)) blocks = 1 << 20;
+  if (blocks < 1) blocks = 1;
+  if (dt == KNOR_F32)
+    hipLaunchKernelGGL(exact_delta<float>, dim3((unsigned)blocks), dim3(256), 0, s,
+                       (const float*)X, src, labels, prev, xp.k, xp.d, xp.slots, nj, dirty, row,
+                       xp.gate, xp.delta_max, kDeltaStream, split, conv, iter);
+  else
+    hipLaunchKernelGGL(exact_delta<uint16_t>, dim3((unsigned)blocks), dim3(256), 0, s,
+                       (const uint16_t*)X, src, labels, prev, xp.k, xp.d, xp.slots, nj, dirty,
+                       row, xp.gate, xp.delta_max, kDeltaStream, split, conv, iter);
   return hipGetLastError();
 }
 

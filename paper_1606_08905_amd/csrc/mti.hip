@@ -183,8 +183,8 @@ __global__ __launch_bounds__(kFilterThreads) void mti_filter_kernel(
     for (int e = 0; e < 4; ++e) {
       cand[e] = false;
       if (pb + e < n) {
-        const double ub = f32_up(((double)uu[e] + (double)dr[e]) * (1.0 + 8.881784197001252e-16));
-        if (ub * (1.0 + kEta) < (double)sh[e]) uu[e] = (float)ub;
+        float ub;
+        if (clause1_keeps(uu[e], dr[e], sh[e], &ub)) uu[e] = ub;
         else cand[e] = true;
       }
     }

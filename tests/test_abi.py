@@ -36,7 +36,7 @@ def test_exports_every_declared_symbol(L):
 def test_status_strings(L):
     for code in range(6):
         assert L.knor_status_string(code)
-    assert L.knor_version() >= 300
+    assert L.knor_version() >= 400
 
 
 FAKE = ctypes.c_void_p(0x1000)   # never dereferenced: validation fails first
@@ -243,3 +243,66 @@ def test_clause2_option_validated(L):
     assert _fit(L, k=9000, n=20000, opts=ctypes.byref(o)) == knor.KNOR_ERR_UNSUPPORTED
     arr = (knor.Problem * 1)(_problem(dt=2))
     assert L.knor_fit_batched(arr, 1, ctypes.byref(o), None) == knor.KNOR_ERR_UNSUPPORTED
+
+
+def _fit_streamed(L, opts=None, sopts=None, **kw):
+    a = dict(X=FAKE, dt=1, n=100, d=8, k=4, init=0, C=FAKE, it=10, tol=0.0,
+             Cout=FAKE, lab=FAKE, st=None)
+    a.update(kw)
+    return L.knor_fit_streamed(a["X"], a["dt"], a["n"], a["d"], a["k"], a["init"], a["C"],
+                               a["it"], a["tol"], opts, sopts, a["Cout"], a["lab"], a["st"])
+
+
+def _exact_opts():
+    o = knor.Opts()
+    o.struct_size = ctypes.sizeof(knor.Opts)
+    o.prune = 1
+    o.recheck = 1
+    o.check_numeric = 1
+    o.update = 1
+    return o
+
+
+@pytest.mark.parametrize("kw", [
+    dict(X=None), dict(dt=0), dict(dt=9), dict(n=0), dict(d=0), dict(d=257), dict(k=0),
+    dict(k=101), dict(it=0), dict(tol=1.0), dict(init=0, C=None), dict(init=4),
+    dict(Cout=None), dict(lab=None), dict(n=1 << 31),
+])
+def test_fit_streamed_rejects_invalid(L, kw):
+    o = _exact_opts()
+    assert _fit_streamed(L, opts=ctypes.byref(o), **kw) == knor.KNOR_ERR_INVALID_ARG
+
+
+def test_fit_streamed_rejects_bad_stream_opts(L):
+    o = _exact_opts()
+    for field, v in [("struct_size", 5), ("batch_rows", -1), ("cache_rows", -2),
+                     ("cache_interval", -1), ("skip_objective", 2)]:
+        so = knor.StreamOpts()
+        so.struct_size = ctypes.sizeof(knor.StreamOpts)
+        setattr(so, field, v)
+        assert _fit_streamed(L, opts=ctypes.byref(o), sopts=ctypes.byref(so)) == \
+            knor.KNOR_ERR_INVALID_ARG, field
+
+
+def test_fit_streamed_unsupported_options(L):
+    # the canonical update (the default), the learned proposal, forced
+    # Clause 2, autotuning and k-means++ are not offered for host rows
+    assert _fit_streamed(L) == knor.KNOR_ERR_UNSUPPORTED
+    for field, v in [("update", 0), ("learned", 1), ("clause2", 2), ("autotune", 1)]:
+        o = _exact_opts()
+        setattr(o, field, v)
+        assert _fit_streamed(L, opts=ctypes.byref(o)) == knor.KNOR_ERR_UNSUPPORTED, field
+    o = _exact_opts()
+    assert _fit_streamed(L, opts=ctypes.byref(o), init=3, C=None) == knor.KNOR_ERR_UNSUPPORTED
+
+
+def test_fit_streamed_needs_pinned_host_rows(L):
+    # a pointer that is not page-locked host memory is refused
+    o = _exact_opts()
+    assert _fit_streamed(L, opts=ctypes.byref(o)) == knor.KNOR_ERR_INVALID_ARG
+
+
+def test_binding_streamed_refuses_unpinned():
+    import torch
+    with pytest.raises(ValueError):
+        knor.fit_streamed(torch.zeros((10, 4)), 2, C0=torch.zeros((2, 4), dtype=torch.float64))
