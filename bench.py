@@ -98,6 +98,15 @@ def parse():
                     help="skip the comparison fits (profiling runs)")
     ap.add_argument("--exact-rows", type=int, default=20000,
                     help="rows whose labels are compared with the oracle per iteration")
+    ap.add_argument("--streamed", action="store_true",
+                    help="the points stay in pinned host memory (knor_fit_streamed, "
+                         "exact update); configs 2, 3 and 5")
+    ap.add_argument("--batch-rows", type=int, default=0,
+                    help="streamed: rows per batch (0 = library default, 2^22)")
+    ap.add_argument("--cache-rows", type=int, default=1 << 22,
+                    help="streamed: row cache capacity in rows")
+    ap.add_argument("--cache-interval", type=int, default=5,
+                    help="streamed: first refresh iteration of the row cache")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="also run one device-to-device copy of this many MiB "
                          "before the timed region (a known-size kernel for "
@@ -450,6 +459,108 @@ def single_config(a, knor, oracle, workloads):
     return out
 
 
+# PCIe 5.0 x16, one direction (the MI355X host link)
+PEAK_LINK = 64.0e9
+
+
+def pinned_points(w):
+    import numpy as np
+    import torch
+    if w.dtype == "bf16":
+        t = torch.from_numpy(w.X.view(np.int16)).view(torch.bfloat16)
+    else:
+        t = torch.from_numpy(w.X)
+    return t.pin_memory()
+
+
+def dma_rate(Xh):
+    """Host-to-device copy rate of one whole pinned array (torch's copy, HIP
+    events on its stream): the practical ceiling of the whole-batch copies."""
+    import torch
+    dst = torch.empty(Xh.shape, dtype=Xh.dtype, device="cuda")
+    dst.copy_(Xh, non_blocking=True)
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    dst.copy_(Xh, non_blocking=True)
+    b.record()
+    torch.cuda.synchronize()
+    nbytes = Xh.numel() * Xh.element_size()
+    del dst
+    return nbytes / (a.elapsed_time(b) / 1e3)
+
+
+def streamed_config(a, knor, oracle, workloads):
+    """The same workload with the points in pinned host memory: a fit reads
+    whole batches in its full passes and, afterwards, only the rows of the
+    points that fail MTI Clause 1 (row cache first, then the host link)."""
+    import numpy as np
+    import torch
+    cfg = a.config
+    if cfg not in (2, 3, 5):
+        raise SystemExit("--streamed takes --config 2, 3 or 5")
+    t_gen = time.perf_counter()
+    w = workloads.config(cfg)
+    log(f"data n={w.n} d={w.d} k={w.k} {w.dtype} generated in "
+        f"{time.perf_counter() - t_gen:.1f}s")
+    Xh = pinned_points(w)
+    C0 = torch.from_numpy(w.C0).cuda()
+    sx = {"f32": 4, "bf16": 2}[w.dtype]
+    rb = w.d * sx
+
+    def fit(**kw):
+        return knor.fit_streamed(Xh, w.k, C0=C0, max_iters=w.max_iters, tol=w.tol,
+                                 counters=True, batch_rows=a.batch_rows,
+                                 cache_rows=a.cache_rows, cache_interval=a.cache_interval,
+                                 **kw)
+
+    outs, dt = timed(fit, a.steps, a.warmup)
+    C, lab, st = outs[-1]
+    iters = st["iters"]
+    io = st["io"]
+    rows_moved = int(io[:, 0].sum() + io[:, 1].sum())
+    link = {
+        "rows_copied_per_fit": int(io[:, 0].sum()),
+        "rows_gathered_per_fit": int(io[:, 1].sum()),
+        "rows_cached_per_fit": int(io[:, 2].sum()),
+        "rows_admitted_per_fit": int(io[:, 3].sum()),
+        "bytes_per_fit": rows_moved * rb,
+        "bytes_if_every_row_every_iteration": (iters + 1) * w.n * rb,
+        "achieved_GBps": round(rows_moved * rb / dt / 1e9, 3),
+        "dma_GBps": round(dma_rate(Xh) / 1e9, 3),
+        "peak_GBps": PEAK_LINK / 1e9,
+        "io_per_iteration": io.tolist(),
+    }
+    out = {
+        "metric": METRIC, "value": round(iters / dt, 3), "unit": "iters/s",
+        "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
+        "ms_per_step": round(1e3 * dt, 3), "higher_is_better": True, "scaling": "strong",
+        "vs_baseline": None, "dtype": w.dtype, "data": "synthetic",
+        "config": {"workload": WORKLOAD_NAMES[cfg] + "; streamed: points in pinned host "
+                   f"memory, batches of {a.batch_rows or 1 << 22} rows, row cache "
+                   f"{a.cache_rows} rows, first refresh at iteration {a.cache_interval}, "
+                   "update=exact", "n": w.n, "d": w.d, "k": w.k, "iters_per_fit": iters},
+        "link": link,
+    }
+    # the same fit with the points resident in HBM
+    if not a.no_baselines:
+        X = device_points(w)
+        (Cm, lm, sm), vm = rate(lambda: knor.fit(X, w.k, C0=C0, max_iters=w.max_iters,
+                                                 tol=w.tol, update="exact", prune=True),
+                                max(1, a.steps - 1), 1)
+        out["in_hbm"] = {"value": round(vm, 3), "unit": "iters/s",
+                         "ratio": round((iters / dt) / vm, 3)}
+        out["same_results_as_in_hbm"] = bool((C == Cm).all() and (lab == lm).all()
+                                             and sm["iters"] == iters)
+        del X
+    if not a.no_exact:
+        out.update(check_exact(oracle, workloads, w, fit, a.exact_rows, "exact"))
+    if not a.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_sample(oracle, workloads, w, w.C0,
+                                         {2: 1.0, 3: 0.1, 5: 0.3}[cfg])
+    return out
+
+
 def batched_config(a, knor, oracle, workloads):
     import numpy as np
     import torch
@@ -535,7 +646,9 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    if a.config == 4:
+    if a.streamed:
+        out = streamed_config(a, knor, oracle, workloads)
+    elif a.config == 4:
         out = batched_config(a, knor, oracle, workloads)
     else:
         out = single_config(a, knor, oracle, workloads)

@@ -290,6 +290,12 @@ typedef struct {
  *   sopts      may be NULL (defaults).
  *   C_init, C_out, labels_out, st: as for knor_fit (C_init, C_out and
  *              labels_out in DEVICE memory).
+ * With opts->check_numeric the initial centroids are checked before the
+ * first iteration and the rows of X as they arrive in iteration 0 (there is
+ * no pass over the link for the check alone): a NaN or Inf then gives
+ * KNOR_ERR_NUMERIC after that iteration, with C_out holding the initial
+ * centroids and labels_out those of the batches before the first bad one;
+ * no kernel reads a batch from the first bad one on.
  * Uses one extra stream (default priority) for the transfers.  Blocks
  * until the fit is complete. */
 knor_status knor_fit_streamed(const void* X, knor_dtype dt, int64_t n, int32_t d,

@@ -22,33 +22,77 @@ namespace knor {
 // small kernels
 // ---------------------------------------------------------------------------
 
+// Non-finite test on the bit pattern (exponent all ones).
+template <typename T>
+__device__ __forceinline__ bool nonfinite_bits(T v);
+template <>
+__device__ __forceinline__ bool nonfinite_bits<double>(double v) {
+  return ((unsigned long long)__double_as_longlong(v) & 0x7ff0000000000000ull) ==
+         0x7ff0000000000000ull;
+}
+template <>
+__device__ __forceinline__ bool nonfinite_bits<float>(float v) {
+  return (__float_as_uint(v) & 0x7f800000u) == 0x7f800000u;
+}
+template <>
+__device__ __forceinline__ bool nonfinite_bits<uint16_t>(uint16_t v) {
+  return (v & 0x7f80u) == 0x7f80u;
+}
+
+// bad |= some element of p[0, count) is NaN or Inf; with kill, a hit also
+// sets *kill = -1 (the convergence word: every later kernel of the fit then
+// returns at once).  16-byte loads, four in flight per thread, when p is
+// aligned.
 template <typename T>
 __global__ __launch_bounds__(256) void check_finite_kernel(const T* __restrict__ p,
                                                            int64_t count,
-                                                           int* __restrict__ bad) {
+                                                           int* __restrict__ bad,
+                                                           int* __restrict__ kill) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   bool b = false;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride)
-    b |= !isfinite(to_f64<T>(p[i]));
-  if (__ballot(b) && lane_id() == 0) atomicOr(bad, 1);
+  int64_t done = 0;
+  if (((uintptr_t)p & 15) == 0) {
+    constexpr int E = 16 / (int)sizeof(T);
+    const int64_t nv = count / E;
+    const uint4* q = reinterpret_cast<const uint4*>(p);
+    for (int64_t i = tid; i < nv; i += 4 * stride) {
+      uint4 w[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        w[r] = i + r * stride < nv ? q[i + r * stride] : make_uint4(0u, 0u, 0u, 0u);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const T* e = reinterpret_cast<const T*>(&w[r]);
+#pragma unroll
+        for (int j = 0; j < E; ++j) b |= nonfinite_bits<T>(e[j]);
+      }
+    }
+    done = nv * E;
+  }
+  for (int64_t i = done + tid; i < count; i += stride) b |= nonfinite_bits<T>(p[i]);
+  if (__ballot(b) && lane_id() == 0) {
+    atomicOr(bad, 1);
+    if (kill) atomicExch(kill, -1);
+  }
 }
 
 hipError_t launch_check_finite(const void* p, knor_dtype dt, int64_t count,
-                               int* bad, hipStream_t s) {
-  int64_t blocks = (count + 255) / 256;
+                               int* bad, hipStream_t s, int* kill) {
+  int64_t blocks = (count + 1023) / 1024;
   int grid = (int)(blocks < 1024 ? (blocks < 1 ? 1 : blocks) : 1024);
   switch (dt) {
     case KNOR_F64:
       hipLaunchKernelGGL(check_finite_kernel<double>, dim3(grid), dim3(256), 0,
-                         s, (const double*)p, count, bad);
+                         s, (const double*)p, count, bad, kill);
       break;
     case KNOR_F32:
       hipLaunchKernelGGL(check_finite_kernel<float>, dim3(grid), dim3(256), 0,
-                         s, (const float*)p, count, bad);
+                         s, (const float*)p, count, bad, kill);
       break;
     case KNOR_BF16:
       hipLaunchKernelGGL(check_finite_kernel<uint16_t>, dim3(grid), dim3(256), 0,
-                         s, (const uint16_t*)p, count, bad);
+                         s, (const uint16_t*)p, count, bad, kill);
       break;
   }
   return hipGetLastError();
@@ -1336,17 +1380,6 @@ static knor_status fit_streamed_impl(const void* X, const void* Xd, knor_dtype d
   HIPCHK(hipMemsetAsync(ctr, 0, ctr_bytes, s));
   HIPCHK(hipMemsetAsync(io, 0, io_bytes, s));
 
-  // numeric check before anything is written to the outputs (one read of
-  // X over the host link)
-  if (o.check_numeric) {
-    HIPCHK(launch_check_finite(Xd, dt, n * (int64_t)d, bad, s));
-    if (init == KNOR_INIT_GIVEN)
-      HIPCHK(launch_check_finite(C_init, KNOR_F64, (int64_t)k * d, bad, s));
-    int hbad = 0;
-    HIPCHK(hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
-    if (hbad) return KNOR_ERR_NUMERIC;
-  }
   if (init == KNOR_INIT_GIVEN) {
     if (C_init != C_out)
       HIPCHK(hipMemcpyAsync(C_out, C_init, sizeof(double) * (size_t)k * d,
@@ -1358,6 +1391,15 @@ static knor_status fit_streamed_impl(const void* X, const void* Xd, knor_dtype d
                           hipMemcpyHostToDevice, s));
     HIPCHK(launch_gather_rows(Xd, dt, d, rows_dev, k, C_out, s));   // k rows over the link
     HIPCHK(hipStreamSynchronize(s));   // `rows` leaves scope
+  }
+  // numeric check: the initial centroids now, the rows of X as they arrive
+  // in iteration 0 (no pass over the link of its own)
+  if (o.check_numeric) {
+    HIPCHK(launch_check_finite(C_out, KNOR_F64, (int64_t)k * d, bad, s));
+    int hbad = 0;
+    HIPCHK(hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (hbad) return KNOR_ERR_NUMERIC;
   }
   HIPCHK(launch_prep_centroids(ops, s));
   HIPCHK(launch_fill_i32(labels_out, n, -1, s));
@@ -1430,6 +1472,9 @@ static knor_status fit_streamed_impl(const void* X, const void* Xd, knor_dtype d
       }
       HIPCHK(hipEventRecord(cl.ready[buf], cl.cs));
       HIPCHK(hipStreamWaitEvent(s, cl.ready[buf], 0));
+      // a non-finite value stops every later kernel of the fit
+      if (t == 0 && o.check_numeric)
+        HIPCHK(launch_check_finite(stage[buf], dt, nb * (int64_t)d, bad, s, conv));
       AssignJob job{};
       job.X = stage[buf]; job.dt = dt; job.n = nb; job.d = d;
       job.labels = labels_out + r0; job.u = mti ? u + r0 : nullptr;
@@ -1462,8 +1507,11 @@ static knor_status fit_streamed_impl(const void* X, const void* Xd, knor_dtype d
     if (mti) HIPCHK(launch_cc_bounds(ops, s_half, nullptr, conv, t, s));
     if (o.label_history)
       HIPCHK(launch_copy_i32(labels_out, o.label_history + (size_t)t * n, n, conv, t, s));
+    int hbad = 0;
     HIPCHK(hipMemcpyAsync(&hconv, conv, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
+    if (hbad) return KNOR_ERR_NUMERIC;
     if (hconv != kNotConverged) break;
   }
 

@@ -495,7 +495,7 @@ hipError_t launch_mti_filter(const void* X, knor_dtype dt, int64_t n, int d,
 
 // Misc.
 hipError_t launch_check_finite(const void* p, knor_dtype dt, int64_t count,
-                               int* bad, hipStream_t s);
+                               int* bad, hipStream_t s, int* kill = nullptr);
 hipError_t launch_fill_i32(int32_t* p, int64_t count, int32_t v,
                            hipStream_t s);
 hipError_t launch_copy_i32(const int32_t* src, int32_t* dst, int64_t count,

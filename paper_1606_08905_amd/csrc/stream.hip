@@ -76,14 +76,18 @@ __device__ __forceinline__ int segment_candidates(
   return total;
 }
 
-// One block per segment of the batch.  Count mode (seg_count != null): the
+// Blocks walk the batch's segments (segment blockIdx.x, then every
+// gridDim.x-th): a small grid keeps most compute units free for the compute
+// stream, which works on the previous batch meanwhile, while enough reads
+// stay in flight for the host link.  Count mode (seg_count != null): each
 // segment's candidate count only.  Otherwise every candidate's row goes to
 // stage[p] (p batch-local): from cache[pslot[p]] when pslot[p] >= 0, else
-// from the host rows Xh.  With adm_rows (a refresh iteration), candidate c of
-// the segment also goes to slot adm_base[seg] + c of the new cache region
+// from the host rows Xh.  With adm_rows (a refresh iteration), candidate c
+// of a segment also goes to slot adm_base[seg] + c of the new cache region
 // when that slot is below adm_cap, and the slot records the point's global
-// index.  io (this iteration): [1] rows read from host memory, [2] rows read
-// from the cache, [3] rows admitted.
+// index.  io (this iteration): [1] rows read from host memory, [2] rows
+// read from the cache, [3] rows admitted.
+constexpr int kFetchInFlight = 8;       // 16-byte reads per thread before their stores
 template <typename T>
 __global__ __launch_bounds__(kFetchThreads) void stream_fetch_kernel(
     const T* __restrict__ Xh, int64_t n, int d, const int32_t* __restrict__ labels,
@@ -98,75 +102,84 @@ __global__ __launch_bounds__(kFetchThreads) void stream_fetch_kernel(
   __shared__ int wcnt[kFetchThreads / 64];
   __shared__ int nhit;
   if (*conv < iter) return;                     // uniform
-  const int seg = blockIdx.x;
-  const int64_t p0 = (int64_t)seg * kSeg;
-  if (threadIdx.x == 0) nhit = 0;
-  const int na = segment_candidates(n, p0, labels, u, drift, s_half, all, cand, wcnt);
-  if (seg_count) {
-    if (threadIdx.x == 0) seg_count[seg] = na;
-    return;
-  }
-  int hits = 0;
-  for (int c = threadIdx.x; c < na; c += kFetchThreads) {
-    const int sl = pslot ? pslot[p0 + cand[c]] : -1;
-    src[c] = sl;
-    hits += sl >= 0 ? 1 : 0;
-  }
-  if (hits) atomicAdd(&nhit, hits);             // LDS
-  int64_t base = 0, nadm = 0;
-  if (adm_rows) {
-    base = adm_base[seg];
-    nadm = adm_cap - base;
-    nadm = nadm < 0 ? 0 : (nadm > na ? na : nadm);
-  }
-  __syncthreads();
-  if (vec) {
-    // 16-byte pieces, four in flight per thread before their stores
-    const int nv = d * (int)sizeof(T) / 16;
-    const int64_t tot = (int64_t)na * nv;
-    for (int64_t e0 = threadIdx.x; e0 < tot; e0 += 4 * kFetchThreads) {
-      uint4 w[4];
-      int cc[4], vv[4];
+  const int nseg = (int)((n + kSeg - 1) / kSeg);
+  unsigned long long miss_tot = 0, hit_tot = 0, adm_tot = 0;   // thread 0's sums
+  for (int seg = blockIdx.x; seg < nseg; seg += gridDim.x) {
+    const int64_t p0 = (int64_t)seg * kSeg;
+    __syncthreads();                            // the previous segment's LDS is free
+    if (threadIdx.x == 0) nhit = 0;
+    const int na = segment_candidates(n, p0, labels, u, drift, s_half, all, cand, wcnt);
+    if (seg_count) {
+      if (threadIdx.x == 0) seg_count[seg] = na;
+      continue;
+    }
+    int hits = 0;
+    for (int c = threadIdx.x; c < na; c += kFetchThreads) {
+      const int sl = pslot ? pslot[p0 + cand[c]] : -1;
+      src[c] = sl;
+      hits += sl >= 0 ? 1 : 0;
+    }
+    if (hits) atomicAdd(&nhit, hits);           // LDS
+    int64_t base = 0, nadm = 0;
+    if (adm_rows) {
+      base = adm_base[seg];
+      nadm = adm_cap - base;
+      nadm = nadm < 0 ? 0 : (nadm > na ? na : nadm);
+    }
+    __syncthreads();
+    if (vec) {
+      // 16-byte pieces, kFetchInFlight in flight per thread before their stores
+      const int nv = d * (int)sizeof(T) / 16;
+      const int tot = na * nv;
+      for (int e0 = threadIdx.x; e0 < tot; e0 += kFetchInFlight * kFetchThreads) {
+        uint4 w[kFetchInFlight];
+        int cc[kFetchInFlight], vv[kFetchInFlight];
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int64_t e = e0 + (int64_t)r * kFetchThreads;
-        cc[r] = e < tot ? (int)(e / nv) : -1;
-        vv[r] = cc[r] >= 0 ? (int)(e - (int64_t)cc[r] * nv) : 0;
-        if (cc[r] >= 0) {
-          const int sl = src[cc[r]];
-          const uint4* from =
-              sl >= 0 ? reinterpret_cast<const uint4*>(cache + (size_t)sl * d)
-                      : reinterpret_cast<const uint4*>(Xh + (size_t)(p0 + cand[cc[r]]) * d);
-          w[r] = from[vv[r]];
+        for (int r = 0; r < kFetchInFlight; ++r) {
+          const int e = e0 + r * kFetchThreads;
+          cc[r] = e < tot ? e / nv : -1;
+          vv[r] = cc[r] >= 0 ? e - cc[r] * nv : 0;
+          if (cc[r] >= 0) {
+            const int sl = src[cc[r]];
+            const uint4* from =
+                sl >= 0 ? reinterpret_cast<const uint4*>(cache + (size_t)sl * d)
+                        : reinterpret_cast<const uint4*>(Xh + (size_t)(p0 + cand[cc[r]]) * d);
+            w[r] = from[vv[r]];
+          }
+        }
+#pragma unroll
+        for (int r = 0; r < kFetchInFlight; ++r) {
+          if (cc[r] < 0) continue;
+          const int64_t p = p0 + cand[cc[r]];
+          reinterpret_cast<uint4*>(stage + (size_t)p * d)[vv[r]] = w[r];
+          if (cc[r] < nadm)
+            reinterpret_cast<uint4*>(adm_rows + (size_t)(base + cc[r]) * d)[vv[r]] = w[r];
         }
       }
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        if (cc[r] < 0) continue;
-        const int64_t p = p0 + cand[cc[r]];
-        reinterpret_cast<uint4*>(stage + (size_t)p * d)[vv[r]] = w[r];
-        if (cc[r] < nadm)
-          reinterpret_cast<uint4*>(adm_rows + (size_t)(base + cc[r]) * d)[vv[r]] = w[r];
+    } else {
+      const int tot = na * d;
+      for (int e = threadIdx.x; e < tot; e += kFetchThreads) {
+        const int c = e / d, i = e - c * d;
+        const int64_t p = p0 + cand[c];
+        const int sl = src[c];
+        const T v = sl >= 0 ? cache[(size_t)sl * d + i] : Xh[(size_t)p * d + i];
+        stage[(size_t)p * d + i] = v;
+        if (c < nadm) adm_rows[(size_t)(base + c) * d + i] = v;
       }
     }
-  } else {
-    const int64_t tot = (int64_t)na * d;
-    for (int64_t e = threadIdx.x; e < tot; e += kFetchThreads) {
-      const int c = (int)(e / d), i = (int)(e - (int64_t)c * d);
-      const int64_t p = p0 + cand[c];
-      const int sl = src[c];
-      const T v = sl >= 0 ? cache[(size_t)sl * d + i] : Xh[(size_t)p * d + i];
-      stage[(size_t)p * d + i] = v;
-      if (c < nadm) adm_rows[(size_t)(base + c) * d + i] = v;
+    for (int c = threadIdx.x; c < nadm; c += kFetchThreads)
+      adm_pts[base + c] = (int)(gid0 + p0 + cand[c]);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      miss_tot += (unsigned long long)(na - nhit);
+      hit_tot += (unsigned long long)nhit;
+      adm_tot += (unsigned long long)nadm;
     }
   }
-  for (int c = threadIdx.x; c < nadm; c += kFetchThreads)
-    adm_pts[base + c] = (int)(gid0 + p0 + cand[c]);
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    atomicAdd(io + 1, (unsigned long long)(na - nhit));
-    atomicAdd(io + 2, (unsigned long long)nhit);
-    if (nadm) atomicAdd(io + 3, (unsigned long long)nadm);
+  if (threadIdx.x == 0 && !seg_count) {
+    if (miss_tot) atomicAdd(io + 1, miss_tot);
+    if (hit_tot) atomicAdd(io + 2, hit_tot);
+    if (adm_tot) atomicAdd(io + 3, adm_tot);
   }
 }
 
@@ -231,22 +244,27 @@ __global__ void stream_map_kernel(int* __restrict__ pslot, const int* __restrict
   if (blockIdx.x == 0 && threadIdx.x == 0) *cnt_out = m;
 }
 
+// Blocks of the fetch kernel: one per segment up to this many (it walks the
+// rest); the count pass, which reads no rows, takes one block per segment.
+constexpr int kFetchGrid = 128;
+
 hipError_t launch_stream_fetch(const StreamFetch& f, hipStream_t s) {
   const int nseg = nseg_of_n(f.n);
   if (nseg == 0) return hipSuccess;
+  const int grid = f.seg_count ? nseg : (nseg < kFetchGrid ? nseg : kFetchGrid);
   const size_t esz = f.dt == KNOR_F32 ? 4 : 2;
   const size_t rb = (size_t)f.d * esz;
   const bool al = ((uintptr_t)f.Xh & 15) == 0 && ((uintptr_t)f.stage & 15) == 0 &&
                   ((uintptr_t)f.cache & 15) == 0 && ((uintptr_t)f.adm_rows & 15) == 0;
   const int vec = (rb % 16 == 0 && al) ? 1 : 0;
   if (f.dt == KNOR_F32)
-    hipLaunchKernelGGL(stream_fetch_kernel<float>, dim3(nseg), dim3(kFetchThreads), 0, s,
+    hipLaunchKernelGGL(stream_fetch_kernel<float>, dim3(grid), dim3(kFetchThreads), 0, s,
                        (const float*)f.Xh, f.n, f.d, f.labels, f.u, f.drift, f.s_half, f.all,
                        f.pslot, (const float*)f.cache, (float*)f.stage, (float*)f.adm_rows,
                        f.adm_pts, f.adm_base, f.adm_cap, f.gid0, f.seg_count, f.io, f.conv,
                        f.iter, vec);
   else if (f.dt == KNOR_BF16)
-    hipLaunchKernelGGL(stream_fetch_kernel<uint16_t>, dim3(nseg), dim3(kFetchThreads), 0, s,
+    hipLaunchKernelGGL(stream_fetch_kernel<uint16_t>, dim3(grid), dim3(kFetchThreads), 0, s,
                        (const uint16_t*)f.Xh, f.n, f.d, f.labels, f.u, f.drift, f.s_half,
                        f.all, f.pslot, (const uint16_t*)f.cache, (uint16_t*)f.stage,
                        (uint16_t*)f.adm_rows, f.adm_pts, f.adm_base, f.adm_cap, f.gid0,

@@ -310,6 +310,26 @@ def test_fit_numeric_error_leaves_outputs():
     assert (C == 7.0).all() and (lab == 3).all()
 
 
+@pytest.mark.parametrize("dtype", ["f32", "bf16", "f64"])
+@pytest.mark.parametrize("where", ["first", "middle", "last", "offset"])
+def test_fit_numeric_check_positions(dtype, where):
+    """The finite check sees every element: aligned vector pieces, the tail
+    past the last whole 16-byte piece, and a start that is not 16-byte
+    aligned (a view one row in)."""
+    import torch
+    knor = _knor()
+    tdt = {"f32": torch.float32, "bf16": torch.bfloat16, "f64": torch.float64}[dtype]
+    base = torch.randn(1002, 3, device="cuda").to(tdt)
+    X = base[1:] if where == "offset" else base[:1001]
+    X = X.contiguous() if where != "offset" else X
+    flat = X.view(-1)
+    pos = {"first": 0, "middle": 1500, "last": flat.numel() - 1, "offset": 7}[where]
+    flat[pos] = float("inf") if where == "last" else float("nan")
+    with pytest.raises(knor.KnorError) as e:
+        knor.fit(X, 4, C0=torch.zeros((4, 3), dtype=torch.float64, device="cuda"))
+    assert e.value.code == knor.KNOR_ERR_NUMERIC
+
+
 def test_fit_workspace_cap():
     import torch
     knor = _knor()

@@ -209,3 +209,30 @@ def test_streamed_rejects_device_rows():
     rc = L.knor_fit_streamed(X.data_ptr(), 1, 100, 4, 3, 0, C.data_ptr(), 5, 0.0,
                              ctypes.byref(o), None, C.data_ptr(), lab.data_ptr(), None)
     assert rc == knor.KNOR_ERR_INVALID_ARG
+
+
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+def test_streamed_numeric_check(dtype):
+    """A NaN in the fourth batch is caught as its rows arrive in iteration 0
+    (KNOR_ERR_NUMERIC); a NaN in the initial centroids before any pass; the
+    library is usable afterwards."""
+    import torch
+    knor = _knor()
+    rng = np.random.default_rng(21)
+    n, d, k = 20000, 8, 5
+    X = workloads.cast(rng.normal(size=(n, d)), dtype)
+    C0 = workloads.to_f64(X[:k], dtype).copy()
+    bad = X.copy()
+    bad[3 * 4096 + 17, 5] = workloads.cast(np.array([np.nan]), dtype)[0]
+    _print_case(test="streamed-numeric", dtype=dtype)
+    with pytest.raises(knor.KnorError) as e:
+        knor.fit_streamed(_pinned(bad, dtype), k, C0=C0, max_iters=5, batch_rows=4096)
+    assert e.value.code == knor.KNOR_ERR_NUMERIC
+    C0n = C0.copy()
+    C0n[2, 1] = np.nan
+    with pytest.raises(knor.KnorError) as e:
+        knor.fit_streamed(_pinned(X, dtype), k, C0=C0n, max_iters=5, batch_rows=4096)
+    assert e.value.code == knor.KNOR_ERR_NUMERIC
+    ref = oracle.mti_fit(workloads.to_f64(X, dtype), C0, 5, exact_mean=True)
+    C, lab, st = knor.fit_streamed(_pinned(X, dtype), k, C0=C0, max_iters=5, batch_rows=4096)
+    assert (C.cpu().numpy() == ref.C).all()
