@@ -15,6 +15,11 @@ Workloads (--config, seeded synthetic Gaussian mixtures, see workloads/):
   3: mixed precision, BF16 points, n=2e7, d=64, k=256, 30 iterations;
   4: 64 batched restarts (uneven n, d, k), FP32, 50 iterations each.
 
+--streamed (configs 2, 3, 5): the same workload with its points in pinned host
+memory (knor_fit_streamed, exact update); the line adds the host-link
+accounting (rows copied whole, gathered one by one, served by the row cache,
+admitted to it, bytes, rates) and the in-HBM exact fit's rate.
+
 Every line also reports, measured in the same run:
   baselines     the same workload on this GPU without the form (plain FP32
                 Lloyd's; for 3 and 5 also FP32 + MTI; for 4 sequential fits
