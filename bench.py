@@ -587,6 +587,15 @@ def batched_config(a, knor, oracle, workloads):
                    "sum_n": int(sum(w.n for w in ws)), "iters_per_batch": iters},
         "eff_dists_per_s": sum(r[2]["iters"] * w.n * w.k for r, w in zip(res, ws)) / dt,
     }
+    # the same batch recorded into one graph (knor_opts.batch_graph)
+    resg, dtg = timed(lambda: knor.fit_batched(probs, update=a.update, graph=True),
+                      a.steps, a.warmup)
+    resg = resg[-1]
+    out["graph"] = {"value": round(sum(r[2]["iters"] for r in resg) / dtg, 3),
+                    "unit": "iters/s", "ms_per_batch": round(dtg * 1e3, 3),
+                    "vs_worker_streams": round(dt / dtg, 3),
+                    "same_results": all(bool((r[0] == q[0]).all() and (r[1] == q[1]).all())
+                                        for r, q in zip(res, resg))}
     if not a.no_baselines:
         def seq(prune):
             return [knor.fit(p["X"], p["k"], C0=p["C0"], max_iters=p["max_iters"],

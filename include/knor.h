@@ -169,6 +169,20 @@ typedef struct {
                            any k <= 8192 (FP32 points with prune = 1, else
                            KNOR_ERR_UNSUPPORTED).  Needs k x k FP32 of
                            workspace.  Labels do not depend on this option */
+  int32_t batch_graph;  /* knor_fit_batched: 1 = set every problem up, record
+                           all their iterations (max_iters each) on four
+                           parallel chains into one HIP graph and launch it
+                           once (iterations after a problem converges do no
+                           work); 0 (default) = host worker threads, each
+                           with its own stream, polling convergence.  Same
+                           results either way; learned = 1 always uses 0   */
+  double* objective_history; /* HOST, optional (knor_fit only): max_iters
+                           entries; entry t receives J_t, the sum over points
+                           of the canonical FP64 D(x, c) to the centroid of
+                           x's label from iteration t's assignment, under the
+                           centroids that assignment used, summed in the
+                           canonical order (leaves of 64, pairwise tree).
+                           Costs one extra pass over X per iteration        */
 } knor_opts;
 
 /* Kernel groups timed by opts->profile_ms. */
@@ -284,8 +298,8 @@ typedef struct {
  *   opts       as for knor_fit, with update = 1 required (the exact mean,
  *              which no order of the passes changes; 0 gives
  *              KNOR_ERR_UNSUPPORTED); learned = 1, clause2 = 2, init =
- *              KNOR_INIT_KMEANSPP, autotune, profile_ms and
- *              profile_launches give KNOR_ERR_UNSUPPORTED.  Convergence is
+ *              KNOR_INIT_KMEANSPP, autotune, objective_history,
+ *              profile_ms and profile_launches give KNOR_ERR_UNSUPPORTED.  Convergence is
  *              polled after every iteration (poll_every is ignored).
  *   sopts      may be NULL (defaults).
  *   C_init, C_out, labels_out, st: as for knor_fit (C_init, C_out and
@@ -387,8 +401,8 @@ typedef struct {
  * problem is done.
  *   probs   HOST array of count problems (count >= 0).
  *   opts    as for knor_fit, except that label_history, iter_counters,
- *           centroid_history and profile_ms / profile_launches must be
- *           NULL.
+ *           centroid_history, objective_history and profile_ms /
+ *           profile_launches must be NULL.
  *   st      HOST array of count stats, or NULL.
  * Every problem is validated before any work starts (an invalid one gives
  * KNOR_ERR_INVALID_ARG and no output is touched).  A runtime error in one
@@ -448,7 +462,8 @@ const char* knor_status_string(knor_status s);
  * SHUFFLE_FIRSTK and KMEANSPP and the kernel group KNOR_PROF_CERTIFY (so
  * profile arrays hold KNOR_NPROF = 10 entries; each new field changed
  * sizeof(knor_opts), which struct_size must equal); 0.4.0 added
- * knor_fit_streamed and knor_stream_opts. */
+ * knor_fit_streamed, knor_stream_opts, knor_opts.batch_graph and
+ * knor_opts.objective_history. */
 int32_t knor_version(void);
 
 #ifdef __cplusplus

@@ -62,7 +62,9 @@ class Opts(ctypes.Structure):
                 ("profile_every", ctypes.c_int32),
                 ("update", ctypes.c_int32),
                 ("centroid_history", ctypes.c_void_p),
-                ("clause2", ctypes.c_int32)]
+                ("clause2", ctypes.c_int32),
+                ("batch_graph", ctypes.c_int32),
+                ("objective_history", ctypes.c_void_p)]
 
 
 NPROF = 10
@@ -188,7 +190,8 @@ def _opts(prune=True, recheck=1, check_numeric=True, seed=0, stream=None,
           workspace_cap=0, label_history=None, iter_counters=None,
           poll_every=0, profile=None, tile_blocks=0, tile_resident=0,
           autotune=False, learned=False, train_iters=0, train_batches=0,
-          update="canonical", centroid_history=None, clause2="auto"):
+          update="canonical", centroid_history=None, clause2="auto",
+          objective_history=None):
     torch = _torch()
     if stream is None:
         stream = torch.cuda.current_stream()
@@ -221,6 +224,8 @@ def _opts(prune=True, recheck=1, check_numeric=True, seed=0, stream=None,
     if clause2 not in CLAUSE2:
         raise ValueError(f"clause2 must be one of {sorted(CLAUSE2)}")
     o.clause2 = CLAUSE2[clause2]
+    o.objective_history = (objective_history.ctypes.data
+                           if objective_history is not None else None)
     return o
 
 
@@ -238,7 +243,7 @@ def fit(X, k, C0=None, init="given", max_iters=100, tol=0.0, prune=True,
         check_numeric=True, workspace_cap=0, poll_every=0, profile=None,
         tile_blocks=0, tile_resident=0, autotune=False, learned=False,
         train_iters=0, train_batches=0, update="canonical",
-        centroid_history=False, clause2="auto"):
+        centroid_history=False, clause2="auto", objective_history=False):
     """Lloyd's k-means on the GPU.  Returns (C, labels, stats dict).
 
     init: "given" (C0), "forgy", "shuffle_first_k" or "kmeans++" (the last
@@ -249,6 +254,9 @@ def fit(X, k, C0=None, init="given", max_iters=100, tol=0.0, prune=True,
     adds stats["centroid_history"]: (iters, k, d) float64 CUDA tensor of the
     centroids each iteration's assignment used.  counters=True adds
     stats["counters"]: (iters, 8) int64 numpy array (KNOR_CNT_* columns).
+    objective_history=True adds stats["objective_history"]: (iters,) float64
+    numpy array of J_t (the canonical-order sum of each point's FP64 distance
+    to its iteration-t centroid, under the centroids iteration t used).
     out=(C, labels) reuses preallocated output tensors.  profile=(ms, launches
     [, mask]) (float64 and int64 numpy arrays of NPROF entries, optional bit
     mask of groups) accumulates per-group GPU time measured with HIP events
@@ -288,9 +296,10 @@ def fit(X, k, C0=None, init="given", max_iters=100, tol=0.0, prune=True,
     chist = (torch.empty((max_iters, k, d), dtype=torch.float64, device=dev)
              if centroid_history else None)
     cnt = np.zeros((max_iters, NCOUNTERS), np.int64) if counters else None
+    objh = np.zeros(max_iters, np.float64) if objective_history else None
     o = _opts(prune, recheck, check_numeric, seed, None, workspace_cap, hist,
               cnt, poll_every, profile, tile_blocks, tile_resident, autotune,
-              learned, train_iters, train_batches, update, chist, clause2)
+              learned, train_iters, train_batches, update, chist, clause2, objh)
     st = Stats()
     rc = L.knor_fit(X.data_ptr(), _dtype_code(X), n, d, k, init_code, c0p,
                     max_iters, float(tol), ctypes.byref(o), C.data_ptr(),
@@ -303,6 +312,8 @@ def fit(X, k, C0=None, init="given", max_iters=100, tol=0.0, prune=True,
         s["counters"] = cnt[: st.iters]
     if centroid_history:
         s["centroid_history"] = chist[: st.iters]
+    if objective_history:
+        s["objective_history"] = objh[: st.iters]
     return C, lab, s
 
 
@@ -377,11 +388,13 @@ def fit_streamed(X, k, C0=None, init="given", max_iters=100, tol=0.0, prune=True
 
 def fit_batched(problems, prune=True, recheck=1, seed=0, check_numeric=True,
                 workspace_cap=0, tile_blocks=0, tile_resident=0, update="canonical",
-                clause2="auto"):
+                clause2="auto", graph=False):
     """knor_fit on each problem of a batch, run concurrently.  problems: list
     of dicts with keys X, k and optionally C0 (None: Forgy from seed + index),
-    max_iters (default 100), tol (default 0).  Returns a list of
-    (C, labels, stats dict), each equal to what fit() gives on its own."""
+    max_iters (default 100), tol (default 0).  graph=True records every
+    problem's iterations into one HIP graph launched once (knor_opts.
+    batch_graph).  Returns a list of (C, labels, stats dict), each equal to
+    what fit() gives on its own."""
     torch = _torch()
     L = load()
     arr = (Problem * max(1, len(problems)))()
@@ -406,6 +419,7 @@ def fit_batched(problems, prune=True, recheck=1, seed=0, check_numeric=True,
     o = _opts(prune, recheck, check_numeric, seed, None, workspace_cap,
               tile_blocks=tile_blocks, tile_resident=tile_resident, update=update,
               clause2=clause2)
+    o.batch_graph = 1 if graph else 0
     sts = (Stats * max(1, len(problems)))()
     rc = L.knor_fit_batched(arr, len(problems), ctypes.byref(o), sts)
     _raise(rc)

@@ -7,6 +7,7 @@
 #include <atomic>
 #include <chrono>
 #include <map>
+#include <memory>
 #include <math.h>
 #include <mutex>
 #include <string.h>
@@ -287,6 +288,8 @@ struct Opts {
   int update = 0;
   double* centroid_history = nullptr;
   int clause2 = 0;
+  int batch_graph = 0;
+  double* objective_history = nullptr;
 };
 
 static knor_status read_opts(const knor_opts* o, Opts* out) {
@@ -326,6 +329,9 @@ static knor_status read_opts(const knor_opts* o, Opts* out) {
   out->centroid_history = o->centroid_history;
   if (o->clause2 < 0 || o->clause2 > 2) return KNOR_ERR_INVALID_ARG;
   out->clause2 = o->clause2;
+  out->objective_history = o->objective_history;
+  if (o->batch_graph < 0 || o->batch_graph > 1) return KNOR_ERR_INVALID_ARG;
+  out->batch_graph = o->batch_graph;
   out->tile_blocks = o->tile_blocks;
   out->tile_resident = o->tile_resident;
   out->autotune = o->autotune;
@@ -602,68 +608,47 @@ static void report_counters(const std::vector<unsigned long long>& hc, int hiter
   }
 }
 
-static knor_status fit_impl(const void* X, knor_dtype dt, int64_t n, int d,
-                            int k, knor_init init, const double* C_init,
-                            int max_iters, double tol, const Opts& o,
-                            double* C_out, int32_t* labels_out,
-                            knor_stats* st) {
-  auto t0 = std::chrono::steady_clock::now();
-  hipStream_t s = o.stream;
-  const int kpad = (k + 15) / 16 * 16;
-  const int dp = pad_dim(d);
-  const bool mti = o.prune == 1;
-  const int nseg = nseg_of_n(n);
-  // Clause 2 per block of survivors (FP32 points, large k by default)
-  const bool use_cand = cand_enabled(o, dt, k);
+// One fit in phases: setup (workspace and initial state; may synchronize),
+// iteration t (enqueues the iteration's kernels on the fit's stream; only
+// the learned proposal synchronizes inside it), poll (reads the convergence
+// word every poll_every iterations), finish (objective, counters, stats).
+// knor_fit runs them in order; the batched form can record the iterations
+// of every problem into one graph between setup and finish.  Not movable
+// once set up (the workspace pieces point at its members).
+struct FitRun {
+  const void* X = nullptr;
+  knor_dtype dt = KNOR_F32;
+  int64_t n = 0;
+  int d = 0, k = 0;
+  knor_init init = KNOR_INIT_GIVEN;
+  const double* C_init = nullptr;
+  int max_iters = 0;
+  double tol = 0.0;
+  Opts o;
+  double* C_out = nullptr;
+  int32_t* labels_out = nullptr;
+  knor_stats* st = nullptr;
 
+  std::chrono::steady_clock::time_point t0;
+  hipStream_t s = nullptr;
+  int kpad = 0, dp = 0, nseg = 0;
+  bool mti = false, use_cand = false, exact = false, learned = false, need_rows = false;
   CentroidOps ops{};
-  ops.k = k; ops.kpad = kpad; ops.d = d; ops.dp = dp; ops.dpb = pad_dim_bf16(d);
-  ops.C64 = C_out;                 // the output buffer is the working copy
-  if (knor_status r = select_tile(ops, o)) return r;
   UpdatePlan plan{};
+  ExactPlan xplan{};
   void* upd_ws = nullptr;
   float *u = nullptr, *drift = nullptr, *s_half = nullptr;
   int *list = nullptr, *seg_cnt = nullptr, *flags = nullptr, *ucnt = nullptr;
-  int *flagbuf = nullptr, *dirty = nullptr;
+  int *flagbuf = nullptr, *dirty = nullptr, *conv = nullptr, *bad = nullptr;
   unsigned long long* ctr = nullptr;
+  size_t ctr_bytes = 0;
   int64_t* rows_dev = nullptr;
   double *dist2 = nullptr, *sumtmp = nullptr, *objective = nullptr;
-
-  Arena ar;
-  add_operands(ar, ops, dt);
-  ar.add((void**)&ops.CT, sizeof(double) * (size_t)k * d);
-  ar.add((void**)&drift, sizeof(float) * (size_t)k);
-  ar.add((void**)&s_half, sizeof(float) * (size_t)k);
-  ar.add((void**)&dirty, sizeof(int) * (size_t)k);
-  ar.add((void**)&flags, sizeof(int) * (size_t)flag_capacity(ops, dt, n, nseg));
-  ar.add((void**)&ucnt, sizeof(int) * (size_t)kTileMaxGrid);
-  if (mti) {
-    ar.add((void**)&u, sizeof(float) * (size_t)n);
-    ar.add((void**)&list, sizeof(int) * (size_t)nseg * kSeg);
-    ar.add((void**)&seg_cnt, sizeof(int) * (size_t)nseg);
-  }
-  const size_t ctr_bytes = sizeof(unsigned long long) * ROW_STRIDE * (size_t)max_iters;
-  ar.add((void**)&ctr, ctr_bytes);
-  ar.add((void**)&flagbuf, sizeof(int) * 8);   // conv, bad
-  ar.add((void**)&rows_dev, sizeof(int64_t) * (size_t)k);
-  ar.add(&upd_ws, update_workspace_bytes(n, k, d));
-  const bool exact = o.update == 1;
-  if (exact && dt == KNOR_F64) return KNOR_ERR_UNSUPPORTED;
+  double* obj_hist = nullptr;                   // J_t per iteration (opt-in)
   void* exact_ws = nullptr;
-  if (exact) ar.add(&exact_ws, exact_workspace_bytes(n, k, d));
-  // learned proposal (MTI survivors only)
-  const bool learned = o.learned && mti;
-  // the centroids' neighbour rows: the candidate lists and the certificate
-  const bool need_rows = use_cand || learned;
   float* ccrows = nullptr;
   void* cand_ws = nullptr;
-  if (need_rows) ar.add((void**)&ccrows, sizeof(float) * (size_t)k * k);
-  if (use_cand) ar.add(&cand_ws, cand_workspace_bytes(n, k));
-  ar.add((void**)&dist2, sizeof(double) * (size_t)n);
-  ar.add((void**)&sumtmp, sizeof(double) * (size_t)(n / kLeaf + 2));
-  ar.add((void**)&objective, sizeof(double));
-  const int hM = kMlpHidden;
-  const int Bt = n < kMlpBatch ? (int)n : kMlpBatch;
+  int hM = kMlpHidden, Bt = 0;
   MlpLayout ML{};
   MlpPacked MP{};
   float *th = nullptr, *am = nullptr, *av = nullptr, *grad = nullptr, *Xs_tr = nullptr;
@@ -672,104 +657,160 @@ static knor_status fit_impl(const void* X, knor_dtype dt, int64_t n, int d,
       *seg_cnt2 = nullptr;
   void *mlp_ws = nullptr, *pack_ws = nullptr;
   double *mean = nullptr, *istd = nullptr, *loss_dev = nullptr, *stat_part = nullptr;
-  if (learned) {
-    ML = mlp_layout(d, hM, k);
-    for (float** q : {&th, &am, &av, &grad}) ar.add((void**)q, sizeof(float) * (size_t)ML.P);
-    ar.add(&mlp_ws, mlp_train_workspace(d, hM, k, Bt));
-    ar.add((void**)&Xs_tr, sizeof(float) * (size_t)Bt * d);
-    ar.add((void**)&y_tr, sizeof(int32_t) * (size_t)Bt);
-    ar.add((void**)&rows_tr, sizeof(int) * (size_t)Bt * o.train_batches);
-    ar.add((void**)&mean, sizeof(double) * (size_t)d);
-    ar.add((void**)&istd, sizeof(double) * (size_t)d);
-    ar.add((void**)&loss_dev, sizeof(double));
-    ar.add((void**)&stat_part, standardize_workspace(d));
-    ar.add(&pack_ws, mlp_pack_bytes(d, hM, k, n));
-    ar.add((void**)&dense, sizeof(int) * (size_t)n);
-    ar.add((void**)&seg_off, sizeof(int) * (size_t)(nseg + 1));
-    ar.add((void**)&list2, sizeof(int) * (size_t)nseg * kSeg);
-    ar.add((void**)&seg_cnt2, sizeof(int) * (size_t)nseg);
-    ar.add((void**)&cand, sizeof(int32_t) * (size_t)n * kMlpTop);
-  }
   void* pp_ws = nullptr;
   unsigned long long* pp_rnd = nullptr;
-  if (init == KNOR_INIT_KMEANSPP) {
-    ar.add(&pp_ws, kmeanspp_workspace_bytes(n, k));
-    ar.add((void**)&pp_rnd, sizeof(unsigned long long) * (size_t)k);
-  }
-  knor_status rs = ar.alloc(s, o.cap);
-  if (rs != KNOR_OK) return rs;
-  update_plan_init(&plan, n, k, d, upd_ws);
-  if (learned) MP = mlp_pack_layout(d, hM, k, n, pack_ws);
-  ExactPlan xplan{};
-  if (exact) exact_plan_init(&xplan, n, k, d, exact_ws);
-  int* conv = flagbuf;
-  int* bad = flagbuf + 1;
-  HIPCHK(update_plan_reset(plan, s));
-
-  HIPCHK(hipMemsetAsync(flagbuf, 0, sizeof(int) * 8, s));
-  HIPCHK(launch_fill_i32(conv, 1, kNotConverged, s));
-  HIPCHK(hipMemsetAsync(ctr, 0, ctr_bytes, s));
-
-  // numeric check of the inputs before anything is written to the outputs
-  if (o.check_numeric) {
-    HIPCHK(launch_check_finite(X, dt, n * (int64_t)d, bad, s));
-    if (init == KNOR_INIT_GIVEN)
-      HIPCHK(launch_check_finite(C_init, KNOR_F64, (int64_t)k * d, bad, s));
-    int hbad = 0;
-    HIPCHK(hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
-    if (hbad) return KNOR_ERR_NUMERIC;
-  }
-
-  // initial centroids into the working buffer C_out
-  if (init == KNOR_INIT_GIVEN) {
-    if (C_init != C_out)
-      HIPCHK(hipMemcpyAsync(C_out, C_init, sizeof(double) * (size_t)k * d,
-                            hipMemcpyDeviceToDevice, s));
-  } else if (init == KNOR_INIT_KMEANSPP) {
-    std::vector<unsigned long long> rnd(k);
-    uint64_t st_r = o.seed;
-    for (auto& r : rnd) r = splitmix64(&st_r);
-    HIPCHK(hipMemcpyAsync(pp_rnd, rnd.data(), sizeof(unsigned long long) * k,
-                          hipMemcpyHostToDevice, s));
-    HIPCHK(launch_kmeanspp(X, dt, n, d, k, pp_rnd, C_out, pp_ws, s));
-    HIPCHK(hipStreamSynchronize(s));   // `rnd` leaves scope
-  } else {
-    std::vector<int64_t> rows = init == KNOR_INIT_FORGY ? forgy_rows(n, k, o.seed)
-                                                        : shuffle_first_k(n, k, o.seed);
-    HIPCHK(hipMemcpyAsync(rows_dev, rows.data(), sizeof(int64_t) * k,
-                          hipMemcpyHostToDevice, s));
-    HIPCHK(launch_gather_rows(X, dt, d, rows_dev, k, C_out, s));
-    HIPCHK(hipStreamSynchronize(s));   // `rows` leaves scope
-  }
-  HIPCHK(launch_prep_centroids(ops, s));
-  HIPCHK(launch_fill_i32(labels_out, n, -1, s));   // every label changes at t = 0
-  HIPCHK(launch_fill_i32(dirty, k, 1, s));         // every cluster is summed at t = 0
-  if (exact) HIPCHK(launch_fill_i32(xplan.prev, n, -1, s));
-  if (learned) {
-    HIPCHK(launch_standardize_stats(X, dt, n, d, mean, istd, stat_part, s));
-    std::vector<float> th0 = mlp_init_host(d, hM, k, o.seed);
-    HIPCHK(hipMemcpyAsync(th, th0.data(), sizeof(float) * th0.size(),
-                          hipMemcpyHostToDevice, s));
-    HIPCHK(hipMemsetAsync(am, 0, sizeof(float) * (size_t)ML.P, s));
-    HIPCHK(hipMemsetAsync(av, 0, sizeof(float) * (size_t)ML.P, s));
-    HIPCHK(hipStreamSynchronize(s));          // `th0` leaves scope
-  }
   int64_t mlp_step = 0, mlp_queries = 0;
-  std::vector<int64_t> queried((size_t)max_iters, 0);   // survivors sent to the MLP
-  std::vector<char> cand_used((size_t)max_iters, 0);     // candidate-list tile ran
+  std::vector<int64_t> queried;                 // survivors sent to the MLP
+  std::vector<char> cand_used;                  // candidate-list tile ran
   bool packed = false;
-
   Prof prof;
-  prof.stream = s;
-  prof.on = o.profile_ms != nullptr || o.profile_launches != nullptr;
-  prof.mask = o.profile_mask ? o.profile_mask : ~0;
-  prof.every = o.profile_every;
-  Prof* pp = prof.on ? &prof : nullptr;
-  const double tol_n = tol * (double)n;
+  Prof* pp = nullptr;
+  double tol_n = 0.0;
   int hconv = kNotConverged;
   int ctl_delta_only = 0;
-  for (int t = 0; t < max_iters; ++t) {
+  Arena ar;
+
+  FitRun() = default;
+  FitRun(const FitRun&) = delete;
+  FitRun& operator=(const FitRun&) = delete;
+
+  knor_status setup() {
+    t0 = std::chrono::steady_clock::now();
+    s = o.stream;
+    kpad = (k + 15) / 16 * 16;
+    dp = pad_dim(d);
+    mti = o.prune == 1;
+    nseg = nseg_of_n(n);
+    // Clause 2 per block of survivors (FP32 points, large k by default)
+    use_cand = cand_enabled(o, dt, k);
+
+    ops.k = k; ops.kpad = kpad; ops.d = d; ops.dp = dp; ops.dpb = pad_dim_bf16(d);
+    ops.C64 = C_out;                 // the output buffer is the working copy
+    if (knor_status r = select_tile(ops, o)) return r;
+    add_operands(ar, ops, dt);
+    ar.add((void**)&ops.CT, sizeof(double) * (size_t)k * d);
+    ar.add((void**)&drift, sizeof(float) * (size_t)k);
+    ar.add((void**)&s_half, sizeof(float) * (size_t)k);
+    ar.add((void**)&dirty, sizeof(int) * (size_t)k);
+    ar.add((void**)&flags, sizeof(int) * (size_t)flag_capacity(ops, dt, n, nseg));
+    ar.add((void**)&ucnt, sizeof(int) * (size_t)kTileMaxGrid);
+    if (mti) {
+      ar.add((void**)&u, sizeof(float) * (size_t)n);
+      ar.add((void**)&list, sizeof(int) * (size_t)nseg * kSeg);
+      ar.add((void**)&seg_cnt, sizeof(int) * (size_t)nseg);
+    }
+    ctr_bytes = sizeof(unsigned long long) * ROW_STRIDE * (size_t)max_iters;
+    ar.add((void**)&ctr, ctr_bytes);
+    ar.add((void**)&flagbuf, sizeof(int) * 8);   // conv, bad
+    ar.add((void**)&rows_dev, sizeof(int64_t) * (size_t)k);
+    ar.add(&upd_ws, update_workspace_bytes(n, k, d));
+    exact = o.update == 1;
+    if (exact && dt == KNOR_F64) return KNOR_ERR_UNSUPPORTED;
+    if (exact) ar.add(&exact_ws, exact_workspace_bytes(n, k, d));
+    // learned proposal (MTI survivors only)
+    learned = o.learned && mti;
+    // the centroids' neighbour rows: the candidate lists and the certificate
+    need_rows = use_cand || learned;
+    if (need_rows) ar.add((void**)&ccrows, sizeof(float) * (size_t)k * k);
+    if (use_cand) ar.add(&cand_ws, cand_workspace_bytes(n, k));
+    ar.add((void**)&dist2, sizeof(double) * (size_t)n);
+    ar.add((void**)&sumtmp, sizeof(double) * (size_t)(n / kLeaf + 2));
+    ar.add((void**)&objective, sizeof(double));
+    if (o.objective_history) ar.add((void**)&obj_hist, sizeof(double) * (size_t)max_iters);
+    Bt = n < kMlpBatch ? (int)n : kMlpBatch;
+    if (learned) {
+      ML = mlp_layout(d, hM, k);
+      for (float** q : {&th, &am, &av, &grad}) ar.add((void**)q, sizeof(float) * (size_t)ML.P);
+      ar.add(&mlp_ws, mlp_train_workspace(d, hM, k, Bt));
+      ar.add((void**)&Xs_tr, sizeof(float) * (size_t)Bt * d);
+      ar.add((void**)&y_tr, sizeof(int32_t) * (size_t)Bt);
+      ar.add((void**)&rows_tr, sizeof(int) * (size_t)Bt * o.train_batches);
+      ar.add((void**)&mean, sizeof(double) * (size_t)d);
+      ar.add((void**)&istd, sizeof(double) * (size_t)d);
+      ar.add((void**)&loss_dev, sizeof(double));
+      ar.add((void**)&stat_part, standardize_workspace(d));
+      ar.add(&pack_ws, mlp_pack_bytes(d, hM, k, n));
+      ar.add((void**)&dense, sizeof(int) * (size_t)n);
+      ar.add((void**)&seg_off, sizeof(int) * (size_t)(nseg + 1));
+      ar.add((void**)&list2, sizeof(int) * (size_t)nseg * kSeg);
+      ar.add((void**)&seg_cnt2, sizeof(int) * (size_t)nseg);
+      ar.add((void**)&cand, sizeof(int32_t) * (size_t)n * kMlpTop);
+    }
+    if (init == KNOR_INIT_KMEANSPP) {
+      ar.add(&pp_ws, kmeanspp_workspace_bytes(n, k));
+      ar.add((void**)&pp_rnd, sizeof(unsigned long long) * (size_t)k);
+    }
+    knor_status rs = ar.alloc(s, o.cap);
+    if (rs != KNOR_OK) return rs;
+    update_plan_init(&plan, n, k, d, upd_ws);
+    if (learned) MP = mlp_pack_layout(d, hM, k, n, pack_ws);
+    if (exact) exact_plan_init(&xplan, n, k, d, exact_ws);
+    conv = flagbuf;
+    bad = flagbuf + 1;
+    HIPCHK(update_plan_reset(plan, s));
+
+    HIPCHK(hipMemsetAsync(flagbuf, 0, sizeof(int) * 8, s));
+    HIPCHK(launch_fill_i32(conv, 1, kNotConverged, s));
+    HIPCHK(hipMemsetAsync(ctr, 0, ctr_bytes, s));
+
+    // numeric check of the inputs before anything is written to the outputs
+    if (o.check_numeric) {
+      HIPCHK(launch_check_finite(X, dt, n * (int64_t)d, bad, s));
+      if (init == KNOR_INIT_GIVEN)
+        HIPCHK(launch_check_finite(C_init, KNOR_F64, (int64_t)k * d, bad, s));
+      int hbad = 0;
+      HIPCHK(hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, s));
+      HIPCHK(hipStreamSynchronize(s));
+      if (hbad) return KNOR_ERR_NUMERIC;
+    }
+
+    // initial centroids into the working buffer C_out
+    if (init == KNOR_INIT_GIVEN) {
+      if (C_init != C_out)
+        HIPCHK(hipMemcpyAsync(C_out, C_init, sizeof(double) * (size_t)k * d,
+                              hipMemcpyDeviceToDevice, s));
+    } else if (init == KNOR_INIT_KMEANSPP) {
+      std::vector<unsigned long long> rnd(k);
+      uint64_t st_r = o.seed;
+      for (auto& r : rnd) r = splitmix64(&st_r);
+      HIPCHK(hipMemcpyAsync(pp_rnd, rnd.data(), sizeof(unsigned long long) * k,
+                            hipMemcpyHostToDevice, s));
+      HIPCHK(launch_kmeanspp(X, dt, n, d, k, pp_rnd, C_out, pp_ws, s));
+      HIPCHK(hipStreamSynchronize(s));   // `rnd` leaves scope
+    } else {
+      std::vector<int64_t> rows = init == KNOR_INIT_FORGY ? forgy_rows(n, k, o.seed)
+                                                          : shuffle_first_k(n, k, o.seed);
+      HIPCHK(hipMemcpyAsync(rows_dev, rows.data(), sizeof(int64_t) * k,
+                            hipMemcpyHostToDevice, s));
+      HIPCHK(launch_gather_rows(X, dt, d, rows_dev, k, C_out, s));
+      HIPCHK(hipStreamSynchronize(s));   // `rows` leaves scope
+    }
+    HIPCHK(launch_prep_centroids(ops, s));
+    HIPCHK(launch_fill_i32(labels_out, n, -1, s));   // every label changes at t = 0
+    HIPCHK(launch_fill_i32(dirty, k, 1, s));         // every cluster is summed at t = 0
+    if (exact) HIPCHK(launch_fill_i32(xplan.prev, n, -1, s));
+    if (learned) {
+      HIPCHK(launch_standardize_stats(X, dt, n, d, mean, istd, stat_part, s));
+      std::vector<float> th0 = mlp_init_host(d, hM, k, o.seed);
+      HIPCHK(hipMemcpyAsync(th, th0.data(), sizeof(float) * th0.size(),
+                            hipMemcpyHostToDevice, s));
+      HIPCHK(hipMemsetAsync(am, 0, sizeof(float) * (size_t)ML.P, s));
+      HIPCHK(hipMemsetAsync(av, 0, sizeof(float) * (size_t)ML.P, s));
+      HIPCHK(hipStreamSynchronize(s));          // `th0` leaves scope
+    }
+    queried.assign((size_t)max_iters, 0);
+    cand_used.assign((size_t)max_iters, 0);
+
+    prof.stream = s;
+    prof.on = o.profile_ms != nullptr || o.profile_launches != nullptr;
+    prof.mask = o.profile_mask ? o.profile_mask : ~0;
+    prof.every = o.profile_every;
+    pp = prof.on ? &prof : nullptr;
+    tol_n = tol * (double)n;
+    return KNOR_OK;
+  }
+
+  knor_status iteration(int t) {
     prof.iter = t;
     unsigned long long* row = ctr + (size_t)t * ROW_STRIDE;
     if (o.centroid_history)
@@ -859,6 +900,11 @@ static knor_status fit_impl(const void* X, knor_dtype dt, int64_t n, int d,
     if (o.label_history)
       HIPCHK(launch_copy_i32(labels_out, o.label_history + (size_t)t * n, n,
                              conv, t, s));
+    if (obj_hist) {
+      // J_t under the centroids this assignment used (the update follows)
+      HIPCHK(launch_exact_dist2(X, dt, n, d, C_out, labels_out, dist2, s));
+      HIPCHK(launch_canonical_sum(dist2, n, sumtmp, obj_hist + t, s));
+    }
     IterCtl ctl;
     ctl.row = row; ctl.conv = conv; ctl.iter = t; ctl.tol_n = tol_n;
     ctl.segmented = seg; ctl.n = n;
@@ -876,42 +922,77 @@ static knor_status fit_impl(const void* X, knor_dtype dt, int64_t n, int d,
       HIPCHK(launch_cc_bounds(ops, s_half, need_rows ? ccrows : nullptr, conv, t, s));
       prof.end();
     }
+    return KNOR_OK;
+  }
+
+  knor_status poll(int t, bool* stop) {
+    const unsigned long long* row = ctr + (size_t)t * ROW_STRIDE;
     if ((t + 1) % o.poll_every == 0 || t + 1 == max_iters) {
       unsigned long long hch = 0;
       HIPCHK(hipMemcpyAsync(&hconv, conv, sizeof(int), hipMemcpyDeviceToHost, s));
       if (exact && !ctl_delta_only)
         HIPCHK(hipMemcpyAsync(&hch, row + ROW_CHANGED, sizeof(hch), hipMemcpyDeviceToHost, s));
       HIPCHK(hipStreamSynchronize(s));
-      if (hconv != kNotConverged) break;
+      if (hconv != kNotConverged) {
+        *stop = true;
+        return KNOR_OK;
+      }
       // the exact update: once few labels change, stop launching the full
       // pass (both modes give the same centroids; this only saves launches)
       if (exact && !ctl_delta_only && hch <= (unsigned long long)xplan.delta_max)
         ctl_delta_only = 1;
     }
+    return KNOR_OK;
   }
 
-  // final objective: sum over points of D(x, C_out[label]) in the canonical order
-  HIPCHK(launch_exact_dist2(X, dt, n, d, C_out, labels_out, dist2, s));
-  HIPCHK(launch_canonical_sum(dist2, n, sumtmp, objective, s));
+  knor_status finish() {
+    // final objective: sum over points of D(x, C_out[label]) in the canonical order
+    HIPCHK(launch_exact_dist2(X, dt, n, d, C_out, labels_out, dist2, s));
+    HIPCHK(launch_canonical_sum(dist2, n, sumtmp, objective, s));
 
-  std::vector<unsigned long long> hc((size_t)ROW_STRIDE * max_iters);
-  double hobj = 0.0;
-  HIPCHK(hipMemcpyAsync(&hconv, conv, sizeof(int), hipMemcpyDeviceToHost, s));
-  HIPCHK(hipMemcpyAsync(hc.data(), ctr, ctr_bytes, hipMemcpyDeviceToHost, s));
-  HIPCHK(hipMemcpyAsync(&hobj, objective, sizeof(double), hipMemcpyDeviceToHost, s));
-  HIPCHK(hipStreamSynchronize(s));
-  prof.collect(o.profile_ms, o.profile_launches);
-  const int converged = hconv != kNotConverged;
-  const int hiters = converged ? hconv + 1 : max_iters;
+    std::vector<unsigned long long> hc((size_t)ROW_STRIDE * max_iters);
+    double hobj = 0.0;
+    HIPCHK(hipMemcpyAsync(&hconv, conv, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(hc.data(), ctr, ctr_bytes, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(&hobj, objective, sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    prof.collect(o.profile_ms, o.profile_launches);
+    const int converged = hconv != kNotConverged;
+    const int hiters = converged ? hconv + 1 : max_iters;
+    if (obj_hist) {
+      HIPCHK(hipMemcpyAsync(o.objective_history, obj_hist, sizeof(double) * (size_t)hiters,
+                            hipMemcpyDeviceToHost, s));
+      HIPCHK(hipStreamSynchronize(s));
+    }
 
-  report_counters(hc, hiters, n, k, mti, cand_used, queried, o.iter_counters, st);
-  if (st) {
-    st->converged = converged;
-    st->mlp_queries = mlp_queries;
-    st->objective = hobj;
-    st->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    report_counters(hc, hiters, n, k, mti, cand_used, queried, o.iter_counters, st);
+    if (st) {
+      st->converged = converged;
+      st->mlp_queries = mlp_queries;
+      st->objective = hobj;
+      st->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    }
+    return KNOR_OK;
   }
-  return KNOR_OK;
+};
+
+static knor_status fit_impl(const void* X, knor_dtype dt, int64_t n, int d,
+                            int k, knor_init init, const double* C_init,
+                            int max_iters, double tol, const Opts& o,
+                            double* C_out, int32_t* labels_out,
+                            knor_stats* st) {
+  FitRun r;
+  r.X = X; r.dt = dt; r.n = n; r.d = d; r.k = k; r.init = init; r.C_init = C_init;
+  r.max_iters = max_iters; r.tol = tol; r.o = o; r.C_out = C_out;
+  r.labels_out = labels_out; r.st = st;
+  if (knor_status e = r.setup()) return e;
+  for (int t = 0; t < max_iters; ++t) {
+    if (knor_status e = r.iteration(t)) return e;
+    bool stop = false;
+    if (knor_status e = r.poll(t, &stop)) return e;
+    if (stop) break;
+  }
+  return r.finish();
 }
 
 // ---------------------------------------------------------------------------
@@ -1135,13 +1216,101 @@ knor_status knor_fit(const void* X, knor_dtype dt, int64_t n, int32_t d,
 // those of knor_fit on it alone.
 constexpr int kBatchStreams = 4;
 
+// The batched form as one graph: every problem is set up on its chain's
+// stream, then one capture records each problem's max_iters iterations on
+// one of kBatchStreams parallel chains (largest work first, each problem on
+// the chain with the least work so far), the graph is launched once, and
+// every problem is finished.  A problem's iterations after its convergence
+// return at once (its convergence word).
+struct GraphRes {
+  hipStream_t cs[kBatchStreams] = {};
+  hipEvent_t ev[kBatchStreams + 1] = {};
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  ~GraphRes() {
+    for (hipStream_t x : cs)
+      if (x) (void)hipStreamSynchronize(x);
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    for (hipEvent_t e : ev)
+      if (e) (void)hipEventDestroy(e);
+    for (hipStream_t x : cs)
+      if (x) (void)hipStreamDestroy(x);
+    (void)hipGetLastError();
+  }
+};
+
+static knor_status fit_batched_graph(const knor_problem* probs, int count, const Opts& o,
+                                     const std::vector<int>& order, knor_stats* st) {
+  GraphRes g;
+  for (int w = 0; w < kBatchStreams; ++w)
+    HIPCHK(hipStreamCreateWithFlags(&g.cs[w], hipStreamNonBlocking));
+  for (hipEvent_t& e : g.ev) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  // the chains follow everything already on opts->stream
+  HIPCHK(hipEventRecord(g.ev[0], o.stream));
+  for (hipStream_t x : g.cs) HIPCHK(hipStreamWaitEvent(x, g.ev[0], 0));
+  std::vector<int> chain(count, 0);
+  double load[kBatchStreams] = {};
+  for (int q : order) {
+    int w = 0;
+    for (int v = 1; v < kBatchStreams; ++v)
+      if (load[v] < load[w]) w = v;
+    chain[q] = w;
+    load[w] += (double)probs[q].n * probs[q].k * probs[q].d * probs[q].max_iters;
+  }
+  std::vector<std::unique_ptr<FitRun>> runs(count);
+  for (int q : order) {
+    const knor_problem& p = probs[q];
+    runs[q].reset(new FitRun());
+    FitRun& r = *runs[q];
+    r.X = p.X; r.dt = p.dt; r.n = p.n; r.d = p.d; r.k = p.k;
+    r.init = p.C_init ? KNOR_INIT_GIVEN : KNOR_INIT_FORGY;
+    r.C_init = p.C_init; r.max_iters = p.max_iters; r.tol = p.tol;
+    r.o = o;
+    r.o.stream = g.cs[chain[q]];
+    r.o.seed = o.seed + (uint64_t)q;
+    r.C_out = p.C_out; r.labels_out = p.labels_out; r.st = st ? &st[q] : nullptr;
+    if (knor_status e = r.setup()) return e;
+  }
+  // record: a fork from chain 0, each chain's problems in order, a join
+  HIPCHK(hipStreamBeginCapture(g.cs[0], hipStreamCaptureModeRelaxed));
+  knor_status rec = KNOR_OK;
+  if (hipEventRecord(g.ev[1], g.cs[0]) != hipSuccess) rec = KNOR_ERR_HIP;
+  for (int w = 1; w < kBatchStreams && rec == KNOR_OK; ++w)
+    if (hipStreamWaitEvent(g.cs[w], g.ev[1], 0) != hipSuccess) rec = KNOR_ERR_HIP;
+  for (int w = 0; w < kBatchStreams && rec == KNOR_OK; ++w)
+    for (int q : order) {
+      if (chain[q] != w || rec != KNOR_OK) continue;
+      for (int t = 0; t < probs[q].max_iters && rec == KNOR_OK; ++t)
+        rec = runs[q]->iteration(t);
+    }
+  for (int w = 1; w < kBatchStreams && rec == KNOR_OK; ++w)
+    if (hipEventRecord(g.ev[1 + w], g.cs[w]) != hipSuccess ||
+        hipStreamWaitEvent(g.cs[0], g.ev[1 + w], 0) != hipSuccess)
+      rec = KNOR_ERR_HIP;
+  if (hipStreamEndCapture(g.cs[0], &g.graph) != hipSuccess) rec = KNOR_ERR_HIP;
+  if (rec != KNOR_OK) {
+    (void)hipGetLastError();
+    return rec;
+  }
+  HIPCHK(hipGraphInstantiate(&g.exec, g.graph, nullptr, nullptr, 0));
+  HIPCHK(hipGraphLaunch(g.exec, g.cs[0]));
+  HIPCHK(hipStreamSynchronize(g.cs[0]));
+  knor_status first = KNOR_OK;
+  for (int q = 0; q < count; ++q) {
+    const knor_status e = runs[q]->finish();
+    if (e != KNOR_OK && first == KNOR_OK) first = e;
+  }
+  return first;
+}
+
 knor_status knor_fit_batched(const knor_problem* probs, int32_t count,
                              const knor_opts* opts, knor_stats* st) {
   Opts o;
   if (knor_status r = read_opts(opts, &o)) return r;
   if (count < 0 || (count > 0 && !probs)) return KNOR_ERR_INVALID_ARG;
   if (o.label_history || o.iter_counters || o.profile_ms || o.profile_launches ||
-      o.centroid_history)
+      o.centroid_history || o.objective_history)
     return KNOR_ERR_INVALID_ARG;           // per-call arrays: single fits only
   for (int i = 0; i < count; ++i) {
     const knor_problem& p = probs[i];
@@ -1192,6 +1361,11 @@ knor_status knor_fit_batched(const knor_problem* probs, int32_t count,
     return probs[a].n * (int64_t)probs[a].k * probs[a].d >
            probs[b].n * (int64_t)probs[b].k * probs[b].d;
   });
+  if (o.batch_graph && !o.learned) {
+    const knor_status r = fit_batched_graph(probs, count, o, order, st);
+    (void)hipEventDestroy(ready);
+    return r;
+  }
   std::vector<knor_status> res(count, KNOR_OK);
   std::atomic<int> next{0};
   const int nw = count < kBatchStreams ? count : kBatchStreams;
@@ -1599,7 +1773,8 @@ knor_status knor_fit_streamed(const void* X, knor_dtype dt, int64_t n, int32_t d
   if (sc.batch > nr) sc.batch = nr;
   if (sc.cache > n) sc.cache = n;
   if (o.update != 1 || o.learned || o.clause2 == 2 || o.autotune ||
-      init == KNOR_INIT_KMEANSPP || o.profile_ms || o.profile_launches)
+      init == KNOR_INIT_KMEANSPP || o.profile_ms || o.profile_launches ||
+      o.objective_history)
     return KNOR_ERR_UNSUPPORTED;
   const void* Xd = nullptr;
   if (knor_status r = host_rows_on_device(X, &Xd)) return r;

@@ -68,6 +68,12 @@ def test_fit_rejects_bad_opts(L):
     o = knor.Opts()
     o.struct_size = ctypes.sizeof(knor.Opts)
     o.prune = 1
+    o.recheck = 1
+    o.batch_graph = 2
+    assert _fit(L, opts=ctypes.byref(o)) == knor.KNOR_ERR_INVALID_ARG
+    o = knor.Opts()
+    o.struct_size = ctypes.sizeof(knor.Opts)
+    o.prune = 1
     o.recheck = 7
     assert _fit(L, opts=ctypes.byref(o)) == knor.KNOR_ERR_INVALID_ARG
     o.recheck = 1
@@ -212,13 +218,14 @@ def test_binding_update_names():
     assert knor._update_code("canonical") == 0 and knor._update_code("exact") == 1
 
 
-def test_fit_batched_rejects_centroid_history(L):
+@pytest.mark.parametrize("field", ["centroid_history", "objective_history"])
+def test_fit_batched_rejects_histories(L, field):
     o = knor.Opts()
     o.struct_size = ctypes.sizeof(knor.Opts)
     o.prune = 1
     o.recheck = 1
     o.check_numeric = 1
-    o.centroid_history = 0x1000
+    setattr(o, field, 0x1000)
     arr = (knor.Problem * 1)(_problem())
     assert L.knor_fit_batched(arr, 1, ctypes.byref(o), None) == knor.KNOR_ERR_INVALID_ARG
 
@@ -288,7 +295,8 @@ def test_fit_streamed_unsupported_options(L):
     # the canonical update (the default), the learned proposal, forced
     # Clause 2, autotuning and k-means++ are not offered for host rows
     assert _fit_streamed(L) == knor.KNOR_ERR_UNSUPPORTED
-    for field, v in [("update", 0), ("learned", 1), ("clause2", 2), ("autotune", 1)]:
+    for field, v in [("update", 0), ("learned", 1), ("clause2", 2), ("autotune", 1),
+                     ("objective_history", 0x1000)]:
         o = _exact_opts()
         setattr(o, field, v)
         assert _fit_streamed(L, opts=ctypes.byref(o)) == knor.KNOR_ERR_UNSUPPORTED, field

@@ -220,7 +220,8 @@ def test_exact_fit_config2_full_size():
     print("exact config2 iters", st["iters"], flush=True)
 
 
-def test_exact_fit_batched_equals_single():
+@pytest.mark.parametrize("graph", [False, True])
+def test_exact_fit_batched_equals_single(graph):
     knor = _knor()
     probs, singles = [], []
     for i, (n, d, k) in enumerate([(20000, 16, 30), (9000, 32, 100), (15000, 8, 7)]):
@@ -231,7 +232,7 @@ def test_exact_fit_batched_equals_single():
         probs.append({"X": _dev(X, "f32"), "k": k, "C0": C0, "max_iters": 25})
         singles.append(knor.fit(_dev(X, "f32"), k, C0=_dev(C0, "f64"), max_iters=25,
                                 update="exact"))
-    out = knor.fit_batched(probs, update="exact")
+    out = knor.fit_batched(probs, update="exact", graph=graph)
     for (C, lab, st), (C1, lab1, st1) in zip(out, singles):
         assert (C.cpu().numpy() == C1.cpu().numpy()).all()
         assert (lab.cpu().numpy() == lab1.cpu().numpy()).all()

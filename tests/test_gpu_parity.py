@@ -310,6 +310,33 @@ def test_fit_numeric_error_leaves_outputs():
     assert (C == 7.0).all() and (lab == 3).all()
 
 
+@pytest.mark.parametrize("dtype,prune,update", [("f32", True, "canonical"),
+                                                 ("bf16", True, "exact"),
+                                                 ("f64", False, "canonical"),
+                                                 ("f32", False, "exact")])
+def test_objective_history_matches_oracle(dtype, prune, update):
+    """J_t at every iteration equals the oracle's traced objective bit for bit
+    (same canonical distances, same canonical summation order), and the final
+    objective too."""
+    knor = _knor()
+    w = workloads.config(2, n=60000, seed=3, k=30)
+    X = workloads.cast(w.x64(), dtype)
+    X64 = workloads.to_f64(X, dtype)
+    ex = update == "exact"
+    _print_case(test="objective-history", dtype=dtype, prune=prune, update=update)
+    if prune:
+        ref = oracle.mti_fit(X64, w.C0, 25, history=False, exact_mean=ex)
+    elif ex:
+        ref = oracle.fit_exact_mean(X64, w.C0, 25)
+    else:
+        ref = oracle.fit(X64, w.C0, 25)
+    C, lab, st = knor.fit(_dev(X, dtype), w.k, C0=_dev(w.C0, "f64"), max_iters=25,
+                          prune=prune, update=update, objective_history=True)
+    assert st["iters"] == ref.iters
+    assert st["objective_history"].tolist() == ref.objective.tolist()
+    assert st["objective"] == oracle.objective(X64, ref.C, ref.labels)
+
+
 @pytest.mark.parametrize("dtype", ["f32", "bf16", "f64"])
 @pytest.mark.parametrize("where", ["first", "middle", "last", "offset"])
 def test_fit_numeric_check_positions(dtype, where):
@@ -432,9 +459,11 @@ def test_autotuned_fit_matches_default():
     assert (a[0] == b[0]).all() and (a[1] == b[1]).all()
 
 
-def test_fit_batched_equals_single_fits():
+@pytest.mark.parametrize("graph", [False, True])
+def test_fit_batched_equals_single_fits(graph):
     """A batch mixing dtypes, shapes, given and Forgy starts: every problem's
-    result equals knor_fit on it alone, and the oracle's."""
+    result equals knor_fit on it alone, and the oracle's (worker streams, or
+    one graph holding every problem's iterations)."""
     knor = _knor()
     specs = [(9000, 8, 12, "f32", True), (20000, 32, 100, "f32", True),
              (5000, 3, 5, "f64", True), (7000, 64, 40, "bf16", True),
@@ -447,8 +476,8 @@ def test_fit_batched_equals_single_fits():
         data.append((X, C0, dt))
         probs.append(dict(X=_dev(X, dt), k=k, C0=_dev(C0, "f64") if given else None,
                           max_iters=20))
-    _print_case(test="batched", count=len(probs))
-    out = knor.fit_batched(probs, seed=77)
+    _print_case(test="batched", count=len(probs), graph=graph)
+    out = knor.fit_batched(probs, seed=77, graph=graph)
     for i, ((X, C0, dt), p, (C, lab, st)) in enumerate(zip(data, probs, out)):
         single = knor.fit(p["X"], p["k"], C0=p["C0"], init="given" if p["C0"] is not None else "forgy",
                           seed=77 + i, max_iters=20)
@@ -460,20 +489,38 @@ def test_fit_batched_equals_single_fits():
             assert (C.cpu().numpy() == ref.C).all(), i
 
 
-def test_fit_batched_workload_sample():
+@pytest.mark.parametrize("graph", [False, True])
+def test_fit_batched_workload_sample(graph):
     """Eight instances of the batched-restart workload (n scaled by 1/20),
     each against the FP64 oracle."""
     knor = _knor()
     ws = workloads.batched(8, n_scale=0.05)
     probs = [dict(X=_dev(w.X, "f32"), k=w.k, C0=_dev(w.C0, "f64"),
                   max_iters=w.max_iters) for w in ws]
-    out = knor.fit_batched(probs)
+    out = knor.fit_batched(probs, graph=graph)
     for w, (C, lab, st) in zip(ws, out):
         _print_case(test="batched-workload", n=w.n, d=w.d, k=w.k)
         ref = oracle.mti_fit(w.x64(), w.C0, w.max_iters)
         assert st["iters"] == ref.iters
         assert (lab.cpu().numpy() == ref.labels).all()
         assert (C.cpu().numpy() == ref.C).all()
+
+
+def test_fit_batched_graph_repeated():
+    """The graph form three times in a row, with eager fits between the calls:
+    every call's results equal the worker-stream form's."""
+    knor = _knor()
+    ws = workloads.batched(6, n_scale=0.03)
+    probs = [dict(X=_dev(w.X, "f32"), k=w.k, C0=_dev(w.C0, "f64"),
+                  max_iters=w.max_iters) for w in ws]
+    _print_case(test="batched-graph-repeated")
+    ref = knor.fit_batched(probs)
+    for rep in range(3):
+        out = knor.fit_batched(probs, graph=True)
+        for i, ((C, lab, st), (Cr, labr, str_)) in enumerate(zip(out, ref)):
+            assert (C == Cr).all() and (lab == labr).all(), (rep, i)
+            assert st["iters"] == str_["iters"], (rep, i)
+        knor.fit(probs[rep]["X"], ws[rep].k, C0=probs[rep]["C0"], max_iters=5)
 
 
 # ---------------------------------------------------------------------------
