@@ -134,7 +134,7 @@ MLP_BATCH = 4096
 def group_work(g, w, sx, ctr, iters, its, train_iters=5, train_batches=16):
     """Algorithmic work of kernel group g summed over the iterations `its` of
     one fit, and the group's launches among them: (amount, launches, unit,
-    bound, peak).  ctr: per-iteration counters (iters x 8)."""
+    bound, peak).  ctr: per-iteration counters (iters x 9)."""
     n, d, k = w.n, w.d, w.k
     its = [t for t in its if t < iters]
     after0 = [t for t in its if t >= 1]
@@ -143,7 +143,12 @@ def group_work(g, w, sx, ctr, iters, its, train_iters=5, train_batches=16):
         at0 = [t for t in its if t == 0]
         return (2.0 * d * k * sum(int(ctr[t, 1]) for t in at0), len(at0),
                 "TFLOP/s", "mfma", mfma_peak)
-    if g == 1:     # survivor tile
+    if g == 1:     # survivor tile: all k per survivor, or with Clause 2 per block
+        # (FP32, 1024 <= k <= 8192) the survivor-candidate pairs it evaluated
+        # (the dists counter less the Clause-3 tightening distances)
+        if w.dtype == "f32" and 1024 <= k <= 8192:
+            pairs = sum(int(ctr[t, 7]) - (n - int(ctr[t, 2])) for t in after0)
+            return 2.0 * d * pairs, len(after0), "TFLOP/s", "mfma", mfma_peak
         return (2.0 * d * k * sum(int(ctr[t, 1]) for t in after0), len(after0),
                 "TFLOP/s", "mfma", mfma_peak)
     if g == 2:     # FP64 recheck: subtract, multiply, add per (point, centroid, dim)
@@ -160,12 +165,13 @@ def group_work(g, w, sx, ctr, iters, its, train_iters=5, train_batches=16):
     if g == 5:     # leaf sums: every row gathered once + perm + leaf sums out
         per_iter = n * d * sx + 4.0 * n + (n / 64.0 + k) * d * 8.0
         return per_iter * len(its), len(its), "GB/s", "hbm", PEAK_HBM
-    if g == 8:     # MLP on the BF16 matrix cores: forward of every query, and
-        # training (forward + two backward products ~ 3x forward per row)
+    if g == 8:     # MLP on the BF16 matrix cores: forward of every row that went
+        # through the network (a point's candidates are computed once per fit),
+        # and training (forward + two backward products ~ 3x forward per row)
         fwd = 2.0 * (d * MLP_H + MLP_H * MLP_H + MLP_H * k)
         tot, launches = 0.0, 0
         for t in its:
-            q = int(ctr[t, 6])
+            q = int(ctr[t, 8])
             tot += fwd * q
             if 1 <= t <= train_iters:
                 tot += 3.0 * fwd * MLP_BATCH * train_batches
@@ -426,6 +432,7 @@ def single_config(a, knor, oracle, workloads):
     if cfg == 5:
         out["certified_per_fit"] = st["certified"]
         out["mlp_queries_per_fit"] = st["mlp_queries"]
+        out["mlp_forward_rows_per_fit"] = st["mlp_forward_rows"]
     if m["cal_n"][0] and cfg != 1:
         fl = group_work(0, w, sx, ctr, iters, [0])[0]
         sec = m["cal_ms"][0] / m["cal_n"][0] / 1e3

@@ -208,10 +208,13 @@ enum {
   KNOR_CNT_PRUNED_B = 3,  /* MTI: decided after tightening the bound          */
   KNOR_CNT_RECHECKED = 4, /* points recomputed in FP64                        */
   KNOR_CNT_CERTIFIED = 5, /* survivors decided by a certified proposal        */
-  KNOR_CNT_QUERIED = 6,   /* survivors sent to the proposal MLP               */
+  KNOR_CNT_QUERIED = 6,   /* survivors that took a proposal (from the network
+                             or from their cached candidates)                */
   KNOR_CNT_DISTS = 7,     /* point-centroid distances evaluated (tiles, FP64
                              rechecks, Clause-3 tightening)                   */
-  KNOR_NCOUNTERS = 8
+  KNOR_CNT_FORWARD = 8,   /* survivors whose proposal was computed: a point
+                             goes through the network at most once per fit */
+  KNOR_NCOUNTERS = 9
 };
 
 typedef struct {
@@ -227,7 +230,8 @@ typedef struct {
                              labels and the centroids they were assigned to  */
   double seconds;         /* wall time of the call                           */
   int64_t certified;      /* sum of KNOR_CNT_CERTIFIED                       */
-  int64_t mlp_queries;    /* survivors sent to the proposal MLP              */
+  int64_t mlp_queries;    /* sum of KNOR_CNT_QUERIED                         */
+  int64_t mlp_forward_rows; /* sum of KNOR_CNT_FORWARD                       */
 } knor_stats;
 
 /* knor_fit: Lloyd's algorithm (Sections "Introduction", "Parallel Lloyd's

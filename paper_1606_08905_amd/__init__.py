@@ -30,9 +30,9 @@ KNOR_OK, KNOR_ERR_INVALID_ARG, KNOR_ERR_OUT_OF_MEMORY, KNOR_ERR_HIP, \
 INIT_GIVEN, INIT_FORGY, INIT_SHUFFLE_FIRSTK, INIT_KMEANSPP = 0, 1, 2, 3
 INITS = {"given": INIT_GIVEN, "forgy": INIT_FORGY,
          "shuffle_first_k": INIT_SHUFFLE_FIRSTK, "kmeans++": INIT_KMEANSPP}
-NCOUNTERS = 8
+NCOUNTERS = 9
 COUNTERS = ("changed", "scanned", "pruned_a", "pruned_b", "rechecked",
-            "certified", "queried", "dists")
+            "certified", "queried", "dists", "forward")
 CLAUSE2 = {"auto": 0, "off": 1, "on": 2}
 
 
@@ -87,7 +87,8 @@ class Stats(ctypes.Structure):
                 ("scanned", ctypes.c_int64), ("pruned_a", ctypes.c_int64),
                 ("pruned_b", ctypes.c_int64), ("rechecked", ctypes.c_int64),
                 ("objective", ctypes.c_double), ("seconds", ctypes.c_double),
-                ("certified", ctypes.c_int64), ("mlp_queries", ctypes.c_int64)]
+                ("certified", ctypes.c_int64), ("mlp_queries", ctypes.c_int64),
+                ("mlp_forward_rows", ctypes.c_int64)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -253,7 +254,7 @@ def fit(X, k, C0=None, init="given", max_iters=100, tol=0.0, prune=True,
     the labels each iteration's assignment produced; centroid_history=True
     adds stats["centroid_history"]: (iters, k, d) float64 CUDA tensor of the
     centroids each iteration's assignment used.  counters=True adds
-    stats["counters"]: (iters, 8) int64 numpy array (KNOR_CNT_* columns).
+    stats["counters"]: (iters, 9) int64 numpy array (KNOR_CNT_* columns).
     objective_history=True adds stats["objective_history"]: (iters,) float64
     numpy array of J_t (the canonical-order sum of each point's FP64 distance
     to its iteration-t centroid, under the centroids iteration t used).

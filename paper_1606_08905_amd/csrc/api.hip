@@ -571,8 +571,13 @@ static bool cand_enabled(const Opts& o, knor_dtype dt, int k) {
 // or the candidate lists), and Clause-3 tightening.
 static void report_counters(const std::vector<unsigned long long>& hc, int hiters, int64_t n,
                             int k, bool mti, const std::vector<char>& cand_used,
-                            const std::vector<int64_t>& queried, int64_t* iter_counters,
+                            const std::vector<char>& proposed,
+                            const std::vector<int64_t>& forwarded, int64_t* iter_counters,
                             knor_stats* st) {
+  // survivors that took a proposal: every survivor of a proposal iteration
+  auto queried = [&](int i) {
+    return proposed[(size_t)i] ? (int64_t)hc[(size_t)i * ROW_STRIDE + ROW_SURVIVED] : 0;
+  };
   auto dists_of = [&](int i) {
     const unsigned long long* r = &hc[(size_t)i * ROW_STRIDE];
     const int64_t tighten = (mti && i > 0) ? (n - (int64_t)r[ROW_PRUNED_A]) : 0;
@@ -589,8 +594,9 @@ static void report_counters(const std::vector<unsigned long long>& hc, int hiter
       dst[KNOR_CNT_PRUNED_B] = (int64_t)r[ROW_PRUNED_B];
       dst[KNOR_CNT_RECHECKED] = (int64_t)r[ROW_FLAG_HEAD];
       dst[KNOR_CNT_CERTIFIED] = (int64_t)r[ROW_CERTIFIED];
-      dst[KNOR_CNT_QUERIED] = queried[(size_t)i];
+      dst[KNOR_CNT_QUERIED] = queried(i);
       dst[KNOR_CNT_DISTS] = dists_of(i);
+      dst[KNOR_CNT_FORWARD] = forwarded[(size_t)i];
     }
   if (st) {
     memset(st, 0, sizeof(*st));
@@ -604,6 +610,8 @@ static void report_counters(const std::vector<unsigned long long>& hc, int hiter
       st->rechecked += (int64_t)r[ROW_FLAG_HEAD];
       st->certified += (int64_t)r[ROW_CERTIFIED];
       st->dists_computed += dists_of(i);
+      st->mlp_queries += queried(i);
+      st->mlp_forward_rows += forwarded[(size_t)i];
     }
   }
 }
@@ -659,9 +667,11 @@ struct FitRun {
   double *mean = nullptr, *istd = nullptr, *loss_dev = nullptr, *stat_part = nullptr;
   void* pp_ws = nullptr;
   unsigned long long* pp_rnd = nullptr;
-  int64_t mlp_step = 0, mlp_queries = 0;
-  std::vector<int64_t> queried;                 // survivors sent to the MLP
+  int64_t mlp_step = 0;
+  std::vector<char> proposed;                   // survivors took a proposal
+  std::vector<int64_t> forwarded;               // rows through the forward pass
   std::vector<char> cand_used;                  // candidate-list tile ran
+  int* seg_new = nullptr;                       // per segment: unproposed survivors
   bool packed = false;
   Prof prof;
   Prof* pp = nullptr;
@@ -735,6 +745,7 @@ struct FitRun {
       ar.add((void**)&list2, sizeof(int) * (size_t)nseg * kSeg);
       ar.add((void**)&seg_cnt2, sizeof(int) * (size_t)nseg);
       ar.add((void**)&cand, sizeof(int32_t) * (size_t)n * kMlpTop);
+      ar.add((void**)&seg_new, sizeof(int) * (size_t)nseg);
     }
     if (init == KNOR_INIT_KMEANSPP) {
       ar.add(&pp_ws, kmeanspp_workspace_bytes(n, k));
@@ -796,9 +807,11 @@ struct FitRun {
                             hipMemcpyHostToDevice, s));
       HIPCHK(hipMemsetAsync(am, 0, sizeof(float) * (size_t)ML.P, s));
       HIPCHK(hipMemsetAsync(av, 0, sizeof(float) * (size_t)ML.P, s));
+      HIPCHK(launch_fill_i32(cand, n * kMlpTop, kUnproposed, s));
       HIPCHK(hipStreamSynchronize(s));          // `th0` leaves scope
     }
-    queried.assign((size_t)max_iters, 0);
+    proposed.assign((size_t)max_iters, 0);
+    forwarded.assign((size_t)max_iters, 0);
     cand_used.assign((size_t)max_iters, 0);
 
     prof.stream = s;
@@ -839,22 +852,24 @@ struct FitRun {
         HIPCHK(launch_mlp_pack(th, ML, MP, s));
         packed = true;
       }
-      HIPCHK(launch_seg_dense(list, seg_cnt, nseg, seg_off, dense, conv, t, s));
+      // only survivors that were never proposed for go through the network:
+      // a point's candidates do not change once training is over
+      HIPCHK(launch_seg_unproposed(list, seg_cnt, nseg, cand, seg_new, seg_off, dense, conv,
+                                   t, s));
       int hm[2] = {0, 0};
       HIPCHK(hipMemcpyAsync(&hm[0], seg_off + nseg, sizeof(int), hipMemcpyDeviceToHost, s));
       HIPCHK(hipMemcpyAsync(&hm[1], conv, sizeof(int), hipMemcpyDeviceToHost, s));
       HIPCHK(hipStreamSynchronize(s));
       if (hm[1] == kNotConverged) {
-        const int m_tot = hm[0];
-        mlp_queries += m_tot;
-        queried[t] = m_tot;
-        HIPCHK(launch_mlp_forward(X, dt, d, dense, m_tot, nullptr, mean, istd, th, ML, MP,
-                                  cand, s));
+        const int m_new = hm[0];
+        proposed[t] = 1;
+        forwarded[t] = m_new;
+        HIPCHK(launch_mlp_forward(X, dt, d, dense, m_new, nullptr, mean, istd, th, ML, MP,
+                                  cand, dense, s));
         prof.end();
         prof.begin(KNOR_PROF_CERTIFY);
-        HIPCHK(launch_mlp_certify(X, dt, d, C_out, k, ccrows, list, seg_cnt, seg_off,
-                                  nseg, cand, labels_out, u, dirty, list2, seg_cnt2, row,
-                                  conv, t, s));
+        HIPCHK(launch_mlp_certify(X, dt, d, C_out, k, ccrows, list, seg_cnt, nseg, cand,
+                                  labels_out, u, dirty, list2, seg_cnt2, row, conv, t, s));
         job.list = list2;
         job.seg_cnt = seg_cnt2;
       }
@@ -965,10 +980,9 @@ struct FitRun {
       HIPCHK(hipStreamSynchronize(s));
     }
 
-    report_counters(hc, hiters, n, k, mti, cand_used, queried, o.iter_counters, st);
+    report_counters(hc, hiters, n, k, mti, cand_used, proposed, forwarded, o.iter_counters, st);
     if (st) {
       st->converged = converged;
-      st->mlp_queries = mlp_queries;
       st->objective = hobj;
       st->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     }
@@ -1158,7 +1172,7 @@ knor_status knor_mlp_propose(const float* params, int32_t d, int32_t h,
   HIPCHK(launch_mlp_pack(params, L, P, s));
   // Xs is already standardized: no row list, no mean / scale
   HIPCHK(launch_mlp_forward(Xs, KNOR_F32, d, nullptr, (int)m, nullptr, nullptr, nullptr,
-                            params, L, P, cand_out, s));
+                            params, L, P, cand_out, nullptr, s));
   return KNOR_OK;
 }
 
@@ -1727,9 +1741,9 @@ static knor_status fit_streamed_impl(const void* X, const void* Xd, knor_dtype d
       dst[KNOR_IO_CACHED] = (int64_t)r[2];
       dst[KNOR_IO_ADMITTED] = (int64_t)r[3];
     }
-  std::vector<char> cand_used((size_t)max_iters, 0);
-  std::vector<int64_t> queried((size_t)max_iters, 0);
-  report_counters(hc, hiters, n, k, mti, cand_used, queried, o.iter_counters, st);
+  std::vector<char> cand_used((size_t)max_iters, 0), proposed((size_t)max_iters, 0);
+  std::vector<int64_t> forwarded((size_t)max_iters, 0);
+  report_counters(hc, hiters, n, k, mti, cand_used, proposed, forwarded, o.iter_counters, st);
   if (st) {
     st->converged = converged;
     st->objective = hobj;

@@ -525,7 +525,10 @@ struct GemmArgs {
   int relu;
   const float* mask; int ldm;
 };
-hipError_t launch_gemm_bf16(const GemmArgs& g, hipStream_t s);
+// part: FP32 workspace of gemm_split_floats(M, N, K) floats for split-K
+// partials, or null (no split)
+hipError_t launch_gemm_bf16(const GemmArgs& g, float* part, hipStream_t s);
+size_t gemm_split_floats(int M, int N, int K);
 
 // The proposal MLP d -> h -> h -> k: offsets of W1 (d x h), b1, W2 (h x h),
 // b2, W3 (h x k), b3 in the flat FP32 parameter vector of P entries.
@@ -557,20 +560,27 @@ hipError_t launch_mlp_pack(const float* th, const MlpLayout& L, const MlpPacked&
 hipError_t launch_mlp_forward(const void* X, knor_dtype dt, int d, const int* rows, int m,
                               const int* mdev, const double* mean, const double* istd,
                               const float* th, const MlpLayout& L, const MlpPacked& P,
-                              int32_t* cand, hipStream_t s);
+                              int32_t* cand, const int* outpos, hipStream_t s);
 size_t standardize_workspace(int d);
 hipError_t launch_standardize_stats(const void* X, knor_dtype dt, int64_t n, int d,
                                     double* mean, double* istd, double* part, hipStream_t s);
 hipError_t launch_gather_std(const void* X, knor_dtype dt, int d, const int* rows,
                              int64_t count, const int* cdev, const double* mean,
                              const double* istd, float* Xs, hipStream_t s);
-hipError_t launch_seg_dense(const int* list, const int* seg_cnt, int nseg, int* seg_off,
-                            int* dense, const int* conv, int iter, hipStream_t s);
 constexpr int kMlpTop = 16;          // candidates per point
+// Inside a fit the proposals are kept per point: row p of cand (16 ints)
+// starts as kUnproposed and holds p's candidates once p has been through the
+// forward pass (the trained network and p's input are fixed from then on).
+constexpr int32_t kUnproposed = -2;
+// Survivors without a proposal yet: cnt_new (per segment), seg_off (their
+// exclusive prefix, total at seg_off[nseg]) and their point indices in dense.
+hipError_t launch_seg_unproposed(const int* list, const int* seg_cnt, int nseg,
+                                 const int32_t* cand, int* cnt_new, int* seg_off, int* dense,
+                                 const int* conv, int iter, hipStream_t s);
 // nrows: the k x k neighbour rows of launch_cc_bounds
 hipError_t launch_mlp_certify(const void* X, knor_dtype dt, int d, const double* C64,
                               int k, const float* nrows, const int* list,
-                              const int* seg_cnt, const int* seg_off, int nseg,
+                              const int* seg_cnt, int nseg,
                               const int32_t* cand, int32_t* labels, float* u, int* dirty,
                               int* list2, int* seg_cnt2, unsigned long long* row,
                               const int* conv, int iter, hipStream_t s);

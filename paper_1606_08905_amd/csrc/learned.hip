@@ -18,12 +18,12 @@
 // are FP32.  Training (softmax cross-entropy, Adam) uses FP32 master
 // weights; gradients of the biases, softmax and Adam are FP32.
 //
-// Proposal rule: the k classes are split into 16 fixed subsets -- class j
-// belongs to subset 4 ((j mod 16) div 4) + ((j div 16) mod 4) -- and the
-// candidates are the 16 subset-wise largest logits, which include the
-// overall largest.  Each lane of the output tile owns one subset of its
-// point's classes, so the selection is one compare and two selects per
-// logit in the matrix-core epilogue.
+// Proposal rule: the 16 classes with the largest keys, where a class's key
+// is its FP32 logit with the low mantissa bits replaced by a code of the
+// class index (value and class in one sortable float).  Each lane of the
+// output tile keeps the largest keys of its share of the point's classes in
+// a sorted list (median-of-three insertion), and the four lanes of a point
+// merge their lists through LDS.
 #include <math.h>
 
 #include <vector>
@@ -45,84 +45,230 @@ __device__ __forceinline__ uint16_t f32_bf16_rne(float f) {
 // generic GEMM: C[M x N] = op(A)[M x K] op(B)[K x N] (+ bias[N]) (ReLU)
 // (masked by mask > 0); op = transpose when the flag is set
 // ---------------------------------------------------------------------------
+//
+// A workgroup of 4 waves computes a 128 x 128 tile of C, each wave 64 x 64
+// (4 x 4 blocks of v_mfma_f32_16x16x32_bf16).  Per K-step of 32 the
+// operands are read from global memory as 16-byte FP32 pieces along their
+// contiguous dimension, rounded to BF16 and stored in LDS with K
+// contiguous (both operands), double-buffered: the next step's pieces are
+// loaded into registers while the current step's MFMAs run, one barrier per
+// step.  Long K with few output tiles is split over blockIdx.z; the splits
+// write FP32 partial tiles and a second kernel adds them in split order and
+// applies the epilogue, so the result does not depend on scheduling.
 
-constexpr int kGT = 64;            // output tile rows and columns
+constexpr int kGT = 128;           // output tile rows and columns
 constexpr int kGK = 32;            // K-step
 constexpr int kGLD = kGK + 8;      // LDS row stride (bf16), 16-byte aligned
+constexpr int kGTargetWG = 1024;   // split K until about this many workgroups
+constexpr int kGMaxSplit = 16;
 
-__global__ __launch_bounds__(256) void gemm_bf16_kernel(GemmArgs g) {
-  __shared__ __attribute__((aligned(16))) uint16_t sA[kGT * kGLD];
-  __shared__ __attribute__((aligned(16))) uint16_t sB[kGT * kGLD];
+// The K range of split z of ksplit (multiples of kGK).
+__device__ __forceinline__ void split_range(int K, int ksplit, int z, int& kb, int& ke) {
+  const int steps = (K + kGK - 1) / kGK;
+  const int per = (steps + ksplit - 1) / ksplit;
+  kb = z * per * kGK;
+  ke = (z + 1) * per * kGK < K ? (z + 1) * per * kGK : K;
+}
+
+// four consecutive elements p[0..3] that lie in [0, lim): one 16-byte load
+// when all do and p is 16-byte aligned, else element by element (zeros past
+// the limit)
+__device__ __forceinline__ float4 load4(const float* p, int lim, bool vec) {
+  if (vec && lim >= 4) return *reinterpret_cast<const float4*>(p);
+  float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+  if (lim > 0) v.x = p[0];
+  if (lim > 1) v.y = p[1];
+  if (lim > 2) v.z = p[2];
+  if (lim > 3) v.w = p[3];
+  return v;
+}
+
+template <bool TA, bool TB>
+__global__ __launch_bounds__(256) void gemm_bf16_kernel(GemmArgs g, int ksplit,
+                                                        float* __restrict__ part) {
+  __shared__ __attribute__((aligned(16))) uint16_t sA[2][kGT * kGLD];
+  __shared__ __attribute__((aligned(16))) uint16_t sB[2][kGT * kGLD];
   const int M = g.Mdev ? (g.M < *g.Mdev ? g.M : *g.Mdev) : g.M;
+  const int N = g.N, K = g.K;
   const int m0 = blockIdx.y * kGT, n0 = blockIdx.x * kGT;
   if (m0 >= M) return;
+  int kb, ke;
+  split_range(K, ksplit, blockIdx.z, kb, ke);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wr = wave >> 1, wc = wave & 1, col = lane & 15, grp = lane >> 4;
-  f4l acc[2][2];
+  const bool va = (g.lda & 3) == 0 && ((uintptr_t)g.A & 15) == 0;
+  const bool vb = (g.ldb & 3) == 0 && ((uintptr_t)g.B & 15) == 0;
+  // piece i of this thread: f = tid + 256 i.  Along K (A plain, B
+  // transposed): row f / 8, K offset 4 (f mod 8).  Along M or N (A
+  // transposed, B plain): K offset f / 32, rows or columns 4 (f mod 32).
+  float4 ra[4], rb[4];
+  auto load = [&](int k0) {
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
-#pragma unroll
-    for (int b = 0; b < 2; ++b) acc[a][b] = f4l{0.f, 0.f, 0.f, 0.f};
-  for (int k0 = 0; k0 < g.K; k0 += kGK) {
-#pragma unroll
-    for (int i = 0; i < (kGT * kGK) / 256; ++i) {
-      const int e = tid + 256 * i;
-      int r, kk;
-      if (!g.transA) { r = e / kGK; kk = e % kGK; } else { kk = e / kGT; r = e % kGT; }
-      const int row = m0 + r, kx = k0 + kk;
-      float v = 0.0f;
-      if (row < M && kx < g.K)
-        v = g.transA ? g.A[(size_t)kx * g.lda + row] : g.A[(size_t)row * g.lda + kx];
-      sA[r * kGLD + kk] = f32_bf16_rne(v);
+    for (int i = 0; i < 4; ++i) {
+      const int f = tid + 256 * i;
+      if (!TA) {
+        const int r = f >> 3, kk = 4 * (f & 7);
+        const int row = m0 + r, kx = k0 + kk;
+        ra[i] = row < M ? load4(g.A + (size_t)row * g.lda + kx, ke - kx, va)
+                        : make_float4(0.f, 0.f, 0.f, 0.f);
+      } else {
+        const int kk = f >> 5, r = 4 * (f & 31);
+        const int row = m0 + r, kx = k0 + kk;
+        ra[i] = kx < ke ? load4(g.A + (size_t)kx * g.lda + row, M - row, va)
+                        : make_float4(0.f, 0.f, 0.f, 0.f);
+      }
+      if (TB) {
+        const int c = f >> 3, kk = 4 * (f & 7);
+        const int cn = n0 + c, kx = k0 + kk;
+        rb[i] = cn < N ? load4(g.B + (size_t)cn * g.ldb + kx, ke - kx, vb)
+                       : make_float4(0.f, 0.f, 0.f, 0.f);
+      } else {
+        const int kk = f >> 5, c = 4 * (f & 31);
+        const int cn = n0 + c, kx = k0 + kk;
+        rb[i] = kx < ke ? load4(g.B + (size_t)kx * g.ldb + cn, N - cn, vb)
+                        : make_float4(0.f, 0.f, 0.f, 0.f);
+      }
     }
+  };
+  auto store = [&](int buf) {
+    uint16_t* a = sA[buf];
+    uint16_t* b = sB[buf];
 #pragma unroll
-    for (int i = 0; i < (kGT * kGK) / 256; ++i) {
-      const int e = tid + 256 * i;
-      int c, kk;
-      if (!g.transB) { kk = e / kGT; c = e % kGT; } else { c = e / kGK; kk = e % kGK; }
-      const int cn = n0 + c, kx = k0 + kk;
-      float v = 0.0f;
-      if (cn < g.N && kx < g.K)
-        v = g.transB ? g.B[(size_t)cn * g.ldb + kx] : g.B[(size_t)kx * g.ldb + cn];
-      sB[c * kGLD + kk] = f32_bf16_rne(v);
+    for (int i = 0; i < 4; ++i) {
+      const int f = tid + 256 * i;
+      const uint16_t x0 = f32_bf16_rne(ra[i].x), x1 = f32_bf16_rne(ra[i].y);
+      const uint16_t x2 = f32_bf16_rne(ra[i].z), x3 = f32_bf16_rne(ra[i].w);
+      if (!TA) {
+        const int r = f >> 3, kk = 4 * (f & 7);
+        *reinterpret_cast<uint2*>(&a[r * kGLD + kk]) =
+            make_uint2((uint32_t)x0 | ((uint32_t)x1 << 16), (uint32_t)x2 | ((uint32_t)x3 << 16));
+      } else {
+        const int kk = f >> 5, r = 4 * (f & 31);
+        a[(r + 0) * kGLD + kk] = x0;
+        a[(r + 1) * kGLD + kk] = x1;
+        a[(r + 2) * kGLD + kk] = x2;
+        a[(r + 3) * kGLD + kk] = x3;
+      }
+      const uint16_t y0 = f32_bf16_rne(rb[i].x), y1 = f32_bf16_rne(rb[i].y);
+      const uint16_t y2 = f32_bf16_rne(rb[i].z), y3 = f32_bf16_rne(rb[i].w);
+      if (TB) {
+        const int c = f >> 3, kk = 4 * (f & 7);
+        *reinterpret_cast<uint2*>(&b[c * kGLD + kk]) =
+            make_uint2((uint32_t)y0 | ((uint32_t)y1 << 16), (uint32_t)y2 | ((uint32_t)y3 << 16));
+      } else {
+        const int kk = f >> 5, c = 4 * (f & 31);
+        b[(c + 0) * kGLD + kk] = y0;
+        b[(c + 1) * kGLD + kk] = y1;
+        b[(c + 2) * kGLD + kk] = y2;
+        b[(c + 3) * kGLD + kk] = y3;
+      }
     }
-    __syncthreads();
-    bf8l a[2], b[2];
+  };
+  f4l acc[4][4];
 #pragma unroll
-    for (int rb = 0; rb < 2; ++rb)
-      a[rb] = *reinterpret_cast<const bf8l*>(&sA[(wr * 32 + rb * 16 + col) * kGLD + grp * 8]);
+  for (int x = 0; x < 4; ++x)
 #pragma unroll
-    for (int cb = 0; cb < 2; ++cb)
-      b[cb] = *reinterpret_cast<const bf8l*>(&sB[(wc * 32 + cb * 16 + col) * kGLD + grp * 8]);
-#pragma unroll
-    for (int rb = 0; rb < 2; ++rb)
-#pragma unroll
-      for (int cb = 0; cb < 2; ++cb)
-        acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[rb], b[cb], acc[rb][cb], 0, 0, 0);
-    __syncthreads();
+    for (int y = 0; y < 4; ++y) acc[x][y] = f4l{0.f, 0.f, 0.f, 0.f};
+  int buf = 0;
+  if (kb < ke) {
+    load(kb);
+    store(0);
   }
+  __syncthreads();
+  for (int k0 = kb; k0 < ke; k0 += kGK) {
+    const bool more = k0 + kGK < ke;
+    if (more) load(k0 + kGK);                  // in flight during the MFMAs
+    bf8l av[4], bv[4];
 #pragma unroll
-  for (int rb = 0; rb < 2; ++rb)
+    for (int x = 0; x < 4; ++x)
+      av[x] = *reinterpret_cast<const bf8l*>(&sA[buf][(wr * 64 + x * 16 + col) * kGLD + grp * 8]);
 #pragma unroll
-    for (int cb = 0; cb < 2; ++cb)
+    for (int y = 0; y < 4; ++y)
+      bv[y] = *reinterpret_cast<const bf8l*>(&sB[buf][(wc * 64 + y * 16 + col) * kGLD + grp * 8]);
+#pragma unroll
+    for (int x = 0; x < 4; ++x)
+#pragma unroll
+      for (int y = 0; y < 4; ++y)
+        acc[x][y] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[x], bv[y], acc[x][y], 0, 0, 0);
+    if (more) store(buf ^ 1);
+    __syncthreads();
+    buf ^= 1;
+  }
+  float* out = ksplit > 1 ? part + (size_t)blockIdx.z * g.M * N : nullptr;
+#pragma unroll
+  for (int x = 0; x < 4; ++x)
+#pragma unroll
+    for (int y = 0; y < 4; ++y)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int row = m0 + wr * 32 + rb * 16 + 4 * grp + r;
-        const int cn = n0 + wc * 32 + cb * 16 + col;
-        if (row < M && cn < g.N) {
-          float v = acc[rb][cb][r];
-          if (g.bias) v += g.bias[cn];
-          if (g.relu) v = v > 0.0f ? v : 0.0f;
-          if (g.mask) v = g.mask[(size_t)row * g.ldm + cn] > 0.0f ? v : 0.0f;
-          g.C[(size_t)row * g.ldc + cn] = v;
+        const int row = m0 + wr * 64 + x * 16 + 4 * grp + r;
+        const int cn = n0 + wc * 64 + y * 16 + col;
+        if (row < M && cn < N) {
+          float v = acc[x][y][r];
+          if (out) {
+            out[(size_t)row * N + cn] = v;
+          } else {
+            if (g.bias) v += g.bias[cn];
+            if (g.relu) v = v > 0.0f ? v : 0.0f;
+            if (g.mask) v = g.mask[(size_t)row * g.ldm + cn] > 0.0f ? v : 0.0f;
+            g.C[(size_t)row * g.ldc + cn] = v;
+          }
         }
       }
 }
 
-hipError_t launch_gemm_bf16(const GemmArgs& g, hipStream_t s) {
+// The split partials added in split order, then the epilogue.
+__global__ __launch_bounds__(256) void gemm_split_sum_kernel(GemmArgs g, int ksplit,
+                                                             const float* __restrict__ part) {
+  const int M = g.Mdev ? (g.M < *g.Mdev ? g.M : *g.Mdev) : g.M;
+  const int64_t MN = (int64_t)M * g.N, stride = (int64_t)g.M * g.N;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < MN;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int row = (int)(e / g.N), cn = (int)(e - (int64_t)row * g.N);
+    float v = 0.0f;
+    for (int z = 0; z < ksplit; ++z) v += part[(size_t)z * stride + e];
+    if (g.bias) v += g.bias[cn];
+    if (g.relu) v = v > 0.0f ? v : 0.0f;
+    if (g.mask) v = g.mask[(size_t)row * g.ldm + cn] > 0.0f ? v : 0.0f;
+    g.C[(size_t)row * g.ldc + cn] = v;
+  }
+}
+
+// Splits of K for an M x N x K product: enough workgroups to fill the chip
+// when the output has few tiles, each split at least 256 deep.
+static int gemm_splits(int M, int N, int K) {
+  const int tiles = ((M + kGT - 1) / kGT) * ((N + kGT - 1) / kGT);
+  int sp = (kGTargetWG + tiles - 1) / tiles;
+  const int kmax = K / 256 > 1 ? K / 256 : 1;
+  if (sp > kmax) sp = kmax;
+  if (sp > kGMaxSplit) sp = kGMaxSplit;
+  return sp < 1 ? 1 : sp;
+}
+
+size_t gemm_split_floats(int M, int N, int K) {
+  const int sp = gemm_splits(M, N, K);
+  return sp > 1 ? (size_t)sp * M * N : 0;
+}
+
+hipError_t launch_gemm_bf16(const GemmArgs& g, float* part, hipStream_t s) {
   if (g.M <= 0 || g.N <= 0) return hipSuccess;
-  dim3 grid((g.N + kGT - 1) / kGT, (g.M + kGT - 1) / kGT);
-  hipLaunchKernelGGL(gemm_bf16_kernel, grid, dim3(256), 0, s, g);
+  const int sp = part ? gemm_splits(g.M, g.N, g.K) : 1;
+  dim3 grid((g.N + kGT - 1) / kGT, (g.M + kGT - 1) / kGT, sp);
+  if (g.transA && g.transB)
+    hipLaunchKernelGGL((gemm_bf16_kernel<true, true>), grid, dim3(256), 0, s, g, sp, part);
+  else if (g.transA)
+    hipLaunchKernelGGL((gemm_bf16_kernel<true, false>), grid, dim3(256), 0, s, g, sp, part);
+  else if (g.transB)
+    hipLaunchKernelGGL((gemm_bf16_kernel<false, true>), grid, dim3(256), 0, s, g, sp, part);
+  else
+    hipLaunchKernelGGL((gemm_bf16_kernel<false, false>), grid, dim3(256), 0, s, g, sp, part);
+  if (sp > 1) {
+    const int64_t mn = (int64_t)g.M * g.N;
+    int64_t blocks = (mn + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(gemm_split_sum_kernel, dim3((unsigned)blocks), dim3(256), 0, s, g, sp,
+                       part);
+  }
   return hipGetLastError();
 }
 
@@ -278,10 +424,21 @@ std::vector<float> mlp_init_host(int d, int h, int k, uint64_t seed) {
   return th;
 }
 
+// split-K partials of the training products (the largest of them)
+static size_t train_split_floats(int d, int h, int k, int B) {
+  const size_t c[] = {gemm_split_floats(h, k, B), gemm_split_floats(B, h, k),
+                      gemm_split_floats(h, h, B), gemm_split_floats(d, h, B),
+                      gemm_split_floats(B, h, h), gemm_split_floats(B, k, h),
+                      gemm_split_floats(B, h, d)};
+  size_t m = 0;
+  for (size_t v : c) m = v > m ? v : m;
+  return m;
+}
+
 size_t mlp_train_workspace(int d, int h, int k, int B) {
-  (void)d;
   return sizeof(float) * ((size_t)B * h * 4 + (size_t)B * k) + sizeof(double) * ((size_t)B + 1) +
-         sizeof(float) * (size_t)kColRB * (k > h ? k : h) + 8192;
+         sizeof(float) * (size_t)kColRB * (k > h ? k : h) +
+         sizeof(float) * train_split_floats(d, h, k, B) + 8192;
 }
 
 // One minibatch: forward, softmax cross-entropy, backward into grad, Adam
@@ -300,6 +457,9 @@ hipError_t mlp_train_step(float* th, float* am, float* av, int64_t step,
   double* lrow = (double*)c; c += sizeof(double) * ((size_t)B + 1);
   c = (char*)(((uintptr_t)c + 255) & ~(uintptr_t)255);
   float* cpart = (float*)c;
+  c += sizeof(float) * (size_t)kColRB * (k > h ? k : h);
+  c = (char*)(((uintptr_t)c + 255) & ~(uintptr_t)255);
+  float* gpart = train_split_floats(d, h, k, B) ? (float*)c : nullptr;
   hipError_t e;
   auto gemm = [&](const float* A, int lda, int tA, const float* Bm, int ldb, int tB,
                   float* C, int ldc, int M, int N, int K, const float* bias, int relu,
@@ -308,7 +468,7 @@ hipError_t mlp_train_step(float* th, float* am, float* av, int64_t step,
     g.A = A; g.lda = lda; g.transA = tA; g.B = Bm; g.ldb = ldb; g.transB = tB;
     g.C = C; g.ldc = ldc; g.M = M; g.N = N; g.K = K; g.bias = bias; g.relu = relu;
     g.mask = mask; g.ldm = ldm;
-    return launch_gemm_bf16(g, s);
+    return launch_gemm_bf16(g, gpart, s);
   };
   // forward
   if ((e = gemm(Xs, d, 0, th + L.W1, h, 0, H1, h, B, h, d, th + L.b1, 1, nullptr, 0))) return e;
@@ -737,7 +897,7 @@ template <int KD, int KH, typename T>
 static hipError_t fwd_launch(const T* X, int d, const int* rows, int m, const int* mdev,
                              const double* mean, const double* istd, const float* th,
                              const MlpLayout& L, const MlpPacked& P, int32_t* cand,
-                             hipStream_t s) {
+                             const int* outpos, hipStream_t s) {
   constexpr int LD = 32 * KH + 8;
   const size_t lds_w = sizeof(uint16_t) * 2 * kFwdRows * LD;
   const size_t lds_k = sizeof(float) * kFwdWaves * kFwdPB * 16 * 4 * 16;
@@ -756,7 +916,7 @@ static hipError_t fwd_launch(const T* X, int d, const int* rows, int m, const in
   hipLaunchKernelGGL((mlp_forward_kernel<KD, KH, kFwdList, T>), dim3(grid), dim3(64 * kFwdWaves),
                      lds, s, X, d, rows, m, mdev, mean, istd, P.W1b, th + L.b1, P.W2b,
                      th + L.b2, P.W3b, P.b3p, L.k, P.kpad, code_bits(P.kpad), cand,
-                     (const int*)nullptr, P.fl_rows, P.fl_pos, P.fl_cnt);
+                     outpos, P.fl_rows, P.fl_pos, P.fl_cnt);
   hipLaunchKernelGGL((mlp_forward_kernel<KD, KH, 16, T>), dim3(grid), dim3(64 * kFwdWaves),
                      lds, s, X, d, (const int*)P.fl_rows, m, (const int*)P.fl_cnt, mean, istd,
                      P.W1b, th + L.b1, P.W2b, th + L.b2, P.W3b, P.b3p, L.k, P.kpad,
@@ -768,12 +928,17 @@ static hipError_t fwd_launch(const T* X, int d, const int* rows, int m, const in
 template <int KD, typename T>
 static hipError_t fwd_kh(const T* X, int d, const int* rows, int m, const int* mdev,
                          const double* mean, const double* istd, const float* th,
-                         const MlpLayout& L, const MlpPacked& P, int32_t* cand, hipStream_t s) {
+                         const MlpLayout& L, const MlpPacked& P, int32_t* cand,
+                         const int* outpos, hipStream_t s) {
   switch (L.h) {
-    case 32: return fwd_launch<KD, 1, T>(X, d, rows, m, mdev, mean, istd, th, L, P, cand, s);
-    case 64: return fwd_launch<KD, 2, T>(X, d, rows, m, mdev, mean, istd, th, L, P, cand, s);
-    case 128: return fwd_launch<KD, 4, T>(X, d, rows, m, mdev, mean, istd, th, L, P, cand, s);
-    case 256: return fwd_launch<KD, 8, T>(X, d, rows, m, mdev, mean, istd, th, L, P, cand, s);
+    case 32:
+      return fwd_launch<KD, 1, T>(X, d, rows, m, mdev, mean, istd, th, L, P, cand, outpos, s);
+    case 64:
+      return fwd_launch<KD, 2, T>(X, d, rows, m, mdev, mean, istd, th, L, P, cand, outpos, s);
+    case 128:
+      return fwd_launch<KD, 4, T>(X, d, rows, m, mdev, mean, istd, th, L, P, cand, outpos, s);
+    case 256:
+      return fwd_launch<KD, 8, T>(X, d, rows, m, mdev, mean, istd, th, L, P, cand, outpos, s);
   }
   return hipErrorInvalidValue;
 }
@@ -781,12 +946,13 @@ static hipError_t fwd_kh(const T* X, int d, const int* rows, int m, const int* m
 template <typename T>
 static hipError_t fwd_kd(const T* X, int d, const int* rows, int m, const int* mdev,
                          const double* mean, const double* istd, const float* th,
-                         const MlpLayout& L, const MlpPacked& P, int32_t* cand, hipStream_t s) {
+                         const MlpLayout& L, const MlpPacked& P, int32_t* cand,
+                         const int* outpos, hipStream_t s) {
   switch (P.KP1 / 32) {
-    case 1: return fwd_kh<1, T>(X, d, rows, m, mdev, mean, istd, th, L, P, cand, s);
-    case 2: return fwd_kh<2, T>(X, d, rows, m, mdev, mean, istd, th, L, P, cand, s);
-    case 4: return fwd_kh<4, T>(X, d, rows, m, mdev, mean, istd, th, L, P, cand, s);
-    case 8: return fwd_kh<8, T>(X, d, rows, m, mdev, mean, istd, th, L, P, cand, s);
+    case 1: return fwd_kh<1, T>(X, d, rows, m, mdev, mean, istd, th, L, P, cand, outpos, s);
+    case 2: return fwd_kh<2, T>(X, d, rows, m, mdev, mean, istd, th, L, P, cand, outpos, s);
+    case 4: return fwd_kh<4, T>(X, d, rows, m, mdev, mean, istd, th, L, P, cand, outpos, s);
+    case 8: return fwd_kh<8, T>(X, d, rows, m, mdev, mean, istd, th, L, P, cand, outpos, s);
   }
   return hipErrorInvalidValue;
 }
@@ -794,16 +960,18 @@ static hipError_t fwd_kd(const T* X, int d, const int* rows, int m, const int* m
 hipError_t launch_mlp_forward(const void* X, knor_dtype dt, int d, const int* rows, int m,
                               const int* mdev, const double* mean, const double* istd,
                               const float* th, const MlpLayout& L, const MlpPacked& P,
-                              int32_t* cand, hipStream_t s) {
+                              int32_t* cand, const int* outpos, hipStream_t s) {
   if (m <= 0) return hipSuccess;
   switch (dt) {
     case KNOR_F32:
-      return fwd_kd<float>((const float*)X, d, rows, m, mdev, mean, istd, th, L, P, cand, s);
+      return fwd_kd<float>((const float*)X, d, rows, m, mdev, mean, istd, th, L, P, cand,
+                           outpos, s);
     case KNOR_F64:
-      return fwd_kd<double>((const double*)X, d, rows, m, mdev, mean, istd, th, L, P, cand, s);
+      return fwd_kd<double>((const double*)X, d, rows, m, mdev, mean, istd, th, L, P, cand,
+                            outpos, s);
     case KNOR_BF16:
       return fwd_kd<uint16_t>((const uint16_t*)X, d, rows, m, mdev, mean, istd, th, L, P, cand,
-                              s);
+                              outpos, s);
   }
   return hipErrorInvalidValue;
 }
@@ -955,24 +1123,50 @@ __global__ __launch_bounds__(1024) void seg_scan_kernel(const int* __restrict__ 
   if (threadIdx.x == 1023) seg_off[nseg] = part[1023];
 }
 
-__global__ __launch_bounds__(256) void seg_dense_kernel(const int* __restrict__ list,
-                                                        const int* __restrict__ seg_cnt,
-                                                        const int* __restrict__ seg_off,
-                                                        int* __restrict__ dense,
-                                                        const int* __restrict__ conv,
-                                                        int iter) {
+// Survivors of segment b that have no proposal yet (cand[p][0] ==
+// kUnproposed): their count (count pass) or, at seg_off[b] on, their point
+// indices (order within a segment is immaterial: each output row lands at
+// its point's own candidate slots).
+template <bool WRITE>
+__global__ __launch_bounds__(256) void seg_unproposed_kernel(
+    const int* __restrict__ list, const int* __restrict__ seg_cnt,
+    const int32_t* __restrict__ cand, int* __restrict__ cnt_new,
+    const int* __restrict__ seg_off, int* __restrict__ dense,
+    const int* __restrict__ conv, int iter) {
+  __shared__ int run;
   if (*conv < iter) return;
   const int b = blockIdx.x;
-  const int cnt = seg_cnt[b], o = seg_off[b];
-  for (int q = threadIdx.x; q < cnt; q += 256) dense[o + q] = list[(size_t)b * kSeg + q];
+  const int cnt = seg_cnt[b];
+  if (threadIdx.x == 0) run = 0;
+  __syncthreads();
+  const int lane = threadIdx.x & 63;
+  const uint64_t lt = lanemask_lt();
+  for (int q0 = 0; q0 < cnt; q0 += 256) {
+    const int q = q0 + (int)threadIdx.x;
+    const int p = q < cnt ? list[(size_t)b * kSeg + q] : 0;
+    const bool fresh = q < cnt && cand[(size_t)p * kMlpTop] == kUnproposed;
+    const uint64_t m = __ballot(fresh);
+    if (m) {
+      const int leader = __ffsll((unsigned long long)m) - 1;
+      int base = 0;
+      if (lane == leader) base = atomicAdd(&run, __popcll(m));   // LDS
+      base = __shfl(base, leader);
+      if (WRITE && fresh) dense[seg_off[b] + base + __popcll(m & lt)] = p;
+    }
+  }
+  __syncthreads();
+  if (!WRITE && threadIdx.x == 0) cnt_new[b] = run;
 }
 
-hipError_t launch_seg_dense(const int* list, const int* seg_cnt, int nseg, int* seg_off,
-                            int* dense, const int* conv, int iter, hipStream_t s) {
-  hipLaunchKernelGGL(seg_scan_kernel, dim3(1), dim3(1024), 0, s, seg_cnt, nseg, seg_off,
+hipError_t launch_seg_unproposed(const int* list, const int* seg_cnt, int nseg,
+                                 const int32_t* cand, int* cnt_new, int* seg_off, int* dense,
+                                 const int* conv, int iter, hipStream_t s) {
+  hipLaunchKernelGGL(seg_unproposed_kernel<false>, dim3(nseg), dim3(256), 0, s, list, seg_cnt,
+                     cand, cnt_new, (const int*)nullptr, (int*)nullptr, conv, iter);
+  hipLaunchKernelGGL(seg_scan_kernel, dim3(1), dim3(1024), 0, s, cnt_new, nseg, seg_off,
                      conv, iter);
-  hipLaunchKernelGGL(seg_dense_kernel, dim3(nseg), dim3(256), 0, s, list, seg_cnt,
-                     seg_off, dense, conv, iter);
+  hipLaunchKernelGGL(seg_unproposed_kernel<true>, dim3(nseg), dim3(256), 0, s, list, seg_cnt,
+                     cand, cnt_new, (const int*)seg_off, dense, conv, iter);
   return hipGetLastError();
 }
 
@@ -997,14 +1191,14 @@ __global__ __launch_bounds__(256) void mlp_certify_kernel(
     const T* __restrict__ X, int d, const double* __restrict__ C64,
     int k, const float* __restrict__ nrows, int ib,
     const int* __restrict__ list, const int* __restrict__ seg_cnt,
-    const int* __restrict__ seg_off, const int32_t* __restrict__ cand,
+    const int32_t* __restrict__ cand,
     int32_t* __restrict__ labels, float* __restrict__ ub_out, int* __restrict__ dirty,
     int* __restrict__ list2, int* __restrict__ seg_cnt2,
     unsigned long long* __restrict__ row, const int* __restrict__ conv, int iter, int vec4) {
   __shared__ int run;
   if (*conv < iter) return;
   const int b = blockIdx.x;
-  const int cnt = seg_cnt[b], o = seg_off[b];
+  const int cnt = seg_cnt[b];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int ps = lane >> 4, cs = lane & 15;
   const uint64_t lt = lanemask_lt();
@@ -1015,7 +1209,7 @@ __global__ __launch_bounds__(256) void mlp_certify_kernel(
     const int q = q0 + ps;
     const bool live = q < cnt;
     const int p = live ? list[(size_t)b * kSeg + q] : 0;
-    const int j = live ? cand[(size_t)(o + q) * kMlpTop + cs] : -1;
+    const int j = live ? cand[(size_t)p * kMlpTop + cs] : -1;
     double D = INFINITY;
     if (j >= 0) {
       if constexpr (sizeof(T) == 4) {
@@ -1107,7 +1301,7 @@ __global__ __launch_bounds__(256) void mlp_certify_kernel(
 
 hipError_t launch_mlp_certify(const void* X, knor_dtype dt, int d, const double* C64,
                               int k, const float* nrows, const int* list,
-                              const int* seg_cnt, const int* seg_off, int nseg,
+                              const int* seg_cnt, int nseg,
                               const int32_t* cand, int32_t* labels, float* u, int* dirty,
                               int* list2, int* seg_cnt2, unsigned long long* row,
                               const int* conv, int iter, hipStream_t s) {
@@ -1115,17 +1309,17 @@ hipError_t launch_mlp_certify(const void* X, knor_dtype dt, int d, const double*
   switch (dt) {
     case KNOR_F32:
       hipLaunchKernelGGL(mlp_certify_kernel<float>, dim3(nseg), dim3(256), 0, s,
-                         (const float*)X, d, C64, k, nrows, cc_rows_bits(k), list, seg_cnt, seg_off,
+                         (const float*)X, d, C64, k, nrows, cc_rows_bits(k), list, seg_cnt,
                          cand, labels, u, dirty, list2, seg_cnt2, row, conv, iter, vec4);
       break;
     case KNOR_F64:
       hipLaunchKernelGGL(mlp_certify_kernel<double>, dim3(nseg), dim3(256), 0, s,
-                         (const double*)X, d, C64, k, nrows, cc_rows_bits(k), list, seg_cnt, seg_off,
+                         (const double*)X, d, C64, k, nrows, cc_rows_bits(k), list, seg_cnt,
                          cand, labels, u, dirty, list2, seg_cnt2, row, conv, iter, vec4);
       break;
     case KNOR_BF16:
       hipLaunchKernelGGL(mlp_certify_kernel<uint16_t>, dim3(nseg), dim3(256), 0, s,
-                         (const uint16_t*)X, d, C64, k, nrows, cc_rows_bits(k), list, seg_cnt, seg_off,
+                         (const uint16_t*)X, d, C64, k, nrows, cc_rows_bits(k), list, seg_cnt,
                          cand, labels, u, dirty, list2, seg_cnt2, row, conv, iter, vec4);
       break;
   }

@@ -642,8 +642,15 @@ def test_learned_fit_exact_and_certifies(k):
     if ref.iters > 4:
         assert st["mlp_queries"] > 0
         assert st["certified"] > 0
-    print("learned-fit k", k, "queries", st["mlp_queries"], "certified", st["certified"],
-          flush=True)
+    # a point's candidates are computed once: the network sees each point at
+    # most once per fit, and a later iteration's new rows are only survivors
+    # that never survived before
+    ctr = st["counters"]
+    assert st["mlp_forward_rows"] == int(ctr[:, 8].sum()) <= w.n
+    assert (ctr[:, 8] <= ctr[:, 6]).all()
+    assert st["mlp_queries"] == int(ctr[:, 6].sum())
+    print("learned-fit k", k, "queries", st["mlp_queries"], "forward rows",
+          st["mlp_forward_rows"], "certified", st["certified"], flush=True)
 
 
 # ---------------------------------------------------------------------------
