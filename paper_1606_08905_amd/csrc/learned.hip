@@ -1205,11 +1205,22 @@ __global__ __launch_bounds__(256) void mlp_certify_kernel(
   if (threadIdx.x == 0) run = 0;
   __syncthreads();
   unsigned long long certified = 0, changes = 0;
-  for (int q0 = wave * 4; q0 < cnt; q0 += 16) {
+  // the next step's survivor and candidate are loaded a step ahead (two
+  // dependent loads off the critical path)
+  int pn = 0, jn = -1;
+  bool ln = false;
+  auto fetch = [&](int q0) {
     const int q = q0 + ps;
-    const bool live = q < cnt;
-    const int p = live ? list[(size_t)b * kSeg + q] : 0;
-    const int j = live ? cand[(size_t)p * kMlpTop + cs] : -1;
+    ln = q < cnt;
+    pn = ln ? list[(size_t)b * kSeg + q] : 0;
+    jn = ln ? cand[(size_t)pn * kMlpTop + cs] : -1;
+  };
+  fetch(wave * 4);
+  for (int q0 = wave * 4; q0 < cnt; q0 += 16) {
+    const bool live = ln;
+    const int p = pn;
+    const int j = jn;
+    if (q0 + 16 < cnt) fetch(q0 + 16);
     double D = INFINITY;
     if (j >= 0) {
       if constexpr (sizeof(T) == 4) {

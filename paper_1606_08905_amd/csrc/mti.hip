@@ -84,7 +84,8 @@ __global__ __launch_bounds__(256) void cc_bounds_kernel(
   for (int size = 2; size <= kp2; size <<= 1)
     for (int stride = size >> 1; stride > 0; stride >>= 1) {
       for (int t = threadIdx.x; t < (kp2 >> 1); t += blockDim.x) {
-        const int lo = ((t / stride) * 2 * stride) + (t % stride), hi = lo + stride;
+        // stride is a power of two: (t / stride) 2 stride + t mod stride
+        const int lo = 2 * t - (t & (stride - 1)), hi = lo + stride;
         const bool asc = (lo & size) == 0;
         const float x = sKey[lo], y = sKey[hi];
         if ((x > y) == asc) { sKey[lo] = y; sKey[hi] = x; }

@@ -36,17 +36,22 @@
 namespace knor {
 
 constexpr int kTaskMembers = 2048;  // members per task (all may survive)
-constexpr int kCandBlock = 64;      // survivors per candidate prefix (4 waves x 16)
+constexpr int kCandBlockMax = 128;  // survivors per candidate prefix, at most
 constexpr int kSlotBits = 11;       // survivor slot in a sort key
 // the largest finite float on the grid of rounded bounds; a bound that
 // rounds up to it or beyond is taken as unbounded (every centroid competes)
 constexpr uint32_t kTopKey = 0x7f7ff800u;
 static_assert((1 << kSlotBits) == kTaskMembers, "slot field holds a task's members");
-static_assert(kCandBlock == 4 * 16, "one 16-point block per wave");
 
+
+// Survivors per candidate prefix: 4 waves of PB blocks of 16 points; two
+// blocks per wave (two independent MFMA chains) where the rows are narrow
+// enough for the registers, one otherwise.
 template <int DP>
 struct CandTile {
-  using T = F32Tile<DP, 1>;
+  static constexpr int PB = DP <= 64 ? 2 : 1;
+  static constexpr int BLOCK = 64 * PB;
+  using T = F32Tile<DP, PB>;
   static constexpr int CK = (4096 / DP) < 16 ? 16 : ((4096 / DP) > 128 ? 128 : (4096 / DP));
   static constexpr int Q = T::KS;                           // 16-byte pieces per row
   static constexpr int PER = (CK * Q + kTileThreads - 1) / kTileThreads;
@@ -95,13 +100,14 @@ __global__ __launch_bounds__(kTileThreads) void tile_f32_cand_kernel(
     const int* __restrict__ conv, int iter, int vec, int vec4) {
   using G = CandTile<DP>;
   using T = typename G::T;
-  constexpr int LDA = T::LDA, CK = G::CK, KS = T::KS, Q = G::Q;
+  constexpr int LDA = T::LDA, CK = G::CK, KS = T::KS, Q = G::Q, PB = G::PB, BLOCK = G::BLOCK;
+  static_assert(BLOCK <= kCandBlockMax, "flag slots");
   extern __shared__ __attribute__((aligned(16))) float sRow[];   // a's neighbour row
   __shared__ __attribute__((aligned(16))) float sC[CK * LDA];
   __shared__ __attribute__((aligned(16))) float sN[CK];
   __shared__ int sP[kTaskMembers];
   __shared__ float sKey[kTaskMembers];
-  __shared__ int sFl[kCandBlock];
+  __shared__ int sFl[kCandBlockMax];
   __shared__ int4 sPair[kPairCap];
   __shared__ int sCnt, sFlN, sPairN;
   if (*conv < iter || (int)blockIdx.x >= *ntask) return;     // uniform
@@ -167,7 +173,8 @@ __global__ __launch_bounds__(kTileThreads) void tile_f32_cand_kernel(
   for (int size = 2; size <= N2; size <<= 1)
     for (int stride = size >> 1; stride > 0; stride >>= 1) {
       for (int i = threadIdx.x; i < (N2 >> 1); i += kTileThreads) {
-        const int lo = ((i / stride) * 2 * stride) + (i % stride), hi = lo + stride;
+        // stride is a power of two: (i / stride) 2 stride + i mod stride
+        const int lo = 2 * i - (i & (stride - 1)), hi = lo + stride;
         const bool asc = (lo & size) == 0;
         const float x = sKey[lo], y = sKey[hi];
         if ((x > y) == asc) { sKey[lo] = y; sKey[hi] = x; }
@@ -177,10 +184,10 @@ __global__ __launch_bounds__(kTileThreads) void tile_f32_cand_kernel(
 
   unsigned long long chg = 0, nflag = 0, ndist = 0;
   const uint32_t smask = (1u << kSlotBits) - 1u;
-  for (int b0 = 0; b0 < nS; b0 += kCandBlock) {
-    const int last = b0 + kCandBlock - 1 < nS ? b0 + kCandBlock - 1 : nS - 1;
-    // the block's largest bound (rounded up), and its prefix of a's row:
-    // L = the number of entries whose lower bound h passes !(thr < h)
+  // the prefix of a's row that block b0's largest bound (rounded up) needs:
+  // the number of entries whose lower bound h passes !(thr < h)
+  auto prefix_of = [&](int b0) {
+    const int last = b0 + BLOCK - 1 < nS ? b0 + BLOCK - 1 : nS - 1;
     const uint32_t tb = __float_as_uint(sKey[last]) & ~smask;
     const double thr = tb >= kTopKey ? (double)INFINITY
                                      : (double)__uint_as_float(tb) * (1.0 + kEta);
@@ -190,65 +197,92 @@ __global__ __launch_bounds__(kTileThreads) void tile_f32_cand_kernel(
       const double h = (double)__uint_as_float(__float_as_uint(sRow[mid]) & ~mask);
       if (thr < h) hi = mid; else lo = mid + 1;
     }
-    const int L = lo;                           // >= 1: a itself has h = 0
+    return lo;                                  // >= 1: a itself has h = 0
+  };
+  auto cand_in = [&](int pos, int Lb) {
+    return pos < Lb ? (int)(__float_as_uint(sRow[pos]) & mask) : -1;
+  };
+  // block b0's points for this lane (16 PB per wave) and their rows
+  float nbx[PB][KS];
+  int npid[PB];
+  bool nvalid[PB];
+  auto load_points = [&](int b0) {
+#pragma unroll
+    for (int pb = 0; pb < PB; ++pb) {
+      const int q = b0 + wave * 16 * PB + pb * 16 + col;
+      nvalid[pb] = q < nS;
+      npid[pb] = nvalid[pb] ? sP[__float_as_uint(sKey[q]) & smask] : 0;
+      T::load_row(nbx[pb], X, npid[pb], d, grp, vec, nvalid[pb]);
+    }
+  };
+  // candidate rows, CK at a time: a chunk's loads are issued before the
+  // previous chunk's matrix work (across blocks too: a block's last chunk
+  // overlaps the loads of the next block's points and first chunk)
+  float4 pre[G::PER];
+  float pn = INFINITY;
+  auto load_chunk = [&](int c0, int Lb) {
+    const int Lp = (Lb + 15) / 16 * 16;
+    const int cc = (Lp - c0) < CK ? (Lp - c0) : CK;
+#pragma unroll
+    for (int i = 0; i < G::PER; ++i) {
+      const int e = threadIdx.x + i * kTileThreads;
+      const int r = e / Q, q4 = e - r * Q;
+      const int j = (e < cc * Q) ? cand_in(c0 + r, Lb) : -1;
+      pre[i] = j >= 0 ? *reinterpret_cast<const float4*>(Cm2 + (size_t)j * DP + q4 * 4)
+                      : make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+    const int jn = (int)threadIdx.x < cc ? cand_in(c0 + threadIdx.x, Lb) : -1;
+    pn = jn >= 0 ? cn[jn] : INFINITY;
+  };
+  auto store_chunk = [&](int c0, int Lb) {
+    const int Lp = (Lb + 15) / 16 * 16;
+    const int cc = (Lp - c0) < CK ? (Lp - c0) : CK;
+#pragma unroll
+    for (int i = 0; i < G::PER; ++i) {
+      const int e = threadIdx.x + i * kTileThreads;
+      const int r = e / Q, q4 = e - r * Q;
+      if (e < cc * Q) *reinterpret_cast<float4*>(&sC[r * LDA + q4 * 4]) = pre[i];
+    }
+    if ((int)threadIdx.x < cc) sN[threadIdx.x] = pn;
+  };
+  int Lnext = prefix_of(0);
+  load_points(0);
+  load_chunk(0, Lnext);
+  for (int b0 = 0; b0 < nS; b0 += BLOCK) {
+    const int L = Lnext;
     const int Lpad = (L + 15) / 16 * 16;
-    auto cand_of = [&](int pos) {
-      return pos < L ? (int)(__float_as_uint(sRow[pos]) & mask) : -1;
-    };
-    // the wave's 16 points
+    auto cand_of = [&](int pos) { return cand_in(pos, L); };
+    // the wave's 16 points (their rows were loaded ahead)
     WaveState<T> w;
-    {
-      const int q = b0 + wave * 16 + col;
-      const bool valid = q < nS;
-      const int p = valid ? sP[__float_as_uint(sKey[q]) & smask] : 0;
-      w.valid[0] = valid;
-      w.pid[0] = p;
-      w.old[0] = a;
-      T::load_row(w.bx[0], X, p, d, grp, vec, valid);
+#pragma unroll
+    for (int pb = 0; pb < PB; ++pb) {
+      w.valid[pb] = nvalid[pb];
+      w.pid[pb] = npid[pb];
+      w.old[pb] = a;
       double acc = 0.0;
 #pragma unroll
-      for (int s = 0; s < KS; ++s) {
-        const double v = (double)w.bx[0][s];
+      for (int s2 = 0; s2 < KS; ++s2) {
+        w.bx[pb][s2] = nbx[pb][s2];
+        const double v = (double)nbx[pb][s2];
         acc = acc + v * v;
       }
-      w.xs[0] = acc;
-      top3_reset(w.b1[0], w.b2[0], w.b3[0], w.i1[0], w.i2[0]);
+      w.xs[pb] = acc;
+      top3_reset(w.b1[pb], w.b2[pb], w.b3[pb], w.i1[pb], w.i2[pb]);
     }
-    // candidate rows, CK at a time; the next chunk's loads are issued
-    // before the current chunk's matrix work
-    float4 pre[G::PER];
-    float pn = INFINITY;
-    auto load_chunk = [&](int c0) {
-      const int cc = (Lpad - c0) < CK ? (Lpad - c0) : CK;
-#pragma unroll
-      for (int i = 0; i < G::PER; ++i) {
-        const int e = threadIdx.x + i * kTileThreads;
-        const int r = e / Q, q4 = e - r * Q;
-        const int j = (e < cc * Q) ? cand_of(c0 + r) : -1;
-        pre[i] = j >= 0 ? *reinterpret_cast<const float4*>(Cm2 + (size_t)j * DP + q4 * 4)
-                        : make_float4(0.f, 0.f, 0.f, 0.f);
-      }
-      const int jn = (int)threadIdx.x < cc ? cand_of(c0 + threadIdx.x) : -1;
-      pn = jn >= 0 ? cn[jn] : INFINITY;
-    };
-    auto store_chunk = [&](int c0) {
-      const int cc = (Lpad - c0) < CK ? (Lpad - c0) : CK;
-#pragma unroll
-      for (int i = 0; i < G::PER; ++i) {
-        const int e = threadIdx.x + i * kTileThreads;
-        const int r = e / Q, q4 = e - r * Q;
-        if (e < cc * Q) *reinterpret_cast<float4*>(&sC[r * LDA + q4 * 4]) = pre[i];
-      }
-      if ((int)threadIdx.x < cc) sN[threadIdx.x] = pn;
-    };
+    const bool more_blocks = b0 + BLOCK < nS;
     float cmax = 0.0f;
-    load_chunk(0);
     for (int c0 = 0; c0 < Lpad; c0 += CK) {
       const int cc = (Lpad - c0) < CK ? (Lpad - c0) : CK;
       __syncthreads();                          // the previous chunk is consumed
-      store_chunk(c0);
+      store_chunk(c0, L);
       __syncthreads();
-      if (c0 + CK < Lpad) load_chunk(c0 + CK);
+      if (c0 + CK < Lpad) {
+        load_chunk(c0 + CK, L);
+      } else if (more_blocks) {
+        Lnext = prefix_of(b0 + BLOCK);
+        load_points(b0 + BLOCK);
+        load_chunk(0, Lnext);
+      }
       float mx = 0.0f;
       for (int e = lane; e < cc; e += 64)
         if (c0 + e < L) mx = fmax_nc(mx, sN[e]);
@@ -258,11 +292,12 @@ __global__ __launch_bounds__(kTileThreads) void tile_f32_cand_kernel(
       tile_sweep<T, true>(w, sC, sN, cc, c0, col, grp);
     }
     merge_groups<T>(w);
-    {
-      const int j1 = cand_of(w.i1[0]);
-      const int j2 = cand_of(w.i2[0]);
-      w.i1[0] = j1;
-      w.i2[0] = j2 >= 0 ? j2 : j1;
+#pragma unroll
+    for (int pb = 0; pb < PB; ++pb) {
+      const int j1 = cand_of(w.i1[pb]);
+      const int j2 = cand_of(w.i2[pb]);
+      w.i1[pb] = j1;
+      w.i2[pb] = j2 >= 0 ? j2 : j1;
     }
     bool flag, changed;
     int fp;
@@ -294,7 +329,7 @@ __global__ __launch_bounds__(kTileThreads) void tile_f32_cand_kernel(
         chg += commit_label(p, a, bj, pair_bound(best, d), labels, u, dirty) ? 1 : 0;
     }
     if (threadIdx.x == 0) {
-      const int nv = (nS - b0) < kCandBlock ? (nS - b0) : kCandBlock;
+      const int nv = (nS - b0) < BLOCK ? (nS - b0) : BLOCK;
       ndist += (unsigned long long)(nv + nfl) * (unsigned long long)L;
       nflag += (unsigned long long)nfl;
     }
