@@ -213,6 +213,8 @@ __device__ __forceinline__ void tile_block_bf_acc(f4 (&acc)[T::PB],
       acc[pb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(o.hi[s], bx[pb][s], acc[pb], 0, 0, 0);
 }
 
+// Epilogue per value: the three smallest values and the index of the
+// smallest (the two-candidate pass is off, so no second index is kept).
 template <class T>
 __device__ __forceinline__ void tile_block_bf(WaveState<T>& w,
                                               const ABlockBf<T>& o, int jb) {
@@ -223,7 +225,7 @@ __device__ __forceinline__ void tile_block_bf(WaveState<T>& w,
   for (int pb = 0; pb < PB; ++pb)
 #pragma unroll
     for (int r = 0; r < 4; ++r)
-      top3_insert(w.b1[pb], w.b2[pb], w.b3[pb], w.i1[pb], w.i2[pb], acc[pb][r], jb + r);
+      top3_insert_lite(w.b1[pb], w.b2[pb], w.b3[pb], w.i1[pb], acc[pb][r], jb + r);
 }
 
 template <class T>
@@ -315,10 +317,10 @@ __global__ __launch_bounds__(kTileThreads) void tile_bf16_resident_kernel(
     if (!unit_range(wu, WUP, n, seg_cnt, segc, nseg, q0, m, base)) continue;
     load_points_bf<T>(w, X, d, vec, list, labels, base, q0, m, col, grp);
     tile_sweep_bf<T>(w, sH, sL, sN, kpad, 0, col, grp);
-    merge_groups<T>(w);
+    merge_groups<T, false>(w);
     bool flag, changed;
     int fp;
-    finalize_points<T>(w, cmax, d, grp, recheck_all, pairs, sPair, &sPairN,
+    finalize_points<T, false>(w, cmax, d, grp, recheck_all, pairs, sPair, &sPairN,
                        labels, ub, dirty, flag, fp, changed);
     const int nf = append_flags(flag, fp, &sFlag, slice, lane);
     const int nc = __popcll(__ballot(changed));
@@ -387,10 +389,10 @@ __global__ __launch_bounds__(kTileThreads) void tile_bf16_chunked_kernel(
       cmax = fmax_nc(cmax, chunk_cmax(sN, cc, c0, k, lane));
       tile_sweep_bf<T>(w, sH, sL, sN, cc, c0, col, grp);
     }
-    merge_groups<T>(w);
+    merge_groups<T, false>(w);
     bool flag, changed;
     int fp;
-    finalize_points<T>(w, cmax, d, grp, recheck_all, pairs, sPair, &sPairN,
+    finalize_points<T, false>(w, cmax, d, grp, recheck_all, pairs, sPair, &sPairN,
                        labels, ub, dirty, flag, fp, changed);
     append_flags(flag, fp, &sFlag, slice, lane);
     const uint64_t cm = __ballot(changed);
