@@ -236,3 +236,22 @@ def test_streamed_numeric_check(dtype):
     ref = oracle.mti_fit(workloads.to_f64(X, dtype), C0, 5, exact_mean=True)
     C, lab, st = knor.fit_streamed(_pinned(X, dtype), k, C0=C0, max_iters=5, batch_rows=4096)
     assert (C.cpu().numpy() == ref.C).all()
+
+
+def test_streamed_split_adds_large_n():
+    """n >= 2^23: every point's entry at iteration 0 and every move after it
+    goes to the digits in two pieces (the split form); labels and centroids
+    still equal the oracle's exact-mean reading."""
+    knor = _knor()
+    rng = np.random.default_rng(31)
+    n, d, k = (1 << 23) + 4097, 4, 8
+    mu = rng.uniform(-6, 6, size=(k, d))
+    X = workloads.gaussian_mixture(rng, n, mu, np.full(k, 2.0), np.ones(k), "f32")
+    C0 = X[workloads.distinct_rows(rng, n, k)].astype(np.float64)
+    _print_case(test="streamed-split", n=n)
+    ref = oracle.mti_fit(X.astype(np.float64), C0, 4, history=False, exact_mean=True)
+    C, lab, st = knor.fit_streamed(_pinned(X, "f32"), k, C0=C0, max_iters=4,
+                                   batch_rows=1 << 21, cache_rows=1 << 20, cache_interval=1)
+    assert st["iters"] == ref.iters
+    assert (lab.cpu().numpy() == ref.labels).all()
+    assert (C.cpu().numpy() == ref.C).all()
