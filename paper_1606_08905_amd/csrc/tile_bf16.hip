@@ -213,8 +213,9 @@ __device__ __forceinline__ void tile_block_bf_acc(f4 (&acc)[T::PB],
       acc[pb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(o.hi[s], bx[pb][s], acc[pb], 0, 0, 0);
 }
 
-// Epilogue per value: the three smallest values and the index of the
-// smallest (the two-candidate pass is off, so no second index is kept).
+// Epilogue per value: the two smallest values and the index of the smallest
+// (the two-candidate pass is off, so neither a third value nor a second
+// index is kept; b3 stays +inf).
 template <class T>
 __device__ __forceinline__ void tile_block_bf(WaveState<T>& w,
                                               const ABlockBf<T>& o, int jb) {
@@ -225,7 +226,7 @@ __device__ __forceinline__ void tile_block_bf(WaveState<T>& w,
   for (int pb = 0; pb < PB; ++pb)
 #pragma unroll
     for (int r = 0; r < 4; ++r)
-      top3_insert_lite(w.b1[pb], w.b2[pb], w.b3[pb], w.i1[pb], acc[pb][r], jb + r);
+      top2_insert(w.b1[pb], w.b2[pb], w.i1[pb], acc[pb][r], jb + r);
 }
 
 template <class T>

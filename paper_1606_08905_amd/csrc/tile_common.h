@@ -62,6 +62,15 @@ __device__ __forceinline__ void top3_insert(float& b1, float& b2, float& b3,
   b1 = lt1 ? y : b1;
 }
 
+// The two smallest values and the index of the smallest (for tiles that
+// never resolve two-candidate points: the third value is not kept).
+__device__ __forceinline__ void top2_insert(float& b1, float& b2, int& i1, float y, int j) {
+  const bool lt1 = y < b1;
+  b2 = __builtin_amdgcn_fmed3f(b1, b2, y);
+  i1 = lt1 ? j : i1;
+  b1 = lt1 ? y : b1;
+}
+
 __device__ __forceinline__ int wave_sum(int v) {
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
