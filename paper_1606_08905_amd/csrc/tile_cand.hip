@@ -15,21 +15,30 @@
 // a, its neighbour row: all centroids in increasing order of a lower bound
 // h(a, j) (a float key that also carries j), so C(x) is a prefix of a's row.
 //
-// Work is split into tasks of at most kTaskMembers members of one cluster
-// (in the update's sorted member order).  A task keeps the members the
-// filter marked as survivors (sign bit of their bound; Clause 3 has
-// tightened the bound to the exact distance rounded up), sorts them by
-// bound in LDS and takes them 64 at a time in increasing bound: the 64
-// share the prefix of a's row that the largest of their bounds needs.  The
-// FP32 tile runs over the gathered candidate rows with the top-3 epilogue
-// of the dense tile; a point is decided by the same rounding-bound test (its
-// R^2 taken over the candidates, the only centroids whose values it
-// compares).  The order in which candidates are visited decides no label:
-// a decided point has a strict gap to every other value, and two-candidate
-// and undecided points are resolved from canonical FP64 distances with the
-// lowest-index rule -- undecided ones over the block's whole candidate list,
-// which contains the FP64 argmin and every centroid tied with it.
+// Work is split in two launches.  A task holds at most kTaskMembers
+// members of one cluster (in the update's sorted member order); the sort
+// pass keeps the members the filter marked as survivors (sign bit of their
+// bound; Clause 3 has tightened the bound to the exact distance rounded
+// up), sorts them by bound in LDS, and cuts them into blocks of BLOCK in
+// increasing bound: the members of a block share the prefix of a's row
+// that the largest of their bounds needs.  Each block goes to a global list
+// (long prefixes first) with its cluster, its sorted members and its
+// prefix length.  The tile pass is persistent: each workgroup takes blocks
+// from the list with an atomic counter, so the work of one cluster spreads
+// over the whole GPU instead of serialising in one workgroup.
+//
+// For each block the FP32 tile runs over the gathered candidate rows with
+// the top-3 epilogue of the dense tile; a point is decided by the same
+// rounding-bound test (its R^2 taken over the candidates, the only
+// centroids whose values it compares).  The order in which candidates are
+// visited decides no label: a decided point has a strict gap to every
+// other value, and two-candidate and undecided points are resolved from
+// canonical FP64 distances with the lowest-index rule -- undecided ones over
+// the block's whole candidate list, which contains the FP64 argmin and
+// every centroid tied with it.
 #include <math.h>
+
+#include <atomic>
 
 #include "tile_f32.h"
 
@@ -57,13 +66,52 @@ struct CandTile {
   static constexpr int PER = (CK * Q + kTileThreads - 1) / kTileThreads;
 };
 
+// Workspace: a header of ints (task count, long and short block counts,
+// the block counter of the tile pass), the task table, the block list
+// (long blocks from the front, short ones from the back) and the members
+// of every task in bound order.
+constexpr int kHdrTasks = 0, kHdrLong = 1, kHdrShort = 2, kHdrNext = 3;
+// a block whose prefix is at least this long goes to the front of the list
+constexpr int kLongPrefix = 512;
+
+struct CandWs {
+  int* hdr;
+  int2* tasks;
+  int4* blocks;
+  int* sorted;
+  int cap;  // block list entries
+};
+
+static int64_t cand_task_cap(int64_t n, int k) { return n / kTaskMembers + k + 1; }
+static int64_t cand_block_cap(int64_t n, int k) { return n / 64 + cand_task_cap(n, k) + 1; }
+
+static CandWs cand_ws(void* ws, int64_t n, int k) {
+  CandWs w;
+  char* c = (char*)ws;
+  w.hdr = (int*)c;
+  c += 256;
+  w.tasks = (int2*)c;
+  c += (sizeof(int2) * (size_t)cand_task_cap(n, k) + 255) / 256 * 256;
+  w.blocks = (int4*)c;
+  w.cap = (int)cand_block_cap(n, k);
+  c += (sizeof(int4) * (size_t)w.cap + 255) / 256 * 256;
+  w.sorted = (int*)c;
+  return w;
+}
+
+size_t cand_workspace_bytes(int64_t n, int k) {
+  return 256 + (sizeof(int2) * (size_t)cand_task_cap(n, k) + 255) / 256 * 256 +
+         (sizeof(int4) * (size_t)cand_block_cap(n, k) + 255) / 256 * 256 + sizeof(int) * (size_t)n;
+}
+
 // Task table: task t of cluster a covers members [c kTaskMembers, ...) of
 // a, c < ceil(n_a / kTaskMembers); tasks are numbered cluster by cluster.
 // One workgroup of 1024 threads: an exclusive scan of the per-cluster task
-// counts, then each thread writes the tasks of its clusters.
+// counts, then each thread writes the tasks of its clusters.  It also
+// clears the block counts and the block counter of this iteration.
 __global__ __launch_bounds__(1024) void cand_tasks_kernel(const int* __restrict__ off, int k,
                                                           int2* __restrict__ tasks,
-                                                          int* __restrict__ ntask,
+                                                          int* __restrict__ hdr,
                                                           const int* __restrict__ conv,
                                                           int iter) {
   __shared__ int part[1024];
@@ -86,40 +134,32 @@ __global__ __launch_bounds__(1024) void cand_tasks_kernel(const int* __restrict_
     const int nt = (off[a + 1] - off[a] + kTaskMembers - 1) / kTaskMembers;
     for (int c = 0; c < nt; ++c) tasks[t++] = make_int2(a, c);
   }
-  if (threadIdx.x == 1023) *ntask = part[1023];
+  if (threadIdx.x == 1023) hdr[kHdrTasks] = part[1023];
+  if (threadIdx.x < 3) hdr[kHdrLong + threadIdx.x] = 0;
 }
 
-template <int DP>
-__global__ __launch_bounds__(kTileThreads) void tile_f32_cand_kernel(
-    const float* __restrict__ X, int d, const float* __restrict__ Cm2,
-    const float* __restrict__ cn, const double* __restrict__ C64, int k,
-    const int* __restrict__ perm, const int* __restrict__ off,
-    const float* __restrict__ rows, int ib, const int2* __restrict__ tasks,
-    const int* __restrict__ ntask, float* __restrict__ u, int32_t* __restrict__ labels,
-    int* __restrict__ dirty, unsigned long long* __restrict__ row,
-    const int* __restrict__ conv, int iter, int vec, int vec4) {
-  using G = CandTile<DP>;
-  using T = typename G::T;
-  constexpr int LDA = T::LDA, CK = G::CK, KS = T::KS, Q = G::Q, PB = G::PB, BLOCK = G::BLOCK;
-  static_assert(BLOCK <= kCandBlockMax, "flag slots");
+// The sort pass: one workgroup per task.  The survivors' members are
+// written to sorted[m0 + i] in increasing rounded bound, and each block of
+// BLOCK of them becomes one record (a, first member slot, count, prefix
+// length L) of the block list.
+template <int BLOCK>
+__global__ __launch_bounds__(kTileThreads) void cand_sort_kernel(
+    int k, const int* __restrict__ perm, const int* __restrict__ off,
+    const float* __restrict__ rows, int ib, const float* __restrict__ u, CandWs ws,
+    const int* __restrict__ conv, int iter) {
   extern __shared__ __attribute__((aligned(16))) float sRow[];   // a's neighbour row
-  __shared__ __attribute__((aligned(16))) float sC[CK * LDA];
-  __shared__ __attribute__((aligned(16))) float sN[CK];
   __shared__ int sP[kTaskMembers];
   __shared__ float sKey[kTaskMembers];
-  __shared__ int sFl[kCandBlockMax];
-  __shared__ int4 sPair[kPairCap];
-  __shared__ int sCnt, sFlN, sPairN;
-  if (*conv < iter || (int)blockIdx.x >= *ntask) return;     // uniform
-  const int2 tk = tasks[blockIdx.x];
+  __shared__ int sCnt;
+  if (*conv < iter || (int)blockIdx.x >= ws.hdr[kHdrTasks]) return;     // uniform
+  const int2 tk = ws.tasks[blockIdx.x];
   const int a = tk.x;
   const int m0 = off[a] + tk.y * kTaskMembers;
   const int m1 = off[a + 1] < m0 + kTaskMembers ? off[a + 1] : m0 + kTaskMembers;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int col = lane & 15, grp = lane >> 4;
+  const int lane = threadIdx.x & 63;
   const uint64_t lt = lanemask_lt();
   const uint32_t mask = (1u << ib) - 1u;
-  if (threadIdx.x == 0) { sCnt = 0; sFlN = 0; sPairN = 0; }
+  if (threadIdx.x == 0) sCnt = 0;
   // a's neighbour row into LDS (its loads overlap the member walk below)
   stage_batched<8, float>(
       k, [&](int e) { return rows[(size_t)a * k + e]; }, [&](int e, float v) { sRow[e] = v; });
@@ -181,12 +221,15 @@ __global__ __launch_bounds__(kTileThreads) void tile_f32_cand_kernel(
       }
       __syncthreads();
     }
-
-  unsigned long long chg = 0, nflag = 0, ndist = 0;
   const uint32_t smask = (1u << kSlotBits) - 1u;
-  // the prefix of a's row that block b0's largest bound (rounded up) needs:
-  // the number of entries whose lower bound h passes !(thr < h)
-  auto prefix_of = [&](int b0) {
+  for (int i = threadIdx.x; i < nS; i += kTileThreads)
+    ws.sorted[m0 + i] = sP[__float_as_uint(sKey[i]) & smask];
+  // one record per block: the prefix of a's row that its largest bound
+  // (rounded up) needs, the number of entries whose lower bound h passes
+  // !(thr < h)
+  const int nb = (nS + BLOCK - 1) / BLOCK;
+  for (int bl = threadIdx.x; bl < nb; bl += kTileThreads) {
+    const int b0 = bl * BLOCK;
     const int last = b0 + BLOCK - 1 < nS ? b0 + BLOCK - 1 : nS - 1;
     const uint32_t tb = __float_as_uint(sKey[last]) & ~smask;
     const double thr = tb >= kTopKey ? (double)INFINITY
@@ -197,27 +240,46 @@ __global__ __launch_bounds__(kTileThreads) void tile_f32_cand_kernel(
       const double h = (double)__uint_as_float(__float_as_uint(sRow[mid]) & ~mask);
       if (thr < h) hi = mid; else lo = mid + 1;
     }
-    return lo;                                  // >= 1: a itself has h = 0
-  };
+    // lo >= 1: a itself has h = 0
+    const int cnt = nS - b0 < BLOCK ? nS - b0 : BLOCK;
+    const int pos = lo >= kLongPrefix ? atomicAdd(&ws.hdr[kHdrLong], 1)
+                                      : ws.cap - 1 - atomicAdd(&ws.hdr[kHdrShort], 1);
+    ws.blocks[pos] = make_int4(a, m0 + b0, cnt, lo);
+  }
+}
+
+// The tile pass: a persistent grid; each workgroup takes the next block of
+// the list (long ones first) until the list is exhausted.
+template <int DP>
+__global__ __launch_bounds__(kTileThreads) void tile_f32_cand_kernel(
+    const float* __restrict__ X, int d, const float* __restrict__ Cm2,
+    const float* __restrict__ cn, const double* __restrict__ C64, int k,
+    const float* __restrict__ rows, int ib, CandWs ws, float* __restrict__ u,
+    int32_t* __restrict__ labels, int* __restrict__ dirty, unsigned long long* __restrict__ row,
+    const int* __restrict__ conv, int iter, int vec, int vec4) {
+  using G = CandTile<DP>;
+  using T = typename G::T;
+  constexpr int LDA = T::LDA, CK = G::CK, KS = T::KS, Q = G::Q, PB = G::PB, BLOCK = G::BLOCK;
+  static_assert(BLOCK <= kCandBlockMax, "flag slots");
+  extern __shared__ __attribute__((aligned(16))) float sRow[];   // the block's prefix
+  __shared__ __attribute__((aligned(16))) float sC[CK * LDA];
+  __shared__ __attribute__((aligned(16))) float sN[CK];
+  __shared__ int sFl[kCandBlockMax];
+  __shared__ int4 sPair[kPairCap];
+  __shared__ int sFlN, sPairN, sBlk;
+  if (*conv < iter) return;                                   // uniform
+  const int nlong = ws.hdr[kHdrLong];
+  const int nblk = nlong + ws.hdr[kHdrShort];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int col = lane & 15, grp = lane >> 4;
+  const uint32_t mask = (1u << ib) - 1u;
+  if (threadIdx.x == 0) { sFlN = 0; sPairN = 0; }
+  unsigned long long chg = 0, nflag = 0, ndist = 0;
   auto cand_in = [&](int pos, int Lb) {
     return pos < Lb ? (int)(__float_as_uint(sRow[pos]) & mask) : -1;
   };
-  // block b0's points for this lane (16 PB per wave) and their rows
-  float nbx[PB][KS];
-  int npid[PB];
-  bool nvalid[PB];
-  auto load_points = [&](int b0) {
-#pragma unroll
-    for (int pb = 0; pb < PB; ++pb) {
-      const int q = b0 + wave * 16 * PB + pb * 16 + col;
-      nvalid[pb] = q < nS;
-      npid[pb] = nvalid[pb] ? sP[__float_as_uint(sKey[q]) & smask] : 0;
-      T::load_row(nbx[pb], X, npid[pb], d, grp, vec, nvalid[pb]);
-    }
-  };
   // candidate rows, CK at a time: a chunk's loads are issued before the
-  // previous chunk's matrix work (across blocks too: a block's last chunk
-  // overlaps the loads of the next block's points and first chunk)
+  // previous chunk's matrix work
   float4 pre[G::PER];
   float pn = INFINITY;
   auto load_chunk = [&](int c0, int Lb) {
@@ -245,44 +307,47 @@ __global__ __launch_bounds__(kTileThreads) void tile_f32_cand_kernel(
     }
     if ((int)threadIdx.x < cc) sN[threadIdx.x] = pn;
   };
-  int Lnext = prefix_of(0);
-  load_points(0);
-  load_chunk(0, Lnext);
-  for (int b0 = 0; b0 < nS; b0 += BLOCK) {
-    const int L = Lnext;
+  for (;;) {
+    if (threadIdx.x == 0) sBlk = atomicAdd(&ws.hdr[kHdrNext], 1);
+    __syncthreads();                          // also: the previous block is done
+    const int bi = sBlk;
+    if (bi >= nblk) break;                    // uniform
+    const int4 rec = ws.blocks[bi < nlong ? bi : ws.cap - 1 - (bi - nlong)];
+    const int a = rec.x, s0 = rec.y, nv = rec.z, L = rec.w;
     const int Lpad = (L + 15) / 16 * 16;
     auto cand_of = [&](int pos) { return cand_in(pos, L); };
-    // the wave's 16 points (their rows were loaded ahead)
+    // the wave's 16 PB points and their rows; a's row prefix into LDS
     WaveState<T> w;
 #pragma unroll
     for (int pb = 0; pb < PB; ++pb) {
-      w.valid[pb] = nvalid[pb];
-      w.pid[pb] = npid[pb];
+      const int q = wave * 16 * PB + pb * 16 + col;
+      w.valid[pb] = q < nv;
+      w.pid[pb] = w.valid[pb] ? ws.sorted[s0 + q] : 0;
       w.old[pb] = a;
+    }
+    stage_batched<8, float>(
+        L, [&](int e) { return rows[(size_t)a * k + e]; }, [&](int e, float v) { sRow[e] = v; });
+#pragma unroll
+    for (int pb = 0; pb < PB; ++pb) {
+      T::load_row(w.bx[pb], X, w.pid[pb], d, grp, vec, w.valid[pb]);
       double acc = 0.0;
 #pragma unroll
       for (int s2 = 0; s2 < KS; ++s2) {
-        w.bx[pb][s2] = nbx[pb][s2];
-        const double v = (double)nbx[pb][s2];
+        const double v = (double)w.bx[pb][s2];
         acc = acc + v * v;
       }
       w.xs[pb] = acc;
       top3_reset(w.b1[pb], w.b2[pb], w.b3[pb], w.i1[pb], w.i2[pb]);
     }
-    const bool more_blocks = b0 + BLOCK < nS;
+    __syncthreads();                          // the prefix is staged
+    load_chunk(0, L);
     float cmax = 0.0f;
     for (int c0 = 0; c0 < Lpad; c0 += CK) {
       const int cc = (Lpad - c0) < CK ? (Lpad - c0) : CK;
-      __syncthreads();                          // the previous chunk is consumed
+      __syncthreads();                        // the previous chunk is consumed
       store_chunk(c0, L);
       __syncthreads();
-      if (c0 + CK < Lpad) {
-        load_chunk(c0 + CK, L);
-      } else if (more_blocks) {
-        Lnext = prefix_of(b0 + BLOCK);
-        load_points(b0 + BLOCK);
-        load_chunk(0, Lnext);
-      }
+      if (c0 + CK < Lpad) load_chunk(c0 + CK, L);
       float mx = 0.0f;
       for (int e = lane; e < cc; e += 64)
         if (c0 + e < L) mx = fmax_nc(mx, sN[e]);
@@ -328,48 +393,66 @@ __global__ __launch_bounds__(kTileThreads) void tile_f32_cand_kernel(
       if (lane == 0)
         chg += commit_label(p, a, bj, pair_bound(best, d), labels, u, dirty) ? 1 : 0;
     }
+    // two-candidate points of this block
+    const int np = sPairN < kPairCap ? sPairN : kPairCap;
+    if (np) chg += resolve_pairs<T, float>(X, d, vec, C64, sPair, np, labels, u, dirty);
     if (threadIdx.x == 0) {
-      const int nv = (nS - b0) < BLOCK ? (nS - b0) : BLOCK;
       ndist += (unsigned long long)(nv + nfl) * (unsigned long long)L;
       nflag += (unsigned long long)nfl;
     }
     __syncthreads();
-    if (threadIdx.x == 0) sFlN = 0;
+    if (threadIdx.x == 0) { sFlN = 0; sPairN = 0; }
   }
-  __syncthreads();
-  const int np = sPairN < kPairCap ? sPairN : kPairCap;
-  if (np) chg += resolve_pairs<T, float>(X, d, vec, C64, sPair, np, labels, u, dirty);
   const int qs[3] = {SLOT_CHANGED, SLOT_FLAGGED, SLOT_DISTS};
   const unsigned long long v[3] = {chg, nflag, ndist};
   block_add_slots<3>(row, qs, v);
 }
 
-size_t cand_workspace_bytes(int64_t n, int k) {
-  return sizeof(int2) * (size_t)(n / kTaskMembers + k + 1) + 256;
+// Workgroups of the persistent tile pass: as many as are resident at once.
+template <int DP>
+static int cand_grid(size_t lds) {
+  static std::atomic<int> cached{0};
+  const int c = cached.load(std::memory_order_relaxed);
+  if (c) return c;
+  int dev = 0, cus = 0, per = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(
+          &per, reinterpret_cast<const void*>(&tile_f32_cand_kernel<DP>), kTileThreads,
+          lds) != hipSuccess ||
+      cus <= 0 || per <= 0)
+    return 1024;
+  cached.store(cus * per, std::memory_order_relaxed);
+  return cus * per;
 }
 
 template <int DP>
 static hipError_t launch_cand_dp(const CentroidOps& o, const AssignJob& j, const int* perm,
-                                 const int* off, const float* rows, void* ws,
-                                 hipStream_t s) {
+                                 const int* off, const float* rows, void* ws_, hipStream_t s) {
   const int vec = (int)(j.d == DP && ((uintptr_t)j.X & 15) == 0);
   const int vec4 = (int)(j.d % 4 == 0 && ((uintptr_t)j.X & 15) == 0 &&
                          ((uintptr_t)o.C64 & 15) == 0);
   const size_t lds = sizeof(float) * (size_t)o.k;
-  // with the static arrays the total can pass the default 64 KB
+  // with the static arrays the totals can pass the default 64 KB
   hipError_t e = hipFuncSetAttribute(
       reinterpret_cast<const void*>(&tile_f32_cand_kernel<DP>),
       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
-  int* ntask = (int*)ws;
-  int2* tasks = (int2*)((char*)ws + 256);
-  hipLaunchKernelGGL(cand_tasks_kernel, dim3(1), dim3(1024), 0, s, off, o.k, tasks, ntask,
+  e = hipFuncSetAttribute(reinterpret_cast<const void*>(&cand_sort_kernel<CandTile<DP>::BLOCK>),
+                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  const CandWs ws = cand_ws(ws_, j.n, o.k);
+  const int ib = cc_rows_bits(o.k);
+  hipLaunchKernelGGL(cand_tasks_kernel, dim3(1), dim3(1024), 0, s, off, o.k, ws.tasks, ws.hdr,
                      j.conv, j.iter);
-  const int64_t grid = j.n / kTaskMembers + o.k + 1;      // >= the number of tasks
-  hipLaunchKernelGGL((tile_f32_cand_kernel<DP>), dim3((unsigned)grid), dim3(kTileThreads), lds,
-                     s, (const float*)j.X, j.d, o.Cm2, o.cn, o.C64, o.k, perm, off, rows,
-                     cc_rows_bits(o.k), tasks, ntask, j.u, j.labels, j.dirty, j.row, j.conv,
-                     j.iter, vec, vec4);
+  const int64_t tgrid = cand_task_cap(j.n, o.k);           // >= the number of tasks
+  hipLaunchKernelGGL((cand_sort_kernel<CandTile<DP>::BLOCK>), dim3((unsigned)tgrid),
+                     dim3(kTileThreads), lds, s, o.k, perm, off, rows, ib, (const float*)j.u,
+                     ws, j.conv, j.iter);
+  hipLaunchKernelGGL((tile_f32_cand_kernel<DP>), dim3((unsigned)cand_grid<DP>(lds)),
+                     dim3(kTileThreads), lds, s, (const float*)j.X, j.d, o.Cm2, o.cn, o.C64,
+                     o.k, rows, ib, ws, j.u, j.labels, j.dirty, j.row, j.conv, j.iter, vec,
+                     vec4);
   return hipGetLastError();
 }
 
