@@ -249,9 +249,12 @@ __global__ __launch_bounds__(kTileThreads) void cand_sort_kernel(
 }
 
 // The tile pass: a persistent grid; each workgroup takes the next block of
-// the list (long ones first) until the list is exhausted.
+// the list (long ones first) until the list is exhausted.  Rows up to 32
+// wide fit three waves per SIMD in the register file (the LDS holds four
+// workgroups), which hides more of each block's load latency.
 template <int DP>
-__global__ __launch_bounds__(kTileThreads) void tile_f32_cand_kernel(
+__global__ __launch_bounds__(kTileThreads)
+__attribute__((amdgpu_waves_per_eu(DP <= 32 ? 3 : 1))) void tile_f32_cand_kernel(
     const float* __restrict__ X, int d, const float* __restrict__ Cm2,
     const float* __restrict__ cn, const double* __restrict__ C64, int k,
     const float* __restrict__ rows, int ib, CandWs ws, float* __restrict__ u,
