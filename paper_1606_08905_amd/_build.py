@@ -29,6 +29,14 @@ FLAGS = [
 ]
 
 
+# per-source flags: keep the matrix-core accumulators in VGPRs (the
+# epilogue reads every accumulator; from AGPRs each read is one more VALU
+# instruction)
+SOURCE_FLAGS = {
+    "tile_bf16.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"],
+}
+
+
 def sources():
     return sorted(glob.glob(os.path.join(CSRC, "*.hip")))
 
@@ -45,7 +53,8 @@ def build(verbose: bool = False) -> str:
 
     def compile_one(pair):
         src, obj = pair
-        cmd = [HIPCC, *FLAGS, "-I", INCLUDE, "-I", CSRC, "-c", src, "-o", obj]
+        extra = SOURCE_FLAGS.get(os.path.basename(src), [])
+        cmd = [HIPCC, *FLAGS, *extra, "-I", INCLUDE, "-I", CSRC, "-c", src, "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         r = subprocess.run(cmd, capture_output=True, text=True)

@@ -91,6 +91,27 @@ struct Bf16Tile {
       bx[s] = __builtin_bit_cast(bf8, v4);
     }
   }
+  // load_row for loads that stay in flight across other work: with vec, the
+  // loads are unconditional (row 0 stands in for an invalid point and the
+  // value is replaced by zero afterwards), so no branch joins with a load
+  // outstanding
+  template <bool VEC>
+  __device__ static void load_row_ahead(Frag (&bx)[KS], const uint16_t* __restrict__ X,
+                                        int64_t p, int d, int grp, bool valid) {
+    if constexpr (!VEC) {
+      load_row(bx, X, p, d, grp, 0, valid);
+      return;
+    }
+    const uint16_t* xr = X + (size_t)(valid ? p : 0) * d;
+    uint4 v[KS];
+#pragma unroll
+    for (int s = 0; s < KS; ++s) v[s] = *reinterpret_cast<const uint4*>(xr + s * 32 + grp * 8);
+#pragma unroll
+    for (int s = 0; s < KS; ++s) {
+      const uint4 z = {0u, 0u, 0u, 0u};
+      bx[s] = __builtin_bit_cast(bf8, valid ? v[s] : z);
+    }
+  }
   __device__ static double bound(double xn2, double R2, int) {
     const double u24 = 5.9604644775390625e-08;
     const double xn = sqrt(xn2), R = sqrt(R2);
@@ -174,6 +195,43 @@ __device__ __forceinline__ void load_points_bf(
   }
 }
 
+// load_points_bf in two halves for a pipelined unit loop: the loads of a
+// unit's rows and labels (indices given), and, once they are needed, the
+// squared norms and the reset of the running minima.
+template <class T, bool VEC>
+__device__ __forceinline__ void issue_points_bf(WaveState<T>& w, const uint16_t* __restrict__ X,
+                                                int d, const int32_t* __restrict__ labels,
+                                                bool listed, const int64_t (&q)[T::PB],
+                                                const int (&raw)[T::PB],
+                                                const bool (&valid)[T::PB], int grp) {
+#pragma unroll
+  for (int pb = 0; pb < T::PB; ++pb) {
+    const int64_t pid = valid[pb] ? (listed ? (int64_t)raw[pb] : q[pb]) : 0;
+    w.valid[pb] = valid[pb];
+    w.pid[pb] = pid;
+    w.old[pb] = labels[pid];                  // unconditional (point 0 stands in); see finish
+    T::template load_row_ahead<VEC>(w.bx[pb], X, pid, d, grp, valid[pb]);
+  }
+}
+
+template <class T>
+__device__ __forceinline__ void finish_points_bf(WaveState<T>& w, int grp) {
+#pragma unroll
+  for (int pb = 0; pb < T::PB; ++pb) {
+    w.old[pb] = (w.valid[pb] && (pb & 3) == grp) ? w.old[pb] : 0;
+    double acc = 0.0;
+#pragma unroll
+    for (int s = 0; s < T::KS; ++s)
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const double v = T::xval(w.bx[pb], s, e);
+        acc = acc + v * v;
+      }
+    w.xs[pb] = acc;
+    top3_reset(w.b1[pb], w.b2[pb], w.b3[pb], w.i1[pb], w.i2[pb]);
+  }
+}
+
 template <class T>
 struct ABlockBf {
   bf8 hi[T::KS], lo[T::KS];
@@ -234,14 +292,19 @@ __device__ __forceinline__ void tile_sweep_bf(WaveState<T>& w, const uint16_t* s
                                               const uint16_t* sL, const float* sN,
                                               int cc, int c0, int col, int grp) {
   constexpr int LDA = T::LDA;
-  ABlockBf<T> cur, nxt;
-  load_ablock_bf<T>(cur, &sH[col * LDA + grp * 8], &sL[col * LDA + grp * 8], &sN[4 * grp]);
-  for (int cb = 0; cb < cc; cb += 16) {
-    if (cb + 16 < cc)
-      load_ablock_bf<T>(nxt, &sH[(cb + 16 + col) * LDA + grp * 8],
-                        &sL[(cb + 16 + col) * LDA + grp * 8], &sN[cb + 16 + 4 * grp]);
-    tile_block_bf<T>(w, cur, c0 + cb + 4 * grp);
-    cur = nxt;
+  // two operand buffers used in turn (no register copy between blocks)
+  ABlockBf<T> a0, a1;
+  auto load = [&](ABlockBf<T>& o, int cb) {
+    load_ablock_bf<T>(o, &sH[(cb + col) * LDA + grp * 8], &sL[(cb + col) * LDA + grp * 8],
+                      &sN[cb + 4 * grp]);
+  };
+  load(a0, 0);
+  for (int cb = 0; cb < cc; cb += 32) {
+    if (cb + 16 < cc) load(a1, cb + 16);
+    tile_block_bf<T>(w, a0, c0 + cb + 4 * grp);
+    if (cb + 16 >= cc) break;
+    if (cb + 32 < cc) load(a0, cb + 32);
+    tile_block_bf<T>(w, a1, c0 + cb + 16 + 4 * grp);
   }
 }
 
@@ -273,7 +336,7 @@ __device__ __forceinline__ void stage_bf(uint16_t* sH, uint16_t* sL, float* sN,
       cc, [&](int e) { return cn[c0 + e]; }, [&](int e, float v) { sN[e] = v; });
 }
 
-template <int DP>
+template <int DP, bool VEC>
 __global__ __launch_bounds__(kTileThreads) void tile_bf16_resident_kernel(
     const uint16_t* __restrict__ X, int64_t n, int d,
     const uint16_t* __restrict__ Chi, const uint16_t* __restrict__ Clo,
@@ -310,13 +373,55 @@ __global__ __launch_bounds__(kTileThreads) void tile_bf16_resident_kernel(
   int64_t nwu = seg_cnt ? (int64_t)nseg * (kSeg / WUP) : (n + WUP - 1) / WUP;
   if (seg_cnt) nwu = seg_units_bound(sWmax, nseg, nwu);
   const int* segc = (seg_cnt && nseg <= kSegCache) ? sSeg : nullptr;
-  WaveState<T> w;
   unsigned long long tot_flag = 0, tot_chg = 0;
-  for (int64_t wu = (int64_t)blockIdx.x * 4 + wave; wu < nwu;
-       wu += (int64_t)gridDim.x * 4) {
-    int64_t q0, m, base;
-    if (!unit_range(wu, WUP, n, seg_cnt, segc, nseg, q0, m, base)) continue;
-    load_points_bf<T>(w, X, d, vec, list, labels, base, q0, m, col, grp);
+  WaveState<T> w;
+  // Rows up to 128 wide run the wave's units as a two-stage pipeline: while
+  // a unit is swept, the next unit's rows and labels are loaded (their list
+  // entries were read one unit earlier) and the list entries of the unit
+  // after that.  Every such load is unconditional and its value untouched
+  // until the next unit starts, so no wait inside the sweep drains them.
+  constexpr bool PIPE = DP <= 128;
+  const int64_t stride = (int64_t)gridDim.x * 4;
+  int64_t q0, m, base;
+  auto advance = [&](int64_t& u) {            // the wave's next non-empty unit from u
+    for (; u < nwu; u += stride)
+      if (unit_range(u, WUP, n, seg_cnt, segc, nseg, q0, m, base)) return true;
+    return false;
+  };
+  int64_t nq[PB];
+  int nraw[PB];
+  bool nval[PB];
+  auto unit_pids = [&](bool ok) {
+#pragma unroll
+    for (int pb = 0; pb < PB; ++pb) {
+      nq[pb] = q0 + pb * 16 + col;
+      nval[pb] = ok && nq[pb] < m;
+      nraw[pb] = list ? list[nval[pb] ? base + nq[pb] : 0] : 0;
+    }
+  };
+  int64_t wu = (int64_t)blockIdx.x * 4 + wave;
+  bool hcur = advance(wu), hnext = false;
+  int64_t wn_u = wu + stride;
+  if constexpr (PIPE) {
+    unit_pids(hcur);
+    issue_points_bf<T, VEC>(w, X, d, labels, list != nullptr, nq, nraw, nval, grp);
+    hnext = hcur && advance(wn_u);
+    unit_pids(hnext);
+  }
+  while (hcur) {                              // wave-uniform
+    bool hafter = false;
+    WaveState<T> wn;
+    if constexpr (PIPE) {
+      finish_points_bf<T>(w, grp);            // waits for this unit's rows
+      // the unit after next is found before the next unit's loads are
+      // issued (the search reads segment counts; its waits would drain them)
+      wn_u += stride;
+      hafter = hnext && advance(wn_u);
+      issue_points_bf<T, VEC>(wn, X, d, labels, list != nullptr, nq, nraw, nval, grp);
+      unit_pids(hafter);
+    } else {
+      load_points_bf<T>(w, X, d, vec, list, labels, base, q0, m, col, grp);
+    }
     tile_sweep_bf<T>(w, sH, sL, sN, kpad, 0, col, grp);
     merge_groups<T, false>(w);
     bool flag, changed;
@@ -328,6 +433,14 @@ __global__ __launch_bounds__(kTileThreads) void tile_bf16_resident_kernel(
     if (lane == 0) {
       tot_flag += nf;
       tot_chg += nc;
+    }
+    if constexpr (PIPE) {
+      w = wn;
+      hcur = hnext;
+      hnext = hafter;
+    } else {
+      wu += stride;
+      hcur = advance(wu);
     }
   }
   __syncthreads();
@@ -422,13 +535,14 @@ static hipError_t launch_bf_dp(const CentroidOps& o, const AssignJob& j,
   const TileGeom g = tile_bf16_geometry(DP, o.kpad, j.n, seg, j.nseg);
   if (g.resident) {
     const size_t lds = bf_resident_bytes(DP, o.kpad);
+    // rows of exactly DP columns, 16-byte aligned, get the branch-free loads
+    auto kern = vec ? &tile_bf16_resident_kernel<DP, true> : &tile_bf16_resident_kernel<DP, false>;
     if (lds > 49152) {   // with the static arrays, past the default 64 KB
-      hipError_t e = hipFuncSetAttribute(
-          reinterpret_cast<const void*>(&tile_bf16_resident_kernel<DP>),
-          hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+      hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
       if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(tile_bf16_resident_kernel<DP>, dim3(g.grid), dim3(kTileThreads),
+    hipLaunchKernelGGL(kern, dim3(g.grid), dim3(kTileThreads),
                        lds, s, (const uint16_t*)j.X, j.n, j.d, o.Chi, o.Clo, o.cn,
                        o.k, o.kpad, j.list, j.seg_cnt, j.nseg, j.labels, j.u,
                        j.flags, g.cap, j.ucnt, j.row, j.conv, j.iter, j.dirty,
