@@ -869,7 +869,8 @@ struct FitRun {
         prof.end();
         prof.begin(KNOR_PROF_CERTIFY);
         HIPCHK(launch_mlp_certify(X, dt, d, C_out, k, ccrows, list, seg_cnt, nseg, cand,
-                                  labels_out, u, dirty, list2, seg_cnt2, row, conv, t, s));
+                                  labels_out, u, dirty, list2, seg_cnt2, row, conv, t,
+                                  use_cand, s));
         job.list = list2;
         job.seg_cnt = seg_cnt2;
       }

@@ -577,13 +577,16 @@ constexpr int32_t kUnproposed = -2;
 hipError_t launch_seg_unproposed(const int* list, const int* seg_cnt, int nseg,
                                  const int32_t* cand, int* cnt_new, int* seg_off, int* dense,
                                  const int* conv, int iter, hipStream_t s);
-// nrows: the k x k neighbour rows of launch_cc_bounds
+// nrows: the k x k neighbour rows of launch_cc_bounds.  tight: every
+// listed survivor's |u| is its distance to its centroid rounded up (the
+// filter's Clause 3); the certificate is then skipped where it cannot pass
+// with c* = the survivor's centroid.
 hipError_t launch_mlp_certify(const void* X, knor_dtype dt, int d, const double* C64,
                               int k, const float* nrows, const int* list,
                               const int* seg_cnt, int nseg,
                               const int32_t* cand, int32_t* labels, float* u, int* dirty,
                               int* list2, int* seg_cnt2, unsigned long long* row,
-                              const int* conv, int iter, hipStream_t s);
+                              const int* conv, int iter, bool tight, hipStream_t s);
 constexpr int kMlpHidden = 256;      // hidden width inside knor_fit
 constexpr int kMlpBatch = 4096;      // training minibatch inside knor_fit
 constexpr float kMlpLr = 1e-3f;

@@ -1186,6 +1186,13 @@ hipError_t launch_seg_unproposed(const int* list, const int* seg_cnt, int nseg,
 // Certified points take c* (and ub as their MTI bound); the others are
 // appended to list2 (order within a segment is immaterial to every later
 // pass).
+//
+// tight: with 16 candidates, the first non-candidate of a row is at
+// position 16 at the latest, so with c* = a (the survivor's centroid) the
+// test needs d(x, a) (1 + eta) < h(a, row_a[16]).  A survivor whose bound,
+// scaled down below d(x, a), fails this is not tested (it goes to the
+// fallback scan like any uncertified point); only a survivor whose c*
+// would differ from a could have passed.
 template <typename T>
 __global__ __launch_bounds__(256) void mlp_certify_kernel(
     const T* __restrict__ X, int d, const double* __restrict__ C64,
@@ -1194,7 +1201,8 @@ __global__ __launch_bounds__(256) void mlp_certify_kernel(
     const int32_t* __restrict__ cand,
     int32_t* __restrict__ labels, float* __restrict__ ub_out, int* __restrict__ dirty,
     int* __restrict__ list2, int* __restrict__ seg_cnt2,
-    unsigned long long* __restrict__ row, const int* __restrict__ conv, int iter, int vec4) {
+    unsigned long long* __restrict__ row, const int* __restrict__ conv, int iter, int vec4,
+    int tight) {
   __shared__ int run;
   if (*conv < iter) return;
   const int b = blockIdx.x;
@@ -1205,21 +1213,34 @@ __global__ __launch_bounds__(256) void mlp_certify_kernel(
   if (threadIdx.x == 0) run = 0;
   __syncthreads();
   unsigned long long certified = 0, changes = 0;
-  // the next step's survivor and candidate are loaded a step ahead (two
-  // dependent loads off the critical path)
-  int pn = 0, jn = -1;
+  // the next step's survivor, candidate, bound and centroid are loaded a
+  // step ahead (dependent loads off the critical path)
+  int pn = 0, jn = -1, an = 0;
+  float un = 0.0f;
   bool ln = false;
   auto fetch = [&](int q0) {
     const int q = q0 + ps;
     ln = q < cnt;
     pn = ln ? list[(size_t)b * kSeg + q] : 0;
     jn = ln ? cand[(size_t)pn * kMlpTop + cs] : -1;
+    if (tight) {
+      un = ln ? ub_out[pn] : 0.0f;
+      an = ln ? labels[pn] : 0;
+    }
   };
+  const uint32_t tmask = (1u << ib) - 1u;
   fetch(wave * 4);
   for (int q0 = wave * 4; q0 < cnt; q0 += 16) {
     const bool live = ln;
     const int p = pn;
-    const int j = jn;
+    int j = jn;
+    if (tight && k > kMlpTop) {
+      // d(x, a) >= |u| (1 - 2^-20): |u| is d(x, a) rounded up to FP32
+      const float key = nrows[(size_t)an * k + kMlpTop];
+      const double h16 = (double)__uint_as_float(__float_as_uint(key) & ~tmask);
+      const double dlo = (double)fabsf(un) * (1.0 - 9.5367431640625e-07);
+      if (!(dlo * (1.0 + kEta) < h16)) j = -1;    // cannot pass with c* = a
+    }
     if (q0 + 16 < cnt) fetch(q0 + 16);
     double D = INFINITY;
     if (j >= 0) {
@@ -1315,23 +1336,26 @@ hipError_t launch_mlp_certify(const void* X, knor_dtype dt, int d, const double*
                               const int* seg_cnt, int nseg,
                               const int32_t* cand, int32_t* labels, float* u, int* dirty,
                               int* list2, int* seg_cnt2, unsigned long long* row,
-                              const int* conv, int iter, hipStream_t s) {
+                              const int* conv, int iter, bool tight, hipStream_t s) {
   const int vec4 = (int)(d % 4 == 0 && ((uintptr_t)X & 15) == 0 && ((uintptr_t)C64 & 15) == 0);
   switch (dt) {
     case KNOR_F32:
       hipLaunchKernelGGL(mlp_certify_kernel<float>, dim3(nseg), dim3(256), 0, s,
                          (const float*)X, d, C64, k, nrows, cc_rows_bits(k), list, seg_cnt,
-                         cand, labels, u, dirty, list2, seg_cnt2, row, conv, iter, vec4);
+                         cand, labels, u, dirty, list2, seg_cnt2, row, conv, iter, vec4,
+                         (int)tight);
       break;
     case KNOR_F64:
       hipLaunchKernelGGL(mlp_certify_kernel<double>, dim3(nseg), dim3(256), 0, s,
                          (const double*)X, d, C64, k, nrows, cc_rows_bits(k), list, seg_cnt,
-                         cand, labels, u, dirty, list2, seg_cnt2, row, conv, iter, vec4);
+                         cand, labels, u, dirty, list2, seg_cnt2, row, conv, iter, vec4,
+                         (int)tight);
       break;
     case KNOR_BF16:
       hipLaunchKernelGGL(mlp_certify_kernel<uint16_t>, dim3(nseg), dim3(256), 0, s,
                          (const uint16_t*)X, d, C64, k, nrows, cc_rows_bits(k), list, seg_cnt,
-                         cand, labels, u, dirty, list2, seg_cnt2, row, conv, iter, vec4);
+                         cand, labels, u, dirty, list2, seg_cnt2, row, conv, iter, vec4,
+                         (int)tight);
       break;
   }
   return hipGetLastError();
