@@ -855,7 +855,7 @@ struct FitRun {
       // only survivors that were never proposed for go through the network:
       // a point's candidates do not change once training is over
       HIPCHK(launch_seg_unproposed(list, seg_cnt, nseg, cand, seg_new, seg_off, dense, conv,
-                                   t, s));
+                                   t, u, labels_out, use_cand ? ccrows : nullptr, k, s));
       int hm[2] = {0, 0};
       HIPCHK(hipMemcpyAsync(&hm[0], seg_off + nseg, sizeof(int), hipMemcpyDeviceToHost, s));
       HIPCHK(hipMemcpyAsync(&hm[1], conv, sizeof(int), hipMemcpyDeviceToHost, s));

@@ -574,9 +574,13 @@ constexpr int kMlpTop = 16;          // candidates per point
 constexpr int32_t kUnproposed = -2;
 // Survivors without a proposal yet: cnt_new (per segment), seg_off (their
 // exclusive prefix, total at seg_off[nseg]) and their point indices in dense.
+// rows (or null): the neighbour rows; survivors that the certificate will
+// not test (launch_mlp_certify with tight: u, labels) are left out.
 hipError_t launch_seg_unproposed(const int* list, const int* seg_cnt, int nseg,
                                  const int32_t* cand, int* cnt_new, int* seg_off, int* dense,
-                                 const int* conv, int iter, hipStream_t s);
+                                 const int* conv, int iter, const float* u,
+                                 const int32_t* labels, const float* rows, int k,
+                                 hipStream_t s);
 // nrows: the k x k neighbour rows of launch_cc_bounds.  tight: every
 // listed survivor's |u| is its distance to its centroid rounded up (the
 // filter's Clause 3); the certificate is then skipped where it cannot pass

@@ -1127,12 +1127,29 @@ __global__ __launch_bounds__(1024) void seg_scan_kernel(const int* __restrict__ 
 // kUnproposed): their count (count pass) or, at seg_off[b] on, their point
 // indices (order within a segment is immaterial: each output row lands at
 // its point's own candidate slots).
+// CertPre: the certificate's test for c* = a (see mlp_certify_kernel), to
+// skip survivors that cannot pass it.  Active when rows is not null.
+struct CertPre {
+  const float* u;       // |u|: distance to the centroid rounded up
+  const int32_t* labels;
+  const float* rows;    // neighbour rows (k x k keys)
+  int k, ib;
+  __device__ bool can_pass(int p) const {
+    if (!rows || k <= kMlpTop) return true;
+    const int a = labels[p];
+    const float key = rows[(size_t)a * k + kMlpTop];
+    const double h16 = (double)__uint_as_float(__float_as_uint(key) & ~((1u << ib) - 1u));
+    const double dlo = (double)fabsf(u[p]) * (1.0 - 9.5367431640625e-07);
+    return dlo * (1.0 + kEta) < h16;
+  }
+};
+
 template <bool WRITE>
 __global__ __launch_bounds__(256) void seg_unproposed_kernel(
     const int* __restrict__ list, const int* __restrict__ seg_cnt,
     const int32_t* __restrict__ cand, int* __restrict__ cnt_new,
     const int* __restrict__ seg_off, int* __restrict__ dense,
-    const int* __restrict__ conv, int iter) {
+    const int* __restrict__ conv, int iter, CertPre pre) {
   __shared__ int run;
   if (*conv < iter) return;
   const int b = blockIdx.x;
@@ -1144,7 +1161,8 @@ __global__ __launch_bounds__(256) void seg_unproposed_kernel(
   for (int q0 = 0; q0 < cnt; q0 += 256) {
     const int q = q0 + (int)threadIdx.x;
     const int p = q < cnt ? list[(size_t)b * kSeg + q] : 0;
-    const bool fresh = q < cnt && cand[(size_t)p * kMlpTop] == kUnproposed;
+    // survivors the certificate will not test need no proposal yet
+    const bool fresh = q < cnt && cand[(size_t)p * kMlpTop] == kUnproposed && pre.can_pass(p);
     const uint64_t m = __ballot(fresh);
     if (m) {
       const int leader = __ffsll((unsigned long long)m) - 1;
@@ -1160,13 +1178,16 @@ __global__ __launch_bounds__(256) void seg_unproposed_kernel(
 
 hipError_t launch_seg_unproposed(const int* list, const int* seg_cnt, int nseg,
                                  const int32_t* cand, int* cnt_new, int* seg_off, int* dense,
-                                 const int* conv, int iter, hipStream_t s) {
+                                 const int* conv, int iter, const float* u,
+                                 const int32_t* labels, const float* rows, int k,
+                                 hipStream_t s) {
+  const CertPre pre{u, labels, rows, k, rows ? cc_rows_bits(k) : 0};
   hipLaunchKernelGGL(seg_unproposed_kernel<false>, dim3(nseg), dim3(256), 0, s, list, seg_cnt,
-                     cand, cnt_new, (const int*)nullptr, (int*)nullptr, conv, iter);
+                     cand, cnt_new, (const int*)nullptr, (int*)nullptr, conv, iter, pre);
   hipLaunchKernelGGL(seg_scan_kernel, dim3(1), dim3(1024), 0, s, cnt_new, nseg, seg_off,
                      conv, iter);
   hipLaunchKernelGGL(seg_unproposed_kernel<true>, dim3(nseg), dim3(256), 0, s, list, seg_cnt,
-                     cand, cnt_new, (const int*)seg_off, dense, conv, iter);
+                     cand, cnt_new, (const int*)seg_off, dense, conv, iter, pre);
   return hipGetLastError();
 }
 
@@ -1235,7 +1256,8 @@ __global__ __launch_bounds__(256) void mlp_certify_kernel(
     const int p = pn;
     int j = jn;
     if (tight && k > kMlpTop) {
-      // d(x, a) >= |u| (1 - 2^-20): |u| is d(x, a) rounded up to FP32
+      // the test of CertPre::can_pass on the values loaded a step ahead
+      // (d(x, a) >= |u| (1 - 2^-20): |u| is d(x, a) rounded up to FP32)
       const float key = nrows[(size_t)an * k + kMlpTop];
       const double h16 = (double)__uint_as_float(__float_as_uint(key) & ~tmask);
       const double dlo = (double)fabsf(un) * (1.0 - 9.5367431640625e-07);
