@@ -41,6 +41,15 @@ __device__ __forceinline__ uint16_t f32_bf16_rne(float f) {
   return (uint16_t)(b >> 16);
 }
 
+// Two values rounded to BF16 (nearest, ties to even, as f32_bf16_rne for
+// finite values) by one v_cvt_pk_bf16_f32: a in the low half, b in the high.
+typedef float f2l __attribute__((ext_vector_type(2)));
+typedef __bf16 bf2l __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ uint32_t bf16_pair(float a, float b) {
+  const f2l v = {a, b};
+  return __builtin_bit_cast(uint32_t, __builtin_convertvector(v, bf2l));
+}
+
 // ---------------------------------------------------------------------------
 // generic GEMM: C[M x N] = op(A)[M x K] op(B)[K x N] (+ bias[N]) (ReLU)
 // (masked by mask > 0); op = transpose when the flag is set
@@ -57,7 +66,7 @@ __device__ __forceinline__ uint16_t f32_bf16_rne(float f) {
 // applies the epilogue, so the result does not depend on scheduling.
 
 constexpr int kGT = 128;           // output tile rows and columns
-constexpr int kGK = 32;            // K-step
+constexpr int kGK = 32;            // K-step (one MFMA K-block)
 constexpr int kGLD = kGK + 8;      // LDS row stride (bf16), 16-byte aligned
 constexpr int kGTargetWG = 1024;   // split K until about this many workgroups
 constexpr int kGMaxSplit = 16;
@@ -99,15 +108,18 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(GemmArgs g, int ksplit,
   const bool va = (g.lda & 3) == 0 && ((uintptr_t)g.A & 15) == 0;
   const bool vb = (g.ldb & 3) == 0 && ((uintptr_t)g.B & 15) == 0;
   // piece i of this thread: f = tid + 256 i.  Along K (A plain, B
-  // transposed): row f / 8, K offset 4 (f mod 8).  Along M or N (A
-  // transposed, B plain): K offset f / 32, rows or columns 4 (f mod 32).
-  float4 ra[4], rb[4];
+  // transposed): row f / (kGK / 4), K offset 4 (f mod (kGK / 4)).  Along M
+  // or N (A transposed, B plain): K offset f / 32, rows or columns 4 (f mod
+  // 32).
+  constexpr int NP = kGT * kGK / 4 / 256;     // 16-byte pieces per operand per thread
+  constexpr int QK = kGK / 4, QS = QK == 16 ? 4 : 3;
+  float4 ra[NP], rb[NP];
   auto load = [&](int k0) {
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
+    for (int i = 0; i < NP; ++i) {
       const int f = tid + 256 * i;
       if (!TA) {
-        const int r = f >> 3, kk = 4 * (f & 7);
+        const int r = f >> QS, kk = 4 * (f & (QK - 1));
         const int row = m0 + r, kx = k0 + kk;
         ra[i] = row < M ? load4(g.A + (size_t)row * g.lda + kx, ke - kx, va)
                         : make_float4(0.f, 0.f, 0.f, 0.f);
@@ -118,7 +130,7 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(GemmArgs g, int ksplit,
                         : make_float4(0.f, 0.f, 0.f, 0.f);
       }
       if (TB) {
-        const int c = f >> 3, kk = 4 * (f & 7);
+        const int c = f >> QS, kk = 4 * (f & (QK - 1));
         const int cn = n0 + c, kx = k0 + kk;
         rb[i] = cn < N ? load4(g.B + (size_t)cn * g.ldb + kx, ke - kx, vb)
                        : make_float4(0.f, 0.f, 0.f, 0.f);
@@ -134,33 +146,29 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(GemmArgs g, int ksplit,
     uint16_t* a = sA[buf];
     uint16_t* b = sB[buf];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
+    for (int i = 0; i < NP; ++i) {
       const int f = tid + 256 * i;
-      const uint16_t x0 = f32_bf16_rne(ra[i].x), x1 = f32_bf16_rne(ra[i].y);
-      const uint16_t x2 = f32_bf16_rne(ra[i].z), x3 = f32_bf16_rne(ra[i].w);
+      const uint32_t x01 = bf16_pair(ra[i].x, ra[i].y), x23 = bf16_pair(ra[i].z, ra[i].w);
       if (!TA) {
-        const int r = f >> 3, kk = 4 * (f & 7);
-        *reinterpret_cast<uint2*>(&a[r * kGLD + kk]) =
-            make_uint2((uint32_t)x0 | ((uint32_t)x1 << 16), (uint32_t)x2 | ((uint32_t)x3 << 16));
+        const int r = f >> QS, kk = 4 * (f & (QK - 1));
+        *reinterpret_cast<uint2*>(&a[r * kGLD + kk]) = make_uint2(x01, x23);
       } else {
         const int kk = f >> 5, r = 4 * (f & 31);
-        a[(r + 0) * kGLD + kk] = x0;
-        a[(r + 1) * kGLD + kk] = x1;
-        a[(r + 2) * kGLD + kk] = x2;
-        a[(r + 3) * kGLD + kk] = x3;
+        a[(r + 0) * kGLD + kk] = (uint16_t)x01;
+        a[(r + 1) * kGLD + kk] = (uint16_t)(x01 >> 16);
+        a[(r + 2) * kGLD + kk] = (uint16_t)x23;
+        a[(r + 3) * kGLD + kk] = (uint16_t)(x23 >> 16);
       }
-      const uint16_t y0 = f32_bf16_rne(rb[i].x), y1 = f32_bf16_rne(rb[i].y);
-      const uint16_t y2 = f32_bf16_rne(rb[i].z), y3 = f32_bf16_rne(rb[i].w);
+      const uint32_t y01 = bf16_pair(rb[i].x, rb[i].y), y23 = bf16_pair(rb[i].z, rb[i].w);
       if (TB) {
-        const int c = f >> 3, kk = 4 * (f & 7);
-        *reinterpret_cast<uint2*>(&b[c * kGLD + kk]) =
-            make_uint2((uint32_t)y0 | ((uint32_t)y1 << 16), (uint32_t)y2 | ((uint32_t)y3 << 16));
+        const int c = f >> QS, kk = 4 * (f & (QK - 1));
+        *reinterpret_cast<uint2*>(&b[c * kGLD + kk]) = make_uint2(y01, y23);
       } else {
         const int kk = f >> 5, c = 4 * (f & 31);
-        b[(c + 0) * kGLD + kk] = y0;
-        b[(c + 1) * kGLD + kk] = y1;
-        b[(c + 2) * kGLD + kk] = y2;
-        b[(c + 3) * kGLD + kk] = y3;
+        b[(c + 0) * kGLD + kk] = (uint16_t)y01;
+        b[(c + 1) * kGLD + kk] = (uint16_t)(y01 >> 16);
+        b[(c + 2) * kGLD + kk] = (uint16_t)y23;
+        b[(c + 3) * kGLD + kk] = (uint16_t)(y23 >> 16);
       }
     }
   };
@@ -178,18 +186,23 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(GemmArgs g, int ksplit,
   for (int k0 = kb; k0 < ke; k0 += kGK) {
     const bool more = k0 + kGK < ke;
     if (more) load(k0 + kGK);                  // in flight during the MFMAs
-    bf8l av[4], bv[4];
 #pragma unroll
-    for (int x = 0; x < 4; ++x)
-      av[x] = *reinterpret_cast<const bf8l*>(&sA[buf][(wr * 64 + x * 16 + col) * kGLD + grp * 8]);
+    for (int kq = 0; kq < kGK; kq += 32) {
+      bf8l av[4], bv[4];
 #pragma unroll
-    for (int y = 0; y < 4; ++y)
-      bv[y] = *reinterpret_cast<const bf8l*>(&sB[buf][(wc * 64 + y * 16 + col) * kGLD + grp * 8]);
-#pragma unroll
-    for (int x = 0; x < 4; ++x)
+      for (int x = 0; x < 4; ++x)
+        av[x] = *reinterpret_cast<const bf8l*>(
+            &sA[buf][(wr * 64 + x * 16 + col) * kGLD + kq + grp * 8]);
 #pragma unroll
       for (int y = 0; y < 4; ++y)
-        acc[x][y] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[x], bv[y], acc[x][y], 0, 0, 0);
+        bv[y] = *reinterpret_cast<const bf8l*>(
+            &sB[buf][(wc * 64 + y * 16 + col) * kGLD + kq + grp * 8]);
+#pragma unroll
+      for (int x = 0; x < 4; ++x)
+#pragma unroll
+        for (int y = 0; y < 4; ++y)
+          acc[x][y] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[x], bv[y], acc[x][y], 0, 0, 0);
+    }
     if (more) store(buf ^ 1);
     __syncthreads();
     buf ^= 1;
