@@ -489,11 +489,20 @@ __global__ __launch_bounds__(1024) void colscan_b(int* __restrict__ segsum,
   SKIP_IF_CONVERGED
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j < k) {
+    // 64 segments' loads in flight before their stores (one memory round
+    // trip per 64 segments, not per segment)
+    constexpr int U = 64;
     int run = 0;
-    for (int s = 0; s < nsegc; ++s) {
-      int v = segsum[(size_t)s * k + j];
-      segsum[(size_t)s * k + j] = run;
-      run += v;
+    for (int s0 = 0; s0 < nsegc; s0 += U) {
+      int v[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) v[u] = s0 + u < nsegc ? segsum[(size_t)(s0 + u) * k + j] : 0;
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        if (s0 + u < nsegc) {
+          segsum[(size_t)(s0 + u) * k + j] = run;
+          run += v[u];
+        }
     }
     nj[j] = run;
   }
@@ -523,6 +532,7 @@ __global__ __launch_bounds__(64) void scatter_kernel(
   const int lane = threadIdx.x;
   const int seg = b / seglen;
   const int* sp = segsum + (size_t)seg * k;
+#pragma unroll 8
   for (int j = lane; j < k; j += 64) {
     int r = off[j] + sp[j];
     for (int bb = seg * seglen; bb < b; ++bb) r += blockcnt[(size_t)bb * k + j];
@@ -531,22 +541,40 @@ __global__ __launch_bounds__(64) void scatter_kernel(
   __syncthreads();
   const uint64_t lt = lanemask_lt();
   int64_t p0 = (int64_t)b * B, p1 = p0 + B < n ? p0 + B : n;
-  for (int64_t c = p0; c < p1; c += 64) {
-    int64_t p = c + lane;
-    int lab = p < p1 ? labels[p] : 0;
-    bool valid = p < p1 && (unsigned)lab < (unsigned)k;
-    if (!valid) lab = 0;
-    const uint64_t mask = same_label_mask(valid, lab, bits);
-    int rank = __popcll(mask & lt);
-    int cnt = __popcll(mask);
-    int pos = 0;
-    if (valid) pos = run[lab] + rank;
-    __builtin_amdgcn_wave_barrier();
-    if (valid) {
-      if (!dirty || dirty[lab]) perm[pos] = (int)p;
-      if (rank == cnt - 1) run[lab] = pos + 1;
+  // eight chunks of 64 labels (and their clusters' dirty flags) are loaded
+  // before the first of them is placed: one memory round trip per eight
+  // chunks instead of per chunk
+  constexpr int U = 8;
+  for (int64_t c0 = p0; c0 < p1; c0 += 64 * U) {
+    int labv[U], dv[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t p = c0 + 64 * u + lane;
+      labv[u] = p < p1 ? labels[p] : -1;
     }
-    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      dv[u] = (!dirty || (unsigned)labv[u] >= (unsigned)k) ? 1 : dirty[labv[u]];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t c = c0 + 64 * u;
+      if (c >= p1) break;                       // uniform
+      const int64_t p = c + lane;
+      int lab = labv[u];
+      bool valid = p < p1 && (unsigned)lab < (unsigned)k;
+      if (!valid) lab = 0;
+      const uint64_t mask = same_label_mask(valid, lab, bits);
+      int rank = __popcll(mask & lt);
+      int cnt = __popcll(mask);
+      int pos = 0;
+      if (valid) pos = run[lab] + rank;
+      __builtin_amdgcn_wave_barrier();
+      if (valid) {
+        if (dv[u]) perm[pos] = (int)p;
+        if (rank == cnt - 1) run[lab] = pos + 1;
+      }
+      __builtin_amdgcn_wave_barrier();
+    }
   }
 }
 
