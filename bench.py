@@ -56,24 +56,27 @@ PEAK_FP64_VALU = 78.6e12
 # it was measured on are unchanged.
 MEASURED_TRAFFIC = {
     # the Clause-2 group: task table, sort pass and persistent tile (medians
-    # over 78 launches; fetch 10.4 + 645458.2 + 266534.8 KiB, x2 by the copy
-    # calibration; write 59.0 + 15074.4 + 117384.5 KiB)
+    # over 78 launches; fetch 10.4 + 645413.2 + 266493.4 KiB, x2 by the copy
+    # calibration; write 59.0 + 15073.8 + 117387.5 KiB)
     (5, "assign_list"): {
-        "bytes": (2 * (10.4 + 645458.2 + 266534.8) + (59.0 + 15074.4 + 117384.5)) * 1024,
+        "bytes": (2 * (10.4 + 645413.2 + 266493.4) + (59.0 + 15073.8 + 117387.5)) * 1024,
         "sources": {
             "tile_cand.hip": "57f6948fa2f1fb7ec0e387e58181d20550c6bb7ea57849740c84cb3a72573bd9",
             "tile_f32.h": "3f97de7c2787a14799266d891081f1fd542dd9b455574650329a9c58bb22cabd",
             "tile_common.h": "18b57551b211404e935b936f88115a6a233d856df775a30d73da76270589ecec",
-            "common.h": "66f700b56d01e15d1060c2921d5e657a5f22e4bfcb86b78b026c3c7cef120615",
+            "common.h": "f337e306c80e02e196ee7200ae18bd4ad4eaf8e7f4cebdc6146cc08bf0cd56d3",
         },
     },
+    # the survivor tile (median over 200 launches; fetch 23296.0 KiB x2,
+    # write 7139.0 KiB)
     (2, "assign_list"): {
-        "bytes": (48329.6 + 7175.5) * 1024,
+        "bytes": (2 * 23296.0 + 7139.0) * 1024,
         "sources": {
-            "tile_f32.hip": "2612d89d6dc47fbd775b81bd9ce49294ad3a4d247af1c3305ac012019ea8ca94",
-            "tile_common.h": "208a2d868f991aa4158f135ad044dfc08bbe3bffd9259f2d02bddd769813b5c3",
+            "tile_f32.hip": "cef7dd31ffbab019dc1801c79ac232c39157b1ac5d06b1542b4e30f6b10845d6",
+            "tile_f32.h": "3f97de7c2787a14799266d891081f1fd542dd9b455574650329a9c58bb22cabd",
+            "tile_common.h": "18b57551b211404e935b936f88115a6a233d856df775a30d73da76270589ecec",
             "recheck.h": "cdd421f2b40c729a29f70a8c818d95f62f97c9fad5a0e4854d07f66baacaf0ad",
-            "common.h": "9a05b505ae0a355b1e38564c49bbb05d5e2fd54df548525528e69a8451a6638a",
+            "common.h": "f337e306c80e02e196ee7200ae18bd4ad4eaf8e7f4cebdc6146cc08bf0cd56d3",
         },
     },
 }
