@@ -1237,46 +1237,78 @@ __global__ __launch_bounds__(256) void mlp_certify_kernel(
     int* __restrict__ list2, int* __restrict__ seg_cnt2,
     unsigned long long* __restrict__ row, const int* __restrict__ conv, int iter, int vec4,
     int tight) {
-  __shared__ int run;
+  __shared__ int run, sQn;
+  __shared__ int sQ[kSeg];                   // the segment's survivors to test (tight)
   if (*conv < iter) return;
   const int b = blockIdx.x;
   const int cnt = seg_cnt[b];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int ps = lane >> 4, cs = lane & 15;
   const uint64_t lt = lanemask_lt();
-  if (threadIdx.x == 0) run = 0;
+  if (threadIdx.x == 0) { run = 0; sQn = 0; }
   __syncthreads();
   unsigned long long certified = 0, changes = 0;
-  // the next step's survivor, candidate, bound and centroid are loaded a
-  // step ahead (dependent loads off the critical path)
-  int pn = 0, jn = -1, an = 0;
-  float un = 0.0f;
+  // tight: every listed survivor is first put through the pre-test (all of
+  // the segment's loads issued in three rounds); those that can pass with
+  // c* = their centroid are gathered in sQ, the others go to list2 at once
+  const bool pre = tight && k > kMlpTop;
+  int cnt2 = cnt;
+  if (pre) {
+    constexpr int E = kSeg / 256;
+    static_assert(E * 256 == kSeg, "one pass of the workgroup covers a segment");
+    const uint32_t tmask = (1u << ib) - 1u;
+    int pp[E], aa[E];
+    float uu[E], kk[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int q = (int)threadIdx.x + 256 * e;
+      pp[e] = q < cnt ? list[(size_t)b * kSeg + q] : 0;
+    }
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      aa[e] = labels[pp[e]];
+      uu[e] = ub_out[pp[e]];
+    }
+#pragma unroll
+    for (int e = 0; e < E; ++e) kk[e] = nrows[(size_t)aa[e] * k + kMlpTop];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int q = (int)threadIdx.x + 256 * e;
+      const bool in = q < cnt;
+      // d(x, a) >= |u| (1 - 2^-20): |u| is d(x, a) rounded up to FP32
+      const double h16 = (double)__uint_as_float(__float_as_uint(kk[e]) & ~tmask);
+      const double dlo = (double)fabsf(uu[e]) * (1.0 - 9.5367431640625e-07);
+      const bool can = in && dlo * (1.0 + kEta) < h16;
+      const uint64_t mc = __ballot(can), mo = __ballot(in && !can);
+      const int leader = lane == 0;
+      int bc = 0, bo = 0;
+      if (leader && mc) bc = atomicAdd(&sQn, __popcll(mc));   // LDS
+      if (leader && mo) bo = atomicAdd(&run, __popcll(mo));
+      bc = __shfl(bc, 0);
+      bo = __shfl(bo, 0);
+      if (can) sQ[bc + __popcll(mc & lt)] = pp[e];
+      if (in && !can) list2[(size_t)b * kSeg + bo + __popcll(mo & lt)] = pp[e];
+    }
+    __syncthreads();
+    cnt2 = sQn;
+  }
+  auto entry = [&](int q) { return pre ? sQ[q] : list[(size_t)b * kSeg + q]; };
+  // the next step's survivor and candidate are loaded a step ahead (two
+  // dependent loads off the critical path)
+  int pn = 0, jn = -1;
   bool ln = false;
   auto fetch = [&](int q0) {
     const int q = q0 + ps;
-    ln = q < cnt;
-    pn = ln ? list[(size_t)b * kSeg + q] : 0;
+    ln = q < cnt2;
+    pn = ln ? entry(q) : 0;
     jn = ln ? cand[(size_t)pn * kMlpTop + cs] : -1;
-    if (tight) {
-      un = ln ? ub_out[pn] : 0.0f;
-      an = ln ? labels[pn] : 0;
-    }
   };
-  const uint32_t tmask = (1u << ib) - 1u;
   fetch(wave * 4);
-  for (int q0 = wave * 4; q0 < cnt; q0 += 16) {
+  for (int q0 = wave * 4; q0 < cnt2; q0 += 16) {
     const bool live = ln;
     const int p = pn;
-    int j = jn;
-    if (tight && k > kMlpTop) {
-      // the test of CertPre::can_pass on the values loaded a step ahead
-      // (d(x, a) >= |u| (1 - 2^-20): |u| is d(x, a) rounded up to FP32)
-      const float key = nrows[(size_t)an * k + kMlpTop];
-      const double h16 = (double)__uint_as_float(__float_as_uint(key) & ~tmask);
-      const double dlo = (double)fabsf(un) * (1.0 - 9.5367431640625e-07);
-      if (!(dlo * (1.0 + kEta) < h16)) j = -1;    // cannot pass with c* = a
-    }
-    if (q0 + 16 < cnt) fetch(q0 + 16);
+    const int j = jn;
+    if (q0 + 16 < cnt2) fetch(q0 + 16);
     double D = INFINITY;
     if (j >= 0) {
       if constexpr (sizeof(T) == 4) {
