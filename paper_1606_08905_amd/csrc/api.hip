@@ -672,6 +672,7 @@ struct FitRun {
   std::vector<int64_t> forwarded;               // rows through the forward pass
   std::vector<char> cand_used;                  // candidate-list tile ran
   int* seg_new = nullptr;                       // per segment: unproposed survivors
+  uint8_t* prop = nullptr;                      // per point: sent to the network
   bool packed = false;
   Prof prof;
   Prof* pp = nullptr;
@@ -746,6 +747,7 @@ struct FitRun {
       ar.add((void**)&seg_cnt2, sizeof(int) * (size_t)nseg);
       ar.add((void**)&cand, sizeof(int32_t) * (size_t)n * kMlpTop);
       ar.add((void**)&seg_new, sizeof(int) * (size_t)nseg);
+      ar.add((void**)&prop, sizeof(int32_t) * (size_t)((n + 3) / 4));
     }
     if (init == KNOR_INIT_KMEANSPP) {
       ar.add(&pp_ws, kmeanspp_workspace_bytes(n, k));
@@ -808,6 +810,7 @@ struct FitRun {
       HIPCHK(hipMemsetAsync(am, 0, sizeof(float) * (size_t)ML.P, s));
       HIPCHK(hipMemsetAsync(av, 0, sizeof(float) * (size_t)ML.P, s));
       HIPCHK(launch_fill_i32(cand, n * kMlpTop, kUnproposed, s));
+      HIPCHK(launch_fill_i32(reinterpret_cast<int32_t*>(prop), (n + 3) / 4, 0, s));
       HIPCHK(hipStreamSynchronize(s));          // `th0` leaves scope
     }
     proposed.assign((size_t)max_iters, 0);
@@ -854,7 +857,7 @@ struct FitRun {
       }
       // only survivors that were never proposed for go through the network:
       // a point's candidates do not change once training is over
-      HIPCHK(launch_seg_unproposed(list, seg_cnt, nseg, cand, seg_new, seg_off, dense, conv,
+      HIPCHK(launch_seg_unproposed(list, seg_cnt, nseg, prop, seg_new, seg_off, dense, conv,
                                    t, u, labels_out, use_cand ? ccrows : nullptr, k, s));
       int hm[2] = {0, 0};
       HIPCHK(hipMemcpyAsync(&hm[0], seg_off + nseg, sizeof(int), hipMemcpyDeviceToHost, s));

@@ -574,10 +574,12 @@ constexpr int kMlpTop = 16;          // candidates per point
 constexpr int32_t kUnproposed = -2;
 // Survivors without a proposal yet: cnt_new (per segment), seg_off (their
 // exclusive prefix, total at seg_off[nseg]) and their point indices in dense.
-// rows (or null): the neighbour rows; survivors that the certificate will
-// not test (launch_mlp_certify with tight: u, labels) are left out.
+// prop: one byte per point, zero until the point is listed here (the
+// caller then runs the forward pass over dense).  rows (or null): the
+// neighbour rows; survivors that the certificate will not test
+// (launch_mlp_certify with tight: u, labels) are left out.
 hipError_t launch_seg_unproposed(const int* list, const int* seg_cnt, int nseg,
-                                 const int32_t* cand, int* cnt_new, int* seg_off, int* dense,
+                                 uint8_t* prop, int* cnt_new, int* seg_off, int* dense,
                                  const int* conv, int iter, const float* u,
                                  const int32_t* labels, const float* rows, int k,
                                  hipStream_t s);

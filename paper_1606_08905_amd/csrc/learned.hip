@@ -1157,10 +1157,13 @@ struct CertPre {
   }
 };
 
+// prop[p] != 0 once p has been sent to the network (set by the write pass,
+// whose points the forward pass of the same iteration proposes for): one
+// byte per point, so a segment's flags share a few cache lines.
 template <bool WRITE>
 __global__ __launch_bounds__(256) void seg_unproposed_kernel(
     const int* __restrict__ list, const int* __restrict__ seg_cnt,
-    const int32_t* __restrict__ cand, int* __restrict__ cnt_new,
+    uint8_t* __restrict__ prop, int* __restrict__ cnt_new,
     const int* __restrict__ seg_off, int* __restrict__ dense,
     const int* __restrict__ conv, int iter, CertPre pre) {
   __shared__ int run;
@@ -1175,14 +1178,17 @@ __global__ __launch_bounds__(256) void seg_unproposed_kernel(
     const int q = q0 + (int)threadIdx.x;
     const int p = q < cnt ? list[(size_t)b * kSeg + q] : 0;
     // survivors the certificate will not test need no proposal yet
-    const bool fresh = q < cnt && cand[(size_t)p * kMlpTop] == kUnproposed && pre.can_pass(p);
+    const bool fresh = q < cnt && prop[p] == 0 && pre.can_pass(p);
     const uint64_t m = __ballot(fresh);
     if (m) {
       const int leader = __ffsll((unsigned long long)m) - 1;
       int base = 0;
       if (lane == leader) base = atomicAdd(&run, __popcll(m));   // LDS
       base = __shfl(base, leader);
-      if (WRITE && fresh) dense[seg_off[b] + base + __popcll(m & lt)] = p;
+      if (WRITE && fresh) {
+        dense[seg_off[b] + base + __popcll(m & lt)] = p;
+        prop[p] = 1;
+      }
     }
   }
   __syncthreads();
@@ -1190,17 +1196,17 @@ __global__ __launch_bounds__(256) void seg_unproposed_kernel(
 }
 
 hipError_t launch_seg_unproposed(const int* list, const int* seg_cnt, int nseg,
-                                 const int32_t* cand, int* cnt_new, int* seg_off, int* dense,
+                                 uint8_t* prop, int* cnt_new, int* seg_off, int* dense,
                                  const int* conv, int iter, const float* u,
                                  const int32_t* labels, const float* rows, int k,
                                  hipStream_t s) {
   const CertPre pre{u, labels, rows, k, rows ? cc_rows_bits(k) : 0};
   hipLaunchKernelGGL(seg_unproposed_kernel<false>, dim3(nseg), dim3(256), 0, s, list, seg_cnt,
-                     cand, cnt_new, (const int*)nullptr, (int*)nullptr, conv, iter, pre);
+                     prop, cnt_new, (const int*)nullptr, (int*)nullptr, conv, iter, pre);
   hipLaunchKernelGGL(seg_scan_kernel, dim3(1), dim3(1024), 0, s, cnt_new, nseg, seg_off,
                      conv, iter);
   hipLaunchKernelGGL(seg_unproposed_kernel<true>, dim3(nseg), dim3(256), 0, s, list, seg_cnt,
-                     cand, cnt_new, (const int*)seg_off, dense, conv, iter, pre);
+                     prop, cnt_new, (const int*)seg_off, dense, conv, iter, pre);
   return hipGetLastError();
 }
 
