@@ -357,7 +357,7 @@ __attribute__((amdgpu_waves_per_eu(DP <= 32 ? 3 : 1))) void tile_f32_cand_kernel
 #pragma unroll
       for (int o = 32; o > 0; o >>= 1) mx = fmax_nc(mx, __shfl_xor(mx, o));
       cmax = fmax_nc(cmax, mx);
-      tile_sweep<T, true>(w, sC, sN, cc, c0, col, grp);
+      tile_sweep<T, true, true>(w, sC, sN, cc, c0, col, grp);
     }
     merge_groups<T>(w);
 #pragma unroll

@@ -126,18 +126,34 @@ __device__ __forceinline__ void tile_block(WaveState<T>& w, const ABlock<T>& o,
 
 // All centroid blocks [c0, c0 + cc) staged at sC/sN, with the next block's
 // operands loaded from LDS before the current block's matrix work.
-template <class T, bool I2>
+template <class T, bool I2, bool PP = false>
 __device__ __forceinline__ void tile_sweep(WaveState<T>& w, const float* sC,
                                            const float* sN, int cc, int c0,
                                            int col, int grp) {
   constexpr int LDA = T::LDA, KS = T::KS;
-  ABlock<T> cur, nxt;
-  load_ablock<T>(cur, &sC[col * LDA + grp * KS], &sN[4 * grp]);
-  for (int cb = 0; cb < cc; cb += 16) {
-    if (cb + 16 < cc)
-      load_ablock<T>(nxt, &sC[(cb + 16 + col) * LDA + grp * KS], &sN[cb + 16 + 4 * grp]);
-    tile_block<T, I2>(w, cur, c0 + cb + 4 * grp);
-    cur = nxt;
+  auto load = [&](ABlock<T>& o, int cb) {
+    load_ablock<T>(o, &sC[(cb + col) * LDA + grp * KS], &sN[cb + 4 * grp]);
+  };
+  if constexpr (PP) {
+    // two operand buffers used in turn (no register copy between blocks;
+    // a few more registers live)
+    ABlock<T> a0, a1;
+    load(a0, 0);
+    for (int cb = 0; cb < cc; cb += 32) {
+      if (cb + 16 < cc) load(a1, cb + 16);
+      tile_block<T, I2>(w, a0, c0 + cb + 4 * grp);
+      if (cb + 16 >= cc) break;
+      if (cb + 32 < cc) load(a0, cb + 32);
+      tile_block<T, I2>(w, a1, c0 + cb + 16 + 4 * grp);
+    }
+  } else {
+    ABlock<T> cur, nxt;
+    load(cur, 0);
+    for (int cb = 0; cb < cc; cb += 16) {
+      if (cb + 16 < cc) load(nxt, cb + 16);
+      tile_block<T, I2>(w, cur, c0 + cb + 4 * grp);
+      cur = nxt;
+    }
   }
 }
 

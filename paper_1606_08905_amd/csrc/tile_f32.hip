@@ -239,7 +239,7 @@ __global__ __launch_bounds__(kTileThreads) void tile_f32_resident_kernel(
     int64_t q0, m, base;
     if (!unit_range(wu, WUP, n, seg_cnt, segc, nseg, q0, m, base)) continue;
     load_points<T>(w, X, d, vec, list, labels, base, q0, m, col, grp);
-    tile_sweep<T, false>(w, sC, sN, kpad, 0, col, grp);
+    tile_sweep<T, false, true>(w, sC, sN, kpad, 0, col, grp);
     merge_groups<T, false>(w);
     bool flag, changed;
     int fp;
