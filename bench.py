@@ -109,8 +109,11 @@ def parse():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", type=int, default=5, choices=[1, 2, 3, 4, 5])
-    ap.add_argument("--update", default="canonical", choices=["canonical", "exact"],
-                    help="centroid update of the measured fits")
+    ap.add_argument("--update", default=None, choices=["canonical", "exact"],
+                    help="centroid update of the measured fits and their baselines: the exact "
+                         "member mean, moving only changed points (default for FP32 and BF16 "
+                         "points), or the canonical leaf(64) + pairwise tree sums (default, and "
+                         "the only rule, for FP64 points: --config 1)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-exact", action="store_true",
                     help="skip the oracle comparison (profiling runs)")
@@ -131,7 +134,10 @@ def parse():
                     help="also run one device-to-device copy of this many MiB "
                          "before the timed region (a known-size kernel for "
                          "scaling HBM byte counters)")
-    return ap.parse_args()
+    a = ap.parse_args()
+    if a.update is None:
+        a.update = "canonical" if a.config == 1 else "exact"
+    return a
 
 
 def log(msg):

@@ -849,6 +849,16 @@ struct FitRun {
       job.seg_cnt = seg_cnt;
       job.nseg = nseg;
     }
+    const bool cand_t = seg && use_cand;
+    if (cand_t && exact) {
+      // the exact update keeps no member order between iterations.  The sort
+      // also recounts the members, which the exact update then moves point
+      // by point: it must see the labels of the previous update, before the
+      // certificate below relabels any point.
+      prof.begin(KNOR_PROF_SORT);
+      HIPCHK(launch_sort(plan, labels_out, nullptr, conv, t, s, 0));
+      prof.end();
+    }
     if (learned && seg && t > o.train_iters) {
       prof.begin(KNOR_PROF_LEARNED);
       if (!packed) {                          // training is over
@@ -879,14 +889,7 @@ struct FitRun {
       }
       prof.end();
     }
-    const bool cand_t = seg && use_cand;
     cand_used[t] = cand_t ? 1 : 0;
-    if (cand_t && exact) {
-      // the exact update keeps no member order between iterations
-      prof.begin(KNOR_PROF_SORT);
-      HIPCHK(launch_sort(plan, labels_out, nullptr, conv, t, s, 0));
-      prof.end();
-    }
     prof.begin(seg ? KNOR_PROF_ASSIGN_LIST : KNOR_PROF_ASSIGN_DENSE);
     if (cand_t)
       HIPCHK(launch_tile_cand(ops, job, plan.perm, plan.off, ccrows, cand_ws, s));

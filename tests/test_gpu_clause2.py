@@ -110,3 +110,11 @@ def test_with_learned_proposal():
 def test_with_exact_update():
     w = workloads.config(5, n=60000, k=1024, seed=4)
     _compare(w.X, w.C0, w.k, 20, exact_mean=True)
+
+
+def test_learned_with_exact_update():
+    """The certificate relabels points before the Clause-2 tile; the exact
+    update's member counts must still move each relabelled point once."""
+    w = workloads.config(5, n=60000, k=1024, seed=5)
+    st = _compare(w.X, w.C0, w.k, 20, exact_mean=True, learned=True, train_iters=3)
+    assert st["mlp_queries"] > 0
