@@ -849,16 +849,6 @@ struct FitRun {
       job.seg_cnt = seg_cnt;
       job.nseg = nseg;
     }
-    const bool cand_t = seg && use_cand;
-    if (cand_t && exact) {
-      // the exact update keeps no member order between iterations.  The sort
-      // also recounts the members, which the exact update then moves point
-      // by point: it must see the labels of the previous update, before the
-      // certificate below relabels any point.
-      prof.begin(KNOR_PROF_SORT);
-      HIPCHK(launch_sort(plan, labels_out, nullptr, conv, t, s, 0));
-      prof.end();
-    }
     if (learned && seg && t > o.train_iters) {
       prof.begin(KNOR_PROF_LEARNED);
       if (!packed) {                          // training is over
@@ -889,10 +879,11 @@ struct FitRun {
       }
       prof.end();
     }
+    const bool cand_t = seg && use_cand;
     cand_used[t] = cand_t ? 1 : 0;
     prof.begin(seg ? KNOR_PROF_ASSIGN_LIST : KNOR_PROF_ASSIGN_DENSE);
     if (cand_t)
-      HIPCHK(launch_tile_cand(ops, job, plan.perm, plan.off, ccrows, cand_ws, s));
+      HIPCHK(launch_tile_cand(ops, job, ccrows, cand_ws, s));
     else
       HIPCHK(launch_assign(ops, job, s));
     prof.end();
@@ -932,7 +923,6 @@ struct FitRun {
     ctl.segmented = seg; ctl.n = n;
     if (seg) { ctl.list = list; ctl.seg_cnt = seg_cnt; ctl.nseg = nseg; }
     ctl.delta_only = ctl_delta_only;
-    ctl.full_perm = use_cand ? 1 : 0;
     if (exact)
       HIPCHK(launch_update_exact(plan, xplan, X, dt, labels_out, C_out, C_out, nullptr, &ops,
                                  mti ? drift : nullptr, dirty, &ctl, s, pp));

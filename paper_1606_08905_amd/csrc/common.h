@@ -336,14 +336,14 @@ hipError_t launch_tile_values_f32(const CentroidOps& o, const float* X, int64_t 
 hipError_t launch_tile_values_bf16(const CentroidOps& o, const uint16_t* X, int64_t n,
                                    int d, float* Y, double* E, hipStream_t s);
 // The survivor pass with Clause 2 per block of survivors (tile_cand.hip):
-// FP32 points, k <= kCandMaxK; perm/off: members sorted by (label, index)
-// for every cluster; rows: the neighbour rows of launch_cc_bounds;
-// survivors carry a set sign bit in u; ws: cand_workspace_bytes(n, k).
+// FP32 points, k <= kCandMaxK; the job's segmented list holds the
+// survivors, each with a set sign bit in u; rows: the neighbour rows of
+// launch_cc_bounds; ws: cand_workspace_bytes(n, k).
 constexpr int kCandMaxK = 8192;
 constexpr int kCandMinK = 1024;      // default use from this many centroids
 size_t cand_workspace_bytes(int64_t n, int k);
-hipError_t launch_tile_cand(const CentroidOps& o, const AssignJob& j, const int* perm,
-                            const int* off, const float* rows, void* ws, hipStream_t s);
+hipError_t launch_tile_cand(const CentroidOps& o, const AssignJob& j, const float* rows,
+                            void* ws, hipStream_t s);
 
 hipError_t launch_prep_centroids(const CentroidOps& ops, hipStream_t s);
 hipError_t launch_assign(const CentroidOps& ops, const AssignJob& job,
@@ -419,7 +419,6 @@ struct IterCtl {
   const int* seg_cnt = nullptr;
   int nseg = 0;
   int delta_only = 0;                 // exact update: moved points only
-  int full_perm = 0;                  // sort writes every cluster's members
 };
 
 hipError_t launch_update(const UpdatePlan& p, const void* X, knor_dtype dt,

@@ -15,13 +15,18 @@
 // a, its neighbour row: all centroids in increasing order of a lower bound
 // h(a, j) (a float key that also carries j), so C(x) is a prefix of a's row.
 //
-// Work is split in two launches.  A task holds at most kTaskMembers
-// members of one cluster (in the update's sorted member order); the sort
-// pass keeps the members the filter marked as survivors (sign bit of their
-// bound; Clause 3 has tightened the bound to the exact distance rounded
-// up), sorts them by bound in LDS, and cuts them into blocks of BLOCK in
-// increasing bound: the members of a block share the prefix of a's row
-// that the largest of their bounds needs.  Each block goes to a global list
+// The survivors still to assign (the segmented list; their bounds carry a
+// set sign bit, Clause 3 having tightened them to the exact distance
+// rounded up) are first grouped by cluster without global atomics: each
+// grouping workgroup counts the survivors of its segments per cluster in
+// LDS (one row of a count table), a column scan turns the rows into
+// offsets, one workgroup scans the cluster totals and writes the task
+// table, and each grouping workgroup then places its survivors from its own
+// offsets with LDS cursors.  The order within a cluster is not fixed; it
+// decides no label.  A task holds at most kTaskMembers survivors of one cluster;
+// the sort pass sorts them by bound in LDS and cuts them into blocks of
+// BLOCK in increasing bound: the members of a block share the prefix of
+// a's row that the largest of their bounds needs.  Each block goes to a global list
 // (long prefixes first) with its cluster, its sorted members and its
 // prefix length.  The tile pass is persistent: each workgroup takes blocks
 // from the list with an atomic counter, so the work of one cluster spreads
@@ -68,22 +73,35 @@ struct CandTile {
 
 // Workspace: a header of ints (task count, long and short block counts,
 // the block counter of the tile pass), the task table, the block list
-// (long blocks from the front, short ones from the back) and the members
-// of every task in bound order.
+// (long blocks from the front, short ones from the back), the members of
+// every task in bound order, and the grouping: survivors per cluster,
+// cluster offsets, the count table (one row of k per grouping workgroup)
+// and the survivors by cluster.
 constexpr int kHdrTasks = 0, kHdrLong = 1, kHdrShort = 2, kHdrNext = 3;
 // a block whose prefix is at least this long goes to the front of the list
 constexpr int kLongPrefix = 512;
+// grouping: workgroups (rows of the count table), their threads, the
+// entries of a segment per thread, segments in flight per workgroup
+constexpr int kGroupBlocks = 256;
+constexpr int kGroupThreads = 1024;
+constexpr int kGroupPer = kSeg / kGroupThreads;
+constexpr int kGroupSegs = 2;
 
 struct CandWs {
   int* hdr;
   int2* tasks;
   int4* blocks;
   int* sorted;
-  int cap;  // block list entries
+  int* gcnt;   // k
+  int* goff;   // k + 1
+  int* table;  // kGroupBlocks x k
+  int* gperm;  // n
+  int cap;     // block list entries
 };
 
 static int64_t cand_task_cap(int64_t n, int k) { return n / kTaskMembers + k + 1; }
 static int64_t cand_block_cap(int64_t n, int k) { return n / 64 + cand_task_cap(n, k) + 1; }
+static size_t al256(size_t b) { return (b + 255) / 256 * 256; }
 
 static CandWs cand_ws(void* ws, int64_t n, int k) {
   CandWs w;
@@ -91,62 +109,163 @@ static CandWs cand_ws(void* ws, int64_t n, int k) {
   w.hdr = (int*)c;
   c += 256;
   w.tasks = (int2*)c;
-  c += (sizeof(int2) * (size_t)cand_task_cap(n, k) + 255) / 256 * 256;
+  c += al256(sizeof(int2) * (size_t)cand_task_cap(n, k));
   w.blocks = (int4*)c;
   w.cap = (int)cand_block_cap(n, k);
-  c += (sizeof(int4) * (size_t)w.cap + 255) / 256 * 256;
+  c += al256(sizeof(int4) * (size_t)w.cap);
   w.sorted = (int*)c;
+  c += al256(sizeof(int) * (size_t)n);
+  w.gcnt = (int*)c;
+  c += al256(sizeof(int) * (size_t)k);
+  w.goff = (int*)c;
+  c += al256(sizeof(int) * (size_t)(k + 1));
+  w.table = (int*)c;
+  c += al256(sizeof(int) * (size_t)kGroupBlocks * k);
+  w.gperm = (int*)c;
   return w;
 }
 
 size_t cand_workspace_bytes(int64_t n, int k) {
-  return 256 + (sizeof(int2) * (size_t)cand_task_cap(n, k) + 255) / 256 * 256 +
-         (sizeof(int4) * (size_t)cand_block_cap(n, k) + 255) / 256 * 256 + sizeof(int) * (size_t)n;
+  return 256 + al256(sizeof(int2) * (size_t)cand_task_cap(n, k)) +
+         al256(sizeof(int4) * (size_t)cand_block_cap(n, k)) + al256(sizeof(int) * (size_t)n) +
+         al256(sizeof(int) * (size_t)k) + al256(sizeof(int) * (size_t)(k + 1)) +
+         al256(sizeof(int) * (size_t)kGroupBlocks * k) + sizeof(int) * (size_t)n;
 }
 
-// Task table: task t of cluster a covers members [c kTaskMembers, ...) of
-// a, c < ceil(n_a / kTaskMembers); tasks are numbered cluster by cluster.
-// One workgroup of 1024 threads: an exclusive scan of the per-cluster task
-// counts, then each thread writes the tasks of its clusters.  It also
-// clears the block counts and the block counter of this iteration.
-__global__ __launch_bounds__(1024) void cand_tasks_kernel(const int* __restrict__ off, int k,
-                                                          int2* __restrict__ tasks,
-                                                          int* __restrict__ hdr,
+// Grouping, count and scatter passes.  Workgroup g visits the segments b =
+// g, g + G, ... (G = gridDim.x, the same in both passes) of the list,
+// kGroupSegs of them at a time (all list loads, then all label loads, then
+// LDS atomics).  SCATTER = false counts the survivors of each cluster in LDS
+// and writes the counts as row g of the table; true starts a cursor per
+// cluster at its offset plus row g's exclusive prefix (written by the
+// column scan) and puts each survivor in the next slot of its cluster.
+template <bool SCATTER>
+__global__ __launch_bounds__(kGroupThreads) void cand_group_kernel(
+    const int* __restrict__ list, const int* __restrict__ seg_cnt, int nseg,
+    const int32_t* __restrict__ labels, int k, int* __restrict__ table,
+    const int* __restrict__ goff, int* __restrict__ gperm, const int* __restrict__ conv,
+    int iter) {
+  extern __shared__ int sH[];                                    // k
+  if (*conv < iter) return;                                      // uniform
+  int* trow = table + (size_t)blockIdx.x * k;
+  for (int a = threadIdx.x; a < k; a += kGroupThreads) sH[a] = SCATTER ? goff[a] + trow[a] : 0;
+  __syncthreads();
+  const int G = (int)gridDim.x;
+  for (int b0 = blockIdx.x; b0 < nseg; b0 += G * kGroupSegs) {
+    int cnt[kGroupSegs];
+#pragma unroll
+    for (int q = 0; q < kGroupSegs; ++q) {
+      const int b = b0 + q * G;
+      cnt[q] = b < nseg ? seg_cnt[b] : 0;
+    }
+    int p[kGroupSegs * kGroupPer], a[kGroupSegs * kGroupPer];
+#pragma unroll
+    for (int q = 0; q < kGroupSegs; ++q)
+#pragma unroll
+      for (int e = 0; e < kGroupPer; ++e) {
+        const int i = (int)threadIdx.x + e * kGroupThreads;
+        p[q * kGroupPer + e] = i < cnt[q] ? list[(size_t)(b0 + q * G) * kSeg + i] : -1;
+      }
+#pragma unroll
+    for (int e = 0; e < kGroupSegs * kGroupPer; ++e) a[e] = p[e] >= 0 ? labels[p[e]] : 0;
+#pragma unroll
+    for (int e = 0; e < kGroupSegs * kGroupPer; ++e) {
+      if (p[e] < 0) continue;
+      if (SCATTER)
+        gperm[atomicAdd(&sH[a[e]], 1)] = p[e];
+      else
+        atomicAdd(&sH[a[e]], 1);
+    }
+  }
+  if (!SCATTER) {
+    __syncthreads();
+    for (int a = threadIdx.x; a < k; a += kGroupThreads) trow[a] = sH[a];
+  }
+}
+
+// Column scan of the count table: for each cluster (one thread), the
+// exclusive prefix over the rows replaces each count, and the total is the
+// cluster's survivor count.
+constexpr int kScanRows = 64;   // table loads in flight per thread
+__global__ __launch_bounds__(256) void cand_colscan_kernel(int* __restrict__ table, int rows,
+                                                           int k, int* __restrict__ gcnt,
+                                                           const int* __restrict__ conv,
+                                                           int iter) {
+  if (*conv < iter) return;
+  const int a = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+  if (a >= k) return;
+  int run = 0;
+  for (int r0 = 0; r0 < rows; r0 += kScanRows) {
+    int v[kScanRows];
+#pragma unroll
+    for (int e = 0; e < kScanRows; ++e)
+      v[e] = r0 + e < rows ? table[(size_t)(r0 + e) * k + a] : 0;
+#pragma unroll
+    for (int e = 0; e < kScanRows; ++e)
+      if (r0 + e < rows) {
+        table[(size_t)(r0 + e) * k + a] = run;
+        run += v[e];
+      }
+  }
+  gcnt[a] = run;
+}
+
+// Offsets and task table, one workgroup of 1024 threads: exclusive scans of
+// the per-cluster survivor and task counts, then each thread writes the
+// offsets and tasks of its clusters.  Task c of cluster a covers its
+// survivors [c kTaskMembers, ...), c < ceil(n_a / kTaskMembers); tasks are
+// numbered cluster by cluster.  It also clears the block counts and the
+// block counter of this iteration.
+__global__ __launch_bounds__(1024) void cand_tasks_kernel(int k, CandWs ws,
                                                           const int* __restrict__ conv,
                                                           int iter) {
-  __shared__ int part[1024];
+  __shared__ int part[1024], tpart[1024];
   if (*conv < iter) return;
   const int per = (k + 1023) / 1024;
   const int a0 = threadIdx.x * per;
-  int loc = 0;
-  for (int a = a0; a < a0 + per && a < k; ++a)
-    loc += (off[a + 1] - off[a] + kTaskMembers - 1) / kTaskMembers;
-  part[threadIdx.x] = loc;
+  int mem = 0, loc = 0;
+  for (int a = a0; a < a0 + per && a < k; ++a) {
+    const int c = ws.gcnt[a];
+    mem += c;
+    loc += (c + kTaskMembers - 1) / kTaskMembers;
+  }
+  part[threadIdx.x] = mem;
+  tpart[threadIdx.x] = loc;
   __syncthreads();
   for (int s = 1; s < 1024; s <<= 1) {
-    const int t = threadIdx.x >= (unsigned)s ? part[threadIdx.x - s] : 0;
+    const int m = threadIdx.x >= (unsigned)s ? part[threadIdx.x - s] : 0;
+    const int t = threadIdx.x >= (unsigned)s ? tpart[threadIdx.x - s] : 0;
     __syncthreads();
-    part[threadIdx.x] += t;
+    part[threadIdx.x] += m;
+    tpart[threadIdx.x] += t;
     __syncthreads();
   }
-  int t = part[threadIdx.x] - loc;
+  int m = part[threadIdx.x] - mem;
+  int t = tpart[threadIdx.x] - loc;
   for (int a = a0; a < a0 + per && a < k; ++a) {
-    const int nt = (off[a + 1] - off[a] + kTaskMembers - 1) / kTaskMembers;
-    for (int c = 0; c < nt; ++c) tasks[t++] = make_int2(a, c);
+    const int c = ws.gcnt[a];
+    ws.goff[a] = m;
+    m += c;
+    const int nt = (c + kTaskMembers - 1) / kTaskMembers;
+    for (int q = 0; q < nt; ++q) ws.tasks[t++] = make_int2(a, q);
   }
-  if (threadIdx.x == 1023) hdr[kHdrTasks] = part[1023];
-  if (threadIdx.x < 3) hdr[kHdrLong + threadIdx.x] = 0;
+  if (threadIdx.x == 1023) {
+    ws.goff[k] = part[1023];
+    ws.hdr[kHdrTasks] = tpart[1023];
+  }
+  if (threadIdx.x < 3) ws.hdr[kHdrLong + threadIdx.x] = 0;
 }
 
-// The sort pass: one workgroup per task.  The survivors' members are
+// The sort pass: one workgroup per task.  The task's survivors are
 // written to sorted[m0 + i] in increasing rounded bound, and each block of
 // BLOCK of them becomes one record (a, first member slot, count, prefix
 // length L) of the block list.
 template <int BLOCK>
 __global__ __launch_bounds__(kTileThreads) void cand_sort_kernel(
-    int k, const int* __restrict__ perm, const int* __restrict__ off,
-    const float* __restrict__ rows, int ib, const float* __restrict__ u, CandWs ws,
+    int k, const float* __restrict__ rows, int ib, const float* __restrict__ u, CandWs ws,
     const int* __restrict__ conv, int iter) {
+  const int* __restrict__ perm = ws.gperm;
+  const int* __restrict__ off = ws.goff;
   extern __shared__ __attribute__((aligned(16))) float sRow[];   // a's neighbour row
   __shared__ int sP[kTaskMembers];
   __shared__ float sKey[kTaskMembers];
@@ -164,8 +283,8 @@ __global__ __launch_bounds__(kTileThreads) void cand_sort_kernel(
   stage_batched<8, float>(
       k, [&](int e) { return rows[(size_t)a * k + e]; }, [&](int e, float v) { sRow[e] = v; });
   __syncthreads();
-  // the survivors among the task's members: all member indices first, then
-  // all their bounds (two memory round trips)
+  // the task's survivors (a set sign bit, checked again): all indices
+  // first, then all their bounds (two memory round trips)
   {
     constexpr int E = kTaskMembers / kTileThreads;
     int p[E];
@@ -430,8 +549,8 @@ static int cand_grid(size_t lds) {
 }
 
 template <int DP>
-static hipError_t launch_cand_dp(const CentroidOps& o, const AssignJob& j, const int* perm,
-                                 const int* off, const float* rows, void* ws_, hipStream_t s) {
+static hipError_t launch_cand_dp(const CentroidOps& o, const AssignJob& j, const float* rows,
+                                 void* ws_, hipStream_t s) {
   const int vec = (int)(j.d == DP && ((uintptr_t)j.X & 15) == 0);
   const int vec4 = (int)(j.d % 4 == 0 && ((uintptr_t)j.X & 15) == 0 &&
                          ((uintptr_t)o.C64 & 15) == 0);
@@ -446,12 +565,22 @@ static hipError_t launch_cand_dp(const CentroidOps& o, const AssignJob& j, const
   if (e != hipSuccess) return e;
   const CandWs ws = cand_ws(ws_, j.n, o.k);
   const int ib = cc_rows_bits(o.k);
-  hipLaunchKernelGGL(cand_tasks_kernel, dim3(1), dim3(1024), 0, s, off, o.k, ws.tasks, ws.hdr,
-                     j.conv, j.iter);
+  // the count and scatter passes take the same segments per workgroup
+  const int gg = j.nseg < kGroupBlocks ? (j.nseg > 0 ? j.nseg : 1) : kGroupBlocks;
+  const size_t glds = sizeof(int) * (size_t)o.k;
+  hipLaunchKernelGGL(cand_group_kernel<false>, dim3(gg), dim3(kGroupThreads), glds, s, j.list,
+                     j.seg_cnt, j.nseg, (const int32_t*)j.labels, o.k, ws.table, ws.goff,
+                     ws.gperm, j.conv, j.iter);
+  hipLaunchKernelGGL(cand_colscan_kernel, dim3((o.k + 255) / 256), dim3(256), 0, s, ws.table,
+                     gg, o.k, ws.gcnt, j.conv, j.iter);
+  hipLaunchKernelGGL(cand_tasks_kernel, dim3(1), dim3(1024), 0, s, o.k, ws, j.conv, j.iter);
+  hipLaunchKernelGGL(cand_group_kernel<true>, dim3(gg), dim3(kGroupThreads), glds, s, j.list,
+                     j.seg_cnt, j.nseg, (const int32_t*)j.labels, o.k, ws.table, ws.goff,
+                     ws.gperm, j.conv, j.iter);
   const int64_t tgrid = cand_task_cap(j.n, o.k);           // >= the number of tasks
   hipLaunchKernelGGL((cand_sort_kernel<CandTile<DP>::BLOCK>), dim3((unsigned)tgrid),
-                     dim3(kTileThreads), lds, s, o.k, perm, off, rows, ib, (const float*)j.u,
-                     ws, j.conv, j.iter);
+                     dim3(kTileThreads), lds, s, o.k, rows, ib, (const float*)j.u, ws, j.conv,
+                     j.iter);
   hipLaunchKernelGGL((tile_f32_cand_kernel<DP>), dim3((unsigned)cand_grid<DP>(lds)),
                      dim3(kTileThreads), lds, s, (const float*)j.X, j.d, o.Cm2, o.cn, o.C64,
                      o.k, rows, ib, ws, j.u, j.labels, j.dirty, j.row, j.conv, j.iter, vec,
@@ -459,16 +588,16 @@ static hipError_t launch_cand_dp(const CentroidOps& o, const AssignJob& j, const
   return hipGetLastError();
 }
 
-hipError_t launch_tile_cand(const CentroidOps& o, const AssignJob& j, const int* perm,
-                            const int* off, const float* rows, void* ws, hipStream_t s) {
-  if (j.dt != KNOR_F32 || o.k > kCandMaxK) return hipErrorInvalidValue;
+hipError_t launch_tile_cand(const CentroidOps& o, const AssignJob& j, const float* rows,
+                            void* ws, hipStream_t s) {
+  if (j.dt != KNOR_F32 || o.k > kCandMaxK || !j.list) return hipErrorInvalidValue;
   switch (o.dp) {
-    case 8: return launch_cand_dp<8>(o, j, perm, off, rows, ws, s);
-    case 16: return launch_cand_dp<16>(o, j, perm, off, rows, ws, s);
-    case 32: return launch_cand_dp<32>(o, j, perm, off, rows, ws, s);
-    case 64: return launch_cand_dp<64>(o, j, perm, off, rows, ws, s);
-    case 128: return launch_cand_dp<128>(o, j, perm, off, rows, ws, s);
-    case 256: return launch_cand_dp<256>(o, j, perm, off, rows, ws, s);
+    case 8: return launch_cand_dp<8>(o, j, rows, ws, s);
+    case 16: return launch_cand_dp<16>(o, j, rows, ws, s);
+    case 32: return launch_cand_dp<32>(o, j, rows, ws, s);
+    case 64: return launch_cand_dp<64>(o, j, rows, ws, s);
+    case 128: return launch_cand_dp<128>(o, j, rows, ws, s);
+    case 256: return launch_cand_dp<256>(o, j, rows, ws, s);
     default: return hipErrorInvalidValue;
   }
 }

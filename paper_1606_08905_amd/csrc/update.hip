@@ -831,11 +831,8 @@ hipError_t launch_update(const UpdatePlan& p, const void* X, knor_dtype dt,
   const int* conv = ctl->conv;
   const int iter = ctl->iter;
   if (prof) prof->begin(KNOR_PROF_SORT);
-  // a full member order (every cluster written) serves the next
-  // iteration's candidate-list tile; otherwise clean clusters are skipped
-  const int* sort_dirty = (ctl && ctl->full_perm) ? nullptr : dirty;
-  if (hipError_t e = launch_sort(p, labels, const_cast<int*>(sort_dirty), conv, iter, s, 0))
-    return e;
+  // clean clusters keep their member order (and their sums)
+  if (hipError_t e = launch_sort(p, labels, dirty, conv, iter, s, 0)) return e;
   if (prof) { prof->end(); prof->begin(KNOR_PROF_LEAF); }
   const int64_t lblocks = (p.max_leaves + kLeafWaves - 1) / kLeafWaves;
   const size_t esz = dt == KNOR_F64 ? 8 : (dt == KNOR_F32 ? 4 : 2);
