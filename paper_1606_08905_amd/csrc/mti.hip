@@ -41,6 +41,8 @@ __device__ __forceinline__ float half_dist_down(double D, int d) {
 // 23 - ib mantissa bits, then by index, and the value of a key with its low
 // ib bits cleared is still a lower bound of the half distance.  The row is
 // sorted in LDS (bitonic, padded with +inf to kp2 = the next power of two).
+constexpr int kCcDims = 16;   // CT loads issued before their dimensions are summed
+
 __global__ __launch_bounds__(256) void cc_bounds_kernel(
     const double* __restrict__ C64, const double* __restrict__ CT, int k,
     int d, float* __restrict__ s_half, float* __restrict__ rows, int ib, int kp2,
@@ -58,10 +60,17 @@ __global__ __launch_bounds__(256) void cc_bounds_kernel(
       continue;
     }
     double acc = 0.0;
-#pragma unroll 8
-    for (int dim = 0; dim < d; ++dim) {
-      double t = __dsub_rn(ci[dim], CT[(size_t)dim * k + j]);
-      acc = __dadd_rn(acc, __dmul_rn(t, t));
+    for (int d0 = 0; d0 < d; d0 += kCcDims) {
+      double c[kCcDims];                               // loads in flight together
+#pragma unroll
+      for (int e = 0; e < kCcDims; ++e)
+        c[e] = d0 + e < d ? CT[(size_t)(d0 + e) * k + j] : 0.0;
+#pragma unroll
+      for (int e = 0; e < kCcDims; ++e)
+        if (d0 + e < d) {
+          const double t = __dsub_rn(ci[d0 + e], c[e]);
+          acc = __dadd_rn(acc, __dmul_rn(t, t));
+        }
     }
     if (rows)
       sKey[j] = __uint_as_float((__float_as_uint(half_dist_down(acc, d)) & ~mask) | (uint32_t)j);
@@ -95,6 +104,181 @@ __global__ __launch_bounds__(256) void cc_bounds_kernel(
   for (int j = threadIdx.x; j < k; j += blockDim.x) rows[(size_t)i * k + j] = sKey[j];
 }
 
+// With rows and 256 <= kp2 <= 4096 (KPL = kp2 / 64 keys per lane): four
+// rows per workgroup.  Each thread computes, for its centroids j, the
+// squared distances to the centroids i0 .. i0 + 3 from one read of CT (the
+// FP64 operations of cc_bounds_kernel in its order, so keys and s_half are
+// the same) and stores the keys in LDS (one pad word per KPL keys: the
+// reads below are free of bank conflicts).  Wave w then sorts row i0 + w in
+// registers, lane l holding keys l KPL .. l KPL + KPL - 1, and writes it.
+// The network is bitonic in its direction-free form: a merge of size s
+// first compares i with i xor (s - 1), then i with i + t for t = s/4 .. 1,
+// the smaller key always going to the lower index.  Merges within a lane
+// are unrolled; across lanes the partner comes by a lane shuffle.  Keys are
+// non-negative floats or +inf, so their integer order is their float order.
+constexpr int kRowsPerBlock = 4;
+
+__device__ __forceinline__ void cmpx(uint32_t& a, uint32_t& b) {
+  const uint32_t lo = a < b ? a : b, hi = a < b ? b : a;
+  a = lo;
+  b = hi;
+}
+
+// lane keeps the smaller (low) or the larger of its key and the partner's
+__device__ __forceinline__ uint32_t keep(uint32_t a, uint32_t p, bool low) {
+  const uint32_t lo = a < p ? a : p, hi = a < p ? p : a;
+  return low ? lo : hi;
+}
+
+template <int KPL>
+__device__ __forceinline__ void lane_half_cleaners(uint32_t (&v)[KPL]) {
+#pragma unroll
+  for (int st = KPL >> 1; st > 0; st >>= 1)
+#pragma unroll
+    for (int r = 0; r < KPL; ++r)
+      if ((r & st) == 0) cmpx(v[r], v[r + st]);
+}
+
+template <int KPL>
+__device__ void wave_bitonic(uint32_t (&v)[KPL], int lane) {
+  // merges of size 2 .. KPL, within each lane
+#pragma unroll
+  for (int size = 2; size <= KPL; size <<= 1) {
+#pragma unroll
+    for (int r = 0; r < KPL; ++r)
+      if ((r & (size >> 1)) == 0) cmpx(v[r], v[r ^ (size - 1)]);
+#pragma unroll
+    for (int st = size >> 2; st > 0; st >>= 1)
+#pragma unroll
+      for (int r = 0; r < KPL; ++r)
+        if ((r & st) == 0) cmpx(v[r], v[r + st]);
+  }
+  // merges of size lsz KPL, lsz = 2 .. 64 lanes
+  for (int lsz = 2; lsz <= 64; lsz <<= 1) {
+    // key r of lane l pairs with key KPL - 1 - r of lane l xor (lsz - 1)
+    const bool low = (lane & (lsz >> 1)) == 0;
+#pragma unroll
+    for (int r = 0; r < KPL / 2; ++r) {
+      const int q = KPL - 1 - r;
+      const uint32_t pr = (uint32_t)__shfl_xor((int)v[q], lsz - 1);
+      const uint32_t pq = (uint32_t)__shfl_xor((int)v[r], lsz - 1);
+      v[r] = keep(v[r], pr, low);
+      v[q] = keep(v[q], pq, low);
+    }
+    for (int ls = lsz >> 2; ls > 0; ls >>= 1) {
+      const bool lo = (lane & ls) == 0;
+#pragma unroll
+      for (int r = 0; r < KPL; ++r) v[r] = keep(v[r], (uint32_t)__shfl_xor((int)v[r], ls), lo);
+    }
+    lane_half_cleaners<KPL>(v);
+  }
+}
+
+template <int KPL>
+__global__ __launch_bounds__(64 * kRowsPerBlock) void cc_rows_kernel(
+    const double* __restrict__ C64, const double* __restrict__ CT, int k, int d,
+    float* __restrict__ s_half, float* __restrict__ rows, int ib,
+    const int* __restrict__ conv, int iter) {
+  constexpr int KP2 = 64 * KPL, RS = KP2 + 64;       // LDS row stride (words)
+  constexpr int R = kRowsPerBlock;
+  extern __shared__ uint32_t sK[];                    // R x RS
+  __shared__ double red[R][R];                        // [wave][row]
+  if (*conv < iter) return;
+  const int i0 = blockIdx.x * R;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const uint32_t mask = (1u << ib) - 1u;
+  const double* ci[R];
+#pragma unroll
+  for (int w = 0; w < R; ++w) ci[w] = C64 + (size_t)(i0 + w < k ? i0 + w : k - 1) * d;
+  double best[R];
+#pragma unroll
+  for (int w = 0; w < R; ++w) best[w] = INFINITY;
+  for (int j = threadIdx.x; j < KP2; j += blockDim.x) {
+    const int a = j + j / KPL;
+    if (j >= k) {
+#pragma unroll
+      for (int w = 0; w < R; ++w) sK[w * RS + a] = 0x7f800000u;   // +inf
+      continue;
+    }
+    double acc[R];
+#pragma unroll
+    for (int w = 0; w < R; ++w) acc[w] = 0.0;
+    for (int d0 = 0; d0 < d; d0 += kCcDims) {
+      double c[kCcDims];                               // loads in flight together
+#pragma unroll
+      for (int e = 0; e < kCcDims; ++e)
+        c[e] = d0 + e < d ? CT[(size_t)(d0 + e) * k + j] : 0.0;
+#pragma unroll
+      for (int e = 0; e < kCcDims; ++e)
+        if (d0 + e < d)
+#pragma unroll
+          for (int w = 0; w < R; ++w) {
+            const double t = __dsub_rn(ci[w][d0 + e], c[e]);
+            acc[w] = __dadd_rn(acc[w], __dmul_rn(t, t));
+          }
+    }
+#pragma unroll
+    for (int w = 0; w < R; ++w) {
+      uint32_t key = (uint32_t)j;                      // i itself: half distance 0
+      if (j != i0 + w) {
+        key = (__float_as_uint(half_dist_down(acc[w], d)) & ~mask) | (uint32_t)j;
+        best[w] = acc[w] < best[w] ? acc[w] : best[w];
+      }
+      sK[w * RS + a] = key;
+    }
+  }
+#pragma unroll
+  for (int w = 0; w < R; ++w) {
+    double b = best[w];
+    for (int o = 32; o > 0; o >>= 1) {
+      const double x = __shfl_xor(b, o);
+      b = x < b ? x : b;
+    }
+    if (lane == 0) red[wave][w] = b;
+  }
+  __syncthreads();
+  if (threadIdx.x < R && i0 + (int)threadIdx.x < k) {
+    double m = red[0][threadIdx.x];
+#pragma unroll
+    for (int v = 1; v < R; ++v) m = red[v][threadIdx.x] < m ? red[v][threadIdx.x] : m;
+    s_half[i0 + threadIdx.x] = m < INFINITY ? half_dist_down(m, d) : INFINITY;
+  }
+  const int i = i0 + wave;
+  if (i >= k) return;                                 // uniform per wave; no barrier follows
+  uint32_t v[KPL];
+#pragma unroll
+  for (int r = 0; r < KPL; ++r) v[r] = sK[wave * RS + lane * (KPL + 1) + r];
+  wave_bitonic<KPL>(v, lane);
+  float* out = rows + (size_t)i * k;
+  const int base = lane * KPL;
+  if ((k & 3) == 0) {
+    // base + 4q < k implies base + 4q + 3 < k
+#pragma unroll
+    for (int q = 0; q < KPL / 4; ++q)
+      if (base + 4 * q < k)
+        *reinterpret_cast<float4*>(out + base + 4 * q) =
+            make_float4(__uint_as_float(v[4 * q]), __uint_as_float(v[4 * q + 1]),
+                        __uint_as_float(v[4 * q + 2]), __uint_as_float(v[4 * q + 3]));
+  } else {
+#pragma unroll
+    for (int r = 0; r < KPL; ++r)
+      if (base + r < k) out[base + r] = __uint_as_float(v[r]);
+  }
+}
+
+template <int KPL>
+static hipError_t launch_cc_rows(const CentroidOps& o, float* s_half, float* rows, int ib,
+                                 const int* conv, int iter, hipStream_t s) {
+  const size_t lds = sizeof(uint32_t) * (size_t)kRowsPerBlock * (64 * KPL + 64);
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&cc_rows_kernel<KPL>),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(cc_rows_kernel<KPL>, dim3((o.k + kRowsPerBlock - 1) / kRowsPerBlock),
+                     dim3(64 * kRowsPerBlock), lds, s, o.C64, o.CT, o.k, o.d, s_half, rows, ib,
+                     conv, iter);
+  return hipGetLastError();
+}
+
 int cc_rows_bits(int k) {
   int ib = 0;
   while ((1 << ib) < k) ++ib;
@@ -105,6 +289,17 @@ hipError_t launch_cc_bounds(const CentroidOps& o, float* s_half, float* rows,
                             const int* conv, int iter, hipStream_t s) {
   int kp2 = 1;
   while (kp2 < o.k) kp2 <<= 1;
+  if (rows) {
+    const int ib = cc_rows_bits(o.k);
+    switch (kp2) {
+      case 256: return launch_cc_rows<4>(o, s_half, rows, ib, conv, iter, s);
+      case 512: return launch_cc_rows<8>(o, s_half, rows, ib, conv, iter, s);
+      case 1024: return launch_cc_rows<16>(o, s_half, rows, ib, conv, iter, s);
+      case 2048: return launch_cc_rows<32>(o, s_half, rows, ib, conv, iter, s);
+      case 4096: return launch_cc_rows<64>(o, s_half, rows, ib, conv, iter, s);
+      default: break;
+    }
+  }
   const size_t lds = rows ? sizeof(float) * (size_t)kp2 : 0;
   if (lds) {
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&cc_bounds_kernel),
