@@ -55,34 +55,41 @@ PEAK_FP64_VALU = 78.6e12
 # figure is reported only for its workload and only while the kernel sources
 # it was measured on are unchanged.
 MEASURED_TRAFFIC = {
-    # the Clause-2 group: task table, sort pass and persistent tile (medians
-    # over 78 launches; fetch 10.4 + 645387.8 + 266385.1 KiB, x2 by the copy
-    # calibration; write 59.0 + 15073.8 + 117388.7 KiB)
+    # the Clause-2 group: grouping (count, column scan, tasks, scatter), sort
+    # pass and persistent tile (medians over 78 launches; fetch 26873.8 +
+    # 2121.0 + 11.1 + 35057.7 + 232560.0 + 269647.7 KiB, x2 by the copy
+    # calibration; write 4096.0 + 4112.0 + 36.0 + 73662.1 + 15058.4 +
+    # 117478.2 KiB)
     (5, "assign_list"): {
-        "bytes": (2 * (10.4 + 645387.8 + 266385.1) + (59.0 + 15073.8 + 117388.7)) * 1024,
+        "bytes": (2 * (26873.8 + 2121.0 + 11.1 + 35057.7 + 232560.0 + 269647.7) +
+                  (4096.0 + 4112.0 + 36.0 + 73662.1 + 15058.4 + 117478.2)) * 1024,
         "sources": {
-            "tile_cand.hip": "57f6948fa2f1fb7ec0e387e58181d20550c6bb7ea57849740c84cb3a72573bd9",
-            "tile_f32.h": "3f97de7c2787a14799266d891081f1fd542dd9b455574650329a9c58bb22cabd",
+            "tile_cand.hip": "3ada08acc297c6f059de8283cded0337b9d6bd5d0113d5d55ff2c3d2e5123f99",
+            "tile_f32.h": "4d4931263f7e8e9204b2ce22f0239481b0adcf71b0ce66e01e2e60c1020c482d",
             "tile_common.h": "18b57551b211404e935b936f88115a6a233d856df775a30d73da76270589ecec",
-            "common.h": "595ee45b642e94cd549263e927c436aaada5dffd88b25d561c75da418b34219b",
+            "common.h": "b7a10460ff0b305b2edee9c0bd2fb1626a7566c3cf72a32115c6749f80c115aa",
         },
     },
-    # the survivor tile (median over 200 launches; fetch 23344.5 KiB x2,
-    # write 7139.5 KiB)
+    # the survivor tile (median over 200 launches; fetch 23669.1 KiB x2,
+    # write 7148.2 KiB)
     (2, "assign_list"): {
-        "bytes": (2 * 23344.5 + 7139.5) * 1024,
+        "bytes": (2 * 23669.1 + 7148.2) * 1024,
         "sources": {
-            "tile_f32.hip": "cef7dd31ffbab019dc1801c79ac232c39157b1ac5d06b1542b4e30f6b10845d6",
-            "tile_f32.h": "3f97de7c2787a14799266d891081f1fd542dd9b455574650329a9c58bb22cabd",
+            "tile_f32.hip": "f64f23906e4711f6ec395efd562820cb6065cff0252a454b0ea2af5c815dd33f",
+            "tile_f32.h": "4d4931263f7e8e9204b2ce22f0239481b0adcf71b0ce66e01e2e60c1020c482d",
             "tile_common.h": "18b57551b211404e935b936f88115a6a233d856df775a30d73da76270589ecec",
             "recheck.h": "cdd421f2b40c729a29f70a8c818d95f62f97c9fad5a0e4854d07f66baacaf0ad",
-            "common.h": "595ee45b642e94cd549263e927c436aaada5dffd88b25d561c75da418b34219b",
+            "common.h": "b7a10460ff0b305b2edee9c0bd2fb1626a7566c3cf72a32115c6749f80c115aa",
         },
     },
 }
 
-# iterations whose dominant-group launches are timed inside the timed region
+# iterations whose dominant-group launches are timed inside the timed region:
+# every 10th where launches take tens of microseconds (the events stay out of
+# the way), every one on the large-k workload, whose launches take
+# milliseconds (the mean then covers the same launches as a kernel trace)
 PROFILE_EVERY = 10
+PROFILE_EVERY_BY_CONFIG = {5: 1}
 
 METRIC = ("Lloyd iters/s and point·centroid dists/s (% MFMA peak) "
           "at exact assignments")
@@ -246,11 +253,11 @@ def timed(fn, steps, warmup):
     return outs, (time.perf_counter() - t) / steps
 
 
-def measure(knor, fit, steps, warmup):
+def measure(knor, fit, steps, warmup, every=PROFILE_EVERY):
     """Warm-up fits, one untimed calibration fit with every kernel group under
     HIP events (the breakdown, and which group dominates), then `steps` timed
-    fits in which the dominant group's launches of every PROFILE_EVERY-th
-    iteration are bracketed by events."""
+    fits in which the dominant group's launches of every `every`-th iteration
+    are bracketed by events."""
     import numpy as np
     import torch
     for _ in range(warmup):
@@ -264,7 +271,7 @@ def measure(knor, fit, steps, warmup):
     la = np.zeros(knor.NPROF, np.int64)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    outs = [fit(profile=(ms, la, 1 << g, PROFILE_EVERY)) for _ in range(steps)]
+    outs = [fit(profile=(ms, la, 1 << g, every)) for _ in range(steps)]
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     iters = sum(o[2]["iters"] for o in outs)
@@ -427,11 +434,12 @@ def single_config(a, knor, oracle, workloads):
         return knor.fit(Xt, w.k, C0=C0, max_iters=w.max_iters, tol=w.tol, counters=True,
                         update=a.update, **opts)
 
-    m = measure(knor, fit, a.steps, a.warmup)
+    every = PROFILE_EVERY_BY_CONFIG.get(cfg, PROFILE_EVERY)
+    m = measure(knor, fit, a.steps, a.warmup, every)
     st = m["outs"][-1][2]
     ctr, iters = st["counters"], st["iters"]
     sx = {"f64": 8, "f32": 4, "bf16": 2}[w.dtype]
-    sampled = [t for t in range(iters) if t % PROFILE_EVERY == 0]
+    sampled = [t for t in range(iters) if t % every == 0]
     g = m["g"]
     work = group_work(g, w, sx, ctr, iters, sampled)
     out = {
