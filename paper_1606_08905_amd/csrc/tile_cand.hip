@@ -389,6 +389,7 @@ __attribute__((amdgpu_waves_per_eu(DP <= 32 ? 3 : 1))) void tile_f32_cand_kernel
   __shared__ int sFl[kCandBlockMax];
   __shared__ int4 sPair[kPairCap];
   __shared__ int sFlN, sPairN, sBlk;
+  __shared__ float sWmax[kTileThreads / 64];   // per wave: largest candidate norm
   if (*conv < iter) return;                                   // uniform
   const int nlong = ws.hdr[kHdrLong];
   const int nblk = nlong + ws.hdr[kHdrShort];
@@ -404,6 +405,7 @@ __attribute__((amdgpu_waves_per_eu(DP <= 32 ? 3 : 1))) void tile_f32_cand_kernel
   // previous chunk's matrix work
   float4 pre[G::PER];
   float pn = INFINITY;
+  float tmax = 0.0f;
   auto load_chunk = [&](int c0, int Lb) {
     const int Lp = (Lb + 15) / 16 * 16;
     const int cc = (Lp - c0) < CK ? (Lp - c0) : CK;
@@ -427,7 +429,13 @@ __attribute__((amdgpu_waves_per_eu(DP <= 32 ? 3 : 1))) void tile_f32_cand_kernel
       const int r = e / Q, q4 = e - r * Q;
       if (e < cc * Q) *reinterpret_cast<float4*>(&sC[r * LDA + q4 * 4]) = pre[i];
     }
-    if ((int)threadIdx.x < cc) sN[threadIdx.x] = pn;
+    if ((int)threadIdx.x < cc) {
+      sN[threadIdx.x] = pn;
+      // the rounding bound takes the largest norm over the block's
+      // candidates: each thread keeps the largest it stored, reduced once
+      // per block after the sweep
+      if (pn < INFINITY) tmax = fmax_nc(tmax, pn);
+    }
   };
   for (;;) {
     if (threadIdx.x == 0) sBlk = atomicAdd(&ws.hdr[kHdrNext], 1);
@@ -463,21 +471,22 @@ __attribute__((amdgpu_waves_per_eu(DP <= 32 ? 3 : 1))) void tile_f32_cand_kernel
     }
     __syncthreads();                          // the prefix is staged
     load_chunk(0, L);
-    float cmax = 0.0f;
+    tmax = 0.0f;
     for (int c0 = 0; c0 < Lpad; c0 += CK) {
       const int cc = (Lpad - c0) < CK ? (Lpad - c0) : CK;
       __syncthreads();                        // the previous chunk is consumed
       store_chunk(c0, L);
       __syncthreads();
       if (c0 + CK < Lpad) load_chunk(c0 + CK, L);
-      float mx = 0.0f;
-      for (int e = lane; e < cc; e += 64)
-        if (c0 + e < L) mx = fmax_nc(mx, sN[e]);
-#pragma unroll
-      for (int o = 32; o > 0; o >>= 1) mx = fmax_nc(mx, __shfl_xor(mx, o));
-      cmax = fmax_nc(cmax, mx);
       tile_sweep<T, true, true>(w, sC, sN, cc, c0, col, grp);
     }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) tmax = fmax_nc(tmax, __shfl_xor(tmax, o));
+    if (lane == 0) sWmax[wave] = tmax;
+    __syncthreads();
+    float cmax = sWmax[0];
+#pragma unroll
+    for (int v = 1; v < kTileThreads / 64; ++v) cmax = fmax_nc(cmax, sWmax[v]);
     merge_groups<T>(w);
 #pragma unroll
     for (int pb = 0; pb < PB; ++pb) {
