@@ -215,32 +215,88 @@ hipError_t launch_recheck(const CentroidOps& o, const AssignJob& j,
 // exact per-point distance to the assigned centroid, and the canonical sum
 // ---------------------------------------------------------------------------
 
-template <typename T>
+// dist2_canon of each point and its centroid, its operations in its order;
+// the operands of 8 dimensions are loaded together before they are summed
+// (every load in range: the last dimension stands in past d).  VEC: d is a
+// multiple of 8 and both rows start on 16 bytes, so the 8 dimensions come
+// in 16-byte pieces.
+constexpr int kDist2Dims = 8;
+
+template <typename T, bool VEC>
 __global__ __launch_bounds__(256) void exact_dist2_kernel(
     const T* __restrict__ X, int64_t n, int d, const double* __restrict__ C64,
     const int32_t* __restrict__ labels, double* __restrict__ out) {
   int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= n) return;
-  out[p] = dist2_canon<T>(X + (size_t)p * d, C64 + (size_t)labels[p] * d, d);
+  const T* x = X + (size_t)p * d;
+  const double* c = C64 + (size_t)labels[p] * d;
+  double acc = 0.0;
+  for (int d0 = 0; d0 < d; d0 += kDist2Dims) {
+    double xv[kDist2Dims], cv[kDist2Dims];
+    if constexpr (VEC) {
+      constexpr int XE = 16 / (int)sizeof(T);          // elements per 16-byte piece
+      static_assert(kDist2Dims % XE == 0 || XE > kDist2Dims, "piece size");
+      if constexpr (XE <= kDist2Dims) {
+#pragma unroll
+        for (int q = 0; q < kDist2Dims / XE; ++q) {
+          const uint4 w = *reinterpret_cast<const uint4*>(x + d0 + q * XE);
+          const T* e = reinterpret_cast<const T*>(&w);
+#pragma unroll
+          for (int r = 0; r < XE; ++r) xv[q * XE + r] = to_f64<T>(e[r]);
+        }
+      } else {
+        // 8 BF16 values are one 16-byte piece
+        const uint4 w = *reinterpret_cast<const uint4*>(x + d0);
+        const T* e = reinterpret_cast<const T*>(&w);
+#pragma unroll
+        for (int r = 0; r < kDist2Dims; ++r) xv[r] = to_f64<T>(e[r]);
+      }
+#pragma unroll
+      for (int q = 0; q < kDist2Dims / 2; ++q) {
+        const double2 w = *reinterpret_cast<const double2*>(c + d0 + 2 * q);
+        cv[2 * q] = w.x;
+        cv[2 * q + 1] = w.y;
+      }
+    } else {
+#pragma unroll
+      for (int e = 0; e < kDist2Dims; ++e) {
+        const int i = d0 + e < d ? d0 + e : d - 1;
+        xv[e] = to_f64<T>(x[i]);
+        cv[e] = c[i];
+      }
+    }
+#pragma unroll
+    for (int e = 0; e < kDist2Dims; ++e)
+      if (d0 + e < d) {
+        const double t = __dsub_rn(xv[e], cv[e]);
+        acc = __dadd_rn(acc, __dmul_rn(t, t));
+      }
+  }
+  out[p] = acc;
+}
+
+template <typename T>
+static void launch_dist2_t(const T* X, int64_t n, int d, const double* C64,
+                           const int32_t* labels, double* out, bool vec, hipStream_t s) {
+  const int64_t blocks = (n + 255) / 256;
+  auto kern = vec ? exact_dist2_kernel<T, true> : exact_dist2_kernel<T, false>;
+  hipLaunchKernelGGL(kern, dim3(blocks), dim3(256), 0, s, X, n, d, C64, labels, out);
 }
 
 hipError_t launch_exact_dist2(const void* X, knor_dtype dt, int64_t n, int d,
                               const double* C64, const int32_t* labels,
                               double* out, hipStream_t s) {
   if (n == 0) return hipSuccess;
-  int64_t blocks = (n + 255) / 256;
+  const bool vec = d % kDist2Dims == 0 && ((uintptr_t)X & 15) == 0 && ((uintptr_t)C64 & 15) == 0;
   switch (dt) {
     case KNOR_F64:
-      hipLaunchKernelGGL(exact_dist2_kernel<double>, dim3(blocks), dim3(256), 0,
-                         s, (const double*)X, n, d, C64, labels, out);
+      launch_dist2_t<double>((const double*)X, n, d, C64, labels, out, vec, s);
       break;
     case KNOR_F32:
-      hipLaunchKernelGGL(exact_dist2_kernel<float>, dim3(blocks), dim3(256), 0,
-                         s, (const float*)X, n, d, C64, labels, out);
+      launch_dist2_t<float>((const float*)X, n, d, C64, labels, out, vec, s);
       break;
     case KNOR_BF16:
-      hipLaunchKernelGGL(exact_dist2_kernel<uint16_t>, dim3(blocks), dim3(256),
-                         0, s, (const uint16_t*)X, n, d, C64, labels, out);
+      launch_dist2_t<uint16_t>((const uint16_t*)X, n, d, C64, labels, out, vec, s);
       break;
   }
   return hipGetLastError();
@@ -262,11 +318,31 @@ __global__ __launch_bounds__(256) void leaf_sum_scalar(const double* __restrict_
 
 // Pairwise tree over the leaf sums, bottom-up: at stride s, node a (a a
 // multiple of 2s) absorbs node a+s when it exists.  This equals splitting
-// each range at the largest power of two below its length.
+// each range at the largest power of two below its length.  Strides below
+// kTreeRun stay inside aligned runs of kTreeRun nodes: tree_runs takes them,
+// one workgroup per run in LDS, and leaves each run's node at its first
+// position; tree_scalar takes the strides from s0 on.
+constexpr int kTreeRun = 1024;
+
+__global__ __launch_bounds__(kTreeRun / 2) void tree_runs(double* __restrict__ t, int64_t m) {
+  __shared__ double sv[kTreeRun];
+  const int64_t b0 = (int64_t)blockIdx.x * kTreeRun;
+  for (int i = threadIdx.x; i < kTreeRun; i += blockDim.x) sv[i] = b0 + i < m ? t[b0 + i] : 0.0;
+  __syncthreads();
+  for (int s = 1; s < kTreeRun; s <<= 1) {
+    for (int i = threadIdx.x; i * 2 * s + s < kTreeRun; i += blockDim.x) {
+      const int a = i * 2 * s;
+      if (b0 + a + s < m) sv[a] = __dadd_rn(sv[a], sv[a + s]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) t[b0] = sv[0];
+}
+
 __global__ __launch_bounds__(1024) void tree_scalar(double* __restrict__ t,
-                                                    int64_t m,
+                                                    int64_t m, int64_t s0,
                                                     double* __restrict__ out) {
-  for (int64_t s = 1; s < m; s <<= 1) {
+  for (int64_t s = s0; s < m; s <<= 1) {
     for (int64_t i = threadIdx.x; i * 2 * s + s < m; i += blockDim.x) {
       int64_t a = i * 2 * s;
       t[a] = __dadd_rn(t[a], t[a + s]);
@@ -283,7 +359,13 @@ hipError_t launch_canonical_sum(const double* v, int64_t n, double* tmp,
     hipLaunchKernelGGL(leaf_sum_scalar, dim3((leaves + 255) / 256), dim3(256),
                        0, s, v, n, tmp);
   }
-  hipLaunchKernelGGL(tree_scalar, dim3(1), dim3(1024), 0, s, tmp, leaves, out);
+  int64_t s0 = 1;
+  if (leaves > kTreeRun) {
+    hipLaunchKernelGGL(tree_runs, dim3((unsigned)((leaves + kTreeRun - 1) / kTreeRun)),
+                       dim3(kTreeRun / 2), 0, s, tmp, leaves);
+    s0 = kTreeRun;
+  }
+  hipLaunchKernelGGL(tree_scalar, dim3(1), dim3(1024), 0, s, tmp, leaves, s0, out);
   return hipGetLastError();
 }
 
