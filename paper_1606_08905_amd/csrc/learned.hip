@@ -290,7 +290,11 @@ hipError_t launch_gemm_bf16(const GemmArgs& g, float* part, hipStream_t s) {
 // ---------------------------------------------------------------------------
 
 // One workgroup per row b of Z (B x k): loss_row[b] = logsumexp(z) - z[y],
-// and dZ = (softmax(z) - onehot(y)) / B in place.
+// and dZ = (softmax(z) - onehot(y)) / B in place.  Thread t takes the
+// entries t, t + 256, ...; up to kSoftRegs of them stay in registers
+// (with their exponentials) between the passes, the rest are read again.
+constexpr int kSoftRegs = 16;
+
 __global__ __launch_bounds__(256) void softmax_ce_kernel(float* __restrict__ Z,
                                                          int k,
                                                          const int32_t* __restrict__ y,
@@ -298,8 +302,17 @@ __global__ __launch_bounds__(256) void softmax_ce_kernel(float* __restrict__ Z,
                                                          double* __restrict__ loss_row) {
   __shared__ float red[256];
   float* z = Z + (size_t)blockIdx.x * k;
+  float v[kSoftRegs];
+#pragma unroll
+  for (int q = 0; q < kSoftRegs; ++q) {
+    const int j = threadIdx.x + 256 * q;
+    v[q] = j < k ? z[j] : -INFINITY;
+  }
   float mx = -INFINITY;
-  for (int j = threadIdx.x; j < k; j += 256) mx = fmaxf(mx, z[j]);
+#pragma unroll
+  for (int q = 0; q < kSoftRegs; ++q)
+    if (threadIdx.x + 256 * q < k) mx = fmaxf(mx, v[q]);
+  for (int j = threadIdx.x + 256 * kSoftRegs; j < k; j += 256) mx = fmaxf(mx, z[j]);
   red[threadIdx.x] = mx;
   __syncthreads();
   for (int s = 128; s > 0; s >>= 1) {
@@ -309,7 +322,13 @@ __global__ __launch_bounds__(256) void softmax_ce_kernel(float* __restrict__ Z,
   mx = red[0];
   __syncthreads();
   float sum = 0.0f;
-  for (int j = threadIdx.x; j < k; j += 256) sum += expf(z[j] - mx);
+#pragma unroll
+  for (int q = 0; q < kSoftRegs; ++q)
+    if (threadIdx.x + 256 * q < k) {
+      v[q] = expf(v[q] - mx);
+      sum += v[q];
+    }
+  for (int j = threadIdx.x + 256 * kSoftRegs; j < k; j += 256) sum += expf(z[j] - mx);
   red[threadIdx.x] = sum;
   __syncthreads();
   for (int s = 128; s > 0; s >>= 1) {
@@ -321,7 +340,12 @@ __global__ __launch_bounds__(256) void softmax_ce_kernel(float* __restrict__ Z,
   if (threadIdx.x == 0) loss_row[blockIdx.x] = (double)logf(sum) + (double)mx - (double)z[yb];
   __syncthreads();
   const float inv = 1.0f / sum;
-  for (int j = threadIdx.x; j < k; j += 256) {
+#pragma unroll
+  for (int q = 0; q < kSoftRegs; ++q) {
+    const int j = threadIdx.x + 256 * q;
+    if (j < k) z[j] = (v[q] * inv - (j == yb ? 1.0f : 0.0f)) * invB;
+  }
+  for (int j = threadIdx.x + 256 * kSoftRegs; j < k; j += 256) {
     const float p = expf(z[j] - mx) * inv;
     z[j] = (p - (j == yb ? 1.0f : 0.0f)) * invB;
   }
