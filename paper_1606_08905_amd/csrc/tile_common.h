@@ -98,6 +98,27 @@ __device__ __forceinline__ float chunk_cmax(const float* sN, int cc, int c0,
   return mx;
 }
 
+// Largest fp32(|c|^2) over all k centroids, read from memory by one wave
+// (8 loads per lane in flight): the same value as chunk_cmax over every
+// chunk of a pass that compares each point with all centroids.
+__device__ __forceinline__ float all_cmax(const float* __restrict__ cn, int k, int lane) {
+  float mx = 0.0f;
+  for (int e0 = 0; e0 < k; e0 += 64 * 8) {
+    float v[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int e = e0 + 64 * q + lane;
+      v[q] = cn[e < k ? e : 0];
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q)
+      if (e0 + 64 * q + lane < k) mx = fmax_nc(mx, v[q]);
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) mx = fmax_nc(mx, __shfl_xor(mx, off));
+  return mx;
+}
+
 // Combine the four lane groups (each saw a different quarter of centroids).
 // For two sorted triples a and o the union's second smallest is
 // min(max(a1, o1), a2, o2) and its third smallest is

@@ -297,19 +297,20 @@ __global__ __launch_bounds__(kTileThreads) void tile_f32_chunked_kernel(
   const int* segc = (seg_cnt && nseg <= kSegCache) ? sSeg : nullptr;
 
   int* slice = flags + (int64_t)blockIdx.x * cap;
+  // every point meets every centroid: the rounding bound's largest norm is
+  // the same for all units, taken once per wave
+  const float cmax = all_cmax(cn, k, lane);
   WaveState<T> w;
   for (int64_t unit = blockIdx.x; unit < units; unit += gridDim.x) {
     int64_t q0, m, base;
     if (!unit_range(unit, BUP, n, seg_cnt, segc, nseg, q0, m, base))
       continue;                                // uniform over the workgroup
     load_points<T>(w, X, d, vec, list, labels, base, q0 + wave * WUP, m, col, grp);
-    float cmax = 0.0f;
     for (int c0 = 0; c0 < kpad; c0 += CK) {
       const int cc = (kpad - c0) < CK ? (kpad - c0) : CK;
       __syncthreads();
       stage_cents<T, 2>(sC, sN, Cm2, cn, c0, cc);     // point state is live here
       __syncthreads();
-      cmax = fmax_nc(cmax, chunk_cmax(sN, cc, c0, k, lane));
       tile_sweep<T, true>(w, sC, sN, cc, c0, col, grp);
     }
     merge_groups<T>(w);
