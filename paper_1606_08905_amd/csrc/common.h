@@ -548,6 +548,7 @@ struct MlpPacked {
   uint16_t *W1b, *W2b, *W3b;
   float* b3p;
   int *fl_rows, *fl_pos, *fl_cnt;   // points the short-list pass defers (<= mmax)
+  float* keys;                      // per point and class slice: its 16 largest keys
 };
 int mlp_kpad(int k);
 size_t mlp_pack_bytes(int d, int h, int k, int64_t mmax);

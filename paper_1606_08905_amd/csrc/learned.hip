@@ -570,6 +570,10 @@ constexpr int kFwdPoints = kFwdWaves * 16 * kFwdPB;
 constexpr int kFwdRows = 64;                     // weight rows per LDS chunk
 constexpr float kPadLogit = -3.0e38f;            // classes past k
 constexpr int kFwdList = 10;                     // keys per lane in the first pass
+// Small launches split the classes: up to kFwdSplitMax slices, each a
+// workgroup of its own over the same points, for at most kFwdSplitRows points
+constexpr int kFwdSplitMax = 16;
+constexpr int kFwdSplitRows = 8192;
 
 // W1b (h x KP1, KP1 = 32 KD >= d; input dims in natural order, zero past d),
 // W2b (h x h) and W3b (kpad x h), both with permuted K columns; b3p (kpad)
@@ -675,7 +679,7 @@ __global__ __launch_bounds__(64 * kFwdWaves) void mlp_forward_kernel(
     const float* __restrict__ b2, const uint16_t* __restrict__ W3b,
     const float* __restrict__ b3p, int k, int kpad, int cbits,
     int32_t* __restrict__ cand, const int* __restrict__ outpos, int* __restrict__ fl_rows,
-    int* __restrict__ fl_pos, int* __restrict__ fl_cnt) {
+    int* __restrict__ fl_pos, int* __restrict__ fl_cnt, float* __restrict__ keys_out) {
   static_assert(TL >= 1 && TL <= 16, "list length");
   constexpr int H = 32 * KH, LD = H + 8, KP1 = 32 * KD, PB = kFwdPB;
   using RS = RowStage<KH>;
@@ -683,6 +687,11 @@ __global__ __launch_bounds__(64 * kFwdWaves) void mlp_forward_kernel(
   const int mm = mdev ? (m < *mdev ? m : *mdev) : m;
   const int q0 = blockIdx.x * kFwdPoints;
   if (q0 >= mm) return;                                           // uniform
+  // this workgroup's classes: W3 chunks [cb, ce) of slice blockIdx.y of
+  // gridDim.y (all of them when the grid has one slice)
+  const int NC3 = kpad / kFwdRows;
+  const int cb = (int)((int64_t)blockIdx.y * NC3 / gridDim.y);
+  const int ce = (int)((int64_t)(blockIdx.y + 1) * NC3 / gridDim.y);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int col = lane & 15, grp = lane >> 4;
   uint16_t* buf0 = sW;
@@ -758,7 +767,7 @@ __global__ __launch_bounds__(64 * kFwdWaves) void mlp_forward_kernel(
     uint16_t* nxt = (c & 1) ? buf0 : buf1;
     // the next chunk: W2b's next rows, or after the last the first W3b rows
     if (c + 1 < NC2) pre.load(W2b, (c + 1) * kFwdRows, H);
-    else pre.load(W3b, 0, kpad);
+    else pre.load(W3b, cb * kFwdRows, kpad);
 #pragma unroll
     for (int bb = 0; bb < kFwdRows / 16; ++bb) {
       const int vb = c * (kFwdRows / 16) + bb;             // unit block
@@ -794,13 +803,12 @@ __global__ __launch_bounds__(64 * kFwdWaves) void mlp_forward_kernel(
 #pragma unroll
     for (int i = 0; i < TL; ++i) L[pb][i] = -INFINITY;
   const uint32_t cmask = (1u << cbits) - 1u;
-  const int NC3 = kpad / kFwdRows;
 #pragma unroll 1
-  for (int c = 0; c < NC3; ++c) {
-    const int slot = (c + NC2) & 1;
+  for (int c = cb; c < ce; ++c) {
+    const int slot = (c - cb + NC2) & 1;
     uint16_t* cur = slot ? buf1 : buf0;
     uint16_t* nxt = slot ? buf0 : buf1;
-    if (c + 1 < NC3) pre.load(W3b, (c + 1) * kFwdRows, kpad);
+    if (c + 1 < ce) pre.load(W3b, (c + 1) * kFwdRows, kpad);
 #pragma unroll 1
     for (int bb = 0; bb < kFwdRows / 16; ++bb) {
       const int cl0 = c * kFwdRows + 16 * bb;
@@ -827,7 +835,7 @@ __global__ __launch_bounds__(64 * kFwdWaves) void mlp_forward_kernel(
         }
       }
     }
-    if (c + 1 < NC3) pre.store(nxt);
+    if (c + 1 < ce) pre.store(nxt);
     __syncthreads();
   }
 
@@ -847,6 +855,7 @@ __global__ __launch_bounds__(64 * kFwdWaves) void mlp_forward_kernel(
       const float* src = sK + (((size_t)wave * PB + pb) * 16 + cc) * 4 * 16;
       int hd[4] = {0, 0, 0, 0};
       int32_t out[16];
+      float okey[16];
       float best = -INFINITY;
 #pragma unroll
       for (int i = 0; i < 16; ++i) {
@@ -861,6 +870,16 @@ __global__ __launch_bounds__(64 * kFwdWaves) void mlp_forward_kernel(
         for (int g = 0; g < 4; ++g) hd[g] += (g == bg) ? 1 : 0;
         const int j = (int)(cmask - (__float_as_uint(best) & cmask));
         out[i] = (best == -INFINITY || j >= k) ? -1 : j;
+        okey[i] = best;
+      }
+      if (keys_out) {
+        // a slice of the classes: its 16 largest keys, in decreasing order
+        float4* k4 = reinterpret_cast<float4*>(
+            keys_out + ((size_t)q * gridDim.y + blockIdx.y) * kMlpTop);
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+          k4[i] = make_float4(okey[4 * i], okey[4 * i + 1], okey[4 * i + 2], okey[4 * i + 3]);
+        return;                                  // no barrier follows
       }
       if constexpr (TL < 16) {
         // best is now the 16th largest merged key
@@ -885,6 +904,43 @@ __global__ __launch_bounds__(64 * kFwdWaves) void mlp_forward_kernel(
   }
 }
 
+// Point q's 16 largest keys over the S class slices (each slice's keys in
+// decreasing order, as the forward kernel writes them), decoded as the
+// one-pass kernel decodes its merged list: the same candidates, in the same
+// order.
+__global__ __launch_bounds__(256) void mlp_merge_kernel(const float* __restrict__ keys, int m,
+                                                        int S, int k, int cbits,
+                                                        int32_t* __restrict__ cand,
+                                                        const int* __restrict__ outpos) {
+  const int q = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+  if (q >= m) return;
+  const float* kq = keys + (size_t)q * S * kMlpTop;
+  const uint32_t cmask = (1u << cbits) - 1u;
+  int hd[kFwdSplitMax];
+#pragma unroll
+  for (int s = 0; s < kFwdSplitMax; ++s) hd[s] = 0;
+  int32_t out[kMlpTop];
+#pragma unroll
+  for (int i = 0; i < kMlpTop; ++i) {
+    float best = -INFINITY;
+    int bs = 0;
+#pragma unroll
+    for (int s = 0; s < kFwdSplitMax; ++s) {
+      const float v = (s < S && hd[s] < kMlpTop) ? kq[s * kMlpTop + hd[s]] : -INFINITY;
+      if (v > best) { best = v; bs = s; }
+    }
+#pragma unroll
+    for (int s = 0; s < kFwdSplitMax; ++s) hd[s] += (s == bs) ? 1 : 0;
+    const int j = (int)(cmask - (__float_as_uint(best) & cmask));
+    out[i] = (best == -INFINITY || j >= k) ? -1 : j;
+  }
+  const int qo = outpos ? outpos[q] : q;
+  int4* o4 = reinterpret_cast<int4*>(cand + (size_t)qo * kMlpTop);
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+    o4[i] = make_int4(out[4 * i], out[4 * i + 1], out[4 * i + 2], out[4 * i + 3]);
+}
+
 // padded class count and code bits of the proposal
 int mlp_kpad(int k) { return (k + kFwdRows - 1) / kFwdRows * kFwdRows; }
 static int code_bits(int kpad) {
@@ -903,7 +959,8 @@ size_t mlp_pack_bytes(int d, int h, int k, int64_t mmax) {
   auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
   return al(sizeof(uint16_t) * (size_t)h * KP1) + al(sizeof(uint16_t) * (size_t)h * h) +
          al(sizeof(uint16_t) * (size_t)kpad * h) + al(sizeof(float) * (size_t)kpad) +
-         2 * al(sizeof(int) * (size_t)mmax) + al(sizeof(int));
+         2 * al(sizeof(int) * (size_t)mmax) + al(sizeof(int)) +
+         al(sizeof(float) * (size_t)kFwdSplitRows * kFwdSplitMax * kMlpTop);
 }
 
 MlpPacked mlp_pack_layout(int d, int h, int k, int64_t mmax, void* ws) {
@@ -917,7 +974,8 @@ MlpPacked mlp_pack_layout(int d, int h, int k, int64_t mmax, void* ws) {
   P.b3p = (float*)c; c += al(sizeof(float) * (size_t)P.kpad);
   P.fl_rows = (int*)c; c += al(sizeof(int) * (size_t)mmax);
   P.fl_pos = (int*)c; c += al(sizeof(int) * (size_t)mmax);
-  P.fl_cnt = (int*)c;
+  P.fl_cnt = (int*)c; c += al(sizeof(int));
+  P.keys = (float*)c;
   return P;
 }
 
@@ -944,21 +1002,42 @@ static hipError_t fwd_launch(const T* X, int d, const int* rows, int m, const in
     hipError_t e = hipFuncSetAttribute(kp, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
   }
+  const int grid = (m + kFwdPoints - 1) / kFwdPoints;
+  // few points: the classes are split over slices, enough workgroups to
+  // cover the GPU's compute units (full lists, no second pass), and the
+  // slices' lists merged per point
+  int S = 1;
+  if (!mdev && m <= kFwdSplitRows) {
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        cus <= 0)
+      cus = 256;
+    while (S < kFwdSplitMax && grid * S < cus && 2 * S <= P.kpad / kFwdRows) S *= 2;
+  }
+  if (S > 1) {
+    hipLaunchKernelGGL((mlp_forward_kernel<KD, KH, 16, T>), dim3(grid, S), dim3(64 * kFwdWaves),
+                       lds, s, X, d, rows, m, (const int*)nullptr, mean, istd, P.W1b, th + L.b1,
+                       P.W2b, th + L.b2, P.W3b, P.b3p, L.k, P.kpad, code_bits(P.kpad), cand,
+                       outpos, (int*)nullptr, (int*)nullptr, (int*)nullptr, P.keys);
+    hipLaunchKernelGGL(mlp_merge_kernel, dim3((m + 255) / 256), dim3(256), 0, s,
+                       (const float*)P.keys, m, S, L.k, code_bits(P.kpad), cand, outpos);
+    return hipGetLastError();
+  }
   // first pass with short lists; the points it flags again with full lists
   // (the second grid covers every point; workgroups past the flagged count
   // return at once)
   hipError_t e = launch_fill_i32(P.fl_cnt, 1, 0, s);
   if (e != hipSuccess) return e;
-  const int grid = (m + kFwdPoints - 1) / kFwdPoints;
   hipLaunchKernelGGL((mlp_forward_kernel<KD, KH, kFwdList, T>), dim3(grid), dim3(64 * kFwdWaves),
                      lds, s, X, d, rows, m, mdev, mean, istd, P.W1b, th + L.b1, P.W2b,
                      th + L.b2, P.W3b, P.b3p, L.k, P.kpad, code_bits(P.kpad), cand,
-                     outpos, P.fl_rows, P.fl_pos, P.fl_cnt);
+                     outpos, P.fl_rows, P.fl_pos, P.fl_cnt, (float*)nullptr);
   hipLaunchKernelGGL((mlp_forward_kernel<KD, KH, 16, T>), dim3(grid), dim3(64 * kFwdWaves),
                      lds, s, X, d, (const int*)P.fl_rows, m, (const int*)P.fl_cnt, mean, istd,
                      P.W1b, th + L.b1, P.W2b, th + L.b2, P.W3b, P.b3p, L.k, P.kpad,
                      code_bits(P.kpad), cand, (const int*)P.fl_pos, (int*)nullptr,
-                     (int*)nullptr, (int*)nullptr);
+                     (int*)nullptr, (int*)nullptr, (float*)nullptr);
   return hipGetLastError();
 }
 
