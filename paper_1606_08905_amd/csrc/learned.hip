@@ -69,7 +69,7 @@ constexpr int kGT = 128;           // output tile rows and columns
 constexpr int kGK = 32;            // K-step (one MFMA K-block)
 constexpr int kGLD = kGK + 8;      // LDS row stride (bf16), 16-byte aligned
 constexpr int kGTargetWG = 1024;   // split K until about this many workgroups
-constexpr int kGMaxSplit = 16;
+constexpr int kGMaxSplit = 32;
 
 // The K range of split z of ksplit (multiples of kGK).
 __device__ __forceinline__ void split_range(int K, int ksplit, int z, int& kb, int& ke) {
@@ -248,11 +248,11 @@ __global__ __launch_bounds__(256) void gemm_split_sum_kernel(GemmArgs g, int ksp
 }
 
 // Splits of K for an M x N x K product: enough workgroups to fill the chip
-// when the output has few tiles, each split at least 256 deep.
+// when the output has few tiles, each split at least 64 deep.
 static int gemm_splits(int M, int N, int K) {
   const int tiles = ((M + kGT - 1) / kGT) * ((N + kGT - 1) / kGT);
   int sp = (kGTargetWG + tiles - 1) / tiles;
-  const int kmax = K / 256 > 1 ? K / 256 : 1;
+  const int kmax = K / 64 > 1 ? K / 64 : 1;
   if (sp > kmax) sp = kmax;
   if (sp > kGMaxSplit) sp = kGMaxSplit;
   return sp < 1 ? 1 : sp;
