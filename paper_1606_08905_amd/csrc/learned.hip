@@ -109,10 +109,19 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(GemmArgs g, int ksplit,
   const bool vb = (g.ldb & 3) == 0 && ((uintptr_t)g.B & 15) == 0;
   // piece i of this thread: f = tid + 256 i.  Along K (A plain, B
   // transposed): row f / (kGK / 4), K offset 4 (f mod (kGK / 4)).  Along M
-  // or N (A transposed, B plain): K offset f / 32, rows or columns 4 (f mod
-  // 32).
+  // or N (A transposed, B plain), with l = f mod 64 and w = f / 64: K offset
+  // 8 (w mod 4) + l mod 8, rows or columns 4 (8 (w / 4) + l / 8).  A wave's
+  // load then reads 128 contiguous bytes in each of 8 K rows, and its
+  // 16-bit stores into the K-contiguous LDS rows spread over 8 banks (rows 4
+  // apart, as 32 consecutive lanes would take, all fall on 2 banks).
   constexpr int NP = kGT * kGK / 4 / 256;     // 16-byte pieces per operand per thread
   constexpr int QK = kGK / 4, QS = QK == 16 ? 4 : 3;
+  static_assert(kGK == 32 && kGT == 128, "the transposed piece layout covers 32 x 128");
+  auto tpiece = [](int f, int& kk, int& r) {
+    const int l = f & 63, w = f >> 6;
+    kk = 8 * (w & 3) + (l & 7);
+    r = 4 * (8 * (w >> 2) + (l >> 3));
+  };
   float4 ra[NP], rb[NP];
   auto load = [&](int k0) {
 #pragma unroll
@@ -124,7 +133,8 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(GemmArgs g, int ksplit,
         ra[i] = row < M ? load4(g.A + (size_t)row * g.lda + kx, ke - kx, va)
                         : make_float4(0.f, 0.f, 0.f, 0.f);
       } else {
-        const int kk = f >> 5, r = 4 * (f & 31);
+        int kk, r;
+        tpiece(f, kk, r);
         const int row = m0 + r, kx = k0 + kk;
         ra[i] = kx < ke ? load4(g.A + (size_t)kx * g.lda + row, M - row, va)
                         : make_float4(0.f, 0.f, 0.f, 0.f);
@@ -135,7 +145,8 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(GemmArgs g, int ksplit,
         rb[i] = cn < N ? load4(g.B + (size_t)cn * g.ldb + kx, ke - kx, vb)
                        : make_float4(0.f, 0.f, 0.f, 0.f);
       } else {
-        const int kk = f >> 5, c = 4 * (f & 31);
+        int kk, c;
+        tpiece(f, kk, c);
         const int cn = n0 + c, kx = k0 + kk;
         rb[i] = kx < ke ? load4(g.B + (size_t)kx * g.ldb + cn, N - cn, vb)
                         : make_float4(0.f, 0.f, 0.f, 0.f);
@@ -153,7 +164,8 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(GemmArgs g, int ksplit,
         const int r = f >> QS, kk = 4 * (f & (QK - 1));
         *reinterpret_cast<uint2*>(&a[r * kGLD + kk]) = make_uint2(x01, x23);
       } else {
-        const int kk = f >> 5, r = 4 * (f & 31);
+        int kk, r;
+        tpiece(f, kk, r);
         a[(r + 0) * kGLD + kk] = (uint16_t)x01;
         a[(r + 1) * kGLD + kk] = (uint16_t)(x01 >> 16);
         a[(r + 2) * kGLD + kk] = (uint16_t)x23;
@@ -164,7 +176,8 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(GemmArgs g, int ksplit,
         const int c = f >> QS, kk = 4 * (f & (QK - 1));
         *reinterpret_cast<uint2*>(&b[c * kGLD + kk]) = make_uint2(y01, y23);
       } else {
-        const int kk = f >> 5, c = 4 * (f & 31);
+        int kk, c;
+        tpiece(f, kk, c);
         b[(c + 0) * kGLD + kk] = (uint16_t)y01;
         b[(c + 1) * kGLD + kk] = (uint16_t)(y01 >> 16);
         b[(c + 2) * kGLD + kk] = (uint16_t)y23;
