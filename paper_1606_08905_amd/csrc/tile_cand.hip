@@ -478,7 +478,7 @@ __attribute__((amdgpu_waves_per_eu(DP <= 32 ? 3 : 1))) void tile_f32_cand_kernel
       store_chunk(c0, L);
       __syncthreads();
       if (c0 + CK < Lpad) load_chunk(c0 + CK, L);
-      tile_sweep<T, true, true>(w, sC, sN, cc, c0, col, grp);
+      tile_sweep<T, false, true>(w, sC, sN, cc, c0, col, grp);
     }
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) tmax = fmax_nc(tmax, __shfl_xor(tmax, o));
@@ -487,18 +487,15 @@ __attribute__((amdgpu_waves_per_eu(DP <= 32 ? 3 : 1))) void tile_f32_cand_kernel
     float cmax = sWmax[0];
 #pragma unroll
     for (int v = 1; v < kTileThreads / 64; ++v) cmax = fmax_nc(cmax, sWmax[v]);
-    merge_groups<T>(w);
+    // one index kept per point: a two-candidate point is recomputed in FP64
+    // with the undecided ones
+    merge_groups<T, false>(w);
 #pragma unroll
-    for (int pb = 0; pb < PB; ++pb) {
-      const int j1 = cand_of(w.i1[pb]);
-      const int j2 = cand_of(w.i2[pb]);
-      w.i1[pb] = j1;
-      w.i2[pb] = j2 >= 0 ? j2 : j1;
-    }
+    for (int pb = 0; pb < PB; ++pb) w.i1[pb] = cand_of(w.i1[pb]);
     bool flag, changed;
     int fp;
-    finalize_points<T>(w, cmax, d, grp, 0, true, sPair, &sPairN, labels, u, dirty,
-                       flag, fp, changed);
+    finalize_points<T, false>(w, cmax, d, grp, 0, false, sPair, &sPairN, labels, u, dirty,
+                              flag, fp, changed);
     chg += changed ? 1 : 0;
     if (flag) sFl[atomicAdd(&sFlN, 1)] = fp;   // at most one per point of the block
     __syncthreads();
