@@ -311,13 +311,15 @@ __global__ __launch_bounds__(kTileThreads) void tile_f32_chunked_kernel(
       __syncthreads();
       stage_cents<T, 2>(sC, sN, Cm2, cn, c0, cc);     // point state is live here
       __syncthreads();
-      tile_sweep<T, true>(w, sC, sN, cc, c0, col, grp);
+      tile_sweep<T, false>(w, sC, sN, cc, c0, col, grp);
     }
-    merge_groups<T>(w);
+    // one index per point: a two-candidate point goes to the FP64 recheck
+    // with the undecided ones (centroids are not resident for a re-sweep)
+    merge_groups<T, false>(w);
     bool flag, changed;
     int fp;
-    finalize_points<T>(w, cmax, d, grp, recheck_all, pairs, sPair, &sPairN,
-                       labels, ub, dirty, flag, fp, changed);
+    finalize_points<T, false>(w, cmax, d, grp, recheck_all, false, sPair, &sPairN,
+                              labels, ub, dirty, flag, fp, changed);
     append_flags(flag, fp, &sFlag, slice, lane);
     const uint64_t cm = __ballot(changed);
     if (cm && lane == 0) atomicAdd(&sChg, __popcll(cm));
