@@ -56,26 +56,26 @@ PEAK_FP64_VALU = 78.6e12
 # it was measured on are unchanged.
 MEASURED_TRAFFIC = {
     # the Clause-2 group: grouping (count, column scan, tasks, scatter), sort
-    # pass and persistent tile (medians over 78 launches; fetch 26873.8 + 2121.0 + 11.1 +
-    # 35105.2 + 232582.1 + 269796.6 KiB, x2 by the copy
-    # calibration; write 4096.0 + 4112.0 + 36.0 + 73542.2 + 15058.7 +
-    # 117483.6 KiB)
+    # pass and persistent tile (medians over 78 launches; fetch 26872.5 + 2121.0 + 11.1 +
+    # 35890.5 + 232409.2 + 269945.2 KiB, x2 by the copy
+    # calibration; write 4096.0 + 4112.0 + 36.0 + 73699.1 + 15057.8 +
+    # 117503.2 KiB)
     (5, "assign_list"): {
-        "bytes": (2 * (26873.8 + 2121.0 + 11.1 + 35105.2 + 232582.1 + 269796.6) +
-                  (4096.0 + 4112.0 + 36.0 + 73542.2 + 15058.7 + 117483.6)) * 1024,
+        "bytes": (2 * (26872.5 + 2121.0 + 11.1 + 35890.5 + 232409.2 + 269945.2) +
+                  (4096.0 + 4112.0 + 36.0 + 73699.1 + 15057.8 + 117503.2)) * 1024,
         "sources": {
-            "tile_cand.hip": "02aba6bb5bacbe83005e4f6dfd0ef83dce28cab651443a4385c67093e393307b",
+            "tile_cand.hip": "33134145ac7c2e98d78b6d23ac50b7ea8e845985d1619ff55ecf8185b92ac963",
             "tile_f32.h": "4d4931263f7e8e9204b2ce22f0239481b0adcf71b0ce66e01e2e60c1020c482d",
             "tile_common.h": "66c8fecd8cd91705c6d3c0012eff17d6a12ef5dd3a53a3b8a7c82ec76ec33cca",
             "common.h": "1ea23988c276bf76d5a82e60bfdc7ba13bc26b76aeece46aaeb95bd9033c67a1",
         },
     },
-    # the survivor tile (median over 200 launches; fetch 23662.9 KiB x2,
-    # write 7153.5 KiB)
+    # the survivor tile (median over 200 launches; fetch 23664.3 KiB x2,
+    # write 7153.4 KiB)
     (2, "assign_list"): {
-        "bytes": (2 * 23662.9 + 7153.5) * 1024,
+        "bytes": (2 * 23664.3 + 7153.4) * 1024,
         "sources": {
-            "tile_f32.hip": "323919b2287f735f9b00dfcc9fc0c91563eda9994268a4047f03d101205c73de",
+            "tile_f32.hip": "5fac685a160eca932c038b1b3a5e9a2cddee25145289a5578c06fd29f7e6e20b",
             "tile_f32.h": "4d4931263f7e8e9204b2ce22f0239481b0adcf71b0ce66e01e2e60c1020c482d",
             "tile_common.h": "66c8fecd8cd91705c6d3c0012eff17d6a12ef5dd3a53a3b8a7c82ec76ec33cca",
             "recheck.h": "cdd421f2b40c729a29f70a8c818d95f62f97c9fad5a0e4854d07f66baacaf0ad",

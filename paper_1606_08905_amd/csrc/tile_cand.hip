@@ -32,15 +32,15 @@
 // from the list with an atomic counter, so the work of one cluster spreads
 // over the whole GPU instead of serialising in one workgroup.
 //
-// For each block the FP32 tile runs over the gathered candidate rows with
-// the top-3 epilogue of the dense tile; a point is decided by the same
-// rounding-bound test (its R^2 taken over the candidates, the only
-// centroids whose values it compares).  The order in which candidates are
-// visited decides no label: a decided point has a strict gap to every
-// other value, and two-candidate and undecided points are resolved from
-// canonical FP64 distances with the lowest-index rule -- undecided ones over
-// the block's whole candidate list, which contains the FP64 argmin and
-// every centroid tied with it.
+// For each block the FP32 tile runs over the gathered candidate rows,
+// keeping each point's smallest values and the index of the smallest; a
+// point is decided by the dense tile's rounding-bound test (its R^2 taken
+// over the candidates, the only centroids whose values it compares).  The
+// order in which candidates are visited decides no label: a decided point
+// has a strict gap to every other value, and every other point is resolved
+// from canonical FP64 distances with the lowest-index rule over the block's
+// whole candidate list, which contains the FP64 argmin and every centroid
+// tied with it.
 #include <math.h>
 
 #include <atomic>
@@ -387,8 +387,7 @@ __attribute__((amdgpu_waves_per_eu(DP <= 32 ? 3 : 1))) void tile_f32_cand_kernel
   __shared__ __attribute__((aligned(16))) float sC[CK * LDA];
   __shared__ __attribute__((aligned(16))) float sN[CK];
   __shared__ int sFl[kCandBlockMax];
-  __shared__ int4 sPair[kPairCap];
-  __shared__ int sFlN, sPairN, sBlk;
+  __shared__ int sFlN, sBlk;
   __shared__ float sWmax[kTileThreads / 64];   // per wave: largest candidate norm
   if (*conv < iter) return;                                   // uniform
   const int nlong = ws.hdr[kHdrLong];
@@ -396,7 +395,7 @@ __attribute__((amdgpu_waves_per_eu(DP <= 32 ? 3 : 1))) void tile_f32_cand_kernel
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int col = lane & 15, grp = lane >> 4;
   const uint32_t mask = (1u << ib) - 1u;
-  if (threadIdx.x == 0) { sFlN = 0; sPairN = 0; }
+  if (threadIdx.x == 0) sFlN = 0;
   unsigned long long chg = 0, nflag = 0, ndist = 0;
   auto cand_in = [&](int pos, int Lb) {
     return pos < Lb ? (int)(__float_as_uint(sRow[pos]) & mask) : -1;
@@ -494,7 +493,7 @@ __attribute__((amdgpu_waves_per_eu(DP <= 32 ? 3 : 1))) void tile_f32_cand_kernel
     for (int pb = 0; pb < PB; ++pb) w.i1[pb] = cand_of(w.i1[pb]);
     bool flag, changed;
     int fp;
-    finalize_points<T, false>(w, cmax, d, grp, 0, false, sPair, &sPairN, labels, u, dirty,
+    finalize_points<T, false>(w, cmax, d, grp, 0, false, nullptr, nullptr, labels, u, dirty,
                               flag, fp, changed);
     chg += changed ? 1 : 0;
     if (flag) sFl[atomicAdd(&sFlN, 1)] = fp;   // at most one per point of the block
@@ -521,15 +520,12 @@ __attribute__((amdgpu_waves_per_eu(DP <= 32 ? 3 : 1))) void tile_f32_cand_kernel
       if (lane == 0)
         chg += commit_label(p, a, bj, pair_bound(best, d), labels, u, dirty) ? 1 : 0;
     }
-    // two-candidate points of this block
-    const int np = sPairN < kPairCap ? sPairN : kPairCap;
-    if (np) chg += resolve_pairs<T, float>(X, d, vec, C64, sPair, np, labels, u, dirty);
     if (threadIdx.x == 0) {
       ndist += (unsigned long long)(nv + nfl) * (unsigned long long)L;
       nflag += (unsigned long long)nfl;
     }
     __syncthreads();
-    if (threadIdx.x == 0) { sFlN = 0; sPairN = 0; }
+    if (threadIdx.x == 0) sFlN = 0;
   }
   const int qs[3] = {SLOT_CHANGED, SLOT_FLAGGED, SLOT_DISTS};
   const unsigned long long v[3] = {chg, nflag, ndist};
